@@ -1,0 +1,207 @@
+/*
+ * sipo.h -- C ABI of the MI355X (gfx950) SiPO hot path.
+ *
+ * SiPO (Woo, Lee, Taylor: "Scale-invariant projection optimization in
+ * tomographic volumetric additive manufacturing") designs projection patterns
+ * by solving a Charnes-Cooper linear program with a matrix-free PDHG method
+ * (Sec. 2.6-2.8).  This library provides the operators of that solve and the
+ * solve itself as hand-written HIP kernels:
+ *
+ *   sipo_backproject   P^T, projection -> voxel        (Eq. 2-3)
+ *   sipo_project       P,   voxel -> projection        (Sec. 2.3, adjoint of P^T)
+ *   sipo_blur          K,   object-space PSF           (Eq. 1-3)
+ *   sipo_regions       gel / band / exterior labels    (Sec. 2.2, Fig. 2a)
+ *   sipo_active_rays   active-ray mask                 (Sec. 2.2, Fig. 2b)
+ *   sipo_pdhg_solve    the LP of Eq. 19-24 / 32-37 / 40-45 by PDHG (Sec. 2.8)
+ *
+ * Conventions shared by every call
+ *   - Array pointers named "device" are HIP device pointers owned by the
+ *     caller; the library never frees them and never keeps them after the
+ *     call returns.  Pointers named "host" are ordinary host memory.
+ *   - Volume layout: [nz][n][n], x fastest (row r = y, column c = x).
+ *     Sinogram layout: [n_angles][nz][n_bins], bin fastest (one detector row
+ *     per angle and slice).  Elements are float (SIPO_F32) or double
+ *     (SIPO_F64) as fixed by the plan; labels and masks are uint8.
+ *   - Geometry: the n x n grid covers [-1,1]^2 with voxel centres
+ *     -1 + (c + 1/2) 2/n; voxels with centre outside the unit disk (the vial)
+ *     receive no dose.  n_bins detector bins cover [-1,1].  A view at angle t
+ *     sends light along (cos t, sin t); the detector coordinate of (x, y) is
+ *     s = -x sin t + y cos t.  Each (voxel, view) pair has two linear-
+ *     interpolation taps at bins floor(u) and floor(u)+1, u = (s+1) n_bins/2
+ *     - 1/2, weighted by the Beer-Lambert factor
+ *     exp(-atten (x cos t + y sin t + sqrt(1 - s^2))).  Slices are independent
+ *     (parallel beam perpendicular to the rotation axis z).
+ *   - Every operator call is asynchronous on the given HIP stream (NULL =
+ *     default stream).  sipo_pdhg_solve returns after its stream finishes,
+ *     because its results are host data.
+ *   - Every call returns a sipo_status.  Argument errors (null pointers, bad
+ *     sizes, in == out where forbidden, workspace too small) are detected
+ *     before anything is launched.  HIP failures return SIPO_E_DEVICE.
+ *     sipo_last_error() gives a thread-local message for the last failure.
+ *     No exception or abort crosses this boundary.
+ */
+#ifndef SIPO_H
+#define SIPO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SIPO_OK = 0,
+    SIPO_E_INVALID = -1,      /* bad argument; nothing was launched          */
+    SIPO_E_DEVICE = -2,       /* a HIP call failed                           */
+    SIPO_E_WORKSPACE = -3,    /* caller workspace smaller than required      */
+    SIPO_E_UNSUPPORTED = -4   /* valid request this build does not support   */
+} sipo_status;
+
+typedef enum { SIPO_F32 = 0, SIPO_F64 = 1 } sipo_dtype;
+
+/* Object and projection domains (Sec. 2.2, Fig. 2). */
+typedef struct {
+    int32_t n;               /* grid is n x n per slice, n >= 1                 */
+    int32_t nz;              /* slices along the rotation axis, nz >= 1         */
+    int32_t n_angles;        /* views, >= 1                                     */
+    int32_t n_bins;          /* detector bins per row (the paper uses n), >= 1  */
+    const double *angles;    /* host, n_angles view angles in radians           */
+    double atten;            /* Beer-Lambert coefficient per vial radius, >= 0  */
+} sipo_geometry;
+
+/* Separable object-space PSF K (Eq. 1-3): normalised 1D taps per axis. */
+typedef struct {
+    int32_t rx, ry, rz;      /* tap radii (0 .. SIPO_MAX_PSF_RADIUS); 2r+1 taps  */
+    const double *kx;        /* host, 2rx+1 taps along x (NULL iff rx == 0 -> 1) */
+    const double *ky;        /* host, 2ry+1 taps along y                        */
+    const double *kz;        /* host, 2rz+1 taps along z                        */
+} sipo_psf;
+
+#define SIPO_MAX_PSF_RADIUS 8
+
+/* A plan binds a geometry, an optional PSF and an element type, and holds the
+ * device-side tables the kernels need (view sines and cosines).  Creating a
+ * plan allocates a few KB of device memory on the current device; the plan
+ * must be used on that device only.  psf == NULL means K = I. */
+typedef struct sipo_plan_s *sipo_plan;
+
+int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype dtype,
+                     sipo_plan *plan_out);
+int sipo_plan_destroy(sipo_plan plan);
+
+/* vol (+)= P^T sino: backprojection, the geometric part of the dose model
+ * f = A^T g = K P^T g (Eq. 2-3).  sino: device [n_angles][nz][n_bins];
+ * vol: device [nz][n][n].  accumulate != 0 adds to vol, else overwrites.
+ * sino and vol must not overlap. */
+int sipo_backproject(sipo_plan plan, const void *sino, void *vol, int accumulate, void *stream);
+
+/* sino (+)= P vol: forward projection, the exact transpose of
+ * sipo_backproject (Sec. 2.3).  vol: device [nz][n][n];
+ * sino: device [n_angles][nz][n_bins].  Must not overlap. */
+int sipo_project(sipo_plan plan, const void *vol, void *sino, int accumulate, void *stream);
+
+/* out = K in: the plan's separable PSF with zero boundary ("same" size).
+ * K is symmetric, so this is also K^T (Eq. 51).  in, out: device
+ * [nz][n][n], in != out.  With psf == NULL this is a copy. */
+int sipo_blur(sipo_plan plan, const void *in, void *out, void *stream);
+
+/* Region labels (Sec. 2.2, Fig. 2a): labels[i] = 2 where f_target[i] != 0
+ * inside the vial (gel); 1 where i is inside the vial, not gel, and either
+ * within Euclidean centre distance band_width (voxel units, 3D distance) of a
+ * gel voxel or inside the PSF's box support around a gel voxel (band); 0
+ * otherwise (exterior).  band_width < 0 means band-free (every non-gel vial
+ * voxel is band); otherwise 0 <= band_width <= SIPO_MAX_BAND_WIDTH.
+ * f_target: device [nz][n][n] in the plan dtype; labels and scratch: device
+ * uint8 [nz][n][n] (scratch contents are overwritten). */
+#define SIPO_MAX_BAND_WIDTH 11.0
+int sipo_regions(sipo_plan plan, const void *f_target, double band_width, uint8_t *labels,
+                 uint8_t *scratch, void *stream);
+
+/* Active rays (Sec. 2.2, Fig. 2b): act[j] = 1 where (P f_target)_j exceeds
+ * 1e-6 times its maximum, else 0.  scratch_sino: device sinogram of the plan
+ * dtype used for P f_target (left holding it); act: device uint8 sinogram. */
+int sipo_active_rays(sipo_plan plan, const void *f_target, void *scratch_sino, uint8_t *act,
+                     void *stream);
+
+/* ------------------------------------------------------------------ LP --- */
+/* The unified LP (Eq. 19-24; Case 1 Eq. 32-37; Case 2 Eq. 40-45):
+ *     minimise   w1 u + w2 v
+ *     subject to D_i <= u        on band   (u = band_cap when u_free == 0)
+ *                D_i <= v U_i    on gel    (v = 1 when v_free == 0)
+ *                D_i >= L_i      on gel
+ *                y >= 0 on active rays, y = 0 on masked rays, u, v >= 0
+ * where D = K P^T y is the normalised dose.  General LP: u_free = v_free = 1,
+ * L = U = normalised target.  Case 1: w = (1,0), v_free = 0, L/U = tolerance
+ * bounds.  Case 2: w = (0,1), u_free = 0, band_cap = 1, L = U = normalised
+ * target. */
+typedef struct {
+    sipo_plan plan;            /* geometry, PSF, dtype                              */
+    const uint8_t *labels;     /* device [nz][n][n]: 0 ext, 1 band, 2 gel           */
+    const uint8_t *act;        /* device sinogram mask, 1 = active ray              */
+    const void *lo;            /* device per-voxel L (plan dtype) or NULL           */
+    const void *hi;            /* device per-voxel U (plan dtype) or NULL           */
+    double lo_scalar;          /* L on every gel voxel when lo == NULL              */
+    double hi_scalar;          /* U on every gel voxel when hi == NULL              */
+    int32_t u_free, v_free;    /* 1 = scalar is an LP variable                      */
+    double w1, w2;             /* objective weights (>= 0)                          */
+    double band_cap;           /* u when u_free == 0                                */
+    void *y;                   /* device in/out sinogram: warm start, then y*       */
+    void *lam_up;              /* device in/out [nz][n][n]: lambda1 (band), lambda2 (gel) */
+    void *lam_lo;              /* device in/out [nz][n][n]: lambda3 (gel)           */
+    double u0, v0;             /* warm-start scalars (ignored when fixed)           */
+    void *dose_out;            /* device [nz][n][n] or NULL: D = K P^T y* on return */
+} sipo_problem;
+
+typedef enum { SIPO_PDHG_PLAIN = 0, SIPO_PDHG_RESTARTED = 1 } sipo_pdhg_mode;
+
+typedef struct {
+    int32_t mode;              /* sipo_pdhg_mode                                          */
+    int32_t max_iters;         /* iteration budget (>= 1)                                 */
+    int32_t check_every;       /* KKT/restart check period (restarted mode; >= 1)         */
+    double tol;                /* relative KKT tolerance (restarted mode), e.g. 1e-4      */
+    double tau, sigma;         /* plain mode: > 0 overrides the 0.9/||G|| steps           */
+    int32_t power_iters;       /* plain mode: power iterations for ||G|| (e.g. 100)       */
+    double eta;                /* restarted mode step factor (< 1), e.g. 0.95             */
+    double infeas_tol;         /* restarted mode Farkas test tolerance, e.g. 1e-6         */
+    int32_t use_graph;         /* 1 = capture the iteration block in a HIP graph          */
+} sipo_pdhg_options;
+
+typedef enum {
+    SIPO_OPTIMAL = 0, SIPO_PRIMAL_INFEASIBLE = 1, SIPO_ITER_LIMIT = 2, SIPO_NUMERICAL = 3
+} sipo_solve_status;
+
+typedef struct {
+    int32_t status;            /* sipo_solve_status                                       */
+    int32_t iters, restarts;
+    double primal_obj, dual_obj;
+    double rel_primal, rel_dual, rel_gap;   /* relative KKT residuals of the returned point */
+    double u, v;               /* returned scalars                                        */
+    double tau, sigma;         /* plain mode scalar steps                                 */
+    double omega;              /* restarted mode final primal weight                      */
+    double time_ms;            /* wall time of the solve on its stream                    */
+} sipo_pdhg_result;
+
+/* Bytes of device workspace sipo_pdhg_solve needs for these problems. */
+size_t sipo_pdhg_workspace_size(const sipo_problem *probs, int32_t n_probs,
+                                const sipo_pdhg_options *opts);
+
+/* Solve n_probs independent LPs.  workspace: device buffer of at least
+ * sipo_pdhg_workspace_size bytes (contents ignored on entry).  results: host
+ * array of n_probs.  An infeasible LP is not an error: its status is
+ * SIPO_PRIMAL_INFEASIBLE and lam_up / lam_lo then hold the certificate
+ * (a dual ray lambda >= 0 with P K z >= 0 on active rays and positive
+ * dual objective; Supp. 6.1).  Returns after the stream has finished. */
+int sipo_pdhg_solve(const sipo_problem *probs, int32_t n_probs, const sipo_pdhg_options *opts,
+                    void *workspace, size_t ws_bytes, sipo_pdhg_result *results, void *stream);
+
+/* Thread-local text for the last non-OK return of this thread. */
+const char *sipo_last_error(void);
+
+/* Library version string. */
+const char *sipo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIPO_H */

@@ -29,11 +29,19 @@ import scipy.sparse as sp
 from .geometry import Geometry, plane_coords, in_vial
 
 
-def slice_matrix(geom: Geometry) -> sp.csr_matrix:
-    """P^T for one slice: shape (n*n, n_angles*n_bins), CSR, float64."""
+def slice_matrix(geom: Geometry, voxels=None) -> sp.csr_matrix:
+    """P^T for one slice: shape (n*n, n_angles*n_bins), CSR, float64.
+
+    ``voxels`` (flat slice indices) restricts the build to those rows; the
+    other rows are left empty (used to sample large operators row by row).
+    """
     n, nb = geom.n, geom.n_bins
     X, Y = plane_coords(n)
     inside = in_vial(n).ravel()
+    if voxels is not None:
+        sel = np.zeros(n * n, dtype=bool)
+        sel[np.asarray(voxels)] = True
+        inside = inside & sel
     vox = np.nonzero(inside)[0]
     x = X.ravel()[vox]
     y = Y.ravel()[vox]

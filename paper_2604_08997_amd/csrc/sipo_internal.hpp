@@ -1,0 +1,121 @@
+// Internal declarations shared by the SiPO HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "sipo.h"
+
+namespace sipo {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+int fail(int code, const char *fmt, ...);
+
+#define SIPO_HIP(call)                                                                  \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return ::sipo::fail(SIPO_E_DEVICE, "%s failed: %s (%s:%d)", #call,          \
+                                hipGetErrorString(e_), __FILE__, __LINE__);             \
+    } while (0)
+
+#define SIPO_LAUNCHED(name)                                                             \
+    do {                                                                                \
+        hipError_t e_ = hipGetLastError();                                              \
+        if (e_ != hipSuccess)                                                           \
+            return ::sipo::fail(SIPO_E_DEVICE, "launch of %s failed: %s", name,         \
+                                hipGetErrorString(e_));                                 \
+    } while (0)
+
+#define SIPO_REQUIRE(cond, ...)                                                         \
+    do {                                                                                \
+        if (!(cond)) return ::sipo::fail(SIPO_E_INVALID, __VA_ARGS__);                  \
+    } while (0)
+
+// --------------------------------------------------------------- PSF taps
+// Taps travel to kernels by value (kernel argument space), in both precisions.
+constexpr int kMaxR = 8;
+template <typename T>
+struct Taps {
+    int rx, ry, rz;
+    T kx[2 * kMaxR + 1], ky[2 * kMaxR + 1], kz[2 * kMaxR + 1];
+};
+
+// -------------------------------------------------------------------- plan
+// Small device scratch owned by a plan: reduction partials and scalars.
+constexpr size_t kPlanScratchBytes = 1 << 20;
+
+}  // namespace sipo
+
+struct sipo_plan_s {
+    int n, nz, n_angles, n_bins;
+    double atten;
+    sipo_dtype dtype;
+    int device;
+    bool has_psf;
+    sipo::Taps<float> taps_f;
+    sipo::Taps<double> taps_d;
+    double2 *d_trig;        // [n_angles] (sin, cos)
+    void *d_scratch;        // kPlanScratchBytes
+    // per-angle march axis split, on the host, for launch decisions
+    int n_xmajor;
+    int *d_angle_order;     // [n_angles]: x-major angles first, then y-major
+    size_t vol_elems() const { return (size_t)nz * n * n; }
+    size_t sino_elems() const { return (size_t)n_angles * nz * n_bins; }
+    size_t elem_bytes() const { return dtype == SIPO_F64 ? 8 : 4; }
+};
+
+namespace sipo {
+
+int check_plan(sipo_plan p);
+
+// Launchers (return sipo_status).
+int launch_backproject(sipo_plan p, const void *sino, void *vol, int accumulate, hipStream_t s);
+int launch_project(sipo_plan p, const void *vol, void *sino, int accumulate, hipStream_t s);
+int launch_blur(sipo_plan p, const void *in, void *out, hipStream_t s);
+
+// ------------------------------------------------------------- geometry
+// The per-(voxel, view) interpolation taps, shared verbatim by the
+// backprojector and the projector so that the two are exact transposes.
+// Position and detector coordinate are evaluated in double precision; the
+// Beer-Lambert factor in the element type.
+__device__ __forceinline__ double centre(int c, double h) { return fma((double)c + 0.5, h, -1.0); }
+
+template <typename T>
+__device__ __forceinline__ T exp_t(T v);
+template <>
+__device__ __forceinline__ float exp_t<float>(float v) { return expf(v); }
+template <>
+__device__ __forceinline__ double exp_t<double>(double v) { return exp(v); }
+
+template <typename T>
+__device__ __forceinline__ T sqrt_t(T v);
+template <>
+__device__ __forceinline__ float sqrt_t<float>(float v) { return sqrtf(v); }
+template <>
+__device__ __forceinline__ double sqrt_t<double>(double v) { return sqrt(v); }
+
+// Returns b = floor(u); w0 = a (1 - f) belongs to bin b and w1 = a f to bin b+1.
+template <typename T>
+__device__ __forceinline__ int taps(double x, double y, double sn, double cs, double inv_ds, T atten,
+                                    T &w0, T &w1) {
+#pragma clang fp contract(off)
+    const double s = fma(-x, sn, y * cs);
+    const double u = fma(s + 1.0, inv_ds, -0.5);
+    const double bf = floor(u);
+    const T f = (T)(u - bf);
+    const double t = fma(x, cs, y * sn);
+    T r = (T)fma(-s, s, 1.0);
+    r = r > (T)0 ? sqrt_t<T>(r) : (T)0;
+    const T a = exp_t<T>(-atten * ((T)t + r));
+    w1 = a * f;
+    w0 = a - w1;
+    return (int)bf;
+}
+
+}  // namespace sipo

@@ -1,0 +1,162 @@
+"""GPU parity of the HIP operators (P^T, P, K, regions, active rays) against the oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import blur as oblur, regions as oregions
+from oracle.geometry import make_geometry
+from oracle.projector import Projector, slice_matrix
+from sipo_inputs import uniform_field, signed_field, ellipses_target, ellipsoids_target, angles_uniform
+
+pytestmark = pytest.mark.gpu
+
+F32_NORM_TOL = 1e-5      # normwise relative error bound for FP32 projector outputs
+F64_TOL = 1e-12
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def plan_for(n, angles, nz=1, n_bins=None, atten=1.0, sigma=None, dtype=torch.float32):
+    from paper_2604_08997_amd import Plan
+    return Plan(n, angles, n_bins=n_bins, nz=nz, atten=atten, sigma=sigma, dtype=dtype, device=dev())
+
+
+def to_gpu(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=dev())
+
+
+def rel_norm(got, want):
+    return float(np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300))
+
+
+CASES = [
+    # (n, angles, nz, n_bins, atten)
+    (64, 180, 1, None, 1.0),       # 2D slice of the small FP64 workload
+    (67, 37, 1, 70, 0.7),          # ragged grid, non-square detector, odd angle count
+    (40, 23, 13, 41, 1.0),         # 3D with a slice count that is not a multiple of the z chunk
+    (24, [0.0, math.pi / 2, math.pi, 1.5 * math.pi, 0.25 * math.pi], 3, None, 0.0),   # exact axis/diagonal views
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("case", CASES)
+def test_backproject_and_project_match_oracle(case, dtype):
+    n, angles, nz, nb, atten = case
+    ang = angles_uniform(angles) if isinstance(angles, int) else np.asarray(angles)
+    g = make_geometry(n, ang, n_bins=nb, nz=nz, atten=atten)
+    P = Projector(g)
+    plan = plan_for(n, list(ang), nz=nz, n_bins=nb, atten=atten, dtype=dtype)
+    sino = uniform_field(g.sino_shape, 101)
+    vol = signed_field(g.vol_shape, 102)
+    bp = plan.backproject(to_gpu(sino, dtype)).double().cpu().numpy()
+    fp = plan.project(to_gpu(vol, dtype)).double().cpu().numpy()
+    bp_ref, fp_ref = P.backproject(sino), P.project(vol)
+    if dtype == torch.float64:
+        np.testing.assert_allclose(bp, bp_ref, rtol=F64_TOL, atol=F64_TOL * np.abs(bp_ref).max())
+        np.testing.assert_allclose(fp, fp_ref, rtol=F64_TOL, atol=F64_TOL * np.abs(fp_ref).max())
+    else:
+        assert rel_norm(bp, bp_ref) < F32_NORM_TOL
+        assert rel_norm(fp, fp_ref) < F32_NORM_TOL
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_adjoint_identity_on_gpu(dtype):
+    n, nz = 96, 5
+    plan = plan_for(n, 90, nz=nz, dtype=dtype)
+    x = to_gpu(uniform_field(plan.vol_shape, 3), dtype)
+    y = to_gpu(signed_field(plan.sino_shape, 4), dtype)
+    lhs = float((plan.project(x).double() * y.double()).sum())
+    rhs = float((x.double() * plan.backproject(y).double()).sum())
+    scale = float(plan.project(x).double().norm() * y.double().norm())
+    tol = 1e-13 if dtype == torch.float64 else 1e-6
+    assert abs(lhs - rhs) <= tol * scale
+
+
+def test_accumulate_flag_adds_to_output():
+    plan = plan_for(32, 20, nz=2)
+    s = to_gpu(uniform_field(plan.sino_shape, 8), torch.float32)
+    v0 = to_gpu(uniform_field(plan.vol_shape, 9), torch.float32)
+    base = plan.backproject(s)
+    acc = plan.backproject(s, out=v0.clone(), accumulate=True)
+    torch.testing.assert_close(acc, base + v0, rtol=1e-6, atol=1e-6)
+    x = to_gpu(uniform_field(plan.vol_shape, 10), torch.float32)
+    y0 = to_gpu(uniform_field(plan.sino_shape, 11), torch.float32)
+    torch.testing.assert_close(plan.project(x, out=y0.clone(), accumulate=True), plan.project(x) + y0,
+                               rtol=1e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("sigma,shape", [((1.5, 1.5, 1.5), (37, 70, 70)), ((1.0, 1.0, 2.0), (9, 33, 33)),
+                                         ((0.6, 2.4, 0.0), (5, 20, 20))])
+def test_blur_matches_oracle(sigma, shape, dtype):
+    nz, n, _ = shape
+    plan = plan_for(n, 4, nz=nz, sigma=sigma, dtype=dtype)
+    vol = uniform_field(shape, 12)
+    got = plan.blur(to_gpu(vol, dtype)).double().cpu().numpy()
+    want = oblur.apply(vol, oblur.psf_taps(sigma))
+    tol = 1e-13 if dtype == torch.float64 else 2e-6
+    np.testing.assert_allclose(got, want, rtol=tol, atol=tol)
+
+
+@pytest.mark.parametrize("w", [0.0, 2.0, 3.5, 10.0, math.inf])
+def test_regions_match_oracle_2d(w):
+    n = 96
+    f = ellipses_target(n, 21)
+    plan = plan_for(n, 8, dtype=torch.float32)
+    got = plan.regions(to_gpu(f, torch.float32), band_width=w).cpu().numpy()
+    want = oregions.labels(f, band_width=w)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_regions_match_oracle_3d_with_psf():
+    f = ellipsoids_target(40, 5, count=3, nz=24)
+    sigma = (1.0, 1.0, 2.0)
+    plan = plan_for(40, 8, nz=24, sigma=sigma, dtype=torch.float64)
+    for w in (0.0, 1.5, 4.0):
+        got = plan.regions(to_gpu(f, torch.float64), band_width=w).cpu().numpy()
+        want = oregions.labels(f, band_width=w, taps=oblur.psf_taps(sigma))
+        np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_active_rays_match_oracle(dtype):
+    n = 64
+    g = make_geometry(n, 60, atten=1.0)
+    P = Projector(g)
+    f = ellipses_target(n, 33)
+    plan = plan_for(n, 60, dtype=dtype)
+    got = plan.active_rays(to_gpu(f, dtype)).cpu().numpy().astype(bool)
+    want = oregions.active_rays(P, f)
+    pf = P.project(f)
+    thr = 1e-6 * pf.max()
+    decided = np.abs(pf - thr) > 1e-5 * thr          # rays not within rounding of the threshold
+    np.testing.assert_array_equal(got[decided], want[decided])
+
+
+def test_full_size_3d_projector_sampled_outputs():
+    # 256^3 volume, 360 views, 256 x 256 detector rows, FP32: sampled outputs vs the oracle
+    n, nz, na = 256, 256, 360
+    g = make_geometry(n, na, nz=nz, atten=1.0)
+    plan = plan_for(n, na, nz=nz, dtype=torch.float32)
+    rng = np.random.default_rng(7)
+    vol = uniform_field((nz, n, n), 3002).astype(np.float32)
+    sino = uniform_field((na, nz, n), 3001).astype(np.float32)
+    fp = plan.project(to_gpu(vol, torch.float32)).cpu().numpy()
+    bp = plan.backproject(to_gpu(sino, torch.float32)).cpu().numpy()
+    PT = slice_matrix(g)                                   # (n*n, na*n)
+    # sampled detector bins: (angle, z, bin)
+    ia, iz, ib = rng.integers(0, na, 3000), rng.integers(0, nz, 3000), rng.integers(0, n, 3000)
+    cols = PT[:, ia * n + ib].tocsc()
+    want = np.array([cols[:, k].T @ vol[iz[k]].reshape(-1).astype(np.float64) for k in range(3000)]).ravel()
+    got = fp[ia, iz, ib]
+    assert rel_norm(got, want) < F32_NORM_TOL
+    # sampled voxels
+    vz, vr, vc = rng.integers(0, nz, 3000), rng.integers(0, n, 3000), rng.integers(0, n, 3000)
+    rows = PT[vr * n + vc]
+    s64 = sino.astype(np.float64)
+    want_b = np.array([rows[k] @ s64[:, vz[k], :].reshape(-1) for k in range(3000)]).ravel()
+    assert rel_norm(bp[vz, vr, vc], want_b) < F32_NORM_TOL

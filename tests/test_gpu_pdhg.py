@@ -1,0 +1,121 @@
+"""GPU parity of the PDHG solve (Sec. 2.8) against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lp as olp, pdhg as opdhg, kkt as okkt, regions as oregions
+from oracle.geometry import make_geometry
+from oracle.projector import Projector
+from sipo_inputs import ellipses_target, annulus_disks_target, angles_uniform
+
+pytestmark = pytest.mark.gpu
+
+CASE_NAMES = {0: "general", 1: "case1", 2: "case2"}
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def gpu_lp(n, n_angles, f, case, dtype, band=10.0, **kw):
+    import paper_2604_08997_amd as sipo
+    plan = sipo.Plan(n, list(angles_uniform(n_angles)), dtype=dtype, device=dev())
+    ft = torch.as_tensor(f, dtype=dtype, device=dev())
+    return sipo.LP.build(plan, ft, case, band_width=band, f_min=1.0, **kw)
+
+
+def oracle_lp(n, n_angles, f, case, band=10.0, **kw):
+    g = make_geometry(n, angles_uniform(n_angles), atten=1.0)
+    return olp.build(Projector(g), f, case, band_width=band, **kw)
+
+
+def gpu_state(lp):
+    return (lp.y.double().cpu().numpy(), lp.lam_up.double().cpu().numpy(), lp.lam_lo.double().cpu().numpy())
+
+
+def test_plain_fp64_iterates_match_oracle_64():
+    # 64 x 64 slice, 180 views, 3 random ellipses (seed 0), Case 1, plain PDHG, 2000 iterations, FP64
+    import paper_2604_08997_amd as sipo
+    n, na, iters = 64, 180, 2000
+    f = ellipses_target(n, 0)
+    op = oracle_lp(n, na, f, olp.CASE1)
+    gl = gpu_lp(n, na, f, sipo.CASE1, torch.float64)
+    np.testing.assert_array_equal(gl.labels.cpu().numpy(), op.labels)
+    np.testing.assert_array_equal(gl.act.cpu().numpy().astype(bool), op.act)
+    res = sipo.solve(gl, sipo.pdhg_options(mode=sipo.PLAIN, max_iters=iters, power_iters=100))
+    nrm = opdhg.power_norm(op, iters=100)
+    tau_o = 0.9 / nrm
+    assert res["tau"] == pytest.approx(tau_o, rel=1e-10)
+    ro = opdhg.pdhg_plain(op, iters, tau=tau_o, sigma=tau_o)
+    y, lu, ll = gpu_state(gl)
+    assert np.linalg.norm(y - ro.state.y) <= 1e-8 * np.linalg.norm(ro.state.y)
+    assert np.linalg.norm(lu - ro.state.lam_up) <= 1e-8 * max(np.linalg.norm(ro.state.lam_up), 1e-30)
+    assert np.linalg.norm(ll - ro.state.lam_lo) <= 1e-8 * max(np.linalg.norm(ro.state.lam_lo), 1e-30)
+    assert res["u"] == pytest.approx(ro.state.u, rel=1e-8, abs=1e-12)
+    # objective and violation of the GPU iterate, evaluated by the oracle
+    assert abs(res["primal_obj"] - ro.kkt.primal_obj) <= 1e-4 * (1 + abs(ro.kkt.primal_obj))
+    assert abs(op.violation(y, res["u"], res["v"]) - op.violation(ro.state.y, ro.state.u, ro.state.v)) <= 1e-4
+    k = okkt.residuals(op, y, res["u"], res["v"], lu, ll)
+    assert k.eps_p == pytest.approx(res["rel_primal"], rel=1e-6, abs=1e-12)
+    assert k.eps_d == pytest.approx(res["rel_dual"], rel=1e-6, abs=1e-12)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("case", [0, 1, 2])
+def test_restarted_matches_highs_small(case, dtype):
+    import paper_2604_08997_amd as sipo
+    n, na, seed = 24, 30, 3
+    f = ellipses_target(n, seed)
+    kw = {"cap": 0.9} if case == 2 else {}
+    op = oracle_lp(n, na, f, case, band=3.0, **kw)
+    ref = olp.solve_highs(op)
+    gl = gpu_lp(n, na, f, case, dtype, band=3.0, **kw)
+    tol = 1e-6 if dtype == torch.float64 else 2e-5
+    res = sipo.solve(gl, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=100000, tol=tol, check_every=64))
+    if ref.status == "infeasible":
+        assert res["status_name"] == "infeasible"
+        return
+    assert res["status_name"] == "optimal", res
+    assert abs(res["primal_obj"] - ref.objective) <= 1e-4 * (1 + abs(ref.objective))
+    y, lu, ll = gpu_state(gl)
+    k = okkt.residuals(op, y, res["u"], res["v"], lu, ll)
+    assert k.rel <= 5 * tol
+    assert op.violation(y, res["u"], res["v"]) <= 1e-4
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_infeasible_case1_returns_checked_certificate(dtype):
+    import paper_2604_08997_amd as sipo
+    n, na = 24, 30
+    f = ellipses_target(n, 2)
+    op = oracle_lp(n, na, f, olp.CASE1, band=3.0, tol_lo=1.0, tol_hi=0.95)
+    assert olp.solve_highs(op).status == "infeasible"
+    gl = gpu_lp(n, na, f, sipo.CASE1, dtype, band=3.0, tol_lo=1.0, tol_hi=0.95)
+    res = sipo.solve(gl, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=50000, tol=1e-6,
+                                           infeas_tol=1e-7 if dtype == torch.float64 else 1e-5))
+    assert res["status_name"] == "infeasible"
+    _, lu, ll = gpu_state(gl)
+    chk = okkt.farkas_check(op, lu, ll, tol=1e-6 if dtype == torch.float64 else 1e-4)
+    assert chk["valid"], chk
+
+
+@pytest.mark.parametrize("case", [1, 2])
+def test_slice256_fp32_solution_passes_oracle_kkt(case):
+    # 256 x 256 slice, 360 views, annulus + 4 disks (seed 1000), FP32 restarted PDHG to 1e-4
+    import paper_2604_08997_amd as sipo
+    n, na = 256, 360
+    f = annulus_disks_target(n, 1000)
+    gl = gpu_lp(n, na, f, case, torch.float32)
+    res = sipo.solve(gl, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=30000, tol=1e-4, infeas_tol=1e-5))
+    print(CASE_NAMES[case], {k: res[k] for k in ("status_name", "iters", "restarts", "primal_obj", "rel_primal",
+                                                "rel_dual", "rel_gap", "time_ms")})
+    op = oracle_lp(n, na, f, case)
+    np.testing.assert_array_equal(gl.labels.cpu().numpy(), op.labels)
+    y, lu, ll = gpu_state(gl)
+    if res["status_name"] == "infeasible":
+        assert okkt.farkas_check(op, lu, ll, tol=1e-3)["valid"]
+        return
+    assert res["status_name"] == "optimal"
+    k = okkt.residuals(op, y, res["u"], res["v"], lu, ll)
+    assert k.rel <= 3e-4, k
+    assert abs(k.primal_obj - res["primal_obj"]) <= 1e-4 * (1 + abs(k.primal_obj))
