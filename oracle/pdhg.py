@@ -24,16 +24,16 @@ q = P K z (Eq. 51):
 ``pdhg_plain`` uses scalar steps tau = sigma = 0.9 / ||G|| (100 power
 iterations from the all-ones vector on the act columns and free scalars).
 
-``pdhg_restarted`` adds, after PDLP (Applegate et al.), in this build's own
-arrangement: diagonal Pock-Chambolle steps (alpha = 1) T_j = 1 / sum_i |G_ij|,
-S_i = 1 / sum_j |G_ij| computed from P K w (w = 1 on band, 2 on gel) and
-K P^T 1_act; a primal weight omega (tau = eta T / omega, sigma = eta omega S);
-uniform averages of the iterates since the last restart; a KKT check every
-``check_every`` iterations that tests termination on both the current and
-the averaged iterate, restarts to the better of the two under the
-sufficient (0.2) / necessary (0.8) / artificial (0.36) rules, updates omega
-from the movement since the previous restart, and tests the dual iterate
-difference over the check window as a Farkas certificate.
+``pdhg_restarted`` is a restarted reflected Halpern PDHG (prior art: the
+Halpern-iteration and restart schemes for PDHG on LPs of Lu and Yang, and
+PDLP by Applegate et al.), arranged here as: diagonal Pock-Chambolle steps
+(alpha = 1) T_j = 1 / sum_i |G_ij|, S_i = 1 / sum_j |G_ij| from P K w (w = 1 on
+band, 2 on gel) and K P^T 1_act; a primal weight omega (tau = eta T / omega,
+sigma = eta omega S); the Halpern anchor at the last restart; a KKT check
+every ``check_every`` iterations on the PDHG output; restarts under the
+sufficient (0.2) / necessary (0.8) / artificial (0.36) rules; omega updated
+from the movement between restarts; and Farkas tests of two dual
+differences (one step, and one check window).
 """
 from __future__ import annotations
 
@@ -209,77 +209,89 @@ def infeasibility_ray(prob: LPProblem, d_up, d_lo, tol: float):
     return chk["valid"], chk
 
 
+def _combine(w: float, rho: float, t: State, z: State, anchor: State) -> State:
+    """Reflected Halpern update: w ((1 + rho) t - rho z) + (1 - w) anchor."""
+    def c(a, b, an):
+        return w * ((1.0 + rho) * a - rho * b) + (1.0 - w) * an
+    return State(c(t.y, z.y, anchor.y), c(t.u, z.u, anchor.u), c(t.v, z.v, anchor.v),
+                 c(t.lam_up, z.lam_up, anchor.lam_up), c(t.lam_lo, z.lam_lo, anchor.lam_lo),
+                 c(t.D, z.D, anchor.D))
+
+
 def pdhg_restarted(prob: LPProblem, tol: float = 1e-4, max_iters: int = 20000, check_every: int = 64,
                    eta: float = 0.95, omega0: float = 1.0, infeas_tol: float = 1e-7,
                    beta_suff: float = 0.2, beta_nec: float = 0.8, beta_art: float = 0.36,
-                   merit: str = "relative", update_omega: bool = True, restart_to: str = "best") -> Result:
+                   rho: float = 1.0) -> Result:
+    """Restarted reflected Halpern PDHG with diagonal steps and a primal weight.
+
+    z_{k+1} = w_k ((1 + rho) T(z_k) - rho z_k) + (1 - w_k) z_0,  w_k = (k + 1)/(k + 2),
+    where T is one Chambolle-Pock step (``step``) with tau = eta T / omega,
+    sigma = eta omega S, k counts iterations since the last restart and z_0 is
+    the restart point.  Every ``check_every`` iterations the PDHG output
+    t = T(z) (which satisfies the bounds) is checked: termination on its
+    relative KKT error, a Farkas test of the dual one-step difference
+    lambda(t) - lambda(z) and of the window difference lambda(t) - lambda(t at
+    the previous check), and the restart rules on the l2 merit of the relative
+    residuals (sufficient 0.2, necessary 0.8 with no progress, artificial
+    0.36 of all iterations).  A restart moves z to t, makes it the new z_0 and
+    updates omega from the primal / dual movement since the previous restart
+    (scaled norms, geometric smoothing 1/2).
+    """
     sc = diagonal_scaling(prob)
-    band, gel = prob.band, prob.gel
     omega = omega0
-    st = initial_state(prob)
-    avg = st.copy()
-    n_avg = 0
-    anchor = st.copy()
-    k0 = _kkt.residuals(prob, st.y, st.u, st.v, st.lam_up, st.lam_lo, D=st.D)
-    m_anchor = _merit(k0, omega, merit)
+    z = initial_state(prob)
+    anchor = z.copy()
+    last = z.copy()
+    k_in = 0
+    k0 = _kkt.residuals(prob, z.y, z.u, z.v, z.lam_up, z.lam_lo, D=z.D)
+    m_anchor = _merit(k0)
     m_prev = np.inf
     k_restart = 0
     restarts = 0
-    snap_up, snap_lo = st.lam_up.copy(), st.lam_lo.copy()
+    snap = None
     hist = []
+    t = z
+    kc = k0
     for k in range(1, max_iters + 1):
-        st = step(prob, st, eta * sc.T / omega, eta * sc.Tu / omega, eta * sc.Tv / omega,
-                  eta * omega * sc.S_up, eta * omega * sc.S_lo)
-        n_avg += 1
-        a = 1.0 / n_avg
-        avg.y += a * (st.y - avg.y)
-        avg.u += a * (st.u - avg.u)
-        avg.v += a * (st.v - avg.v)
-        avg.lam_up += a * (st.lam_up - avg.lam_up)
-        avg.lam_lo += a * (st.lam_lo - avg.lam_lo)
-        if k % check_every:
+        t = step(prob, z, eta * sc.T / omega, eta * sc.Tu / omega, eta * sc.Tv / omega,
+                 eta * omega * sc.S_up, eta * omega * sc.S_lo)
+        w = (k_in + 1.0) / (k_in + 2.0)
+        check = k % check_every == 0
+        if check:
+            fx = (t.lam_up - z.lam_up, t.lam_lo - z.lam_lo)
+        z = _combine(w, rho, t, z, anchor)
+        k_in += 1
+        if not check:
             continue
-        if not (np.isfinite(st.y).all() and np.isfinite(st.lam_up).all()):
-            return Result(NUMERICAL, k, st, None, restarts, omega=omega, history=hist)
-        kc = _kkt.residuals(prob, st.y, st.u, st.v, st.lam_up, st.lam_lo, D=st.D)
-        avg.D = prob.dose(avg.y)
-        ka = _kkt.residuals(prob, avg.y, avg.u, avg.v, avg.lam_up, avg.lam_lo, D=avg.D)
-        hist.append((k, kc.rel, ka.rel, omega))
+        if not (np.isfinite(t.y).all() and np.isfinite(t.lam_up).all()):
+            return Result(NUMERICAL, k, t, None, restarts, omega=omega, history=hist)
+        kc = _kkt.residuals(prob, t.y, t.u, t.v, t.lam_up, t.lam_lo, D=t.D)
+        hist.append((k, kc.rel, omega))
         if kc.rel <= tol:
-            return Result(OPTIMAL, k, st, kc, restarts, omega=omega, history=hist)
-        if ka.rel <= tol:
-            return Result(OPTIMAL, k, avg.copy(), ka, restarts, omega=omega, history=hist)
-        ok, _ = infeasibility_ray(prob, st.lam_up - snap_up, st.lam_lo - snap_lo, infeas_tol)
-        if ok:
-            return Result(PRIMAL_INFEASIBLE, k, st, kc, restarts, omega=omega, history=hist,
-                          certificate=(st.lam_up - snap_up, st.lam_lo - snap_lo))
-        snap_up, snap_lo = st.lam_up.copy(), st.lam_lo.copy()
-        mc, ma = _merit(kc, omega, merit), _merit(ka, omega, merit)
-        use_avg = (ma < mc) if restart_to == "best" else (restart_to == "average")
-        if restart_to == "current":
-            ma = mc
-        m_cand = min(ma, mc)
-        do_restart = (m_cand <= beta_suff * m_anchor
-                      or (m_cand <= beta_nec * m_anchor and m_cand > m_prev)
-                      or (k - k_restart >= beta_art * k))
-        m_prev = m_cand
-        if not do_restart:
+            return Result(OPTIMAL, k, t, kc, restarts, omega=omega, history=hist)
+        for cand in ([fx] + ([(t.lam_up - snap[0], t.lam_lo - snap[1])] if snap is not None else [])):
+            ok, _ = infeasibility_ray(prob, cand[0], cand[1], infeas_tol)
+            if ok:
+                return Result(PRIMAL_INFEASIBLE, k, t, kc, restarts, omega=omega, history=hist, certificate=cand)
+        snap = (t.lam_up.copy(), t.lam_lo.copy())
+        m = _merit(kc)
+        if not (m <= beta_suff * m_anchor or (m <= beta_nec * m_anchor and m > m_prev)
+                or (k - k_restart) >= beta_art * k):
+            m_prev = m
             continue
-        if use_avg:
-            st = avg.copy()
-        dx = np.sqrt(_wnorm((st.y - anchor.y).ravel(), sc.T.ravel()) ** 2
-                     + ((st.u - anchor.u) ** 2 / sc.Tu if sc.Tu > 0 else 0.0)
-                     + ((st.v - anchor.v) ** 2 / sc.Tv if sc.Tv > 0 else 0.0))
-        dl = np.sqrt(_wnorm((st.lam_up - anchor.lam_up).ravel(), sc.S_up.ravel()) ** 2
-                     + _wnorm((st.lam_lo - anchor.lam_lo).ravel(), sc.S_lo.ravel()) ** 2)
-        if update_omega and dx > 1e-10 and dl > 1e-10:
+        dx = np.sqrt(_wnorm((t.y - last.y).ravel(), sc.T.ravel()) ** 2
+                     + ((t.u - last.u) ** 2 / sc.Tu if sc.Tu > 0 else 0.0)
+                     + ((t.v - last.v) ** 2 / sc.Tv if sc.Tv > 0 else 0.0))
+        dl = np.sqrt(_wnorm((t.lam_up - last.lam_up).ravel(), sc.S_up.ravel()) ** 2
+                     + _wnorm((t.lam_lo - last.lam_lo).ravel(), sc.S_lo.ravel()) ** 2)
+        if dx > 1e-10 and dl > 1e-10:
             omega = float(np.exp(0.5 * np.log(dl / dx) + 0.5 * np.log(omega)))
-        anchor = st.copy()
-        avg = st.copy()
-        n_avg = 0
-        m_anchor = _merit(ka if use_avg else kc, omega, merit)
+        z = t.copy()
+        anchor = t.copy()
+        last = t.copy()
+        k_in = 0
+        m_anchor = m
         m_prev = np.inf
         k_restart = k
         restarts += 1
-    kc = _kkt.residuals(prob, st.y, st.u, st.v, st.lam_up, st.lam_lo, D=st.D)
-    return Result(ITER_LIMIT, max_iters, st, kc, restarts, omega=omega, history=hist)
+    return Result(ITER_LIMIT, max_iters, t, kc, restarts, omega=omega, history=hist)

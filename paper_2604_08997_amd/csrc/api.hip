@@ -72,7 +72,7 @@ int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype 
     SIPO_REQUIRE(geom->n >= 1 && geom->nz >= 1 && geom->n_angles >= 1 && geom->n_bins >= 1,
                  "sizes must be >= 1 (n=%d nz=%d n_angles=%d n_bins=%d)", geom->n, geom->nz, geom->n_angles,
                  geom->n_bins);
-    SIPO_REQUIRE(geom->n <= 16384 && geom->n_bins <= 16384 && geom->n_angles <= 65536 && geom->nz <= 16384,
+    SIPO_REQUIRE(geom->n <= 16384 && geom->n_bins <= 16384 && geom->n_angles <= 65535 && geom->nz <= 16384,
                  "sizes exceed the supported maximum");
     SIPO_REQUIRE(geom->angles != nullptr, "angles pointer is NULL");
     SIPO_REQUIRE(std::isfinite(geom->atten) && geom->atten >= 0.0, "atten must be finite and >= 0");
@@ -106,9 +106,19 @@ int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype 
     if (e == hipSuccess) e = hipMemcpy(p->d_trig, trig.data(), sizeof(double2) * geom->n_angles, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_angle_order, order.data(), sizeof(int) * geom->n_angles, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        hipFree(p->d_trig); hipFree(p->d_angle_order); hipFree(p->d_scratch);
+        (void)hipFree(p->d_trig); (void)hipFree(p->d_angle_order); (void)hipFree(p->d_scratch);
         delete p;
         return fail(SIPO_E_DEVICE, "plan device allocation failed: %s", hipGetErrorString(e));
+    }
+    p->d_batches = nullptr;
+    p->d_vol_t = nullptr;
+    p->d_sino_t = nullptr;
+    rc = plan_build_batches(p, trig.data());
+    if (rc != SIPO_OK) {
+        (void)hipFree(p->d_trig); (void)hipFree(p->d_angle_order); (void)hipFree(p->d_scratch);
+        (void)hipFree(p->d_batches);
+        delete p;
+        return rc;
     }
     *plan_out = p;
     return SIPO_OK;
@@ -117,12 +127,15 @@ int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype 
 int sipo_plan_destroy(sipo_plan p) {
     if (!p) return SIPO_OK;
     int cur = -1;
-    hipGetDevice(&cur);
-    if (cur != p->device) hipSetDevice(p->device);
-    hipFree(p->d_trig);
-    hipFree(p->d_angle_order);
-    hipFree(p->d_scratch);
-    if (cur >= 0 && cur != p->device) hipSetDevice(cur);
+    (void)hipGetDevice(&cur);
+    if (cur != p->device) (void)hipSetDevice(p->device);
+    (void)hipFree(p->d_trig);
+    (void)hipFree(p->d_angle_order);
+    (void)hipFree(p->d_scratch);
+    (void)hipFree(p->d_batches);
+    if (p->d_vol_t) (void)hipFree(p->d_vol_t);
+    if (p->d_sino_t) (void)hipFree(p->d_sino_t);
+    if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);
     delete p;
     return SIPO_OK;
 }

@@ -2,28 +2,36 @@
 //
 // Saddle problem  min_{x in X} max_{lambda >= 0} c^T x + lambda^T (G x - h)
 // with x = (y, u, v), D = K P^T y and the rows (band: D - u_bar, gel: D - v_bar U,
-// gel: L - D).  One iteration (Chambolle-Pock, primal first):
+// gel: L - D).  One Chambolle-Pock step t = T(z) from z = (y, u, v, lambda):
 //
-//   q   = P K z,  z = lambda_up[band | gel] - lambda_lo[gel]          (Eq. 51)
-//   y+  = act ? max(0, y - tau_j q) : 0                               (Eq. 50)
-//   u+  = max(0, u - tau_u (w1 - sum lambda1)),  v+ likewise          (Eq. 48-49)
-//   D+  = K P^T y+,  Dbar = 2 D+ - D,  ubar = 2 u+ - u,  vbar = 2 v+ - v
-//   lambda_up <- max(0, lambda_up + s_i (Dbar - ubar | vbar U))       band | gel
-//   lambda_lo <- max(0, lambda_lo + s_i (L - Dbar))                   gel
+//   q   = P K z_lambda,  z_lambda = lambda_up[band | gel] - lambda_lo[gel]  (Eq. 51)
+//   t.y = act ? max(0, y - tau_j q) : 0                                    (Eq. 50)
+//   t.u = max(0, u - tau_u (w1 - sum lambda1)),  t.v likewise              (Eq. 48-49)
+//   D_t = K P^T t.y,  Dbar = 2 D_t - D(y),  ubar = 2 t.u - u,  vbar = 2 t.v - v
+//   t.lambda_up = max(0, lambda_up + s_i (Dbar - ubar | vbar U))           band | gel
+//   t.lambda_lo = max(0, lambda_lo + s_i (L - Dbar))                       gel
 //
-// Plain mode: scalar tau = sigma = 0.9 / ||G|| (FP64 power iteration).
-// Restarted mode: diagonal steps T_j = 1 / colsum_j(|G|), S_i = 1 / rowsum_i(|G|)
-// with a primal weight omega (tau = eta T / omega, sigma = eta omega S), uniform
-// averages since the last restart, KKT checks every check_every iterations on
-// the current and the averaged iterate, restarts to the better of the two
-// (sufficient 0.2 / necessary 0.8 / artificial 0.36), omega updated from the
-// movement between restarts, and the dual iterate difference over each check
-// window tested as a Farkas certificate.
+// and the next iterate z+ = w ((1 + rho) t - rho z) + (1 - w) z0 (D carried along
+// by linearity):
+//   plain mode:     w = 1, rho = 0 (z+ = t), scalar tau = sigma = 0.9 / ||G||
+//                   from an FP64 power iteration;
+//   restarted mode: reflected Halpern, rho = 1, w = (k+1)/(k+2) with k counted
+//                   from the last restart and z0 the restart point; diagonal
+//                   Pock-Chambolle steps T_j = 1/colsum_j |G|, S_i = 1/rowsum_i |G|
+//                   with a primal weight omega (tau = eta T / omega, sigma =
+//                   eta omega S).  Every check_every iterations the PDHG output
+//                   t is checked: relative KKT termination, Farkas tests of
+//                   lambda(t) - lambda(z) and of lambda(t) - lambda(t at the
+//                   previous check), restart rules (sufficient 0.2, necessary
+//                   0.8, artificial 0.36) on the l2 merit of the relative KKT
+//                   residuals; a restart moves z and z0 to t and updates omega
+//                   from the movement since the previous restart.
 //
-// Everything that changes from one iteration to the next lives in a device
-// scalar block, so an iteration is a fixed sequence of launches with fixed
-// arguments (graph-capturable).  Reductions are two-level (per-block FP64
-// partials, then one block summing them in a fixed order): deterministic.
+// All iteration-varying scalars live in a device block, so an iteration is a
+// fixed sequence of launches with fixed arguments; a block of iterations can
+// be captured once in a HIP graph and replayed.  Reductions are two-level
+// (per-block FP64 partials summed in a fixed order by one block), so results
+// are deterministic.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -37,15 +45,18 @@ constexpr int kRedBlocks = 1024;   // upper bound on reduction blocks
 constexpr int kNS = 8;             // sums carried per reduction
 constexpr int kThreads = 256;
 
-// Device scalar block (FP64): all iteration-varying values.
+// Device scalar block (FP64): everything that changes from one iteration to the next.
 struct DevScal {
-    double u, v;              // current u^k, v^k
-    double u_next, v_next;    // u^{k+1}, v^{k+1}
-    double ubar, vbar;        // extrapolated scalars for the dual update
-    double tau_fac, sig_fac;  // array step factors (eta/omega, eta*omega) or plain tau, sigma
+    double u, v;              // z.u, z.v (Halpern iterate)
+    double ut, vt;            // t.u, t.v of the iteration about to run
+    double ut_done, vt_done;  // t.u, t.v of the iteration just completed
+    double u0, v0;            // anchor scalars
+    double ubar, vbar;        // extrapolated scalars for the dual step
+    double tau_fac, sig_fac;  // array step factors (eta/omega, eta*omega) or the plain tau, sigma
     double tau_u, tau_v;      // scalar primal steps
-    double avg_w, n_avg;      // weight of the current iterate in the running average
-    double u_avg, v_avg;
+    double w, rho;            // Halpern weight of the iteration about to run, reflection
+    double k_in;              // iterations since the last restart
+    double halpern;           // 1 = restarted mode (w = (k+1)/(k+2)), 0 = plain (w = 1)
     double sum_l1, sum_Ul2;   // sums of the current lambda
     double sums[kNS];         // last generic reduction result
 };
@@ -80,7 +91,7 @@ __device__ __forceinline__ void block_sums(double (&v)[NS], double *partials) {
     }
 }
 
-// Sum per-block partials (fixed order) into dst[0..NS).
+// Sum per-block partials (fixed order) into dst[0..ns).
 __global__ void finish_sums(const double *__restrict__ partials, int nblocks, double *dst, int ns) {
     const int k = threadIdx.x;
     if (k < ns) {
@@ -90,21 +101,20 @@ __global__ void finish_sums(const double *__restrict__ partials, int nblocks, do
     }
 }
 
-static int red_blocks(size_t n) { return (int)std::min<size_t>((n + kThreads * 4 - 1) / (kThreads * 4), kRedBlocks); }
-
-#define GRID_LOOP(i, n) for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
+#define GRID_LOOP(i, n) \
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
 
 template <typename T>
 __device__ __forceinline__ T ld_or(const T *p, size_t i, double s) { return p ? p[i] : (T)s; }
 
 // ------------------------------------------------------------- setup kernels
-// y <- act ? max(y, 0) : 0  (warm start sanitised onto X)
+// y <- act ? max(y, 0) : 0  (warm start projected onto X)
 template <typename T>
 __global__ void k_project_y(T *y, const uint8_t *act, size_t n) {
     GRID_LOOP(i, n) y[i] = act[i] ? (y[i] > (T)0 ? y[i] : (T)0) : (T)0;
 }
 
-// lambda sanitised onto its regions and made >= 0; z = lambda_up - lambda_lo; sums of lambda.
+// lambda projected onto its regions and >= 0; z = lambda_up - lambda_lo; [0] sum_band lambda1, [1] sum_gel U lambda2.
 template <typename T>
 __global__ void k_lambda_z(T *lu, T *ll, T *z, const uint8_t *lab, const T *hi, LPConst c, size_t n,
                            double *partials) {
@@ -139,7 +149,8 @@ __global__ void k_inv_colsum(T *t, const uint8_t *act, size_t n) {
     GRID_LOOP(i, n) t[i] = (act[i] && t[i] > (T)0) ? (T)1 / t[i] : (T)0;
 }
 
-// S_up = 1/(R + [band, u free] + [gel, v free] U), S_lo = [gel] 1/R; sums |band|, sum_gel U, ||h||^2 pieces
+// S_up = 1/(R + [band, u free] + [gel, v free] U), S_lo = [gel] 1/R;
+// [0] |band|, [1] sum_gel U, [2] ||h||^2, [3] |gel|
 template <typename T>
 __global__ void k_row_scaling(const T *R, T *s_up, T *s_lo, const uint8_t *lab, const T *lo, const T *hi, LPConst c,
                               size_t n, double *partials) {
@@ -169,64 +180,82 @@ __global__ void k_row_scaling(const T *R, T *s_up, T *s_lo, const uint8_t *lab, 
 }
 
 // --------------------------------------------------------- iteration kernels
-// y+ = act ? max(0, y - tau q) : 0, with tau = tau_fac * T_j (or tau_fac); running average of y.
+// t.y = act ? max(0, y - tau q) : 0 with tau = tau_fac T_j (or tau_fac); y <- w ((1+rho) t.y - rho y) + (1-w) y0.
 template <typename T>
-__global__ void k_primal(T *__restrict__ y, const T *__restrict__ q, const T *__restrict__ Tj,
-                         const uint8_t *__restrict__ act, T *__restrict__ y_avg, const DevScal *__restrict__ sc,
+__global__ void k_primal(T *__restrict__ y, T *__restrict__ yt, const T *__restrict__ q, const T *__restrict__ Tj,
+                         const uint8_t *__restrict__ act, const T *__restrict__ y0, const DevScal *__restrict__ sc,
                          size_t n) {
     const T tf = (T)sc->tau_fac;
-    const T aw = (T)sc->avg_w;
+    const T w = (T)sc->w, rho = (T)sc->rho;
     GRID_LOOP(i, n) {
-        T yn = (T)0;
+        T t = (T)0;
+        const T yo = y[i];
         if (act[i]) {
-            const T t = Tj ? tf * Tj[i] : tf;
-            yn = y[i] - t * q[i];
-            yn = yn > (T)0 ? yn : (T)0;
+            const T st = Tj ? tf * Tj[i] : tf;
+            t = yo - st * q[i];
+            t = t > (T)0 ? t : (T)0;
         }
-        y[i] = yn;
-        if (y_avg) y_avg[i] += aw * (yn - y_avg[i]);
+        yt[i] = t;
+        y[i] = y0 ? w * (((T)1 + rho) * t - rho * yo) + ((T)1 - w) * y0[i] : t;
     }
 }
 
-// Dual update on voxels; writes lambda, z, averages; block sums of lambda1 and U lambda2.
+// Dual step on voxels from D_t (= K P^T t.y) and D (= K P^T z.y); Halpern update of lambda and D;
+// z_lambda for the next step; on check iterations t.lambda and the pre-step lambda are kept.
+// [0] sum_band lambda1, [1] sum_gel U lambda2 of the new lambda.
 template <typename T>
-__global__ void k_dual(const T *__restrict__ Dn, const T *__restrict__ Do, T *__restrict__ lu, T *__restrict__ ll,
-                       T *__restrict__ z, const uint8_t *__restrict__ lab, const T *__restrict__ lo,
-                       const T *__restrict__ hi, const T *__restrict__ s_up, const T *__restrict__ s_lo,
-                       T *__restrict__ lu_avg, T *__restrict__ ll_avg, const DevScal *__restrict__ sc, LPConst c,
-                       size_t n, double *partials) {
+__global__ void k_dual(const T *__restrict__ Dt, T *__restrict__ D, const T *__restrict__ D0, T *__restrict__ lu,
+                       T *__restrict__ ll, const T *__restrict__ lu0, const T *__restrict__ ll0, T *__restrict__ z,
+                       const uint8_t *__restrict__ lab, const T *__restrict__ lo, const T *__restrict__ hi,
+                       const T *__restrict__ s_up, const T *__restrict__ s_lo, T *__restrict__ lut,
+                       T *__restrict__ llt, T *__restrict__ luo, T *__restrict__ llo, const DevScal *__restrict__ sc,
+                       LPConst c, size_t n, double *partials) {
     const double sf = sc->sig_fac;
     const T ub = (T)(c.u_free ? sc->ubar : c.h);
     const T vb = (T)(c.v_free ? sc->vbar : 1.0);
-    const T aw = (T)sc->avg_w;
+    const T w = (T)sc->w, rho = (T)sc->rho, w1 = (T)1 - w, rp = (T)1 + rho;
     double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
     GRID_LOOP(i, n) {
+        const T dt = Dt[i], dz = D[i];
+        D[i] = D0 ? w * (rp * dt - rho * dz) + w1 * D0[i] : dt;
         const uint8_t L = lab[i];
         if (L == 0) continue;
-        const T Db = (T)2 * Dn[i] - Do[i];
+        const T Db = (T)2 * dt - dz;
         const T su = s_up ? (T)sf * s_up[i] : (T)sf;
-        T a = lu[i] + su * (Db - (L == 1 ? ub : vb * ld_or(hi, i, c.hi_s)));
+        const T a_old = lu[i];
+        T a = a_old + su * (Db - (L == 1 ? ub : vb * ld_or(hi, i, c.hi_s)));
         a = a > (T)0 ? a : (T)0;
-        lu[i] = a;
-        T zz = a;
-        if (lu_avg) lu_avg[i] += aw * (a - lu_avg[i]);
+        const T a_new = lu0 ? w * (rp * a - rho * a_old) + w1 * lu0[i] : a;
+        lu[i] = a_new;
+        if (lut) { lut[i] = a; luo[i] = a_old; }
+        T zz = a_new;
         if (L == 1) {
-            acc[0] += (double)a;
+            acc[0] += (double)a_new;
         } else {
             const T sl = s_lo ? (T)sf * s_lo[i] : (T)sf;
-            T b = ll[i] + sl * (ld_or(lo, i, c.lo_s) - Db);
+            const T b_old = ll[i];
+            T b = b_old + sl * (ld_or(lo, i, c.lo_s) - Db);
             b = b > (T)0 ? b : (T)0;
-            ll[i] = b;
-            zz = a - b;
-            if (ll_avg) ll_avg[i] += aw * (b - ll_avg[i]);
-            acc[1] += (double)ld_or(hi, i, c.hi_s) * (double)a;
+            const T b_new = ll0 ? w * (rp * b - rho * b_old) + w1 * ll0[i] : b;
+            ll[i] = b_new;
+            if (llt) { llt[i] = b; llo[i] = b_old; }
+            zz = a_new - b_new;
+            acc[1] += (double)ld_or(hi, i, c.hi_s) * (double)a_new;
         }
         z[i] = zz;
     }
     block_sums<kNS>(acc, partials);
 }
 
-// One block: finish the lambda sums and roll the scalars for the next iteration.
+// Next scalar primal step from the current z and the lambda sums.
+__device__ __forceinline__ void roll_next(DevScal *sc, const LPConst &c) {
+    sc->ut = c.u_free ? fmax(0.0, sc->u - sc->tau_u * (c.w1 - sc->sum_l1)) : c.h;
+    sc->vt = c.v_free ? fmax(0.0, sc->v - sc->tau_v * (c.w2 - sc->sum_Ul2)) : 1.0;
+    sc->ubar = 2.0 * sc->ut - sc->u;
+    sc->vbar = 2.0 * sc->vt - sc->v;
+}
+
+// One block: finish the lambda sums, apply the Halpern update to (u, v), prepare the next step.
 __global__ void k_scalars(const double *__restrict__ partials, int nblocks, DevScal *sc, LPConst c) {
     __shared__ double s[2];
     if (threadIdx.x < 2) {
@@ -236,32 +265,27 @@ __global__ void k_scalars(const double *__restrict__ partials, int nblocks, DevS
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    const double w = sc->avg_w;
-    // the iterate just completed is (u_next, v_next) = (u^{k+1}, v^{k+1})
-    sc->u = sc->u_next;
-    sc->v = sc->v_next;
-    sc->u_avg += w * (sc->u - sc->u_avg);
-    sc->v_avg += w * (sc->v - sc->v_avg);
-    sc->n_avg += 1.0;
-    sc->avg_w = 1.0 / sc->n_avg;
+    const double w = sc->w, rho = sc->rho;
+    sc->ut_done = sc->ut;
+    sc->vt_done = sc->vt;
+    if (c.u_free) sc->u = w * ((1.0 + rho) * sc->ut - rho * sc->u) + (1.0 - w) * sc->u0;
+    else sc->u = c.h;
+    if (c.v_free) sc->v = w * ((1.0 + rho) * sc->vt - rho * sc->v) + (1.0 - w) * sc->v0;
+    else sc->v = 1.0;
     sc->sum_l1 = s[0];
     sc->sum_Ul2 = s[1];
-    if (c.u_free) sc->u_next = fmax(0.0, sc->u - sc->tau_u * (c.w1 - s[0]));
-    else sc->u_next = c.h;
-    if (c.v_free) sc->v_next = fmax(0.0, sc->v - sc->tau_v * (c.w2 - s[1]));
-    else sc->v_next = 1.0;
-    sc->ubar = 2.0 * sc->u_next - sc->u;
-    sc->vbar = 2.0 * sc->v_next - sc->v;
+    sc->k_in += 1.0;
+    sc->w = sc->halpern != 0.0 ? (sc->k_in + 1.0) / (sc->k_in + 2.0) : 1.0;
+    roll_next(sc, c);
 }
 
-// Initial roll: given sums of lambda^0 in sc->sums[0..1], set u_next, ubar for iteration 0.
+// After a (re)start: sums of lambda in sums[0..1]; set the weight and the first step.
 __global__ void k_scalars_init(DevScal *sc, LPConst c) {
     sc->sum_l1 = sc->sums[0];
     sc->sum_Ul2 = sc->sums[1];
-    sc->u_next = c.u_free ? fmax(0.0, sc->u - sc->tau_u * (c.w1 - sc->sum_l1)) : c.h;
-    sc->v_next = c.v_free ? fmax(0.0, sc->v - sc->tau_v * (c.w2 - sc->sum_Ul2)) : 1.0;
-    sc->ubar = 2.0 * sc->u_next - sc->u;
-    sc->vbar = 2.0 * sc->v_next - sc->v;
+    sc->k_in = 0.0;
+    sc->w = sc->halpern != 0.0 ? 0.5 : 1.0;
+    roll_next(sc, c);
 }
 
 // ---------------------------------------------------------------- KKT pieces
@@ -308,23 +332,24 @@ __global__ void k_kkt_ray(const T *q, const T *y, const uint8_t *act, size_t n, 
     block_sums<kNS>(acc, partials);
 }
 
-// Farkas candidate: d = max(lam - snap, 0) on regions -> z_d; sums for the ray objective.
-// [0] sum L d3, [1] sum_band d1, [2] sum_gel U d2, [3] sum |d| (l1)
+// Farkas candidate d = max(a - b, 0) on the regions -> z_d; [0] sum L d3, [1] sum_band d1,
+// [2] sum_gel U d2, [3] ||d||_1.
 template <typename T>
-__global__ void k_ray_candidate(const T *lu, const T *ll, const T *su, const T *sl, T *zd, const uint8_t *lab,
+__global__ void k_ray_candidate(const T *alu, const T *all, const T *blu, const T *bll, T *zd, const uint8_t *lab,
                                 const T *lo, const T *hi, LPConst c, size_t n, double *partials) {
     double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
     GRID_LOOP(i, n) {
         const uint8_t L = lab[i];
         T zz = 0;
         if (L) {
-            T a = lu[i] - su[i];
+            T a = alu[i] - blu[i];
             a = a > (T)0 ? a : (T)0;
             zz = a;
             acc[3] += (double)a;
-            if (L == 1) acc[1] += (double)a;
-            else {
-                T b = ll[i] - sl[i];
+            if (L == 1) {
+                acc[1] += (double)a;
+            } else {
+                T b = all[i] - bll[i];
                 b = b > (T)0 ? b : (T)0;
                 zz = a - b;
                 acc[0] += (double)ld_or(lo, i, c.lo_s) * (double)b;
@@ -337,15 +362,16 @@ __global__ void k_ray_candidate(const T *lu, const T *ll, const T *su, const T *
     block_sums<kNS>(acc, partials);
 }
 
-// Certificate output: lambda_up <- max(lambda_up - snap_up, 0), lambda_lo <- max(lambda_lo - snap_lo, 0) on regions.
+// Certificate output: out = max(a - b, 0) on the regions (lambda_lo on gel only).
 template <typename T>
-__global__ void k_certificate(T *lu, T *ll, const T *su, const T *sl, const uint8_t *lab, size_t n) {
+__global__ void k_certificate(T *olu, T *oll, const T *alu, const T *all, const T *blu, const T *bll,
+                              const uint8_t *lab, size_t n) {
     GRID_LOOP(i, n) {
         const uint8_t L = lab[i];
-        T a = L ? lu[i] - su[i] : (T)0;
-        T b = (L == 2) ? ll[i] - sl[i] : (T)0;
-        lu[i] = a > (T)0 ? a : (T)0;
-        ll[i] = b > (T)0 ? b : (T)0;
+        T a = L ? alu[i] - blu[i] : (T)0;
+        T b = (L == 2) ? all[i] - bll[i] : (T)0;
+        olu[i] = a > (T)0 ? a : (T)0;
+        oll[i] = b > (T)0 ? b : (T)0;
     }
 }
 
@@ -384,7 +410,7 @@ __global__ void finish_max(const double *__restrict__ partials, int nblocks, dou
     }
 }
 
-// power iteration: rows of G x for x = (y, u, v) with D = K P^T y -> z = G^T-row combination,
+// power iteration: G^T-side combination of the rows of G x with D = K P^T y,
 // [0] sum_band (D - u), [1] sum_gel U (D - v U)
 template <typename T>
 __global__ void k_pi_rows(const T *D, T *z, const uint8_t *lab, const T *hi, LPConst c, double u, double v, size_t n,
@@ -430,7 +456,7 @@ __global__ void k_copy(T *dst, const T *src, size_t n) {
     GRID_LOOP(i, n) dst[i] = src[i];
 }
 
-// weighted movement norms: [0] sum (a-b)^2 / w over w > 0
+// weighted movement: [0] sum (a-b)^2 / w over w > 0
 template <typename T>
 __global__ void k_wdist(const T *a, const T *b, const T *w, size_t n, double *partials) {
     double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -446,10 +472,12 @@ __global__ void k_wdist(const T *a, const T *b, const T *w, size_t n, double *pa
 
 // ================================================================= host side
 struct Workspace {
-    // sinogram-sized
-    void *q, *Tj, *y_avg, *y_anchor;
+    // sinogram-sized, internal layout
+    void *q, *Tj, *yt, *y0, *ylast, *y_int;
+    uint8_t *act_int;
     // volume-sized
-    void *D, *Dn, *z, *tmp, *tmp2, *s_up, *s_lo, *lu_avg, *ll_avg, *lu_anchor, *ll_anchor, *lu_snap, *ll_snap;
+    void *D, *Dt, *D0, *z, *tmp, *tmp2, *s_up, *s_lo, *lut, *llt, *luo, *llo, *snap_u, *snap_l, *lu0, *ll0,
+        *lul, *lll, *vol_t;
     double *partials;
     DevScal *scal;
 };
@@ -466,11 +494,15 @@ static size_t layout(const sipo_problem &pb, Workspace *ws, char *base) {
         off += bytes;
         return r;
     };
-    Workspace w;
-    w.q = take(sb); w.Tj = take(sb); w.y_avg = take(sb); w.y_anchor = take(sb);
-    w.D = take(vb); w.Dn = take(vb); w.z = take(vb); w.tmp = take(vb); w.tmp2 = take(vb);
-    w.s_up = take(vb); w.s_lo = take(vb); w.lu_avg = take(vb); w.ll_avg = take(vb);
-    w.lu_anchor = take(vb); w.ll_anchor = take(vb); w.lu_snap = take(vb); w.ll_snap = take(vb);
+    Workspace w{};
+    w.q = take(sb); w.Tj = take(sb); w.yt = take(sb); w.y0 = take(sb); w.ylast = take(sb);
+    const bool t3 = p->fast3d();
+    w.y_int = t3 ? take(sb) : nullptr;
+    w.act_int = t3 ? (uint8_t *)take(align_up(p->sino_elems())) : nullptr;
+    w.vol_t = t3 ? take(vb) : nullptr;
+    w.D = take(vb); w.Dt = take(vb); w.D0 = take(vb); w.z = take(vb); w.tmp = take(vb); w.tmp2 = take(vb);
+    w.s_up = take(vb); w.s_lo = take(vb); w.lut = take(vb); w.llt = take(vb); w.luo = take(vb); w.llo = take(vb);
+    w.snap_u = take(vb); w.snap_l = take(vb); w.lu0 = take(vb); w.ll0 = take(vb); w.lul = take(vb); w.lll = take(vb);
     w.partials = (double *)take(align_up(sizeof(double) * kRedBlocks * kNS));
     w.scal = (DevScal *)take(align_up(sizeof(DevScal)));
     if (ws) *ws = w;
@@ -492,16 +524,18 @@ class Solver {
         c_.lo_s = pb.lo_scalar;
         c_.hi_s = pb.hi_scalar;
         lab_ = pb.labels;
-        act_ = pb.act;
+        t3_ = p_->fast3d();
+        act_ = t3_ ? w.act_int : pb.act;
         lo_ = (const T *)pb.lo;
         hi_ = (const T *)pb.hi;
-        y_ = (T *)pb.y;
+        y_ = t3_ ? (T *)w.y_int : (T *)pb.y;
         lu_ = (T *)pb.lam_up;
         ll_ = (T *)pb.lam_lo;
-        gv_ = std::min<size_t>((nv_ + kThreads * 4 - 1) / (kThreads * 4), kRedBlocks);
-        gs_ = std::min<size_t>((ns_ + kThreads * 4 - 1) / (kThreads * 4), kRedBlocks);
-        gv_ = std::max(gv_, 1);
-        gs_ = std::max(gs_, 1);
+        gv_ = std::max(1, (int)std::min<size_t>((nv_ + kThreads * 4 - 1) / (kThreads * 4), kRedBlocks));
+        gs_ = std::max(1, (int)std::min<size_t>((ns_ + kThreads * 4 - 1) / (kThreads * 4), kRedBlocks));
+    }
+    ~Solver() {
+        if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
     }
 
     int run(sipo_pdhg_result *res);
@@ -516,23 +550,36 @@ class Solver {
     int gv_, gs_;
     LPConst c_;
     const uint8_t *lab_, *act_;
+    bool t3_ = false;     // sinograms held in the internal [view][bin][z] layout
     const T *lo_, *hi_;
     T *y_, *lu_, *ll_;
     double h_norm_ = 0, c_norm_ = 0;
     double Tu_ = 0, Tv_ = 0;
-    double anchor_u_ = 0, anchor_v_ = 0;
     DevScal hs_{};
+    hipGraphExec_t graph_exec_ = nullptr;
+    int graph_len_ = 0;
 
-    // operators
+    template <typename U>
+    void copy(U *dst, const U *src, size_t n, int grid) {
+        hipLaunchKernelGGL((k_copy<U>), dim3(grid), dim3(kThreads), 0, s_, dst, src, n);
+    }
+    T *V(void *p) { return (T *)p; }
+    // operators on the solver's layouts: sinograms as held internally, volumes [z][y][x]
     int dose(const T *y, T *out) {   // out = K P^T y  (uses tmp when K != I)
-        if (!p_->has_psf) return launch_backproject(p_, y, out, 0, s_);
-        int rc = launch_backproject(p_, y, w_.tmp, 0, s_);
+        if (!p_->has_psf) return launch_backproject_t(p_, y, out, 0, s_);
+        int rc = launch_backproject_t(p_, y, w_.tmp, 0, s_);
         return rc ? rc : launch_blur(p_, w_.tmp, out, s_);
     }
     int adjoint(const T *z, T *out) {   // out = P K z
-        if (!p_->has_psf) return launch_project(p_, z, out, 0, s_);
-        int rc = launch_blur(p_, z, w_.tmp, s_);
-        return rc ? rc : launch_project(p_, w_.tmp, out, 0, s_);
+        const void *src = z;
+        if (p_->has_psf) {
+            int rc = launch_blur(p_, z, w_.tmp, s_);
+            if (rc) return rc;
+            src = w_.tmp;
+        }
+        if (!t3_) return launch_project_t(p_, src, out, s_);
+        int rc = launch_vol_to_t(p_, src, w_.vol_t, s_);
+        return rc ? rc : launch_project_t(p_, w_.vol_t, out, s_);
     }
     int sums(int nblocks, int ns, double *host) {
         hipLaunchKernelGGL(finish_sums, dim3(1), dim3(64), 0, s_, w_.partials, nblocks, w_.scal->sums, ns);
@@ -564,59 +611,66 @@ class Solver {
         double rel() const { return std::max(eps_p, std::max(eps_d, eps_gap)); }
         double merit() const { return std::sqrt(eps_p * eps_p + eps_d * eps_d + eps_gap * eps_gap); }
     };
-    // KKT at (y, D, u, v, lambda); z must hold lambda_up - lambda_lo.  Uses q as scratch.
-    int kkt(const T *y, const T *D, double u, double v, const T *lu, const T *ll, const T *z, Kkt *out) {
-        hipLaunchKernelGGL((k_kkt_vox<T>), dim3(gv_), dim3(kThreads), 0, s_, D, lu, ll, lab_, lo_, hi_, c_, u, v,
-                           nv_, w_.partials);
-        double hv[4];
-        int rc = sums(gv_, 4, hv);
-        if (rc) return rc;
-        rc = adjoint(z, (T *)w_.q);
-        if (rc) return rc;
-        hipLaunchKernelGGL((k_kkt_ray<T>), dim3(gs_), dim3(kThreads), 0, s_, (const T *)w_.q, y, act_, ns_,
-                           w_.partials);
-        double hr[2];
-        rc = sums(gs_, 2, hr);
-        if (rc) return rc;
-        double rp2 = hv[0] + hr[1];
-        if (c_.u_free) { const double r = -u; if (r > 0) rp2 += r * r; }
-        if (c_.v_free) { const double r = -v; if (r > 0) rp2 += r * r; }
-        double rd2 = hr[0];
-        if (c_.u_free) { const double r = c_.w1 - hv[2]; if (r < 0) rd2 += r * r; }
-        if (c_.v_free) { const double r = c_.w2 - hv[3]; if (r < 0) rd2 += r * r; }
-        const double pobj = (c_.u_free ? c_.w1 * u : 0.0) + (c_.v_free ? c_.w2 * v : 0.0);
-        double dobj = hv[1];
-        if (!c_.u_free) dobj -= c_.h * hv[2];
-        if (!c_.v_free) dobj -= hv[3];
-        out->r_p = std::sqrt(rp2);
-        out->r_d = std::sqrt(rd2);
-        out->eps_p = out->r_p / (1.0 + h_norm_);
-        out->eps_d = out->r_d / (1.0 + c_norm_);
-        out->eps_gap = std::fabs(pobj - dobj) / (1.0 + std::fabs(pobj) + std::fabs(dobj));
-        out->p = pobj;
-        out->d = dobj;
-        return SIPO_OK;
-    }
+    int kkt(const T *y, const T *D, double u, double v, const T *lu, const T *ll, const T *z, Kkt *out);
     int setup_common();
     int power_norm(int iters, double *nrm);
-    int farkas(double tol, T *zd, bool *ok);
+    int farkas(const T *alu, const T *all, const T *blu, const T *bll, double tol, bool *ok);
+    int iteration(bool check);
+    int run_block(int nblk);
 };
+
+// KKT at (y, D, u, v, lambda); z must hold lambda_up - lambda_lo.  Uses q as scratch.
+template <typename T>
+int Solver<T>::kkt(const T *y, const T *D, double u, double v, const T *lu, const T *ll, const T *z, Kkt *out) {
+    hipLaunchKernelGGL((k_kkt_vox<T>), dim3(gv_), dim3(kThreads), 0, s_, D, lu, ll, lab_, lo_, hi_, c_, u, v, nv_,
+                       w_.partials);
+    double hv[4];
+    int rc = sums(gv_, 4, hv);
+    if (rc) return rc;
+    rc = adjoint(z, V(w_.q));
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_kkt_ray<T>), dim3(gs_), dim3(kThreads), 0, s_, (const T *)w_.q, y, act_, ns_, w_.partials);
+    double hr[2];
+    rc = sums(gs_, 2, hr);
+    if (rc) return rc;
+    double rp2 = hv[0] + hr[1];
+    if (c_.u_free && u < 0) rp2 += u * u;
+    if (c_.v_free && v < 0) rp2 += v * v;
+    double rd2 = hr[0];
+    if (c_.u_free) { const double r = c_.w1 - hv[2]; if (r < 0) rd2 += r * r; }
+    if (c_.v_free) { const double r = c_.w2 - hv[3]; if (r < 0) rd2 += r * r; }
+    const double pobj = (c_.u_free ? c_.w1 * u : 0.0) + (c_.v_free ? c_.w2 * v : 0.0);
+    double dobj = hv[1];
+    if (!c_.u_free) dobj -= c_.h * hv[2];
+    if (!c_.v_free) dobj -= hv[3];
+    out->r_p = std::sqrt(rp2);
+    out->r_d = std::sqrt(rd2);
+    out->eps_p = out->r_p / (1.0 + h_norm_);
+    out->eps_d = out->r_d / (1.0 + c_norm_);
+    out->eps_gap = std::fabs(pobj - dobj) / (1.0 + std::fabs(pobj) + std::fabs(dobj));
+    out->p = pobj;
+    out->d = dobj;
+    return SIPO_OK;
+}
 
 template <typename T>
 int Solver<T>::setup_common() {
-    // sanitise the warm start onto X and the regions; z, lambda sums
+    if (t3_) {
+        int rc = launch_sino_to_t(p_, pb_.y, y_, s_);
+        if (!rc) rc = launch_mask_to_t(p_, pb_.act, (uint8_t *)act_, s_);
+        if (rc) return rc;
+    }
     hipLaunchKernelGGL((k_project_y<T>), dim3(gs_), dim3(kThreads), 0, s_, y_, act_, ns_);
     double l1, ul2;
-    int rc = lambda_z(lu_, ll_, (T *)w_.z, &l1, &ul2);
+    int rc = lambda_z(lu_, ll_, V(w_.z), &l1, &ul2);
     if (rc) return rc;
-    // region sizes and ||h||
-    hipLaunchKernelGGL((k_colweight<T>), dim3(gv_), dim3(kThreads), 0, s_, (T *)w_.tmp2, lab_, nv_);
-    // R = K P^T 1_act -> s_up/s_lo (restarted) ; also |band|, sum U, ||h||^2
-    hipLaunchKernelGGL((k_act_to_float<T>), dim3(gs_), dim3(kThreads), 0, s_, (T *)w_.q, act_, ns_);
-    rc = dose((const T *)w_.q, (T *)w_.Dn);
+    // R = K P^T 1_act -> dual scalings; region sizes, ||h||
+    hipLaunchKernelGGL((k_colweight<T>), dim3(gv_), dim3(kThreads), 0, s_, V(w_.tmp2), lab_, nv_);
+    hipLaunchKernelGGL((k_act_to_float<T>), dim3(gs_), dim3(kThreads), 0, s_, V(w_.q), act_, ns_);
+    rc = dose((const T *)w_.q, V(w_.Dt));
     if (rc) return rc;
-    hipLaunchKernelGGL((k_row_scaling<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)w_.Dn, (T *)w_.s_up,
-                       (T *)w_.s_lo, lab_, lo_, hi_, c_, nv_, w_.partials);
+    hipLaunchKernelGGL((k_row_scaling<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)w_.Dt, V(w_.s_up),
+                       V(w_.s_lo), lab_, lo_, hi_, c_, nv_, w_.partials);
     double hs[4];
     rc = sums(gv_, 4, hs);
     if (rc) return rc;
@@ -624,12 +678,12 @@ int Solver<T>::setup_common() {
     Tv_ = (c_.v_free && hs[1] > 0) ? 1.0 / hs[1] : 0.0;
     h_norm_ = std::sqrt(hs[2]);
     c_norm_ = std::hypot(c_.u_free ? c_.w1 : 0.0, c_.v_free ? c_.w2 : 0.0);
-    // column scaling T_j = 1 / (P K w)_j
-    rc = adjoint((const T *)w_.tmp2, (T *)w_.Tj);
+    // primal scaling T_j = 1 / (P K w)_j
+    rc = adjoint((const T *)w_.tmp2, V(w_.Tj));
     if (rc) return rc;
-    hipLaunchKernelGGL((k_inv_colsum<T>), dim3(gs_), dim3(kThreads), 0, s_, (T *)w_.Tj, act_, ns_);
-    // D = K P^T y (current dose)
-    rc = dose(y_, (T *)w_.D);
+    hipLaunchKernelGGL((k_inv_colsum<T>), dim3(gs_), dim3(kThreads), 0, s_, V(w_.Tj), act_, ns_);
+    // D = K P^T y
+    rc = dose(y_, V(w_.D));
     if (rc) return rc;
     std::memset(&hs_, 0, sizeof(hs_));
     hs_.u = c_.u_free ? std::max(0.0, pb_.u0) : c_.h;
@@ -641,8 +695,7 @@ int Solver<T>::setup_common() {
 
 template <typename T>
 int Solver<T>::power_norm(int iters, double *nrm) {
-    // x = (act, 1, 1) normalised
-    T *y = (T *)w_.y_avg;   // scratch sinogram
+    T *y = V(w_.y0);   // scratch sinogram
     hipLaunchKernelGGL((k_act_to_float<T>), dim3(gs_), dim3(kThreads), 0, s_, y, act_, ns_);
     hipLaunchKernelGGL((k_pi_mask<T>), dim3(gs_), dim3(kThreads), 0, s_, y, (const T *)y, act_, ns_, w_.partials);
     double yy;
@@ -656,14 +709,14 @@ int Solver<T>::power_norm(int iters, double *nrm) {
     v /= nr;
     double lam = 0.0;
     for (int it = 0; it < iters; ++it) {
-        rc = dose(y, (T *)w_.Dn);
+        rc = dose(y, V(w_.Dt));
         if (rc) return rc;
-        hipLaunchKernelGGL((k_pi_rows<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)w_.Dn, (T *)w_.tmp2, lab_,
-                           hi_, c_, u, v, nv_, w_.partials);
+        hipLaunchKernelGGL((k_pi_rows<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)w_.Dt, V(w_.tmp2), lab_, hi_,
+                           c_, u, v, nv_, w_.partials);
         double rs[2];
         rc = sums(gv_, 2, rs);
         if (rc) return rc;
-        rc = adjoint((const T *)w_.tmp2, (T *)w_.q);
+        rc = adjoint((const T *)w_.tmp2, V(w_.q));
         if (rc) return rc;
         hipLaunchKernelGGL((k_pi_mask<T>), dim3(gs_), dim3(kThreads), 0, s_, y, (const T *)w_.q, act_, ns_,
                            w_.partials);
@@ -680,12 +733,13 @@ int Solver<T>::power_norm(int iters, double *nrm) {
     return SIPO_OK;
 }
 
-// Farkas test of d = max(lambda - snapshot, 0) (see k_ray_candidate); ok = certificate accepted.
+// Farkas test of the candidate d = max(a - b, 0): scaled to dual objective 1, every
+// reduced-cost violation must be <= tol.  Uses tmp2 (z_d) and q.
 template <typename T>
-int Solver<T>::farkas(double tol, T *zd, bool *ok) {
+int Solver<T>::farkas(const T *alu, const T *all, const T *blu, const T *bll, double tol, bool *ok) {
     *ok = false;
-    hipLaunchKernelGGL((k_ray_candidate<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)lu_, (const T *)ll_,
-                       (const T *)w_.lu_snap, (const T *)w_.ll_snap, zd, lab_, lo_, hi_, c_, nv_, w_.partials);
+    hipLaunchKernelGGL((k_ray_candidate<T>), dim3(gv_), dim3(kThreads), 0, s_, alu, all, blu, bll, V(w_.tmp2), lab_,
+                       lo_, hi_, c_, nv_, w_.partials);
     double r[4];
     int rc = sums(gv_, 4, r);
     if (rc) return rc;
@@ -693,19 +747,72 @@ int Solver<T>::farkas(double tol, T *zd, bool *ok) {
     if (!c_.u_free) ray_obj -= c_.h * r[1];
     if (!c_.v_free) ray_obj -= r[2];
     if (!(ray_obj > 0) || !(r[3] > 0)) return SIPO_OK;
-    // scale to ray_obj = 1 and test the reduced costs
     const double worst_u = c_.u_free ? r[1] / ray_obj : 0.0;
     const double worst_v = c_.v_free ? r[2] / ray_obj : 0.0;
-    rc = adjoint((const T *)zd, (T *)w_.q);
+    if (std::max(worst_u, worst_v) > tol) return SIPO_OK;
+    rc = adjoint((const T *)w_.tmp2, V(w_.q));
     if (rc) return rc;
     hipLaunchKernelGGL((k_ray_check<T>), dim3(gs_), dim3(kThreads), 0, s_, (const T *)w_.q, act_, ns_, w_.partials);
     hipLaunchKernelGGL(finish_max, dim3(1), dim3(64), 0, s_, w_.partials, gs_, w_.scal->sums);
     double m[2];
     SIPO_HIP(hipMemcpyAsync(m, w_.scal->sums, sizeof(m), hipMemcpyDeviceToHost, s_));
     SIPO_HIP(hipStreamSynchronize(s_));
-    const double worst_q = m[0] / ray_obj;
-    const double worst = std::max(worst_q, std::max(worst_u, worst_v));
-    *ok = worst <= tol;
+    *ok = m[0] / ray_obj <= tol;
+    return SIPO_OK;
+}
+
+// One iteration: t = T(z), z <- Halpern update.  On check iterations t.lambda and the
+// pre-step lambda are written out.
+template <typename T>
+int Solver<T>::iteration(bool check) {
+    const bool hal = o_.mode == SIPO_PDHG_RESTARTED;
+    int rc = adjoint((const T *)w_.z, V(w_.q));
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_primal<T>), dim3(gs_), dim3(kThreads), 0, s_, y_, V(w_.yt), (const T *)w_.q,
+                       hal ? (const T *)w_.Tj : (const T *)nullptr, act_, hal ? (const T *)w_.y0 : (const T *)nullptr,
+                       (const DevScal *)w_.scal, ns_);
+    rc = dose((const T *)w_.yt, V(w_.Dt));
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_dual<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)w_.Dt, V(w_.D),
+                       hal ? (const T *)w_.D0 : (const T *)nullptr, lu_, ll_,
+                       hal ? (const T *)w_.lu0 : (const T *)nullptr, hal ? (const T *)w_.ll0 : (const T *)nullptr,
+                       V(w_.z), lab_, lo_, hi_, hal ? (const T *)w_.s_up : (const T *)nullptr,
+                       hal ? (const T *)w_.s_lo : (const T *)nullptr, check ? V(w_.lut) : (T *)nullptr,
+                       check ? V(w_.llt) : (T *)nullptr, check ? V(w_.luo) : (T *)nullptr,
+                       check ? V(w_.llo) : (T *)nullptr, (const DevScal *)w_.scal, c_, nv_, w_.partials);
+    hipLaunchKernelGGL(k_scalars, dim3(1), dim3(64), 0, s_, w_.partials, gv_, w_.scal, c_);
+    return SIPO_OK;
+}
+
+// nblk iterations, the last one a check iteration; captured once into a graph when requested.
+template <typename T>
+int Solver<T>::run_block(int nblk) {
+    if (!o_.use_graph) {
+        for (int j = 0; j < nblk; ++j) {
+            int rc = iteration(j == nblk - 1);
+            if (rc) return rc;
+        }
+        SIPO_LAUNCHED("pdhg iteration");
+        return SIPO_OK;
+    }
+    if (!graph_exec_ || graph_len_ != nblk) {
+        if (graph_exec_) {
+            SIPO_HIP(hipGraphExecDestroy(graph_exec_));
+            graph_exec_ = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        SIPO_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+        int rc = SIPO_OK;
+        for (int j = 0; j < nblk && rc == SIPO_OK; ++j) rc = iteration(j == nblk - 1);
+        hipError_t e = hipStreamEndCapture(s_, &g);
+        if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+        if (e != hipSuccess) return fail(SIPO_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&graph_exec_, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(SIPO_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+        graph_len_ = nblk;
+    }
+    SIPO_HIP(hipGraphLaunch(graph_exec_, s_));
     return SIPO_OK;
 }
 
@@ -715,11 +822,11 @@ int Solver<T>::run(sipo_pdhg_result *res) {
     std::memset(res, 0, sizeof(*res));
     int rc = setup_common();
     if (rc) return rc;
-    const bool restarted = o_.mode == SIPO_PDHG_RESTARTED;
+    const bool hal = o_.mode == SIPO_PDHG_RESTARTED;
     double omega = 1.0;
     const double eta = o_.eta > 0 ? o_.eta : 0.95;
     double tau = o_.tau, sigma = o_.sigma;
-    if (!restarted) {
+    if (!hal) {
         if (!(tau > 0 && sigma > 0)) {
             double nrm = 0;
             rc = power_norm(o_.power_iters > 0 ? o_.power_iters : 100, &nrm);
@@ -731,71 +838,52 @@ int Solver<T>::run(sipo_pdhg_result *res) {
         hs_.sig_fac = sigma;
         hs_.tau_u = tau;
         hs_.tau_v = tau;
+        hs_.halpern = 0.0;
+        hs_.rho = 0.0;
     } else {
         hs_.tau_fac = eta / omega;
         hs_.sig_fac = eta * omega;
         hs_.tau_u = eta * Tu_ / omega;
         hs_.tau_v = eta * Tv_ / omega;
+        hs_.halpern = 1.0;
+        hs_.rho = 1.0;
     }
-    hs_.n_avg = 1.0;
-    hs_.avg_w = 1.0;
-    hs_.u_avg = hs_.u;
-    hs_.v_avg = hs_.v;
-    anchor_u_ = hs_.u;
-    anchor_v_ = hs_.v;
+    hs_.u0 = hs_.u;
+    hs_.v0 = hs_.v;
+    double last_u = hs_.u, last_v = hs_.v;
     rc = put_scal();
     if (rc) return rc;
     hipLaunchKernelGGL(k_scalars_init, dim3(1), dim3(1), 0, s_, w_.scal, c_);
-    // averages / anchor / snapshot start at the initial point
-    if (restarted) {
-        hipLaunchKernelGGL((k_copy<T>), dim3(gs_), dim3(kThreads), 0, s_, (T *)w_.y_avg, (const T *)y_, ns_);
-        hipLaunchKernelGGL((k_copy<T>), dim3(gs_), dim3(kThreads), 0, s_, (T *)w_.y_anchor, (const T *)y_, ns_);
-        for (auto pr : {std::make_pair(w_.lu_avg, (void *)lu_), std::make_pair(w_.ll_avg, (void *)ll_),
-                        std::make_pair(w_.lu_anchor, (void *)lu_), std::make_pair(w_.ll_anchor, (void *)ll_),
-                        std::make_pair(w_.lu_snap, (void *)lu_), std::make_pair(w_.ll_snap, (void *)ll_)})
-            hipLaunchKernelGGL((k_copy<T>), dim3(gv_), dim3(kThreads), 0, s_, (T *)pr.first, (const T *)pr.second, nv_);
+    if (hal) {
+        // anchor, restart point and snapshot start at the initial point
+        copy(V(w_.y0), (const T *)y_, ns_, gs_);
+        copy(V(w_.ylast), (const T *)y_, ns_, gs_);
+        copy(V(w_.D0), (const T *)w_.D, nv_, gv_);
+        for (void *dst : {w_.lu0, w_.lul, w_.snap_u}) copy(V(dst), (const T *)lu_, nv_, gv_);
+        for (void *dst : {w_.ll0, w_.lll, w_.snap_l}) copy(V(dst), (const T *)ll_, nv_, gv_);
     }
     SIPO_LAUNCHED("pdhg setup");
 
-    T *D = (T *)w_.D, *Dn = (T *)w_.Dn;
-    const T *Tj = restarted ? (const T *)w_.Tj : nullptr;
-    const T *su = restarted ? (const T *)w_.s_up : nullptr;
-    const T *sl = restarted ? (const T *)w_.s_lo : nullptr;
-    T *y_avg = restarted ? (T *)w_.y_avg : nullptr;
-    T *lu_avg = restarted ? (T *)w_.lu_avg : nullptr;
-    T *ll_avg = restarted ? (T *)w_.ll_avg : nullptr;
-    const int check = restarted ? std::max(1, o_.check_every) : o_.max_iters;
-    Kkt k0{};
+    const int check = hal ? std::max(1, o_.check_every) : o_.max_iters;
+    const double itol = o_.infeas_tol > 0 ? o_.infeas_tol : 1e-6;
+    int status = SIPO_ITER_LIMIT, restarts = 0, it = 0, k_restart = 0;
+    Kkt kc{};
     double m_anchor = 0, m_prev = 1e300;
-    int k_restart = 0, restarts = 0;
-    int status = SIPO_ITER_LIMIT;
-    int it = 0;
-    bool use_avg_final = false;
-    Kkt final_kkt{};
-    if (restarted) {
-        rc = kkt(y_, D, hs_.u, hs_.v, lu_, ll_, (const T *)w_.z, &k0);
+    bool have_t = false;          // lut/llt/yt/Dt/ut_done hold a PDHG output t
+    const T *cert_a_u = nullptr, *cert_a_l = nullptr, *cert_b_u = nullptr, *cert_b_l = nullptr;
+    if (hal) {
+        Kkt k0{};
+        rc = kkt(y_, (const T *)w_.D, hs_.u, hs_.v, lu_, ll_, (const T *)w_.z, &k0);
         if (rc) return rc;
         m_anchor = k0.merit();
     }
     while (it < o_.max_iters) {
         const int nblk = std::min(check, o_.max_iters - it);
-        for (int j = 0; j < nblk; ++j) {
-            rc = adjoint((const T *)w_.z, (T *)w_.q);
-            if (rc) return rc;
-            hipLaunchKernelGGL((k_primal<T>), dim3(gs_), dim3(kThreads), 0, s_, y_, (const T *)w_.q, Tj, act_, y_avg,
-                               (const DevScal *)w_.scal, ns_);
-            rc = dose(y_, Dn);
-            if (rc) return rc;
-            hipLaunchKernelGGL((k_dual<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)Dn, (const T *)D, lu_, ll_,
-                               (T *)w_.z, lab_, lo_, hi_, su, sl, lu_avg, ll_avg, (const DevScal *)w_.scal, c_, nv_,
-                               w_.partials);
-            hipLaunchKernelGGL(k_scalars, dim3(1), dim3(64), 0, s_, w_.partials, gv_, w_.scal, c_);
-            std::swap(D, Dn);
-        }
-        SIPO_LAUNCHED("pdhg iteration");
+        rc = run_block(nblk);
+        if (rc) return rc;
         it += nblk;
-        if (!restarted) break;
-        // ---------------- check: KKT of current and average
+        have_t = true;
+        if (!hal) break;
         rc = get_scal();
         if (rc) return rc;
         if (!std::isfinite(hs_.u) || !std::isfinite(hs_.v) || !std::isfinite(hs_.sum_l1) ||
@@ -803,126 +891,118 @@ int Solver<T>::run(sipo_pdhg_result *res) {
             status = SIPO_NUMERICAL;
             break;
         }
-        Kkt kc{}, ka{};
-        rc = kkt(y_, D, hs_.u, hs_.v, lu_, ll_, (const T *)w_.z, &kc);
+        // KKT of the PDHG output t; z_lambda(t) into tmp2
+        double tl1, tul2;
+        rc = lambda_z(V(w_.lut), V(w_.llt), V(w_.tmp2), &tl1, &tul2);
+        if (rc) return rc;
+        rc = kkt((const T *)w_.yt, (const T *)w_.Dt, hs_.ut_done, hs_.vt_done, (const T *)w_.lut,
+                 (const T *)w_.llt, (const T *)w_.tmp2, &kc);
         if (rc) return rc;
         if (!std::isfinite(kc.r_p) || !std::isfinite(kc.r_d)) { status = SIPO_NUMERICAL; break; }
-        // average: D_avg into tmp2, z_avg into Dn (Dn is free between iterations)
-        rc = dose((const T *)y_avg, (T *)w_.tmp2);
+        if (kc.rel() <= o_.tol) { status = SIPO_OPTIMAL; break; }
+        bool inf = false;
+        rc = farkas((const T *)w_.lut, (const T *)w_.llt, (const T *)w_.luo, (const T *)w_.llo, itol, &inf);
         if (rc) return rc;
-        double al1, aul2;
-        rc = lambda_z(lu_avg, ll_avg, Dn, &al1, &aul2);
-        if (rc) return rc;
-        rc = kkt(y_avg, (const T *)w_.tmp2, hs_.u_avg, hs_.v_avg, lu_avg, ll_avg, Dn, &ka);
-        if (rc) return rc;
-        if (kc.rel() <= o_.tol) { status = SIPO_OPTIMAL; final_kkt = kc; break; }
-        if (ka.rel() <= o_.tol) { status = SIPO_OPTIMAL; final_kkt = ka; use_avg_final = true; break; }
-        bool infeasible = false;
-        rc = farkas(o_.infeas_tol > 0 ? o_.infeas_tol : 1e-6, Dn, &infeasible);   // Dn is free here
-        if (rc) return rc;
-        if (infeasible) {
-            status = SIPO_PRIMAL_INFEASIBLE;
-            final_kkt = kc;
-            break;
+        if (inf) {
+            cert_a_u = (const T *)w_.lut; cert_a_l = (const T *)w_.llt;
+            cert_b_u = (const T *)w_.luo; cert_b_l = (const T *)w_.llo;
+        } else {
+            rc = farkas((const T *)w_.lut, (const T *)w_.llt, (const T *)w_.snap_u, (const T *)w_.snap_l, itol, &inf);
+            if (rc) return rc;
+            if (inf) {
+                cert_a_u = (const T *)w_.lut; cert_a_l = (const T *)w_.llt;
+                cert_b_u = (const T *)w_.snap_u; cert_b_l = (const T *)w_.snap_l;
+            }
         }
-        hipLaunchKernelGGL((k_copy<T>), dim3(gv_), dim3(kThreads), 0, s_, (T *)w_.lu_snap, (const T *)lu_, nv_);
-        hipLaunchKernelGGL((k_copy<T>), dim3(gv_), dim3(kThreads), 0, s_, (T *)w_.ll_snap, (const T *)ll_, nv_);
-        const double mc = kc.merit(), ma = ka.merit();
-        const bool use_avg = ma < mc;
-        const double mcand = std::min(ma, mc);
-        const bool do_restart = mcand <= 0.2 * m_anchor || (mcand <= 0.8 * m_anchor && mcand > m_prev) ||
-                                (double)(it - k_restart) >= 0.36 * (double)it;
-        m_prev = mcand;
-        if (!do_restart) continue;
-        if (use_avg) {
-            hipLaunchKernelGGL((k_copy<T>), dim3(gs_), dim3(kThreads), 0, s_, y_, (const T *)y_avg, ns_);
-            hipLaunchKernelGGL((k_copy<T>), dim3(gv_), dim3(kThreads), 0, s_, lu_, (const T *)lu_avg, nv_);
-            hipLaunchKernelGGL((k_copy<T>), dim3(gv_), dim3(kThreads), 0, s_, ll_, (const T *)ll_avg, nv_);
-            hipLaunchKernelGGL((k_copy<T>), dim3(gv_), dim3(kThreads), 0, s_, D, (const T *)w_.tmp2, nv_);
-            hs_.u = hs_.u_avg;
-            hs_.v = hs_.v_avg;
+        if (inf) { status = SIPO_PRIMAL_INFEASIBLE; break; }
+        copy(V(w_.snap_u), (const T *)w_.lut, nv_, gv_);
+        copy(V(w_.snap_l), (const T *)w_.llt, nv_, gv_);
+        const double m = kc.merit();
+        if (!(m <= 0.2 * m_anchor || (m <= 0.8 * m_anchor && m > m_prev) ||
+              (double)(it - k_restart) >= 0.36 * (double)it)) {
+            m_prev = m;
+            continue;
         }
-        // movement since the previous restart, in the scaled norms
+        // ---- restart at t: movement since the previous restart -> primal weight
         double dy2, dlu2, dll2;
-        hipLaunchKernelGGL((k_wdist<T>), dim3(gs_), dim3(kThreads), 0, s_, (const T *)y_, (const T *)w_.y_anchor,
+        hipLaunchKernelGGL((k_wdist<T>), dim3(gs_), dim3(kThreads), 0, s_, (const T *)w_.yt, (const T *)w_.ylast,
                            (const T *)w_.Tj, ns_, w_.partials);
         rc = sums(gs_, 1, &dy2);
         if (rc) return rc;
-        hipLaunchKernelGGL((k_wdist<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)lu_, (const T *)w_.lu_anchor,
+        hipLaunchKernelGGL((k_wdist<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)w_.lut, (const T *)w_.lul,
                            (const T *)w_.s_up, nv_, w_.partials);
         rc = sums(gv_, 1, &dlu2);
         if (rc) return rc;
-        hipLaunchKernelGGL((k_wdist<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)ll_, (const T *)w_.ll_anchor,
+        hipLaunchKernelGGL((k_wdist<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)w_.llt, (const T *)w_.lll,
                            (const T *)w_.s_lo, nv_, w_.partials);
         rc = sums(gv_, 1, &dll2);
         if (rc) return rc;
-        const double du = hs_.u - anchor_u_, dv = hs_.v - anchor_v_;
-        double dx2 = dy2 + (Tu_ > 0 ? du * du / Tu_ : 0.0) + (Tv_ > 0 ? dv * dv / Tv_ : 0.0);
-        const double dx = std::sqrt(dx2), dl = std::sqrt(dlu2 + dll2);
+        const double du = hs_.ut_done - last_u, dv = hs_.vt_done - last_v;
+        const double dx = std::sqrt(dy2 + (Tu_ > 0 ? du * du / Tu_ : 0.0) + (Tv_ > 0 ? dv * dv / Tv_ : 0.0));
+        const double dl = std::sqrt(dlu2 + dll2);
         if (dx > 1e-10 && dl > 1e-10) omega = std::exp(0.5 * std::log(dl / dx) + 0.5 * std::log(omega));
-        // new anchor / average start / z and lambda sums of the restart point
-        hipLaunchKernelGGL((k_copy<T>), dim3(gs_), dim3(kThreads), 0, s_, (T *)w_.y_anchor, (const T *)y_, ns_);
-        hipLaunchKernelGGL((k_copy<T>), dim3(gs_), dim3(kThreads), 0, s_, (T *)w_.y_avg, (const T *)y_, ns_);
-        for (auto pr : {std::make_pair(w_.lu_anchor, (void *)lu_), std::make_pair(w_.ll_anchor, (void *)ll_),
-                        std::make_pair(w_.lu_avg, (void *)lu_), std::make_pair(w_.ll_avg, (void *)ll_)})
-            hipLaunchKernelGGL((k_copy<T>), dim3(gv_), dim3(kThreads), 0, s_, (T *)pr.first, (const T *)pr.second, nv_);
+        // z, z0 and the restart point become t
+        for (void *dst : {(void *)y_, w_.y0, w_.ylast}) copy(V(dst), (const T *)w_.yt, ns_, gs_);
+        for (void *dst : {(void *)lu_, w_.lu0, w_.lul}) copy(V(dst), (const T *)w_.lut, nv_, gv_);
+        for (void *dst : {(void *)ll_, w_.ll0, w_.lll}) copy(V(dst), (const T *)w_.llt, nv_, gv_);
+        for (void *dst : {w_.D, w_.D0}) copy(V(dst), (const T *)w_.Dt, nv_, gv_);
         double l1, ul2;
-        rc = lambda_z(lu_, ll_, (T *)w_.z, &l1, &ul2);
+        rc = lambda_z(lu_, ll_, V(w_.z), &l1, &ul2);
         if (rc) return rc;
+        hs_.u = hs_.u0 = last_u = hs_.ut_done;
+        hs_.v = hs_.v0 = last_v = hs_.vt_done;
         hs_.sums[0] = l1;
         hs_.sums[1] = ul2;
-        anchor_u_ = hs_.u;
-        anchor_v_ = hs_.v;
         hs_.tau_fac = eta / omega;
         hs_.sig_fac = eta * omega;
         hs_.tau_u = eta * Tu_ / omega;
         hs_.tau_v = eta * Tv_ / omega;
-        hs_.n_avg = 1.0;
-        hs_.avg_w = 1.0;
-        hs_.u_avg = hs_.u;
-        hs_.v_avg = hs_.v;
         rc = put_scal();
         if (rc) return rc;
         hipLaunchKernelGGL(k_scalars_init, dim3(1), dim3(1), 0, s_, w_.scal, c_);
-        m_anchor = use_avg ? ka.merit() : kc.merit();
+        m_anchor = m;
         m_prev = 1e300;
         k_restart = it;
         ++restarts;
     }
-    // ---------------- final point
+    // ---------------- returned point: the PDHG output t (restarted) or z = t (plain)
     rc = get_scal();
     if (rc) return rc;
     double u = hs_.u, v = hs_.v;
-    if (use_avg_final) {
-        hipLaunchKernelGGL((k_copy<T>), dim3(gs_), dim3(kThreads), 0, s_, y_, (const T *)y_avg, ns_);
-        hipLaunchKernelGGL((k_copy<T>), dim3(gv_), dim3(kThreads), 0, s_, lu_, (const T *)lu_avg, nv_);
-        hipLaunchKernelGGL((k_copy<T>), dim3(gv_), dim3(kThreads), 0, s_, ll_, (const T *)ll_avg, nv_);
-        hipLaunchKernelGGL((k_copy<T>), dim3(gv_), dim3(kThreads), 0, s_, D, (const T *)w_.tmp2, nv_);
-        u = hs_.u_avg;
-        v = hs_.v_avg;
+    if (hal && have_t) {
+        u = hs_.ut_done;
+        v = hs_.vt_done;
+        copy(y_, (const T *)w_.yt, ns_, gs_);
+        copy(V(w_.D), (const T *)w_.Dt, nv_, gv_);
+        if (status == SIPO_PRIMAL_INFEASIBLE) {
+            hipLaunchKernelGGL((k_certificate<T>), dim3(gv_), dim3(kThreads), 0, s_, lu_, ll_, cert_a_u, cert_a_l,
+                               cert_b_u, cert_b_l, lab_, nv_);
+        } else {
+            copy(lu_, (const T *)w_.lut, nv_, gv_);
+            copy(ll_, (const T *)w_.llt, nv_, gv_);
+        }
     }
-    if (status == SIPO_PRIMAL_INFEASIBLE) {
-        // the certificate d = max(lambda - snapshot, 0) replaces lambda; the KKT fields keep the last iterate's
-        hipLaunchKernelGGL((k_certificate<T>), dim3(gv_), dim3(kThreads), 0, s_, lu_, ll_, (const T *)w_.lu_snap,
-                           (const T *)w_.ll_snap, lab_, nv_);
-    } else if (status != SIPO_OPTIMAL) {
-        hipLaunchKernelGGL((k_lambda_z<T>), dim3(gv_), dim3(kThreads), 0, s_, lu_, ll_, (T *)w_.z, lab_, hi_, c_, nv_,
+    if (status == SIPO_ITER_LIMIT || status == SIPO_NUMERICAL || !hal) {
+        hipLaunchKernelGGL((k_lambda_z<T>), dim3(gv_), dim3(kThreads), 0, s_, lu_, ll_, V(w_.z), lab_, hi_, c_, nv_,
                            w_.partials);
-        rc = kkt(y_, D, u, v, lu_, ll_, (const T *)w_.z, &final_kkt);
+        rc = kkt(y_, (const T *)w_.D, u, v, lu_, ll_, (const T *)w_.z, &kc);
         if (rc) return rc;
     }
-    if (pb_.dose_out) {
-        hipLaunchKernelGGL((k_copy<T>), dim3(gv_), dim3(kThreads), 0, s_, (T *)pb_.dose_out, (const T *)D, nv_);
+    if (pb_.dose_out) copy((T *)pb_.dose_out, (const T *)w_.D, nv_, gv_);
+    if (t3_) {
+        rc = launch_sino_from_t(p_, y_, pb_.y, 0, s_);
+        if (rc) return rc;
     }
+    SIPO_LAUNCHED("pdhg finish");
     SIPO_HIP(hipStreamSynchronize(s_));
     res->status = status;
     res->iters = it;
     res->restarts = restarts;
-    res->primal_obj = final_kkt.p;
-    res->dual_obj = final_kkt.d;
-    res->rel_primal = final_kkt.eps_p;
-    res->rel_dual = final_kkt.eps_d;
-    res->rel_gap = final_kkt.eps_gap;
+    res->primal_obj = kc.p;
+    res->dual_obj = kc.d;
+    res->rel_primal = kc.eps_p;
+    res->rel_dual = kc.eps_d;
+    res->rel_gap = kc.eps_gap;
     res->u = u;
     res->v = v;
     res->tau = tau;
@@ -974,12 +1054,12 @@ int sipo_pdhg_solve(const sipo_problem *probs, int32_t n, const sipo_pdhg_option
     SIPO_REQUIRE(workspace != nullptr, "workspace is NULL");
     if (ws_bytes < need) return fail(SIPO_E_WORKSPACE, "workspace of %zu bytes < %zu required", ws_bytes, need);
     hipStream_t s = (hipStream_t)stream;
+    SIPO_REQUIRE(!(opts->use_graph && s == nullptr), "graph capture needs a non-default stream");
     for (int i = 0; i < n; ++i) {
         Workspace w;
         layout(probs[i], &w, (char *)workspace);
-        int rc = probs[i].plan->dtype == SIPO_F64
-                     ? Solver<double>(probs[i], *opts, w, s).run(&results[i])
-                     : Solver<float>(probs[i], *opts, w, s).run(&results[i]);
+        int rc = probs[i].plan->dtype == SIPO_F64 ? Solver<double>(probs[i], *opts, w, s).run(&results[i])
+                                                  : Solver<float>(probs[i], *opts, w, s).run(&results[i]);
         if (rc) return rc;
     }
     return SIPO_OK;

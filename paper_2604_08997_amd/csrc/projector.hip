@@ -1,16 +1,36 @@
 // Backprojector P^T and projector P (Eq. 2-3): gathers in both directions.
 //
-// P^T: one thread per voxel column (x, y) and a chunk of ZC slices; the
-//      per-view taps are computed once and reused for every slice of the
-//      chunk, and the two sinogram samples of each tap pair are gathered.
-// P:   one thread per detector bin and view and a chunk of ZC slices; the
-//      ray is walked along its major axis and, per step, the few voxels
-//      whose taps can reach the bin are tested with the same tap function
-//      as P^T, which makes P the exact transpose of P^T.
+// Slice kernels (nz == 1, and the general fallback):
+//   P^T: one thread per voxel (x, y) and a chunk of ZC slices; per view the two
+//        interpolation taps are computed once and the two sinogram samples
+//        of every slice in the chunk are gathered.
+//   P:   one thread per (bin, view) and a chunk of ZC slices; the ray is
+//        walked along its major axis and, per step, the few voxels whose taps
+//        can reach the bin are tested with the same tap function as P^T.
+//
+// Volume kernels (nz > 1): LDS-staged, z-contiguous layouts (see below).
+#include <algorithm>
+#include <vector>
+
 #include "sipo_internal.hpp"
 
 namespace sipo {
 
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> { using type = float4; };
+template <>
+struct Vec4<double> { using type = double4; };
+
+// Exact integer form of "voxel centre inside the closed unit disk":
+// ((2c+1-n)^2 + (2r+1-n)^2 <= n^2) <=> x^2 + y^2 <= 1 with x = -1 + (c+1/2) 2/n.
+__device__ __forceinline__ bool vial_ij(int c, int r, int n) {
+    const long long a = 2LL * c + 1 - n, b = 2LL * r + 1 - n;
+    return a * a + b * b <= (long long)n * n;
+}
+
+// ------------------------------------------------------------- slice kernels
 template <typename T, int ZC>
 __global__ void __launch_bounds__(256) backproject_kernel(const T *__restrict__ sino, T *__restrict__ vol, int n,
                                                           int nz, int n_angles, int nb,
@@ -25,7 +45,7 @@ __global__ void __launch_bounds__(256) backproject_kernel(const T *__restrict__ 
 #pragma unroll
     for (int k = 0; k < ZC; ++k) acc[k] = (T)0;
     const int zc = min(ZC, nz - z0);
-    if (fma(x, x, y * y) <= 1.0) {
+    if (vial_ij(c, r, n)) {
         for (int a = 0; a < n_angles; ++a) {
             const double2 tr = trig[a];
             T w0, w1;
@@ -74,8 +94,7 @@ __global__ void __launch_bounds__(256) project_kernel(const T *__restrict__ vol,
     const double lo_t = (double)b - 1.0, hi_t = (double)b + 1.0;
     const double c0 = centre(0, h);
     for (int i = 0; i < n; ++i) {
-        const double pm = centre(i, h);  // coordinate along the major axis
-        // detector coordinate at minor index 0
+        const double pm = centre(i, h);
         const double s0 = xmajor ? fma(-pm, sn, c0 * cs) : fma(-c0, sn, pm * cs);
         const double U = fma(s0 + 1.0, inv_ds, -0.5);
         double j1 = (lo_t - U) / du, j2 = (hi_t - U) / du;
@@ -86,8 +105,8 @@ __global__ void __launch_bounds__(256) project_kernel(const T *__restrict__ vol,
         for (int j = jlo; j <= jhi; ++j) {
             const int c = xmajor ? i : j;
             const int r = xmajor ? j : i;
+            if (!vial_ij(c, r, n)) continue;
             const double x = centre(c, h), y = centre(r, h);
-            if (fma(x, x, y * y) > 1.0) continue;
             T w0, w1;
             const int bv = taps<T>(x, y, sn, cs, inv_ds, atten, w0, w1);
             T w;
@@ -109,8 +128,373 @@ __global__ void __launch_bounds__(256) project_kernel(const T *__restrict__ vol,
     }
 }
 
+// ------------------------------------------------------------------ 3D P^T
+// Input sinogram [view][bin][z].  One workgroup = a 32 x 16 voxel tile and ZC
+// slices; 256 threads, each owning two voxels (rows ty, ty + 8) and ZC slices
+// in registers.  Views go in batches of kBpTB: for each view the bins the tile
+// can reach (floor(u_min) - 1 .. floor(u_max) + 2 over the tile, at most kBpW)
+// are copied into LDS as [view][bin][z] rows -- a straight copy of
+// z-contiguous 16-byte chunks -- padded by 4 elements so that the rows read
+// by the 16 lanes of one LDS pass land in different banks.  A voxel then reads
+// four slices of each tap bin per 128-bit load.  Bins outside the detector are
+// staged as zeros, so the inner loop has no bounds tests.
+constexpr int kBpTX = 32, kBpTY = 16, kBpTB = 6, kBpW = 40;
+
+static bool bp3d_fits(int n, int nb) {
+    const double span = std::sqrt((double)(kBpTX - 1) * (kBpTX - 1) + (double)(kBpTY - 1) * (kBpTY - 1)) * nb / n;
+    return span + 5.0 <= (double)kBpW;
+}
+
+template <typename T, int ZC>
+__global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict__ sino_t, T *__restrict__ vol, int n,
+                                                            int nz, int n_angles, int nb,
+                                                            const double2 *__restrict__ trig, double h,
+                                                            double inv_ds, T atten, int accumulate) {
+    using V4 = typename Vec4<T>::type;
+    constexpr int Z4 = ZC / 4, ZP = ZC + 4;
+    __shared__ __align__(16) T lds[kBpTB][kBpW][ZP];
+    __shared__ int bmin_s[kBpTB];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int x0 = blockIdx.x * kBpTX, y0 = blockIdx.y * kBpTY, z0 = blockIdx.z * ZC;
+    const int c = x0 + tx;
+    const int r[2] = {y0 + ty, y0 + ty + 8};
+    const double xv = centre(c, h);
+    const double yv[2] = {centre(r[0], h), centre(r[1], h)};
+    bool inside[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) inside[j] = c < n && r[j] < n && vial_ij(c, r[j], n);
+    T acc[2][ZC];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int k = 0; k < ZC; ++k) acc[j][k] = (T)0;
+    const bool vec_ok = (nz & 3) == 0;
+    const int cx1 = min(x0 + kBpTX, n) - 1, cy1 = min(y0 + kBpTY, n) - 1;
+    for (int a0 = 0; a0 < n_angles; a0 += kBpTB) {
+        const int na = min(kBpTB, n_angles - a0);
+        if ((int)threadIdx.x < na) {
+            const double2 tr = trig[a0 + threadIdx.x];
+            double umin = 1e300;
+            const int cs_[2] = {x0, cx1}, rs_[2] = {y0, cy1};
+            for (int i = 0; i < 2; ++i)
+                for (int k = 0; k < 2; ++k) {
+                    const double s = fma(-centre(cs_[i], h), tr.x, centre(rs_[k], h) * tr.y);
+                    umin = fmin(umin, fma(s + 1.0, inv_ds, -0.5));
+                }
+            bmin_s[threadIdx.x] = (int)floor(umin) - 1;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < na * kBpW * Z4; e += 256) {
+            const int z4 = e % Z4;
+            const int rest = e / Z4;
+            const int b = rest % kBpW;
+            const int k = rest / kBpW;
+            const int gb = bmin_s[k] + b, gz = z0 + 4 * z4;
+            V4 v;
+            T *vv = (T *)&v;
+            if (gb >= 0 && gb < nb) {
+                const T *src = sino_t + ((size_t)(a0 + k) * nb + gb) * nz + gz;
+                if (vec_ok && gz + 3 < nz) {
+                    v = *(const V4 *)src;   // 16-byte aligned: nz % 4 == 0
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) vv[q] = (gz + q < nz) ? src[q] : (T)0;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) vv[q] = (T)0;
+            }
+            *(V4 *)&lds[k][b][4 * z4] = v;
+        }
+        __syncthreads();
+        for (int k = 0; k < na; ++k) {
+            const double2 tr = trig[a0 + k];
+            const int bm = bmin_s[k];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (!inside[j]) continue;
+                T w0, w1;
+                const int br = taps<T>(xv, yv[j], tr.x, tr.y, inv_ds, atten, w0, w1) - bm;
+                const T *row0 = &lds[k][br][0];
+                const T *row1 = &lds[k][br + 1][0];
+#pragma unroll
+                for (int z4 = 0; z4 < Z4; ++z4) {
+                    const V4 s0 = *(const V4 *)(row0 + 4 * z4);
+                    const V4 s1 = *(const V4 *)(row1 + 4 * z4);
+                    acc[j][4 * z4 + 0] = fma(w1, s1.x, fma(w0, s0.x, acc[j][4 * z4 + 0]));
+                    acc[j][4 * z4 + 1] = fma(w1, s1.y, fma(w0, s0.y, acc[j][4 * z4 + 1]));
+                    acc[j][4 * z4 + 2] = fma(w1, s1.z, fma(w0, s0.z, acc[j][4 * z4 + 2]));
+                    acc[j][4 * z4 + 3] = fma(w1, s1.w, fma(w0, s0.w, acc[j][4 * z4 + 3]));
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        if (c >= n || r[j] >= n) continue;
+#pragma unroll
+        for (int k = 0; k < ZC; ++k) {
+            if (z0 + k < nz) {
+                const size_t idx = ((size_t)(z0 + k) * n + r[j]) * n + c;
+                vol[idx] = accumulate ? vol[idx] + acc[j][k] : acc[j][k];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------- 3D P
+// Input volume [y][x][z], output sinogram [view][bin][z].  One workgroup = a
+// bundle of kPB = 32 neighbouring bins x up to kPV = 8 views that march along
+// the same grid axis (consecutive in the plan's view order) x ZC slices.
+// Thread = one (bin, view) ray with ZC accumulators.  The bundle walks the
+// march axis kPCM steps at a time; for each chunk the union of the cross-axis
+// ranges the bundle can reach is staged in LDS as [step][z/4][cross][4]
+// (coalesced copies of z-contiguous chunks).  Along the cross axis the
+// detector coordinate s, the depth t and u move linearly, so per step a ray
+// takes its NC candidate voxels j = jlo .. jlo + NC - 1 (exactly those with
+// floor(u_j) in {b-1, b} when they lie in [jlo, jhi]) and weights each by
+// a_j (1 - |u_j - b|); invalid candidates get weight 0 (no divergence).
+// The host splits view batches so the staged range never exceeds kPCR.
+template <typename T, int ZC, int NC>
+__global__ void __launch_bounds__(256) project3d_kernel(const T *__restrict__ vol_t, T *__restrict__ sino_t, int n,
+                                                        int nz, int nb, const double2 *__restrict__ trig,
+                                                        const int *__restrict__ order,
+                                                        const int4 *__restrict__ batches, double h, double inv_ds,
+                                                        T atten) {
+    using V4 = typename Vec4<T>::type;
+    constexpr int Z4 = ZC / 4;
+    __shared__ V4 lds[kPCM][Z4][kPCR];
+    __shared__ int jmin_s, jmax_s;
+    const int4 bt = batches[blockIdx.y];
+    const int tb = threadIdx.x % kPB, tk = threadIdx.x / kPB;
+    const int b = blockIdx.x * kPB + tb;
+    const int z0 = blockIdx.z * ZC;
+    const bool xmajor = bt.z != 0;
+    const bool active = tk < bt.y && b < nb;
+    const int a = order[bt.x + min(tk, bt.y - 1)];
+    const double2 tr = trig[a];
+    const double sn = tr.x, cs = tr.y;
+    // affine frame: s(m, j) = s00 + m dsm + j dsj, t(m, j) = t00 + m dtm + j dtj, u = (s + 1) inv_ds - 1/2
+    const double c0 = centre(0, h);
+    const double s00 = fma(-c0, sn, c0 * cs), t00 = fma(c0, cs, c0 * sn);
+    const double dsj = (xmajor ? cs : -sn) * h, dsm = (xmajor ? -sn : cs) * h;
+    const double dtj = (xmajor ? sn : cs) * h, dtm = (xmajor ? cs : sn) * h;
+    const double du = dsj * inv_ds, dU = dsm * inv_ds, U00 = fma(s00 + 1.0, inv_ds, -0.5);
+    const double inv_du = 1.0 / du;
+    const T du_t = (T)du, dsj_t = (T)dsj, dtj_t = (T)dtj;
+    T acc[ZC];
+#pragma unroll
+    for (int k = 0; k < ZC; ++k) acc[k] = (T)0;
+    const bool vec_ok = (nz & 3) == 0;
+    for (int m0 = 0; m0 < n; m0 += kPCM) {
+        if (threadIdx.x == 0) { jmin_s = 1 << 30; jmax_s = -(1 << 30); }
+        __syncthreads();
+        if (active) {
+            double lo = 1e300, hi = -1e300;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const double U = fma((double)(e ? m0 + kPCM - 1 : m0), dU, U00);
+                const double jA = ((double)b - 1.0 - U) * inv_du, jB = ((double)b + 1.0 - U) * inv_du;
+                lo = fmin(lo, fmin(jA, jB));
+                hi = fmax(hi, fmax(jA, jB));
+            }
+            atomicMin(&jmin_s, (int)floor(lo) - 1);
+            atomicMax(&jmax_s, (int)ceil(hi) + 1);
+        }
+        __syncthreads();
+        const int j0 = jmin_s;
+        const int cr = min(jmax_s - j0 + 1, kPCR);
+        const int mc = min(kPCM, n - m0);
+        for (int e = threadIdx.x; e < mc * cr * Z4; e += 256) {
+            const int z4 = e % Z4;
+            const int rest = e / Z4;
+            const int jj = rest % cr;
+            const int mm = rest / cr;
+            const int j = j0 + jj, m = m0 + mm;
+            V4 v;
+            T *vv = (T *)&v;
+            if (j >= 0 && j < n) {
+                const int c = xmajor ? m : j, r = xmajor ? j : m;
+                const T *src = vol_t + ((size_t)r * n + c) * nz + z0 + 4 * z4;
+                if (vec_ok && z0 + 4 * z4 + 3 < nz) {
+                    v = *(const V4 *)src;   // 16-byte aligned: nz % 4 == 0
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) vv[q] = (z0 + 4 * z4 + q < nz) ? src[q] : (T)0;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) vv[q] = (T)0;
+            }
+            lds[mm][z4][jj] = v;
+        }
+        __syncthreads();
+        if (active) {
+            for (int mm = 0; mm < mc; ++mm) {
+                const int m = m0 + mm;
+                const double U = fma((double)m, dU, U00);
+                const double jA = ((double)b - 1.0 - U) * inv_du, jB = ((double)b + 1.0 - U) * inv_du;
+                const int jlo = (int)ceil(fmin(jA, jB) - 1e-9);
+                const int jhi = (int)floor(fmax(jA, jB) + 1e-9);
+                const double jl = (double)jlo;
+                const T d0 = (T)(fma(jl, du, U) - (double)b);
+                const T s0 = (T)fma(jl, dsj, fma((double)m, dsm, s00));
+                const T t0 = (T)fma(jl, dtj, fma((double)m, dtm, t00));
+#pragma unroll
+                for (int q = 0; q < NC; ++q) {
+                    const int j = jlo + q;
+                    const T hat = (T)1 - fabs(d0 + (T)q * du_t);
+                    const bool valid = j <= jhi && j >= 0 && j < n && hat > (T)0 &&
+                                       vial_ij(xmajor ? m : j, xmajor ? j : m, n);
+                    const T sq = s0 + (T)q * dsj_t;
+                    T rr = (T)1 - sq * sq;
+                    rr = rr > (T)0 ? sqrt_t<T>(rr) : (T)0;
+                    const T w = valid ? hat * exp_neg<T>(atten, t0 + (T)q * dtj_t + rr) : (T)0;
+                    const int jj = min(max(j - j0, 0), cr - 1);
+#pragma unroll
+                    for (int z4 = 0; z4 < Z4; ++z4) {
+                        const V4 v = lds[mm][z4][jj];
+                        acc[4 * z4 + 0] = fma(w, v.x, acc[4 * z4 + 0]);
+                        acc[4 * z4 + 1] = fma(w, v.y, acc[4 * z4 + 1]);
+                        acc[4 * z4 + 2] = fma(w, v.z, acc[4 * z4 + 2]);
+                        acc[4 * z4 + 3] = fma(w, v.w, acc[4 * z4 + 3]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (!active) return;
+    T *dst = sino_t + ((size_t)a * nb + b) * nz + z0;
+#pragma unroll
+    for (int z4 = 0; z4 < Z4; ++z4) {
+        if (vec_ok && z0 + 4 * z4 + 3 < nz) {
+            V4 v;
+            v.x = acc[4 * z4 + 0]; v.y = acc[4 * z4 + 1]; v.z = acc[4 * z4 + 2]; v.w = acc[4 * z4 + 3];
+            *(V4 *)(dst + 4 * z4) = v;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (z0 + 4 * z4 + q < nz) dst[4 * z4 + q] = acc[4 * z4 + q];
+        }
+    }
+}
+
+// Batched transpose: [B][R][C] -> [B][C][R] (out = in^T, or out += in^T).
 template <typename T>
-static int bp_dispatch(sipo_plan p, const void *sino, void *vol, int accumulate, hipStream_t s) {
+__global__ void __launch_bounds__(256) transpose_kernel(const T *__restrict__ in, T *__restrict__ out, int rows,
+                                                        int cols, int accumulate) {
+    __shared__ T tile[64][65];
+    const size_t plane = (size_t)rows * cols;
+    const T *src = in + (size_t)blockIdx.z * plane;
+    T *dst = out + (size_t)blockIdx.z * plane;
+    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int r = r0 + i, c = c0 + tx;
+        tile[i][tx] = (r < rows && c < cols) ? src[(size_t)r * cols + c] : (T)0;
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int c = c0 + i, r = r0 + tx;
+        if (r < rows && c < cols) {
+            const size_t o = (size_t)c * rows + r;
+            dst[o] = accumulate ? dst[o] + tile[tx][i] : tile[tx][i];
+        }
+    }
+}
+
+template <typename T>
+static void transpose(const void *in, void *out, int batch, int rows, int cols, int accumulate, hipStream_t s) {
+    const dim3 grid((cols + 63) / 64, (rows + 63) / 64, batch);
+    hipLaunchKernelGGL((transpose_kernel<T>), grid, dim3(256), 0, s, (const T *)in, (T *)out, rows, cols, accumulate);
+}
+
+static int transpose_any(sipo_plan p, const void *in, void *out, int batch, int rows, int cols, int accumulate,
+                         hipStream_t s) {
+    if (p->dtype == SIPO_F64) transpose<double>(in, out, batch, rows, cols, accumulate, s);
+    else transpose<float>(in, out, batch, rows, cols, accumulate, s);
+    SIPO_LAUNCHED("transpose_kernel");
+    return SIPO_OK;
+}
+
+// --------------------------------------------------------- host: batching
+// Cross-axis range (in voxels, with the kernel's guards) a bundle of views and
+// kPB bins starting at b0 can reach during the kPCM steps starting at m0.
+static int chunk_range(bool xmajor, const double2 *trig, const int *idx, int cnt, int b0, int m0, double h,
+                       double inv_ds) {
+    double lo = 1e300, hi = -1e300;
+    for (int k = 0; k < cnt; ++k) {
+        const double sn = trig[idx[k]].x, cs = trig[idx[k]].y;
+        for (int e = 0; e < 2; ++e) {
+            const int m = e ? m0 + kPCM - 1 : m0;
+            const double c0 = -1.0 + 0.5 * h, pm = -1.0 + (m + 0.5) * h;
+            const double s0 = xmajor ? -pm * sn + c0 * cs : -c0 * sn + pm * cs;
+            const double U = (s0 + 1.0) * inv_ds - 0.5;
+            const double du = (xmajor ? cs : -sn) * h * inv_ds;
+            for (int f = 0; f < 2; ++f) {
+                const double bb = f ? b0 + kPB : b0 - 1.0;
+                const double j = (bb - U) / du;
+                lo = std::min(lo, j);
+                hi = std::max(hi, j);
+            }
+        }
+    }
+    return (int)std::ceil(hi) + 1 - ((int)std::floor(lo) - 1) + 1;
+}
+
+int plan_build_batches(sipo_plan p, const double2 *trig) {
+    const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
+    std::vector<int> order;
+    double min_du = 1e300;
+    for (int a = 0; a < p->n_angles; ++a)
+        if (std::fabs(trig[a].y) >= std::fabs(trig[a].x)) order.push_back(a);
+    const int nx = (int)order.size();
+    for (int a = 0; a < p->n_angles; ++a)
+        if (!(std::fabs(trig[a].y) >= std::fabs(trig[a].x))) order.push_back(a);
+    for (int k = 0; k < p->n_angles; ++k) {
+        const double sn = trig[order[k]].x, cs = trig[order[k]].y;
+        min_du = std::min(min_du, std::fabs((k < nx ? cs : -sn) * h * inv_ds));
+    }
+    std::vector<int4> batches;
+    bool ok = true;
+    const int last_b0 = ((p->n_bins - 1) / kPB) * kPB;
+    const int last_m0 = ((p->n - 1) / kPCM) * kPCM;
+    auto fits = [&](bool xm, int start, int cnt) {
+        int worst = 0;
+        for (int b0 : {0, last_b0})
+            for (int m0 : {0, last_m0})
+                worst = std::max(worst, chunk_range(xm, trig, order.data() + start, cnt, b0, m0, h, inv_ds));
+        return worst + 2 <= kPCR;
+    };
+    for (int part = 0; part < 2; ++part) {
+        const int beg = part ? nx : 0, end = part ? p->n_angles : nx;
+        int i = beg;
+        while (i < end) {
+            int cnt = 1;
+            if (!fits(part == 0, i, 1)) ok = false;
+            while (cnt < kPV && i + cnt < end && fits(part == 0, i, cnt + 1)) ++cnt;
+            batches.push_back(make_int4(i, cnt, part == 0 ? 1 : 0, 0));
+            i += cnt;
+        }
+    }
+    // candidates per ray step: the integers in an interval of length 2/|du| (plus guards)
+    const int nc = (int)std::floor(2.0 / min_du + 1e-6) + 1;
+    p->p3d_nc = nc <= 3 ? 3 : (nc <= 4 ? 4 : (nc <= 6 ? 6 : 0));
+    p->n_batches = (int)batches.size();
+    p->p3d_ok = ok && p->p3d_nc > 0;
+    p->bp3d_ok = bp3d_fits(p->n, p->n_bins);
+    SIPO_HIP(hipMalloc(&p->d_batches, sizeof(int4) * std::max<size_t>(batches.size(), 1)));
+    if (!batches.empty())
+        SIPO_HIP(hipMemcpy(p->d_batches, batches.data(), sizeof(int4) * batches.size(), hipMemcpyHostToDevice));
+    SIPO_HIP(hipMemcpy(p->d_angle_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
+    return SIPO_OK;
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename T>
+static int bp_slices(sipo_plan p, const void *sino, void *vol, int accumulate, hipStream_t s) {
     const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
     const dim3 block(64, 4);
     if (p->nz == 1) {
@@ -128,7 +512,7 @@ static int bp_dispatch(sipo_plan p, const void *sino, void *vol, int accumulate,
 }
 
 template <typename T>
-static int fp_dispatch(sipo_plan p, const void *vol, void *sino, int accumulate, hipStream_t s) {
+static int fp_slices(sipo_plan p, const void *vol, void *sino, int accumulate, hipStream_t s) {
     const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
     const dim3 block(64, 4);
     if (p->nz == 1) {
@@ -145,14 +529,95 @@ static int fp_dispatch(sipo_plan p, const void *vol, void *sino, int accumulate,
     return SIPO_OK;
 }
 
+template <typename T>
+static int bp3d(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s) {
+    constexpr int ZC = sizeof(T) == 8 ? 16 : 32;
+    const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
+    const dim3 grid((p->n + kBpTX - 1) / kBpTX, (p->n + kBpTY - 1) / kBpTY, (p->nz + ZC - 1) / ZC);
+    hipLaunchKernelGGL((backproject3d_kernel<T, ZC>), grid, dim3(256), 0, s, (const T *)sino_t, (T *)vol, p->n, p->nz,
+                       p->n_angles, p->n_bins, p->d_trig, h, inv_ds, (T)p->atten, accumulate);
+    SIPO_LAUNCHED("backproject3d_kernel");
+    return SIPO_OK;
+}
+
+template <typename T, int NC>
+static void fp3d_nc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+    constexpr int ZC = sizeof(T) == 8 ? 16 : 32;
+    const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
+    const dim3 grid((p->n_bins + kPB - 1) / kPB, p->n_batches, (p->nz + ZC - 1) / ZC);
+    hipLaunchKernelGGL((project3d_kernel<T, ZC, NC>), grid, dim3(256), 0, s, (const T *)vol_t, (T *)sino_t, p->n,
+                       p->nz, p->n_bins, p->d_trig, p->d_angle_order, p->d_batches, h, inv_ds, (T)p->atten);
+}
+
+template <typename T>
+static int fp3d(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+    switch (p->p3d_nc) {
+        case 3: fp3d_nc<T, 3>(p, vol_t, sino_t, s); break;
+        case 4: fp3d_nc<T, 4>(p, vol_t, sino_t, s); break;
+        case 6: fp3d_nc<T, 6>(p, vol_t, sino_t, s); break;
+        default: return fail(SIPO_E_UNSUPPORTED, "3D projector: unsupported candidate count");
+    }
+    SIPO_LAUNCHED("project3d_kernel");
+    return SIPO_OK;
+}
+
+int launch_vol_to_t(sipo_plan p, const void *vol, void *vol_t, hipStream_t s) {
+    return transpose_any(p, vol, vol_t, 1, p->nz, p->n * p->n, 0, s);
+}
+
+int launch_sino_to_t(sipo_plan p, const void *sino, void *sino_t, hipStream_t s) {
+    return transpose_any(p, sino, sino_t, p->n_angles, p->nz, p->n_bins, 0, s);
+}
+
+int launch_sino_from_t(sipo_plan p, const void *sino_t, void *sino, int accumulate, hipStream_t s) {
+    return transpose_any(p, sino_t, sino, p->n_angles, p->n_bins, p->nz, accumulate, s);
+}
+
+int launch_mask_to_t(sipo_plan p, const uint8_t *mask, uint8_t *mask_t, hipStream_t s) {
+    transpose<uint8_t>(mask, mask_t, p->n_angles, p->nz, p->n_bins, 0, s);
+    SIPO_LAUNCHED("transpose_kernel<u8>");
+    return SIPO_OK;
+}
+
+// Internal-layout entry points (see sipo_internal.hpp).  Slice and fallback
+// plans have no separate internal layout: they run the slice kernels directly.
+int launch_backproject_t(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s) {
+    if (!p->fast3d())
+        return p->dtype == SIPO_F64 ? bp_slices<double>(p, sino_t, vol, accumulate, s)
+                                    : bp_slices<float>(p, sino_t, vol, accumulate, s);
+    return p->dtype == SIPO_F64 ? bp3d<double>(p, sino_t, vol, accumulate, s)
+                                : bp3d<float>(p, sino_t, vol, accumulate, s);
+}
+
+int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+    if (!p->fast3d())
+        return p->dtype == SIPO_F64 ? fp_slices<double>(p, vol_t, sino_t, 0, s)
+                                    : fp_slices<float>(p, vol_t, sino_t, 0, s);
+    return p->dtype == SIPO_F64 ? fp3d<double>(p, vol_t, sino_t, s) : fp3d<float>(p, vol_t, sino_t, s);
+}
+
+static int ensure_scratch(sipo_plan p) {
+    if (!p->d_vol_t) SIPO_HIP(hipMalloc(&p->d_vol_t, p->vol_elems() * p->elem_bytes()));
+    if (!p->d_sino_t) SIPO_HIP(hipMalloc(&p->d_sino_t, p->sino_elems() * p->elem_bytes()));
+    return SIPO_OK;
+}
+
+// ABI-layout entry points: the volume kernels run on z-contiguous copies made in the plan's scratch.
 int launch_backproject(sipo_plan p, const void *sino, void *vol, int accumulate, hipStream_t s) {
-    return p->dtype == SIPO_F64 ? bp_dispatch<double>(p, sino, vol, accumulate, s)
-                                : bp_dispatch<float>(p, sino, vol, accumulate, s);
+    if (!p->fast3d()) return launch_backproject_t(p, sino, vol, accumulate, s);
+    int rc = ensure_scratch(p);
+    if (!rc) rc = launch_sino_to_t(p, sino, p->d_sino_t, s);
+    return rc ? rc : launch_backproject_t(p, p->d_sino_t, vol, accumulate, s);
 }
 
 int launch_project(sipo_plan p, const void *vol, void *sino, int accumulate, hipStream_t s) {
-    return p->dtype == SIPO_F64 ? fp_dispatch<double>(p, vol, sino, accumulate, s)
-                                : fp_dispatch<float>(p, vol, sino, accumulate, s);
+    if (!p->fast3d())
+        return p->dtype == SIPO_F64 ? fp_slices<double>(p, vol, sino, accumulate, s)
+                                    : fp_slices<float>(p, vol, sino, accumulate, s);
+    int rc = ensure_scratch(p);
+    if (!rc) rc = launch_vol_to_t(p, vol, p->d_vol_t, s);
+    if (!rc) rc = launch_project_t(p, p->d_vol_t, p->d_sino_t, s);
+    return rc ? rc : launch_sino_from_t(p, p->d_sino_t, sino, accumulate, s);
 }
 
 }  // namespace sipo

@@ -65,6 +65,15 @@ struct sipo_plan_s {
     // per-angle march axis split, on the host, for launch decisions
     int n_xmajor;
     int *d_angle_order;     // [n_angles]: x-major angles first, then y-major
+    // view batches of the 3D projector: (first index into d_angle_order, count, x-major flag, unused)
+    int n_batches;
+    int4 *d_batches;
+    bool p3d_ok;            // every batch fits the projector's LDS strip
+    int p3d_nc;             // candidate voxels per ray step of the 3D projector (0 = unsupported)
+    bool bp3d_ok;           // the 3D backprojector's bin window fits its LDS tile
+    void *d_vol_t;          // lazily allocated [y][x][z] scratch volume (standalone 3D calls)
+    void *d_sino_t;         // lazily allocated [view][bin][z] scratch sinogram (standalone 3D calls)
+    bool fast3d() const { return nz > 1 && p3d_ok && bp3d_ok; }
     size_t vol_elems() const { return (size_t)nz * n * n; }
     size_t sino_elems() const { return (size_t)n_angles * nz * n_bins; }
     size_t elem_bytes() const { return dtype == SIPO_F64 ? 8 : 4; }
@@ -78,6 +87,17 @@ int check_plan(sipo_plan p);
 int launch_backproject(sipo_plan p, const void *sino, void *vol, int accumulate, hipStream_t s);
 int launch_project(sipo_plan p, const void *vol, void *sino, int accumulate, hipStream_t s);
 int launch_blur(sipo_plan p, const void *in, void *out, hipStream_t s);
+// Internal 3D layouts (fast3d plans): sinograms [view][bin][z] ("sino_t") and, as
+// the projector's input, volumes [y][x][z] ("vol_t"); both keep z contiguous.
+// Volumes produced by the backprojector stay in the ABI layout [z][y][x].
+int launch_backproject_t(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s);
+int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s);
+int launch_vol_to_t(sipo_plan p, const void *vol, void *vol_t, hipStream_t s);
+int launch_sino_to_t(sipo_plan p, const void *sino, void *sino_t, hipStream_t s);
+int launch_sino_from_t(sipo_plan p, const void *sino_t, void *sino, int accumulate, hipStream_t s);
+int launch_mask_to_t(sipo_plan p, const uint8_t *mask, uint8_t *mask_t, hipStream_t s);
+int plan_build_batches(sipo_plan p, const double2 *trig_host);
+constexpr int kPB = 32, kPV = 8, kPCM = 4, kPCR = 96;   // bins, views, steps per stage, max staged cross range
 
 // ------------------------------------------------------------- geometry
 // The per-(voxel, view) interpolation taps, shared verbatim by the
@@ -86,17 +106,23 @@ int launch_blur(sipo_plan p, const void *in, void *out, hipStream_t s);
 // Beer-Lambert factor in the element type.
 __device__ __forceinline__ double centre(int c, double h) { return fma((double)c + 0.5, h, -1.0); }
 
+// exp(-k v) and sqrt: the FP32 path uses the hardware v_exp_f32 / v_sqrt_f32
+// (about 1 ulp), the FP64 path the correctly rounded library functions.
+constexpr double kLog2e = 1.4426950408889634;
+
 template <typename T>
-__device__ __forceinline__ T exp_t(T v);
+__device__ __forceinline__ T exp_neg(T k, T v);   // exp(-k v)
 template <>
-__device__ __forceinline__ float exp_t<float>(float v) { return expf(v); }
+__device__ __forceinline__ float exp_neg<float>(float k, float v) {
+    return __builtin_amdgcn_exp2f(-(k * (float)kLog2e) * v);
+}
 template <>
-__device__ __forceinline__ double exp_t<double>(double v) { return exp(v); }
+__device__ __forceinline__ double exp_neg<double>(double k, double v) { return exp(-k * v); }
 
 template <typename T>
 __device__ __forceinline__ T sqrt_t(T v);
 template <>
-__device__ __forceinline__ float sqrt_t<float>(float v) { return sqrtf(v); }
+__device__ __forceinline__ float sqrt_t<float>(float v) { return __builtin_amdgcn_sqrtf(v); }
 template <>
 __device__ __forceinline__ double sqrt_t<double>(double v) { return sqrt(v); }
 
@@ -112,7 +138,7 @@ __device__ __forceinline__ int taps(double x, double y, double sn, double cs, do
     const double t = fma(x, cs, y * sn);
     T r = (T)fma(-s, s, 1.0);
     r = r > (T)0 ? sqrt_t<T>(r) : (T)0;
-    const T a = exp_t<T>(-atten * ((T)t + r));
+    const T a = exp_neg<T>(atten, (T)t + r);
     w1 = a * f;
     w0 = a - w1;
     return (int)bf;

@@ -39,6 +39,9 @@ CASES = [
     (67, 37, 1, 70, 0.7),          # ragged grid, non-square detector, odd angle count
     (40, 23, 13, 41, 1.0),         # 3D with a slice count that is not a multiple of the z chunk
     (24, [0.0, math.pi / 2, math.pi, 1.5 * math.pi, 0.25 * math.pi], 3, None, 0.0),   # exact axis/diagonal views
+    (64, 45, 36, None, 1.0),       # 3D with a slice count divisible by 4 (vector staging path)
+    (16, 10, 4, 40, 1.0),          # 3D with a detector much finer than the grid (general fallback path)
+    (70, 181, 8, 70, 1.0),         # odd view count, views on both sides of the 45 degree split
 ]
 
 
