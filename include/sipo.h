@@ -90,6 +90,15 @@ int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype 
                      sipo_plan *plan_out);
 int sipo_plan_destroy(sipo_plan plan);
 
+/* Times the plan's kernel variants that compute the same result with
+ * different work splits (slices per projector thread, slices per blur
+ * workgroup) on scratch arrays of the plan's shape and keeps the fastest for
+ * later calls.  Optional: a plan starts from built-in defaults, and results
+ * do not depend on the choice beyond rounding order.  Allocates and frees its
+ * scratch; synchronous on stream.  Not thread-safe against concurrent use of
+ * the same plan. */
+int sipo_plan_autotune(sipo_plan plan, void *stream);
+
 /* vol (+)= P^T sino: backprojection, the geometric part of the dose model
  * f = A^T g = K P^T g (Eq. 2-3).  sino: device [n_angles][nz][n_bins];
  * vol: device [nz][n][n].  accumulate != 0 adds to vol, else overwrites.

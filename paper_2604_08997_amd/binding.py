@@ -67,6 +67,7 @@ class PdhgResult(C.Structure):
 SIGNATURES = {
     "sipo_plan_create": (C.c_int, [C.POINTER(Geometry), C.POINTER(Psf), C.c_int, C.POINTER(C.c_void_p)]),
     "sipo_plan_destroy": (C.c_int, [C.c_void_p]),
+    "sipo_plan_autotune": (C.c_int, [C.c_void_p, C.c_void_p]),
     "sipo_backproject": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "sipo_project": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "sipo_blur": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -192,6 +193,12 @@ class Plan:
 
     def empty_sino(self, dtype=None):
         return torch.empty(self.sino_shape, dtype=dtype or self.dtype, device=self.device)
+
+    def autotune(self):
+        """Time the plan's equivalent kernel variants and keep the fastest (synchronous)."""
+        with torch.cuda.device(self.device):
+            _check(lib().sipo_plan_autotune(self.handle, _stream()))
+        return self
 
     # ------------------------------------------------------------ operators
     def backproject(self, sino, out=None, accumulate=False):

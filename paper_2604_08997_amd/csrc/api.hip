@@ -111,12 +111,14 @@ int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype 
         return fail(SIPO_E_DEVICE, "plan device allocation failed: %s", hipGetErrorString(e));
     }
     p->d_batches = nullptr;
+    p->d_partner = nullptr;
     p->d_vol_t = nullptr;
     p->d_sino_t = nullptr;
     rc = plan_build_batches(p, trig.data());
     if (rc != SIPO_OK) {
         (void)hipFree(p->d_trig); (void)hipFree(p->d_angle_order); (void)hipFree(p->d_scratch);
         (void)hipFree(p->d_batches);
+        (void)hipFree(p->d_partner);
         delete p;
         return rc;
     }
@@ -133,6 +135,7 @@ int sipo_plan_destroy(sipo_plan p) {
     (void)hipFree(p->d_angle_order);
     (void)hipFree(p->d_scratch);
     (void)hipFree(p->d_batches);
+    (void)hipFree(p->d_partner);
     if (p->d_vol_t) (void)hipFree(p->d_vol_t);
     if (p->d_sino_t) (void)hipFree(p->d_sino_t);
     if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);

@@ -4,63 +4,84 @@
 // A workgroup owns a 64 x 16 (x, y) tile and a chunk of slices.  It streams
 // the slices in z order: each slice tile (with its x/y halo) is staged in LDS,
 // blurred along x and then y, and the xy-blurred values of a thread's four
-// columns are pushed through a register ring of 2 rz + 1 slices; when the
-// ring is full the z taps produce one output slice.  Every input slice is
-// read from HBM once per tile (plus halos) and every output written once.
+// rows are pushed through a register ring of 2 rz + 1 slices; once the ring
+// is full the z taps produce one output slice.  The next slice is fetched into
+// registers while the current one is being blurred, so the HBM stream does not
+// wait on the two LDS passes.  Every input slice is read once per tile (plus
+// halos, mostly from L2) and every output written once.
+//
+// The x and y radii share one compile-time radius RXY = max(rx, ry); an axis
+// with a smaller radius gets its taps zero-padded to that width.
 #include "sipo_internal.hpp"
 
 namespace sipo {
 
-constexpr int kBTX = 64, kBTY = 16, kBRows = 4;   // tile and rows per thread (256 threads)
+constexpr int kBTX = 64, kBTY = 16, kBRows = kBTY / 4;   // tile; 256 threads = 64 x 4, 4 rows per thread
 
-template <typename T, int RZ>
+template <typename T, int RXY, int RZ>
 __global__ void __launch_bounds__(256) blur_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int nz,
                                                    Taps<T> tp, int zchunk) {
-    __shared__ T raw[(kBTY + 2 * kMaxR) * (kBTX + 2 * kMaxR)];
-    __shared__ T xb[(kBTY + 2 * kMaxR) * kBTX];
+    constexpr int RW = kBTX + 2 * RXY, RH = kBTY + 2 * RXY;
+    constexpr int LR = (RH + 3) / 4;   // staged rows per thread
+    __shared__ T raw[RH][RW + 1];
+    __shared__ T xb[RH][kBTX + 1];
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int tid = ty * kBTX + tx;
     const int x0 = blockIdx.x * kBTX, y0 = blockIdx.y * kBTY;
     const int z0 = blockIdx.z * zchunk;
     const int zend = min(nz, z0 + zchunk);
-    const int rx = tp.rx, ry = tp.ry;
-    const int RW = kBTX + 2 * rx, RH = kBTY + 2 * ry;
     const size_t plane = (size_t)n * n;
+    const int gxm = x0 - RXY + tx, gxh = x0 - RXY + kBTX + tx;
+    const bool okm = gxm >= 0 && gxm < n, okh = tx < 2 * RXY && gxh >= 0 && gxh < n;
+
+    T pm[LR], ph[LR];
+    auto fetch = [&](int zi) {
+        const bool zok = zi >= 0 && zi < nz;
+        const T *src = in + (size_t)(zok ? zi : 0) * plane;
+#pragma unroll
+        for (int k = 0; k < LR; ++k) {
+            const int ly = ty + 4 * k, gy = y0 - RXY + ly;
+            const bool yok = zok && ly < RH && gy >= 0 && gy < n;
+            pm[k] = (yok && okm) ? src[(size_t)gy * n + gxm] : (T)0;
+            ph[k] = (yok && okh) ? src[(size_t)gy * n + gxh] : (T)0;
+        }
+    };
+
     T ring[kBRows][2 * RZ + 1];
 #pragma unroll
     for (int j = 0; j < kBRows; ++j)
 #pragma unroll
         for (int m = 0; m < 2 * RZ + 1; ++m) ring[j][m] = (T)0;
 
+    fetch(z0 - RZ);
     for (int zi = z0 - RZ; zi < zend + RZ; ++zi) {
+#pragma unroll
+        for (int k = 0; k < LR; ++k) {
+            const int ly = ty + 4 * k;
+            if (ly < RH) {
+                raw[ly][tx] = pm[k];
+                if (tx < 2 * RXY) raw[ly][kBTX + tx] = ph[k];
+            }
+        }
+        __syncthreads();
+        if (zi + 1 < zend + RZ) fetch(zi + 1);
+#pragma unroll
+        for (int k = 0; k < LR; ++k) {
+            const int ly = ty + 4 * k;
+            if (ly < RH) {
+                T s = (T)0;
+#pragma unroll
+                for (int d = 0; d <= 2 * RXY; ++d) s = fma(tp.kx[d], raw[ly][tx + d], s);
+                xb[ly][tx] = s;
+            }
+        }
+        __syncthreads();
         T v[kBRows];
-        if (zi >= 0 && zi < nz) {
-            const T *src = in + (size_t)zi * plane;
-            for (int e = tid; e < RW * RH; e += 256) {
-                const int ly = e / RW, lx = e - ly * RW;
-                const int gy = y0 - ry + ly, gx = x0 - rx + lx;
-                raw[ly * (kBTX + 2 * kMaxR) + lx] =
-                    (gx >= 0 && gx < n && gy >= 0 && gy < n) ? src[(size_t)gy * n + gx] : (T)0;
-            }
-            __syncthreads();
-            for (int e = tid; e < RH * kBTX; e += 256) {
-                const int ly = e / kBTX, lx = e - ly * kBTX;
-                const T *rr = raw + ly * (kBTX + 2 * kMaxR) + lx;
-                T s = (T)0;
-                for (int k = 0; k <= 2 * rx; ++k) s = fma(tp.kx[k], rr[k], s);
-                xb[ly * kBTX + lx] = s;
-            }
-            __syncthreads();
 #pragma unroll
-            for (int j = 0; j < kBRows; ++j) {
-                const int ly = ty + 4 * j;
-                T s = (T)0;
-                for (int k = 0; k <= 2 * ry; ++k) s = fma(tp.ky[k], xb[(ly + k) * kBTX + tx], s);
-                v[j] = s;
-            }
-        } else {
+        for (int j = 0; j < kBRows; ++j) {
+            T s = (T)0;
 #pragma unroll
-            for (int j = 0; j < kBRows; ++j) v[j] = (T)0;
+            for (int d = 0; d <= 2 * RXY; ++d) s = fma(tp.ky[d], xb[ty + 4 * j + d][tx], s);
+            v[j] = s;
         }
 #pragma unroll
         for (int j = 0; j < kBRows; ++j) {
@@ -83,27 +104,72 @@ __global__ void __launch_bounds__(256) blur_kernel(const T *__restrict__ in, T *
     }
 }
 
-template <typename T, int RZ>
-static void launch_rz(const Taps<T> &tp, const void *in, void *out, int n, int nz, hipStream_t s) {
-    const int zchunk = nz <= 32 ? nz : 32;
+// Re-centre an axis' taps of radius r on radius R >= r (zeros outside).
+template <typename T>
+static void pad_taps(T *k, int r, int R) {
+    T tmp[2 * kMaxR + 1];
+    for (int d = 0; d <= 2 * R; ++d) {
+        const int o = d - R + r;
+        tmp[d] = (o >= 0 && o <= 2 * r) ? k[o] : (T)0;
+    }
+    for (int d = 0; d <= 2 * kMaxR; ++d) k[d] = d <= 2 * R ? tmp[d] : (T)0;
+}
+
+// z chunk: enough workgroups to fill the chip (about eight per CU) without
+// letting the z halo dominate.
+static int pick_zchunk(int n, int nz, int rz) {
+    const long tiles = (long)((n + kBTX - 1) / kBTX) * ((n + kBTY - 1) / kBTY);
+    long zc = (tiles * nz + 2047) / 2048;
+    zc = std::max<long>(zc, std::max(8, 2 * rz));
+    return (int)std::min<long>(zc, nz);
+}
+
+template <typename T, int RXY, int RZ>
+static void launch_r(const Taps<T> &tp, const void *in, void *out, int n, int nz, int zc, hipStream_t s) {
+    const int zchunk = zc > 0 ? std::min(zc, nz) : pick_zchunk(n, nz, RZ);
     const dim3 grid((n + kBTX - 1) / kBTX, (n + kBTY - 1) / kBTY, (nz + zchunk - 1) / zchunk);
-    hipLaunchKernelGGL((blur_kernel<T, RZ>), grid, dim3(kBTX, 4), 0, s, (const T *)in, (T *)out, n, nz, tp, zchunk);
+    hipLaunchKernelGGL((blur_kernel<T, RXY, RZ>), grid, dim3(kBTX, 4), 0, s, (const T *)in, (T *)out, n, nz, tp,
+                       zchunk);
+}
+
+template <typename T, int RXY>
+static int launch_rz(const Taps<T> &tp, const void *in, void *out, int n, int nz, int zc, hipStream_t s) {
+    switch (tp.rz) {
+        case 0: launch_r<T, RXY, 0>(tp, in, out, n, nz, zc, s); break;
+        case 1: launch_r<T, RXY, 1>(tp, in, out, n, nz, zc, s); break;
+        case 2: launch_r<T, RXY, 2>(tp, in, out, n, nz, zc, s); break;
+        case 3: launch_r<T, RXY, 3>(tp, in, out, n, nz, zc, s); break;
+        case 4: launch_r<T, RXY, 4>(tp, in, out, n, nz, zc, s); break;
+        case 5: launch_r<T, RXY, 5>(tp, in, out, n, nz, zc, s); break;
+        case 6: launch_r<T, RXY, 6>(tp, in, out, n, nz, zc, s); break;
+        case 7: launch_r<T, RXY, 7>(tp, in, out, n, nz, zc, s); break;
+        case 8: launch_r<T, RXY, 8>(tp, in, out, n, nz, zc, s); break;
+        default: return fail(SIPO_E_UNSUPPORTED, "PSF z radius %d > %d", tp.rz, kMaxR);
+    }
+    return SIPO_OK;
 }
 
 template <typename T>
-static int blur_dispatch(sipo_plan p, const Taps<T> &tp, const void *in, void *out, hipStream_t s) {
-    switch (tp.rz) {
-        case 0: launch_rz<T, 0>(tp, in, out, p->n, p->nz, s); break;
-        case 1: launch_rz<T, 1>(tp, in, out, p->n, p->nz, s); break;
-        case 2: launch_rz<T, 2>(tp, in, out, p->n, p->nz, s); break;
-        case 3: launch_rz<T, 3>(tp, in, out, p->n, p->nz, s); break;
-        case 4: launch_rz<T, 4>(tp, in, out, p->n, p->nz, s); break;
-        case 5: launch_rz<T, 5>(tp, in, out, p->n, p->nz, s); break;
-        case 6: launch_rz<T, 6>(tp, in, out, p->n, p->nz, s); break;
-        case 7: launch_rz<T, 7>(tp, in, out, p->n, p->nz, s); break;
-        case 8: launch_rz<T, 8>(tp, in, out, p->n, p->nz, s); break;
-        default: return fail(SIPO_E_UNSUPPORTED, "PSF z radius %d > %d", tp.rz, kMaxR);
+static int blur_dispatch(sipo_plan p, const Taps<T> &taps, const void *in, void *out, hipStream_t s) {
+    Taps<T> tp = taps;
+    const int R = std::max(tp.rx, tp.ry);
+    pad_taps(tp.kx, tp.rx, R);
+    pad_taps(tp.ky, tp.ry, R);
+    tp.rx = tp.ry = R;
+    int rc;
+    switch (R) {
+        case 0: rc = launch_rz<T, 0>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
+        case 1: rc = launch_rz<T, 1>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
+        case 2: rc = launch_rz<T, 2>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
+        case 3: rc = launch_rz<T, 3>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
+        case 4: rc = launch_rz<T, 4>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
+        case 5: rc = launch_rz<T, 5>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
+        case 6: rc = launch_rz<T, 6>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
+        case 7: rc = launch_rz<T, 7>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
+        case 8: rc = launch_rz<T, 8>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
+        default: return fail(SIPO_E_UNSUPPORTED, "PSF xy radius %d > %d", R, kMaxR);
     }
+    if (rc) return rc;
     SIPO_LAUNCHED("blur_kernel");
     return SIPO_OK;
 }

@@ -91,13 +91,34 @@ __device__ __forceinline__ void block_sums(double (&v)[NS], double *partials) {
     }
 }
 
-// Sum per-block partials (fixed order) into dst[0..ns).
-__global__ void finish_sums(const double *__restrict__ partials, int nblocks, double *dst, int ns) {
-    const int k = threadIdx.x;
-    if (k < ns) {
-        double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += partials[b * kNS + k];
-        dst[k] = s;
+// Total of column k of the per-block partials, by one block of kThreads threads:
+// strided per-thread sums, then a fixed tree, so the result does not depend on timing.
+template <bool MAX>
+__device__ double block_total(const double *__restrict__ partials, int nblocks, int k, double *sh) {
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kThreads) {
+        const double v = partials[b * kNS + k];
+        a = MAX ? fmax(a, v) : a + v;
+    }
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] = MAX ? fmax(sh[threadIdx.x], sh[threadIdx.x + o])
+                                                       : sh[threadIdx.x] + sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Sum per-block partials into dst[0..ns).
+__global__ void __launch_bounds__(kThreads) finish_sums(const double *__restrict__ partials, int nblocks,
+                                                         double *dst, int ns) {
+    __shared__ double sh[kThreads];
+    for (int k = 0; k < ns; ++k) {
+        const double r = block_total<false>(partials, nblocks, k, sh);
+        if (threadIdx.x == 0) dst[k] = r;
     }
 }
 
@@ -256,14 +277,11 @@ __device__ __forceinline__ void roll_next(DevScal *sc, const LPConst &c) {
 }
 
 // One block: finish the lambda sums, apply the Halpern update to (u, v), prepare the next step.
-__global__ void k_scalars(const double *__restrict__ partials, int nblocks, DevScal *sc, LPConst c) {
-    __shared__ double s[2];
-    if (threadIdx.x < 2) {
-        double a = 0.0;
-        for (int b = 0; b < nblocks; ++b) a += partials[b * kNS + threadIdx.x];
-        s[threadIdx.x] = a;
-    }
-    __syncthreads();
+__global__ void __launch_bounds__(kThreads) k_scalars(const double *__restrict__ partials, int nblocks,
+                                                       DevScal *sc, LPConst c) {
+    __shared__ double sh[kThreads];
+    const double s0 = block_total<false>(partials, nblocks, 0, sh);
+    const double s1 = block_total<false>(partials, nblocks, 1, sh);
     if (threadIdx.x != 0) return;
     const double w = sc->w, rho = sc->rho;
     sc->ut_done = sc->ut;
@@ -272,8 +290,8 @@ __global__ void k_scalars(const double *__restrict__ partials, int nblocks, DevS
     else sc->u = c.h;
     if (c.v_free) sc->v = w * ((1.0 + rho) * sc->vt - rho * sc->v) + (1.0 - w) * sc->v0;
     else sc->v = 1.0;
-    sc->sum_l1 = s[0];
-    sc->sum_Ul2 = s[1];
+    sc->sum_l1 = s0;
+    sc->sum_Ul2 = s1;
     sc->k_in += 1.0;
     sc->w = sc->halpern != 0.0 ? (sc->k_in + 1.0) / (sc->k_in + 2.0) : 1.0;
     roll_next(sc, c);
@@ -402,12 +420,12 @@ __global__ void k_ray_check(const T *q, const uint8_t *act, size_t n, double *pa
     }
 }
 
-__global__ void finish_max(const double *__restrict__ partials, int nblocks, double *dst) {
-    if (threadIdx.x < 2) {
-        double m = 0.0;
-        for (int b = 0; b < nblocks; ++b) m = fmax(m, partials[b * kNS + threadIdx.x]);
-        dst[threadIdx.x] = m;
-    }
+__global__ void __launch_bounds__(kThreads) finish_max(const double *__restrict__ partials, int nblocks,
+                                                        double *dst) {
+    __shared__ double sh[kThreads];
+    const double m0 = block_total<true>(partials, nblocks, 0, sh);
+    const double m1 = block_total<true>(partials, nblocks, 1, sh);
+    if (threadIdx.x == 0) { dst[0] = m0; dst[1] = m1; }
 }
 
 // power iteration: G^T-side combination of the rows of G x with D = K P^T y,
@@ -582,7 +600,7 @@ class Solver {
         return rc ? rc : launch_project_t(p_, w_.vol_t, out, s_);
     }
     int sums(int nblocks, int ns, double *host) {
-        hipLaunchKernelGGL(finish_sums, dim3(1), dim3(64), 0, s_, w_.partials, nblocks, w_.scal->sums, ns);
+        hipLaunchKernelGGL(finish_sums, dim3(1), dim3(kThreads), 0, s_, w_.partials, nblocks, w_.scal->sums, ns);
         SIPO_HIP(hipMemcpyAsync(host, w_.scal->sums, sizeof(double) * ns, hipMemcpyDeviceToHost, s_));
         SIPO_HIP(hipStreamSynchronize(s_));
         return SIPO_OK;
@@ -753,7 +771,7 @@ int Solver<T>::farkas(const T *alu, const T *all, const T *blu, const T *bll, do
     rc = adjoint((const T *)w_.tmp2, V(w_.q));
     if (rc) return rc;
     hipLaunchKernelGGL((k_ray_check<T>), dim3(gs_), dim3(kThreads), 0, s_, (const T *)w_.q, act_, ns_, w_.partials);
-    hipLaunchKernelGGL(finish_max, dim3(1), dim3(64), 0, s_, w_.partials, gs_, w_.scal->sums);
+    hipLaunchKernelGGL(finish_max, dim3(1), dim3(kThreads), 0, s_, w_.partials, gs_, w_.scal->sums);
     double m[2];
     SIPO_HIP(hipMemcpyAsync(m, w_.scal->sums, sizeof(m), hipMemcpyDeviceToHost, s_));
     SIPO_HIP(hipStreamSynchronize(s_));
@@ -780,7 +798,7 @@ int Solver<T>::iteration(bool check) {
                        hal ? (const T *)w_.s_lo : (const T *)nullptr, check ? V(w_.lut) : (T *)nullptr,
                        check ? V(w_.llt) : (T *)nullptr, check ? V(w_.luo) : (T *)nullptr,
                        check ? V(w_.llo) : (T *)nullptr, (const DevScal *)w_.scal, c_, nv_, w_.partials);
-    hipLaunchKernelGGL(k_scalars, dim3(1), dim3(64), 0, s_, w_.partials, gv_, w_.scal, c_);
+    hipLaunchKernelGGL(k_scalars, dim3(1), dim3(kThreads), 0, s_, w_.partials, gv_, w_.scal, c_);
     return SIPO_OK;
 }
 

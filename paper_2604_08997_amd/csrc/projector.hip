@@ -250,21 +250,30 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
 // Thread = one (bin, view) ray with ZC accumulators.  The bundle walks the
 // march axis kPCM steps at a time; for each chunk the union of the cross-axis
 // ranges the bundle can reach is staged in LDS as [step][z/4][cross][4]
-// (coalesced copies of z-contiguous chunks).  Along the cross axis the
-// detector coordinate s, the depth t and u move linearly, so per step a ray
-// takes its NC candidate voxels j = jlo .. jlo + NC - 1 (exactly those with
-// floor(u_j) in {b-1, b} when they lie in [jlo, jhi]) and weights each by
-// a_j (1 - |u_j - b|); invalid candidates get weight 0 (no divergence).
+// (coalesced copies of z-contiguous chunks; voxels outside the vial are staged
+// as zeros, which is where their columns of P vanish).  Along the cross axis
+// the detector coordinate s, the depth t and u move linearly, so per step a
+// ray takes its NC candidate voxels j = jlo .. jlo + NC - 1 and weights each by
+// a_j max(0, 1 - |u_j - b|); a candidate outside the ray's reach gets weight 0
+// (no divergence).
+//
+// PAIR: every view comes with its opposite view (theta + pi).  The opposite
+// ray of bin b is bin nb - 1 - b: it meets the same voxels with the same
+// interpolation weights (s and t change sign), so one staged operand feeds
+// both rays and only the attenuation factor is evaluated twice.
+//
 // The host splits view batches so the staged range never exceeds kPCR.
-template <typename T, int ZC, int NC>
+template <typename T, int ZC, int NC, bool PAIR>
 __global__ void __launch_bounds__(256) project3d_kernel(const T *__restrict__ vol_t, T *__restrict__ sino_t, int n,
                                                         int nz, int nb, const double2 *__restrict__ trig,
                                                         const int *__restrict__ order,
+                                                        const int *__restrict__ partner,
                                                         const int4 *__restrict__ batches, double h, double inv_ds,
                                                         T atten) {
     using V4 = typename Vec4<T>::type;
     constexpr int Z4 = ZC / 4;
-    __shared__ V4 lds[kPCM][Z4][kPCR];
+    constexpr int NR = PAIR ? 2 : 1;
+    __shared__ V4 lds[kPCM][Z4][kPCR + 1];   // +1: the z/4 planes start on different banks
     __shared__ int jmin_s, jmax_s;
     const int4 bt = batches[blockIdx.y];
     const int tb = threadIdx.x % kPB, tk = threadIdx.x / kPB;
@@ -283,9 +292,11 @@ __global__ void __launch_bounds__(256) project3d_kernel(const T *__restrict__ vo
     const double du = dsj * inv_ds, dU = dsm * inv_ds, U00 = fma(s00 + 1.0, inv_ds, -0.5);
     const double inv_du = 1.0 / du;
     const T du_t = (T)du, dsj_t = (T)dsj, dtj_t = (T)dtj;
-    T acc[ZC];
+    T acc[NR][ZC];
 #pragma unroll
-    for (int k = 0; k < ZC; ++k) acc[k] = (T)0;
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int k = 0; k < ZC; ++k) acc[r][k] = (T)0;
     const bool vec_ok = (nz & 3) == 0;
     for (int m0 = 0; m0 < n; m0 += kPCM) {
         if (threadIdx.x == 0) { jmin_s = 1 << 30; jmax_s = -(1 << 30); }
@@ -312,10 +323,10 @@ __global__ void __launch_bounds__(256) project3d_kernel(const T *__restrict__ vo
             const int jj = rest % cr;
             const int mm = rest / cr;
             const int j = j0 + jj, m = m0 + mm;
+            const int c = xmajor ? m : j, r = xmajor ? j : m;
             V4 v;
             T *vv = (T *)&v;
-            if (j >= 0 && j < n) {
-                const int c = xmajor ? m : j, r = xmajor ? j : m;
+            if (j >= 0 && j < n && vial_ij(c, r, n)) {
                 const T *src = vol_t + ((size_t)r * n + c) * nz + z0 + 4 * z4;
                 if (vec_ok && z0 + 4 * z4 + 3 < nz) {
                     v = *(const V4 *)src;   // 16-byte aligned: nz % 4 == 0
@@ -336,29 +347,33 @@ __global__ void __launch_bounds__(256) project3d_kernel(const T *__restrict__ vo
                 const double U = fma((double)m, dU, U00);
                 const double jA = ((double)b - 1.0 - U) * inv_du, jB = ((double)b + 1.0 - U) * inv_du;
                 const int jlo = (int)ceil(fmin(jA, jB) - 1e-9);
-                const int jhi = (int)floor(fmax(jA, jB) + 1e-9);
                 const double jl = (double)jlo;
                 const T d0 = (T)(fma(jl, du, U) - (double)b);
                 const T s0 = (T)fma(jl, dsj, fma((double)m, dsm, s00));
                 const T t0 = (T)fma(jl, dtj, fma((double)m, dtm, t00));
+                const int jj0 = jlo - j0;
 #pragma unroll
                 for (int q = 0; q < NC; ++q) {
-                    const int j = jlo + q;
-                    const T hat = (T)1 - fabs(d0 + (T)q * du_t);
-                    const bool valid = j <= jhi && j >= 0 && j < n && hat > (T)0 &&
-                                       vial_ij(xmajor ? m : j, xmajor ? j : m, n);
+                    T hat = (T)1 - fabs(d0 + (T)q * du_t);
+                    hat = hat > (T)0 ? hat : (T)0;
                     const T sq = s0 + (T)q * dsj_t;
                     T rr = (T)1 - sq * sq;
                     rr = rr > (T)0 ? sqrt_t<T>(rr) : (T)0;
-                    const T w = valid ? hat * exp_neg<T>(atten, t0 + (T)q * dtj_t + rr) : (T)0;
-                    const int jj = min(max(j - j0, 0), cr - 1);
+                    const T tq = t0 + (T)q * dtj_t;
+                    T w[NR];
+                    w[0] = hat * exp_neg<T>(atten, tq + rr);
+                    if (PAIR) w[NR - 1] = hat * exp_neg<T>(atten, rr - tq);
+                    const int jj = min(max(jj0 + q, 0), cr - 1);
 #pragma unroll
                     for (int z4 = 0; z4 < Z4; ++z4) {
                         const V4 v = lds[mm][z4][jj];
-                        acc[4 * z4 + 0] = fma(w, v.x, acc[4 * z4 + 0]);
-                        acc[4 * z4 + 1] = fma(w, v.y, acc[4 * z4 + 1]);
-                        acc[4 * z4 + 2] = fma(w, v.z, acc[4 * z4 + 2]);
-                        acc[4 * z4 + 3] = fma(w, v.w, acc[4 * z4 + 3]);
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) {
+                            acc[r][4 * z4 + 0] = fma(w[r], v.x, acc[r][4 * z4 + 0]);
+                            acc[r][4 * z4 + 1] = fma(w[r], v.y, acc[r][4 * z4 + 1]);
+                            acc[r][4 * z4 + 2] = fma(w[r], v.z, acc[r][4 * z4 + 2]);
+                            acc[r][4 * z4 + 3] = fma(w[r], v.w, acc[r][4 * z4 + 3]);
+                        }
                     }
                 }
             }
@@ -366,17 +381,21 @@ __global__ void __launch_bounds__(256) project3d_kernel(const T *__restrict__ vo
         __syncthreads();
     }
     if (!active) return;
-    T *dst = sino_t + ((size_t)a * nb + b) * nz + z0;
 #pragma unroll
-    for (int z4 = 0; z4 < Z4; ++z4) {
-        if (vec_ok && z0 + 4 * z4 + 3 < nz) {
-            V4 v;
-            v.x = acc[4 * z4 + 0]; v.y = acc[4 * z4 + 1]; v.z = acc[4 * z4 + 2]; v.w = acc[4 * z4 + 3];
-            *(V4 *)(dst + 4 * z4) = v;
-        } else {
+    for (int r = 0; r < NR; ++r) {
+        T *dst = r == 0 ? sino_t + ((size_t)a * nb + b) * nz + z0
+                        : sino_t + ((size_t)partner[a] * nb + (nb - 1 - b)) * nz + z0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (z0 + 4 * z4 + q < nz) dst[4 * z4 + q] = acc[4 * z4 + q];
+        for (int z4 = 0; z4 < Z4; ++z4) {
+            if (vec_ok && z0 + 4 * z4 + 3 < nz) {
+                V4 v;
+                v.x = acc[r][4 * z4 + 0]; v.y = acc[r][4 * z4 + 1]; v.z = acc[r][4 * z4 + 2]; v.w = acc[r][4 * z4 + 3];
+                *(V4 *)(dst + 4 * z4) = v;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (z0 + 4 * z4 + q < nz) dst[4 * z4 + q] = acc[r][4 * z4 + q];
+            }
         }
     }
 }
@@ -444,16 +463,47 @@ static int chunk_range(bool xmajor, const double2 *trig, const int *idx, int cnt
     return (int)std::ceil(hi) + 1 - ((int)std::floor(lo) - 1) + 1;
 }
 
+// Opposite view of every view (sin and cos both change sign, to 1e-12), or -1;
+// views are paired greedily, each at most once.
+static std::vector<int> opposite_views(const double2 *trig, int na) {
+    std::vector<int> idx(na), opp(na, -1);
+    for (int a = 0; a < na; ++a) idx[a] = a;
+    std::sort(idx.begin(), idx.end(), [&](int i, int j) {
+        return trig[i].x < trig[j].x || (trig[i].x == trig[j].x && trig[i].y < trig[j].y);
+    });
+    constexpr double eps = 1e-12;
+    for (int a = 0; a < na; ++a) {
+        if (opp[a] >= 0) continue;
+        const double ts = -trig[a].x, tc = -trig[a].y;
+        auto it = std::lower_bound(idx.begin(), idx.end(), ts - eps,
+                                   [&](int i, double v) { return trig[i].x < v; });
+        for (; it != idx.end() && trig[*it].x <= ts + eps; ++it) {
+            const int b = *it;
+            if (b != a && opp[b] < 0 && std::fabs(trig[b].y - tc) <= eps) {
+                opp[a] = b;
+                opp[b] = a;
+                break;
+            }
+        }
+    }
+    return opp;
+}
+
 int plan_build_batches(sipo_plan p, const double2 *trig) {
     const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
+    const std::vector<int> opp = opposite_views(trig, p->n_angles);
+    bool pair = p->n_angles >= 2;
+    for (int a = 0; a < p->n_angles; ++a) pair = pair && opp[a] >= 0;
+    auto walked = [&](int a) { return !pair || a < opp[a]; };
     std::vector<int> order;
     double min_du = 1e300;
     for (int a = 0; a < p->n_angles; ++a)
-        if (std::fabs(trig[a].y) >= std::fabs(trig[a].x)) order.push_back(a);
+        if (walked(a) && std::fabs(trig[a].y) >= std::fabs(trig[a].x)) order.push_back(a);
     const int nx = (int)order.size();
     for (int a = 0; a < p->n_angles; ++a)
-        if (!(std::fabs(trig[a].y) >= std::fabs(trig[a].x))) order.push_back(a);
-    for (int k = 0; k < p->n_angles; ++k) {
+        if (walked(a) && !(std::fabs(trig[a].y) >= std::fabs(trig[a].x))) order.push_back(a);
+    const int nw = (int)order.size();
+    for (int k = 0; k < nw; ++k) {
         const double sn = trig[order[k]].x, cs = trig[order[k]].y;
         min_du = std::min(min_du, std::fabs((k < nx ? cs : -sn) * h * inv_ds));
     }
@@ -469,7 +519,7 @@ int plan_build_batches(sipo_plan p, const double2 *trig) {
         return worst + 2 <= kPCR;
     };
     for (int part = 0; part < 2; ++part) {
-        const int beg = part ? nx : 0, end = part ? p->n_angles : nx;
+        const int beg = part ? nx : 0, end = part ? nw : nx;
         int i = beg;
         while (i < end) {
             int cnt = 1;
@@ -482,13 +532,18 @@ int plan_build_batches(sipo_plan p, const double2 *trig) {
     // candidates per ray step: the integers in an interval of length 2/|du| (plus guards)
     const int nc = (int)std::floor(2.0 / min_du + 1e-6) + 1;
     p->p3d_nc = nc <= 3 ? 3 : (nc <= 4 ? 4 : (nc <= 6 ? 6 : 0));
+    p->p3d_pair = pair;
+    p->p3d_zc = p->dtype == SIPO_F64 ? 16 : 32;
+    p->blur_zc = 0;
     p->n_batches = (int)batches.size();
     p->p3d_ok = ok && p->p3d_nc > 0;
     p->bp3d_ok = bp3d_fits(p->n, p->n_bins);
     SIPO_HIP(hipMalloc(&p->d_batches, sizeof(int4) * std::max<size_t>(batches.size(), 1)));
+    SIPO_HIP(hipMalloc(&p->d_partner, sizeof(int) * p->n_angles));
     if (!batches.empty())
         SIPO_HIP(hipMemcpy(p->d_batches, batches.data(), sizeof(int4) * batches.size(), hipMemcpyHostToDevice));
     SIPO_HIP(hipMemcpy(p->d_angle_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
+    SIPO_HIP(hipMemcpy(p->d_partner, opp.data(), sizeof(int) * opp.size(), hipMemcpyHostToDevice));
     return SIPO_OK;
 }
 
@@ -540,23 +595,44 @@ static int bp3d(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipS
     return SIPO_OK;
 }
 
-template <typename T, int NC>
+template <typename T, int ZC, int NC>
 static void fp3d_nc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
-    constexpr int ZC = sizeof(T) == 8 ? 16 : 32;
     const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
     const dim3 grid((p->n_bins + kPB - 1) / kPB, p->n_batches, (p->nz + ZC - 1) / ZC);
-    hipLaunchKernelGGL((project3d_kernel<T, ZC, NC>), grid, dim3(256), 0, s, (const T *)vol_t, (T *)sino_t, p->n,
-                       p->nz, p->n_bins, p->d_trig, p->d_angle_order, p->d_batches, h, inv_ds, (T)p->atten);
+    if (p->p3d_pair)
+        hipLaunchKernelGGL((project3d_kernel<T, ZC, NC, true>), grid, dim3(256), 0, s, (const T *)vol_t, (T *)sino_t,
+                           p->n, p->nz, p->n_bins, p->d_trig, p->d_angle_order, p->d_partner, p->d_batches, h, inv_ds,
+                           (T)p->atten);
+    else
+        hipLaunchKernelGGL((project3d_kernel<T, ZC, NC, false>), grid, dim3(256), 0, s, (const T *)vol_t,
+                           (T *)sino_t, p->n, p->nz, p->n_bins, p->d_trig, p->d_angle_order, p->d_partner,
+                           p->d_batches, h, inv_ds, (T)p->atten);
+}
+
+template <typename T, int ZC>
+static int fp3d_zc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+    switch (p->p3d_nc) {
+        case 3: fp3d_nc<T, ZC, 3>(p, vol_t, sino_t, s); break;
+        case 4: fp3d_nc<T, ZC, 4>(p, vol_t, sino_t, s); break;
+        case 6: fp3d_nc<T, ZC, 6>(p, vol_t, sino_t, s); break;
+        default: return fail(SIPO_E_UNSUPPORTED, "3D projector: unsupported candidate count");
+    }
+    return SIPO_OK;
 }
 
 template <typename T>
 static int fp3d(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
-    switch (p->p3d_nc) {
-        case 3: fp3d_nc<T, 3>(p, vol_t, sino_t, s); break;
-        case 4: fp3d_nc<T, 4>(p, vol_t, sino_t, s); break;
-        case 6: fp3d_nc<T, 6>(p, vol_t, sino_t, s); break;
-        default: return fail(SIPO_E_UNSUPPORTED, "3D projector: unsupported candidate count");
+    int rc;
+    switch (p->p3d_zc) {
+        case 8: rc = fp3d_zc<T, 8>(p, vol_t, sino_t, s); break;
+        case 16: rc = fp3d_zc<T, 16>(p, vol_t, sino_t, s); break;
+        case 32:
+            if constexpr (sizeof(T) == 4) rc = fp3d_zc<T, 32>(p, vol_t, sino_t, s);
+            else rc = fail(SIPO_E_UNSUPPORTED, "3D projector: 32 slices per thread in FP64");
+            break;
+        default: return fail(SIPO_E_UNSUPPORTED, "3D projector: %d slices per thread", p->p3d_zc);
     }
+    if (rc) return rc;
     SIPO_LAUNCHED("project3d_kernel");
     return SIPO_OK;
 }

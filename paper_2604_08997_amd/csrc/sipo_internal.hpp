@@ -64,12 +64,17 @@ struct sipo_plan_s {
     void *d_scratch;        // kPlanScratchBytes
     // per-angle march axis split, on the host, for launch decisions
     int n_xmajor;
-    int *d_angle_order;     // [n_angles]: x-major angles first, then y-major
+    int *d_angle_order;     // views the 3D projector walks: x-major first, then y-major
+                            // (only the first view of each opposite pair when p3d_pair)
+    int *d_partner;         // [n_angles]: index of the opposite view (theta + pi), or -1
     // view batches of the 3D projector: (first index into d_angle_order, count, x-major flag, unused)
     int n_batches;
     int4 *d_batches;
     bool p3d_ok;            // every batch fits the projector's LDS strip
+    bool p3d_pair;          // every view has an opposite view: the projector walks pairs
     int p3d_nc;             // candidate voxels per ray step of the 3D projector (0 = unsupported)
+    int p3d_zc;             // slices per projector thread (set by defaults or sipo_plan_autotune)
+    int blur_zc;            // slices per blur workgroup (0 = built-in choice)
     bool bp3d_ok;           // the 3D backprojector's bin window fits its LDS tile
     void *d_vol_t;          // lazily allocated [y][x][z] scratch volume (standalone 3D calls)
     void *d_sino_t;         // lazily allocated [view][bin][z] scratch sinogram (standalone 3D calls)

@@ -42,6 +42,8 @@ CASES = [
     (64, 45, 36, None, 1.0),       # 3D with a slice count divisible by 4 (vector staging path)
     (16, 10, 4, 40, 1.0),          # 3D with a detector much finer than the grid (general fallback path)
     (70, 181, 8, 70, 1.0),         # odd view count, views on both sides of the 45 degree split
+    (48, 60, 20, None, 1.0),       # 3D, every view has its opposite: the projector walks view pairs
+    (33, 90, 11, 35, 0.7),         # view pairs with a ragged grid, slice count and detector
 ]
 
 
@@ -64,6 +66,26 @@ def test_backproject_and_project_match_oracle(case, dtype):
     else:
         assert rel_norm(bp, bp_ref) < F32_NORM_TOL
         assert rel_norm(fp, fp_ref) < F32_NORM_TOL
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_autotuned_plan_matches_oracle(dtype):
+    # the autotuner only changes work splits: outputs stay within the parity bound
+    n, nz, na = 40, 24, 36
+    ang = angles_uniform(na)
+    g = make_geometry(n, ang, nz=nz, atten=1.0)
+    P = Projector(g)
+    plan = plan_for(n, list(ang), nz=nz, sigma=(1.0, 1.0, 1.5), dtype=dtype).autotune()
+    vol = signed_field(g.vol_shape, 7)
+    fp = plan.project(to_gpu(vol, dtype)).double().cpu().numpy()
+    kb = plan.blur(to_gpu(vol, dtype)).double().cpu().numpy()
+    kb_ref = oblur.apply(vol, oblur.psf_taps((1.0, 1.0, 1.5)))
+    if dtype == torch.float64:
+        np.testing.assert_allclose(fp, P.project(vol), rtol=F64_TOL, atol=F64_TOL * np.abs(fp).max())
+        np.testing.assert_allclose(kb, kb_ref, rtol=F64_TOL, atol=F64_TOL * np.abs(kb_ref).max())
+    else:
+        assert rel_norm(fp, P.project(vol)) < F32_NORM_TOL
+        assert rel_norm(kb, kb_ref) < F32_NORM_TOL
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
