@@ -112,6 +112,9 @@ int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype 
     }
     p->d_batches = nullptr;
     p->d_partner = nullptr;
+    p->d_ranges = nullptr;
+    p->d_vial_rows = nullptr;
+    p->d_zero = nullptr;
     p->d_vol_t = nullptr;
     p->d_sino_t = nullptr;
     rc = plan_build_batches(p, trig.data());
@@ -119,6 +122,9 @@ int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype 
         (void)hipFree(p->d_trig); (void)hipFree(p->d_angle_order); (void)hipFree(p->d_scratch);
         (void)hipFree(p->d_batches);
         (void)hipFree(p->d_partner);
+        (void)hipFree(p->d_ranges);
+        (void)hipFree(p->d_vial_rows);
+        (void)hipFree(p->d_zero);
         delete p;
         return rc;
     }
@@ -136,6 +142,9 @@ int sipo_plan_destroy(sipo_plan p) {
     (void)hipFree(p->d_scratch);
     (void)hipFree(p->d_batches);
     (void)hipFree(p->d_partner);
+    (void)hipFree(p->d_ranges);
+    (void)hipFree(p->d_vial_rows);
+    (void)hipFree(p->d_zero);
     if (p->d_vol_t) (void)hipFree(p->d_vol_t);
     if (p->d_sino_t) (void)hipFree(p->d_sino_t);
     if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);

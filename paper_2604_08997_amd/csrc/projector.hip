@@ -400,6 +400,169 @@ __global__ void __launch_bounds__(256) project3d_kernel(const T *__restrict__ vo
     }
 }
 
+// ------------------------------------------------ 3D P, asynchronous staging
+// Same rays, candidates and weights as project3d_kernel (FP32, nz % 4 == 0),
+// but the volume strips are copied HBM -> LDS with direct-to-LDS loads
+// (global_load_lds_dwordx4) into two buffers: while a workgroup computes the
+// rays' contributions of one kDmaCM-step chunk from one buffer, the next
+// chunk is already in flight into the other, so the staging latency is hidden
+// behind compute instead of stalling every chunk.
+//
+// LDS layout of a buffer: [step][z/4][kPCR + 1] 16-byte slots.  A wave's load
+// instruction fills 64 consecutive slots, so each thread owns fixed slots
+// (decoded once); per chunk only the source address changes.  Slots beyond a
+// chunk's cross range, outside the grid or outside the vial load from a 16-byte
+// zero block.  Cross ranges per (batch, bin group, chunk) come precomputed
+// from the plan (conservative by one voxel on each side).
+constexpr int kDmaCM = 2;
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int ZC, int NC, bool PAIR>
+__global__ void __launch_bounds__(256) project3d_dma_kernel(
+    const float *__restrict__ vol_t, float *__restrict__ sino_t, int n, int nz, int nb,
+    const double2 *__restrict__ trig, const int *__restrict__ order, const int *__restrict__ partner,
+    const int4 *__restrict__ batches, const int2 *__restrict__ ranges, const int2 *__restrict__ vial_rows,
+    const float4 *__restrict__ zero16, double h, double inv_ds, float atten) {
+    constexpr int Z4 = ZC / 4, RS = kPCR + 1, SLOTS = kDmaCM * Z4 * RS, PER = (SLOTS + 255) / 256;
+    constexpr int NR = PAIR ? 2 : 1;
+    __shared__ float4 bufA[SLOTS];
+    __shared__ float4 bufB[SLOTS];
+    const int tid = threadIdx.x;
+    const int4 bt = batches[blockIdx.y];
+    const int tb = tid % kPB, tk = tid / kPB;
+    const int b = blockIdx.x * kPB + tb;
+    const int z0 = blockIdx.z * ZC;
+    const bool xmajor = bt.z != 0;
+    const bool active = tk < bt.y && b < nb;
+    const int a = order[bt.x + min(tk, bt.y - 1)];
+    const double2 tr = trig[a];
+    const double sn = tr.x, cs = tr.y;
+    const double c0 = centre(0, h);
+    const double s00 = fma(-c0, sn, c0 * cs), t00 = fma(c0, cs, c0 * sn);
+    const double dsj = (xmajor ? cs : -sn) * h, dsm = (xmajor ? -sn : cs) * h;
+    const double dtj = (xmajor ? sn : cs) * h, dtm = (xmajor ? cs : sn) * h;
+    const double du = dsj * inv_ds, dU = dsm * inv_ds, U00 = fma(s00 + 1.0, inv_ds, -0.5);
+    const double inv_du = 1.0 / du;
+    const float du_t = (float)du, dsj_t = (float)dsj, dtj_t = (float)dtj;
+    const int nch = (n + kDmaCM - 1) / kDmaCM;
+    const int2 *rg = ranges + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * nch;
+    const size_t zrow = (size_t)(nz >> 2), zoff = (size_t)(z0 >> 2);
+    const float4 *vol4 = (const float4 *)vol_t;
+
+    // fixed slots of this thread: (step, z/4, cross offset)
+    int s_mm[PER], s_z4[PER], s_jj[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int slot = i * 256 + tid;
+        s_mm[i] = slot / (Z4 * RS);
+        const int rem = slot - s_mm[i] * (Z4 * RS);
+        s_z4[i] = rem / RS;
+        s_jj[i] = rem - s_z4[i] * RS;
+    }
+    static_assert(kDmaCM == 2, "the staging below reads the vial intervals of two rows");
+    auto issue = [&](float4 *buf, int k) {
+        const int2 r = rg[k];
+        const int m0 = k * kDmaCM;
+        const int2 v0 = vial_rows[m0], v1 = vial_rows[min(m0 + 1, n - 1)];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            if (i * 256 + tid < SLOTS) {
+                const int m = m0 + s_mm[i], j = r.x + s_jj[i];
+                const int2 v = s_mm[i] ? v1 : v0;
+                const float4 *src = zero16;
+                if (m < n && s_jj[i] < r.y && z0 + 4 * s_z4[i] < nz && j >= v.x && j <= v.y)
+                    src = vol4 + (xmajor ? ((size_t)j * n + m) : ((size_t)m * n + j)) * zrow + zoff + s_z4[i];
+                __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)(buf + i * 256 + (tid & ~63)), 16, 0,
+                                                 0);
+            }
+        }
+        asm volatile("" ::: "memory");   // keep the copies ahead of the compute that follows
+    };
+
+    float acc[NR][ZC];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int k = 0; k < ZC; ++k) acc[r][k] = 0.f;
+
+    auto compute = [&](const float4 *buf, int k) {
+        const int2 r = rg[k];
+        const int j0 = r.x, cr = r.y;
+        const int m0 = k * kDmaCM;
+        const int mc = min(kDmaCM, n - m0);
+        for (int mm = 0; mm < mc; ++mm) {
+            const int m = m0 + mm;
+            const double U = fma((double)m, dU, U00);
+            const double jA = ((double)b - 1.0 - U) * inv_du, jB = ((double)b + 1.0 - U) * inv_du;
+            const int jlo = (int)ceil(fmin(jA, jB) - 1e-9);
+            const double jl = (double)jlo;
+            const float d0 = (float)(fma(jl, du, U) - (double)b);
+            const float s0 = (float)fma(jl, dsj, fma((double)m, dsm, s00));
+            const float t0 = (float)fma(jl, dtj, fma((double)m, dtm, t00));
+            const int jj0 = jlo - j0;
+            const float4 *row = buf + mm * (Z4 * RS);
+#pragma unroll
+            for (int q = 0; q < NC; ++q) {
+                float hat = 1.f - fabsf(d0 + (float)q * du_t);
+                hat = hat > 0.f ? hat : 0.f;
+                const float sq = s0 + (float)q * dsj_t;
+                float rr = 1.f - sq * sq;
+                rr = rr > 0.f ? sqrt_t<float>(rr) : 0.f;
+                const float tq = t0 + (float)q * dtj_t;
+                float w[NR];
+                w[0] = hat * exp_neg<float>(atten, tq + rr);
+                if (PAIR) w[NR - 1] = hat * exp_neg<float>(atten, rr - tq);
+                const int jj = min(max(jj0 + q, 0), cr - 1);
+#pragma unroll
+                for (int z4 = 0; z4 < Z4; ++z4) {
+                    const float4 v = row[z4 * RS + jj];
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        acc[r][4 * z4 + 0] = fmaf(w[r], v.x, acc[r][4 * z4 + 0]);
+                        acc[r][4 * z4 + 1] = fmaf(w[r], v.y, acc[r][4 * z4 + 1]);
+                        acc[r][4 * z4 + 2] = fmaf(w[r], v.z, acc[r][4 * z4 + 2]);
+                        acc[r][4 * z4 + 3] = fmaf(w[r], v.w, acc[r][4 * z4 + 3]);
+                    }
+                }
+            }
+        }
+    };
+
+    issue(bufA, 0);
+    for (int k = 0; k < nch; k += 2) {
+        __builtin_amdgcn_s_waitcnt(0);   // this thread's copies into bufA have landed
+        lds_barrier();                   // everyone's have; bufB is no longer being read
+        if (k + 1 < nch) issue(bufB, k + 1);
+        if (active) compute(bufA, k);
+        if (k + 1 >= nch) break;
+        __builtin_amdgcn_s_waitcnt(0);
+        lds_barrier();
+        if (k + 2 < nch) issue(bufA, k + 2);
+        if (active) compute(bufB, k + 1);
+    }
+    if (!active) return;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        float *dst = r == 0 ? sino_t + ((size_t)a * nb + b) * nz + z0
+                            : sino_t + ((size_t)partner[a] * nb + (nb - 1 - b)) * nz + z0;
+#pragma unroll
+        for (int z4 = 0; z4 < Z4; ++z4) {
+            if (z0 + 4 * z4 < nz) {
+                float4 v;
+                v.x = acc[r][4 * z4 + 0]; v.y = acc[r][4 * z4 + 1]; v.z = acc[r][4 * z4 + 2]; v.w = acc[r][4 * z4 + 3];
+                *(float4 *)(dst + 4 * z4) = v;
+            }
+        }
+    }
+}
+
 // Batched transpose: [B][R][C] -> [B][C][R] (out = in^T, or out += in^T).
 template <typename T>
 __global__ void __launch_bounds__(256) transpose_kernel(const T *__restrict__ in, T *__restrict__ out, int rows,
@@ -439,28 +602,37 @@ static int transpose_any(sipo_plan p, const void *in, void *out, int batch, int 
 }
 
 // --------------------------------------------------------- host: batching
-// Cross-axis range (in voxels, with the kernel's guards) a bundle of views and
-// kPB bins starting at b0 can reach during the kPCM steps starting at m0.
-static int chunk_range(bool xmajor, const double2 *trig, const int *idx, int cnt, int b0, int m0, double h,
-                       double inv_ds) {
+// Staged cross range (first index j0 and count, with the kernels' one-voxel
+// guards) of a bundle of views and the kPB bins from b0 over steps m0 .. m1.
+static void staged_range(bool xmajor, const double2 *trig, const int *idx, int cnt, int b0, int m0, int m1, double h,
+                         double inv_ds, int *j0, int *count) {
     double lo = 1e300, hi = -1e300;
     for (int k = 0; k < cnt; ++k) {
         const double sn = trig[idx[k]].x, cs = trig[idx[k]].y;
         for (int e = 0; e < 2; ++e) {
-            const int m = e ? m0 + kPCM - 1 : m0;
+            const int m = e ? m1 : m0;
             const double c0 = -1.0 + 0.5 * h, pm = -1.0 + (m + 0.5) * h;
             const double s0 = xmajor ? -pm * sn + c0 * cs : -c0 * sn + pm * cs;
             const double U = (s0 + 1.0) * inv_ds - 0.5;
             const double du = (xmajor ? cs : -sn) * h * inv_ds;
             for (int f = 0; f < 2; ++f) {
-                const double bb = f ? b0 + kPB : b0 - 1.0;
-                const double j = (bb - U) / du;
+                const double j = ((f ? b0 + kPB : b0 - 1.0) - U) / du;
                 lo = std::min(lo, j);
                 hi = std::max(hi, j);
             }
         }
     }
-    return (int)std::ceil(hi) + 1 - ((int)std::floor(lo) - 1) + 1;
+    *j0 = (int)std::floor(lo) - 1;
+    *count = (int)std::ceil(hi) + 1 - *j0 + 1;
+}
+
+// Cross-axis range (in voxels, with the kernel's guards) a bundle of views and
+// kPB bins starting at b0 can reach during the kPCM steps starting at m0.
+static int chunk_range(bool xmajor, const double2 *trig, const int *idx, int cnt, int b0, int m0, double h,
+                       double inv_ds) {
+    int j0, count;
+    staged_range(xmajor, trig, idx, cnt, b0, m0, m0 + kPCM - 1, h, inv_ds, &j0, &count);
+    return count;
 }
 
 // Opposite view of every view (sin and cos both change sign, to 1e-12), or -1;
@@ -538,6 +710,47 @@ int plan_build_batches(sipo_plan p, const double2 *trig) {
     p->n_batches = (int)batches.size();
     p->p3d_ok = ok && p->p3d_nc > 0;
     p->bp3d_ok = bp3d_fits(p->n, p->n_bins);
+    // staged cross range of every (batch, bin group, kDmaCM-step chunk) for the asynchronous projector
+    const int ngroups = (p->n_bins + kPB - 1) / kPB, nch = (p->n + kDmaCM - 1) / kDmaCM;
+    std::vector<int2> ranges;
+    bool dma = p->dtype == SIPO_F32 && (p->nz & 3) == 0 && p->p3d_ok;
+    if (dma) {
+        ranges.resize((size_t)batches.size() * ngroups * nch);
+        for (size_t bi = 0; bi < batches.size() && dma; ++bi) {
+            const int4 bt = batches[bi];
+            for (int g = 0; g < ngroups && dma; ++g)
+                for (int k = 0; k < nch; ++k) {
+                    int j0, cr;
+                    staged_range(bt.z != 0, trig, order.data() + bt.x, bt.y, g * kPB, k * kDmaCM,
+                                 std::min(k * kDmaCM + kDmaCM, p->n) - 1, h, inv_ds, &j0, &cr);
+                    if (cr > kPCR) { dma = false; break; }
+                    ranges[(bi * ngroups + g) * nch + k] = make_int2(j0, cr);
+                }
+        }
+    }
+    std::vector<int2> vial(p->n);
+    for (int m = 0; m < p->n; ++m) {
+        // indices j with (2j+1-n)^2 <= n^2 - (2m+1-n)^2, found from a square root and fixed up exactly
+        const long long nn = p->n, am = 2LL * m + 1 - nn, rem = nn * nn - am * am;
+        long long c = (long long)std::sqrt((double)rem);
+        while (c > 0 && c * c > rem) --c;
+        while ((c + 1) * (c + 1) <= rem) ++c;
+        long long lo = (nn - 1 - c + 1) / 2, hi = (nn - 1 + c) / 2;   // ceil((n-1-c)/2), floor((n-1+c)/2)
+        if (nn - 1 - c < 0) lo = 0;
+        auto inside = [&](long long j) { const long long q = 2 * j + 1 - nn; return q * q <= rem; };
+        while (lo <= hi && !inside(lo)) ++lo;
+        while (hi >= lo && !inside(hi)) --hi;
+        vial[m] = lo <= hi ? make_int2((int)lo, (int)hi) : make_int2(1, 0);
+    }
+    p->p3d_dma_ok = p->p3d_dma = dma;
+    if (dma) {
+        SIPO_HIP(hipMalloc(&p->d_ranges, sizeof(int2) * ranges.size()));
+        SIPO_HIP(hipMemcpy(p->d_ranges, ranges.data(), sizeof(int2) * ranges.size(), hipMemcpyHostToDevice));
+    }
+    SIPO_HIP(hipMalloc(&p->d_vial_rows, sizeof(int2) * vial.size()));
+    SIPO_HIP(hipMemcpy(p->d_vial_rows, vial.data(), sizeof(int2) * vial.size(), hipMemcpyHostToDevice));
+    SIPO_HIP(hipMalloc(&p->d_zero, 256));
+    SIPO_HIP(hipMemset(p->d_zero, 0, 256));
     SIPO_HIP(hipMalloc(&p->d_batches, sizeof(int4) * std::max<size_t>(batches.size(), 1)));
     SIPO_HIP(hipMalloc(&p->d_partner, sizeof(int) * p->n_angles));
     if (!batches.empty())
@@ -609,8 +822,35 @@ static void fp3d_nc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s)
                            p->d_batches, h, inv_ds, (T)p->atten);
 }
 
+template <int ZC, int NC>
+static void fp3d_dma_nc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+    const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
+    const dim3 grid((p->n_bins + kPB - 1) / kPB, p->n_batches, (p->nz + ZC - 1) / ZC);
+    if (p->p3d_pair)
+        hipLaunchKernelGGL((project3d_dma_kernel<ZC, NC, true>), grid, dim3(256), 0, s, (const float *)vol_t,
+                           (float *)sino_t, p->n, p->nz, p->n_bins, p->d_trig, p->d_angle_order, p->d_partner,
+                           p->d_batches, p->d_ranges, p->d_vial_rows, (const float4 *)p->d_zero, h, inv_ds,
+                           (float)p->atten);
+    else
+        hipLaunchKernelGGL((project3d_dma_kernel<ZC, NC, false>), grid, dim3(256), 0, s, (const float *)vol_t,
+                           (float *)sino_t, p->n, p->nz, p->n_bins, p->d_trig, p->d_angle_order, p->d_partner,
+                           p->d_batches, p->d_ranges, p->d_vial_rows, (const float4 *)p->d_zero, h, inv_ds,
+                           (float)p->atten);
+}
+
 template <typename T, int ZC>
 static int fp3d_zc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+    if constexpr (sizeof(T) == 4 && ZC >= 16) {
+        if (p->p3d_dma) {
+            switch (p->p3d_nc) {
+                case 3: fp3d_dma_nc<ZC, 3>(p, vol_t, sino_t, s); break;
+                case 4: fp3d_dma_nc<ZC, 4>(p, vol_t, sino_t, s); break;
+                case 6: fp3d_dma_nc<ZC, 6>(p, vol_t, sino_t, s); break;
+                default: return fail(SIPO_E_UNSUPPORTED, "3D projector: unsupported candidate count");
+            }
+            return SIPO_OK;
+        }
+    }
     switch (p->p3d_nc) {
         case 3: fp3d_nc<T, ZC, 3>(p, vol_t, sino_t, s); break;
         case 4: fp3d_nc<T, ZC, 4>(p, vol_t, sino_t, s); break;

@@ -74,6 +74,11 @@ struct sipo_plan_s {
     bool p3d_pair;          // every view has an opposite view: the projector walks pairs
     int p3d_nc;             // candidate voxels per ray step of the 3D projector (0 = unsupported)
     int p3d_zc;             // slices per projector thread (set by defaults or sipo_plan_autotune)
+    bool p3d_dma_ok;        // the asynchronous-staging projector applies (FP32, nz % 4 == 0, ranges fit)
+    bool p3d_dma;           // use it (default when it applies; sipo_plan_autotune may switch)
+    int2 *d_ranges;         // [n_batches][bin groups][chunks of kDmaCM steps]: staged cross range (j0, count)
+    int2 *d_vial_rows;      // [n]: first and last index along a grid line inside the vial
+    void *d_zero;           // 256 zero bytes (source of empty staging slots)
     int blur_zc;            // slices per blur workgroup (0 = built-in choice)
     bool bp3d_ok;           // the 3D backprojector's bin window fits its LDS tile
     void *d_vol_t;          // lazily allocated [y][x][z] scratch volume (standalone 3D calls)
