@@ -9,19 +9,20 @@ band width 10 voxels, isotropic Gaussian blur sigma = 1.5 voxels, Case 1
 
 A step is one PDHG iteration: blur + project + primal update, backproject +
 blur, fused dual update, scalar update, with the KKT / restart check every 64
-iterations included.  ``value`` is iterations per second measured over the
-timed solve (setup and final KKT evaluation included, so it is a lower bound
-on the steady-state rate).  The operator pair P + P^T is also timed on its own
-with HIP events on the launch stream, which gives the A + A^T figure and the
-roofline entry for the dominant kernel.
+iterations included.  ``value`` is iterations per second over one timed solve
+of ``--steps`` iterations (its setup and final KKT evaluation included).  The
+solve runs in profile mode: the library records HIP events on the solve's
+stream around every iteration launch, which gives the per-phase times, the
+A + A^T rate of the operator pair as the solver runs it, and the roofline entry
+of the dominant kernel (the forward projector).
 
 Only one GPU is used; --gpus above 1 exits with a message.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -31,25 +32,55 @@ sys.path.insert(0, HERE)
 
 FP32_PEAK_TFLOPS = 157.3      # MI355X published FP32 vector peak
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic_project3d_256cube_360.json")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--angles", type=int, default=360)
-    ap.add_argument("--op-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slices", type=int, default=8, help="z slices in the bounded oracle sample")
+    ap.add_argument("--cpu-slices", type=int, default=32, help="z slices in the bounded oracle sample")
+    ap.add_argument("--ttk", action="store_true", help="also time a cold solve to relative KKT 1e-4")
+    ap.add_argument("--probe", choices=["project", "copy"], default=None,
+                    help="run only a few launches of one kernel (for hardware counter runs) and exit")
     return ap.parse_args()
+
+
+def vial_voxels(n):
+    """Voxels of an n x n slice whose centre lies in the unit disk (exact integer test)."""
+    import numpy as np
+    c = 2 * np.arange(n, dtype=np.int64) + 1 - n
+    return int(((c[:, None] ** 2 + c[None, :] ** 2) <= n * n).sum())
+
+
+def source_digest():
+    """Digest of the forward projector's source: recorded traffic is valid only for this source."""
+    path = os.path.join(HERE, "paper_2604_08997_amd", "csrc", "projector.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per forward-projector launch from the committed counter runs, or None
+    when they are absent or were taken on another version of the kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256_16") != source_digest():
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(n, angles, slices):
     """The oracle's PDHG iteration timed on a bounded sample: the same slice
     geometry with ``slices`` z slices instead of n, scaled to the full volume."""
-    import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import lp as olp, pdhg as opdhg, blur as oblur
     from oracle.geometry import make_geometry
     from oracle.projector import Projector
@@ -60,15 +91,37 @@ def cpu_baseline(n, angles, slices):
     prob = olp.build(P, f, olp.CASE1, taps=oblur.psf_taps((1.5, 1.5, 1.5)), band_width=10.0)
     sc = opdhg.diagonal_scaling(prob)
     st = opdhg.initial_state(prob)
-    reps = 2
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        st = opdhg.step(prob, st, 0.95 * sc.T, 0.95 * sc.Tu, 0.95 * sc.Tv, 0.95 * sc.S_up, 0.95 * sc.S_lo)
-    dt = (time.perf_counter() - t0) / reps
+    reps = 12
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st = opdhg.step(prob, st, 0.95 * sc.T, 0.95 * sc.Tu, 0.95 * sc.Tv, 0.95 * sc.S_up, 0.95 * sc.S_lo)
+        dt = (time.perf_counter() - t0) / reps
     per_full_iter = dt * (n / slices)
-    return {"value": 1.0 / per_full_iter, "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} oracle PDHG iterations on {slices} of {n} z slices ({n}^2 x {angles} views, "
-                      f"blur 1.5, Case 1), scaled by {n}/{slices}; scipy.sparse runs single-threaded"}
+    return {"value": round(1.0 / per_full_iter, 5), "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} oracle PDHG iterations (FP64 SciPy CSR, one thread) on {slices} of {n} z slices "
+                      f"({n}^2 x {angles} views, blur 1.5, Case 1), time scaled by {n}/{slices}"}
+
+
+def probe(args, plan, dev):
+    """A few launches of one kernel, for hardware-counter runs (rocprofv3 --pmc)."""
+    import torch
+    if args.probe == "copy":
+        a = torch.ones(64 << 20, dtype=torch.float32, device=dev)     # 256 MiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[probe] copy of {a.numel() * 4} bytes x 3", file=sys.stderr, flush=True)
+        return 0
+    plan.autotune()
+    vol = torch.rand(plan.vol_shape, device=dev)
+    sino = plan.empty_sino()
+    for _ in range(3):
+        plan.project(vol, out=sino)
+    torch.cuda.synchronize()
+    print("[probe] project x 3 after autotune", file=sys.stderr, flush=True)
+    return 0
 
 
 def main():
@@ -76,7 +129,6 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         return 2
-    import numpy as np
     import torch
     import paper_2604_08997_amd as sipo
     from sipo_inputs import ellipsoids_target, angles_uniform
@@ -86,41 +138,19 @@ def main():
     torch.cuda.set_device(dev)
     plan = sipo.Plan(n, list(angles_uniform(na)), nz=n, atten=1.0, sigma=(1.5, 1.5, 1.5), dtype=torch.float32,
                      device=dev)
+    if args.probe:
+        return probe(args, plan, dev)
+    plan.autotune()
     f = torch.as_tensor(ellipsoids_target(n, 3000), dtype=torch.float32, device=dev)
     lp = sipo.LP.build(plan, f, sipo.CASE1, band_width=10.0, f_min=1.0)
     print(f"[bench] workload built: {n}^3, {na} views, gel voxels {int((lp.labels == 2).sum())}, "
           f"band voxels {int((lp.labels == 1).sum())}, active rays {int(lp.act.sum())}", file=sys.stderr, flush=True)
 
-    # --- operator pair, timed with events on the launch stream
-    vol = torch.rand(plan.vol_shape, device=dev)
-    sino = torch.rand(plan.sino_shape, device=dev)
-    out_v, out_s = plan.empty_vol(), plan.empty_sino()
-    plan.project(vol, out=out_s); plan.backproject(sino, out=out_v); torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    ev[0].record()
-    for _ in range(args.op_reps):
-        plan.project(vol, out=out_s)
-    ev[1].record()
-    for _ in range(args.op_reps):
-        plan.backproject(sino, out=out_v)
-    ev[2].record()
-    torch.cuda.synchronize()
-    t_p = ev[0].elapsed_time(ev[1]) / args.op_reps
-    t_bp = ev[1].elapsed_time(ev[2]) / args.op_reps
-    samples = float(n) * n * n * na
-    flops = 4.0 * samples                                   # 2 FMA per (voxel, view) sample
-    bytes_pair = 2.0 * 4.0 * (plan.n_angles * n * n + n * n * n)   # each operator reads one array and writes the other
-    dom_name, dom_t = ("project", t_p) if t_p >= t_bp else ("backproject", t_bp)
-    achieved = flops / (dom_t * 1e-3) / 1e12
-    print(f"[bench] project {t_p:.3f} ms, backproject {t_bp:.3f} ms", file=sys.stderr, flush=True)
-
-    # --- PDHG iterations
-    opts_w = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=max(args.warmup, 1), tol=1e-12, check_every=64)
-    ws = None
-    sipo.solve(lp, opts_w, want_dose=False)
+    # --- warm-up solve, then the timed solve (profile mode: HIP events on the solve's stream)
+    sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=max(args.warmup, 1), tol=1e-12), want_dose=False)
     torch.cuda.synchronize()
     print(f"[bench] warmup {args.warmup} iterations done", file=sys.stderr, flush=True)
-    opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=args.steps, tol=1e-12, check_every=64)
+    opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=args.steps, tol=1e-12, check_every=64, profile=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = sipo.solve(lp, opts, want_dose=False)
@@ -128,13 +158,32 @@ def main():
     dt = time.perf_counter() - t0
     iters = res["iters"]
     ips = iters / dt
-    print(f"[bench] {iters} iterations in {dt:.3f} s; rel KKT p/d/gap {res['rel_primal']:.2e}/"
-          f"{res['rel_dual']:.2e}/{res['rel_gap']:.2e}", file=sys.stderr, flush=True)
+    ph_ms, ph_n = res["phase_ms"], res["phase_launches"]
+    ph_avg = {k: (ph_ms[k] / ph_n[k] if ph_n[k] else 0.0) for k in ph_ms}
+    print(f"[bench] {iters} iterations in {dt:.3f} s; per-phase ms per launch: "
+          + ", ".join(f"{k} {v:.4f}" for k, v in ph_avg.items()), file=sys.stderr, flush=True)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(n, na, args.cpu_slices)
-        cpu["cores"] = 1
+    # --- operator pair and roofline of the dominant kernel (the forward projector)
+    samples = float(vial_voxels(n)) * n * na          # (in-vial voxel, slice, view) pairs per application
+    flops = 4.0 * samples                             # 2 FMA per sample
+    t_p, t_bp = ph_avg["project"], ph_avg["backproject"]
+    dom = max(("project", "backproject"), key=lambda k: ph_avg[k])
+    achieved = flops / (ph_avg[dom] * 1e-3) / 1e12
+    pair_bytes = 2.0 * 4.0 * (plan.n_angles * n * n + n * n * n)   # each operator reads one array, writes the other
+    traffic = recorded_traffic() if dom == "project" else None
+
+    ttk = None
+    if args.ttk:
+        lp.y.zero_(); lp.lam_up.zero_(); lp.lam_lo.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=100000, tol=1e-4), want_dose=False)
+        torch.cuda.synchronize()
+        ttk = {"seconds": round(time.perf_counter() - t1, 3), "iters": r["iters"], "status": r["status_name"],
+               "restarts": r["restarts"], "objective": r["primal_obj"]}
+        print(f"[bench] time to 1e-4: {ttk}", file=sys.stderr, flush=True)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(n, na, args.cpu_slices)
     line = {
         "metric": "PDHG iters/s",
         "value": round(ips, 3),
@@ -151,13 +200,15 @@ def main():
         "config": {"workload": f"3D {n}^3 vial, {na} views over 360 deg, {n}x{n} detector, 6 random ellipsoids "
                                f"(seed 3000), band 10, blur sigma 1.5, Case 1 [0.9,1.0], restarted PDHG",
                    "n": n, "views": na, "case": 1, "blur_sigma": 1.5},
-        "a_plus_at_gbs": round(bytes_pair / ((t_p + t_bp) * 1e-3) / 1e9, 2),
-        "project_ms": round(t_p, 4),
-        "backproject_ms": round(t_bp, 4),
-        "roofline": {"bound": "alu", "kernel": dom_name, "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None},
+        "a_plus_at_gbs": round(pair_bytes / ((t_p + t_bp) * 1e-3) / 1e9, 2),
+        "phase_ms": {k: round(v, 4) for k, v in ph_avg.items()},
+        "roofline": {"bound": "alu", "kernel": "project3d" if dom == "project" else "backproject3d",
+                     "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic},
         "cpu_baseline": cpu,
     }
+    if ttk is not None:
+        line["time_to_1e-4"] = ttk
     print(json.dumps(line), flush=True)
     return 0
 

@@ -174,7 +174,22 @@ typedef struct {
     double eta;                /* restarted mode step factor (< 1), e.g. 0.95             */
     double infeas_tol;         /* restarted mode Farkas test tolerance, e.g. 1e-6         */
     int32_t use_graph;         /* 1 = capture the iteration block in a HIP graph          */
+    int32_t profile;           /* 1 = time every iteration launch with HIP events on the
+                                  solve's stream (per-phase totals in the result); cannot
+                                  be combined with use_graph                              */
 } sipo_pdhg_options;
+
+/* Phases of one PDHG iteration, for sipo_pdhg_result.phase_ms. */
+typedef enum {
+    SIPO_PHASE_PROJECT = 0,     /* P (forward projection of K z)                           */
+    SIPO_PHASE_BACKPROJECT = 1, /* P^T (of the new y)                                      */
+    SIPO_PHASE_BLUR = 2,        /* both applications of K                                  */
+    SIPO_PHASE_TRANSPOSE = 3,   /* layout changes between the volume kernels               */
+    SIPO_PHASE_PRIMAL = 4,      /* projected primal step on rays                           */
+    SIPO_PHASE_DUAL = 5,        /* fused dual step on voxels with its reductions           */
+    SIPO_PHASE_SCALARS = 6,     /* scalar (u, v) step and reduction finish                 */
+    SIPO_NUM_PHASES = 7
+} sipo_phase;
 
 typedef enum {
     SIPO_OPTIMAL = 0, SIPO_PRIMAL_INFEASIBLE = 1, SIPO_ITER_LIMIT = 2, SIPO_NUMERICAL = 3
@@ -189,6 +204,8 @@ typedef struct {
     double tau, sigma;         /* plain mode scalar steps                                 */
     double omega;              /* restarted mode final primal weight                      */
     double time_ms;            /* wall time of the solve on its stream                    */
+    double phase_ms[SIPO_NUM_PHASES];       /* profile mode: summed launch durations          */
+    int32_t phase_launches[SIPO_NUM_PHASES]; /* profile mode: launches timed per phase        */
 } sipo_pdhg_result;
 
 /* Bytes of device workspace sipo_pdhg_solve needs for these problems. */

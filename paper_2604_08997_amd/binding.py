@@ -49,7 +49,10 @@ class Problem(C.Structure):
 class PdhgOptions(C.Structure):
     _fields_ = [("mode", C.c_int32), ("max_iters", C.c_int32), ("check_every", C.c_int32), ("tol", C.c_double),
                 ("tau", C.c_double), ("sigma", C.c_double), ("power_iters", C.c_int32), ("eta", C.c_double),
-                ("infeas_tol", C.c_double), ("use_graph", C.c_int32)]
+                ("infeas_tol", C.c_double), ("use_graph", C.c_int32), ("profile", C.c_int32)]
+
+NUM_PHASES = 7
+PHASES = ("project", "backproject", "blur", "transpose", "primal", "dual", "scalars")
 
 
 class PdhgResult(C.Structure):
@@ -57,10 +60,14 @@ class PdhgResult(C.Structure):
                 ("primal_obj", C.c_double), ("dual_obj", C.c_double),
                 ("rel_primal", C.c_double), ("rel_dual", C.c_double), ("rel_gap", C.c_double),
                 ("u", C.c_double), ("v", C.c_double), ("tau", C.c_double), ("sigma", C.c_double),
-                ("omega", C.c_double), ("time_ms", C.c_double)]
+                ("omega", C.c_double), ("time_ms", C.c_double),
+                ("phase_ms", C.c_double * NUM_PHASES), ("phase_launches", C.c_int32 * NUM_PHASES)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("phase_")}
+        d["phase_ms"] = dict(zip(PHASES, list(self.phase_ms)))
+        d["phase_launches"] = dict(zip(PHASES, list(self.phase_launches)))
+        return d
 
 
 # name -> (restype, argtypes): every symbol declared in include/sipo.h
@@ -300,9 +307,9 @@ class LP:
 
 
 def pdhg_options(mode=RESTARTED, max_iters=20000, check_every=64, tol=1e-4, tau=0.0, sigma=0.0, power_iters=100,
-                 eta=0.95, infeas_tol=1e-6, use_graph=0):
+                 eta=0.95, infeas_tol=1e-6, use_graph=0, profile=0):
     return PdhgOptions(int(mode), int(max_iters), int(check_every), float(tol), float(tau), float(sigma),
-                       int(power_iters), float(eta), float(infeas_tol), int(use_graph))
+                       int(power_iters), float(eta), float(infeas_tol), int(use_graph), int(profile))
 
 
 def solve(lps, opts=None, want_dose=True, workspace=None):

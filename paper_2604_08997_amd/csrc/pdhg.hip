@@ -554,6 +554,7 @@ class Solver {
     }
     ~Solver() {
         if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+        for (hipEvent_t e : ev_) (void)hipEventDestroy(e);
     }
 
     int run(sipo_pdhg_result *res);
@@ -584,20 +585,70 @@ class Solver {
     T *V(void *p) { return (T *)p; }
     // operators on the solver's layouts: sinograms as held internally, volumes [z][y][x]
     int dose(const T *y, T *out) {   // out = K P^T y  (uses tmp when K != I)
-        if (!p_->has_psf) return launch_backproject_t(p_, y, out, 0, s_);
+        if (!p_->has_psf) {
+            int rc = launch_backproject_t(p_, y, out, 0, s_);
+            return rc ? rc : mark(SIPO_PHASE_BACKPROJECT);
+        }
         int rc = launch_backproject_t(p_, y, w_.tmp, 0, s_);
-        return rc ? rc : launch_blur(p_, w_.tmp, out, s_);
+        if (!rc) rc = mark(SIPO_PHASE_BACKPROJECT);
+        if (!rc) rc = launch_blur(p_, w_.tmp, out, s_);
+        return rc ? rc : mark(SIPO_PHASE_BLUR);
     }
     int adjoint(const T *z, T *out) {   // out = P K z
         const void *src = z;
         if (p_->has_psf) {
             int rc = launch_blur(p_, z, w_.tmp, s_);
+            if (!rc) rc = mark(SIPO_PHASE_BLUR);
             if (rc) return rc;
             src = w_.tmp;
         }
-        if (!t3_) return launch_project_t(p_, src, out, s_);
+        if (!t3_) {
+            int rc = launch_project_t(p_, src, out, s_);
+            return rc ? rc : mark(SIPO_PHASE_PROJECT);
+        }
         int rc = launch_vol_to_t(p_, src, w_.vol_t, s_);
-        return rc ? rc : launch_project_t(p_, w_.vol_t, out, s_);
+        if (!rc) rc = mark(SIPO_PHASE_TRANSPOSE);
+        if (!rc) rc = launch_project_t(p_, w_.vol_t, out, s_);
+        return rc ? rc : mark(SIPO_PHASE_PROJECT);
+    }
+    // ---- profile mode: a timeline of events between consecutive iteration launches
+    bool prof_on_ = false;                // inside an iteration of a profiled solve
+    std::vector<hipEvent_t> ev_;
+    std::vector<int> ev_phase_;           // phase of the launch that ends at ev_[i]
+    size_t ev_used_ = 0;
+    double phase_ms_[SIPO_NUM_PHASES] = {};
+    int phase_n_[SIPO_NUM_PHASES] = {};
+    int mark(int phase) {
+        if (!prof_on_) return SIPO_OK;
+        if (ev_used_ == ev_.size()) {
+            if (ev_.size() >= 4096) {
+                int rc = flush_profile();
+                if (rc) return rc;
+            } else {
+                hipEvent_t e;
+                SIPO_HIP(hipEventCreate(&e));
+                ev_.push_back(e);
+                ev_phase_.push_back(-1);
+            }
+        }
+        ev_phase_[ev_used_] = phase;
+        SIPO_HIP(hipEventRecord(ev_[ev_used_], s_));
+        ++ev_used_;
+        return SIPO_OK;
+    }
+    int flush_profile() {   // fold the recorded intervals into the phase totals
+        if (ev_used_ == 0) return SIPO_OK;
+        SIPO_HIP(hipEventSynchronize(ev_[ev_used_ - 1]));
+        for (size_t i = 1; i < ev_used_; ++i) {
+            const int ph = ev_phase_[i];
+            if (ph < 0) continue;   // interval that starts a new timeline segment
+            float ms = 0.f;
+            SIPO_HIP(hipEventElapsedTime(&ms, ev_[i - 1], ev_[i]));
+            phase_ms_[ph] += ms;
+            phase_n_[ph] += 1;
+        }
+        ev_used_ = 0;
+        return SIPO_OK;
     }
     int sums(int nblocks, int ns, double *host) {
         hipLaunchKernelGGL(finish_sums, dim3(1), dim3(kThreads), 0, s_, w_.partials, nblocks, w_.scal->sums, ns);
@@ -784,12 +835,15 @@ int Solver<T>::farkas(const T *alu, const T *all, const T *blu, const T *bll, do
 template <typename T>
 int Solver<T>::iteration(bool check) {
     const bool hal = o_.mode == SIPO_PDHG_RESTARTED;
-    int rc = adjoint((const T *)w_.z, V(w_.q));
+    prof_on_ = o_.profile != 0;
+    int rc = mark(-1);   // start of this iteration's timeline segment
+    if (!rc) rc = adjoint((const T *)w_.z, V(w_.q));
     if (rc) return rc;
     hipLaunchKernelGGL((k_primal<T>), dim3(gs_), dim3(kThreads), 0, s_, y_, V(w_.yt), (const T *)w_.q,
                        hal ? (const T *)w_.Tj : (const T *)nullptr, act_, hal ? (const T *)w_.y0 : (const T *)nullptr,
                        (const DevScal *)w_.scal, ns_);
-    rc = dose((const T *)w_.yt, V(w_.Dt));
+    rc = mark(SIPO_PHASE_PRIMAL);
+    if (!rc) rc = dose((const T *)w_.yt, V(w_.Dt));
     if (rc) return rc;
     hipLaunchKernelGGL((k_dual<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)w_.Dt, V(w_.D),
                        hal ? (const T *)w_.D0 : (const T *)nullptr, lu_, ll_,
@@ -798,8 +852,12 @@ int Solver<T>::iteration(bool check) {
                        hal ? (const T *)w_.s_lo : (const T *)nullptr, check ? V(w_.lut) : (T *)nullptr,
                        check ? V(w_.llt) : (T *)nullptr, check ? V(w_.luo) : (T *)nullptr,
                        check ? V(w_.llo) : (T *)nullptr, (const DevScal *)w_.scal, c_, nv_, w_.partials);
+    rc = mark(SIPO_PHASE_DUAL);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_scalars, dim3(1), dim3(kThreads), 0, s_, w_.partials, gv_, w_.scal, c_);
-    return SIPO_OK;
+    rc = mark(SIPO_PHASE_SCALARS);
+    prof_on_ = false;
+    return rc;
 }
 
 // nblk iterations, the last one a check iteration; captured once into a graph when requested.
@@ -898,6 +956,7 @@ int Solver<T>::run(sipo_pdhg_result *res) {
     while (it < o_.max_iters) {
         const int nblk = std::min(check, o_.max_iters - it);
         rc = run_block(nblk);
+        if (!rc) rc = flush_profile();
         if (rc) return rc;
         it += nblk;
         have_t = true;
@@ -1027,6 +1086,10 @@ int Solver<T>::run(sipo_pdhg_result *res) {
     res->sigma = sigma;
     res->omega = omega;
     res->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int ph = 0; ph < SIPO_NUM_PHASES; ++ph) {
+        res->phase_ms[ph] = phase_ms_[ph];
+        res->phase_launches[ph] = phase_n_[ph];
+    }
     return SIPO_OK;
 }
 
@@ -1042,6 +1105,7 @@ static int validate(const sipo_problem &pb, const sipo_pdhg_options &o, int idx)
                  "problem %d: scalars must be finite", idx);
     SIPO_REQUIRE(o.mode == SIPO_PDHG_PLAIN || o.mode == SIPO_PDHG_RESTARTED, "unknown PDHG mode %d", o.mode);
     SIPO_REQUIRE(o.max_iters >= 1, "max_iters must be >= 1");
+    SIPO_REQUIRE(!(o.profile && o.use_graph), "profile and use_graph cannot be combined");
     SIPO_REQUIRE(o.mode == SIPO_PDHG_PLAIN || o.check_every >= 1, "check_every must be >= 1");
     SIPO_REQUIRE(!(o.eta >= 1.0), "eta must be < 1");
     return SIPO_OK;
