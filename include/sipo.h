@@ -162,6 +162,12 @@ typedef struct {
     void *dose_out;            /* device [nz][n][n] or NULL: D = K P^T y* on return */
 } sipo_problem;
 
+/* PLAIN: Chambolle-Pock steps with scalar tau = sigma = 0.9/||G|| (FP64 power
+ * iteration), no restarts, max_iters iterations, then a KKT evaluation.
+ * RESTARTED: reflected Halpern PDHG with diagonal (Pock-Chambolle) steps, a
+ * primal weight, KKT termination checks on the PDHG output every
+ * check_every iterations, adaptive restarts and Farkas infeasibility tests
+ * (prior art: PDLP, and Halpern/restart schemes for PDHG on LPs). */
 typedef enum { SIPO_PDHG_PLAIN = 0, SIPO_PDHG_RESTARTED = 1 } sipo_pdhg_mode;
 
 typedef struct {
