@@ -7,3 +7,4 @@ package is the thin Python binding over it.
 from .binding import (Plan, SipoError, lib, version, gaussian_taps, LIB_PATH,  # noqa: F401
                       PLAIN, RESTARTED, OPTIMAL, PRIMAL_INFEASIBLE, ITER_LIMIT, NUMERICAL, STATUS_NAMES,
                       LP, GENERAL, CASE1, CASE2, pdhg_options, solve)
+from .autograd import SipoDose, dose  # noqa: F401,E402
