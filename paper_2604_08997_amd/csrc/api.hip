@@ -115,9 +115,14 @@ int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype 
     p->d_ranges = nullptr;
     p->d_vial_rows = nullptr;
     p->d_zero = nullptr;
+    p->d_geo2d = nullptr;
+    p->d_items_bp2d = p->d_items_fp2d = nullptr;
+    p->n_items_bp2d = p->n_items_fp2d = 0;
+    p->p2d_ok = false;
     p->d_vol_t = nullptr;
     p->d_sino_t = nullptr;
     rc = plan_build_batches(p, trig.data());
+    if (rc == SIPO_OK) rc = plan_build_2d(p);
     if (rc != SIPO_OK) {
         (void)hipFree(p->d_trig); (void)hipFree(p->d_angle_order); (void)hipFree(p->d_scratch);
         (void)hipFree(p->d_batches);
@@ -125,6 +130,9 @@ int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype 
         (void)hipFree(p->d_ranges);
         (void)hipFree(p->d_vial_rows);
         (void)hipFree(p->d_zero);
+        (void)hipFree(p->d_geo2d);
+        (void)hipFree(p->d_items_bp2d);
+        (void)hipFree(p->d_items_fp2d);
         delete p;
         return rc;
     }
@@ -145,6 +153,9 @@ int sipo_plan_destroy(sipo_plan p) {
     (void)hipFree(p->d_ranges);
     (void)hipFree(p->d_vial_rows);
     (void)hipFree(p->d_zero);
+    (void)hipFree(p->d_geo2d);
+    (void)hipFree(p->d_items_bp2d);
+    (void)hipFree(p->d_items_fp2d);
     if (p->d_vol_t) (void)hipFree(p->d_vol_t);
     if (p->d_sino_t) (void)hipFree(p->d_sino_t);
     if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);

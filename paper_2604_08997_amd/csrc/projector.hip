@@ -705,6 +705,7 @@ int plan_build_batches(sipo_plan p, const double2 *trig) {
     const int nc = (int)std::floor(2.0 / min_du + 1e-6) + 1;
     p->p3d_nc = nc <= 3 ? 3 : (nc <= 4 ? 4 : (nc <= 6 ? 6 : 0));
     p->p3d_pair = pair;
+    p->n_walk = nw;
     p->p3d_zc = p->dtype == SIPO_F64 ? 16 : 32;
     p->blur_zc = 0;
     p->n_batches = (int)batches.size();
@@ -898,6 +899,8 @@ int launch_mask_to_t(sipo_plan p, const uint8_t *mask, uint8_t *mask_t, hipStrea
 // Internal-layout entry points (see sipo_internal.hpp).  Slice and fallback
 // plans have no separate internal layout: they run the slice kernels directly.
 int launch_backproject_t(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s) {
+    if (p->p2d_ok)
+        return launch_bp2d(p->dtype, p->d_geo2d, p->d_items_bp2d, p->n_items_bp2d, sino_t, vol, accumulate, s);
     if (!p->fast3d())
         return p->dtype == SIPO_F64 ? bp_slices<double>(p, sino_t, vol, accumulate, s)
                                     : bp_slices<float>(p, sino_t, vol, accumulate, s);
@@ -906,6 +909,8 @@ int launch_backproject_t(sipo_plan p, const void *sino_t, void *vol, int accumul
 }
 
 int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+    if (p->p2d_ok)
+        return launch_fp2d(p->dtype, p->p3d_nc, p->d_geo2d, p->d_items_fp2d, p->n_items_fp2d, vol_t, sino_t, 0, s);
     if (!p->fast3d())
         return p->dtype == SIPO_F64 ? fp_slices<double>(p, vol_t, sino_t, 0, s)
                                     : fp_slices<float>(p, vol_t, sino_t, 0, s);
@@ -927,6 +932,9 @@ int launch_backproject(sipo_plan p, const void *sino, void *vol, int accumulate,
 }
 
 int launch_project(sipo_plan p, const void *vol, void *sino, int accumulate, hipStream_t s) {
+    if (p->p2d_ok)
+        return launch_fp2d(p->dtype, p->p3d_nc, p->d_geo2d, p->d_items_fp2d, p->n_items_fp2d, vol, sino, accumulate,
+                           s);
     if (!p->fast3d())
         return p->dtype == SIPO_F64 ? fp_slices<double>(p, vol, sino, accumulate, s)
                                     : fp_slices<float>(p, vol, sino, accumulate, s);

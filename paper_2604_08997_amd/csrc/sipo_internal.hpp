@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <vector>
 
 #include <cmath>
 #include <cstdint>
@@ -50,6 +51,8 @@ struct Taps {
 // Small device scratch owned by a plan: reduction partials and scalars.
 constexpr size_t kPlanScratchBytes = 1 << 20;
 
+struct Geo2D;
+
 }  // namespace sipo
 
 struct sipo_plan_s {
@@ -79,6 +82,11 @@ struct sipo_plan_s {
     int2 *d_ranges;         // [n_batches][bin groups][chunks of kDmaCM steps]: staged cross range (j0, count)
     int2 *d_vial_rows;      // [n]: first and last index along a grid line inside the vial
     void *d_zero;           // 256 zero bytes (source of empty staging slots)
+    int n_walk;             // views the projector walks (entries of d_angle_order)
+    bool p2d_ok;            // single-slice plan served by the 2D kernels
+    sipo::Geo2D *d_geo2d;   // this plan as a one-instance batch
+    int4 *d_items_bp2d, *d_items_fp2d;
+    int n_items_bp2d, n_items_fp2d;
     int blur_zc;            // slices per blur workgroup (0 = built-in choice)
     bool bp3d_ok;           // the 3D backprojector's bin window fits its LDS tile
     void *d_vol_t;          // lazily allocated [y][x][z] scratch volume (standalone 3D calls)
@@ -108,6 +116,30 @@ int launch_sino_from_t(sipo_plan p, const void *sino_t, void *sino, int accumula
 int launch_mask_to_t(sipo_plan p, const uint8_t *mask, uint8_t *mask_t, hipStream_t s);
 int plan_build_batches(sipo_plan p, const double2 *trig_host);
 constexpr int kPB = 32, kPV = 8, kPCM = 4, kPCR = 96;   // bins, views, steps per stage, max staged cross range
+
+// 2D (single-slice) operators, batched over instances.  One Geo2D describes an
+// instance: its plan's tables and where its arrays sit in packed sinogram and
+// volume arrays (element offsets).  Work items are int4 records.
+struct Geo2D {
+    const double2 *trig;     // [n_angles] (sin, cos)
+    const int *walk;         // walked views (first of each opposite pair when pair != 0)
+    const int *partner;      // [n_angles] opposite view or -1
+    long long soff, voff;    // offsets of the instance's sinogram / volume
+    int n, n_angles, n_bins, n_walk;
+    int pair, nc;            // views walked in opposite pairs; candidate voxels per ray step
+    double h, inv_ds, atten;
+};
+constexpr int kB2X = 32, kB2Y = 8;   // P^T tile: 32 x 8 voxels per workgroup
+constexpr int kF2B = 64, kF2V = 4;   // P bundle: 64 bins x 4 walked views per workgroup
+Geo2D plan_geo2d(sipo_plan p, long long soff, long long voff);
+// Items of one instance appended to a list: P^T (geo, x0, y0, 0) and P (geo, first walked view, b0, 0).
+void append_items_bp2d(const Geo2D &g, int geo_index, std::vector<int4> &items);
+void append_items_fp2d(const Geo2D &g, int geo_index, std::vector<int4> &items);
+int launch_bp2d(sipo_dtype dt, const Geo2D *geo, const int4 *items, int n_items, const void *sino, void *vol,
+                int accumulate, hipStream_t s);
+int launch_fp2d(sipo_dtype dt, int nc, const Geo2D *geo, const int4 *items, int n_items, const void *vol,
+                void *sino, int accumulate, hipStream_t s);
+int plan_build_2d(sipo_plan p);
 
 // ------------------------------------------------------------- geometry
 // The per-(voxel, view) interpolation taps, shared verbatim by the
