@@ -1,4 +1,5 @@
-// Matrix-free PDHG for the unified Charnes-Cooper LP (Sec. 2.8, Supp. 6.1).
+// Matrix-free PDHG for the unified Charnes-Cooper LP (Sec. 2.8, Supp. 6.1),
+// for one instance or a batch of independent instances advanced in lockstep.
 //
 // Saddle problem  min_{x in X} max_{lambda >= 0} c^T x + lambda^T (G x - h)
 // with x = (y, u, v), D = K P^T y and the rows (band: D - u_bar, gel: D - v_bar U,
@@ -27,11 +28,19 @@
 //                   residuals; a restart moves z and z0 to t and updates omega
 //                   from the movement since the previous restart.
 //
-// All iteration-varying scalars live in a device block, so an iteration is a
-// fixed sequence of launches with fixed arguments; a block of iterations can
-// be captured once in a HIP graph and replayed.  Reductions are two-level
-// (per-block FP64 partials summed in a fixed order by one block), so results
-// are deterministic.
+// Batching.  Every instance's arrays are packed into shared workspace fields
+// (instance i at element offsets soff_i / voff_i).  Streaming kernels run over
+// segment tables (one workgroup = one chunk of one instance), so one launch
+// serves all unfinished instances; reductions leave per-workgroup FP64 partials
+// that are summed per instance in a fixed order (deterministic).  Single-slice
+// instances without blur share one launch per operator (work-item kernels);
+// other instances run their plan's operators one after another.  Checks,
+// restarts and terminations are decided per instance; a finished instance
+// leaves the tables and keeps its returned point untouched.
+//
+// All iteration-varying scalars live in per-instance device blocks, so an
+// iteration is a fixed sequence of launches with fixed arguments; a block of
+// iterations can be captured once in a HIP graph and replayed.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -41,11 +50,11 @@
 
 namespace sipo {
 
-constexpr int kRedBlocks = 1024;   // upper bound on reduction blocks
-constexpr int kNS = 8;             // sums carried per reduction
+constexpr int kNS = 8;                 // sums carried per reduction
 constexpr int kThreads = 256;
+constexpr long long kChunk = 4096;     // elements per workgroup in segmented launches
 
-// Device scalar block (FP64): everything that changes from one iteration to the next.
+// Device scalar block (FP64) of one instance.
 struct DevScal {
     double u, v;              // z.u, z.v (Halpern iterate)
     double ut, vt;            // t.u, t.v of the iteration about to run
@@ -58,13 +67,28 @@ struct DevScal {
     double k_in;              // iterations since the last restart
     double halpern;           // 1 = restarted mode (w = (k+1)/(k+2)), 0 = plain (w = 1)
     double sum_l1, sum_Ul2;   // sums of the current lambda
-    double sums[kNS];         // last generic reduction result
+    double init_l1, init_Ul2; // lambda sums handed to k_scalars_init
 };
 
 struct LPConst {
     int u_free, v_free;
     double w1, w2, h;         // weights and band cap
     double lo_s, hi_s;        // scalar bounds when arrays are absent
+};
+
+// Per-instance constants and per-call selectors on the device.
+struct InstC {
+    LPConst c;
+    double eu, ev;            // scalars for KKT / power-iteration evaluations
+    double fac;               // per-instance scale factor (power iteration)
+    int flag;                 // selects instances for subset operations
+    int sel;                  // certificate pair: 0 = (t, pre-step), 1 = (t, snapshot)
+};
+
+// One workgroup's share of a segmented launch: instance and packed element range.
+struct Seg {
+    int inst, pad;
+    long long b, e;
 };
 
 // -------------------------------------------------------------- reductions
@@ -74,30 +98,29 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-template <int NS>
-__device__ __forceinline__ void block_sums(double (&v)[NS], double *partials) {
-    __shared__ double red[kThreads / 64][NS];
+__device__ __forceinline__ void block_sums(double (&v)[kNS], double *partials) {
+    __shared__ double red[kThreads / 64][kNS];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
+    for (int k = 0; k < kNS; ++k) {
         const double s = wave_sum(v[k]);
         if (lane == 0) red[w][k] = s;
     }
     __syncthreads();
-    if (threadIdx.x < NS) {
+    if (threadIdx.x < kNS) {
         double s = 0.0;
         for (int i = 0; i < kThreads / 64; ++i) s += red[i][threadIdx.x];
         partials[blockIdx.x * kNS + threadIdx.x] = s;
     }
 }
 
-// Total of column k of the per-block partials, by one block of kThreads threads:
-// strided per-thread sums, then a fixed tree, so the result does not depend on timing.
+// Total of column k over partials[first .. first + count), by one block: strided
+// per-thread sums, then a fixed tree, so the result does not depend on timing.
 template <bool MAX>
-__device__ double block_total(const double *__restrict__ partials, int nblocks, int k, double *sh) {
+__device__ double block_total(const double *__restrict__ partials, int first, int count, int k, double *sh) {
     double a = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kThreads) {
-        const double v = partials[b * kNS + k];
+    for (int b = threadIdx.x; b < count; b += kThreads) {
+        const double v = partials[(size_t)(first + b) * kNS + k];
         a = MAX ? fmax(a, v) : a + v;
     }
     sh[threadIdx.x] = a;
@@ -112,71 +135,79 @@ __device__ double block_total(const double *__restrict__ partials, int nblocks, 
     return r;
 }
 
-// Sum per-block partials into dst[0..ns).
-__global__ void __launch_bounds__(kThreads) finish_sums(const double *__restrict__ partials, int nblocks,
-                                                         double *dst, int ns) {
+// out[i][k] for the instances i = list[blockIdx.x]: totals of their workgroups' partials.
+template <bool MAX>
+__global__ void __launch_bounds__(kThreads) k_finish(const double *__restrict__ partials, const int *__restrict__ first,
+                                                      const int *__restrict__ count, const int *__restrict__ list,
+                                                      int ns, double *__restrict__ out) {
     __shared__ double sh[kThreads];
+    const int i = list[blockIdx.x];
     for (int k = 0; k < ns; ++k) {
-        const double r = block_total<false>(partials, nblocks, k, sh);
-        if (threadIdx.x == 0) dst[k] = r;
+        const double r = block_total<MAX>(partials, first[i], count[i], k, sh);
+        if (threadIdx.x == 0) out[(size_t)i * kNS + k] = r;
     }
 }
 
-#define GRID_LOOP(i, n) \
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
+#define SEG_LOOP(i) \
+    const Seg sg_ = segs[blockIdx.x]; \
+    for (long long i = sg_.b + threadIdx.x; i < sg_.e; i += kThreads)
 
 template <typename T>
-__device__ __forceinline__ T ld_or(const T *p, size_t i, double s) { return p ? p[i] : (T)s; }
+__device__ __forceinline__ T ld_or(const T *p, long long i, double s) { return p ? p[i] : (T)s; }
 
-// ------------------------------------------------------------- setup kernels
+// ------------------------------------------------------------ setup kernels
 // y <- act ? max(y, 0) : 0  (warm start projected onto X)
 template <typename T>
-__global__ void k_project_y(T *y, const uint8_t *act, size_t n) {
-    GRID_LOOP(i, n) y[i] = act[i] ? (y[i] > (T)0 ? y[i] : (T)0) : (T)0;
+__global__ void k_project_y(T *y, const uint8_t *act, const Seg *segs) {
+    SEG_LOOP(i) y[i] = act[i] ? (y[i] > (T)0 ? y[i] : (T)0) : (T)0;
 }
 
 // lambda projected onto its regions and >= 0; z = lambda_up - lambda_lo; [0] sum_band lambda1, [1] sum_gel U lambda2.
 template <typename T>
-__global__ void k_lambda_z(T *lu, T *ll, T *z, const uint8_t *lab, const T *hi, LPConst c, size_t n,
-                           double *partials) {
+__global__ void k_lambda_z(T *lu, T *ll, T *z, const uint8_t *lab, const T *hi, const InstC *insts, const Seg *segs,
+                           int use_flag, double *partials) {
     double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
-    GRID_LOOP(i, n) {
-        const uint8_t L = lab[i];
-        T a = L ? (lu[i] > (T)0 ? lu[i] : (T)0) : (T)0;
-        T b = (L == 2) ? (ll[i] > (T)0 ? ll[i] : (T)0) : (T)0;
-        lu[i] = a;
-        ll[i] = b;
-        z[i] = a - b;
-        if (L == 1) acc[0] += (double)a;
-        if (L == 2) acc[1] += (double)ld_or(hi, i, c.hi_s) * (double)a;
+    const InstC &ic = insts[segs[blockIdx.x].inst];
+    if (!use_flag || ic.flag) {
+        SEG_LOOP(i) {
+            const uint8_t L = lab[i];
+            T a = L ? (lu[i] > (T)0 ? lu[i] : (T)0) : (T)0;
+            T b = (L == 2) ? (ll[i] > (T)0 ? ll[i] : (T)0) : (T)0;
+            lu[i] = a;
+            ll[i] = b;
+            z[i] = a - b;
+            if (L == 1) acc[0] += (double)a;
+            if (L == 2) acc[1] += (double)ld_or(hi, i, ic.c.hi_s) * (double)a;
+        }
     }
-    block_sums<kNS>(acc, partials);
+    block_sums(acc, partials);
 }
 
 // w = 1 on band, 2 on gel (absolute column weights of G)
 template <typename T>
-__global__ void k_colweight(T *w, const uint8_t *lab, size_t n) {
-    GRID_LOOP(i, n) w[i] = lab[i] == 1 ? (T)1 : (lab[i] == 2 ? (T)2 : (T)0);
+__global__ void k_colweight(T *w, const uint8_t *lab, const Seg *segs) {
+    SEG_LOOP(i) w[i] = lab[i] == 1 ? (T)1 : (lab[i] == 2 ? (T)2 : (T)0);
 }
 
 template <typename T>
-__global__ void k_act_to_float(T *a, const uint8_t *act, size_t n) {
-    GRID_LOOP(i, n) a[i] = act[i] ? (T)1 : (T)0;
+__global__ void k_act_to_float(T *a, const uint8_t *act, const Seg *segs) {
+    SEG_LOOP(i) a[i] = act[i] ? (T)1 : (T)0;
 }
 
 // T_j = act & colsum > 0 ? 1 / colsum : 0
 template <typename T>
-__global__ void k_inv_colsum(T *t, const uint8_t *act, size_t n) {
-    GRID_LOOP(i, n) t[i] = (act[i] && t[i] > (T)0) ? (T)1 / t[i] : (T)0;
+__global__ void k_inv_colsum(T *t, const uint8_t *act, const Seg *segs) {
+    SEG_LOOP(i) t[i] = (act[i] && t[i] > (T)0) ? (T)1 / t[i] : (T)0;
 }
 
 // S_up = 1/(R + [band, u free] + [gel, v free] U), S_lo = [gel] 1/R;
 // [0] |band|, [1] sum_gel U, [2] ||h||^2, [3] |gel|
 template <typename T>
-__global__ void k_row_scaling(const T *R, T *s_up, T *s_lo, const uint8_t *lab, const T *lo, const T *hi, LPConst c,
-                              size_t n, double *partials) {
+__global__ void k_row_scaling(const T *R, T *s_up, T *s_lo, const uint8_t *lab, const T *lo, const T *hi,
+                              const InstC *insts, const Seg *segs, double *partials) {
     double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
-    GRID_LOOP(i, n) {
+    const LPConst c = insts[segs[blockIdx.x].inst].c;
+    SEG_LOOP(i) {
         const uint8_t L = lab[i];
         const T r = R[i];
         T su = 0, sl = 0;
@@ -197,18 +228,19 @@ __global__ void k_row_scaling(const T *R, T *s_up, T *s_lo, const uint8_t *lab, 
         s_up[i] = su;
         s_lo[i] = sl;
     }
-    block_sums<kNS>(acc, partials);
+    block_sums(acc, partials);
 }
 
 // --------------------------------------------------------- iteration kernels
 // t.y = act ? max(0, y - tau q) : 0 with tau = tau_fac T_j (or tau_fac); y <- w ((1+rho) t.y - rho y) + (1-w) y0.
 template <typename T>
 __global__ void k_primal(T *__restrict__ y, T *__restrict__ yt, const T *__restrict__ q, const T *__restrict__ Tj,
-                         const uint8_t *__restrict__ act, const T *__restrict__ y0, const DevScal *__restrict__ sc,
-                         size_t n) {
-    const T tf = (T)sc->tau_fac;
-    const T w = (T)sc->w, rho = (T)sc->rho;
-    GRID_LOOP(i, n) {
+                         const uint8_t *__restrict__ act, const T *__restrict__ y0, const DevScal *__restrict__ scal,
+                         const Seg *__restrict__ segs) {
+    const DevScal &sc = scal[segs[blockIdx.x].inst];
+    const T tf = (T)sc.tau_fac;
+    const T w = (T)sc.w, rho = (T)sc.rho;
+    SEG_LOOP(i) {
         T t = (T)0;
         const T yo = y[i];
         if (act[i]) {
@@ -229,14 +261,17 @@ __global__ void k_dual(const T *__restrict__ Dt, T *__restrict__ D, const T *__r
                        T *__restrict__ ll, const T *__restrict__ lu0, const T *__restrict__ ll0, T *__restrict__ z,
                        const uint8_t *__restrict__ lab, const T *__restrict__ lo, const T *__restrict__ hi,
                        const T *__restrict__ s_up, const T *__restrict__ s_lo, T *__restrict__ lut,
-                       T *__restrict__ llt, T *__restrict__ luo, T *__restrict__ llo, const DevScal *__restrict__ sc,
-                       LPConst c, size_t n, double *partials) {
-    const double sf = sc->sig_fac;
-    const T ub = (T)(c.u_free ? sc->ubar : c.h);
-    const T vb = (T)(c.v_free ? sc->vbar : 1.0);
-    const T w = (T)sc->w, rho = (T)sc->rho, w1 = (T)1 - w, rp = (T)1 + rho;
+                       T *__restrict__ llt, T *__restrict__ luo, T *__restrict__ llo, const DevScal *__restrict__ scal,
+                       const InstC *__restrict__ insts, const Seg *__restrict__ segs, double *partials) {
+    const int inst = segs[blockIdx.x].inst;
+    const DevScal &sc = scal[inst];
+    const LPConst c = insts[inst].c;
+    const double sf = sc.sig_fac;
+    const T ub = (T)(c.u_free ? sc.ubar : c.h);
+    const T vb = (T)(c.v_free ? sc.vbar : 1.0);
+    const T w = (T)sc.w, rho = (T)sc.rho, w1 = (T)1 - w, rp = (T)1 + rho;
     double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
-    GRID_LOOP(i, n) {
+    SEG_LOOP(i) {
         const T dt = Dt[i], dz = D[i];
         D[i] = D0 ? w * (rp * dt - rho * dz) + w1 * D0[i] : dt;
         const uint8_t L = lab[i];
@@ -265,7 +300,7 @@ __global__ void k_dual(const T *__restrict__ Dt, T *__restrict__ D, const T *__r
         }
         z[i] = zz;
     }
-    block_sums<kNS>(acc, partials);
+    block_sums(acc, partials);
 }
 
 // Next scalar primal step from the current z and the lambda sums.
@@ -276,13 +311,18 @@ __device__ __forceinline__ void roll_next(DevScal *sc, const LPConst &c) {
     sc->vbar = 2.0 * sc->vt - sc->v;
 }
 
-// One block: finish the lambda sums, apply the Halpern update to (u, v), prepare the next step.
-__global__ void __launch_bounds__(kThreads) k_scalars(const double *__restrict__ partials, int nblocks,
-                                                       DevScal *sc, LPConst c) {
+// One block per listed instance: finish its lambda sums, Halpern update of (u, v), next step.
+__global__ void __launch_bounds__(kThreads) k_scalars(const double *__restrict__ partials,
+                                                       const int *__restrict__ first, const int *__restrict__ count,
+                                                       const int *__restrict__ list, DevScal *scal,
+                                                       const InstC *__restrict__ insts) {
     __shared__ double sh[kThreads];
-    const double s0 = block_total<false>(partials, nblocks, 0, sh);
-    const double s1 = block_total<false>(partials, nblocks, 1, sh);
+    const int i = list[blockIdx.x];
+    const double s0 = block_total<false>(partials, first[i], count[i], 0, sh);
+    const double s1 = block_total<false>(partials, first[i], count[i], 1, sh);
     if (threadIdx.x != 0) return;
+    DevScal *sc = scal + i;
+    const LPConst c = insts[i].c;
     const double w = sc->w, rho = sc->rho;
     sc->ut_done = sc->ut;
     sc->vt_done = sc->vt;
@@ -297,23 +337,30 @@ __global__ void __launch_bounds__(kThreads) k_scalars(const double *__restrict__
     roll_next(sc, c);
 }
 
-// After a (re)start: sums of lambda in sums[0..1]; set the weight and the first step.
-__global__ void k_scalars_init(DevScal *sc, LPConst c) {
-    sc->sum_l1 = sc->sums[0];
-    sc->sum_Ul2 = sc->sums[1];
-    sc->k_in = 0.0;
-    sc->w = sc->halpern != 0.0 ? 0.5 : 1.0;
-    roll_next(sc, c);
+// After a (re)start of the flagged instances: lambda sums from init_*, Halpern weight, first step.
+__global__ void k_scalars_init(DevScal *scal, const InstC *insts, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        if (!insts[i].flag) continue;
+        DevScal *sc = scal + i;
+        sc->sum_l1 = sc->init_l1;
+        sc->sum_Ul2 = sc->init_Ul2;
+        sc->k_in = 0.0;
+        sc->w = sc->halpern != 0.0 ? 0.5 : 1.0;
+        roll_next(sc, insts[i].c);
+    }
 }
 
 // ---------------------------------------------------------------- KKT pieces
-// Voxel side at (D, u, v, lambda): [0] ||(Gx-h)^+||^2 voxel rows, [1] sum L lambda3,
+// Voxel side at (D, eu, ev, lambda): [0] ||(Gx-h)^+||^2 voxel rows, [1] sum L lambda3,
 // [2] sum_band lambda1, [3] sum_gel U lambda2.
 template <typename T>
 __global__ void k_kkt_vox(const T *D, const T *lu, const T *ll, const uint8_t *lab, const T *lo, const T *hi,
-                          LPConst c, double u, double v, size_t n, double *partials) {
+                          const InstC *insts, const Seg *segs, double *partials) {
     double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
-    GRID_LOOP(i, n) {
+    const InstC &ic = insts[segs[blockIdx.x].inst];
+    const LPConst c = ic.c;
+    const double u = ic.eu, v = ic.ev;
+    SEG_LOOP(i) {
         const uint8_t L = lab[i];
         if (L == 0) continue;
         const double d = (double)D[i];
@@ -330,14 +377,14 @@ __global__ void k_kkt_vox(const T *D, const T *lu, const T *ll, const uint8_t *l
             acc[3] += U * (double)lu[i];
         }
     }
-    block_sums<kNS>(acc, partials);
+    block_sums(acc, partials);
 }
 
 // Ray side: [0] sum_act min(q,0)^2, [1] sum_act y^-^2 + sum_mask y^2.
 template <typename T>
-__global__ void k_kkt_ray(const T *q, const T *y, const uint8_t *act, size_t n, double *partials) {
+__global__ void k_kkt_ray(const T *q, const T *y, const uint8_t *act, const Seg *segs, double *partials) {
     double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
-    GRID_LOOP(i, n) {
+    SEG_LOOP(i) {
         const double yi = (double)y[i];
         if (act[i]) {
             const double qi = (double)q[i];
@@ -347,44 +394,53 @@ __global__ void k_kkt_ray(const T *q, const T *y, const uint8_t *act, size_t n, 
             acc[1] += yi * yi;
         }
     }
-    block_sums<kNS>(acc, partials);
+    block_sums(acc, partials);
 }
 
-// Farkas candidate d = max(a - b, 0) on the regions -> z_d; [0] sum L d3, [1] sum_band d1,
-// [2] sum_gel U d2, [3] ||d||_1.
+// Farkas candidate d = max(a - b, 0) on the regions of the flagged instances -> z_d;
+// [0] sum L d3, [1] sum_band d1, [2] sum_gel U d2, [3] ||d||_1.
 template <typename T>
 __global__ void k_ray_candidate(const T *alu, const T *all, const T *blu, const T *bll, T *zd, const uint8_t *lab,
-                                const T *lo, const T *hi, LPConst c, size_t n, double *partials) {
+                                const T *lo, const T *hi, const InstC *insts, const Seg *segs, double *partials) {
     double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
-    GRID_LOOP(i, n) {
-        const uint8_t L = lab[i];
-        T zz = 0;
-        if (L) {
-            T a = alu[i] - blu[i];
-            a = a > (T)0 ? a : (T)0;
-            zz = a;
-            acc[3] += (double)a;
-            if (L == 1) {
-                acc[1] += (double)a;
-            } else {
-                T b = all[i] - bll[i];
-                b = b > (T)0 ? b : (T)0;
-                zz = a - b;
-                acc[0] += (double)ld_or(lo, i, c.lo_s) * (double)b;
-                acc[2] += (double)ld_or(hi, i, c.hi_s) * (double)a;
-                acc[3] += (double)b;
+    const InstC &ic = insts[segs[blockIdx.x].inst];
+    if (ic.flag) {
+        const LPConst c = ic.c;
+        SEG_LOOP(i) {
+            const uint8_t L = lab[i];
+            T zz = 0;
+            if (L) {
+                T a = alu[i] - blu[i];
+                a = a > (T)0 ? a : (T)0;
+                zz = a;
+                acc[3] += (double)a;
+                if (L == 1) {
+                    acc[1] += (double)a;
+                } else {
+                    T b = all[i] - bll[i];
+                    b = b > (T)0 ? b : (T)0;
+                    zz = a - b;
+                    acc[0] += (double)ld_or(lo, i, c.lo_s) * (double)b;
+                    acc[2] += (double)ld_or(hi, i, c.hi_s) * (double)a;
+                    acc[3] += (double)b;
+                }
             }
+            zd[i] = zz;
         }
-        zd[i] = zz;
     }
-    block_sums<kNS>(acc, partials);
+    block_sums(acc, partials);
 }
 
-// Certificate output: out = max(a - b, 0) on the regions (lambda_lo on gel only).
+// Certificate output of the flagged instances: max(a - b, 0) on the regions with b the
+// pre-step (sel 0) or snapshot (sel 1) lambda.
 template <typename T>
-__global__ void k_certificate(T *olu, T *oll, const T *alu, const T *all, const T *blu, const T *bll,
-                              const uint8_t *lab, size_t n) {
-    GRID_LOOP(i, n) {
+__global__ void k_certificate(T *olu, T *oll, const T *alu, const T *all, const T *blu0, const T *bll0,
+                              const T *blu1, const T *bll1, const uint8_t *lab, const InstC *insts, const Seg *segs) {
+    const InstC &ic = insts[segs[blockIdx.x].inst];
+    if (!ic.flag) return;
+    const T *blu = ic.sel ? blu1 : blu0;
+    const T *bll = ic.sel ? bll1 : bll0;
+    SEG_LOOP(i) {
         const uint8_t L = lab[i];
         T a = L ? alu[i] - blu[i] : (T)0;
         T b = (L == 2) ? all[i] - bll[i] : (T)0;
@@ -395,10 +451,10 @@ __global__ void k_certificate(T *olu, T *oll, const T *alu, const T *all, const 
 
 // [0] max over act of -q (clipped at 0), [1] max over act of |q|
 template <typename T>
-__global__ void k_ray_check(const T *q, const uint8_t *act, size_t n, double *partials) {
+__global__ void k_ray_check(const T *q, const uint8_t *act, const Seg *segs, double *partials) {
     __shared__ double m0[kThreads], m1[kThreads];
     double a0 = 0.0, a1 = 0.0;
-    GRID_LOOP(i, n) {
+    SEG_LOOP(i) {
         if (!act[i]) continue;
         const double qi = (double)q[i];
         a0 = fmax(a0, -qi);
@@ -420,137 +476,200 @@ __global__ void k_ray_check(const T *q, const uint8_t *act, size_t n, double *pa
     }
 }
 
-__global__ void __launch_bounds__(kThreads) finish_max(const double *__restrict__ partials, int nblocks,
-                                                        double *dst) {
-    __shared__ double sh[kThreads];
-    const double m0 = block_total<true>(partials, nblocks, 0, sh);
-    const double m1 = block_total<true>(partials, nblocks, 1, sh);
-    if (threadIdx.x == 0) { dst[0] = m0; dst[1] = m1; }
-}
-
-// power iteration: G^T-side combination of the rows of G x with D = K P^T y,
-// [0] sum_band (D - u), [1] sum_gel U (D - v U)
+// power iteration: the rows of G x with D = K P^T y and the scalars (eu, ev) combined for G^T:
+// z = (D - eu) on band, (D - ev U) + D on gel; [0] sum_band (D - eu), [1] sum_gel U (D - ev U)
 template <typename T>
-__global__ void k_pi_rows(const T *D, T *z, const uint8_t *lab, const T *hi, LPConst c, double u, double v, size_t n,
+__global__ void k_pi_rows(const T *D, T *z, const uint8_t *lab, const T *hi, const InstC *insts, const Seg *segs,
                           double *partials) {
     double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
-    GRID_LOOP(i, n) {
+    const InstC &ic = insts[segs[blockIdx.x].inst];
+    const LPConst c = ic.c;
+    SEG_LOOP(i) {
         const uint8_t L = lab[i];
         T zz = 0;
         if (L == 1) {
-            const double r = (double)D[i] - (c.u_free ? u : 0.0);
+            const double r = (double)D[i] - (c.u_free ? ic.eu : 0.0);
             zz = (T)r;
             acc[0] += r;
         } else if (L == 2) {
             const double U = (double)ld_or(hi, i, c.hi_s);
-            const double r = (double)D[i] - (c.v_free ? v * U : 0.0);
+            const double r = (double)D[i] - (c.v_free ? ic.ev * U : 0.0);
             zz = (T)(r + (double)D[i]);   // gel-up row minus gel-lo row (-D)
             acc[1] += U * r;
         }
         z[i] = zz;
     }
-    block_sums<kNS>(acc, partials);
+    block_sums(acc, partials);
 }
 
 // y <- act ? q : 0 ; [0] sum y^2
 template <typename T>
-__global__ void k_pi_mask(T *y, const T *q, const uint8_t *act, size_t n, double *partials) {
+__global__ void k_pi_mask(T *y, const T *q, const uint8_t *act, const Seg *segs, double *partials) {
     double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
-    GRID_LOOP(i, n) {
+    SEG_LOOP(i) {
         const T v = act[i] ? q[i] : (T)0;
         y[i] = v;
         acc[0] += (double)v * (double)v;
     }
-    block_sums<kNS>(acc, partials);
+    block_sums(acc, partials);
 }
 
 template <typename T>
-__global__ void k_scale(T *a, double s, size_t n) {
-    GRID_LOOP(i, n) a[i] = (T)((double)a[i] * s);
+__global__ void k_scale(T *a, const InstC *insts, const Seg *segs) {
+    const double s = insts[segs[blockIdx.x].inst].fac;
+    SEG_LOOP(i) a[i] = (T)((double)a[i] * s);
+}
+
+// dst <- src on all listed instances, or only on flagged ones
+template <typename T>
+__global__ void k_copy(T *dst, const T *src, const InstC *insts, const Seg *segs, int use_flag) {
+    if (use_flag && !insts[segs[blockIdx.x].inst].flag) return;
+    SEG_LOOP(i) dst[i] = src[i];
 }
 
 template <typename T>
-__global__ void k_copy(T *dst, const T *src, size_t n) {
-    GRID_LOOP(i, n) dst[i] = src[i];
+__global__ void k_fill(T *dst, long long n, T v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = v;
 }
 
 // weighted movement: [0] sum (a-b)^2 / w over w > 0
 template <typename T>
-__global__ void k_wdist(const T *a, const T *b, const T *w, size_t n, double *partials) {
+__global__ void k_wdist(const T *a, const T *b, const T *w, const Seg *segs, double *partials) {
     double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
-    GRID_LOOP(i, n) {
+    SEG_LOOP(i) {
         const double wi = (double)w[i];
         if (wi > 0) {
             const double d = (double)a[i] - (double)b[i];
             acc[0] += d * d / wi;
         }
     }
-    block_sums<kNS>(acc, partials);
+    block_sums(acc, partials);
 }
 
 // ================================================================= host side
-struct Workspace {
-    // sinogram-sized, internal layout
-    void *q, *Tj, *yt, *y0, *ylast, *y_int;
-    uint8_t *act_int;
-    // volume-sized
-    void *D, *Dt, *D0, *z, *tmp, *tmp2, *s_up, *s_lo, *lut, *llt, *luo, *llo, *snap_u, *snap_l, *lu0, *ll0,
-        *lul, *lll, *vol_t;
-    double *partials;
-    DevScal *scal;
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+static long long align_elems(long long v) { return (v + 63) & ~63LL; }
+
+// Byte offsets of everything in the caller's workspace.
+struct Layout {
+    int B = 0;
+    std::vector<long long> soff, voff;          // element offsets per instance
+    long long NS = 0, NV = 0;                   // packed sizes (elements)
+    int max_seg_s = 0, max_seg_v = 0, max_items_bp = 0, max_items_fp = 0;
+    size_t eb = 4;
+    bool lohi = false;                          // per-voxel bounds packed (some instance has arrays)
+    size_t vol_t_elems = 0;                     // internal-layout volume scratch (largest 3D instance)
+    // sinogram fields
+    size_t y, q, Tj, yt, y0, ylast, act;
+    // volume fields
+    size_t lu, ll, D, Dt, D0, z, tmp, tmp2, s_up, s_lo, lut, llt, luo, llo, snap_u, snap_l, lu0, ll0, lul, lll, lab,
+        lo, hi, vol_t;
+    // tables
+    size_t partials, insts, scal, segS, segV, firstS, cntS, firstV, cntV, list_act, list_tmp, sums, geo, items_bp,
+        items_fp;
+    size_t total = 0;
 };
 
-static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
-
-static size_t layout(const sipo_problem &pb, Workspace *ws, char *base) {
-    const sipo_plan p = pb.plan;
-    const size_t eb = p->elem_bytes();
-    const size_t sb = align_up(p->sino_elems() * eb), vb = align_up(p->vol_elems() * eb);
-    size_t off = 0;
-    auto take = [&](size_t bytes) -> void * {
-        void *r = base ? (void *)(base + off) : nullptr;
-        off += bytes;
-        return r;
-    };
-    Workspace w{};
-    w.q = take(sb); w.Tj = take(sb); w.yt = take(sb); w.y0 = take(sb); w.ylast = take(sb);
-    const bool t3 = p->fast3d();
-    w.y_int = t3 ? take(sb) : nullptr;
-    w.act_int = t3 ? (uint8_t *)take(align_up(p->sino_elems())) : nullptr;
-    w.vol_t = t3 ? take(vb) : nullptr;
-    w.D = take(vb); w.Dt = take(vb); w.D0 = take(vb); w.z = take(vb); w.tmp = take(vb); w.tmp2 = take(vb);
-    w.s_up = take(vb); w.s_lo = take(vb); w.lut = take(vb); w.llt = take(vb); w.luo = take(vb); w.llo = take(vb);
-    w.snap_u = take(vb); w.snap_l = take(vb); w.lu0 = take(vb); w.ll0 = take(vb); w.lul = take(vb); w.lll = take(vb);
-    w.partials = (double *)take(align_up(sizeof(double) * kRedBlocks * kNS));
-    w.scal = (DevScal *)take(align_up(sizeof(DevScal)));
-    if (ws) *ws = w;
-    return off;
+static bool use_batch2d(const sipo_problem *probs, int B) {
+    for (int i = 0; i < B; ++i) {
+        const sipo_plan p = probs[i].plan;
+        if (!(p->nz == 1 && p->p2d_ok && !p->has_psf)) return false;
+    }
+    return true;
 }
+
+static Layout make_layout(const sipo_problem *probs, int B) {
+    Layout L;
+    L.B = B;
+    L.eb = probs[0].plan->elem_bytes();
+    L.soff.resize(B);
+    L.voff.resize(B);
+    const bool b2d = use_batch2d(probs, B);
+    for (int i = 0; i < B; ++i) {
+        const sipo_plan p = probs[i].plan;
+        const long long ns = (long long)p->sino_elems(), nv = (long long)p->vol_elems();
+        L.soff[i] = L.NS;
+        L.voff[i] = L.NV;
+        L.NS += align_elems(ns);
+        L.NV += align_elems(nv);
+        L.max_seg_s += (int)((ns + kChunk - 1) / kChunk);
+        L.max_seg_v += (int)((nv + kChunk - 1) / kChunk);
+        if (probs[i].lo || probs[i].hi) L.lohi = true;
+        if (p->fast3d()) L.vol_t_elems = std::max(L.vol_t_elems, (size_t)nv);
+        if (b2d) {
+            const Geo2D g = plan_geo2d(p, 0, 0);
+            std::vector<int4> a, b;
+            append_items_bp2d(g, 0, a);
+            append_items_fp2d(g, 0, b);
+            L.max_items_bp += (int)a.size();
+            L.max_items_fp += (int)b.size();
+        }
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t r = off; off += align_up(bytes); return r; };
+    const size_t sb = (size_t)L.NS * L.eb, vb = (size_t)L.NV * L.eb;
+    L.y = take(sb); L.q = take(sb); L.Tj = take(sb); L.yt = take(sb); L.y0 = take(sb); L.ylast = take(sb);
+    L.act = take((size_t)L.NS);
+    L.lu = take(vb); L.ll = take(vb); L.D = take(vb); L.Dt = take(vb); L.D0 = take(vb); L.z = take(vb);
+    L.tmp = take(vb); L.tmp2 = take(vb); L.s_up = take(vb); L.s_lo = take(vb); L.lut = take(vb); L.llt = take(vb);
+    L.luo = take(vb); L.llo = take(vb); L.snap_u = take(vb); L.snap_l = take(vb); L.lu0 = take(vb); L.ll0 = take(vb);
+    L.lul = take(vb); L.lll = take(vb);
+    L.lab = take((size_t)L.NV);
+    L.lo = L.lohi ? take(vb) : 0;
+    L.hi = L.lohi ? take(vb) : 0;
+    L.vol_t = take(L.vol_t_elems * L.eb);
+    const int max_seg = std::max(std::max(L.max_seg_s, L.max_seg_v), 1);
+    L.partials = take(sizeof(double) * kNS * max_seg);
+    L.insts = take(sizeof(InstC) * B);
+    L.scal = take(sizeof(DevScal) * B);
+    L.segS = take(sizeof(Seg) * std::max(L.max_seg_s, 1));
+    L.segV = take(sizeof(Seg) * std::max(L.max_seg_v, 1));
+    L.firstS = take(sizeof(int) * B); L.cntS = take(sizeof(int) * B);
+    L.firstV = take(sizeof(int) * B); L.cntV = take(sizeof(int) * B);
+    L.list_act = take(sizeof(int) * B); L.list_tmp = take(sizeof(int) * B);
+    L.sums = take(sizeof(double) * kNS * B);
+    L.geo = take(sizeof(Geo2D) * B);
+    L.items_bp = take(sizeof(int4) * std::max(L.max_items_bp, 1));
+    L.items_fp = take(sizeof(int4) * std::max(L.max_items_fp, 1));
+    L.total = off;
+    return L;
+}
+
+struct Kkt {
+    double eps_p = 0, eps_d = 0, eps_gap = 0, p = 0, d = 0, r_p = 0, r_d = 0;
+    double rel() const { return std::max(eps_p, std::max(eps_d, eps_gap)); }
+    double merit() const { return std::sqrt(eps_p * eps_p + eps_d * eps_d + eps_gap * eps_gap); }
+};
 
 template <typename T>
 class Solver {
   public:
-    Solver(const sipo_problem &pb, const sipo_pdhg_options &o, const Workspace &w, hipStream_t s)
-        : pb_(pb), o_(o), w_(w), s_(s), p_(pb.plan) {
-        nv_ = p_->vol_elems();
-        ns_ = p_->sino_elems();
-        c_.u_free = pb.u_free;
-        c_.v_free = pb.v_free;
-        c_.w1 = pb.w1;
-        c_.w2 = pb.w2;
-        c_.h = pb.band_cap;
-        c_.lo_s = pb.lo_scalar;
-        c_.hi_s = pb.hi_scalar;
-        lab_ = pb.labels;
-        t3_ = p_->fast3d();
-        act_ = t3_ ? w.act_int : pb.act;
-        lo_ = (const T *)pb.lo;
-        hi_ = (const T *)pb.hi;
-        y_ = t3_ ? (T *)w.y_int : (T *)pb.y;
-        lu_ = (T *)pb.lam_up;
-        ll_ = (T *)pb.lam_lo;
-        gv_ = std::max(1, (int)std::min<size_t>((nv_ + kThreads * 4 - 1) / (kThreads * 4), kRedBlocks));
-        gs_ = std::max(1, (int)std::min<size_t>((ns_ + kThreads * 4 - 1) / (kThreads * 4), kRedBlocks));
+    Solver(const sipo_problem *probs, int B, const sipo_pdhg_options &o, char *ws, const Layout &L, hipStream_t s)
+        : probs_(probs), B_(B), o_(o), ws_(ws), L_(L), s_(s) {
+        b2d_ = use_batch2d(probs, B);
+        in_.resize(B);
+        hin_.resize(B);
+        hsc_.resize(B);
+        for (int i = 0; i < B; ++i) {
+            const sipo_problem &pb = probs[i];
+            Inst &I = in_[i];
+            I.p = pb.plan;
+            I.t3 = pb.plan->fast3d();
+            I.ns = (long long)pb.plan->sino_elems();
+            I.nv = (long long)pb.plan->vol_elems();
+            I.soff = L.soff[i];
+            I.voff = L.voff[i];
+            InstC &c = hin_[i];
+            std::memset(&c, 0, sizeof(c));
+            c.c.u_free = pb.u_free;
+            c.c.v_free = pb.v_free;
+            c.c.w1 = pb.w1;
+            c.c.w2 = pb.w2;
+            c.c.h = pb.band_cap;
+            c.c.lo_s = pb.lo_scalar;
+            c.c.hi_s = pb.hi_scalar;
+        }
     }
     ~Solver() {
         if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
@@ -560,61 +679,208 @@ class Solver {
     int run(sipo_pdhg_result *res);
 
   private:
-    const sipo_problem &pb_;
+    struct Inst {
+        sipo_plan p;
+        bool t3;
+        long long ns, nv, soff, voff;
+        double Tu = 0, Tv = 0, h_norm = 0, c_norm = 0;
+        double omega = 1.0, m_anchor = 0, m_prev = 1e300, last_u = 0, last_v = 0, tau = 0, sigma = 0;
+        int k_restart = 0, restarts = 0, iters = 0, status = SIPO_ITER_LIMIT;
+        bool done = false;
+        int cert = -1;      // certificate pair when infeasible
+        Kkt kc;
+    };
+    const sipo_problem *probs_;
+    int B_;
     sipo_pdhg_options o_;
-    Workspace w_;
+    char *ws_;
+    const Layout &L_;
     hipStream_t s_;
-    sipo_plan p_;
-    size_t nv_, ns_;
-    int gv_, gs_;
-    LPConst c_;
-    const uint8_t *lab_, *act_;
-    bool t3_ = false;     // sinograms held in the internal [view][bin][z] layout
-    const T *lo_, *hi_;
-    T *y_, *lu_, *ll_;
-    double h_norm_ = 0, c_norm_ = 0;
-    double Tu_ = 0, Tv_ = 0;
-    DevScal hs_{};
+    bool b2d_ = false;
+    int nc_max_ = 3;
+    std::vector<Inst> in_;
+    std::vector<InstC> hin_;
+    std::vector<DevScal> hsc_;
+    std::vector<int> active_;               // instances the iteration kernels run on
+    int n_seg_s_ = 0, n_seg_v_ = 0, n_items_bp_ = 0, n_items_fp_ = 0;
+    std::vector<double> hsums_;             // [B][kNS]
     hipGraphExec_t graph_exec_ = nullptr;
     int graph_len_ = 0;
 
-    template <typename U>
-    void copy(U *dst, const U *src, size_t n, int grid) {
-        hipLaunchKernelGGL((k_copy<U>), dim3(grid), dim3(kThreads), 0, s_, dst, src, n);
+    // ---- typed views of the workspace
+    T *F(size_t off) const { return (T *)(ws_ + off); }
+    uint8_t *U8(size_t off) const { return (uint8_t *)(ws_ + off); }
+    template <typename X>
+    X *P(size_t off) const { return (X *)(ws_ + off); }
+    const T *lo_() const { return L_.lohi ? F(L_.lo) : nullptr; }
+    const T *hi_() const { return L_.lohi ? F(L_.hi) : nullptr; }
+    const Seg *segS() const { return P<Seg>(L_.segS); }
+    const Seg *segV() const { return P<Seg>(L_.segV); }
+    double *partials() const { return P<double>(L_.partials); }
+    const InstC *insts() const { return P<InstC>(L_.insts); }
+    DevScal *scal() const { return P<DevScal>(L_.scal); }
+
+    int upload(size_t off, const void *src, size_t bytes) {
+        if (!bytes) return SIPO_OK;
+        SIPO_HIP(hipMemcpyAsync(ws_ + off, src, bytes, hipMemcpyHostToDevice, s_));
+        SIPO_HIP(hipStreamSynchronize(s_));   // host staging may change right after
+        return SIPO_OK;
     }
-    T *V(void *p) { return (T *)p; }
-    // operators on the solver's layouts: sinograms as held internally, volumes [z][y][x]
-    int dose(const T *y, T *out) {   // out = K P^T y  (uses tmp when K != I)
-        if (!p_->has_psf) {
-            int rc = launch_backproject_t(p_, y, out, 0, s_);
+    int put_insts() { return upload(L_.insts, hin_.data(), sizeof(InstC) * B_); }
+    int put_scal() { return upload(L_.scal, hsc_.data(), sizeof(DevScal) * B_); }
+    int get_scal() {
+        SIPO_HIP(hipMemcpyAsync(hsc_.data(), scal(), sizeof(DevScal) * B_, hipMemcpyDeviceToHost, s_));
+        SIPO_HIP(hipStreamSynchronize(s_));
+        return SIPO_OK;
+    }
+    void set_flags(const std::vector<int> &on) {
+        for (int i = 0; i < B_; ++i) hin_[i].flag = 0;
+        for (int i : on) hin_[i].flag = 1;
+    }
+
+    // Segment tables, per-instance workgroup ranges and work items for the instances in `list`.
+    int set_active(const std::vector<int> &list) {
+        active_ = list;
+        if (graph_exec_) {
+            SIPO_HIP(hipGraphExecDestroy(graph_exec_));
+            graph_exec_ = nullptr;
+        }
+        std::vector<Seg> ss, sv;
+        std::vector<int> fs(B_, 0), cs(B_, 0), fv(B_, 0), cv(B_, 0);
+        std::vector<int4> ib, ifp;
+        std::vector<Geo2D> geo(B_);
+        nc_max_ = 3;
+        for (int i : list) {
+            const Inst &I = in_[i];
+            fs[i] = (int)ss.size();
+            for (long long b = 0; b < I.ns; b += kChunk) ss.push_back({i, 0, I.soff + b, I.soff + std::min(I.ns, b + kChunk)});
+            cs[i] = (int)ss.size() - fs[i];
+            fv[i] = (int)sv.size();
+            for (long long b = 0; b < I.nv; b += kChunk) sv.push_back({i, 0, I.voff + b, I.voff + std::min(I.nv, b + kChunk)});
+            cv[i] = (int)sv.size() - fv[i];
+            if (b2d_) {
+                geo[i] = plan_geo2d(I.p, I.soff, I.voff);
+                append_items_bp2d(geo[i], i, ib);
+                append_items_fp2d(geo[i], i, ifp);
+                nc_max_ = std::max(nc_max_, I.p->p3d_nc);
+            }
+        }
+        n_seg_s_ = (int)ss.size();
+        n_seg_v_ = (int)sv.size();
+        n_items_bp_ = (int)ib.size();
+        n_items_fp_ = (int)ifp.size();
+        int rc = upload(L_.segS, ss.data(), sizeof(Seg) * ss.size());
+        if (!rc) rc = upload(L_.segV, sv.data(), sizeof(Seg) * sv.size());
+        if (!rc) rc = upload(L_.firstS, fs.data(), sizeof(int) * B_);
+        if (!rc) rc = upload(L_.cntS, cs.data(), sizeof(int) * B_);
+        if (!rc) rc = upload(L_.firstV, fv.data(), sizeof(int) * B_);
+        if (!rc) rc = upload(L_.cntV, cv.data(), sizeof(int) * B_);
+        if (!rc) rc = upload(L_.list_act, list.data(), sizeof(int) * list.size());
+        if (!rc && b2d_) {
+            rc = upload(L_.geo, geo.data(), sizeof(Geo2D) * B_);
+            if (!rc) rc = upload(L_.items_bp, ib.data(), sizeof(int4) * ib.size());
+            if (!rc) rc = upload(L_.items_fp, ifp.data(), sizeof(int4) * ifp.size());
+        }
+        return rc;
+    }
+
+    // Per-instance totals of the last reduction launched over the sinogram (S) or volume (V)
+    // tables, for the instances in `list`; results in hsums_[i * kNS + k].
+    int finish(bool vol, const std::vector<int> &list, int ns, bool max = false) {
+        if (list.empty()) return SIPO_OK;
+        int rc = upload(L_.list_tmp, list.data(), sizeof(int) * list.size());
+        if (rc) return rc;
+        const int *first = P<int>(vol ? L_.firstV : L_.firstS), *count = P<int>(vol ? L_.cntV : L_.cntS);
+        if (max)
+            hipLaunchKernelGGL(k_finish<true>, dim3(list.size()), dim3(kThreads), 0, s_, partials(), first, count,
+                               P<int>(L_.list_tmp), ns, P<double>(L_.sums));
+        else
+            hipLaunchKernelGGL(k_finish<false>, dim3(list.size()), dim3(kThreads), 0, s_, partials(), first, count,
+                               P<int>(L_.list_tmp), ns, P<double>(L_.sums));
+        SIPO_HIP(hipMemcpyAsync(hsums_.data(), P<double>(L_.sums), sizeof(double) * kNS * B_, hipMemcpyDeviceToHost,
+                                s_));
+        SIPO_HIP(hipStreamSynchronize(s_));
+        return SIPO_OK;
+    }
+    double sum(int i, int k) const { return hsums_[(size_t)i * kNS + k]; }
+
+    // ---- streaming launches over the active tables
+    dim3 gS() const { return dim3(std::max(n_seg_s_, 1)); }
+    dim3 gV() const { return dim3(std::max(n_seg_v_, 1)); }
+    void copyV(size_t dst, size_t src, bool flagged) {
+        if (n_seg_v_) hipLaunchKernelGGL((k_copy<T>), gV(), dim3(kThreads), 0, s_, F(dst), (const T *)F(src), insts(),
+                                         segV(), flagged ? 1 : 0);
+    }
+    void copyS(size_t dst, size_t src, bool flagged) {
+        if (n_seg_s_) hipLaunchKernelGGL((k_copy<T>), gS(), dim3(kThreads), 0, s_, F(dst), (const T *)F(src), insts(),
+                                         segS(), flagged ? 1 : 0);
+    }
+    int lambda_z(size_t lu, size_t ll, size_t z, bool flagged) {
+        if (!n_seg_v_) return SIPO_OK;
+        hipLaunchKernelGGL((k_lambda_z<T>), gV(), dim3(kThreads), 0, s_, F(lu), F(ll), F(z), U8(L_.lab), hi_(),
+                           insts(), segV(), flagged ? 1 : 0, partials());
+        return SIPO_OK;
+    }
+
+    // ---- operators on the solver's layouts (sinograms as held internally, volumes [z][y][x])
+    int dose(size_t yf, size_t outf) {   // out = K P^T y on the active instances
+        if (b2d_) {
+            int rc = launch_bp2d(I_dtype(), P<Geo2D>(L_.geo), P<int4>(L_.items_bp), n_items_bp_, F(yf), F(outf), 0, s_);
             return rc ? rc : mark(SIPO_PHASE_BACKPROJECT);
         }
-        int rc = launch_backproject_t(p_, y, w_.tmp, 0, s_);
-        if (!rc) rc = mark(SIPO_PHASE_BACKPROJECT);
-        if (!rc) rc = launch_blur(p_, w_.tmp, out, s_);
-        return rc ? rc : mark(SIPO_PHASE_BLUR);
-    }
-    int adjoint(const T *z, T *out) {   // out = P K z
-        const void *src = z;
-        if (p_->has_psf) {
-            int rc = launch_blur(p_, z, w_.tmp, s_);
+        for (int i : active_) {
+            const Inst &I = in_[i];
+            const T *y = F(yf) + I.soff;
+            T *out = F(outf) + I.voff;
+            if (!I.p->has_psf) {
+                int rc = launch_backproject_t(I.p, y, out, 0, s_);
+                if (!rc) rc = mark(SIPO_PHASE_BACKPROJECT);
+                if (rc) return rc;
+                continue;
+            }
+            T *tmp = F(L_.tmp) + I.voff;
+            int rc = launch_backproject_t(I.p, y, tmp, 0, s_);
+            if (!rc) rc = mark(SIPO_PHASE_BACKPROJECT);
+            if (!rc) rc = launch_blur(I.p, tmp, out, s_);
             if (!rc) rc = mark(SIPO_PHASE_BLUR);
             if (rc) return rc;
-            src = w_.tmp;
         }
-        if (!t3_) {
-            int rc = launch_project_t(p_, src, out, s_);
+        return SIPO_OK;
+    }
+    int adjoint(size_t zf, size_t outf) {   // out = P K z on the active instances
+        if (b2d_) {
+            int rc = launch_fp2d(I_dtype(), nc_max_, P<Geo2D>(L_.geo), P<int4>(L_.items_fp), n_items_fp_, F(zf),
+                                 F(outf), 0, s_);
             return rc ? rc : mark(SIPO_PHASE_PROJECT);
         }
-        int rc = launch_vol_to_t(p_, src, w_.vol_t, s_);
-        if (!rc) rc = mark(SIPO_PHASE_TRANSPOSE);
-        if (!rc) rc = launch_project_t(p_, w_.vol_t, out, s_);
-        return rc ? rc : mark(SIPO_PHASE_PROJECT);
+        for (int i : active_) {
+            const Inst &I = in_[i];
+            const T *src = F(zf) + I.voff;
+            T *out = F(outf) + I.soff;
+            int rc = SIPO_OK;
+            if (I.p->has_psf) {
+                T *tmp = F(L_.tmp) + I.voff;
+                rc = launch_blur(I.p, src, tmp, s_);
+                if (!rc) rc = mark(SIPO_PHASE_BLUR);
+                src = tmp;
+            }
+            if (!rc && I.t3) {
+                rc = launch_vol_to_t(I.p, src, F(L_.vol_t), s_);
+                if (!rc) rc = mark(SIPO_PHASE_TRANSPOSE);
+                src = F(L_.vol_t);
+            }
+            if (!rc) rc = launch_project_t(I.p, src, out, s_);
+            if (!rc) rc = mark(SIPO_PHASE_PROJECT);
+            if (rc) return rc;
+        }
+        return SIPO_OK;
     }
+    sipo_dtype I_dtype() const { return sizeof(T) == 8 ? SIPO_F64 : SIPO_F32; }
+
     // ---- profile mode: a timeline of events between consecutive iteration launches
-    bool prof_on_ = false;                // inside an iteration of a profiled solve
+    bool prof_on_ = false;
     std::vector<hipEvent_t> ev_;
-    std::vector<int> ev_phase_;           // phase of the launch that ends at ev_[i]
+    std::vector<int> ev_phase_;
     size_t ev_used_ = 0;
     double phase_ms_[SIPO_NUM_PHASES] = {};
     int phase_n_[SIPO_NUM_PHASES] = {};
@@ -636,7 +902,7 @@ class Solver {
         ++ev_used_;
         return SIPO_OK;
     }
-    int flush_profile() {   // fold the recorded intervals into the phase totals
+    int flush_profile() {
         if (ev_used_ == 0) return SIPO_OK;
         SIPO_HIP(hipEventSynchronize(ev_[ev_used_ - 1]));
         for (size_t i = 1; i < ev_used_; ++i) {
@@ -650,217 +916,305 @@ class Solver {
         ev_used_ = 0;
         return SIPO_OK;
     }
-    int sums(int nblocks, int ns, double *host) {
-        hipLaunchKernelGGL(finish_sums, dim3(1), dim3(kThreads), 0, s_, w_.partials, nblocks, w_.scal->sums, ns);
-        SIPO_HIP(hipMemcpyAsync(host, w_.scal->sums, sizeof(double) * ns, hipMemcpyDeviceToHost, s_));
-        SIPO_HIP(hipStreamSynchronize(s_));
-        return SIPO_OK;
-    }
-    int get_scal() {
-        SIPO_HIP(hipMemcpyAsync(&hs_, w_.scal, sizeof(DevScal), hipMemcpyDeviceToHost, s_));
-        SIPO_HIP(hipStreamSynchronize(s_));
-        return SIPO_OK;
-    }
-    int put_scal() {
-        SIPO_HIP(hipMemcpyAsync(w_.scal, &hs_, sizeof(DevScal), hipMemcpyHostToDevice, s_));
-        return SIPO_OK;
-    }
-    int lambda_z(T *lu, T *ll, T *z, double *sum_l1, double *sum_ul2) {
-        hipLaunchKernelGGL((k_lambda_z<T>), dim3(gv_), dim3(kThreads), 0, s_, lu, ll, z, lab_, hi_, c_, nv_,
-                           w_.partials);
-        double h[2];
-        int rc = sums(gv_, 2, h);
-        if (rc) return rc;
-        *sum_l1 = h[0];
-        *sum_ul2 = h[1];
-        return SIPO_OK;
-    }
-    struct Kkt {
-        double eps_p, eps_d, eps_gap, p, d, r_p, r_d;
-        double rel() const { return std::max(eps_p, std::max(eps_d, eps_gap)); }
-        double merit() const { return std::sqrt(eps_p * eps_p + eps_d * eps_d + eps_gap * eps_gap); }
-    };
-    int kkt(const T *y, const T *D, double u, double v, const T *lu, const T *ll, const T *z, Kkt *out);
+
+    int pack();
+    int unpack();
     int setup_common();
-    int power_norm(int iters, double *nrm);
-    int farkas(const T *alu, const T *all, const T *blu, const T *bll, double tol, bool *ok);
+    int power_norm(int iters, std::vector<double> &nrm);
+    int kkt(size_t y, size_t D, bool at_t, size_t lu, size_t ll, size_t z, const std::vector<int> &list);
+    int farkas(size_t alu, size_t all, size_t blu, size_t bll, double tol, const std::vector<int> &list,
+               std::vector<char> &ok);
     int iteration(bool check);
     int run_block(int nblk);
 };
 
-// KKT at (y, D, u, v, lambda); z must hold lambda_up - lambda_lo.  Uses q as scratch.
+// Copy the callers' arrays into the packed workspace (internal layout for 3D instances).
 template <typename T>
-int Solver<T>::kkt(const T *y, const T *D, double u, double v, const T *lu, const T *ll, const T *z, Kkt *out) {
-    hipLaunchKernelGGL((k_kkt_vox<T>), dim3(gv_), dim3(kThreads), 0, s_, D, lu, ll, lab_, lo_, hi_, c_, u, v, nv_,
-                       w_.partials);
-    double hv[4];
-    int rc = sums(gv_, 4, hv);
+int Solver<T>::pack() {
+    for (int i = 0; i < B_; ++i) {
+        const sipo_problem &pb = probs_[i];
+        const Inst &I = in_[i];
+        const size_t vb = (size_t)I.nv * sizeof(T), sb = (size_t)I.ns * sizeof(T);
+        if (I.t3) {
+            int rc = launch_sino_to_t(I.p, pb.y, F(L_.y) + I.soff, s_);
+            if (!rc) rc = launch_mask_to_t(I.p, pb.act, U8(L_.act) + I.soff, s_);
+            if (rc) return rc;
+        } else {
+            SIPO_HIP(hipMemcpyAsync(F(L_.y) + I.soff, pb.y, sb, hipMemcpyDeviceToDevice, s_));
+            SIPO_HIP(hipMemcpyAsync(U8(L_.act) + I.soff, pb.act, (size_t)I.ns, hipMemcpyDeviceToDevice, s_));
+        }
+        SIPO_HIP(hipMemcpyAsync(F(L_.lu) + I.voff, pb.lam_up, vb, hipMemcpyDeviceToDevice, s_));
+        SIPO_HIP(hipMemcpyAsync(F(L_.ll) + I.voff, pb.lam_lo, vb, hipMemcpyDeviceToDevice, s_));
+        SIPO_HIP(hipMemcpyAsync(U8(L_.lab) + I.voff, pb.labels, (size_t)I.nv, hipMemcpyDeviceToDevice, s_));
+        if (L_.lohi) {
+            const int grid = (int)std::min<long long>((I.nv + 255) / 256, 4096);
+            if (pb.lo) SIPO_HIP(hipMemcpyAsync(F(L_.lo) + I.voff, pb.lo, vb, hipMemcpyDeviceToDevice, s_));
+            else hipLaunchKernelGGL((k_fill<T>), dim3(grid), dim3(256), 0, s_, F(L_.lo) + I.voff, I.nv, (T)pb.lo_scalar);
+            if (pb.hi) SIPO_HIP(hipMemcpyAsync(F(L_.hi) + I.voff, pb.hi, vb, hipMemcpyDeviceToDevice, s_));
+            else hipLaunchKernelGGL((k_fill<T>), dim3(grid), dim3(256), 0, s_, F(L_.hi) + I.voff, I.nv, (T)pb.hi_scalar);
+        }
+    }
+    SIPO_LAUNCHED("pdhg pack");
+    return SIPO_OK;
+}
+
+// Returned point and dose back to the callers' arrays.
+template <typename T>
+int Solver<T>::unpack() {
+    for (int i = 0; i < B_; ++i) {
+        const sipo_problem &pb = probs_[i];
+        const Inst &I = in_[i];
+        const size_t vb = (size_t)I.nv * sizeof(T), sb = (size_t)I.ns * sizeof(T);
+        if (I.t3) {
+            int rc = launch_sino_from_t(I.p, F(L_.y) + I.soff, pb.y, 0, s_);
+            if (rc) return rc;
+        } else {
+            SIPO_HIP(hipMemcpyAsync(pb.y, F(L_.y) + I.soff, sb, hipMemcpyDeviceToDevice, s_));
+        }
+        SIPO_HIP(hipMemcpyAsync(pb.lam_up, F(L_.lu) + I.voff, vb, hipMemcpyDeviceToDevice, s_));
+        SIPO_HIP(hipMemcpyAsync(pb.lam_lo, F(L_.ll) + I.voff, vb, hipMemcpyDeviceToDevice, s_));
+        if (pb.dose_out) SIPO_HIP(hipMemcpyAsync(pb.dose_out, F(L_.D) + I.voff, vb, hipMemcpyDeviceToDevice, s_));
+    }
+    SIPO_LAUNCHED("pdhg unpack");
+    return SIPO_OK;
+}
+
+// KKT of every instance in `list` at (y, D, lambda) with z = lambda_up - lambda_lo in field z;
+// the scalars are t's (at_t) or z's.  Uses q as scratch; fills in_[i].kc.
+template <typename T>
+int Solver<T>::kkt(size_t yf, size_t Df, bool at_t, size_t luf, size_t llf, size_t zf, const std::vector<int> &list) {
+    for (int i : list) {
+        hin_[i].eu = at_t ? hsc_[i].ut_done : hsc_[i].u;
+        hin_[i].ev = at_t ? hsc_[i].vt_done : hsc_[i].v;
+    }
+    int rc = put_insts();
     if (rc) return rc;
-    rc = adjoint(z, V(w_.q));
+    hipLaunchKernelGGL((k_kkt_vox<T>), gV(), dim3(kThreads), 0, s_, (const T *)F(Df), (const T *)F(luf),
+                       (const T *)F(llf), (const uint8_t *)U8(L_.lab), lo_(), hi_(), insts(), segV(), partials());
+    rc = finish(true, list, 4);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_kkt_ray<T>), dim3(gs_), dim3(kThreads), 0, s_, (const T *)w_.q, y, act_, ns_, w_.partials);
-    double hr[2];
-    rc = sums(gs_, 2, hr);
+    std::vector<double> hv((size_t)B_ * 4);
+    for (int i : list)
+        for (int k = 0; k < 4; ++k) hv[(size_t)i * 4 + k] = sum(i, k);
+    rc = adjoint(zf, L_.q);
     if (rc) return rc;
-    double rp2 = hv[0] + hr[1];
-    if (c_.u_free && u < 0) rp2 += u * u;
-    if (c_.v_free && v < 0) rp2 += v * v;
-    double rd2 = hr[0];
-    if (c_.u_free) { const double r = c_.w1 - hv[2]; if (r < 0) rd2 += r * r; }
-    if (c_.v_free) { const double r = c_.w2 - hv[3]; if (r < 0) rd2 += r * r; }
-    const double pobj = (c_.u_free ? c_.w1 * u : 0.0) + (c_.v_free ? c_.w2 * v : 0.0);
-    double dobj = hv[1];
-    if (!c_.u_free) dobj -= c_.h * hv[2];
-    if (!c_.v_free) dobj -= hv[3];
-    out->r_p = std::sqrt(rp2);
-    out->r_d = std::sqrt(rd2);
-    out->eps_p = out->r_p / (1.0 + h_norm_);
-    out->eps_d = out->r_d / (1.0 + c_norm_);
-    out->eps_gap = std::fabs(pobj - dobj) / (1.0 + std::fabs(pobj) + std::fabs(dobj));
-    out->p = pobj;
-    out->d = dobj;
+    hipLaunchKernelGGL((k_kkt_ray<T>), gS(), dim3(kThreads), 0, s_, (const T *)F(L_.q), (const T *)F(yf),
+                       (const uint8_t *)U8(L_.act), segS(), partials());
+    rc = finish(false, list, 2);
+    if (rc) return rc;
+    for (int i : list) {
+        Inst &I = in_[i];
+        const LPConst &c = hin_[i].c;
+        const double u = hin_[i].eu, v = hin_[i].ev;
+        const double *h4 = &hv[(size_t)i * 4];
+        double rp2 = h4[0] + sum(i, 1);
+        if (c.u_free && u < 0) rp2 += u * u;
+        if (c.v_free && v < 0) rp2 += v * v;
+        double rd2 = sum(i, 0);
+        if (c.u_free) { const double r = c.w1 - h4[2]; if (r < 0) rd2 += r * r; }
+        if (c.v_free) { const double r = c.w2 - h4[3]; if (r < 0) rd2 += r * r; }
+        const double pobj = (c.u_free ? c.w1 * u : 0.0) + (c.v_free ? c.w2 * v : 0.0);
+        double dobj = h4[1];
+        if (!c.u_free) dobj -= c.h * h4[2];
+        if (!c.v_free) dobj -= h4[3];
+        Kkt &k = I.kc;
+        k.r_p = std::sqrt(rp2);
+        k.r_d = std::sqrt(rd2);
+        k.eps_p = k.r_p / (1.0 + I.h_norm);
+        k.eps_d = k.r_d / (1.0 + I.c_norm);
+        k.eps_gap = std::fabs(pobj - dobj) / (1.0 + std::fabs(pobj) + std::fabs(dobj));
+        k.p = pobj;
+        k.d = dobj;
+    }
     return SIPO_OK;
 }
 
 template <typename T>
 int Solver<T>::setup_common() {
-    if (t3_) {
-        int rc = launch_sino_to_t(p_, pb_.y, y_, s_);
-        if (!rc) rc = launch_mask_to_t(p_, pb_.act, (uint8_t *)act_, s_);
-        if (rc) return rc;
-    }
-    hipLaunchKernelGGL((k_project_y<T>), dim3(gs_), dim3(kThreads), 0, s_, y_, act_, ns_);
-    double l1, ul2;
-    int rc = lambda_z(lu_, ll_, V(w_.z), &l1, &ul2);
+    int rc = pack();
     if (rc) return rc;
+    std::vector<int> all(B_);
+    for (int i = 0; i < B_; ++i) all[i] = i;
+    rc = set_active(all);
+    if (!rc) rc = put_insts();
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_project_y<T>), gS(), dim3(kThreads), 0, s_, F(L_.y), (const uint8_t *)U8(L_.act), segS());
+    rc = lambda_z(L_.lu, L_.ll, L_.z, false);
+    if (!rc) rc = finish(true, all, 2);
+    if (rc) return rc;
+    std::vector<double> l1(B_), ul2(B_);
+    for (int i = 0; i < B_; ++i) { l1[i] = sum(i, 0); ul2[i] = sum(i, 1); }
     // R = K P^T 1_act -> dual scalings; region sizes, ||h||
-    hipLaunchKernelGGL((k_colweight<T>), dim3(gv_), dim3(kThreads), 0, s_, V(w_.tmp2), lab_, nv_);
-    hipLaunchKernelGGL((k_act_to_float<T>), dim3(gs_), dim3(kThreads), 0, s_, V(w_.q), act_, ns_);
-    rc = dose((const T *)w_.q, V(w_.Dt));
+    hipLaunchKernelGGL((k_colweight<T>), gV(), dim3(kThreads), 0, s_, F(L_.tmp2), (const uint8_t *)U8(L_.lab), segV());
+    hipLaunchKernelGGL((k_act_to_float<T>), gS(), dim3(kThreads), 0, s_, F(L_.q), (const uint8_t *)U8(L_.act), segS());
+    rc = dose(L_.q, L_.Dt);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_row_scaling<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)w_.Dt, V(w_.s_up),
-                       V(w_.s_lo), lab_, lo_, hi_, c_, nv_, w_.partials);
-    double hs[4];
-    rc = sums(gv_, 4, hs);
+    hipLaunchKernelGGL((k_row_scaling<T>), gV(), dim3(kThreads), 0, s_, (const T *)F(L_.Dt), F(L_.s_up), F(L_.s_lo),
+                       (const uint8_t *)U8(L_.lab), lo_(), hi_(), insts(), segV(), partials());
+    rc = finish(true, all, 4);
     if (rc) return rc;
-    Tu_ = (c_.u_free && hs[0] > 0) ? 1.0 / hs[0] : 0.0;
-    Tv_ = (c_.v_free && hs[1] > 0) ? 1.0 / hs[1] : 0.0;
-    h_norm_ = std::sqrt(hs[2]);
-    c_norm_ = std::hypot(c_.u_free ? c_.w1 : 0.0, c_.v_free ? c_.w2 : 0.0);
-    // primal scaling T_j = 1 / (P K w)_j
-    rc = adjoint((const T *)w_.tmp2, V(w_.Tj));
-    if (rc) return rc;
-    hipLaunchKernelGGL((k_inv_colsum<T>), dim3(gs_), dim3(kThreads), 0, s_, V(w_.Tj), act_, ns_);
-    // D = K P^T y
-    rc = dose(y_, V(w_.D));
-    if (rc) return rc;
-    std::memset(&hs_, 0, sizeof(hs_));
-    hs_.u = c_.u_free ? std::max(0.0, pb_.u0) : c_.h;
-    hs_.v = c_.v_free ? std::max(0.0, pb_.v0) : 1.0;
-    hs_.sums[0] = l1;
-    hs_.sums[1] = ul2;
-    return SIPO_OK;
-}
-
-template <typename T>
-int Solver<T>::power_norm(int iters, double *nrm) {
-    T *y = V(w_.y0);   // scratch sinogram
-    hipLaunchKernelGGL((k_act_to_float<T>), dim3(gs_), dim3(kThreads), 0, s_, y, act_, ns_);
-    hipLaunchKernelGGL((k_pi_mask<T>), dim3(gs_), dim3(kThreads), 0, s_, y, (const T *)y, act_, ns_, w_.partials);
-    double yy;
-    int rc = sums(gs_, 1, &yy);
-    if (rc) return rc;
-    double u = c_.u_free ? 1.0 : 0.0, v = c_.v_free ? 1.0 : 0.0;
-    double nr = std::sqrt(yy + u * u + v * v);
-    if (nr == 0) { *nrm = 0; return SIPO_OK; }
-    hipLaunchKernelGGL((k_scale<T>), dim3(gs_), dim3(kThreads), 0, s_, y, 1.0 / nr, ns_);
-    u /= nr;
-    v /= nr;
-    double lam = 0.0;
-    for (int it = 0; it < iters; ++it) {
-        rc = dose(y, V(w_.Dt));
-        if (rc) return rc;
-        hipLaunchKernelGGL((k_pi_rows<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)w_.Dt, V(w_.tmp2), lab_, hi_,
-                           c_, u, v, nv_, w_.partials);
-        double rs[2];
-        rc = sums(gv_, 2, rs);
-        if (rc) return rc;
-        rc = adjoint((const T *)w_.tmp2, V(w_.q));
-        if (rc) return rc;
-        hipLaunchKernelGGL((k_pi_mask<T>), dim3(gs_), dim3(kThreads), 0, s_, y, (const T *)w_.q, act_, ns_,
-                           w_.partials);
-        rc = sums(gs_, 1, &yy);
-        if (rc) return rc;
-        const double gu = c_.u_free ? -rs[0] : 0.0, gv = c_.v_free ? -rs[1] : 0.0;
-        lam = std::sqrt(yy + gu * gu + gv * gv);
-        if (lam == 0) break;
-        hipLaunchKernelGGL((k_scale<T>), dim3(gs_), dim3(kThreads), 0, s_, y, 1.0 / lam, ns_);
-        u = gu / lam;
-        v = gv / lam;
+    for (int i = 0; i < B_; ++i) {
+        Inst &I = in_[i];
+        const LPConst &c = hin_[i].c;
+        I.Tu = (c.u_free && sum(i, 0) > 0) ? 1.0 / sum(i, 0) : 0.0;
+        I.Tv = (c.v_free && sum(i, 1) > 0) ? 1.0 / sum(i, 1) : 0.0;
+        I.h_norm = std::sqrt(sum(i, 2));
+        I.c_norm = std::hypot(c.u_free ? c.w1 : 0.0, c.v_free ? c.w2 : 0.0);
     }
-    *nrm = std::sqrt(lam);
+    // primal scaling T_j = 1 / (P K w)_j
+    rc = adjoint(L_.tmp2, L_.Tj);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_inv_colsum<T>), gS(), dim3(kThreads), 0, s_, F(L_.Tj), (const uint8_t *)U8(L_.act), segS());
+    rc = dose(L_.y, L_.D);
+    if (rc) return rc;
+    for (int i = 0; i < B_; ++i) {
+        DevScal &h = hsc_[i];
+        std::memset(&h, 0, sizeof(h));
+        const LPConst &c = hin_[i].c;
+        h.u = c.u_free ? std::max(0.0, probs_[i].u0) : c.h;
+        h.v = c.v_free ? std::max(0.0, probs_[i].v0) : 1.0;
+        h.init_l1 = l1[i];
+        h.init_Ul2 = ul2[i];
+    }
     return SIPO_OK;
 }
 
-// Farkas test of the candidate d = max(a - b, 0): scaled to dual objective 1, every
-// reduced-cost violation must be <= tol.  Uses tmp2 (z_d) and q.
+// FP64 power iteration for ||G|| of every instance at once (plain mode).  Uses y0 as scratch.
 template <typename T>
-int Solver<T>::farkas(const T *alu, const T *all, const T *blu, const T *bll, double tol, bool *ok) {
-    *ok = false;
-    hipLaunchKernelGGL((k_ray_candidate<T>), dim3(gv_), dim3(kThreads), 0, s_, alu, all, blu, bll, V(w_.tmp2), lab_,
-                       lo_, hi_, c_, nv_, w_.partials);
-    double r[4];
-    int rc = sums(gv_, 4, r);
+int Solver<T>::power_norm(int iters, std::vector<double> &nrm) {
+    std::vector<int> all(B_);
+    for (int i = 0; i < B_; ++i) all[i] = i;
+    nrm.assign(B_, 0.0);
+    const size_t y = L_.y0;
+    hipLaunchKernelGGL((k_act_to_float<T>), gS(), dim3(kThreads), 0, s_, F(y), (const uint8_t *)U8(L_.act), segS());
+    hipLaunchKernelGGL((k_pi_mask<T>), gS(), dim3(kThreads), 0, s_, F(y), (const T *)F(y), (const uint8_t *)U8(L_.act),
+                       segS(), partials());
+    int rc = finish(false, all, 1);
     if (rc) return rc;
-    double ray_obj = r[0];
-    if (!c_.u_free) ray_obj -= c_.h * r[1];
-    if (!c_.v_free) ray_obj -= r[2];
-    if (!(ray_obj > 0) || !(r[3] > 0)) return SIPO_OK;
-    const double worst_u = c_.u_free ? r[1] / ray_obj : 0.0;
-    const double worst_v = c_.v_free ? r[2] / ray_obj : 0.0;
-    if (std::max(worst_u, worst_v) > tol) return SIPO_OK;
-    rc = adjoint((const T *)w_.tmp2, V(w_.q));
+    std::vector<double> u(B_), v(B_), lam(B_, 0.0);
+    for (int i = 0; i < B_; ++i) {
+        const LPConst &c = hin_[i].c;
+        u[i] = c.u_free ? 1.0 : 0.0;
+        v[i] = c.v_free ? 1.0 : 0.0;
+        const double nr = std::sqrt(sum(i, 0) + u[i] * u[i] + v[i] * v[i]);
+        if (!(nr > 0)) return fail(SIPO_E_INVALID, "instance %d: operator norm is zero (no active rays or regions)", i);
+        hin_[i].fac = 1.0 / nr;
+        u[i] /= nr;
+        v[i] /= nr;
+    }
+    rc = put_insts();
     if (rc) return rc;
-    hipLaunchKernelGGL((k_ray_check<T>), dim3(gs_), dim3(kThreads), 0, s_, (const T *)w_.q, act_, ns_, w_.partials);
-    hipLaunchKernelGGL(finish_max, dim3(1), dim3(kThreads), 0, s_, w_.partials, gs_, w_.scal->sums);
-    double m[2];
-    SIPO_HIP(hipMemcpyAsync(m, w_.scal->sums, sizeof(m), hipMemcpyDeviceToHost, s_));
-    SIPO_HIP(hipStreamSynchronize(s_));
-    *ok = m[0] / ray_obj <= tol;
+    hipLaunchKernelGGL((k_scale<T>), gS(), dim3(kThreads), 0, s_, F(y), insts(), segS());
+    for (int it = 0; it < iters; ++it) {
+        rc = dose(y, L_.Dt);
+        if (rc) return rc;
+        for (int i = 0; i < B_; ++i) { hin_[i].eu = u[i]; hin_[i].ev = v[i]; }
+        rc = put_insts();
+        if (rc) return rc;
+        hipLaunchKernelGGL((k_pi_rows<T>), gV(), dim3(kThreads), 0, s_, (const T *)F(L_.Dt), F(L_.tmp2),
+                           (const uint8_t *)U8(L_.lab), hi_(), insts(), segV(), partials());
+        rc = finish(true, all, 2);
+        if (rc) return rc;
+        std::vector<double> rs0(B_), rs1(B_);
+        for (int i = 0; i < B_; ++i) { rs0[i] = sum(i, 0); rs1[i] = sum(i, 1); }
+        rc = adjoint(L_.tmp2, L_.q);
+        if (rc) return rc;
+        hipLaunchKernelGGL((k_pi_mask<T>), gS(), dim3(kThreads), 0, s_, F(y), (const T *)F(L_.q),
+                           (const uint8_t *)U8(L_.act), segS(), partials());
+        rc = finish(false, all, 1);
+        if (rc) return rc;
+        for (int i = 0; i < B_; ++i) {
+            const LPConst &c = hin_[i].c;
+            const double gu = c.u_free ? -rs0[i] : 0.0, gv = c.v_free ? -rs1[i] : 0.0;
+            const double l = std::sqrt(sum(i, 0) + gu * gu + gv * gv);
+            lam[i] = l;
+            hin_[i].fac = l > 0 ? 1.0 / l : 1.0;
+            u[i] = l > 0 ? gu / l : u[i];
+            v[i] = l > 0 ? gv / l : v[i];
+        }
+        rc = put_insts();
+        if (rc) return rc;
+        hipLaunchKernelGGL((k_scale<T>), gS(), dim3(kThreads), 0, s_, F(y), insts(), segS());
+    }
+    for (int i = 0; i < B_; ++i) nrm[i] = std::sqrt(lam[i]);
     return SIPO_OK;
 }
 
-// One iteration: t = T(z), z <- Halpern update.  On check iterations t.lambda and the
-// pre-step lambda are written out.
+// Farkas test of d = max(a - b, 0) for the instances in `list`: scaled to dual objective 1,
+// every reduced-cost violation must be <= tol.  Uses tmp2 (z_d) and q.
+template <typename T>
+int Solver<T>::farkas(size_t alu, size_t all, size_t blu, size_t bll, double tol, const std::vector<int> &list,
+                      std::vector<char> &ok) {
+    ok.assign(B_, 0);
+    if (list.empty()) return SIPO_OK;
+    set_flags(list);
+    int rc = put_insts();
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_ray_candidate<T>), gV(), dim3(kThreads), 0, s_, (const T *)F(alu), (const T *)F(all),
+                       (const T *)F(blu), (const T *)F(bll), F(L_.tmp2), (const uint8_t *)U8(L_.lab), lo_(), hi_(),
+                       insts(), segV(), partials());
+    rc = finish(true, list, 4);
+    if (rc) return rc;
+    std::vector<int> need;
+    std::vector<double> obj(B_, 0.0);
+    for (int i : list) {
+        const LPConst &c = hin_[i].c;
+        double ray_obj = sum(i, 0);
+        if (!c.u_free) ray_obj -= c.h * sum(i, 1);
+        if (!c.v_free) ray_obj -= sum(i, 2);
+        if (!(ray_obj > 0) || !(sum(i, 3) > 0)) continue;
+        const double worst_u = c.u_free ? sum(i, 1) / ray_obj : 0.0;
+        const double worst_v = c.v_free ? sum(i, 2) / ray_obj : 0.0;
+        if (std::max(worst_u, worst_v) > tol) continue;
+        obj[i] = ray_obj;
+        need.push_back(i);
+    }
+    if (need.empty()) return SIPO_OK;
+    rc = adjoint(L_.tmp2, L_.q);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_ray_check<T>), gS(), dim3(kThreads), 0, s_, (const T *)F(L_.q), (const uint8_t *)U8(L_.act),
+                       segS(), partials());
+    rc = finish(false, need, 2, true);
+    if (rc) return rc;
+    for (int i : need) ok[i] = sum(i, 0) / obj[i] <= tol;
+    return SIPO_OK;
+}
+
+// One iteration of every active instance: t = T(z), z <- Halpern update.  On check
+// iterations t.lambda and the pre-step lambda are written out.
 template <typename T>
 int Solver<T>::iteration(bool check) {
     const bool hal = o_.mode == SIPO_PDHG_RESTARTED;
     prof_on_ = o_.profile != 0;
     int rc = mark(-1);   // start of this iteration's timeline segment
-    if (!rc) rc = adjoint((const T *)w_.z, V(w_.q));
+    if (!rc) rc = adjoint(L_.z, L_.q);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_primal<T>), dim3(gs_), dim3(kThreads), 0, s_, y_, V(w_.yt), (const T *)w_.q,
-                       hal ? (const T *)w_.Tj : (const T *)nullptr, act_, hal ? (const T *)w_.y0 : (const T *)nullptr,
-                       (const DevScal *)w_.scal, ns_);
+    hipLaunchKernelGGL((k_primal<T>), gS(), dim3(kThreads), 0, s_, F(L_.y), F(L_.yt), (const T *)F(L_.q),
+                       hal ? (const T *)F(L_.Tj) : (const T *)nullptr, (const uint8_t *)U8(L_.act),
+                       hal ? (const T *)F(L_.y0) : (const T *)nullptr, (const DevScal *)scal(), segS());
     rc = mark(SIPO_PHASE_PRIMAL);
-    if (!rc) rc = dose((const T *)w_.yt, V(w_.Dt));
+    if (!rc) rc = dose(L_.yt, L_.Dt);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_dual<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)w_.Dt, V(w_.D),
-                       hal ? (const T *)w_.D0 : (const T *)nullptr, lu_, ll_,
-                       hal ? (const T *)w_.lu0 : (const T *)nullptr, hal ? (const T *)w_.ll0 : (const T *)nullptr,
-                       V(w_.z), lab_, lo_, hi_, hal ? (const T *)w_.s_up : (const T *)nullptr,
-                       hal ? (const T *)w_.s_lo : (const T *)nullptr, check ? V(w_.lut) : (T *)nullptr,
-                       check ? V(w_.llt) : (T *)nullptr, check ? V(w_.luo) : (T *)nullptr,
-                       check ? V(w_.llo) : (T *)nullptr, (const DevScal *)w_.scal, c_, nv_, w_.partials);
+    hipLaunchKernelGGL((k_dual<T>), gV(), dim3(kThreads), 0, s_, (const T *)F(L_.Dt), F(L_.D),
+                       hal ? (const T *)F(L_.D0) : (const T *)nullptr, F(L_.lu), F(L_.ll),
+                       hal ? (const T *)F(L_.lu0) : (const T *)nullptr, hal ? (const T *)F(L_.ll0) : (const T *)nullptr,
+                       F(L_.z), (const uint8_t *)U8(L_.lab), lo_(), hi_(),
+                       hal ? (const T *)F(L_.s_up) : (const T *)nullptr, hal ? (const T *)F(L_.s_lo) : (const T *)nullptr,
+                       check ? F(L_.lut) : (T *)nullptr, check ? F(L_.llt) : (T *)nullptr,
+                       check ? F(L_.luo) : (T *)nullptr, check ? F(L_.llo) : (T *)nullptr, (const DevScal *)scal(),
+                       insts(), segV(), partials());
     rc = mark(SIPO_PHASE_DUAL);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_scalars, dim3(1), dim3(kThreads), 0, s_, w_.partials, gv_, w_.scal, c_);
+    hipLaunchKernelGGL(k_scalars, dim3(active_.size()), dim3(kThreads), 0, s_, (const double *)partials(),
+                       (const int *)P<int>(L_.firstV), (const int *)P<int>(L_.cntV), (const int *)P<int>(L_.list_act),
+                       scal(), insts());
     rc = mark(SIPO_PHASE_SCALARS);
     prof_on_ = false;
     return rc;
 }
 
-// nblk iterations, the last one a check iteration; captured once into a graph when requested.
+// nblk iterations, the last one a check iteration; captured once into a graph when requested
+// (the graph stays valid while the active set does not change).
 template <typename T>
 int Solver<T>::run_block(int nblk) {
     if (!o_.use_graph) {
@@ -895,207 +1249,285 @@ int Solver<T>::run_block(int nblk) {
 template <typename T>
 int Solver<T>::run(sipo_pdhg_result *res) {
     auto t0 = std::chrono::steady_clock::now();
-    std::memset(res, 0, sizeof(*res));
+    for (int i = 0; i < B_; ++i) std::memset(&res[i], 0, sizeof(res[i]));
+    hsums_.assign((size_t)B_ * kNS, 0.0);
     int rc = setup_common();
     if (rc) return rc;
+    std::vector<int> all(B_);
+    for (int i = 0; i < B_; ++i) all[i] = i;
     const bool hal = o_.mode == SIPO_PDHG_RESTARTED;
-    double omega = 1.0;
     const double eta = o_.eta > 0 ? o_.eta : 0.95;
-    double tau = o_.tau, sigma = o_.sigma;
     if (!hal) {
-        if (!(tau > 0 && sigma > 0)) {
-            double nrm = 0;
-            rc = power_norm(o_.power_iters > 0 ? o_.power_iters : 100, &nrm);
+        std::vector<double> nrm;
+        if (!(o_.tau > 0 && o_.sigma > 0)) {
+            rc = power_norm(o_.power_iters > 0 ? o_.power_iters : 100, nrm);
             if (rc) return rc;
-            if (!(nrm > 0)) return fail(SIPO_E_INVALID, "operator norm is zero (no active rays or no regions)");
-            tau = sigma = 0.9 / nrm;
         }
-        hs_.tau_fac = tau;
-        hs_.sig_fac = sigma;
-        hs_.tau_u = tau;
-        hs_.tau_v = tau;
-        hs_.halpern = 0.0;
-        hs_.rho = 0.0;
+        for (int i = 0; i < B_; ++i) {
+            Inst &I = in_[i];
+            if (o_.tau > 0 && o_.sigma > 0) { I.tau = o_.tau; I.sigma = o_.sigma; }
+            else {
+                if (!(nrm[i] > 0)) return fail(SIPO_E_INVALID, "instance %d: operator norm is zero", i);
+                I.tau = I.sigma = 0.9 / nrm[i];
+            }
+            DevScal &h = hsc_[i];
+            h.tau_fac = I.tau;
+            h.sig_fac = I.sigma;
+            h.tau_u = I.tau;
+            h.tau_v = I.tau;
+            h.halpern = 0.0;
+            h.rho = 0.0;
+        }
     } else {
-        hs_.tau_fac = eta / omega;
-        hs_.sig_fac = eta * omega;
-        hs_.tau_u = eta * Tu_ / omega;
-        hs_.tau_v = eta * Tv_ / omega;
-        hs_.halpern = 1.0;
-        hs_.rho = 1.0;
+        for (int i = 0; i < B_; ++i) {
+            const Inst &I = in_[i];
+            DevScal &h = hsc_[i];
+            h.tau_fac = eta / I.omega;
+            h.sig_fac = eta * I.omega;
+            h.tau_u = eta * I.Tu / I.omega;
+            h.tau_v = eta * I.Tv / I.omega;
+            h.halpern = 1.0;
+            h.rho = 1.0;
+        }
     }
-    hs_.u0 = hs_.u;
-    hs_.v0 = hs_.v;
-    double last_u = hs_.u, last_v = hs_.v;
-    rc = put_scal();
+    for (int i = 0; i < B_; ++i) {
+        hsc_[i].u0 = hsc_[i].u;
+        hsc_[i].v0 = hsc_[i].v;
+        in_[i].last_u = hsc_[i].u;
+        in_[i].last_v = hsc_[i].v;
+    }
+    set_flags(all);
+    rc = put_insts();
+    if (!rc) rc = put_scal();
     if (rc) return rc;
-    hipLaunchKernelGGL(k_scalars_init, dim3(1), dim3(1), 0, s_, w_.scal, c_);
+    hipLaunchKernelGGL(k_scalars_init, dim3(1), dim3(kThreads), 0, s_, scal(), insts(), B_);
     if (hal) {
         // anchor, restart point and snapshot start at the initial point
-        copy(V(w_.y0), (const T *)y_, ns_, gs_);
-        copy(V(w_.ylast), (const T *)y_, ns_, gs_);
-        copy(V(w_.D0), (const T *)w_.D, nv_, gv_);
-        for (void *dst : {w_.lu0, w_.lul, w_.snap_u}) copy(V(dst), (const T *)lu_, nv_, gv_);
-        for (void *dst : {w_.ll0, w_.lll, w_.snap_l}) copy(V(dst), (const T *)ll_, nv_, gv_);
+        copyS(L_.y0, L_.y, false);
+        copyS(L_.ylast, L_.y, false);
+        copyV(L_.D0, L_.D, false);
+        for (size_t dst : {L_.lu0, L_.lul, L_.snap_u}) copyV(dst, L_.lu, false);
+        for (size_t dst : {L_.ll0, L_.lll, L_.snap_l}) copyV(dst, L_.ll, false);
+        rc = get_scal();
+        if (!rc) rc = kkt(L_.y, L_.D, false, L_.lu, L_.ll, L_.z, all);
+        if (rc) return rc;
+        for (int i = 0; i < B_; ++i) in_[i].m_anchor = in_[i].kc.merit();
     }
     SIPO_LAUNCHED("pdhg setup");
 
     const int check = hal ? std::max(1, o_.check_every) : o_.max_iters;
     const double itol = o_.infeas_tol > 0 ? o_.infeas_tol : 1e-6;
-    int status = SIPO_ITER_LIMIT, restarts = 0, it = 0, k_restart = 0;
-    Kkt kc{};
-    double m_anchor = 0, m_prev = 1e300;
-    bool have_t = false;          // lut/llt/yt/Dt/ut_done hold a PDHG output t
-    const T *cert_a_u = nullptr, *cert_a_l = nullptr, *cert_b_u = nullptr, *cert_b_l = nullptr;
-    if (hal) {
-        Kkt k0{};
-        rc = kkt(y_, (const T *)w_.D, hs_.u, hs_.v, lu_, ll_, (const T *)w_.z, &k0);
-        if (rc) return rc;
-        m_anchor = k0.merit();
-    }
-    while (it < o_.max_iters) {
+    int it = 0;
+    bool have_t = false;
+    while (it < o_.max_iters && !active_.empty()) {
         const int nblk = std::min(check, o_.max_iters - it);
         rc = run_block(nblk);
         if (!rc) rc = flush_profile();
         if (rc) return rc;
         it += nblk;
         have_t = true;
+        for (int i : active_) in_[i].iters = it;
         if (!hal) break;
         rc = get_scal();
         if (rc) return rc;
-        if (!std::isfinite(hs_.u) || !std::isfinite(hs_.v) || !std::isfinite(hs_.sum_l1) ||
-            !std::isfinite(hs_.sum_Ul2)) {
-            status = SIPO_NUMERICAL;
-            break;
-        }
-        // KKT of the PDHG output t; z_lambda(t) into tmp2
-        double tl1, tul2;
-        rc = lambda_z(V(w_.lut), V(w_.llt), V(w_.tmp2), &tl1, &tul2);
-        if (rc) return rc;
-        rc = kkt((const T *)w_.yt, (const T *)w_.Dt, hs_.ut_done, hs_.vt_done, (const T *)w_.lut,
-                 (const T *)w_.llt, (const T *)w_.tmp2, &kc);
-        if (rc) return rc;
-        if (!std::isfinite(kc.r_p) || !std::isfinite(kc.r_d)) { status = SIPO_NUMERICAL; break; }
-        if (kc.rel() <= o_.tol) { status = SIPO_OPTIMAL; break; }
-        bool inf = false;
-        rc = farkas((const T *)w_.lut, (const T *)w_.llt, (const T *)w_.luo, (const T *)w_.llo, itol, &inf);
-        if (rc) return rc;
-        if (inf) {
-            cert_a_u = (const T *)w_.lut; cert_a_l = (const T *)w_.llt;
-            cert_b_u = (const T *)w_.luo; cert_b_l = (const T *)w_.llo;
-        } else {
-            rc = farkas((const T *)w_.lut, (const T *)w_.llt, (const T *)w_.snap_u, (const T *)w_.snap_l, itol, &inf);
-            if (rc) return rc;
-            if (inf) {
-                cert_a_u = (const T *)w_.lut; cert_a_l = (const T *)w_.llt;
-                cert_b_u = (const T *)w_.snap_u; cert_b_l = (const T *)w_.snap_l;
+        std::vector<int> live;
+        for (int i : active_) {
+            const DevScal &h = hsc_[i];
+            if (!std::isfinite(h.u) || !std::isfinite(h.v) || !std::isfinite(h.sum_l1) || !std::isfinite(h.sum_Ul2)) {
+                in_[i].status = SIPO_NUMERICAL;
+                in_[i].done = true;
+            } else {
+                live.push_back(i);
             }
         }
-        if (inf) { status = SIPO_PRIMAL_INFEASIBLE; break; }
-        copy(V(w_.snap_u), (const T *)w_.lut, nv_, gv_);
-        copy(V(w_.snap_l), (const T *)w_.llt, nv_, gv_);
-        const double m = kc.merit();
-        if (!(m <= 0.2 * m_anchor || (m <= 0.8 * m_anchor && m > m_prev) ||
-              (double)(it - k_restart) >= 0.36 * (double)it)) {
-            m_prev = m;
-            continue;
+        // KKT of the PDHG output t; z_lambda(t) into tmp2
+        rc = lambda_z(L_.lut, L_.llt, L_.tmp2, false);
+        if (!rc) rc = kkt(L_.yt, L_.Dt, true, L_.lut, L_.llt, L_.tmp2, live);
+        if (rc) return rc;
+        std::vector<int> open;
+        for (int i : live) {
+            const Kkt &k = in_[i].kc;
+            if (!std::isfinite(k.r_p) || !std::isfinite(k.r_d)) { in_[i].status = SIPO_NUMERICAL; in_[i].done = true; }
+            else if (k.rel() <= o_.tol) { in_[i].status = SIPO_OPTIMAL; in_[i].done = true; }
+            else open.push_back(i);
         }
-        // ---- restart at t: movement since the previous restart -> primal weight
-        double dy2, dlu2, dll2;
-        hipLaunchKernelGGL((k_wdist<T>), dim3(gs_), dim3(kThreads), 0, s_, (const T *)w_.yt, (const T *)w_.ylast,
-                           (const T *)w_.Tj, ns_, w_.partials);
-        rc = sums(gs_, 1, &dy2);
+        // infeasibility: lambda(t) - lambda(z), then lambda(t) - lambda(t at the previous check)
+        std::vector<char> ok1, ok2;
+        rc = farkas(L_.lut, L_.llt, L_.luo, L_.llo, itol, open, ok1);
         if (rc) return rc;
-        hipLaunchKernelGGL((k_wdist<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)w_.lut, (const T *)w_.lul,
-                           (const T *)w_.s_up, nv_, w_.partials);
-        rc = sums(gv_, 1, &dlu2);
+        std::vector<int> second;
+        for (int i : open) {
+            if (ok1[i]) { in_[i].status = SIPO_PRIMAL_INFEASIBLE; in_[i].cert = 0; in_[i].done = true; }
+            else second.push_back(i);
+        }
+        rc = farkas(L_.lut, L_.llt, L_.snap_u, L_.snap_l, itol, second, ok2);
         if (rc) return rc;
-        hipLaunchKernelGGL((k_wdist<T>), dim3(gv_), dim3(kThreads), 0, s_, (const T *)w_.llt, (const T *)w_.lll,
-                           (const T *)w_.s_lo, nv_, w_.partials);
-        rc = sums(gv_, 1, &dll2);
+        std::vector<int> cont;
+        for (int i : second) {
+            if (ok2[i]) { in_[i].status = SIPO_PRIMAL_INFEASIBLE; in_[i].cert = 1; in_[i].done = true; }
+            else cont.push_back(i);
+        }
+        set_flags(cont);
+        rc = put_insts();
         if (rc) return rc;
-        const double du = hs_.ut_done - last_u, dv = hs_.vt_done - last_v;
-        const double dx = std::sqrt(dy2 + (Tu_ > 0 ? du * du / Tu_ : 0.0) + (Tv_ > 0 ? dv * dv / Tv_ : 0.0));
-        const double dl = std::sqrt(dlu2 + dll2);
-        if (dx > 1e-10 && dl > 1e-10) omega = std::exp(0.5 * std::log(dl / dx) + 0.5 * std::log(omega));
-        // z, z0 and the restart point become t
-        for (void *dst : {(void *)y_, w_.y0, w_.ylast}) copy(V(dst), (const T *)w_.yt, ns_, gs_);
-        for (void *dst : {(void *)lu_, w_.lu0, w_.lul}) copy(V(dst), (const T *)w_.lut, nv_, gv_);
-        for (void *dst : {(void *)ll_, w_.ll0, w_.lll}) copy(V(dst), (const T *)w_.llt, nv_, gv_);
-        for (void *dst : {w_.D, w_.D0}) copy(V(dst), (const T *)w_.Dt, nv_, gv_);
-        double l1, ul2;
-        rc = lambda_z(lu_, ll_, V(w_.z), &l1, &ul2);
-        if (rc) return rc;
-        hs_.u = hs_.u0 = last_u = hs_.ut_done;
-        hs_.v = hs_.v0 = last_v = hs_.vt_done;
-        hs_.sums[0] = l1;
-        hs_.sums[1] = ul2;
-        hs_.tau_fac = eta / omega;
-        hs_.sig_fac = eta * omega;
-        hs_.tau_u = eta * Tu_ / omega;
-        hs_.tau_v = eta * Tv_ / omega;
-        rc = put_scal();
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_scalars_init, dim3(1), dim3(1), 0, s_, w_.scal, c_);
-        m_anchor = m;
-        m_prev = 1e300;
-        k_restart = it;
-        ++restarts;
+        copyV(L_.snap_u, L_.lut, true);
+        copyV(L_.snap_l, L_.llt, true);
+        // restart rules on the l2 merit of the relative KKT residuals
+        std::vector<int> rst;
+        for (int i : cont) {
+            Inst &I = in_[i];
+            const double m = I.kc.merit();
+            if (m <= 0.2 * I.m_anchor || (m <= 0.8 * I.m_anchor && m > I.m_prev) ||
+                (double)(it - I.k_restart) >= 0.36 * (double)it)
+                rst.push_back(i);
+            else
+                I.m_prev = m;
+        }
+        if (!rst.empty()) {
+            // movement since the previous restart -> primal weight
+            std::vector<double> dy2(B_), dlu2(B_), dll2(B_);
+            hipLaunchKernelGGL((k_wdist<T>), gS(), dim3(kThreads), 0, s_, (const T *)F(L_.yt), (const T *)F(L_.ylast),
+                               (const T *)F(L_.Tj), segS(), partials());
+            rc = finish(false, rst, 1);
+            if (rc) return rc;
+            for (int i : rst) dy2[i] = sum(i, 0);
+            hipLaunchKernelGGL((k_wdist<T>), gV(), dim3(kThreads), 0, s_, (const T *)F(L_.lut), (const T *)F(L_.lul),
+                               (const T *)F(L_.s_up), segV(), partials());
+            rc = finish(true, rst, 1);
+            if (rc) return rc;
+            for (int i : rst) dlu2[i] = sum(i, 0);
+            hipLaunchKernelGGL((k_wdist<T>), gV(), dim3(kThreads), 0, s_, (const T *)F(L_.llt), (const T *)F(L_.lll),
+                               (const T *)F(L_.s_lo), segV(), partials());
+            rc = finish(true, rst, 1);
+            if (rc) return rc;
+            for (int i : rst) dll2[i] = sum(i, 0);
+            // z, z0 and the restart point become t
+            set_flags(rst);
+            rc = put_insts();
+            if (rc) return rc;
+            for (size_t dst : {L_.y, L_.y0, L_.ylast}) copyS(dst, L_.yt, true);
+            for (size_t dst : {L_.lu, L_.lu0, L_.lul}) copyV(dst, L_.lut, true);
+            for (size_t dst : {L_.ll, L_.ll0, L_.lll}) copyV(dst, L_.llt, true);
+            for (size_t dst : {L_.D, L_.D0}) copyV(dst, L_.Dt, true);
+            rc = lambda_z(L_.lu, L_.ll, L_.z, true);
+            if (!rc) rc = finish(true, rst, 2);
+            if (rc) return rc;
+            for (int i : rst) {
+                Inst &I = in_[i];
+                DevScal &h = hsc_[i];
+                const double du = h.ut_done - I.last_u, dv = h.vt_done - I.last_v;
+                const double dx = std::sqrt(dy2[i] + (I.Tu > 0 ? du * du / I.Tu : 0.0) + (I.Tv > 0 ? dv * dv / I.Tv : 0.0));
+                const double dl = std::sqrt(dlu2[i] + dll2[i]);
+                if (dx > 1e-10 && dl > 1e-10) I.omega = std::exp(0.5 * std::log(dl / dx) + 0.5 * std::log(I.omega));
+                h.u = h.u0 = I.last_u = h.ut_done;
+                h.v = h.v0 = I.last_v = h.vt_done;
+                h.init_l1 = sum(i, 0);
+                h.init_Ul2 = sum(i, 1);
+                h.tau_fac = eta / I.omega;
+                h.sig_fac = eta * I.omega;
+                h.tau_u = eta * I.Tu / I.omega;
+                h.tau_v = eta * I.Tv / I.omega;
+                I.m_anchor = I.kc.merit();
+                I.m_prev = 1e300;
+                I.k_restart = it;
+                ++I.restarts;
+            }
+            rc = put_scal();   // restarting instances take the host values; the others keep theirs
+            if (rc) return rc;
+            hipLaunchKernelGGL(k_scalars_init, dim3(1), dim3(kThreads), 0, s_, scal(), insts(), B_);
+        }
+        if (cont.size() != active_.size()) {
+            rc = set_active(cont);
+            if (rc) return rc;
+        }
     }
-    // ---------------- returned point: the PDHG output t (restarted) or z = t (plain)
+    // ---------------- returned points: the PDHG output t (restarted) or z = t (plain)
     rc = get_scal();
+    if (!rc) rc = set_active(all);
     if (rc) return rc;
-    double u = hs_.u, v = hs_.v;
-    if (hal && have_t) {
-        u = hs_.ut_done;
-        v = hs_.vt_done;
-        copy(y_, (const T *)w_.yt, ns_, gs_);
-        copy(V(w_.D), (const T *)w_.Dt, nv_, gv_);
-        if (status == SIPO_PRIMAL_INFEASIBLE) {
-            hipLaunchKernelGGL((k_certificate<T>), dim3(gv_), dim3(kThreads), 0, s_, lu_, ll_, cert_a_u, cert_a_l,
-                               cert_b_u, cert_b_l, lab_, nv_);
-        } else {
-            copy(lu_, (const T *)w_.lut, nv_, gv_);
-            copy(ll_, (const T *)w_.llt, nv_, gv_);
+    std::vector<int> from_t, certs, recheck;
+    for (int i = 0; i < B_; ++i) {
+        if (hal && have_t) {
+            from_t.push_back(i);
+            if (in_[i].status == SIPO_PRIMAL_INFEASIBLE) certs.push_back(i);
+        }
+        if (in_[i].status == SIPO_ITER_LIMIT || in_[i].status == SIPO_NUMERICAL || !hal) recheck.push_back(i);
+    }
+    std::vector<double> ru(B_), rv(B_);
+    for (int i = 0; i < B_; ++i) {
+        const bool t = hal && have_t;
+        ru[i] = t ? hsc_[i].ut_done : hsc_[i].u;
+        rv[i] = t ? hsc_[i].vt_done : hsc_[i].v;
+    }
+    if (!from_t.empty()) {
+        set_flags(from_t);
+        for (int i : certs) hin_[i].sel = in_[i].cert;
+        rc = put_insts();
+        if (rc) return rc;
+        copyS(L_.y, L_.yt, true);
+        copyV(L_.D, L_.Dt, true);
+        std::vector<int> plain_copy;
+        for (int i : from_t)
+            if (in_[i].status != SIPO_PRIMAL_INFEASIBLE) plain_copy.push_back(i);
+        set_flags(plain_copy);
+        rc = put_insts();
+        if (rc) return rc;
+        copyV(L_.lu, L_.lut, true);
+        copyV(L_.ll, L_.llt, true);
+        if (!certs.empty()) {
+            set_flags(certs);
+            rc = put_insts();
+            if (rc) return rc;
+            hipLaunchKernelGGL((k_certificate<T>), gV(), dim3(kThreads), 0, s_, F(L_.lu), F(L_.ll), (const T *)F(L_.lut),
+                               (const T *)F(L_.llt), (const T *)F(L_.luo), (const T *)F(L_.llo),
+                               (const T *)F(L_.snap_u), (const T *)F(L_.snap_l), (const uint8_t *)U8(L_.lab), insts(),
+                               segV());
         }
     }
-    if (status == SIPO_ITER_LIMIT || status == SIPO_NUMERICAL || !hal) {
-        hipLaunchKernelGGL((k_lambda_z<T>), dim3(gv_), dim3(kThreads), 0, s_, lu_, ll_, V(w_.z), lab_, hi_, c_, nv_,
-                           w_.partials);
-        rc = kkt(y_, (const T *)w_.D, u, v, lu_, ll_, (const T *)w_.z, &kc);
+    if (!recheck.empty()) {
+        // KKT of the returned point (its u, v passed as the "t" scalars)
+        for (int i : recheck) { hsc_[i].ut_done = ru[i]; hsc_[i].vt_done = rv[i]; }
+        rc = set_active(recheck);
+        if (!rc) rc = lambda_z(L_.lu, L_.ll, L_.z, false);
+        if (!rc) rc = kkt(L_.y, L_.D, true, L_.lu, L_.ll, L_.z, recheck);
+        if (rc) return rc;
+        rc = set_active(all);
         if (rc) return rc;
     }
-    if (pb_.dose_out) copy((T *)pb_.dose_out, (const T *)w_.D, nv_, gv_);
-    if (t3_) {
-        rc = launch_sino_from_t(p_, y_, pb_.y, 0, s_);
-        if (rc) return rc;
-    }
+    rc = unpack();
+    if (rc) return rc;
     SIPO_LAUNCHED("pdhg finish");
     SIPO_HIP(hipStreamSynchronize(s_));
-    res->status = status;
-    res->iters = it;
-    res->restarts = restarts;
-    res->primal_obj = kc.p;
-    res->dual_obj = kc.d;
-    res->rel_primal = kc.eps_p;
-    res->rel_dual = kc.eps_d;
-    res->rel_gap = kc.eps_gap;
-    res->u = u;
-    res->v = v;
-    res->tau = tau;
-    res->sigma = sigma;
-    res->omega = omega;
-    res->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    for (int ph = 0; ph < SIPO_NUM_PHASES; ++ph) {
-        res->phase_ms[ph] = phase_ms_[ph];
-        res->phase_launches[ph] = phase_n_[ph];
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < B_; ++i) {
+        const Inst &I = in_[i];
+        sipo_pdhg_result &r = res[i];
+        r.status = I.status;
+        r.iters = I.iters;
+        r.restarts = I.restarts;
+        r.primal_obj = I.kc.p;
+        r.dual_obj = I.kc.d;
+        r.rel_primal = I.kc.eps_p;
+        r.rel_dual = I.kc.eps_d;
+        r.rel_gap = I.kc.eps_gap;
+        r.u = ru[i];
+        r.v = rv[i];
+        r.tau = I.tau;
+        r.sigma = I.sigma;
+        r.omega = I.omega;
+        r.time_ms = ms;
+        for (int ph = 0; ph < SIPO_NUM_PHASES; ++ph) {
+            r.phase_ms[ph] = phase_ms_[ph];
+            r.phase_launches[ph] = phase_n_[ph];
+        }
     }
     return SIPO_OK;
 }
 
-static int validate(const sipo_problem &pb, const sipo_pdhg_options &o, int idx) {
+static int validate(const sipo_problem &pb, const sipo_pdhg_options &o, int idx, sipo_dtype dt) {
     int rc = check_plan(pb.plan);
     if (rc) return rc;
+    SIPO_REQUIRE(pb.plan->dtype == dt, "problem %d: plan precision differs from problem 0", idx);
     SIPO_REQUIRE(pb.labels && pb.act && pb.y && pb.lam_up && pb.lam_lo, "problem %d: a required pointer is NULL", idx);
     SIPO_REQUIRE(pb.u_free == 0 || pb.u_free == 1, "problem %d: u_free must be 0 or 1", idx);
     SIPO_REQUIRE(pb.v_free == 0 || pb.v_free == 1, "problem %d: v_free must be 0 or 1", idx);
@@ -1118,33 +1550,29 @@ using namespace sipo;
 extern "C" {
 
 size_t sipo_pdhg_workspace_size(const sipo_problem *probs, int32_t n, const sipo_pdhg_options *) {
-    if (!probs || n < 1) return 0;
-    size_t m = 0;
+    if (!probs || n < 1 || n > 65536) return 0;
     for (int i = 0; i < n; ++i)
-        if (probs[i].plan) m = std::max(m, layout(probs[i], nullptr, nullptr));
-    return m;
+        if (!probs[i].plan) return 0;
+    return make_layout(probs, n).total;
 }
 
 int sipo_pdhg_solve(const sipo_problem *probs, int32_t n, const sipo_pdhg_options *opts, void *workspace,
                     size_t ws_bytes, sipo_pdhg_result *results, void *stream) {
-    SIPO_REQUIRE(probs && opts && results && n >= 1, "NULL argument or n < 1");
+    SIPO_REQUIRE(probs && opts && results && n >= 1 && n <= 65536, "NULL argument or n outside [1, 65536]");
+    SIPO_REQUIRE(probs[0].plan != nullptr, "problem 0: plan is NULL");
+    const sipo_dtype dt = probs[0].plan->dtype;
     for (int i = 0; i < n; ++i) {
-        int rc = validate(probs[i], *opts, i);
+        SIPO_REQUIRE(probs[i].plan != nullptr, "problem %d: plan is NULL", i);
+        int rc = validate(probs[i], *opts, i, dt);
         if (rc) return rc;
     }
-    const size_t need = sipo_pdhg_workspace_size(probs, n, opts);
+    const Layout L = make_layout(probs, n);
     SIPO_REQUIRE(workspace != nullptr, "workspace is NULL");
-    if (ws_bytes < need) return fail(SIPO_E_WORKSPACE, "workspace of %zu bytes < %zu required", ws_bytes, need);
+    if (ws_bytes < L.total) return fail(SIPO_E_WORKSPACE, "workspace of %zu bytes < %zu required", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
     SIPO_REQUIRE(!(opts->use_graph && s == nullptr), "graph capture needs a non-default stream");
-    for (int i = 0; i < n; ++i) {
-        Workspace w;
-        layout(probs[i], &w, (char *)workspace);
-        int rc = probs[i].plan->dtype == SIPO_F64 ? Solver<double>(probs[i], *opts, w, s).run(&results[i])
-                                                  : Solver<float>(probs[i], *opts, w, s).run(&results[i]);
-        if (rc) return rc;
-    }
-    return SIPO_OK;
+    return dt == SIPO_F64 ? Solver<double>(probs, n, *opts, (char *)workspace, L, s).run(results)
+                          : Solver<float>(probs, n, *opts, (char *)workspace, L, s).run(results);
 }
 
 }  // extern "C"
