@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=32, help="z slices in the bounded oracle sample")
     ap.add_argument("--ttk", action="store_true", help="also time a cold solve to relative KKT 1e-4")
+    ap.add_argument("--batch", type=int, default=8,
+                    help="instances of the uneven 2D batch (seeds 2000..) for the batched-vs-plain time to 1e-4 "
+                         "(0 = skip)")
+    ap.add_argument("--batch-only", action="store_true", help="run only the batched-vs-plain comparison")
     ap.add_argument("--probe", choices=["project", "copy"], default=None,
                     help="run only a few launches of one kernel (for hardware counter runs) and exit")
     return ap.parse_args()
@@ -103,6 +107,55 @@ def cpu_baseline(n, angles, slices):
                       f"({n}^2 x {angles} views, blur 1.5, Case 1), time scaled by {n}/{slices}"}
 
 
+def batch_vs_plain(count, dev, max_iters=20000):
+    """Time to relative KKT 1e-4 (or a checked infeasibility certificate) of the first
+    ``count`` instances of the uneven 2D batch: one batched, graph-captured solve against
+    the same solver run instance by instance (also graph-captured), on the same GPU."""
+    import torch
+    import paper_2604_08997_amd as sipo
+    from sipo_inputs import batch_instances, angles_uniform
+    insts = batch_instances(count, 2000)
+    lps = []
+    for b in insts:
+        plan = sipo.Plan(b.n, list(angles_uniform(b.n_angles)), dtype=torch.float32, device=dev)
+        lps.append(sipo.LP.build(plan, torch.as_tensor(b.target, dtype=torch.float32, device=dev), b.case,
+                                 band_width=10.0, f_min=1.0))
+    opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=max_iters, tol=1e-4, infeas_tol=1e-5, use_graph=1)
+    stream = torch.cuda.Stream()
+
+    def reset():
+        for lp in lps:
+            lp.y.zero_(); lp.lam_up.zero_(); lp.lam_lo.zero_()
+        torch.cuda.synchronize()
+
+    reset()
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        rb = sipo.solve(lps, opts, want_dose=False)
+        stream.synchronize()
+        t_batch = time.perf_counter() - t0
+    from collections import Counter
+    print(f"[bench] batch of {count}: batched {t_batch:.2f} s, "
+          f"{dict(Counter(r['status_name'] for r in rb))}", file=sys.stderr, flush=True)
+    reset()
+    rp = []
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        for k, lp in enumerate(lps):
+            rp.append(sipo.solve(lp, opts, want_dose=False))
+            print(f"[bench] one by one: instance {k} {rp[-1]['status_name']} after {rp[-1]['iters']} iterations",
+                  file=sys.stderr, flush=True)
+        stream.synchronize()
+        t_plain = time.perf_counter() - t0
+    print(f"[bench] batch of {count}: one by one {t_plain:.2f} s", file=sys.stderr, flush=True)
+    same = all(a["status"] == b["status"] and a["iters"] == b["iters"] for a, b in zip(rb, rp))
+    samples = sum(float(b.n) * b.n * b.n_angles for b in insts)
+    return {"instances": count, "seeds": f"2000-{2000 + count - 1}", "samples_per_application": samples,
+            "batched_s": round(t_batch, 3), "plain_s": round(t_plain, 3), "speedup": round(t_plain / t_batch, 3),
+            "status": dict(Counter(r["status_name"] for r in rb)), "max_iters": max_iters,
+            "max_iters_used": max(r["iters"] for r in rb), "per_instance_results_identical": same}
+
+
 def probe(args, plan, dev):
     """A few launches of one kernel, for hardware-counter runs (rocprofv3 --pmc)."""
     import torch
@@ -140,6 +193,9 @@ def main():
                      device=dev)
     if args.probe:
         return probe(args, plan, dev)
+    if args.batch_only:
+        print(json.dumps({"batched_vs_plain_time_to_1e-4": batch_vs_plain(args.batch, dev)}), flush=True)
+        return 0
     plan.autotune()
     f = torch.as_tensor(ellipsoids_target(n, 3000), dtype=torch.float32, device=dev)
     lp = sipo.LP.build(plan, f, sipo.CASE1, band_width=10.0, f_min=1.0)
@@ -183,6 +239,7 @@ def main():
                "restarts": r["restarts"], "objective": r["primal_obj"]}
         print(f"[bench] time to 1e-4: {ttk}", file=sys.stderr, flush=True)
 
+    bvp = batch_vs_plain(args.batch, dev) if args.batch > 0 else None
     cpu = None if args.no_cpu_baseline else cpu_baseline(n, na, args.cpu_slices)
     line = {
         "metric": "PDHG iters/s",
@@ -209,6 +266,8 @@ def main():
     }
     if ttk is not None:
         line["time_to_1e-4"] = ttk
+    if bvp is not None:
+        line["batched_vs_plain_time_to_1e-4"] = bvp
     print(json.dumps(line), flush=True)
     return 0
 

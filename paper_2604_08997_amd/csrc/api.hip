@@ -116,8 +116,8 @@ int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype 
     p->d_vial_rows = nullptr;
     p->d_zero = nullptr;
     p->d_geo2d = nullptr;
-    p->d_items_bp2d = p->d_items_fp2d = nullptr;
-    p->n_items_bp2d = p->n_items_fp2d = 0;
+    p->d_items_bp2d = p->d_items_fp2d = p->d_items_tr2d = nullptr;
+    p->n_items_bp2d = p->n_items_fp2d = p->n_items_tr2d = 0;
     p->p2d_ok = false;
     p->d_vol_t = nullptr;
     p->d_sino_t = nullptr;
@@ -133,6 +133,7 @@ int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype 
         (void)hipFree(p->d_geo2d);
         (void)hipFree(p->d_items_bp2d);
         (void)hipFree(p->d_items_fp2d);
+        (void)hipFree(p->d_items_tr2d);
         delete p;
         return rc;
     }
@@ -156,6 +157,7 @@ int sipo_plan_destroy(sipo_plan p) {
     (void)hipFree(p->d_geo2d);
     (void)hipFree(p->d_items_bp2d);
     (void)hipFree(p->d_items_fp2d);
+    (void)hipFree(p->d_items_tr2d);
     if (p->d_vol_t) (void)hipFree(p->d_vol_t);
     if (p->d_sino_t) (void)hipFree(p->d_sino_t);
     if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);

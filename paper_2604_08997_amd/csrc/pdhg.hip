@@ -556,7 +556,7 @@ struct Layout {
     int B = 0;
     std::vector<long long> soff, voff;          // element offsets per instance
     long long NS = 0, NV = 0;                   // packed sizes (elements)
-    int max_seg_s = 0, max_seg_v = 0, max_items_bp = 0, max_items_fp = 0;
+    int max_seg_s = 0, max_seg_v = 0, max_items_bp = 0, max_items_fp = 0, max_items_tr = 0;
     size_t eb = 4;
     bool lohi = false;                          // per-voxel bounds packed (some instance has arrays)
     size_t vol_t_elems = 0;                     // internal-layout volume scratch (largest 3D instance)
@@ -567,7 +567,7 @@ struct Layout {
         lo, hi, vol_t;
     // tables
     size_t partials, insts, scal, segS, segV, firstS, cntS, firstV, cntV, list_act, list_tmp, sums, geo, items_bp,
-        items_fp;
+        items_fp, items_tr;
     size_t total = 0;
 };
 
@@ -599,11 +599,13 @@ static Layout make_layout(const sipo_problem *probs, int B) {
         if (p->fast3d()) L.vol_t_elems = std::max(L.vol_t_elems, (size_t)nv);
         if (b2d) {
             const Geo2D g = plan_geo2d(p, 0, 0);
-            std::vector<int4> a, b;
+            std::vector<int4> a, b, c;
             append_items_bp2d(g, 0, a);
             append_items_fp2d(g, 0, b);
+            append_items_tr2d(g, 0, c);
             L.max_items_bp += (int)a.size();
             L.max_items_fp += (int)b.size();
+            L.max_items_tr += (int)c.size();
         }
     }
     size_t off = 0;
@@ -632,6 +634,7 @@ static Layout make_layout(const sipo_problem *probs, int B) {
     L.geo = take(sizeof(Geo2D) * B);
     L.items_bp = take(sizeof(int4) * std::max(L.max_items_bp, 1));
     L.items_fp = take(sizeof(int4) * std::max(L.max_items_fp, 1));
+    L.items_tr = take(sizeof(int4) * std::max(L.max_items_tr, 1));
     L.total = off;
     return L;
 }
@@ -698,11 +701,13 @@ class Solver {
     hipStream_t s_;
     bool b2d_ = false;
     int nc_max_ = 3;
+    bool bp_staged_ = true;
+    int n_max_ = 1;
     std::vector<Inst> in_;
     std::vector<InstC> hin_;
     std::vector<DevScal> hsc_;
     std::vector<int> active_;               // instances the iteration kernels run on
-    int n_seg_s_ = 0, n_seg_v_ = 0, n_items_bp_ = 0, n_items_fp_ = 0;
+    int n_seg_s_ = 0, n_seg_v_ = 0, n_items_bp_ = 0, n_items_fp_ = 0, n_items_tr_ = 0;
     std::vector<double> hsums_;             // [B][kNS]
     hipGraphExec_t graph_exec_ = nullptr;
     int graph_len_ = 0;
@@ -747,9 +752,11 @@ class Solver {
         }
         std::vector<Seg> ss, sv;
         std::vector<int> fs(B_, 0), cs(B_, 0), fv(B_, 0), cv(B_, 0);
-        std::vector<int4> ib, ifp;
+        std::vector<int4> ib, ifp, itr;
         std::vector<Geo2D> geo(B_);
         nc_max_ = 3;
+        n_max_ = 1;
+        bp_staged_ = true;
         for (int i : list) {
             const Inst &I = in_[i];
             fs[i] = (int)ss.size();
@@ -762,13 +769,17 @@ class Solver {
                 geo[i] = plan_geo2d(I.p, I.soff, I.voff);
                 append_items_bp2d(geo[i], i, ib);
                 append_items_fp2d(geo[i], i, ifp);
+                append_items_tr2d(geo[i], i, itr);
                 nc_max_ = std::max(nc_max_, I.p->p3d_nc);
+                bp_staged_ = bp_staged_ && bp2d_stage_fits(I.p->n, I.p->n_bins);
+                n_max_ = std::max(n_max_, I.p->n);
             }
         }
         n_seg_s_ = (int)ss.size();
         n_seg_v_ = (int)sv.size();
         n_items_bp_ = (int)ib.size();
         n_items_fp_ = (int)ifp.size();
+        n_items_tr_ = (int)itr.size();
         int rc = upload(L_.segS, ss.data(), sizeof(Seg) * ss.size());
         if (!rc) rc = upload(L_.segV, sv.data(), sizeof(Seg) * sv.size());
         if (!rc) rc = upload(L_.firstS, fs.data(), sizeof(int) * B_);
@@ -780,6 +791,7 @@ class Solver {
             rc = upload(L_.geo, geo.data(), sizeof(Geo2D) * B_);
             if (!rc) rc = upload(L_.items_bp, ib.data(), sizeof(int4) * ib.size());
             if (!rc) rc = upload(L_.items_fp, ifp.data(), sizeof(int4) * ifp.size());
+            if (!rc) rc = upload(L_.items_tr, itr.data(), sizeof(int4) * itr.size());
         }
         return rc;
     }
@@ -825,7 +837,8 @@ class Solver {
     // ---- operators on the solver's layouts (sinograms as held internally, volumes [z][y][x])
     int dose(size_t yf, size_t outf) {   // out = K P^T y on the active instances
         if (b2d_) {
-            int rc = launch_bp2d(I_dtype(), P<Geo2D>(L_.geo), P<int4>(L_.items_bp), n_items_bp_, F(yf), F(outf), 0, s_);
+            int rc = launch_bp2d(I_dtype(), bp_staged_, P<Geo2D>(L_.geo), P<int4>(L_.items_bp), n_items_bp_, F(yf),
+                                 F(outf), 0, s_);
             return rc ? rc : mark(SIPO_PHASE_BACKPROJECT);
         }
         for (int i : active_) {
@@ -849,8 +862,11 @@ class Solver {
     }
     int adjoint(size_t zf, size_t outf) {   // out = P K z on the active instances
         if (b2d_) {
-            int rc = launch_fp2d(I_dtype(), nc_max_, P<Geo2D>(L_.geo), P<int4>(L_.items_fp), n_items_fp_, F(zf),
-                                 F(outf), 0, s_);
+            // rays marching along x read an [x][y] copy (tmp is free: no blur in this path)
+            int rc = launch_tr2d(I_dtype(), P<Geo2D>(L_.geo), P<int4>(L_.items_tr), n_items_tr_, F(zf), F(L_.tmp), s_);
+            if (!rc) rc = mark(SIPO_PHASE_TRANSPOSE);
+            if (!rc) rc = launch_fp2d(I_dtype(), nc_max_, n_max_, P<Geo2D>(L_.geo), P<int4>(L_.items_fp), n_items_fp_, F(zf),
+                                      F(L_.tmp), F(outf), 0, s_);
             return rc ? rc : mark(SIPO_PHASE_PROJECT);
         }
         for (int i : active_) {

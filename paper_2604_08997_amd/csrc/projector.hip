@@ -896,11 +896,19 @@ int launch_mask_to_t(sipo_plan p, const uint8_t *mask, uint8_t *mask_t, hipStrea
     return SIPO_OK;
 }
 
+// Single-slice P through the plan's [x][y] scratch copy (allocated with the plan).
+static int fp2d_plan(sipo_plan p, const void *vol, void *sino, int accumulate, hipStream_t s) {
+    int rc = launch_tr2d(p->dtype, p->d_geo2d, p->d_items_tr2d, p->n_items_tr2d, vol, p->d_vol_t, s);
+    return rc ? rc : launch_fp2d(p->dtype, p->p3d_nc, p->n, p->d_geo2d, p->d_items_fp2d, p->n_items_fp2d, vol,
+                                 p->d_vol_t, sino, accumulate, s);
+}
+
 // Internal-layout entry points (see sipo_internal.hpp).  Slice and fallback
 // plans have no separate internal layout: they run the slice kernels directly.
 int launch_backproject_t(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s) {
     if (p->p2d_ok)
-        return launch_bp2d(p->dtype, p->d_geo2d, p->d_items_bp2d, p->n_items_bp2d, sino_t, vol, accumulate, s);
+        return launch_bp2d(p->dtype, bp2d_stage_fits(p->n, p->n_bins), p->d_geo2d, p->d_items_bp2d,
+                           p->n_items_bp2d, sino_t, vol, accumulate, s);
     if (!p->fast3d())
         return p->dtype == SIPO_F64 ? bp_slices<double>(p, sino_t, vol, accumulate, s)
                                     : bp_slices<float>(p, sino_t, vol, accumulate, s);
@@ -909,8 +917,7 @@ int launch_backproject_t(sipo_plan p, const void *sino_t, void *vol, int accumul
 }
 
 int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
-    if (p->p2d_ok)
-        return launch_fp2d(p->dtype, p->p3d_nc, p->d_geo2d, p->d_items_fp2d, p->n_items_fp2d, vol_t, sino_t, 0, s);
+    if (p->p2d_ok) return fp2d_plan(p, vol_t, sino_t, 0, s);
     if (!p->fast3d())
         return p->dtype == SIPO_F64 ? fp_slices<double>(p, vol_t, sino_t, 0, s)
                                     : fp_slices<float>(p, vol_t, sino_t, 0, s);
@@ -932,9 +939,7 @@ int launch_backproject(sipo_plan p, const void *sino, void *vol, int accumulate,
 }
 
 int launch_project(sipo_plan p, const void *vol, void *sino, int accumulate, hipStream_t s) {
-    if (p->p2d_ok)
-        return launch_fp2d(p->dtype, p->p3d_nc, p->d_geo2d, p->d_items_fp2d, p->n_items_fp2d, vol, sino, accumulate,
-                           s);
+    if (p->p2d_ok) return fp2d_plan(p, vol, sino, accumulate, s);
     if (!p->fast3d())
         return p->dtype == SIPO_F64 ? fp_slices<double>(p, vol, sino, accumulate, s)
                                     : fp_slices<float>(p, vol, sino, accumulate, s);

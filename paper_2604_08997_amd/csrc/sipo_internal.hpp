@@ -85,8 +85,8 @@ struct sipo_plan_s {
     int n_walk;             // views the projector walks (entries of d_angle_order)
     bool p2d_ok;            // single-slice plan served by the 2D kernels
     sipo::Geo2D *d_geo2d;   // this plan as a one-instance batch
-    int4 *d_items_bp2d, *d_items_fp2d;
-    int n_items_bp2d, n_items_fp2d;
+    int4 *d_items_bp2d, *d_items_fp2d, *d_items_tr2d;
+    int n_items_bp2d, n_items_fp2d, n_items_tr2d;
     int blur_zc;            // slices per blur workgroup (0 = built-in choice)
     bool bp3d_ok;           // the 3D backprojector's bin window fits its LDS tile
     void *d_vol_t;          // lazily allocated [y][x][z] scratch volume (standalone 3D calls)
@@ -128,6 +128,7 @@ struct Geo2D {
     int n, n_angles, n_bins, n_walk;
     int pair, nc;            // views walked in opposite pairs; candidate voxels per ray step
     double h, inv_ds, atten;
+    const int2 *vial;        // [n]: first and last index along a grid line inside the vial
 };
 constexpr int kB2X = 32, kB2Y = 8;   // P^T tile: 32 x 8 voxels per workgroup
 constexpr int kF2B = 64, kF2V = 4;   // P bundle: 64 bins x 4 walked views per workgroup
@@ -135,10 +136,17 @@ Geo2D plan_geo2d(sipo_plan p, long long soff, long long voff);
 // Items of one instance appended to a list: P^T (geo, x0, y0, 0) and P (geo, first walked view, b0, 0).
 void append_items_bp2d(const Geo2D &g, int geo_index, std::vector<int4> &items);
 void append_items_fp2d(const Geo2D &g, int geo_index, std::vector<int4> &items);
-int launch_bp2d(sipo_dtype dt, const Geo2D *geo, const int4 *items, int n_items, const void *sino, void *vol,
-                int accumulate, hipStream_t s);
-int launch_fp2d(sipo_dtype dt, int nc, const Geo2D *geo, const int4 *items, int n_items, const void *vol,
-                void *sino, int accumulate, hipStream_t s);
+bool bp2d_stage_fits(int n, int n_bins);
+int launch_bp2d(sipo_dtype dt, bool staged, const Geo2D *geo, const int4 *items, int n_items, const void *sino,
+                void *vol, int accumulate, hipStream_t s);
+// vol_xt: optional [x][y] copy of the volume (from launch_tr2d), read by rays that march along x
+constexpr int kF2MaxN = 16384;   // largest single-slice grid of the 2D projector (its LDS holds n vial extents)
+int launch_fp2d(sipo_dtype dt, int nc, int n_max, const Geo2D *geo, const int4 *items, int n_items, const void *vol,
+                const void *vol_xt, void *sino, int accumulate, hipStream_t s);
+// Per-instance transpose of single-slice volumes: out[x][y] = in[y][x]; items (geo, x0, y0, 0) of 64 x 64 tiles.
+void append_items_tr2d(const Geo2D &g, int geo_index, std::vector<int4> &items);
+int launch_tr2d(sipo_dtype dt, const Geo2D *geo, const int4 *items, int n_items, const void *in, void *out,
+                hipStream_t s);
 int plan_build_2d(sipo_plan p);
 
 // ------------------------------------------------------------- geometry

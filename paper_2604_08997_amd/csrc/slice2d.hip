@@ -28,65 +28,125 @@ __device__ __forceinline__ bool in_vial(int c, int r, int n) {
     return a * a + b * b <= (long long)n * n;
 }
 
-template <typename T>
+// P^T.  STAGED: per batch of kB2VB walked views the sinogram window each view
+// (and its partner) can send into the tile is copied to LDS first, so the
+// per-voxel gathers hit LDS; used when the tile's bin window fits kB2W.
+constexpr int kB2VB = 16, kB2W = 48;
+
+template <typename T, bool STAGED>
 __global__ void __launch_bounds__(256) bp2d_kernel(const Geo2D *__restrict__ geo, const int4 *__restrict__ items,
                                                    const T *__restrict__ sino, T *__restrict__ vol, int accumulate) {
+    __shared__ T rows[STAGED ? 2 * kB2VB : 1][STAGED ? kB2W : 1];
+    __shared__ int rbase[2 * kB2VB];
+    __shared__ double2 vtrig[kB2VB];   // (sin, cos) of the batch's walked views
     const int4 it = items[blockIdx.x];
     const Geo2D &g = geo[it.x];
     const int n = g.n, nb = g.n_bins;
     const int c = it.y + (int)(threadIdx.x % kB2X), r = it.z + (int)(threadIdx.x / kB2X);
-    if (c >= n || r >= n) return;
+    const bool in_grid = c < n && r < n;
+    const bool inside = in_grid && in_vial(c, r, n);
+    const double x = centre(c, g.h), y = centre(r, g.h);
+    const T atten = (T)g.atten;
+    const T *s0 = sino + g.soff;
     T acc = (T)0;
-    if (in_vial(c, r, n)) {
-        const double x = centre(c, g.h), y = centre(r, g.h);
-        const T atten = (T)g.atten;
-        const T *s0 = sino + g.soff;
-        for (int k = 0; k < g.n_walk; ++k) {
-            const int a = g.walk[k];
-            const double2 tr = g.trig[a];
-            const double s = fma(-x, tr.x, y * tr.y);
-            const double u = fma(s + 1.0, g.inv_ds, -0.5);
-            const double t = fma(x, tr.y, y * tr.x);
-            T rr = (T)fma(-s, s, 1.0);
-            rr = rr > (T)0 ? sqrt_t<T>(rr) : (T)0;
-            {
-                const double bf = floor(u);
-                const int b = (int)bf;
-                const T f = (T)(u - bf);
-                const T w = exp_neg<T>(atten, (T)t + rr);
-                const T *row = s0 + (size_t)a * nb;
-                const T v0 = (b >= 0 && b < nb) ? row[b] : (T)0;
-                const T v1 = (b + 1 >= 0 && b + 1 < nb) ? row[b + 1] : (T)0;
-                const T w1 = w * f;
-                acc = fma(w - w1, v0, acc);
-                acc = fma(w1, v1, acc);
+    for (int k0 = 0; k0 < g.n_walk; k0 += (STAGED ? kB2VB : g.n_walk)) {
+        const int nk = STAGED ? min(kB2VB, g.n_walk - k0) : g.n_walk;
+        if (STAGED) {
+            if ((int)threadIdx.x < 2 * nk) {
+                // first staged bin of row (view, mirror): floor of the smallest u over the tile corners, minus 1
+                const int kk = k0 + (int)threadIdx.x / 2, mir = threadIdx.x & 1;
+                const double2 tr = g.trig[g.walk[kk]];
+                const int cx[2] = {it.y, min(it.y + kB2X, n) - 1}, ry[2] = {it.z, min(it.z + kB2Y, n) - 1};
+                double umin = 1e300, umax = -1e300;
+                for (int i = 0; i < 2; ++i)
+                    for (int j = 0; j < 2; ++j) {
+                        const double xs = centre(cx[i], g.h), ys = centre(ry[j], g.h);
+                        const double u = fma(fma(-xs, tr.x, ys * tr.y) + 1.0, g.inv_ds, -0.5);
+                        umin = fmin(umin, u);
+                        umax = fmax(umax, u);
+                    }
+                const double lo = mir ? (double)(nb - 1) - umax : umin;
+                rbase[threadIdx.x] = (int)floor(lo) - 1;
+                if (!mir) vtrig[threadIdx.x / 2] = tr;
             }
-            if (g.pair) {
-                // opposite view: u' = nb - 1 - u, t' = -t, same sqrt(1 - s^2)
-                const double u2 = (double)(nb - 1) - u;
-                const double bf = floor(u2);
-                const int b = (int)bf;
-                const T f = (T)(u2 - bf);
-                const T w = exp_neg<T>(atten, rr - (T)t);
-                const T *row = s0 + (size_t)g.partner[a] * nb;
-                const T v0 = (b >= 0 && b < nb) ? row[b] : (T)0;
-                const T v1 = (b + 1 >= 0 && b + 1 < nb) ? row[b + 1] : (T)0;
-                const T w1 = w * f;
-                acc = fma(w - w1, v0, acc);
-                acc = fma(w1, v1, acc);
+            __syncthreads();
+            for (int e = threadIdx.x; e < 2 * nk * kB2W; e += 256) {
+                const int row = e / kB2W, col = e - row * kB2W;
+                const int a = g.walk[k0 + row / 2];
+                const int av = (row & 1) ? (g.pair ? g.partner[a] : -1) : a;
+                const int b = rbase[row] + col;
+                rows[row][col] = (av >= 0 && b >= 0 && b < nb) ? s0[(size_t)av * nb + b] : (T)0;
+            }
+            __syncthreads();
+        }
+        if (inside) {
+            for (int kq = 0; kq < nk; ++kq) {
+                const int a = STAGED ? 0 : g.walk[k0 + kq];
+                const double2 tr = STAGED ? vtrig[kq] : g.trig[a];
+                const double s = fma(-x, tr.x, y * tr.y);
+                const double u = fma(s + 1.0, g.inv_ds, -0.5);
+                const double t = fma(x, tr.y, y * tr.x);
+                T rr = (T)fma(-s, s, 1.0);
+                rr = rr > (T)0 ? sqrt_t<T>(rr) : (T)0;
+                {
+                    const double bf = floor(u);
+                    const int b = (int)bf;
+                    const T f = (T)(u - bf);
+                    const T w = exp_neg<T>(atten, (T)t + rr);
+                    T v0, v1;
+                    if (STAGED) {
+                        const int bl = min(max(b - rbase[2 * kq], 0), kB2W - 2);
+                        v0 = rows[2 * kq][bl];
+                        v1 = rows[2 * kq][bl + 1];
+                    } else {
+                        const T *row = s0 + (size_t)a * nb;
+                        v0 = (b >= 0 && b < nb) ? row[b] : (T)0;
+                        v1 = (b + 1 >= 0 && b + 1 < nb) ? row[b + 1] : (T)0;
+                    }
+                    const T w1 = w * f;
+                    acc = fma(w - w1, v0, acc);
+                    acc = fma(w1, v1, acc);
+                }
+                if (g.pair) {
+                    // opposite view: u' = nb - 1 - u, t' = -t, same sqrt(1 - s^2)
+                    const double u2 = (double)(nb - 1) - u;
+                    const double bf = floor(u2);
+                    const int b = (int)bf;
+                    const T f = (T)(u2 - bf);
+                    const T w = exp_neg<T>(atten, rr - (T)t);
+                    T v0, v1;
+                    if (STAGED) {
+                        const int bl = min(max(b - rbase[2 * kq + 1], 0), kB2W - 2);
+                        v0 = rows[2 * kq + 1][bl];
+                        v1 = rows[2 * kq + 1][bl + 1];
+                    } else {
+                        const T *row = s0 + (size_t)g.partner[a] * nb;
+                        v0 = (b >= 0 && b < nb) ? row[b] : (T)0;
+                        v1 = (b + 1 >= 0 && b + 1 < nb) ? row[b + 1] : (T)0;
+                    }
+                    const T w1 = w * f;
+                    acc = fma(w - w1, v0, acc);
+                    acc = fma(w1, v1, acc);
+                }
             }
         }
+        if (STAGED) __syncthreads();
     }
+    if (!in_grid) return;
     T *dst = vol + g.voff + (size_t)r * n + c;
     *dst = accumulate ? *dst + acc : acc;
 }
 
 template <typename T, int NC>
 __global__ void __launch_bounds__(256) fp2d_kernel(const Geo2D *__restrict__ geo, const int4 *__restrict__ items,
-                                                   const T *__restrict__ vol, T *__restrict__ sino, int accumulate) {
+                                                   const T *__restrict__ vol, const T *__restrict__ vol_xt,
+                                                   T *__restrict__ sino, int accumulate) {
+    extern __shared__ int2 vials[];   // vial extent of every grid line of the instance (n entries)
     const int4 it = items[blockIdx.x];
     const Geo2D &g = geo[it.x];
     const int n = g.n, nb = g.n_bins;
+    for (int m = threadIdx.x; m < n; m += 256) vials[m] = g.vial[m];
+    __syncthreads();
     const int b = it.z + (int)(threadIdx.x % kF2B), k = it.y + (int)(threadIdx.x / kF2B);
     if (b >= nb || k >= g.n_walk) return;
     const int a = g.walk[k];
@@ -103,9 +163,13 @@ __global__ void __launch_bounds__(256) fp2d_kernel(const Geo2D *__restrict__ geo
     const double inv_du = 1.0 / du;
     const T du_t = (T)du, dsj_t = (T)dsj, dtj_t = (T)dtj, atten = (T)g.atten;
     const bool pair = g.pair != 0;
-    const T *v0 = vol + g.voff;
+    // along the cross index j the voxels of step m are contiguous in vol ([y][x], y-major rays)
+    // or in vol_xt ([x][y], x-major rays); without vol_xt x-major rays read vol with stride n
+    const T *base = (xmajor && vol_xt) ? vol_xt + g.voff : vol + g.voff;
+    const int sm = xmajor ? (vol_xt ? n : 1) : n, sj = xmajor ? (vol_xt ? 1 : n) : 1;
     T acc1 = (T)0, acc2 = (T)0;
     for (int m = 0; m < n; ++m) {
+        const int2 vr = vials[m];
         const double U = fma((double)m, dU, U00);
         const double jA = ((double)b - 1.0 - U) * inv_du, jB = ((double)b + 1.0 - U) * inv_du;
         const int jlo = (int)ceil(fmin(jA, jB) - 1e-9);
@@ -113,17 +177,17 @@ __global__ void __launch_bounds__(256) fp2d_kernel(const Geo2D *__restrict__ geo
         const T d0 = (T)(fma(jl, du, U) - (double)b);
         const T s0 = (T)fma(jl, dsj, fma((double)m, dsm, s00));
         const T t0 = (T)fma(jl, dtj, fma((double)m, dtm, t00));
+        const T *row = base + m * sm;
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             const int j = jlo + q;
-            const int c = xmajor ? m : j, r = xmajor ? j : m;
             const T hat = (T)1 - fabs(d0 + (T)q * du_t);
-            if (j < 0 || j >= n || !(hat > (T)0) || !in_vial(c, r, n)) continue;
+            if (j < vr.x || j > vr.y || !(hat > (T)0)) continue;
             const T sq = s0 + (T)q * dsj_t;
             T rr = (T)1 - sq * sq;
             rr = rr > (T)0 ? sqrt_t<T>(rr) : (T)0;
             const T tq = t0 + (T)q * dtj_t;
-            const T v = v0[(size_t)r * n + c];
+            const T v = row[j * sj];
             acc1 = fma(hat * exp_neg<T>(atten, tq + rr), v, acc1);
             if (pair) acc2 = fma(hat * exp_neg<T>(atten, rr - tq), v, acc2);
         }
@@ -133,6 +197,28 @@ __global__ void __launch_bounds__(256) fp2d_kernel(const Geo2D *__restrict__ geo
     if (pair) {
         T *d2 = sino + g.soff + (size_t)g.partner[a] * nb + (nb - 1 - b);
         *d2 = accumulate ? *d2 + acc2 : acc2;
+    }
+}
+
+// out[x][y] = in[y][x] per instance, 64 x 64 tiles through LDS.
+template <typename T>
+__global__ void __launch_bounds__(256) tr2d_kernel(const Geo2D *__restrict__ geo, const int4 *__restrict__ items,
+                                                   const T *__restrict__ in, T *__restrict__ out) {
+    __shared__ T tile[64][65];
+    const int4 it = items[blockIdx.x];
+    const Geo2D &g = geo[it.x];
+    const int n = g.n;
+    const T *src = in + g.voff;
+    T *dst = out + g.voff;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int r = it.z + i, c = it.y + tx;
+        tile[i][tx] = (r < n && c < n) ? src[(size_t)r * n + c] : (T)0;
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int c = it.y + i, r = it.z + tx;
+        if (r < n && c < n) dst[(size_t)c * n + r] = tile[tx][i];
     }
 }
 
@@ -153,6 +239,7 @@ Geo2D plan_geo2d(sipo_plan p, long long soff, long long voff) {
     g.h = 2.0 / p->n;
     g.inv_ds = 0.5 * p->n_bins;
     g.atten = p->atten;
+    g.vial = p->d_vial_rows;
     return g;
 }
 
@@ -161,64 +248,102 @@ void append_items_bp2d(const Geo2D &g, int gi, std::vector<int4> &items) {
         for (int x0 = 0; x0 < g.n; x0 += kB2X) items.push_back(make_int4(gi, x0, y0, 0));
 }
 
+void append_items_tr2d(const Geo2D &g, int gi, std::vector<int4> &items) {
+    for (int y0 = 0; y0 < g.n; y0 += 64)
+        for (int x0 = 0; x0 < g.n; x0 += 64) items.push_back(make_int4(gi, x0, y0, 0));
+}
+
+int launch_tr2d(sipo_dtype dt, const Geo2D *geo, const int4 *items, int n_items, const void *in, void *out,
+                hipStream_t s) {
+    if (n_items <= 0) return SIPO_OK;
+    if (dt == SIPO_F64)
+        hipLaunchKernelGGL((tr2d_kernel<double>), dim3(n_items), dim3(256), 0, s, geo, items, (const double *)in,
+                           (double *)out);
+    else
+        hipLaunchKernelGGL((tr2d_kernel<float>), dim3(n_items), dim3(256), 0, s, geo, items, (const float *)in,
+                           (float *)out);
+    SIPO_LAUNCHED("tr2d_kernel");
+    return SIPO_OK;
+}
+
 void append_items_fp2d(const Geo2D &g, int gi, std::vector<int4> &items) {
     for (int k0 = 0; k0 < g.n_walk; k0 += kF2V)
         for (int b0 = 0; b0 < g.n_bins; b0 += kF2B) items.push_back(make_int4(gi, k0, b0, 0));
 }
 
-int launch_bp2d(sipo_dtype dt, const Geo2D *geo, const int4 *items, int n_items, const void *sino, void *vol,
-                int accumulate, hipStream_t s) {
+// The tile's bin window (with guards) fits the staged row width for this detector/grid ratio.
+bool bp2d_stage_fits(int n, int n_bins) {
+    const double span = std::sqrt((double)(kB2X - 1) * (kB2X - 1) + (double)(kB2Y - 1) * (kB2Y - 1)) * n_bins / n;
+    return span + 5.0 <= (double)kB2W;
+}
+
+int launch_bp2d(sipo_dtype dt, bool staged, const Geo2D *geo, const int4 *items, int n_items, const void *sino,
+                void *vol, int accumulate, hipStream_t s) {
     if (n_items <= 0) return SIPO_OK;
-    if (dt == SIPO_F64)
-        hipLaunchKernelGGL((bp2d_kernel<double>), dim3(n_items), dim3(256), 0, s, geo, items, (const double *)sino,
-                           (double *)vol, accumulate);
-    else
-        hipLaunchKernelGGL((bp2d_kernel<float>), dim3(n_items), dim3(256), 0, s, geo, items, (const float *)sino,
-                           (float *)vol, accumulate);
+    const dim3 grid(n_items), block(256);
+    if (dt == SIPO_F64) {
+        if (staged) hipLaunchKernelGGL((bp2d_kernel<double, true>), grid, block, 0, s, geo, items, (const double *)sino,
+                                       (double *)vol, accumulate);
+        else hipLaunchKernelGGL((bp2d_kernel<double, false>), grid, block, 0, s, geo, items, (const double *)sino,
+                                (double *)vol, accumulate);
+    } else {
+        if (staged) hipLaunchKernelGGL((bp2d_kernel<float, true>), grid, block, 0, s, geo, items, (const float *)sino,
+                                       (float *)vol, accumulate);
+        else hipLaunchKernelGGL((bp2d_kernel<float, false>), grid, block, 0, s, geo, items, (const float *)sino,
+                                (float *)vol, accumulate);
+    }
     SIPO_LAUNCHED("bp2d_kernel");
     return SIPO_OK;
 }
 
 template <typename T>
-static int fp2d_t(int nc, const Geo2D *geo, const int4 *items, int n_items, const void *vol, void *sino,
-                  int accumulate, hipStream_t s) {
+static int fp2d_t(int nc, int n_max, const Geo2D *geo, const int4 *items, int n_items, const void *vol,
+                  const void *vol_xt, void *sino, int accumulate, hipStream_t s) {
     const dim3 grid(n_items), block(256);
+    const size_t shm = sizeof(int2) * (size_t)n_max;
+    const T *v = (const T *)vol, *vx = (const T *)vol_xt;
     switch (nc) {
-        case 3: hipLaunchKernelGGL((fp2d_kernel<T, 3>), grid, block, 0, s, geo, items, (const T *)vol, (T *)sino,
-                                   accumulate); break;
-        case 4: hipLaunchKernelGGL((fp2d_kernel<T, 4>), grid, block, 0, s, geo, items, (const T *)vol, (T *)sino,
-                                   accumulate); break;
-        case 6: hipLaunchKernelGGL((fp2d_kernel<T, 6>), grid, block, 0, s, geo, items, (const T *)vol, (T *)sino,
-                                   accumulate); break;
+        case 3: hipLaunchKernelGGL((fp2d_kernel<T, 3>), grid, block, shm, s, geo, items, v, vx, (T *)sino, accumulate);
+                break;
+        case 4: hipLaunchKernelGGL((fp2d_kernel<T, 4>), grid, block, shm, s, geo, items, v, vx, (T *)sino, accumulate);
+                break;
+        case 6: hipLaunchKernelGGL((fp2d_kernel<T, 6>), grid, block, shm, s, geo, items, v, vx, (T *)sino, accumulate);
+                break;
         default: return fail(SIPO_E_UNSUPPORTED, "2D projector: unsupported candidate count %d", nc);
     }
     SIPO_LAUNCHED("fp2d_kernel");
     return SIPO_OK;
 }
 
-int launch_fp2d(sipo_dtype dt, int nc, const Geo2D *geo, const int4 *items, int n_items, const void *vol,
-                void *sino, int accumulate, hipStream_t s) {
+int launch_fp2d(sipo_dtype dt, int nc, int n_max, const Geo2D *geo, const int4 *items, int n_items, const void *vol,
+                const void *vol_xt, void *sino, int accumulate, hipStream_t s) {
     if (n_items <= 0) return SIPO_OK;
-    return dt == SIPO_F64 ? fp2d_t<double>(nc, geo, items, n_items, vol, sino, accumulate, s)
-                          : fp2d_t<float>(nc, geo, items, n_items, vol, sino, accumulate, s);
+    if (n_max < 1 || n_max > kF2MaxN) return fail(SIPO_E_UNSUPPORTED, "2D projector: grid %d > %d", n_max, kF2MaxN);
+    return dt == SIPO_F64 ? fp2d_t<double>(nc, n_max, geo, items, n_items, vol, vol_xt, sino, accumulate, s)
+                          : fp2d_t<float>(nc, n_max, geo, items, n_items, vol, vol_xt, sino, accumulate, s);
 }
 
 // The plan as a one-instance batch (single-slice plans only).
 int plan_build_2d(sipo_plan p) {
-    p->p2d_ok = p->nz == 1 && p->p3d_nc > 0;
+    p->p2d_ok = p->nz == 1 && p->p3d_nc > 0 && p->n <= kF2MaxN;
     if (!p->p2d_ok) return SIPO_OK;
     const Geo2D g = plan_geo2d(p, 0, 0);
-    std::vector<int4> ib, ifp;
+    std::vector<int4> ib, ifp, itr;
     append_items_bp2d(g, 0, ib);
     append_items_fp2d(g, 0, ifp);
+    append_items_tr2d(g, 0, itr);
     SIPO_HIP(hipMalloc(&p->d_geo2d, sizeof(Geo2D)));
     SIPO_HIP(hipMalloc(&p->d_items_bp2d, sizeof(int4) * ib.size()));
     SIPO_HIP(hipMalloc(&p->d_items_fp2d, sizeof(int4) * ifp.size()));
     SIPO_HIP(hipMemcpy(p->d_geo2d, &g, sizeof(Geo2D), hipMemcpyHostToDevice));
     SIPO_HIP(hipMemcpy(p->d_items_bp2d, ib.data(), sizeof(int4) * ib.size(), hipMemcpyHostToDevice));
     SIPO_HIP(hipMemcpy(p->d_items_fp2d, ifp.data(), sizeof(int4) * ifp.size(), hipMemcpyHostToDevice));
+    SIPO_HIP(hipMalloc(&p->d_vol_t, p->vol_elems() * p->elem_bytes()));   // [x][y] copy for P
+    SIPO_HIP(hipMalloc(&p->d_items_tr2d, sizeof(int4) * itr.size()));
+    SIPO_HIP(hipMemcpy(p->d_items_tr2d, itr.data(), sizeof(int4) * itr.size(), hipMemcpyHostToDevice));
     p->n_items_bp2d = (int)ib.size();
     p->n_items_fp2d = (int)ifp.size();
+    p->n_items_tr2d = (int)itr.size();
     return SIPO_OK;
 }
 
