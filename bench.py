@@ -40,8 +40,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=64)
-    ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--angles", type=int, default=360)
+    ap.add_argument("--workload", choices=["vol256", "vol512"], default="vol256",
+                    help="vol256: 256^3 x 360, ellipsoids, blur 1.5, Case 1; "
+                         "vol512: 512^3 x 720, lattice, blur (1, 1, 2), Case 2 cap 0.65")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=32, help="z slices in the bounded oracle sample")
     ap.add_argument("--ttk", action="store_true", help="also time a cold solve to relative KKT 1e-4")
@@ -186,19 +187,24 @@ def main():
     import paper_2604_08997_amd as sipo
     from sipo_inputs import ellipsoids_target, angles_uniform
 
-    n, na = args.n, args.angles
+    big = args.workload == "vol512"
+    n, na = (512, 720) if big else (256, 360)
+    sigma = (1.0, 1.0, 2.0) if big else (1.5, 1.5, 1.5)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    plan = sipo.Plan(n, list(angles_uniform(na)), nz=n, atten=1.0, sigma=(1.5, 1.5, 1.5), dtype=torch.float32,
-                     device=dev)
-    if args.probe:
-        return probe(args, plan, dev)
     if args.batch_only:
         print(json.dumps({"batched_vs_plain_time_to_1e-4": batch_vs_plain(args.batch, dev)}), flush=True)
         return 0
+    plan = sipo.Plan(n, list(angles_uniform(na)), nz=n, atten=1.0, sigma=sigma, dtype=torch.float32, device=dev)
+    if args.probe:
+        return probe(args, plan, dev)
     plan.autotune()
-    f = torch.as_tensor(ellipsoids_target(n, 3000), dtype=torch.float32, device=dev)
-    lp = sipo.LP.build(plan, f, sipo.CASE1, band_width=10.0, f_min=1.0)
+    if big:
+        f = torch.as_tensor(lattice_target(n, 4000), dtype=torch.float32, device=dev)
+        lp = sipo.LP.build(plan, f, sipo.CASE2, band_width=10.0, f_min=1.0, cap=0.65)
+    else:
+        f = torch.as_tensor(ellipsoids_target(n, 3000), dtype=torch.float32, device=dev)
+        lp = sipo.LP.build(plan, f, sipo.CASE1, band_width=10.0, f_min=1.0)
     print(f"[bench] workload built: {n}^3, {na} views, gel voxels {int((lp.labels == 2).sum())}, "
           f"band voxels {int((lp.labels == 1).sum())}, active rays {int(lp.act.sum())}", file=sys.stderr, flush=True)
 
@@ -226,7 +232,7 @@ def main():
     dom = max(("project", "backproject"), key=lambda k: ph_avg[k])
     achieved = flops / (ph_avg[dom] * 1e-3) / 1e12
     pair_bytes = 2.0 * 4.0 * (plan.n_angles * n * n + n * n * n)   # each operator reads one array, writes the other
-    traffic = recorded_traffic() if dom == "project" else None
+    traffic = recorded_traffic() if (dom == "project" and not big) else None
 
     ttk = None
     if args.ttk:
@@ -240,7 +246,7 @@ def main():
         print(f"[bench] time to 1e-4: {ttk}", file=sys.stderr, flush=True)
 
     bvp = batch_vs_plain(args.batch, dev) if args.batch > 0 else None
-    cpu = None if args.no_cpu_baseline else cpu_baseline(n, na, args.cpu_slices)
+    cpu = None if (args.no_cpu_baseline or big) else cpu_baseline(n, na, args.cpu_slices)
     line = {
         "metric": "PDHG iters/s",
         "value": round(ips, 3),
@@ -254,9 +260,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"3D {n}^3 vial, {na} views over 360 deg, {n}x{n} detector, 6 random ellipsoids "
-                               f"(seed 3000), band 10, blur sigma 1.5, Case 1 [0.9,1.0], restarted PDHG",
-                   "n": n, "views": na, "case": 1, "blur_sigma": 1.5},
+        "config": ({"workload": f"3D {n}^3 vial, {na} views over 360 deg, {n}x{n} detector, jittered lattice "
+                                f"(seed 4000), band 10, blur sigma (1,1,2), Case 2 cap 0.65, restarted PDHG",
+                    "n": n, "views": na, "case": 2, "blur_sigma": [1.0, 1.0, 2.0]} if big else
+                   {"workload": f"3D {n}^3 vial, {na} views over 360 deg, {n}x{n} detector, 6 random ellipsoids "
+                                f"(seed 3000), band 10, blur sigma 1.5, Case 1 [0.9,1.0], restarted PDHG",
+                    "n": n, "views": na, "case": 1, "blur_sigma": 1.5}),
         "a_plus_at_gbs": round(pair_bytes / ((t_p + t_bp) * 1e-3) / 1e9, 2),
         "phase_ms": {k: round(v, 4) for k, v in ph_avg.items()},
         "roofline": {"bound": "alu", "kernel": "project3d" if dom == "project" else "backproject3d",

@@ -109,11 +109,30 @@ def _ellipsoid_mask(P: np.ndarray, centre, axes, Rm) -> np.ndarray:
     return ((local / np.asarray(axes)[:, None]) ** 2).sum(axis=0) <= 1.0
 
 
-def _points3d(n: int, nz: int):
+def _box(n: int, nz: int, lo, hi):
+    """Index ranges (z, y, x slices) of the voxel centres inside the box [lo, hi] (x, y, z order)."""
+    out = []
+    for m, l, h in ((nz, lo[2], hi[2]), (n, lo[1], hi[1]), (n, lo[0], hi[0])):
+        i0 = max(0, int(np.floor((l + 1.0) * m / 2.0 - 0.5)) - 1)
+        i1 = min(m, int(np.ceil((h + 1.0) * m / 2.0 - 0.5)) + 2)
+        out.append(slice(i0, max(i0, i1)))
+    return tuple(out)
+
+
+def _paint(inside: np.ndarray, n: int, nz: int, lo, hi, test) -> None:
+    """inside[box] |= test(P) for the voxel-centre points P (3 x m, x/y/z rows) of the box [lo, hi]."""
+    sz, sy, sx = _box(n, nz, lo, hi)
+    if sz.start >= sz.stop or sy.start >= sy.stop or sx.start >= sx.stop:
+        return
+    c, cz = _centres(n), _centres(nz)
+    Z, Y, X = np.meshgrid(cz[sz], c[sy], c[sx], indexing="ij")
+    P = np.stack([X.ravel(), Y.ravel(), Z.ravel()])
+    inside[sz, sy, sx] |= test(P).reshape(Z.shape)
+
+
+def _vial(n: int, nz: int) -> np.ndarray:
     c = _centres(n)
-    cz = _centres(nz)
-    Z, Y, X = np.meshgrid(cz, c, c, indexing="ij")
-    return X, Y, Z
+    return np.broadcast_to((c[None, :] ** 2 + c[:, None] ** 2) <= 1.0, (nz, n, n))
 
 
 def ellipsoids_target(n: int, seed: int, count: int = 6, nz: int | None = None) -> np.ndarray:
@@ -121,12 +140,11 @@ def ellipsoids_target(n: int, seed: int, count: int = 6, nz: int | None = None) 
 
     Centres uniform in the ball r < 0.7, semi-axes U[0.1, 0.3], uniformly
     random rotation (random unit quaternion), clipped to the vial cylinder.
+    Each ellipsoid is tested only inside its bounding box.
     """
     nz = n if nz is None else nz
     g = rng(seed)
-    X, Y, Z = _points3d(n, nz)
-    P = np.stack([X.ravel(), Y.ravel(), Z.ravel()])
-    inside = np.zeros(P.shape[1], dtype=bool)
+    inside = np.zeros((nz, n, n), dtype=bool)
     for _ in range(count):
         while True:
             c = g.uniform(-0.7, 0.7, size=3)
@@ -134,9 +152,10 @@ def ellipsoids_target(n: int, seed: int, count: int = 6, nz: int | None = None) 
                 break
         axes = g.uniform(0.1, 0.3, size=3)
         Rm = _rotation_from_quaternion(g.normal(size=4))
-        inside |= _ellipsoid_mask(P, c, axes, Rm)
-    inside &= (P[0] ** 2 + P[1] ** 2) <= 1.0
-    return inside.reshape(nz, n, n).astype(np.float64)
+        r = float(axes.max())
+        _paint(inside, n, nz, c - r, c + r, lambda P, c=c, axes=axes, Rm=Rm: _ellipsoid_mask(P, c, axes, Rm))
+    inside &= _vial(n, nz)
+    return inside.astype(np.float64)
 
 
 def lattice_target(n: int, seed: int, nz: int | None = None) -> np.ndarray:
@@ -144,25 +163,26 @@ def lattice_target(n: int, seed: int, nz: int | None = None) -> np.ndarray:
 
     3x3x3 node centres at {-0.4, 0, 0.4}^3 jittered by U[-0.04, 0.04]^3;
     nodes are ellipsoids with semi-axes U[0.06, 0.10] and random rotation;
-    54 cylinders of radius 0.04 join axis-adjacent nodes.
+    54 cylinders of radius 0.04 join axis-adjacent nodes.  Each primitive is
+    tested only inside its bounding box.
     """
     nz = n if nz is None else nz
     g = rng(seed)
-    X, Y, Z = _points3d(n, nz)
-    P = np.stack([X.ravel(), Y.ravel(), Z.ravel()])
     grid = np.array([-0.4, 0.0, 0.4])
     nodes = np.zeros((3, 3, 3, 3))
     for i in range(3):
         for j in range(3):
             for k in range(3):
                 nodes[i, j, k] = np.array([grid[i], grid[j], grid[k]]) + g.uniform(-0.04, 0.04, 3)
-    inside = np.zeros(P.shape[1], dtype=bool)
+    inside = np.zeros((nz, n, n), dtype=bool)
     for i in range(3):
         for j in range(3):
             for k in range(3):
                 axes = g.uniform(0.06, 0.10, size=3)
                 Rm = _rotation_from_quaternion(g.normal(size=4))
-                inside |= _ellipsoid_mask(P, nodes[i, j, k], axes, Rm)
+                c = nodes[i, j, k]
+                r = float(axes.max())
+                _paint(inside, n, nz, c - r, c + r, lambda P, c=c, axes=axes, Rm=Rm: _ellipsoid_mask(P, c, axes, Rm))
     rad = 0.04
     for i in range(3):
         for j in range(3):
@@ -174,11 +194,15 @@ def lattice_target(n: int, seed: int, nz: int | None = None) -> np.ndarray:
                     p0, p1 = nodes[i, j, k], nodes[a, b, c]
                     seg = p1 - p0
                     L2 = seg @ seg
-                    t = np.clip(((P - p0[:, None]) * seg[:, None]).sum(0) / L2, 0.0, 1.0)
-                    closest = p0[:, None] + t[None] * seg[:, None]
-                    inside |= ((P - closest) ** 2).sum(0) <= rad * rad
-    inside &= (P[0] ** 2 + P[1] ** 2) <= 1.0
-    return inside.reshape(nz, n, n).astype(np.float64)
+
+                    def cyl(P, p0=p0, seg=seg, L2=L2):
+                        t = np.clip(((P - p0[:, None]) * seg[:, None]).sum(0) / L2, 0.0, 1.0)
+                        closest = p0[:, None] + t[None] * seg[:, None]
+                        return ((P - closest) ** 2).sum(0) <= rad * rad
+
+                    _paint(inside, n, nz, np.minimum(p0, p1) - rad, np.maximum(p0, p1) + rad, cyl)
+    inside &= _vial(n, nz)
+    return inside.astype(np.float64)
 
 
 def uniform_field(shape, seed: int) -> np.ndarray:
