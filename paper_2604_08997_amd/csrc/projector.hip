@@ -424,7 +424,7 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int ZC, int NC, bool PAIR>
+template <int ZC, int NC, bool PAIR, bool SKIP>
 __global__ void __launch_bounds__(256) project3d_dma_kernel(
     const float *__restrict__ vol_t, float *__restrict__ sino_t, int n, int nz, int nb,
     const double2 *__restrict__ trig, const int *__restrict__ order, const int *__restrict__ partner,
@@ -520,6 +520,8 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
                 w[0] = hat * exp_neg<float>(atten, tq + rr);
                 if (PAIR) w[NR - 1] = hat * exp_neg<float>(atten, rr - tq);
                 const int jj = min(max(jj0 + q, 0), cr - 1);
+                // SKIP: lanes whose candidate lies outside their ray's reach issue no LDS reads
+                if (SKIP && !(hat > 0.f)) continue;
 #pragma unroll
                 for (int z4 = 0; z4 < Z4; ++z4) {
                     const float4 v = row[z4 * RS + jj];
@@ -707,6 +709,7 @@ int plan_build_batches(sipo_plan p, const double2 *trig) {
     p->p3d_pair = pair;
     p->n_walk = nw;
     p->p3d_zc = p->dtype == SIPO_F64 ? 16 : 32;
+    p->p3d_skip = false;
     p->blur_zc = 0;
     p->n_batches = (int)batches.size();
     p->p3d_ok = ok && p->p3d_nc > 0;
@@ -823,20 +826,25 @@ static void fp3d_nc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s)
                            p->d_batches, h, inv_ds, (T)p->atten);
 }
 
-template <int ZC, int NC>
-static void fp3d_dma_nc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+template <int ZC, int NC, bool PAIR, bool SKIP>
+static void fp3d_dma_go(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
     const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
     const dim3 grid((p->n_bins + kPB - 1) / kPB, p->n_batches, (p->nz + ZC - 1) / ZC);
-    if (p->p3d_pair)
-        hipLaunchKernelGGL((project3d_dma_kernel<ZC, NC, true>), grid, dim3(256), 0, s, (const float *)vol_t,
-                           (float *)sino_t, p->n, p->nz, p->n_bins, p->d_trig, p->d_angle_order, p->d_partner,
-                           p->d_batches, p->d_ranges, p->d_vial_rows, (const float4 *)p->d_zero, h, inv_ds,
-                           (float)p->atten);
-    else
-        hipLaunchKernelGGL((project3d_dma_kernel<ZC, NC, false>), grid, dim3(256), 0, s, (const float *)vol_t,
-                           (float *)sino_t, p->n, p->nz, p->n_bins, p->d_trig, p->d_angle_order, p->d_partner,
-                           p->d_batches, p->d_ranges, p->d_vial_rows, (const float4 *)p->d_zero, h, inv_ds,
-                           (float)p->atten);
+    hipLaunchKernelGGL((project3d_dma_kernel<ZC, NC, PAIR, SKIP>), grid, dim3(256), 0, s, (const float *)vol_t,
+                       (float *)sino_t, p->n, p->nz, p->n_bins, p->d_trig, p->d_angle_order, p->d_partner,
+                       p->d_batches, p->d_ranges, p->d_vial_rows, (const float4 *)p->d_zero, h, inv_ds,
+                       (float)p->atten);
+}
+
+template <int ZC, int NC>
+static void fp3d_dma_nc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+    if (p->p3d_pair) {
+        if (p->p3d_skip) fp3d_dma_go<ZC, NC, true, true>(p, vol_t, sino_t, s);
+        else fp3d_dma_go<ZC, NC, true, false>(p, vol_t, sino_t, s);
+    } else {
+        if (p->p3d_skip) fp3d_dma_go<ZC, NC, false, true>(p, vol_t, sino_t, s);
+        else fp3d_dma_go<ZC, NC, false, false>(p, vol_t, sino_t, s);
+    }
 }
 
 template <typename T, int ZC>

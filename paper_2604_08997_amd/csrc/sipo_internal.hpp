@@ -79,6 +79,7 @@ struct sipo_plan_s {
     int p3d_zc;             // slices per projector thread (set by defaults or sipo_plan_autotune)
     bool p3d_dma_ok;        // the asynchronous-staging projector applies (FP32, nz % 4 == 0, ranges fit)
     bool p3d_dma;           // use it (default when it applies; sipo_plan_autotune may switch)
+    bool p3d_skip;          // asynchronous projector: lanes skip candidates outside their ray's reach
     int2 *d_ranges;         // [n_batches][bin groups][chunks of kDmaCM steps]: staged cross range (j0, count)
     int2 *d_vial_rows;      // [n]: first and last index along a grid line inside the vial
     void *d_zero;           // 256 zero bytes (source of empty staging slots)

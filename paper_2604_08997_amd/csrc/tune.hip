@@ -48,17 +48,20 @@ extern "C" int sipo_plan_autotune(sipo_plan p, void *stream) {
     if (p->fast3d()) {
         std::vector<int> zcs = p->dtype == SIPO_F64 ? std::vector<int>{8, 16} : std::vector<int>{16, 32};
         int best = p->p3d_zc;
-        bool best_dma = p->p3d_dma;
+        bool best_dma = p->p3d_dma, best_skip = p->p3d_skip;
         float tbest = 1e30f;
         for (int dma = 0; dma <= (p->p3d_dma_ok ? 1 : 0); ++dma)
-            for (int zc : zcs) {
-                p->p3d_zc = zc;
-                p->p3d_dma = dma != 0;
-                const float t = time_ms([&] { return launch_project_t(p, va, sa, s); }, kReps, s);
-                if (t >= 0.f && t < tbest) { tbest = t; best = zc; best_dma = dma != 0; }
-            }
+            for (int skip = 0; skip <= dma; ++skip)
+                for (int zc : zcs) {
+                    p->p3d_zc = zc;
+                    p->p3d_dma = dma != 0;
+                    p->p3d_skip = skip != 0;
+                    const float t = time_ms([&] { return launch_project_t(p, va, sa, s); }, kReps, s);
+                    if (t >= 0.f && t < tbest) { tbest = t; best = zc; best_dma = dma != 0; best_skip = skip != 0; }
+                }
         p->p3d_zc = best;
         p->p3d_dma = best_dma;
+        p->p3d_skip = best_skip;
     }
     if (p->has_psf && p->nz > 1) {
         int best = 0;
