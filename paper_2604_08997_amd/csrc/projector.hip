@@ -436,7 +436,11 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     __shared__ float4 bufB[SLOTS];
     const int tid = threadIdx.x;
     const int4 bt = batches[blockIdx.y];
-    const int tb = tid % kPB, tk = tid / kPB;
+    // lane -> (bin, view): each wave holds two neighbouring views; a 16-lane quarter holds the same
+    // 8 bins of both, whose candidate voxels nearly coincide, so one quarter's LDS reads stay
+    // within about one pass of the 64 banks
+    const int lane = tid & 63, wv = tid >> 6;
+    const int tb = (lane & 7) | ((lane >> 4) << 3), tk = 2 * wv + ((lane >> 3) & 1);
     const int b = blockIdx.x * kPB + tb;
     const int z0 = blockIdx.z * ZC;
     const bool xmajor = bt.z != 0;
