@@ -13,6 +13,8 @@
  *   sipo_regions       gel / band / exterior labels    (Sec. 2.2, Fig. 2a)
  *   sipo_active_rays   active-ray mask                 (Sec. 2.2, Fig. 2b)
  *   sipo_pdhg_solve    the LP of Eq. 19-24 / 32-37 / 40-45 by PDHG (Sec. 2.8)
+ *   sipo_response      material response M and its inverse (Eq. 4-5)
+ *   sipo_evaluate      scale-invariant metrics and post-scaling (Eq. 6-8, 25-28, 46)
  *
  * Conventions shared by every call
  *   - Array pointers named "device" are HIP device pointers owned by the
@@ -132,6 +134,45 @@ int sipo_regions(sipo_plan plan, const void *f_target, double band_width, uint8_
  * dtype used for P f_target (left holding it); act: device uint8 sinogram. */
 int sipo_active_rays(sipo_plan plan, const void *f_target, void *scratch_sino, uint8_t *act,
                      void *stream);
+
+/* ------------------------------------------------- response and metrics --- */
+/* Richards material response (Eq. 4): M(f) = alpha + (k - alpha) / [1 + exp(-beta (f - f0))]^(1/gamma).
+ * The paper prints no resin constants; callers supply them. */
+typedef struct {
+    double alpha, k, beta, gamma, f0;
+} sipo_resin;
+
+/* out = M(in) (inverse == 0) or out = M^-1(in) (inverse != 0, Eq. 5) for every
+ * voxel of a plan-shaped volume.  in, out: device volumes (may be equal).
+ * M^-1 is defined for alpha < m < k; other inputs give NaN.  Errors: resin with
+ * k == alpha, beta == 0 or gamma <= 0 (SIPO_E_INVALID). */
+int sipo_response(sipo_plan plan, const sipo_resin *resin, const void *in, void *out, int inverse, void *stream);
+
+/* Metrics of a normalised dose D = A^T y (Sec. 2.5, 2.6.3, Sec. 3):
+ *   DTVR = max_gel(D / f~_T) / min_gel(D / f~_T)          (Eq. 6, 8)
+ *   DSR  = max_band D / min_gel(D / f~_T)                 (Eq. 8)
+ *   PSR_f = min_gel D / max_band D                        (Eq. 46)
+ *   alpha_f = <D, f_T>_w / <D, D>_w over the gel, f_T = f_crit f~_T   (Eq. 27)
+ * and, when a resin is given, the response-domain calibration
+ *   alpha_m = argmin_{alpha > 0} sum_gel w (M(alpha D) - m_T)^2      (Eq. 28)
+ * with PSR_m (Eq. 46) and DTVR_m = max_gel(m/m_T) / min_gel(m/m_T) at m = M(alpha_m D).
+ * Empty band: DSR, PSR_f and PSR_m are NaN.  min_gel(D / f~_T) = 0: DTVR and DSR are +inf. */
+typedef struct {
+    double dtvr, dsr, psr_f;
+    double gel_ratio_min, gel_ratio_max, band_max, gel_min;
+    double alpha_f;
+    double alpha_m, psr_m, dtvr_m;   /* NaN without a resin */
+    int64_t n_gel, n_band;
+} sipo_metrics;
+
+/* dose: device volume (plan dtype); labels: device uint8 volume; f_target_norm:
+ * device volume of f~_T or NULL (then f_t_scalar everywhere on the gel); f_crit:
+ * physical critical dose (f_T = f_crit f~_T); weights: device volume or NULL (1);
+ * resin, m_target (device volume or NULL -> m_t_scalar): response-domain terms,
+ * skipped when resin is NULL.  Uses the plan's scratch; synchronous on stream. */
+int sipo_evaluate(sipo_plan plan, const void *dose, const uint8_t *labels, const void *f_target_norm,
+                  double f_t_scalar, double f_crit, const void *weights, const sipo_resin *resin,
+                  const void *m_target, double m_t_scalar, sipo_metrics *out, void *stream);
 
 /* ------------------------------------------------------------------ LP --- */
 /* The unified LP (Eq. 19-24; Case 1 Eq. 32-37; Case 2 Eq. 40-45):

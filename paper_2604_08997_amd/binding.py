@@ -70,6 +70,21 @@ class PdhgResult(C.Structure):
         return d
 
 
+class Resin(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("k", C.c_double), ("beta", C.c_double), ("gamma", C.c_double),
+                ("f0", C.c_double)]
+
+
+class Metrics(C.Structure):
+    _fields_ = [("dtvr", C.c_double), ("dsr", C.c_double), ("psr_f", C.c_double),
+                ("gel_ratio_min", C.c_double), ("gel_ratio_max", C.c_double), ("band_max", C.c_double),
+                ("gel_min", C.c_double), ("alpha_f", C.c_double), ("alpha_m", C.c_double), ("psr_m", C.c_double),
+                ("dtvr_m", C.c_double), ("n_gel", C.c_int64), ("n_band", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # name -> (restype, argtypes): every symbol declared in include/sipo.h
 SIGNATURES = {
     "sipo_plan_create": (C.c_int, [C.POINTER(Geometry), C.POINTER(Psf), C.c_int, C.POINTER(C.c_void_p)]),
@@ -83,6 +98,9 @@ SIGNATURES = {
     "sipo_pdhg_workspace_size": (C.c_size_t, [C.POINTER(Problem), C.c_int32, C.POINTER(PdhgOptions)]),
     "sipo_pdhg_solve": (C.c_int, [C.POINTER(Problem), C.c_int32, C.POINTER(PdhgOptions), C.c_void_p, C.c_size_t,
                                   C.POINTER(PdhgResult), C.c_void_p]),
+    "sipo_response": (C.c_int, [C.c_void_p, C.POINTER(Resin), C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "sipo_evaluate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
+                                C.POINTER(Resin), C.c_void_p, C.c_double, C.POINTER(Metrics), C.c_void_p]),
     "sipo_last_error": (C.c_char_p, []),
     "sipo_version": (C.c_char_p, []),
 }
@@ -236,6 +254,30 @@ class Plan:
         bw = -1.0 if band_width is None or math.isinf(band_width) else float(band_width)
         _check(lib().sipo_regions(self.handle, _ptr(f_target), bw, _ptr(lab), _ptr(scratch), _stream()))
         return lab
+
+    def response(self, vol, resin, inverse=False, out=None):
+        """M(vol) (Eq. 4) or M^-1(vol) (Eq. 5) with resin = (alpha, k, beta, gamma, f0)."""
+        _require(vol, "vol", self.vol_shape, self.dtype, self.device)
+        out = self.empty_vol() if out is None else out
+        _require(out, "out", self.vol_shape, self.dtype, self.device)
+        r = Resin(*[float(v) for v in resin])
+        _check(lib().sipo_response(self.handle, C.byref(r), _ptr(vol), _ptr(out), int(bool(inverse)), _stream()))
+        return out
+
+    def evaluate(self, dose, labels, f_target_norm=None, f_t_scalar=1.0, f_crit=1.0, weights=None, resin=None,
+                 m_target=None, m_t_scalar=float("nan")):
+        """Scale-invariant metrics and post-scaling factors of a normalised dose (Eq. 6-8, 25-28, 46)."""
+        _require(dose, "dose", self.vol_shape, self.dtype, self.device)
+        _require(labels, "labels", self.vol_shape, torch.uint8, self.device)
+        for name, t in (("f_target_norm", f_target_norm), ("weights", weights), ("m_target", m_target)):
+            if t is not None:
+                _require(t, name, self.vol_shape, self.dtype, self.device)
+        r = Resin(*[float(v) for v in resin]) if resin is not None else None
+        m = Metrics()
+        _check(lib().sipo_evaluate(self.handle, _ptr(dose), _ptr(labels), _ptr(f_target_norm), float(f_t_scalar),
+                                   float(f_crit), _ptr(weights), C.byref(r) if r is not None else None,
+                                   _ptr(m_target), float(m_t_scalar), C.byref(m), _stream()))
+        return m.as_dict()
 
     def active_rays(self, f_target, scratch=None):
         _require(f_target, "f_target", self.vol_shape, self.dtype, self.device)

@@ -121,3 +121,24 @@ def test_richards_inverse_round_trip():
     p = dict(a=0.05, k=0.95, beta=8.0, gamma=0.7, f0=0.5)
     m = np.linspace(0.1, 0.9, 17)
     np.testing.assert_allclose(metrics.richards(metrics.richards_inverse(m, **p), **p), m, rtol=1e-12)
+
+
+def test_alpha_m_recovers_the_generating_scale_and_beats_a_dense_scan():
+    # Eq. 28: when m_T is exactly M(alpha0 f~*) on the gel, the calibration returns alpha0
+    resin = (0.02, 0.98, 6.0, 0.8, 1.1)
+    rng = np.random.default_rng(11)
+    lab = rng.integers(0, 3, size=(2, 6, 6)).astype(np.uint8)
+    lab[0, 0, 0] = 2
+    fn = rng.uniform(0.8, 1.3, size=lab.shape)
+    alpha0 = 1.37
+    mt = metrics.richards(alpha0 * fn, *resin)
+    assert metrics.alpha_m(fn, mt, lab, resin) == pytest.approx(alpha0, rel=1e-8)
+    # perturbed targets: no alpha on a dense scan does better (brute force)
+    mt2 = mt * rng.uniform(0.95, 1.05, size=mt.shape)
+    w = rng.uniform(0.2, 1.0, size=lab.shape)
+    am = metrics.alpha_m(fn, mt2, lab, resin, w)
+    f_best = metrics.phi_m(am, fn, mt2, lab, resin, w)
+    scan = [metrics.phi_m(a, fn, mt2, lab, resin, w) for a in np.linspace(0.5, 3.0, 5001)]
+    assert f_best <= min(scan) + 1e-12
+    # DTVR_m of the generating dose is exactly 1
+    assert metrics.dtvr_m(alpha0 * fn, mt, lab, resin) == pytest.approx(1.0, abs=1e-12)
