@@ -8,3 +8,4 @@ from .binding import (Plan, SipoError, lib, version, gaussian_taps, LIB_PATH,  #
                       PLAIN, RESTARTED, OPTIMAL, PRIMAL_INFEASIBLE, ITER_LIMIT, NUMERICAL, STATUS_NAMES,
                       LP, GENERAL, CASE1, CASE2, pdhg_options, solve)
 from .autograd import SipoDose, dose  # noqa: F401,E402
+from . import workflow  # noqa: F401,E402

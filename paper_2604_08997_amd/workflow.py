@@ -1,0 +1,124 @@
+"""Two-stage Case 1 -> Case 2 design and trade-off sweeps (Sec. 3.2) as batched GPU solves.
+
+Host-side orchestration only: every LP is solved by ``sipo_pdhg_solve`` (all
+instances of a stage in one batched call), and regions, active rays, doses and
+metrics come from the library's kernels.
+
+Units.  All stages use the normalisation of the general LP, f_crit = min_gel
+f_T, so a binary target has gel lower bound L = 1 (Case 1 with window
+[tol_lo, tol_hi] f_T has the same L and upper bound tol_hi / tol_lo).  Case 2
+at band threshold ``cap`` (f_crit = cap min f_T, band cap 1; Eq. 39-41) is the
+same LP as "band cap h = cap, f~_T = 1" after the joint rescaling of f~_T and
+the band cap by cap (Sec. 2.6.2): v* is unchanged and y is cap times larger.
+Stage 2 is posed that way, so the stage-1 projections are a feasible starting
+point for it without any rescaling.
+
+The h_min LP (general LP with w = (1, 0)) gives the smallest band threshold for
+which Case 2 is feasible at all; it needs no stage-1 result and runs in the
+stage-1 batch.
+"""
+from __future__ import annotations
+
+import math
+
+from . import binding as _b
+
+
+def _f_min(plan, f_target, labels):
+    gel = labels == 2
+    return float(f_target[gel].min().item()) if bool(gel.any()) else 1.0
+
+
+def h_min_lp(plan, labels, act, f_min):
+    """General LP with w = (1, 0): min u s.t. D <= u on band, D >= 1 on gel (v free, unpriced)."""
+    return _b.LP(plan, labels, act, _b.GENERAL, 1, 1, 1.0, 0.0, 1.0, 1.0, 1.0, f_crit=f_min)
+
+
+def case2_lp(plan, labels, act, f_min, cap):
+    """Case 2 (Eq. 40-45) at band threshold ``cap`` in general units: band cap h = cap, f~_T = 1, w = (0, 1)."""
+    return _b.LP(plan, labels, act, _b.CASE2, 0, 1, 0.0, 1.0, float(cap), 1.0, 1.0, f_crit=f_min)
+
+
+def transfer_cap(u1, margin):
+    """Band threshold handed to stage 2: the stage-1 bound widened by a relative margin."""
+    return float(u1) * (1.0 + float(margin))
+
+
+def _metrics(lp, f_min):
+    if lp.dose is None:
+        return None
+    return lp.plan.evaluate(lp.dose, lp.labels, f_t_scalar=1.0, f_crit=f_min)
+
+
+def two_stage(items, band_width=10.0, tol_lo=0.9, tol_hi=1.0, margin=1e-3, opts=None, warm=True,
+              with_h_min=True, workspace=None):
+    """Run the two-stage workflow on every (plan, f_target) in ``items``.
+
+    Stage 1: Case 1 on the window [tol_lo, tol_hi] f_T for every item (and the
+    h_min LP when ``with_h_min``), one batched solve.  Stage 2: Case 2 at
+    cap = u1 (1 + margin) for every item whose stage 1 is optimal, one batched
+    solve, warm-started from the stage-1 projections (feasible for stage 2,
+    with v = tol_hi / tol_lo) when ``warm``.
+
+    Returns one dict per item: ``stage1`` / ``stage2`` / ``h_min`` solver
+    results, ``u1``, ``cap``, ``f_min``, ``metrics1`` / ``metrics2`` (scale-
+    invariant metrics of each stage's dose in general units) and the LP
+    objects ``lp1`` / ``lp2`` holding y, duals and doses.
+    """
+    opts = _b.pdhg_options() if opts is None else opts
+    lp1s, hms, fmins = [], [], []
+    for plan, f in items:
+        lp1 = _b.LP.build(plan, f, _b.CASE1, band_width=band_width, tol_lo=tol_lo, tol_hi=tol_hi)
+        fmin = lp1.f_crit / tol_lo
+        lp1s.append(lp1)
+        fmins.append(fmin)
+        if with_h_min:
+            hms.append(h_min_lp(plan, lp1.labels, lp1.act, fmin))
+    res_a = _b.solve(lp1s + hms, opts, workspace=workspace)
+    res1, resh = res_a[:len(lp1s)], res_a[len(lp1s):]
+    out = []
+    lp2s = []
+    for k, (lp1, r1, fmin) in enumerate(zip(lp1s, res1, fmins)):
+        d = {"stage1": r1, "lp1": lp1, "f_min": fmin, "u1": math.nan, "cap": math.nan, "stage2": None,
+             "lp2": None, "h_min": resh[k]["u"] if with_h_min and resh[k]["status_name"] == "optimal" else math.nan,
+             "h_min_result": resh[k] if with_h_min else None, "metrics1": _metrics(lp1, fmin), "metrics2": None}
+        if r1["status_name"] == "optimal":
+            d["u1"] = r1["u"]
+            d["cap"] = transfer_cap(r1["u"], margin)
+            lp2 = case2_lp(lp1.plan, lp1.labels, lp1.act, fmin, d["cap"])
+            if warm:
+                lp2.y.copy_(lp1.y)
+                lp2.v0 = tol_hi / tol_lo
+            d["lp2"] = lp2
+            lp2s.append((k, lp2))
+        out.append(d)
+    if lp2s:
+        res_b = _b.solve([lp for _, lp in lp2s], opts, workspace=workspace)
+        for (k, lp2), r2 in zip(lp2s, res_b):
+            out[k]["stage2"] = r2
+            out[k]["metrics2"] = _metrics(lp2, out[k]["f_min"])
+    return out
+
+
+def sweep(plan, f_target, weights, band_widths, opts=None, f_min=None, workspace=None):
+    """General LP over every (w1, w2) in ``weights`` and band width in ``band_widths`` as one batched solve.
+
+    ``math.inf`` (or None) in ``band_widths`` is the band-free configuration
+    (every non-gel vial voxel is band, Sec. 3.2).  Region labels are computed
+    once per band width and the active rays once.  Returns a list of dicts
+    (band width major, weight pair minor) with the solver ``result``, the
+    ``metrics`` of the dose and the ``lp`` object.
+    """
+    opts = _b.pdhg_options() if opts is None else opts
+    act = plan.active_rays(f_target)
+    lps, keys = [], []
+    for bw in band_widths:
+        labels = plan.regions(f_target, bw)
+        fmin = _f_min(plan, f_target, labels) if f_min is None else float(f_min)
+        for w1, w2 in weights:
+            lps.append(_b.LP(plan, labels, act, _b.GENERAL, 1, 1, float(w1), float(w2), 1.0, 1.0, 1.0,
+                             f_crit=fmin))
+            keys.append((math.inf if bw is None else bw, float(w1), float(w2), fmin))
+    res = _b.solve(lps, opts, workspace=workspace)
+    return [{"band_width": bw, "w1": w1, "w2": w2, "result": r, "lp": lp, "metrics": _metrics(lp, fmin)}
+            for (bw, w1, w2, fmin), r, lp in zip(keys, res, lps)]

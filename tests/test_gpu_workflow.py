@@ -1,0 +1,127 @@
+"""Two-stage Case 1 -> Case 2 workflow, h_min and trade-off sweeps on the GPU (Sec. 3.2).
+
+Every stage is a batched ``sipo_pdhg_solve``; results are checked against the
+oracle's exact LP solves (HiGHS) at the bounds the GPU stages hand over.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lp as olp, workflow as owf, blur as oblur
+from oracle.geometry import make_geometry
+from oracle.projector import Projector
+from sipo_inputs import ellipses_target, ellipsoids_target, angles_uniform
+
+pytestmark = pytest.mark.gpu
+
+# (n, views, seed): uneven grids and view counts, one batch
+SPECS = [(20, 16, 41), (28, 24, 42), (24, 15, 43)]
+BAND = 3.0
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def items(dtype, specs=SPECS):
+    import paper_2604_08997_amd as sipo
+    out, orc = [], []
+    for n, na, seed in specs:
+        f = ellipses_target(n, seed)
+        plan = sipo.Plan(n, list(angles_uniform(na)), dtype=dtype, device=dev())
+        out.append((plan, torch.as_tensor(f, dtype=dtype, device=dev())))
+        orc.append((Projector(make_geometry(n, angles_uniform(na), atten=1.0)), f))
+    return out, orc
+
+
+def close(a, b, rel):
+    return abs(a - b) <= rel * (1.0 + abs(b))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_two_stage_matches_exact_stages(dtype):
+    import paper_2604_08997_amd as sipo
+    from paper_2604_08997_amd import workflow
+    its, orc = items(dtype)
+    tol = 1e-6 if dtype == torch.float64 else 2e-5
+    res = workflow.two_stage(its, band_width=BAND, margin=1e-3,
+                             opts=sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=100000, tol=tol))
+    for d, (P, f) in zip(res, orc):
+        ref = owf.two_stage(P, f, band_width=BAND, margin=1e-3)
+        assert d["stage1"]["status_name"] == "optimal", d["stage1"]
+        assert close(d["u1"], ref.u1, 1e-4), (d["u1"], ref.u1)
+        assert close(d["h_min"], owf.h_min(P, f, band_width=BAND), 1e-4)
+        assert d["h_min"] <= d["u1"] * (1 + 1e-4)
+        # stage 2 against the exact Case-2 optimum at the cap the GPU handed over
+        assert d["stage2"]["status_name"] == "optimal", d["stage2"]
+        ex = olp.solve_highs(owf.case2_in_general_units(P, f, d["cap"], band_width=BAND))
+        assert close(d["stage2"]["v"], ex.v, 1e-4), (d["stage2"]["v"], ex.v)
+        assert d["stage2"]["v"] <= (1.0 / 0.9) * (1 + 1e-4)
+        # separation kept: stage-2 PSR_f is at least 1 / cap, stage-1 PSR_f is 1 / u1 (Eq. 46)
+        m1, m2 = d["metrics1"], d["metrics2"]
+        assert m2["psr_f"] >= (1.0 / d["cap"]) * (1 - 5e-4)
+        assert close(m1["psr_f"], 1.0 / d["u1"], 5e-4)
+        # stage 2 is at least as uniform on the gel as stage 1 (it minimises exactly that ratio)
+        assert m2["dtvr"] <= m1["dtvr"] * (1 + 5e-4)
+
+
+def test_two_stage_warm_and_cold_agree():
+    import paper_2604_08997_amd as sipo
+    from paper_2604_08997_amd import workflow
+    its, _ = items(torch.float64, SPECS[:2])
+    opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=100000, tol=1e-6)
+    warm = workflow.two_stage(its, band_width=BAND, opts=opts, warm=True, with_h_min=False)
+    cold = workflow.two_stage(its, band_width=BAND, opts=opts, warm=False, with_h_min=False)
+    for a, b in zip(warm, cold):
+        assert a["cap"] == b["cap"]
+        assert a["stage2"]["status_name"] == b["stage2"]["status_name"] == "optimal"
+        assert close(a["stage2"]["v"], b["stage2"]["v"], 1e-5)
+        assert math.isnan(a["h_min"]) and a["h_min_result"] is None
+
+
+def test_two_stage_3d_with_blur():
+    import paper_2604_08997_amd as sipo
+    from paper_2604_08997_amd import workflow
+    n, na, sigma = 16, 12, (1.0, 1.0, 1.0)
+    f = ellipsoids_target(n, 5, count=2)
+    plan = sipo.Plan(n, list(angles_uniform(na)), nz=f.shape[0], sigma=sigma, dtype=torch.float64, device=dev())
+    res = workflow.two_stage([(plan, torch.as_tensor(f, device=dev()))], band_width=2.0,
+                             opts=sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=150000, tol=1e-5))[0]
+    P = Projector(make_geometry(n, angles_uniform(na), nz=f.shape[0], atten=1.0))
+    taps = oblur.psf_taps(sigma)
+    ref = owf.two_stage(P, f, taps=taps, band_width=2.0, margin=1e-3)
+    assert res["stage1"]["status_name"] == "optimal" and res["stage2"]["status_name"] == "optimal"
+    assert close(res["u1"], ref.u1, 1e-4)
+    assert close(res["h_min"], owf.h_min(P, f, taps=taps, band_width=2.0), 1e-4)
+    ex = olp.solve_highs(owf.case2_in_general_units(P, f, res["cap"], taps=taps, band_width=2.0))
+    assert close(res["stage2"]["v"], ex.v, 1e-4)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_sweep_matches_exact_general_lps(dtype):
+    import paper_2604_08997_amd as sipo
+    from paper_2604_08997_amd import workflow
+    n, na, seed = 24, 20, 44
+    f = ellipses_target(n, seed)
+    plan = sipo.Plan(n, list(angles_uniform(na)), dtype=dtype, device=dev())
+    weights = [(0.25, 1.0), (1.0, 1.0), (4.0, 1.0)]
+    bands = [2.0, 4.0, math.inf]
+    tol = 1e-6 if dtype == torch.float64 else 2e-5
+    out = workflow.sweep(plan, torch.as_tensor(f, dtype=dtype, device=dev()), weights, bands,
+                         opts=sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=100000, tol=tol))
+    P = Projector(make_geometry(n, angles_uniform(na), atten=1.0))
+    ref = owf.sweep(P, f, weights, bands)
+    assert [(d["band_width"], d["w1"], d["w2"]) for d in out] == [(r[0], r[1], r[2]) for r in ref]
+    for d, (bw, w1, w2, op, rs) in zip(out, ref):
+        np.testing.assert_array_equal(d["lp"].labels.cpu().numpy(), op.labels)
+        assert d["result"]["status_name"] == "optimal", (bw, w1, d["result"])
+        assert close(d["result"]["primal_obj"], rs.objective, 1e-4), (bw, w1, d["result"]["primal_obj"], rs.objective)
+    # weighted-sum monotonicity on the GPU optima
+    for k in range(len(bands)):
+        row = out[k * len(weights):(k + 1) * len(weights)]
+        us = [d["result"]["u"] for d in row]
+        vs = [d["result"]["v"] for d in row]
+        assert all(us[j + 1] <= us[j] * (1 + 1e-3) for j in range(len(us) - 1)), us
+        assert all(vs[j + 1] >= vs[j] * (1 - 1e-3) for j in range(len(vs) - 1)), vs
