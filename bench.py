@@ -50,6 +50,12 @@ def parse():
                     help="instances of the uneven 2D batch (seeds 2000..) for the batched-vs-plain time to 1e-4 "
                          "(0 = skip)")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched-vs-plain comparison")
+    ap.add_argument("--two-stage", type=int, default=0,
+                    help="run only the two-stage Case 1 -> Case 2 workflow on this many instances of the uneven "
+                         "2D batch, against Case 2 at the fixed cap 0.7 on the same targets")
+    ap.add_argument("--sweep", action="store_true",
+                    help="run only the (w1, w2) x band-width sweep of the general LP on the 256^2 x 360 slice, "
+                         "batched against one by one")
     ap.add_argument("--probe", choices=["project", "copy"], default=None,
                     help="run only a few launches of one kernel (for hardware counter runs) and exit")
     return ap.parse_args()
@@ -157,6 +163,102 @@ def batch_vs_plain(count, dev, max_iters=20000):
             "max_iters_used": max(r["iters"] for r in rb), "per_instance_results_identical": same}
 
 
+def two_stage_batch(count, dev, max_iters=20000):
+    """Two-stage workflow (Case 1, h_min, then Case 2 at the transferred bound; each stage one batched,
+    graph-captured solve) on the first ``count`` instances of the uneven 2D batch, against the one-stage
+    route: Case 2 at the fixed cap 0.7 on the same targets."""
+    import torch
+    import paper_2604_08997_amd as sipo
+    from paper_2604_08997_amd import workflow
+    from sipo_inputs import batch_instances, angles_uniform
+    from statistics import median
+    from collections import Counter
+    insts = batch_instances(count, 2000)
+    items = []
+    for b in insts:
+        plan = sipo.Plan(b.n, list(angles_uniform(b.n_angles)), dtype=torch.float32, device=dev)
+        items.append((plan, torch.as_tensor(b.target, dtype=torch.float32, device=dev)))
+    opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=max_iters, tol=1e-4, infeas_tol=1e-5, use_graph=1)
+    print(f"[bench] two-stage: {count} instances built", file=sys.stderr, flush=True)
+    times = {}
+    stream = torch.cuda.Stream()                      # graph capture needs a non-default stream
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        res = workflow.two_stage(items, band_width=10.0, margin=1e-3, opts=opts, times=times)
+    print(f"[bench] two-stage: stage 1 {times['stage1']:.2f} s, stage 2 {times.get('stage2', 0.0):.2f} s",
+          file=sys.stderr, flush=True)
+    lps = [sipo.LP.build(p, f, sipo.CASE2, band_width=10.0, cap=0.7) for p, f in items]
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        direct = sipo.solve(lps, opts, want_dose=False)
+        t_direct = time.perf_counter() - t0
+    print(f"[bench] one-stage Case 2 cap 0.7: {t_direct:.2f} s", file=sys.stderr, flush=True)
+    ok = [d for d in res if d["stage2"] is not None and d["stage2"]["status_name"] == "optimal"]
+    hm = [d["h_min"] for d in res if d["h_min"] == d["h_min"]]
+    return {
+        "instances": count, "seeds": f"2000-{2000 + count - 1}", "max_iters": max_iters, "margin": 1e-3,
+        "stage1_s": round(times["stage1"], 3), "stage2_s": round(times.get("stage2", 0.0), 3),
+        "stage1_status": dict(Counter(d["stage1"]["status_name"] for d in res)),
+        "h_min_status": dict(Counter(d["h_min_result"]["status_name"] for d in res)),
+        "stage2_status": dict(Counter(d["stage2"]["status_name"] for d in res if d["stage2"] is not None)),
+        "stage1_iters_max": max(d["stage1"]["iters"] for d in res),
+        "stage2_iters_max": max((d["stage2"]["iters"] for d in res if d["stage2"] is not None), default=0),
+        "median_h_min": round(median(hm), 5) if hm else None,
+        "median_u1": round(median(d["u1"] for d in ok), 5) if ok else None,
+        "median_psr_f": [round(median(d["metrics1"]["psr_f"] for d in ok), 5),
+                         round(median(d["metrics2"]["psr_f"] for d in ok), 5)] if ok else None,
+        "median_dtvr": [round(median(d["metrics1"]["dtvr"] for d in ok), 5),
+                        round(median(d["metrics2"]["dtvr"] for d in ok), 5)] if ok else None,
+        "cap_0.7_below_h_min": sum(1 for h in hm if h > 0.7),
+        "one_stage_cap_0.7_s": round(t_direct, 3),
+        "one_stage_cap_0.7_status": dict(Counter(r["status_name"] for r in direct)),
+    }
+
+
+def sweep_slice(dev, max_iters=20000):
+    """General LP over 4 weight pairs x 3 band widths (5, 10, band-free) on the 256^2 x 360 slice
+    (annulus + disks target, seed 1000): one batched, graph-captured solve against the same 12 solves one by one."""
+    import math
+    import torch
+    import paper_2604_08997_amd as sipo
+    from paper_2604_08997_amd import workflow
+    from sipo_inputs import annulus_disks_target, angles_uniform
+    from collections import Counter
+    n, na = 256, 360
+    plan = sipo.Plan(n, list(angles_uniform(na)), dtype=torch.float32, device=dev)
+    f = torch.as_tensor(annulus_disks_target(n, 1000), dtype=torch.float32, device=dev)
+    weights = [(0.25, 1.0), (1.0, 1.0), (4.0, 1.0), (16.0, 1.0)]
+    bands = [5.0, 10.0, math.inf]
+    opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=max_iters, tol=1e-4, infeas_tol=1e-5, use_graph=1)
+    stream = torch.cuda.Stream()                      # graph capture needs a non-default stream
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        out = workflow.sweep(plan, f, weights, bands, opts=opts)
+        t_batch = time.perf_counter() - t0
+        print(f"[bench] sweep of {len(out)}: batched {t_batch:.2f} s", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        single = []
+        for bw in bands:
+            for w in weights:
+                single.append(workflow.sweep(plan, f, [w], [bw], opts=opts)[0])
+                print(f"[bench] sweep one by one: band {bw} w {w} {single[-1]['result']['status_name']}",
+                      file=sys.stderr, flush=True)
+        t_plain = time.perf_counter() - t0
+    same = all(a["result"]["status"] == b["result"]["status"] and a["result"]["iters"] == b["result"]["iters"]
+               for a, b in zip(out, single))
+    return {"instances": len(out), "grid": "256^2 x 360 views, annulus + disks", "weights": weights,
+            "band_widths": ["inf" if math.isinf(b) else b for b in bands], "batched_s": round(t_batch, 3),
+            "plain_s": round(t_plain, 3), "speedup": round(t_plain / t_batch, 3),
+            "status": dict(Counter(d["result"]["status_name"] for d in out)),
+            "per_instance_results_identical": same,
+            "points": [{"band": "inf" if math.isinf(d["band_width"]) else d["band_width"], "w1": d["w1"],
+                        "u": round(d["result"]["u"], 5), "v": round(d["result"]["v"], 5),
+                        "psr_f": round(d["metrics"]["psr_f"], 5), "dtvr": round(d["metrics"]["dtvr"], 5),
+                        "iters": d["result"]["iters"]} for d in out]}
+
+
 def probe(args, plan, dev):
     """A few launches of one kernel, for hardware-counter runs (rocprofv3 --pmc)."""
     import torch
@@ -194,6 +296,12 @@ def main():
     torch.cuda.set_device(dev)
     if args.batch_only:
         print(json.dumps({"batched_vs_plain_time_to_1e-4": batch_vs_plain(args.batch, dev)}), flush=True)
+        return 0
+    if args.two_stage > 0:
+        print(json.dumps({"two_stage": two_stage_batch(args.two_stage, dev)}), flush=True)
+        return 0
+    if args.sweep:
+        print(json.dumps({"sweep": sweep_slice(dev)}), flush=True)
         return 0
     plan = sipo.Plan(n, list(angles_uniform(na)), nz=n, atten=1.0, sigma=sigma, dtype=torch.float32, device=dev)
     if args.probe:

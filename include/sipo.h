@@ -264,7 +264,14 @@ size_t sipo_pdhg_workspace_size(const sipo_problem *probs, int32_t n_probs,
  * array of n_probs.  An infeasible LP is not an error: its status is
  * SIPO_PRIMAL_INFEASIBLE and lam_up / lam_lo then hold the certificate
  * (a dual ray lambda >= 0 with P K z >= 0 on active rays and positive
- * dual objective; Supp. 6.1).  Returns after the stream has finished. */
+ * dual objective; Supp. 6.1).  In restarted mode the warm-start multipliers
+ * are tested first: if max(lambda, 0) on the regions already passes the
+ * Farkas test at infeas_tol (for example the multipliers of the h_min LP,
+ * min u s.t. D <= u on band and D >= L on gel, handed to a Case-2 LP whose
+ * band cap is below that minimum), the instance returns at once with status
+ * SIPO_PRIMAL_INFEASIBLE, iters = 0, that ray as its certificate and y and the
+ * scalars as passed in.  Zero multipliers (a cold start) never pass.
+ * Returns after the stream has finished. */
 int sipo_pdhg_solve(const sipo_problem *probs, int32_t n_probs, const sipo_pdhg_options *opts,
                     void *workspace, size_t ws_bytes, sipo_pdhg_result *results, void *stream);
 

@@ -690,7 +690,7 @@ class Solver {
         double omega = 1.0, m_anchor = 0, m_prev = 1e300, last_u = 0, last_v = 0, tau = 0, sigma = 0;
         int k_restart = 0, restarts = 0, iters = 0, status = SIPO_ITER_LIMIT;
         bool done = false;
-        int cert = -1;      // certificate pair when infeasible
+        int cert = -1;      // certificate when infeasible: 0 / 1 iterate pairs, 2 the warm-start multipliers
         Kkt kc;
     };
     const sipo_problem *probs_;
@@ -826,6 +826,12 @@ class Solver {
     void copyS(size_t dst, size_t src, bool flagged) {
         if (n_seg_s_) hipLaunchKernelGGL((k_copy<T>), gS(), dim3(kThreads), 0, s_, F(dst), (const T *)F(src), insts(),
                                          segS(), flagged ? 1 : 0);
+    }
+    int fill_vol(size_t dst) {   // zero a packed volume field over every instance
+        const long long n = L_.NV;
+        const int grid = (int)std::max<long long>(1, std::min<long long>((n + 255) / 256, 8192));
+        hipLaunchKernelGGL((k_fill<T>), dim3(grid), dim3(256), 0, s_, F(dst), n, (T)0);
+        return SIPO_OK;
     }
     int lambda_z(size_t lu, size_t ll, size_t z, bool flagged) {
         if (!n_seg_v_) return SIPO_OK;
@@ -1333,6 +1339,39 @@ int Solver<T>::run(sipo_pdhg_result *res) {
 
     const int check = hal ? std::max(1, o_.check_every) : o_.max_iters;
     const double itol = o_.infeas_tol > 0 ? o_.infeas_tol : 1e-6;
+    if (hal) {
+        // Warm-start multipliers that already form a Farkas ray (for instance those of a related
+        // LP whose optimum shows the requested bound unreachable) certify infeasibility before
+        // the first iteration: the candidate is max(lambda, 0) on the regions, put to the same
+        // test as the iterates' rays.  Cold starts (all-zero multipliers) drop out of that test
+        // after one reduction.  lut / llt hold zeros here and are rewritten by every iteration.
+        rc = fill_vol(L_.lut);
+        if (!rc) rc = fill_vol(L_.llt);
+        std::vector<char> ok0;
+        if (!rc) rc = farkas(L_.lu, L_.ll, L_.lut, L_.llt, itol, all, ok0);
+        if (rc) return rc;
+        std::vector<int> warm, rest;
+        for (int i : all) (ok0[i] ? warm : rest).push_back(i);
+        if (!warm.empty()) {
+            for (int i : warm) {
+                in_[i].status = SIPO_PRIMAL_INFEASIBLE;
+                in_[i].cert = 2;
+                in_[i].done = true;
+                hin_[i].sel = 0;
+            }
+            set_flags(warm);
+            rc = put_insts();
+            if (rc) return rc;
+            hipLaunchKernelGGL((k_certificate<T>), gV(), dim3(kThreads), 0, s_, F(L_.lu), F(L_.ll), (const T *)F(L_.lu),
+                               (const T *)F(L_.ll), (const T *)F(L_.lut), (const T *)F(L_.llt), (const T *)F(L_.lut),
+                               (const T *)F(L_.llt), (const uint8_t *)U8(L_.lab), insts(), segV());
+            rc = set_active(rest);
+            if (rc) return rc;
+        }
+        set_flags(rest);
+        rc = put_insts();
+        if (rc) return rc;
+    }
     int it = 0;
     bool have_t = false;
     while (it < o_.max_iters && !active_.empty()) {
@@ -1463,7 +1502,7 @@ int Solver<T>::run(sipo_pdhg_result *res) {
     if (rc) return rc;
     std::vector<int> from_t, certs, recheck;
     for (int i = 0; i < B_; ++i) {
-        if (hal && have_t) {
+        if (hal && have_t && in_[i].cert != 2) {
             from_t.push_back(i);
             if (in_[i].status == SIPO_PRIMAL_INFEASIBLE) certs.push_back(i);
         }
@@ -1471,7 +1510,7 @@ int Solver<T>::run(sipo_pdhg_result *res) {
     }
     std::vector<double> ru(B_), rv(B_);
     for (int i = 0; i < B_; ++i) {
-        const bool t = hal && have_t;
+        const bool t = hal && have_t && in_[i].cert != 2;
         ru[i] = t ? hsc_[i].ut_done : hsc_[i].u;
         rv[i] = t ? hsc_[i].vt_done : hsc_[i].v;
     }

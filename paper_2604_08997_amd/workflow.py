@@ -20,6 +20,7 @@ stage-1 batch.
 from __future__ import annotations
 
 import math
+import time
 
 from . import binding as _b
 
@@ -51,7 +52,7 @@ def _metrics(lp, f_min):
 
 
 def two_stage(items, band_width=10.0, tol_lo=0.9, tol_hi=1.0, margin=1e-3, opts=None, warm=True,
-              with_h_min=True, workspace=None):
+              with_h_min=True, workspace=None, times=None):
     """Run the two-stage workflow on every (plan, f_target) in ``items``.
 
     Stage 1: Case 1 on the window [tol_lo, tol_hi] f_T for every item (and the
@@ -63,7 +64,8 @@ def two_stage(items, band_width=10.0, tol_lo=0.9, tol_hi=1.0, margin=1e-3, opts=
     Returns one dict per item: ``stage1`` / ``stage2`` / ``h_min`` solver
     results, ``u1``, ``cap``, ``f_min``, ``metrics1`` / ``metrics2`` (scale-
     invariant metrics of each stage's dose in general units) and the LP
-    objects ``lp1`` / ``lp2`` holding y, duals and doses.
+    objects ``lp1`` / ``lp2`` holding y, duals and doses.  ``times``, if a
+    dict, receives the wall-clock seconds of each stage's batched solve.
     """
     opts = _b.pdhg_options() if opts is None else opts
     lp1s, hms, fmins = [], [], []
@@ -74,7 +76,10 @@ def two_stage(items, band_width=10.0, tol_lo=0.9, tol_hi=1.0, margin=1e-3, opts=
         fmins.append(fmin)
         if with_h_min:
             hms.append(h_min_lp(plan, lp1.labels, lp1.act, fmin))
+    t0 = time.perf_counter()
     res_a = _b.solve(lp1s + hms, opts, workspace=workspace)
+    if times is not None:
+        times["stage1"] = time.perf_counter() - t0
     res1, resh = res_a[:len(lp1s)], res_a[len(lp1s):]
     out = []
     lp2s = []
@@ -93,7 +98,10 @@ def two_stage(items, band_width=10.0, tol_lo=0.9, tol_hi=1.0, margin=1e-3, opts=
             lp2s.append((k, lp2))
         out.append(d)
     if lp2s:
+        t0 = time.perf_counter()
         res_b = _b.solve([lp for _, lp in lp2s], opts, workspace=workspace)
+        if times is not None:
+            times["stage2"] = time.perf_counter() - t0
         for (k, lp2), r2 in zip(lp2s, res_b):
             out[k]["stage2"] = r2
             out[k]["metrics2"] = _metrics(lp2, out[k]["f_min"])
@@ -122,3 +130,47 @@ def sweep(plan, f_target, weights, band_widths, opts=None, f_min=None, workspace
     res = _b.solve(lps, opts, workspace=workspace)
     return [{"band_width": bw, "w1": w1, "w2": w2, "result": r, "lp": lp, "metrics": _metrics(lp, fmin)}
             for (bw, w1, w2, fmin), r, lp in zip(keys, res, lps)]
+
+
+def case2_screened(items, caps, band_width=10.0, opts=None, h_min_opts=None, workspace=None, times=None):
+    """Case 2 at given band thresholds, screened by the h_min LP.
+
+    ``caps[k]`` is item k's band threshold as a fraction of min gel f_T (the
+    paper's Case-2 parameter, Eq. 39).  Stage A solves the h_min LP of every
+    item in one batch (``h_min_opts``, default ``opts``).  Stage B solves every
+    Case 2 in one batch, posed in general units (band cap h = cap).  An item
+    whose cap lies below its h_min estimate starts from the h_min multipliers:
+    those form a Farkas ray for it (band multipliers summing to 1, gel lower
+    multipliers summing to h_min > cap), and the solver's own test accepts them
+    at iteration 0 when they are accurate to its infeas_tol.  Other items start
+    cold.  Returns one dict per item: ``h_min``, ``h_min_result``, ``result``,
+    ``screened`` (started from the h_min multipliers) and ``lp``.
+    """
+    opts = _b.pdhg_options() if opts is None else opts
+    h_min_opts = opts if h_min_opts is None else h_min_opts
+    hms, fmins = [], []
+    for plan, f in items:
+        labels = plan.regions(f, band_width)
+        act = plan.active_rays(f)
+        fmin = _f_min(plan, f, labels)
+        hms.append(h_min_lp(plan, labels, act, fmin))
+        fmins.append(fmin)
+    t0 = time.perf_counter()
+    rh = _b.solve(hms, h_min_opts, want_dose=False, workspace=workspace)
+    if times is not None:
+        times["h_min"] = time.perf_counter() - t0
+    lps, screened = [], []
+    for hm, r, fmin, cap in zip(hms, rh, fmins, caps):
+        lp = case2_lp(hm.plan, hm.labels, hm.act, fmin, cap)
+        below = r["status_name"] in ("optimal", "iter_limit") and float(cap) < r["u"]
+        if below:
+            lp.lam_up.copy_(hm.lam_up)
+            lp.lam_lo.copy_(hm.lam_lo)
+        lps.append(lp)
+        screened.append(below)
+    t0 = time.perf_counter()
+    res = _b.solve(lps, opts, workspace=workspace)
+    if times is not None:
+        times["case2"] = time.perf_counter() - t0
+    return [{"h_min": r["u"] if r["status_name"] == "optimal" else math.nan, "h_min_result": r, "result": rc,
+             "screened": s, "lp": lp} for r, rc, s, lp in zip(rh, res, screened, lps)]

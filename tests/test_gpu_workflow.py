@@ -125,3 +125,51 @@ def test_sweep_matches_exact_general_lps(dtype):
         vs = [d["result"]["v"] for d in row]
         assert all(us[j + 1] <= us[j] * (1 + 1e-3) for j in range(len(us) - 1)), us
         assert all(vs[j + 1] >= vs[j] * (1 - 1e-3) for j in range(len(vs) - 1)), vs
+
+
+def test_case2_screened_certifies_caps_below_h_min():
+    # caps below h_min start from the h_min multipliers, which the solver accepts at iteration 0 as the
+    # Farkas certificate; caps above h_min start cold and reach the exact Case-2 optimum
+    import paper_2604_08997_amd as sipo
+    from paper_2604_08997_amd import workflow
+    from oracle import kkt as okkt
+    its, orc = items(torch.float64)
+    hm = [owf.h_min(P, f, band_width=BAND) for P, f in orc]
+    caps = [0.9 * hm[0], 1.1 * hm[1], 0.95 * hm[2]]
+    res = workflow.case2_screened(its, caps, band_width=BAND,
+                                  opts=sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=100000, tol=1e-6,
+                                                         infeas_tol=1e-5),
+                                  h_min_opts=sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=200000, tol=1e-8))
+    for d, (P, f), cap, h in zip(res, orc, caps, hm):
+        assert close(d["h_min"], h, 1e-6)
+        op = owf.case2_in_general_units(P, f, cap, band_width=BAND)
+        ref = olp.solve_highs(op)
+        if cap < h:
+            assert ref.status == "infeasible"
+            assert d["screened"]
+            assert d["result"]["status_name"] == "infeasible" and d["result"]["iters"] == 0, d["result"]
+            lu, ll = d["lp"].lam_up.cpu().numpy(), d["lp"].lam_lo.cpu().numpy()
+            assert okkt.farkas_check(op, lu, ll, tol=1e-4)["valid"]
+        else:
+            assert not d["screened"]
+            assert d["result"]["status_name"] == "optimal"
+            assert close(d["result"]["v"], ref.v, 1e-4)
+
+
+def test_warm_start_from_an_optimum_is_not_a_certificate():
+    # the optimal multipliers of a feasible LP carry the objective's price, so the iteration-0
+    # Farkas test rejects them and the warm-started solve runs and stays optimal
+    import paper_2604_08997_amd as sipo
+    n, na, seed = SPECS[0]
+    plan = sipo.Plan(n, list(angles_uniform(na)), dtype=torch.float64, device=dev())
+    for case in (sipo.CASE1, sipo.CASE2, sipo.GENERAL):
+        lp = sipo.LP.build(plan, torch.as_tensor(ellipses_target(n, seed), device=dev()), case, band_width=BAND,
+                           cap=0.95)
+        opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=100000, tol=1e-6, infeas_tol=1e-5)
+        r1 = sipo.solve(lp, opts)
+        if r1["status_name"] != "optimal":
+            continue
+        lp.u0, lp.v0 = r1["u"], r1["v"]
+        r2 = sipo.solve(lp, opts)
+        assert r2["status_name"] == "optimal" and r2["iters"] >= 1, (case, r2)
+        assert close(r2["primal_obj"], r1["primal_obj"], 1e-5)
