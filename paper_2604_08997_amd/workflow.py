@@ -51,7 +51,7 @@ def _metrics(lp, f_min):
     return lp.plan.evaluate(lp.dose, lp.labels, f_t_scalar=1.0, f_crit=f_min)
 
 
-def two_stage(items, band_width=10.0, tol_lo=0.9, tol_hi=1.0, margin=1e-3, opts=None, warm=True,
+def two_stage(items, band_width=10.0, tol_lo=0.9, tol_hi=1.0, margin=0.02, opts=None, warm=True,
               with_h_min=True, workspace=None, times=None):
     """Run the two-stage workflow on every (plan, f_target) in ``items``.
 
