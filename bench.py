@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=32, help="z slices in the bounded oracle sample")
     ap.add_argument("--ttk", action="store_true", help="also time a cold solve to relative KKT 1e-4")
+    ap.add_argument("--ttk-iters", type=int, default=60000, help="iteration budget of the --ttk solve")
     ap.add_argument("--batch", type=int, default=8,
                     help="instances of the uneven 2D batch (seeds 2000..) for the batched-vs-plain time to 1e-4 "
                          "(0 = skip)")
@@ -322,6 +323,8 @@ def main():
     if args.probe:
         return probe(args, plan, dev)
     plan.autotune()
+    tuning = plan.tuning()
+    print(f"[bench] autotuned work splits: {tuning}", file=sys.stderr, flush=True)
     if big:
         f = torch.as_tensor(lattice_target(n, 4000), dtype=torch.float32, device=dev)
         lp = sipo.LP.build(plan, f, sipo.CASE2, band_width=10.0, f_min=1.0, cap=0.65)
@@ -362,7 +365,7 @@ def main():
         lp.y.zero_(); lp.lam_up.zero_(); lp.lam_lo.zero_()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        r = sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=100000, tol=1e-4), want_dose=False)
+        r = sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=args.ttk_iters, tol=1e-4), want_dose=False)
         torch.cuda.synchronize()
         ttk = {"seconds": round(time.perf_counter() - t1, 3), "iters": r["iters"], "status": r["status_name"],
                "restarts": r["restarts"], "objective": r["primal_obj"]}
@@ -391,6 +394,7 @@ def main():
                     "n": n, "views": na, "case": 1, "blur_sigma": 1.5}),
         "a_plus_at_gbs": round(pair_bytes / ((t_p + t_bp) * 1e-3) / 1e9, 2),
         "phase_ms": {k: round(v, 4) for k, v in ph_avg.items()},
+        "tuning": tuning,
         "roofline": {"bound": "alu", "kernel": "project3d" if dom == "project" else "backproject3d",
                      "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic},

@@ -101,6 +101,30 @@ int sipo_plan_destroy(sipo_plan plan);
  * the same plan. */
 int sipo_plan_autotune(sipo_plan plan, void *stream);
 
+/* The work-split settings sipo_plan_autotune chooses among, so that a caller
+ * can keep a tuning and restore it on a later plan of the same geometry, or
+ * pin one variant.  They change speed, not results beyond rounding order. */
+typedef struct {
+    int32_t p3d_zc;     /* slices per 3D projector thread: 8 or 16 (FP64); 8, 16 or 32 (FP32)    */
+    int32_t p3d_dma;    /* 1 = 3D projector with asynchronous LDS staging (FP32, slices per
+                           thread >= 16, and only where the plan's staged ranges allow it)      */
+    int32_t p3d_skip;   /* asynchronous projector: lanes skip candidates outside their ray (0/1) */
+    int32_t p3d_cm;     /* asynchronous projector: march steps per staged chunk, 1 or 2          */
+    int32_t blur_zc;    /* slices per blur workgroup: 0 (whole columns), 8, 16 or 32 (<= nz)     */
+} sipo_tuning;
+
+/* Current settings of the plan (defaults, autotuned or set).  Errors: NULL
+ * arguments (SIPO_E_INVALID). */
+int sipo_plan_get_tuning(sipo_plan plan, sipo_tuning *out);
+
+/* Applies settings to the plan; all fields are checked first and nothing is
+ * changed on error (SIPO_E_INVALID for values outside the lists above,
+ * SIPO_E_UNSUPPORTED for an asynchronous projector the plan cannot use).
+ * Fields that do not apply to the plan (a 2D plan's projector settings, the
+ * blur of a plan without a PSF) are stored and ignored.  Not thread-safe
+ * against concurrent use of the same plan. */
+int sipo_plan_set_tuning(sipo_plan plan, const sipo_tuning *t);
+
 /* vol (+)= P^T sino: backprojection, the geometric part of the dose model
  * f = A^T g = K P^T g (Eq. 2-3).  sino: device [n_angles][nz][n_bins];
  * vol: device [nz][n][n].  accumulate != 0 adds to vol, else overwrites.
@@ -224,6 +248,15 @@ typedef struct {
     int32_t profile;           /* 1 = time every iteration launch with HIP events on the
                                   solve's stream (per-phase totals in the result); cannot
                                   be combined with use_graph                              */
+    double scalar_weight;      /* restarted mode: column weight of the free scalars u, v in
+                                  the diagonal steps, as a multiple c >= 0 of the mean row
+                                  sum of their rows (0 = plain Pock-Chambolle, weight 1):
+                                  tau_u = w_u / |band|, band rows sigma = 1/(R + w_u); the
+                                  step bound holds for any positive weight               */
+    double balance;            /* restarted mode: exponent b >= 0 of a residual-balancing
+                                  correction of the primal weight at each restart,
+                                  omega *= clamp((eps_p / max(eps_d, eps_gap))^b, 1/4, 4) after the
+                                  movement-based update (0 = movement only)             */
 } sipo_pdhg_options;
 
 /* Phases of one PDHG iteration, for sipo_pdhg_result.phase_ms. */

@@ -49,7 +49,8 @@ class Problem(C.Structure):
 class PdhgOptions(C.Structure):
     _fields_ = [("mode", C.c_int32), ("max_iters", C.c_int32), ("check_every", C.c_int32), ("tol", C.c_double),
                 ("tau", C.c_double), ("sigma", C.c_double), ("power_iters", C.c_int32), ("eta", C.c_double),
-                ("infeas_tol", C.c_double), ("use_graph", C.c_int32), ("profile", C.c_int32)]
+                ("infeas_tol", C.c_double), ("use_graph", C.c_int32), ("profile", C.c_int32),
+                ("scalar_weight", C.c_double), ("balance", C.c_double)]
 
 NUM_PHASES = 7
 PHASES = ("project", "backproject", "blur", "transpose", "primal", "dual", "scalars")
@@ -68,6 +69,11 @@ class PdhgResult(C.Structure):
         d["phase_ms"] = dict(zip(PHASES, list(self.phase_ms)))
         d["phase_launches"] = dict(zip(PHASES, list(self.phase_launches)))
         return d
+
+
+class Tuning(C.Structure):
+    _fields_ = [("p3d_zc", C.c_int32), ("p3d_dma", C.c_int32), ("p3d_skip", C.c_int32), ("p3d_cm", C.c_int32),
+                ("blur_zc", C.c_int32)]
 
 
 class Resin(C.Structure):
@@ -90,6 +96,8 @@ SIGNATURES = {
     "sipo_plan_create": (C.c_int, [C.POINTER(Geometry), C.POINTER(Psf), C.c_int, C.POINTER(C.c_void_p)]),
     "sipo_plan_destroy": (C.c_int, [C.c_void_p]),
     "sipo_plan_autotune": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "sipo_plan_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning)]),
+    "sipo_plan_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning)]),
     "sipo_backproject": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "sipo_project": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "sipo_blur": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -225,6 +233,22 @@ class Plan:
             _check(lib().sipo_plan_autotune(self.handle, _stream()))
         return self
 
+    def tuning(self):
+        """The plan's work-split settings (dict of the sipo_tuning fields)."""
+        t = Tuning()
+        _check(lib().sipo_plan_get_tuning(self.handle, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+    def set_tuning(self, **fields):
+        """Apply work-split settings; fields not given keep their current values."""
+        cur = self.tuning()
+        unknown = set(fields) - set(cur)
+        if unknown:
+            raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+        cur.update({k: int(v) for k, v in fields.items()})
+        _check(lib().sipo_plan_set_tuning(self.handle, C.byref(Tuning(**cur))))
+        return self
+
     # ------------------------------------------------------------ operators
     def backproject(self, sino, out=None, accumulate=False):
         _require(sino, "sino", self.sino_shape, self.dtype, self.device)
@@ -349,9 +373,10 @@ class LP:
 
 
 def pdhg_options(mode=RESTARTED, max_iters=20000, check_every=64, tol=1e-4, tau=0.0, sigma=0.0, power_iters=100,
-                 eta=0.95, infeas_tol=1e-6, use_graph=0, profile=0):
+                 eta=0.95, infeas_tol=1e-6, use_graph=0, profile=0, scalar_weight=0.0, balance=0.0):
     return PdhgOptions(int(mode), int(max_iters), int(check_every), float(tol), float(tau), float(sigma),
-                       int(power_iters), float(eta), float(infeas_tol), int(use_graph), int(profile))
+                       int(power_iters), float(eta), float(infeas_tol), int(use_graph), int(profile),
+                       float(scalar_weight), float(balance))
 
 
 def solve(lps, opts=None, want_dose=True, workspace=None):

@@ -74,6 +74,7 @@ struct LPConst {
     int u_free, v_free;
     double w1, w2, h;         // weights and band cap
     double lo_s, hi_s;        // scalar bounds when arrays are absent
+    double wu, wv;            // column weights of the free scalars in the diagonal steps
 };
 
 // Per-instance constants and per-call selectors on the device.
@@ -200,8 +201,11 @@ __global__ void k_inv_colsum(T *t, const uint8_t *act, const Seg *segs) {
     SEG_LOOP(i) t[i] = (act[i] && t[i] > (T)0) ? (T)1 / t[i] : (T)0;
 }
 
-// S_up = 1/(R + [band, u free] + [gel, v free] U), S_lo = [gel] 1/R;
-// [0] |band|, [1] sum_gel U, [2] ||h||^2, [3] |gel|
+// S_up = 1/(R + [band, u free] w_u + [gel, v free] w_v U), S_lo = [gel] 1/R (weighted
+// Pock-Chambolle steps: the free scalars' columns carry weights w_u, w_v, their steps are
+// w_u / |band| and w_v / sum_gel U, and the bound on the preconditioned operator holds for any
+// positive weights);
+// [0] |band|, [1] sum_gel U, [2] ||h||^2, [3] |gel|, [4] sum_band R, [5] sum_gel R U
 template <typename T>
 __global__ void k_row_scaling(const T *R, T *s_up, T *s_lo, const uint8_t *lab, const T *lo, const T *hi,
                               const InstC *insts, const Seg *segs, double *partials) {
@@ -212,18 +216,20 @@ __global__ void k_row_scaling(const T *R, T *s_up, T *s_lo, const uint8_t *lab, 
         const T r = R[i];
         T su = 0, sl = 0;
         if (L == 1) {
-            const T rs = r + (c.u_free ? (T)1 : (T)0);
+            const T rs = r + (c.u_free ? (T)c.wu : (T)0);
             su = rs > (T)0 ? (T)1 / rs : (T)0;
             acc[0] += 1.0;
+            acc[4] += (double)r;
             if (!c.u_free) acc[2] += c.h * c.h;
         } else if (L == 2) {
             const double U = (double)ld_or(hi, i, c.hi_s), Lo = (double)ld_or(lo, i, c.lo_s);
-            const T rs = r + (c.v_free ? (T)U : (T)0);
+            const T rs = r + (c.v_free ? (T)(c.wv * U) : (T)0);
             su = rs > (T)0 ? (T)1 / rs : (T)0;
             sl = r > (T)0 ? (T)1 / r : (T)0;
             acc[1] += U;
             acc[2] += Lo * Lo + (c.v_free ? 0.0 : U * U);
             acc[3] += 1.0;
+            acc[5] += (double)r * U;
         }
         s_up[i] = su;
         s_lo[i] = sl;
@@ -672,6 +678,8 @@ class Solver {
             c.c.h = pb.band_cap;
             c.c.lo_s = pb.lo_scalar;
             c.c.hi_s = pb.hi_scalar;
+            c.c.wu = 1.0;
+            c.c.wv = 1.0;
         }
     }
     ~Solver() {
@@ -1073,13 +1081,27 @@ int Solver<T>::setup_common() {
     if (rc) return rc;
     hipLaunchKernelGGL((k_row_scaling<T>), gV(), dim3(kThreads), 0, s_, (const T *)F(L_.Dt), F(L_.s_up), F(L_.s_lo),
                        (const uint8_t *)U8(L_.lab), lo_(), hi_(), insts(), segV(), partials());
-    rc = finish(true, all, 4);
+    rc = finish(true, all, 6);
     if (rc) return rc;
+    if (o_.mode == SIPO_PDHG_RESTARTED && o_.scalar_weight > 0) {
+        // column weights of the free scalars: c times the mean row sum of their rows; redo the rows
+        for (int i = 0; i < B_; ++i) {
+            LPConst &c = hin_[i].c;
+            if (sum(i, 0) > 0 && sum(i, 4) > 0) c.wu = o_.scalar_weight * sum(i, 4) / sum(i, 0);
+            if (sum(i, 1) > 0 && sum(i, 5) > 0) c.wv = o_.scalar_weight * sum(i, 5) / sum(i, 1);
+        }
+        rc = put_insts();
+        if (rc) return rc;
+        hipLaunchKernelGGL((k_row_scaling<T>), gV(), dim3(kThreads), 0, s_, (const T *)F(L_.Dt), F(L_.s_up),
+                           F(L_.s_lo), (const uint8_t *)U8(L_.lab), lo_(), hi_(), insts(), segV(), partials());
+        rc = finish(true, all, 6);
+        if (rc) return rc;
+    }
     for (int i = 0; i < B_; ++i) {
         Inst &I = in_[i];
         const LPConst &c = hin_[i].c;
-        I.Tu = (c.u_free && sum(i, 0) > 0) ? 1.0 / sum(i, 0) : 0.0;
-        I.Tv = (c.v_free && sum(i, 1) > 0) ? 1.0 / sum(i, 1) : 0.0;
+        I.Tu = (c.u_free && sum(i, 0) > 0) ? c.wu / sum(i, 0) : 0.0;
+        I.Tv = (c.v_free && sum(i, 1) > 0) ? c.wv / sum(i, 1) : 0.0;
         I.h_norm = std::sqrt(sum(i, 2));
         I.c_norm = std::hypot(c.u_free ? c.w1 : 0.0, c.v_free ? c.w2 : 0.0);
     }
@@ -1474,6 +1496,11 @@ int Solver<T>::run(sipo_pdhg_result *res) {
                 const double dx = std::sqrt(dy2[i] + (I.Tu > 0 ? du * du / I.Tu : 0.0) + (I.Tv > 0 ? dv * dv / I.Tv : 0.0));
                 const double dl = std::sqrt(dlu2[i] + dll2[i]);
                 if (dx > 1e-10 && dl > 1e-10) I.omega = std::exp(0.5 * std::log(dl / dx) + 0.5 * std::log(I.omega));
+                // residual balancing: a larger weight speeds the dual side (primal feasibility), a
+                // smaller one the primal side (dual feasibility and the gap)
+                const double other = std::max(I.kc.eps_d, I.kc.eps_gap);
+                if (o_.balance > 0 && I.kc.eps_p > 0 && other > 0)
+                    I.omega *= std::min(4.0, std::max(0.25, std::pow(I.kc.eps_p / other, o_.balance)));
                 h.u = h.u0 = I.last_u = h.ut_done;
                 h.v = h.v0 = I.last_v = h.vt_done;
                 h.init_l1 = sum(i, 0);
@@ -1595,6 +1622,8 @@ static int validate(const sipo_problem &pb, const sipo_pdhg_options &o, int idx,
     SIPO_REQUIRE(!(o.profile && o.use_graph), "profile and use_graph cannot be combined");
     SIPO_REQUIRE(o.mode == SIPO_PDHG_PLAIN || o.check_every >= 1, "check_every must be >= 1");
     SIPO_REQUIRE(!(o.eta >= 1.0), "eta must be < 1");
+    SIPO_REQUIRE(std::isfinite(o.scalar_weight) && o.scalar_weight >= 0, "scalar_weight must be finite and >= 0");
+    SIPO_REQUIRE(std::isfinite(o.balance) && o.balance >= 0, "balance must be finite and >= 0");
     return SIPO_OK;
 }
 

@@ -404,17 +404,20 @@ __global__ void __launch_bounds__(256) project3d_kernel(const T *__restrict__ vo
 // Same rays, candidates and weights as project3d_kernel (FP32, nz % 4 == 0),
 // but the volume strips are copied HBM -> LDS with direct-to-LDS loads
 // (global_load_lds_dwordx4) into two buffers: while a workgroup computes the
-// rays' contributions of one kDmaCM-step chunk from one buffer, the next
-// chunk is already in flight into the other, so the staging latency is hidden
-// behind compute instead of stalling every chunk.
+// rays' contributions of one CM-step chunk from one buffer, the next chunk is
+// already in flight into the other, so the staging latency is hidden behind
+// compute instead of stalling every chunk.  CM = 1 halves the LDS footprint
+// (more workgroups per CU) at one barrier per step; CM = 2 halves the
+// barriers.
 //
 // LDS layout of a buffer: [step][z/4][kPCR + 1] 16-byte slots.  A wave's load
 // instruction fills 64 consecutive slots, so each thread owns fixed slots
 // (decoded once); per chunk only the source address changes.  Slots beyond a
 // chunk's cross range, outside the grid or outside the vial load from a 16-byte
-// zero block.  Cross ranges per (batch, bin group, chunk) come precomputed
-// from the plan (conservative by one voxel on each side).
-constexpr int kDmaCM = 2;
+// zero block.  Cross ranges per (batch, bin group, step) come precomputed from
+// the plan (conservative by one voxel on each side); a chunk stages the union
+// of its steps' ranges.
+constexpr int kDmaMaxCM = 2;
 
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -424,13 +427,14 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int ZC, int NC, bool PAIR, bool SKIP>
+template <int ZC, int NC, bool PAIR, bool SKIP, int CM>
 __global__ void __launch_bounds__(256) project3d_dma_kernel(
     const float *__restrict__ vol_t, float *__restrict__ sino_t, int n, int nz, int nb,
     const double2 *__restrict__ trig, const int *__restrict__ order, const int *__restrict__ partner,
     const int4 *__restrict__ batches, const int2 *__restrict__ ranges, const int2 *__restrict__ vial_rows,
     const float4 *__restrict__ zero16, double h, double inv_ds, float atten) {
-    constexpr int Z4 = ZC / 4, RS = kPCR + 1, SLOTS = kDmaCM * Z4 * RS, PER = (SLOTS + 255) / 256;
+    static_assert(CM >= 1 && CM <= kDmaMaxCM, "chunk length");
+    constexpr int Z4 = ZC / 4, RS = kPCR + 1, SLOTS = CM * Z4 * RS, PER = (SLOTS + 255) / 256;
     constexpr int NR = PAIR ? 2 : 1;
     __shared__ float4 bufA[SLOTS];
     __shared__ float4 bufB[SLOTS];
@@ -455,10 +459,24 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     const double du = dsj * inv_ds, dU = dsm * inv_ds, U00 = fma(s00 + 1.0, inv_ds, -0.5);
     const double inv_du = 1.0 / du;
     const float du_t = (float)du, dsj_t = (float)dsj, dtj_t = (float)dtj;
-    const int nch = (n + kDmaCM - 1) / kDmaCM;
-    const int2 *rg = ranges + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * nch;
+    const int nch = (n + CM - 1) / CM;
+    const int2 *rg = ranges + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * n;
     const size_t zrow = (size_t)(nz >> 2), zoff = (size_t)(z0 >> 2);
     const float4 *vol4 = (const float4 *)vol_t;
+
+    // staged cross range of chunk k: the union of its steps' ranges (first index, count)
+    auto chunk_range = [&](int k) {
+        const int m0 = k * CM;
+        int lo = rg[m0].x, hi = rg[m0].x + rg[m0].y;
+#pragma unroll
+        for (int q = 1; q < CM; ++q)
+            if (m0 + q < n) {
+                const int2 r = rg[m0 + q];
+                lo = min(lo, r.x);
+                hi = max(hi, r.x + r.y);
+            }
+        return make_int2(lo, hi - lo);
+    };
 
     // fixed slots of this thread: (step, z/4, cross offset)
     int s_mm[PER], s_z4[PER], s_jj[PER];
@@ -470,16 +488,18 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
         s_z4[i] = rem / RS;
         s_jj[i] = rem - s_z4[i] * RS;
     }
-    static_assert(kDmaCM == 2, "the staging below reads the vial intervals of two rows");
     auto issue = [&](float4 *buf, int k) {
-        const int2 r = rg[k];
-        const int m0 = k * kDmaCM;
-        const int2 v0 = vial_rows[m0], v1 = vial_rows[min(m0 + 1, n - 1)];
+        const int2 r = chunk_range(k);
+        const int m0 = k * CM;
+        int2 vr[CM];   // vial interval of each step's row (uniform loads)
+#pragma unroll
+        for (int q = 0; q < CM; ++q) vr[q] = vial_rows[min(m0 + q, n - 1)];
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             if (i * 256 + tid < SLOTS) {
-                const int m = m0 + s_mm[i], j = r.x + s_jj[i];
-                const int2 v = s_mm[i] ? v1 : v0;
+                const int mm = CM == 1 ? 0 : s_mm[i];
+                const int m = m0 + mm, j = r.x + s_jj[i];
+                const int2 v = CM == 1 ? vr[0] : (mm ? vr[CM - 1] : vr[0]);
                 const float4 *src = zero16;
                 if (m < n && s_jj[i] < r.y && z0 + 4 * s_z4[i] < nz && j >= v.x && j <= v.y)
                     src = vol4 + (xmajor ? ((size_t)j * n + m) : ((size_t)m * n + j)) * zrow + zoff + s_z4[i];
@@ -497,10 +517,10 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
         for (int k = 0; k < ZC; ++k) acc[r][k] = 0.f;
 
     auto compute = [&](const float4 *buf, int k) {
-        const int2 r = rg[k];
+        const int2 r = chunk_range(k);
         const int j0 = r.x, cr = r.y;
-        const int m0 = k * kDmaCM;
-        const int mc = min(kDmaCM, n - m0);
+        const int m0 = k * CM;
+        const int mc = min(CM, n - m0);
         for (int mm = 0; mm < mc; ++mm) {
             const int m = m0 + mm;
             const double U = fma((double)m, dU, U00);
@@ -714,26 +734,36 @@ int plan_build_batches(sipo_plan p, const double2 *trig) {
     p->n_walk = nw;
     p->p3d_zc = p->dtype == SIPO_F64 ? 16 : 32;
     p->p3d_skip = false;
+    p->p3d_cm = kDmaMaxCM;
     p->blur_zc = 0;
     p->n_batches = (int)batches.size();
     p->p3d_ok = ok && p->p3d_nc > 0;
     p->bp3d_ok = bp3d_fits(p->n, p->n_bins);
-    // staged cross range of every (batch, bin group, kDmaCM-step chunk) for the asynchronous projector
-    const int ngroups = (p->n_bins + kPB - 1) / kPB, nch = (p->n + kDmaCM - 1) / kDmaCM;
+    // staged cross range of every (batch, bin group, step) for the asynchronous projector; its chunks
+    // of up to kDmaMaxCM steps stage the union of their steps' ranges, which must fit kPCR
+    const int ngroups = (p->n_bins + kPB - 1) / kPB;
     std::vector<int2> ranges;
     bool dma = p->dtype == SIPO_F32 && (p->nz & 3) == 0 && p->p3d_ok;
     if (dma) {
-        ranges.resize((size_t)batches.size() * ngroups * nch);
+        ranges.resize((size_t)batches.size() * ngroups * p->n);
         for (size_t bi = 0; bi < batches.size() && dma; ++bi) {
             const int4 bt = batches[bi];
-            for (int g = 0; g < ngroups && dma; ++g)
-                for (int k = 0; k < nch; ++k) {
+            for (int g = 0; g < ngroups && dma; ++g) {
+                int2 *row = ranges.data() + (bi * ngroups + g) * p->n;
+                for (int m = 0; m < p->n; ++m) {
                     int j0, cr;
-                    staged_range(bt.z != 0, trig, order.data() + bt.x, bt.y, g * kPB, k * kDmaCM,
-                                 std::min(k * kDmaCM + kDmaCM, p->n) - 1, h, inv_ds, &j0, &cr);
-                    if (cr > kPCR) { dma = false; break; }
-                    ranges[(bi * ngroups + g) * nch + k] = make_int2(j0, cr);
+                    staged_range(bt.z != 0, trig, order.data() + bt.x, bt.y, g * kPB, m, m, h, inv_ds, &j0, &cr);
+                    row[m] = make_int2(j0, cr);
                 }
+                for (int m0 = 0; m0 < p->n && dma; m0 += kDmaMaxCM) {
+                    int lo = row[m0].x, hi = row[m0].x + row[m0].y;
+                    for (int q = 1; q < kDmaMaxCM && m0 + q < p->n; ++q) {
+                        lo = std::min(lo, row[m0 + q].x);
+                        hi = std::max(hi, row[m0 + q].x + row[m0 + q].y);
+                    }
+                    if (hi - lo > kPCR) dma = false;
+                }
+            }
         }
     }
     std::vector<int2> vial(p->n);
@@ -830,14 +860,20 @@ static void fp3d_nc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s)
                            p->d_batches, h, inv_ds, (T)p->atten);
 }
 
-template <int ZC, int NC, bool PAIR, bool SKIP>
-static void fp3d_dma_go(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+template <int ZC, int NC, bool PAIR, bool SKIP, int CM>
+static void fp3d_dma_launch(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
     const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
     const dim3 grid((p->n_bins + kPB - 1) / kPB, p->n_batches, (p->nz + ZC - 1) / ZC);
-    hipLaunchKernelGGL((project3d_dma_kernel<ZC, NC, PAIR, SKIP>), grid, dim3(256), 0, s, (const float *)vol_t,
+    hipLaunchKernelGGL((project3d_dma_kernel<ZC, NC, PAIR, SKIP, CM>), grid, dim3(256), 0, s, (const float *)vol_t,
                        (float *)sino_t, p->n, p->nz, p->n_bins, p->d_trig, p->d_angle_order, p->d_partner,
                        p->d_batches, p->d_ranges, p->d_vial_rows, (const float4 *)p->d_zero, h, inv_ds,
                        (float)p->atten);
+}
+
+template <int ZC, int NC, bool PAIR, bool SKIP>
+static void fp3d_dma_go(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+    if (p->p3d_cm == 1) fp3d_dma_launch<ZC, NC, PAIR, SKIP, 1>(p, vol_t, sino_t, s);
+    else fp3d_dma_launch<ZC, NC, PAIR, SKIP, kDmaMaxCM>(p, vol_t, sino_t, s);
 }
 
 template <int ZC, int NC>

@@ -80,7 +80,8 @@ struct sipo_plan_s {
     bool p3d_dma_ok;        // the asynchronous-staging projector applies (FP32, nz % 4 == 0, ranges fit)
     bool p3d_dma;           // use it (default when it applies; sipo_plan_autotune may switch)
     bool p3d_skip;          // asynchronous projector: lanes skip candidates outside their ray's reach
-    int2 *d_ranges;         // [n_batches][bin groups][chunks of kDmaCM steps]: staged cross range (j0, count)
+    int p3d_cm;             // asynchronous projector: march steps per staged chunk (1 or 2)
+    int2 *d_ranges;         // [n_batches][bin groups][steps]: staged cross range (j0, count)
     int2 *d_vial_rows;      // [n]: first and last index along a grid line inside the vial
     void *d_zero;           // 256 zero bytes (source of empty staging slots)
     int n_walk;             // views the projector walks (entries of d_angle_order)

@@ -185,3 +185,62 @@ def test_full_size_3d_projector_sampled_outputs():
     s64 = sino.astype(np.float64)
     want_b = np.array([rows[k] @ s64[:, vz[k], :].reshape(-1) for k in range(3000)]).ravel()
     assert rel_norm(bp[vz, vr, vc], want_b) < F32_NORM_TOL
+
+
+# 3D FP32 cases whose slice counts allow the asynchronous projector (nz % 4 == 0)
+VARIANT_CASES = [
+    (48, 60, 20, None),     # view pairs
+    (40, 37, 24, None),     # odd view count: no pairing
+    (33, 90, 12, 35),       # ragged grid and detector, view pairs
+]
+
+
+@pytest.mark.parametrize("case", VARIANT_CASES)
+def test_every_projector_and_blur_variant_matches_oracle(case):
+    # each work split the autotuner can choose, pinned through sipo_plan_set_tuning
+    from paper_2604_08997_amd import SipoError
+    n, na, nz, nb = case
+    ang = angles_uniform(na)
+    g = make_geometry(n, ang, n_bins=nb, nz=nz, atten=1.0)
+    P = Projector(g)
+    sigma = (1.0, 1.0, 1.5)
+    plan = plan_for(n, list(ang), nz=nz, n_bins=nb, sigma=sigma)
+    vol = signed_field(g.vol_shape, 11)
+    vol_d = to_gpu(vol, torch.float32)
+    fp_ref = P.project(vol)
+    kb_ref = oblur.apply(vol, oblur.psf_taps(sigma))
+    default = plan.tuning()
+    ran_async = 0
+    for zc in (8, 16, 32):
+        for dma, skip, cm in [(0, 0, 2), (1, 0, 1), (1, 0, 2), (1, 1, 1), (1, 1, 2)]:
+            try:
+                plan.set_tuning(p3d_zc=zc, p3d_dma=dma, p3d_skip=skip, p3d_cm=cm)
+            except SipoError as e:
+                assert dma == 1 and (zc < 16 or not default["p3d_dma"]), (zc, dma, e)
+                continue
+            assert plan.tuning()["p3d_zc"] == zc and plan.tuning()["p3d_cm"] == cm
+            fp = plan.project(vol_d).double().cpu().numpy()
+            assert rel_norm(fp, fp_ref) < F32_NORM_TOL, (zc, dma, skip, cm)
+            ran_async += dma
+    assert ran_async == 8 or not default["p3d_dma"]
+    for bzc in (0, 8, 16, 32):
+        if bzc > nz:
+            with pytest.raises(SipoError):
+                plan.set_tuning(blur_zc=bzc)
+            continue
+        plan.set_tuning(blur_zc=bzc)
+        kb = plan.blur(vol_d).double().cpu().numpy()
+        assert rel_norm(kb, kb_ref) < F32_NORM_TOL, bzc
+
+
+def test_set_tuning_rejects_invalid_settings():
+    from paper_2604_08997_amd import SipoError
+    p64 = plan_for(24, 20, nz=8, dtype=torch.float64)
+    before = p64.tuning()
+    for bad in [dict(p3d_zc=32), dict(p3d_zc=12), dict(p3d_dma=1), dict(p3d_cm=3), dict(p3d_skip=1, p3d_dma=0),
+                dict(blur_zc=16)]:
+        with pytest.raises(SipoError):
+            p64.set_tuning(**bad)
+        assert p64.tuning() == before
+    with pytest.raises(ValueError):
+        p64.set_tuning(zc=16)
