@@ -368,7 +368,8 @@ def main():
         r = sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=args.ttk_iters, tol=1e-4), want_dose=False)
         torch.cuda.synchronize()
         ttk = {"seconds": round(time.perf_counter() - t1, 3), "iters": r["iters"], "status": r["status_name"],
-               "restarts": r["restarts"], "objective": r["primal_obj"]}
+               "restarts": r["restarts"], "objective": r["primal_obj"], "rel_primal": r["rel_primal"],
+               "rel_dual": r["rel_dual"], "rel_gap": r["rel_gap"]}
         print(f"[bench] time to 1e-4: {ttk}", file=sys.stderr, flush=True)
 
     bvp = batch_vs_plain(args.batch, dev) if args.batch > 0 else None

@@ -253,10 +253,6 @@ typedef struct {
                                   sum of their rows (0 = plain Pock-Chambolle, weight 1):
                                   tau_u = w_u / |band|, band rows sigma = 1/(R + w_u); the
                                   step bound holds for any positive weight               */
-    double balance;            /* restarted mode: exponent b >= 0 of a residual-balancing
-                                  correction of the primal weight at each restart,
-                                  omega *= clamp((eps_p / max(eps_d, eps_gap))^b, 1/4, 4) after the
-                                  movement-based update (0 = movement only)             */
 } sipo_pdhg_options;
 
 /* Phases of one PDHG iteration, for sipo_pdhg_result.phase_ms. */

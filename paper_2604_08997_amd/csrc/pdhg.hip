@@ -1496,11 +1496,6 @@ int Solver<T>::run(sipo_pdhg_result *res) {
                 const double dx = std::sqrt(dy2[i] + (I.Tu > 0 ? du * du / I.Tu : 0.0) + (I.Tv > 0 ? dv * dv / I.Tv : 0.0));
                 const double dl = std::sqrt(dlu2[i] + dll2[i]);
                 if (dx > 1e-10 && dl > 1e-10) I.omega = std::exp(0.5 * std::log(dl / dx) + 0.5 * std::log(I.omega));
-                // residual balancing: a larger weight speeds the dual side (primal feasibility), a
-                // smaller one the primal side (dual feasibility and the gap)
-                const double other = std::max(I.kc.eps_d, I.kc.eps_gap);
-                if (o_.balance > 0 && I.kc.eps_p > 0 && other > 0)
-                    I.omega *= std::min(4.0, std::max(0.25, std::pow(I.kc.eps_p / other, o_.balance)));
                 h.u = h.u0 = I.last_u = h.ut_done;
                 h.v = h.v0 = I.last_v = h.vt_done;
                 h.init_l1 = sum(i, 0);
@@ -1623,7 +1618,6 @@ static int validate(const sipo_problem &pb, const sipo_pdhg_options &o, int idx,
     SIPO_REQUIRE(o.mode == SIPO_PDHG_PLAIN || o.check_every >= 1, "check_every must be >= 1");
     SIPO_REQUIRE(!(o.eta >= 1.0), "eta must be < 1");
     SIPO_REQUIRE(std::isfinite(o.scalar_weight) && o.scalar_weight >= 0, "scalar_weight must be finite and >= 0");
-    SIPO_REQUIRE(std::isfinite(o.balance) && o.balance >= 0, "balance must be finite and >= 0");
     return SIPO_OK;
 }
 
