@@ -73,7 +73,7 @@ class PdhgResult(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("p3d_zc", C.c_int32), ("p3d_dma", C.c_int32), ("p3d_skip", C.c_int32), ("p3d_cm", C.c_int32),
-                ("blur_zc", C.c_int32)]
+                ("blur_zc", C.c_int32), ("bp3d_zc", C.c_int32)]
 
 
 class Resin(C.Structure):

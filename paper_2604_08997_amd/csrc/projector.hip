@@ -546,15 +546,20 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
                 const int jj = min(max(jj0 + q, 0), cr - 1);
                 // SKIP: lanes whose candidate lies outside their ray's reach issue no LDS reads
                 if (SKIP && !(hat > 0.f)) continue;
+                // all of the candidate's LDS reads go out before its FMAs, so their latencies
+                // overlap instead of being waited out two reads at a time
+                float4 v[Z4];
+#pragma unroll
+                for (int z4 = 0; z4 < Z4; ++z4) v[z4] = row[z4 * RS + jj];
+                __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the FMAs below
 #pragma unroll
                 for (int z4 = 0; z4 < Z4; ++z4) {
-                    const float4 v = row[z4 * RS + jj];
 #pragma unroll
                     for (int r = 0; r < NR; ++r) {
-                        acc[r][4 * z4 + 0] = fmaf(w[r], v.x, acc[r][4 * z4 + 0]);
-                        acc[r][4 * z4 + 1] = fmaf(w[r], v.y, acc[r][4 * z4 + 1]);
-                        acc[r][4 * z4 + 2] = fmaf(w[r], v.z, acc[r][4 * z4 + 2]);
-                        acc[r][4 * z4 + 3] = fmaf(w[r], v.w, acc[r][4 * z4 + 3]);
+                        acc[r][4 * z4 + 0] = fmaf(w[r], v[z4].x, acc[r][4 * z4 + 0]);
+                        acc[r][4 * z4 + 1] = fmaf(w[r], v[z4].y, acc[r][4 * z4 + 1]);
+                        acc[r][4 * z4 + 2] = fmaf(w[r], v[z4].z, acc[r][4 * z4 + 2]);
+                        acc[r][4 * z4 + 3] = fmaf(w[r], v[z4].w, acc[r][4 * z4 + 3]);
                     }
                 }
             }
@@ -735,6 +740,7 @@ int plan_build_batches(sipo_plan p, const double2 *trig) {
     p->p3d_zc = p->dtype == SIPO_F64 ? 16 : 32;
     p->p3d_skip = false;
     p->p3d_cm = kDmaMaxCM;
+    p->bp3d_zc = p->dtype == SIPO_F64 ? 16 : 32;
     p->blur_zc = 0;
     p->n_batches = (int)batches.size();
     p->p3d_ok = ok && p->p3d_nc > 0;
@@ -835,13 +841,24 @@ static int fp_slices(sipo_plan p, const void *vol, void *sino, int accumulate, h
     return SIPO_OK;
 }
 
-template <typename T>
-static int bp3d(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s) {
-    constexpr int ZC = sizeof(T) == 8 ? 16 : 32;
+template <typename T, int ZC>
+static void bp3d_zc(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s) {
     const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
     const dim3 grid((p->n + kBpTX - 1) / kBpTX, (p->n + kBpTY - 1) / kBpTY, (p->nz + ZC - 1) / ZC);
     hipLaunchKernelGGL((backproject3d_kernel<T, ZC>), grid, dim3(256), 0, s, (const T *)sino_t, (T *)vol, p->n, p->nz,
                        p->n_angles, p->n_bins, p->d_trig, h, inv_ds, (T)p->atten, accumulate);
+}
+
+template <typename T>
+static int bp3d(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s) {
+    switch (p->bp3d_zc) {
+        case 8: bp3d_zc<T, 8>(p, sino_t, vol, accumulate, s); break;
+        case 16: bp3d_zc<T, 16>(p, sino_t, vol, accumulate, s); break;
+        case 32:
+            if constexpr (sizeof(T) == 4) { bp3d_zc<T, 32>(p, sino_t, vol, accumulate, s); break; }
+            else return fail(SIPO_E_UNSUPPORTED, "3D backprojector: 32 slices per thread in FP64");
+        default: return fail(SIPO_E_UNSUPPORTED, "3D backprojector: %d slices per thread", p->bp3d_zc);
+    }
     SIPO_LAUNCHED("backproject3d_kernel");
     return SIPO_OK;
 }
@@ -900,6 +917,9 @@ static int fp3d_zc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) 
             return SIPO_OK;
         }
     }
+    if constexpr (ZC > 32) {
+        return fail(SIPO_E_UNSUPPORTED, "3D projector: %d slices per thread need the asynchronous variant", ZC);
+    } else {
     switch (p->p3d_nc) {
         case 3: fp3d_nc<T, ZC, 3>(p, vol_t, sino_t, s); break;
         case 4: fp3d_nc<T, ZC, 4>(p, vol_t, sino_t, s); break;
@@ -907,6 +927,7 @@ static int fp3d_zc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) 
         default: return fail(SIPO_E_UNSUPPORTED, "3D projector: unsupported candidate count");
     }
     return SIPO_OK;
+    }
 }
 
 template <typename T>
@@ -918,6 +939,10 @@ static int fp3d(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
         case 32:
             if constexpr (sizeof(T) == 4) rc = fp3d_zc<T, 32>(p, vol_t, sino_t, s);
             else rc = fail(SIPO_E_UNSUPPORTED, "3D projector: 32 slices per thread in FP64");
+            break;
+        case 64:
+            if constexpr (sizeof(T) == 4) rc = fp3d_zc<T, 64>(p, vol_t, sino_t, s);
+            else rc = fail(SIPO_E_UNSUPPORTED, "3D projector: 64 slices per thread in FP64");
             break;
         default: return fail(SIPO_E_UNSUPPORTED, "3D projector: %d slices per thread", p->p3d_zc);
     }

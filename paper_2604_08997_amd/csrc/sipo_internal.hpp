@@ -90,6 +90,7 @@ struct sipo_plan_s {
     int4 *d_items_bp2d, *d_items_fp2d, *d_items_tr2d;
     int n_items_bp2d, n_items_fp2d, n_items_tr2d;
     int blur_zc;            // slices per blur workgroup (0 = built-in choice)
+    int bp3d_zc;            // slices per 3D backprojector thread (8 or 16 in FP64; 8, 16 or 32 in FP32)
     bool bp3d_ok;           // the 3D backprojector's bin window fits its LDS tile
     void *d_vol_t;          // lazily allocated [y][x][z] scratch volume (standalone 3D calls)
     void *d_sino_t;         // lazily allocated [view][bin][z] scratch sinogram (standalone 3D calls)

@@ -46,7 +46,7 @@ extern "C" int sipo_plan_autotune(sipo_plan p, void *stream) {
     }
     constexpr int kReps = 3;
     if (p->fast3d()) {
-        std::vector<int> zcs = p->dtype == SIPO_F64 ? std::vector<int>{8, 16} : std::vector<int>{16, 32};
+        std::vector<int> zcs = p->dtype == SIPO_F64 ? std::vector<int>{8, 16} : std::vector<int>{16, 32, 64};
         int best = p->p3d_zc, best_cm = p->p3d_cm;
         bool best_dma = p->p3d_dma, best_skip = p->p3d_skip;
         float tbest = 1e30f;
@@ -54,6 +54,7 @@ extern "C" int sipo_plan_autotune(sipo_plan p, void *stream) {
             for (int skip = 0; skip <= dma; ++skip)
                 for (int cm = dma ? 1 : 2; cm <= 2; ++cm)
                     for (int zc : zcs) {
+                        if (zc > 32 && !dma) continue;   // 64 slices per thread: asynchronous staging only
                         p->p3d_zc = zc;
                         p->p3d_dma = dma != 0;
                         p->p3d_skip = skip != 0;
@@ -67,6 +68,14 @@ extern "C" int sipo_plan_autotune(sipo_plan p, void *stream) {
         p->p3d_dma = best_dma;
         p->p3d_skip = best_skip;
         p->p3d_cm = best_cm;
+        int best_b = p->bp3d_zc;
+        float tb = 1e30f;
+        for (int zc : p->dtype == SIPO_F64 ? std::vector<int>{8, 16} : std::vector<int>{16, 32}) {
+            p->bp3d_zc = zc;
+            const float t = time_ms([&] { return launch_backproject_t(p, sa, va, 0, s); }, kReps, s);
+            if (t >= 0.f && t < tb) { tb = t; best_b = zc; }
+        }
+        p->bp3d_zc = best_b;
     }
     if (p->has_psf && p->nz > 1) {
         int best = 0;
@@ -94,6 +103,7 @@ extern "C" int sipo_plan_get_tuning(sipo_plan p, sipo_tuning *out) {
     out->p3d_skip = p->p3d_skip ? 1 : 0;
     out->p3d_cm = p->p3d_cm;
     out->blur_zc = p->blur_zc;
+    out->bp3d_zc = p->bp3d_zc;
     return SIPO_OK;
 }
 
@@ -102,14 +112,17 @@ extern "C" int sipo_plan_set_tuning(sipo_plan p, const sipo_tuning *t) {
     if (rc) return rc;
     SIPO_REQUIRE(t != nullptr, "tuning is NULL");
     const bool f32 = p->dtype == SIPO_F32;
-    SIPO_REQUIRE(t->p3d_zc == 8 || t->p3d_zc == 16 || (f32 && t->p3d_zc == 32),
-                 "p3d_zc %d: expected 8 or 16%s", t->p3d_zc, f32 ? " or 32" : "");
+    SIPO_REQUIRE(t->p3d_zc == 8 || t->p3d_zc == 16 || (f32 && (t->p3d_zc == 32 || t->p3d_zc == 64)),
+                 "p3d_zc %d: expected 8 or 16%s", t->p3d_zc, f32 ? ", 32 or 64" : "");
+    SIPO_REQUIRE(t->p3d_zc <= 32 || t->p3d_dma, "64 slices per thread need the asynchronous projector");
     SIPO_REQUIRE(t->p3d_dma == 0 || t->p3d_dma == 1, "p3d_dma must be 0 or 1");
     SIPO_REQUIRE(t->p3d_skip == 0 || t->p3d_skip == 1, "p3d_skip must be 0 or 1");
     SIPO_REQUIRE(t->p3d_cm == 1 || t->p3d_cm == 2, "p3d_cm must be 1 or 2");
     SIPO_REQUIRE(t->blur_zc == 0 || ((t->blur_zc == 8 || t->blur_zc == 16 || t->blur_zc == 32) && t->blur_zc <= p->nz),
                  "blur_zc %d: expected 0, or 8, 16 or 32 not above nz = %d", t->blur_zc, p->nz);
     SIPO_REQUIRE(!t->p3d_skip || t->p3d_dma, "p3d_skip applies to the asynchronous projector only");
+    SIPO_REQUIRE(t->bp3d_zc == 8 || t->bp3d_zc == 16 || (f32 && t->bp3d_zc == 32),
+                 "bp3d_zc %d: expected 8 or 16%s", t->bp3d_zc, f32 ? " or 32" : "");
     if (t->p3d_dma && !(p->p3d_dma_ok && t->p3d_zc >= 16))
         return fail(SIPO_E_UNSUPPORTED, "the asynchronous 3D projector does not apply to this plan%s",
                     p->p3d_dma_ok ? " with fewer than 16 slices per thread" : "");
@@ -118,6 +131,7 @@ extern "C" int sipo_plan_set_tuning(sipo_plan p, const sipo_tuning *t) {
     p->p3d_skip = t->p3d_skip != 0;
     p->p3d_cm = t->p3d_cm;
     p->blur_zc = t->blur_zc;
+    p->bp3d_zc = t->bp3d_zc;
     return SIPO_OK;
 }
 

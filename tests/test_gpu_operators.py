@@ -211,18 +211,24 @@ def test_every_projector_and_blur_variant_matches_oracle(case):
     kb_ref = oblur.apply(vol, oblur.psf_taps(sigma))
     default = plan.tuning()
     ran_async = 0
-    for zc in (8, 16, 32):
+    for zc in (8, 16, 32, 64):
         for dma, skip, cm in [(0, 0, 2), (1, 0, 1), (1, 0, 2), (1, 1, 1), (1, 1, 2)]:
             try:
                 plan.set_tuning(p3d_zc=zc, p3d_dma=dma, p3d_skip=skip, p3d_cm=cm)
             except SipoError as e:
-                assert dma == 1 and (zc < 16 or not default["p3d_dma"]), (zc, dma, e)
+                assert (dma == 1 and (zc < 16 or not default["p3d_dma"])) or (zc == 64 and dma == 0), (zc, dma, e)
                 continue
             assert plan.tuning()["p3d_zc"] == zc and plan.tuning()["p3d_cm"] == cm
             fp = plan.project(vol_d).double().cpu().numpy()
             assert rel_norm(fp, fp_ref) < F32_NORM_TOL, (zc, dma, skip, cm)
             ran_async += dma
-    assert ran_async == 8 or not default["p3d_dma"]
+    assert ran_async == 12 or not default["p3d_dma"]
+    sino = uniform_field(g.sino_shape, 12)
+    bp_ref = P.backproject(sino)
+    for bzc in (8, 16, 32):
+        plan.set_tuning(bp3d_zc=bzc)
+        bp = plan.backproject(to_gpu(sino, torch.float32)).double().cpu().numpy()
+        assert rel_norm(bp, bp_ref) < F32_NORM_TOL, bzc
     for bzc in (0, 8, 16, 32):
         if bzc > nz:
             with pytest.raises(SipoError):
@@ -237,8 +243,8 @@ def test_set_tuning_rejects_invalid_settings():
     from paper_2604_08997_amd import SipoError
     p64 = plan_for(24, 20, nz=8, dtype=torch.float64)
     before = p64.tuning()
-    for bad in [dict(p3d_zc=32), dict(p3d_zc=12), dict(p3d_dma=1), dict(p3d_cm=3), dict(p3d_skip=1, p3d_dma=0),
-                dict(blur_zc=16)]:
+    for bad in [dict(p3d_zc=32), dict(p3d_zc=64), dict(p3d_zc=12), dict(p3d_dma=1), dict(p3d_cm=3),
+                dict(p3d_skip=1, p3d_dma=0), dict(blur_zc=16), dict(bp3d_zc=32), dict(bp3d_zc=4)]:
         with pytest.raises(SipoError):
             p64.set_tuning(**bad)
         assert p64.tuning() == before
