@@ -112,6 +112,7 @@ int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype 
     }
     p->d_batches = nullptr;
     p->d_partner = nullptr;
+    p->d_view_batch = nullptr;
     p->d_ranges = nullptr;
     p->d_vial_rows = nullptr;
     p->d_zero = nullptr;
@@ -127,6 +128,7 @@ int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype 
         (void)hipFree(p->d_trig); (void)hipFree(p->d_angle_order); (void)hipFree(p->d_scratch);
         (void)hipFree(p->d_batches);
         (void)hipFree(p->d_partner);
+        (void)hipFree(p->d_view_batch);
         (void)hipFree(p->d_ranges);
         (void)hipFree(p->d_vial_rows);
         (void)hipFree(p->d_zero);
@@ -151,6 +153,7 @@ int sipo_plan_destroy(sipo_plan p) {
     (void)hipFree(p->d_scratch);
     (void)hipFree(p->d_batches);
     (void)hipFree(p->d_partner);
+    (void)hipFree(p->d_view_batch);
     (void)hipFree(p->d_ranges);
     (void)hipFree(p->d_vial_rows);
     (void)hipFree(p->d_zero);

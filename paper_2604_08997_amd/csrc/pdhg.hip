@@ -566,6 +566,11 @@ struct Layout {
     size_t eb = 4;
     bool lohi = false;                          // per-voxel bounds packed (some instance has arrays)
     size_t vol_t_elems = 0;                     // internal-layout volume scratch (largest 3D instance)
+    std::vector<size_t> pfo, bfo;               // byte offsets of each 3D instance's skip flags
+    size_t pf_bytes = 0, bf_bytes = 0;          // projector / backprojector flag totals
+    size_t pflags = 0, bflags = 0;              // their fields
+    size_t part_s = 0, part_v = 0;              // elements of the largest 3D instance's sinogram / volume
+    size_t ppart = 0, bpart = 0;                // partial sums of the split 3D operators
     // sinogram fields
     size_t y, q, Tj, yt, y0, ylast, act;
     // volume fields
@@ -576,6 +581,9 @@ struct Layout {
         items_fp, items_tr;
     size_t total = 0;
 };
+
+// Largest splits of the 3D projector's march and of the backprojector's views in LP solves.
+constexpr int kMaxSplitP = 4, kMaxSplitB = 8;
 
 static bool use_batch2d(const sipo_problem *probs, int B) {
     for (int i = 0; i < B; ++i) {
@@ -591,6 +599,8 @@ static Layout make_layout(const sipo_problem *probs, int B) {
     L.eb = probs[0].plan->elem_bytes();
     L.soff.resize(B);
     L.voff.resize(B);
+    L.pfo.assign(B, 0);
+    L.bfo.assign(B, 0);
     const bool b2d = use_batch2d(probs, B);
     for (int i = 0; i < B; ++i) {
         const sipo_plan p = probs[i].plan;
@@ -602,7 +612,16 @@ static Layout make_layout(const sipo_problem *probs, int B) {
         L.max_seg_s += (int)((ns + kChunk - 1) / kChunk);
         L.max_seg_v += (int)((nv + kChunk - 1) / kChunk);
         if (probs[i].lo || probs[i].hi) L.lohi = true;
-        if (p->fast3d()) L.vol_t_elems = std::max(L.vol_t_elems, (size_t)nv);
+        if (p->fast3d()) {
+            L.vol_t_elems = std::max(L.vol_t_elems, (size_t)nv);
+            L.pfo[i] = L.pf_bytes;
+            L.bfo[i] = L.bf_bytes;
+            // room for the finest slice counts the solve may switch to (8 and 4 slices per thread)
+            L.pf_bytes += align_up(p3d_flag_count(p, 8));
+            L.bf_bytes += align_up(bp3d_flag_count(p, 4));
+            L.part_s = std::max(L.part_s, (size_t)ns);
+            L.part_v = std::max(L.part_v, (size_t)nv);
+        }
         if (b2d) {
             const Geo2D g = plan_geo2d(p, 0, 0);
             std::vector<int4> a, b, c;
@@ -627,6 +646,10 @@ static Layout make_layout(const sipo_problem *probs, int B) {
     L.lo = L.lohi ? take(vb) : 0;
     L.hi = L.lohi ? take(vb) : 0;
     L.vol_t = take(L.vol_t_elems * L.eb);
+    L.pflags = take(L.pf_bytes);
+    L.bflags = take(L.bf_bytes);
+    L.ppart = take(L.part_s * L.eb * kMaxSplitP);
+    L.bpart = take(L.part_v * L.eb * kMaxSplitB);
     const int max_seg = std::max(std::max(L.max_seg_s, L.max_seg_v), 1);
     L.partials = take(sizeof(double) * kNS * max_seg);
     L.insts = take(sizeof(InstC) * B);
@@ -683,6 +706,10 @@ class Solver {
         }
     }
     ~Solver() {
+        for (auto &e : zc_saved_) {
+            e.first->p3d_zc = e.second.first;
+            e.first->bp3d_zc = e.second.second;
+        }
         if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
         for (hipEvent_t e : ev_) (void)hipEventDestroy(e);
     }
@@ -708,6 +735,11 @@ class Solver {
     const Layout &L_;
     hipStream_t s_;
     bool b2d_ = false;
+    bool mask_ = false;                     // 3D operators skip workgroups the LP does not read
+    std::vector<SplitSpec> psp_, bsp_;      // per instance: splits of the masked 3D operators
+    // slices per thread the masked operators run with, per plan, and the plans' own settings, which the
+    // solver restores when it ends
+    std::vector<std::pair<sipo_plan, std::pair<int, int>>> zc_choice_, zc_saved_;
     int nc_max_ = 3;
     bool bp_staged_ = true;
     int n_max_ = 1;
@@ -859,14 +891,17 @@ class Solver {
             const Inst &I = in_[i];
             const T *y = F(yf) + I.soff;
             T *out = F(outf) + I.voff;
+            const bool m = mask_ && I.t3;
+            const uint8_t *on = m ? U8(L_.bflags) + L_.bfo[i] : nullptr;
+            const SplitSpec sp = m ? bsp_[i] : SplitSpec();
             if (!I.p->has_psf) {
-                int rc = launch_backproject_t(I.p, y, out, 0, s_);
+                int rc = launch_backproject_t(I.p, y, out, 0, s_, on, sp);
                 if (!rc) rc = mark(SIPO_PHASE_BACKPROJECT);
                 if (rc) return rc;
                 continue;
             }
             T *tmp = F(L_.tmp) + I.voff;
-            int rc = launch_backproject_t(I.p, y, tmp, 0, s_);
+            int rc = launch_backproject_t(I.p, y, tmp, 0, s_, on, sp);
             if (!rc) rc = mark(SIPO_PHASE_BACKPROJECT);
             if (!rc) rc = launch_blur(I.p, tmp, out, s_);
             if (!rc) rc = mark(SIPO_PHASE_BLUR);
@@ -899,7 +934,11 @@ class Solver {
                 if (!rc) rc = mark(SIPO_PHASE_TRANSPOSE);
                 src = F(L_.vol_t);
             }
-            if (!rc) rc = launch_project_t(I.p, src, out, s_);
+            if (!rc) {
+                const bool m = mask_ && I.t3;
+                rc = launch_project_t(I.p, src, out, s_, m ? U8(L_.pflags) + L_.pfo[i] : nullptr,
+                                      m ? psp_[i] : SplitSpec());
+            }
             if (!rc) rc = mark(SIPO_PHASE_PROJECT);
             if (rc) return rc;
         }
@@ -1069,6 +1108,102 @@ int Solver<T>::setup_common() {
     if (!rc) rc = put_insts();
     if (rc) return rc;
     hipLaunchKernelGGL((k_project_y<T>), gS(), dim3(kThreads), 0, s_, F(L_.y), (const uint8_t *)U8(L_.act), segS());
+    if (o_.mode == SIPO_PDHG_RESTARTED) {
+        // From here on the 3D operators skip what the restarted scheme never reads: q = P K z off the
+        // active rays, and P^T y away from the labelled voxels and their PSF neighbourhood (every row
+        // scaling, residual and certificate test reads D on labelled voxels and q on active rays).
+        // Few workgroups stay on, each with a long serial walk.  Per plan, the masked operators are timed
+        // at the plan's slices per thread and at half of it (finer chunks give more workgroups), and the
+        // backprojector's view walk is split so that the switched-on tiles fill the chip; the projector's
+        // march is split only when very few of its workgroups stay on.
+        int cus = 256;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, probs_[0].plan->device);
+        psp_.assign(B_, SplitSpec());
+        bsp_.assign(B_, SplitSpec());
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        SIPO_HIP(hipEventCreate(&e0));
+        SIPO_HIP(hipEventCreate(&e1));
+        auto timed = [&](auto &&fn) -> float {
+            float best = 1e30f;
+            if (fn() != SIPO_OK) return -1.f;
+            for (int r = 0; r < 3; ++r) {
+                float ms = 0.f;
+                if (hipEventRecord(e0, s_) != hipSuccess || fn() != SIPO_OK || hipEventRecord(e1, s_) != hipSuccess ||
+                    hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                    return -1.f;
+                best = std::min(best, ms);
+            }
+            return best;
+        };
+        auto count_on = [&](size_t flags_off, size_t count) -> long long {
+            std::vector<uint8_t> h(count);
+            if (count && hipMemcpyAsync(h.data(), U8(flags_off), count, hipMemcpyDeviceToHost, s_) != hipSuccess)
+                return -1;
+            if (hipStreamSynchronize(s_) != hipSuccess) return -1;
+            long long on = 0;
+            for (uint8_t f : h) on += f ? 1 : 0;
+            return on;
+        };
+        auto parts_for = [&](long long on, long long want, int max_parts) {
+            if (on <= 0) return 1;
+            return (int)std::min<long long>(max_parts, std::max<long long>(1, (want + on - 1) / on));
+        };
+        int rc2 = SIPO_OK;
+        for (int i = 0; i < B_ && !rc2; ++i) {
+            const Inst &I = in_[i];
+            if (!I.t3) continue;
+            sipo_plan p = I.p;
+            const uint8_t *pf = U8(L_.pflags) + L_.pfo[i], *bf = U8(L_.bflags) + L_.bfo[i];
+            int choice = -1;
+            for (size_t k = 0; k < zc_choice_.size(); ++k)
+                if (zc_choice_[k].first == p) choice = (int)k;
+            if (choice < 0) {
+                zc_saved_.push_back({p, {p->p3d_zc, p->bp3d_zc}});
+                // projector: the plan's slices and half of them (the asynchronous variant takes 8 or more)
+                std::vector<int> pc = {p->p3d_zc}, bc = {p->bp3d_zc};
+                if (p->p3d_zc / 2 >= 8) pc.push_back(p->p3d_zc / 2);
+                if (p->bp3d_zc / 2 >= 4) bc.push_back(p->bp3d_zc / 2);
+                int bpz = p->p3d_zc, bbz = p->bp3d_zc;
+                float tp = 1e30f, tb = 1e30f;
+                for (int zc : pc) {
+                    p->p3d_zc = zc;
+                    rc2 = launch_p3d_flags(p, U8(L_.act) + I.soff, U8(L_.pflags) + L_.pfo[i], s_);
+                    const long long on = rc2 ? -1 : count_on(L_.pflags + L_.pfo[i], p3d_flag_count(p));
+                    if (on < 0) { rc2 = rc2 ? rc2 : fail(SIPO_E_DEVICE, "pdhg setup: reading skip flags failed"); break; }
+                    const SplitSpec sp{parts_for(on, cus, kMaxSplitP), F(L_.ppart)};
+                    const float t = timed([&] { return launch_project_t(p, F(L_.vol_t), F(L_.q) + I.soff, s_, pf, sp); });
+                    if (t >= 0.f && t < tp) { tp = t; bpz = zc; }
+                }
+                for (int zc : bc) {
+                    if (rc2) break;
+                    p->bp3d_zc = zc;
+                    rc2 = launch_bp3d_flags(p, U8(L_.lab) + I.voff, U8(L_.bflags) + L_.bfo[i], s_);
+                    const long long on = rc2 ? -1 : count_on(L_.bflags + L_.bfo[i], bp3d_flag_count(p));
+                    if (on < 0) { rc2 = rc2 ? rc2 : fail(SIPO_E_DEVICE, "pdhg setup: reading skip flags failed"); break; }
+                    const SplitSpec sp{parts_for(on, 4LL * cus, kMaxSplitB), F(L_.bpart)};
+                    const float t = timed([&] { return launch_backproject_t(p, F(L_.y) + I.soff, F(L_.tmp) + I.voff, 0, s_, bf, sp); });
+                    if (t >= 0.f && t < tb) { tb = t; bbz = zc; }
+                }
+                p->p3d_zc = bpz;
+                p->bp3d_zc = bbz;
+                zc_choice_.push_back({p, {bpz, bbz}});
+            }
+            if (rc2) break;
+            // flags and splits of this instance at the plan's chosen slices
+            rc2 = launch_p3d_flags(p, U8(L_.act) + I.soff, U8(L_.pflags) + L_.pfo[i], s_);
+            if (!rc2) rc2 = launch_bp3d_flags(p, U8(L_.lab) + I.voff, U8(L_.bflags) + L_.bfo[i], s_);
+            if (rc2) break;
+            const long long onp = count_on(L_.pflags + L_.pfo[i], p3d_flag_count(p));
+            const long long onb = count_on(L_.bflags + L_.bfo[i], bp3d_flag_count(p));
+            if (onp < 0 || onb < 0) { rc2 = fail(SIPO_E_DEVICE, "pdhg setup: reading skip flags failed"); break; }
+            psp_[i] = SplitSpec{parts_for(onp, cus, kMaxSplitP), F(L_.ppart)};
+            bsp_[i] = SplitSpec{parts_for(onb, 4LL * cus, kMaxSplitB), F(L_.bpart)};
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc2) return rc2;
+        mask_ = true;
+    }
     rc = lambda_z(L_.lu, L_.ll, L_.z, false);
     if (!rc) rc = finish(true, all, 2);
     if (rc) return rc;
@@ -1570,6 +1705,16 @@ int Solver<T>::run(sipo_pdhg_result *res) {
         if (rc) return rc;
         rc = set_active(all);
         if (rc) return rc;
+    }
+    if (mask_) {
+        // a requested dose is returned on the whole volume
+        bool full = false;
+        for (int i = 0; i < B_; ++i) full = full || (probs_[i].dose_out && in_[i].t3);
+        mask_ = false;
+        if (full) {
+            rc = dose(L_.y, L_.D);
+            if (rc) return rc;
+        }
     }
     rc = unpack();
     if (rc) return rc;

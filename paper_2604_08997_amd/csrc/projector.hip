@@ -149,15 +149,28 @@ template <typename T, int ZC>
 __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict__ sino_t, T *__restrict__ vol, int n,
                                                             int nz, int n_angles, int nb,
                                                             const double2 *__restrict__ trig, double h,
-                                                            double inv_ds, T atten, int accumulate) {
+                                                            double inv_ds, T atten, int accumulate,
+                                                            const uint8_t *__restrict__ tile_on, int nsplit,
+                                                            long long split_stride) {
     using V4 = typename Vec4<T>::type;
     constexpr int Z4 = ZC / 4, ZP = ZC + 4;
     __shared__ __align__(16) T lds[kBpTB][kBpW][ZP];
     __shared__ int bmin_s[kBpTB];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    const int x0 = blockIdx.x * kBpTX, y0 = blockIdx.y * kBpTY, z0 = blockIdx.z * ZC;
+    // grid.z = z chunks x view splits; split s sums its share of the views into partial sum s
+    const int nzc = gridDim.z / nsplit, zb = blockIdx.z % nzc, split = blockIdx.z / nzc;
+    const int x0 = blockIdx.x * kBpTX, y0 = blockIdx.y * kBpTY, z0 = zb * ZC;
     const int c = x0 + tx;
     const int r[2] = {y0 + ty, y0 + ty + 8};
+    if (tile_on && !tile_on[((size_t)zb * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x]) {
+        // no voxel of the tile is needed: write zeros (or leave an accumulated output as it is);
+        // with splits the reduction writes those zeros
+        if (!accumulate && nsplit == 1)
+            for (int j = 0; j < 2; ++j)
+                if (c < n && r[j] < n)
+                    for (int k = 0; k < ZC && z0 + k < nz; ++k) vol[((size_t)(z0 + k) * n + r[j]) * n + c] = (T)0;
+        return;
+    }
     const double xv = centre(c, h);
     const double yv[2] = {centre(r[0], h), centre(r[1], h)};
     bool inside[2];
@@ -170,8 +183,10 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
         for (int k = 0; k < ZC; ++k) acc[j][k] = (T)0;
     const bool vec_ok = (nz & 3) == 0;
     const int cx1 = min(x0 + kBpTX, n) - 1, cy1 = min(y0 + kBpTY, n) - 1;
-    for (int a0 = 0; a0 < n_angles; a0 += kBpTB) {
-        const int na = min(kBpTB, n_angles - a0);
+    const int nvb = (n_angles + kBpTB - 1) / kBpTB, per = (nvb + nsplit - 1) / nsplit;
+    const int a_beg = split * per * kBpTB, a_end = min(n_angles, (split + 1) * per * kBpTB);
+    for (int a0 = a_beg; a0 < a_end; a0 += kBpTB) {
+        const int na = min(kBpTB, a_end - a0);
         if ((int)threadIdx.x < na) {
             const double2 tr = trig[a0 + threadIdx.x];
             double umin = 1e300;
@@ -236,10 +251,23 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
 #pragma unroll
         for (int k = 0; k < ZC; ++k) {
             if (z0 + k < nz) {
-                const size_t idx = ((size_t)(z0 + k) * n + r[j]) * n + c;
+                const size_t idx = (size_t)split * split_stride + ((size_t)(z0 + k) * n + r[j]) * n + c;
                 vol[idx] = accumulate ? vol[idx] + acc[j][k] : acc[j][k];
             }
         }
+    }
+}
+
+// Sum of the view splits' partial volumes on switched-on tiles, zero elsewhere (fixed order).
+template <typename T>
+__global__ void k_bp3d_reduce(const T *__restrict__ part, T *__restrict__ vol, const uint8_t *__restrict__ tile_on,
+                              int n, int nz, int zc, int gx, int gy, int nsplit, long long total) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
+        T v = (T)0;
+        if (!tile_on || tile_on[((size_t)(z / zc) * gy + y / kBpTY) * gx + x / kBpTX])
+            for (int k = 0; k < nsplit; ++k) v += part[(size_t)k * total + i];
+        vol[i] = v;
     }
 }
 
@@ -269,7 +297,7 @@ __global__ void __launch_bounds__(256) project3d_kernel(const T *__restrict__ vo
                                                         const int *__restrict__ order,
                                                         const int *__restrict__ partner,
                                                         const int4 *__restrict__ batches, double h, double inv_ds,
-                                                        T atten) {
+                                                        T atten, const uint8_t *__restrict__ wg_on) {
     using V4 = typename Vec4<T>::type;
     constexpr int Z4 = ZC / 4;
     constexpr int NR = PAIR ? 2 : 1;
@@ -282,6 +310,16 @@ __global__ void __launch_bounds__(256) project3d_kernel(const T *__restrict__ vo
     const bool xmajor = bt.z != 0;
     const bool active = tk < bt.y && b < nb;
     const int a = order[bt.x + min(tk, bt.y - 1)];
+    if (wg_on && !wg_on[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * gridDim.z + blockIdx.z]) {
+        // none of this workgroup's rays is active: their outputs are zero
+        if (active)
+            for (int r = 0; r < NR; ++r) {
+                T *dst = r == 0 ? sino_t + ((size_t)a * nb + b) * nz + z0
+                                : sino_t + ((size_t)partner[a] * nb + (nb - 1 - b)) * nz + z0;
+                for (int k = 0; k < ZC && z0 + k < nz; ++k) dst[k] = (T)0;
+            }
+        return;
+    }
     const double2 tr = trig[a];
     const double sn = tr.x, cs = tr.y;
     // affine frame: s(m, j) = s00 + m dsm + j dsj, t(m, j) = t00 + m dtm + j dtj, u = (s + 1) inv_ds - 1/2
@@ -432,7 +470,8 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     const float *__restrict__ vol_t, float *__restrict__ sino_t, int n, int nz, int nb,
     const double2 *__restrict__ trig, const int *__restrict__ order, const int *__restrict__ partner,
     const int4 *__restrict__ batches, const int2 *__restrict__ ranges, const int2 *__restrict__ vial_rows,
-    const float4 *__restrict__ zero16, double h, double inv_ds, float atten) {
+    const float4 *__restrict__ zero16, double h, double inv_ds, float atten, const uint8_t *__restrict__ wg_on,
+    int nsplit, long long split_stride) {
     static_assert(CM >= 1 && CM <= kDmaMaxCM, "chunk length");
     constexpr int Z4 = ZC / 4, RS = kPCR + 1, SLOTS = CM * Z4 * RS, PER = (SLOTS + 255) / 256;
     constexpr int NR = PAIR ? 2 : 1;
@@ -446,10 +485,23 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     const int lane = tid & 63, wv = tid >> 6;
     const int tb = (lane & 7) | ((lane >> 4) << 3), tk = 2 * wv + ((lane >> 3) & 1);
     const int b = blockIdx.x * kPB + tb;
-    const int z0 = blockIdx.z * ZC;
+    // grid.z = z chunks x march splits; split s walks its share of the chunks into partial sum s
+    const int nzc = gridDim.z / nsplit, zb = blockIdx.z % nzc, split = blockIdx.z / nzc;
+    const int z0 = zb * ZC;
     const bool xmajor = bt.z != 0;
     const bool active = tk < bt.y && b < nb;
     const int a = order[bt.x + min(tk, bt.y - 1)];
+    if (wg_on && !wg_on[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * nzc + zb]) {
+        // none of this workgroup's rays is active: their outputs are zero (before any barrier);
+        // with splits the reduction writes those zeros
+        if (active && nsplit == 1)
+            for (int r = 0; r < NR; ++r) {
+                float4 *dst = (float4 *)(r == 0 ? sino_t + ((size_t)a * nb + b) * nz + z0
+                                                : sino_t + ((size_t)partner[a] * nb + (nb - 1 - b)) * nz + z0);
+                for (int z4 = 0; z4 < Z4 && z0 + 4 * z4 < nz; ++z4) dst[z4] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        return;
+    }
     const double2 tr = trig[a];
     const double sn = tr.x, cs = tr.y;
     const double c0 = centre(0, h);
@@ -566,23 +618,25 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
         }
     };
 
-    issue(bufA, 0);
-    for (int k = 0; k < nch; k += 2) {
+    const int per = (nch + nsplit - 1) / nsplit, kb = split * per, ke = min(nch, kb + per);
+    if (kb < ke) issue(bufA, kb);
+    for (int k = kb; k < ke; k += 2) {
         __builtin_amdgcn_s_waitcnt(0);   // this thread's copies into bufA have landed
         lds_barrier();                   // everyone's have; bufB is no longer being read
-        if (k + 1 < nch) issue(bufB, k + 1);
+        if (k + 1 < ke) issue(bufB, k + 1);
         if (active) compute(bufA, k);
-        if (k + 1 >= nch) break;
+        if (k + 1 >= ke) break;
         __builtin_amdgcn_s_waitcnt(0);
         lds_barrier();
-        if (k + 2 < nch) issue(bufA, k + 2);
+        if (k + 2 < ke) issue(bufA, k + 2);
         if (active) compute(bufB, k + 1);
     }
     if (!active) return;
+    float *out = sino_t + (size_t)split * split_stride;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        float *dst = r == 0 ? sino_t + ((size_t)a * nb + b) * nz + z0
-                            : sino_t + ((size_t)partner[a] * nb + (nb - 1 - b)) * nz + z0;
+        float *dst = r == 0 ? out + ((size_t)a * nb + b) * nz + z0
+                            : out + ((size_t)partner[a] * nb + (nb - 1 - b)) * nz + z0;
 #pragma unroll
         for (int z4 = 0; z4 < Z4; ++z4) {
             if (z0 + 4 * z4 < nz) {
@@ -795,6 +849,16 @@ int plan_build_batches(sipo_plan p, const double2 *trig) {
     SIPO_HIP(hipMemcpy(p->d_vial_rows, vial.data(), sizeof(int2) * vial.size(), hipMemcpyHostToDevice));
     SIPO_HIP(hipMalloc(&p->d_zero, 256));
     SIPO_HIP(hipMemset(p->d_zero, 0, 256));
+    // batch of every view (2 * batch, plus 1 for the opposite view of a walked one), -1 if unwalked
+    std::vector<int> vbatch(p->n_angles, -1);
+    for (size_t bi = 0; bi < batches.size(); ++bi)
+        for (int k = batches[bi].x; k < batches[bi].x + batches[bi].y; ++k) {
+            const int v = order[k];
+            vbatch[v] = 2 * (int)bi;
+            if (pair && opp[v] >= 0) vbatch[opp[v]] = 2 * (int)bi + 1;
+        }
+    SIPO_HIP(hipMalloc(&p->d_view_batch, sizeof(int) * p->n_angles));
+    SIPO_HIP(hipMemcpy(p->d_view_batch, vbatch.data(), sizeof(int) * p->n_angles, hipMemcpyHostToDevice));
     SIPO_HIP(hipMalloc(&p->d_batches, sizeof(int4) * std::max<size_t>(batches.size(), 1)));
     SIPO_HIP(hipMalloc(&p->d_partner, sizeof(int) * p->n_angles));
     if (!batches.empty())
@@ -842,20 +906,30 @@ static int fp_slices(sipo_plan p, const void *vol, void *sino, int accumulate, h
 }
 
 template <typename T, int ZC>
-static void bp3d_zc(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s) {
+static void bp3d_zc(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s, const uint8_t *on,
+                    const SplitSpec &sp) {
     const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
-    const dim3 grid((p->n + kBpTX - 1) / kBpTX, (p->n + kBpTY - 1) / kBpTY, (p->nz + ZC - 1) / ZC);
-    hipLaunchKernelGGL((backproject3d_kernel<T, ZC>), grid, dim3(256), 0, s, (const T *)sino_t, (T *)vol, p->n, p->nz,
-                       p->n_angles, p->n_bins, p->d_trig, h, inv_ds, (T)p->atten, accumulate);
+    const int ns = (sp.parts > 1 && !accumulate) ? sp.parts : 1;
+    const int gx = (p->n + kBpTX - 1) / kBpTX, gy = (p->n + kBpTY - 1) / kBpTY, gz = (p->nz + ZC - 1) / ZC;
+    hipLaunchKernelGGL((backproject3d_kernel<T, ZC>), dim3(gx, gy, gz * ns), dim3(256), 0, s, (const T *)sino_t,
+                       (T *)(ns > 1 ? sp.partial : vol), p->n, p->nz, p->n_angles, p->n_bins, p->d_trig, h, inv_ds,
+                       (T)p->atten, accumulate, on, ns, (long long)p->vol_elems());
+    if (ns > 1) {
+        const long long total = (long long)p->vol_elems();
+        hipLaunchKernelGGL((k_bp3d_reduce<T>), dim3((unsigned)std::min<long long>((total + 255) / 256, 16384)), dim3(256),
+                           0, s, (const T *)sp.partial, (T *)vol, on, p->n, p->nz, ZC, gx, gy, ns, total);
+    }
 }
 
 template <typename T>
-static int bp3d(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s) {
+static int bp3d(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s, const uint8_t *on,
+                const SplitSpec &sp) {
     switch (p->bp3d_zc) {
-        case 8: bp3d_zc<T, 8>(p, sino_t, vol, accumulate, s); break;
-        case 16: bp3d_zc<T, 16>(p, sino_t, vol, accumulate, s); break;
+        case 4: bp3d_zc<T, 4>(p, sino_t, vol, accumulate, s, on, sp); break;
+        case 8: bp3d_zc<T, 8>(p, sino_t, vol, accumulate, s, on, sp); break;
+        case 16: bp3d_zc<T, 16>(p, sino_t, vol, accumulate, s, on, sp); break;
         case 32:
-            if constexpr (sizeof(T) == 4) { bp3d_zc<T, 32>(p, sino_t, vol, accumulate, s); break; }
+            if constexpr (sizeof(T) == 4) { bp3d_zc<T, 32>(p, sino_t, vol, accumulate, s, on, sp); break; }
             else return fail(SIPO_E_UNSUPPORTED, "3D backprojector: 32 slices per thread in FP64");
         default: return fail(SIPO_E_UNSUPPORTED, "3D backprojector: %d slices per thread", p->bp3d_zc);
     }
@@ -864,54 +938,89 @@ static int bp3d(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipS
 }
 
 template <typename T, int ZC, int NC>
-static void fp3d_nc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+static void fp3d_nc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on) {
     const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
     const dim3 grid((p->n_bins + kPB - 1) / kPB, p->n_batches, (p->nz + ZC - 1) / ZC);
     if (p->p3d_pair)
         hipLaunchKernelGGL((project3d_kernel<T, ZC, NC, true>), grid, dim3(256), 0, s, (const T *)vol_t, (T *)sino_t,
                            p->n, p->nz, p->n_bins, p->d_trig, p->d_angle_order, p->d_partner, p->d_batches, h, inv_ds,
-                           (T)p->atten);
+                           (T)p->atten, on);
     else
         hipLaunchKernelGGL((project3d_kernel<T, ZC, NC, false>), grid, dim3(256), 0, s, (const T *)vol_t,
                            (T *)sino_t, p->n, p->nz, p->n_bins, p->d_trig, p->d_angle_order, p->d_partner,
-                           p->d_batches, h, inv_ds, (T)p->atten);
+                           p->d_batches, h, inv_ds, (T)p->atten, on);
+}
+
+// Sum of the march splits' partial sinograms ([view][bin][z], four slices per element) on
+// switched-on workgroups, zero elsewhere (fixed order).
+__global__ void k_p3d_reduce(const float4 *__restrict__ part, float4 *__restrict__ out,
+                             const uint8_t *__restrict__ wg_on, const int *__restrict__ view_batch, int n_angles, int nb,
+                             int nz, int ngroups, int zc, int nzc, int nsplit, long long total4) {
+    const int nz4 = nz / 4;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total4; i += (long long)gridDim.x * blockDim.x) {
+        const int z = (int)(i % nz4) * 4;
+        const long long ab = i / nz4;
+        const int bin = (int)(ab % nb), a = (int)(ab / nb);
+        const int vb = view_batch[a];
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (vb >= 0) {
+            const int b = (vb & 1) ? nb - 1 - bin : bin;
+            if (!wg_on || wg_on[((size_t)(vb >> 1) * ngroups + b / kPB) * nzc + z / zc])
+                for (int k = 0; k < nsplit; ++k) {
+                    const float4 w = part[(size_t)k * total4 + i];
+                    v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
+                }
+        }
+        out[i] = v;
+    }
 }
 
 template <int ZC, int NC, bool PAIR, bool SKIP, int CM>
-static void fp3d_dma_launch(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+static void fp3d_dma_launch(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
+                            const SplitSpec &sp) {
     const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
-    const dim3 grid((p->n_bins + kPB - 1) / kPB, p->n_batches, (p->nz + ZC - 1) / ZC);
+    const int ns = sp.parts > 1 ? sp.parts : 1;
+    const dim3 grid((p->n_bins + kPB - 1) / kPB, p->n_batches, ((p->nz + ZC - 1) / ZC) * ns);
     hipLaunchKernelGGL((project3d_dma_kernel<ZC, NC, PAIR, SKIP, CM>), grid, dim3(256), 0, s, (const float *)vol_t,
-                       (float *)sino_t, p->n, p->nz, p->n_bins, p->d_trig, p->d_angle_order, p->d_partner,
-                       p->d_batches, p->d_ranges, p->d_vial_rows, (const float4 *)p->d_zero, h, inv_ds,
-                       (float)p->atten);
+                       (float *)(ns > 1 ? sp.partial : sino_t), p->n, p->nz, p->n_bins, p->d_trig, p->d_angle_order,
+                       p->d_partner, p->d_batches, p->d_ranges, p->d_vial_rows, (const float4 *)p->d_zero, h, inv_ds,
+                       (float)p->atten, on, ns, (long long)p->sino_elems());
+    if (ns > 1) {
+        const long long total4 = (long long)p->sino_elems() / 4;
+        hipLaunchKernelGGL(k_p3d_reduce, dim3((unsigned)std::min<long long>((total4 + 255) / 256, 16384)), dim3(256), 0,
+                           s, (const float4 *)sp.partial, (float4 *)sino_t, on, p->d_view_batch, p->n_angles, p->n_bins,
+                           p->nz, (p->n_bins + kPB - 1) / kPB, ZC, (p->nz + ZC - 1) / ZC, ns, total4);
+    }
 }
 
 template <int ZC, int NC, bool PAIR, bool SKIP>
-static void fp3d_dma_go(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
-    if (p->p3d_cm == 1) fp3d_dma_launch<ZC, NC, PAIR, SKIP, 1>(p, vol_t, sino_t, s);
-    else fp3d_dma_launch<ZC, NC, PAIR, SKIP, kDmaMaxCM>(p, vol_t, sino_t, s);
+static void fp3d_dma_go(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
+                        const SplitSpec &sp) {
+    if (p->p3d_cm == 1) fp3d_dma_launch<ZC, NC, PAIR, SKIP, 1>(p, vol_t, sino_t, s, on, sp);
+    else fp3d_dma_launch<ZC, NC, PAIR, SKIP, kDmaMaxCM>(p, vol_t, sino_t, s, on, sp);
 }
 
 template <int ZC, int NC>
-static void fp3d_dma_nc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+static void fp3d_dma_nc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
+                        const SplitSpec &sp) {
     if (p->p3d_pair) {
-        if (p->p3d_skip) fp3d_dma_go<ZC, NC, true, true>(p, vol_t, sino_t, s);
-        else fp3d_dma_go<ZC, NC, true, false>(p, vol_t, sino_t, s);
+        if (p->p3d_skip) fp3d_dma_go<ZC, NC, true, true>(p, vol_t, sino_t, s, on, sp);
+        else fp3d_dma_go<ZC, NC, true, false>(p, vol_t, sino_t, s, on, sp);
     } else {
-        if (p->p3d_skip) fp3d_dma_go<ZC, NC, false, true>(p, vol_t, sino_t, s);
-        else fp3d_dma_go<ZC, NC, false, false>(p, vol_t, sino_t, s);
+        if (p->p3d_skip) fp3d_dma_go<ZC, NC, false, true>(p, vol_t, sino_t, s, on, sp);
+        else fp3d_dma_go<ZC, NC, false, false>(p, vol_t, sino_t, s, on, sp);
     }
 }
 
 template <typename T, int ZC>
-static int fp3d_zc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
-    if constexpr (sizeof(T) == 4 && ZC >= 16) {
+static int fp3d_zc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
+                   const SplitSpec &sp) {
+    if constexpr (sizeof(T) == 4 && ZC >= 8) {
         if (p->p3d_dma) {
             switch (p->p3d_nc) {
-                case 3: fp3d_dma_nc<ZC, 3>(p, vol_t, sino_t, s); break;
-                case 4: fp3d_dma_nc<ZC, 4>(p, vol_t, sino_t, s); break;
-                case 6: fp3d_dma_nc<ZC, 6>(p, vol_t, sino_t, s); break;
+                case 3: fp3d_dma_nc<ZC, 3>(p, vol_t, sino_t, s, on, sp); break;
+                case 4: fp3d_dma_nc<ZC, 4>(p, vol_t, sino_t, s, on, sp); break;
+                case 6: fp3d_dma_nc<ZC, 6>(p, vol_t, sino_t, s, on, sp); break;
                 default: return fail(SIPO_E_UNSUPPORTED, "3D projector: unsupported candidate count");
             }
             return SIPO_OK;
@@ -921,9 +1030,9 @@ static int fp3d_zc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) 
         return fail(SIPO_E_UNSUPPORTED, "3D projector: %d slices per thread need the asynchronous variant", ZC);
     } else {
     switch (p->p3d_nc) {
-        case 3: fp3d_nc<T, ZC, 3>(p, vol_t, sino_t, s); break;
-        case 4: fp3d_nc<T, ZC, 4>(p, vol_t, sino_t, s); break;
-        case 6: fp3d_nc<T, ZC, 6>(p, vol_t, sino_t, s); break;
+        case 3: fp3d_nc<T, ZC, 3>(p, vol_t, sino_t, s, on); break;
+        case 4: fp3d_nc<T, ZC, 4>(p, vol_t, sino_t, s, on); break;
+        case 6: fp3d_nc<T, ZC, 6>(p, vol_t, sino_t, s, on); break;
         default: return fail(SIPO_E_UNSUPPORTED, "3D projector: unsupported candidate count");
     }
     return SIPO_OK;
@@ -931,17 +1040,18 @@ static int fp3d_zc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) 
 }
 
 template <typename T>
-static int fp3d(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+static int fp3d(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
+                const SplitSpec &sp) {
     int rc;
     switch (p->p3d_zc) {
-        case 8: rc = fp3d_zc<T, 8>(p, vol_t, sino_t, s); break;
-        case 16: rc = fp3d_zc<T, 16>(p, vol_t, sino_t, s); break;
+        case 8: rc = fp3d_zc<T, 8>(p, vol_t, sino_t, s, on, sp); break;
+        case 16: rc = fp3d_zc<T, 16>(p, vol_t, sino_t, s, on, sp); break;
         case 32:
-            if constexpr (sizeof(T) == 4) rc = fp3d_zc<T, 32>(p, vol_t, sino_t, s);
+            if constexpr (sizeof(T) == 4) rc = fp3d_zc<T, 32>(p, vol_t, sino_t, s, on, sp);
             else rc = fail(SIPO_E_UNSUPPORTED, "3D projector: 32 slices per thread in FP64");
             break;
         case 64:
-            if constexpr (sizeof(T) == 4) rc = fp3d_zc<T, 64>(p, vol_t, sino_t, s);
+            if constexpr (sizeof(T) == 4) rc = fp3d_zc<T, 64>(p, vol_t, sino_t, s, on, sp);
             else rc = fail(SIPO_E_UNSUPPORTED, "3D projector: 64 slices per thread in FP64");
             break;
         default: return fail(SIPO_E_UNSUPPORTED, "3D projector: %d slices per thread", p->p3d_zc);
@@ -978,23 +1088,109 @@ static int fp2d_plan(sipo_plan p, const void *vol, void *sino, int accumulate, h
 
 // Internal-layout entry points (see sipo_internal.hpp).  Slice and fallback
 // plans have no separate internal layout: they run the slice kernels directly.
-int launch_backproject_t(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s) {
+int launch_backproject_t(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s,
+                         const uint8_t *tile_on, const SplitSpec &sp) {
     if (p->p2d_ok)
         return launch_bp2d(p->dtype, bp2d_stage_fits(p->n, p->n_bins), p->d_geo2d, p->d_items_bp2d,
                            p->n_items_bp2d, sino_t, vol, accumulate, s);
     if (!p->fast3d())
         return p->dtype == SIPO_F64 ? bp_slices<double>(p, sino_t, vol, accumulate, s)
                                     : bp_slices<float>(p, sino_t, vol, accumulate, s);
-    return p->dtype == SIPO_F64 ? bp3d<double>(p, sino_t, vol, accumulate, s)
-                                : bp3d<float>(p, sino_t, vol, accumulate, s);
+    return p->dtype == SIPO_F64 ? bp3d<double>(p, sino_t, vol, accumulate, s, tile_on, sp)
+                                : bp3d<float>(p, sino_t, vol, accumulate, s, tile_on, sp);
 }
 
-int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s) {
+int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *wg_on,
+                     const SplitSpec &sp) {
     if (p->p2d_ok) return fp2d_plan(p, vol_t, sino_t, 0, s);
     if (!p->fast3d())
         return p->dtype == SIPO_F64 ? fp_slices<double>(p, vol_t, sino_t, 0, s)
                                     : fp_slices<float>(p, vol_t, sino_t, 0, s);
-    return p->dtype == SIPO_F64 ? fp3d<double>(p, vol_t, sino_t, s) : fp3d<float>(p, vol_t, sino_t, s);
+    return p->dtype == SIPO_F64 ? fp3d<double>(p, vol_t, sino_t, s, wg_on, sp) : fp3d<float>(p, vol_t, sino_t, s, wg_on, sp);
+}
+
+// ------------------------------------------------------- skip flags (LP solves)
+// An LP uses P only on its active rays and P^T only where its constrained voxels (band and gel)
+// or the blur around them read the result.  The solver therefore runs the 3D operators with one
+// flag per workgroup: a projector workgroup is on when one of its rays (or their opposite rays)
+// is active, a backprojector tile when it lies within the PSF radius of a labelled voxel.
+// Workgroups that are off write zeros.
+static int p3d_zchunks(sipo_plan p) { return (p->nz + p->p3d_zc - 1) / p->p3d_zc; }
+
+size_t p3d_flag_count(sipo_plan p, int zc) {
+    if (zc <= 0) zc = p->p3d_zc;
+    return p->fast3d() ? (size_t)p->n_batches * ((p->n_bins + kPB - 1) / kPB) * ((p->nz + zc - 1) / zc) : 0;
+}
+
+size_t bp3d_flag_count(sipo_plan p, int zc) {
+    if (!p->fast3d()) return 0;
+    if (zc <= 0) zc = p->bp3d_zc;
+    return (size_t)((p->n + kBpTX - 1) / kBpTX) * ((p->n + kBpTY - 1) / kBpTY) * ((p->nz + zc - 1) / zc);
+}
+
+__global__ void k_flags_clear(uint8_t *f, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        f[i] = 0;
+}
+
+// act_t: [view][bin][z]; view_batch[v] = 2 * batch + (v is the opposite view of a walked one)
+__global__ void k_p3d_flags(const uint8_t *__restrict__ act_t, uint8_t *__restrict__ flags,
+                            const int *__restrict__ view_batch, int n_angles, int nb, int nz, int ngroups, int zc,
+                            int nzc) {
+    const long long total = (long long)n_angles * nb * nz;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+        if (!act_t[i]) continue;
+        const int z = (int)(i % nz);
+        const long long ab = i / nz;
+        const int bin = (int)(ab % nb), a = (int)(ab / nb);
+        const int vb = view_batch[a];
+        if (vb < 0) continue;
+        const int b = (vb & 1) ? nb - 1 - bin : bin;
+        flags[((size_t)(vb >> 1) * ngroups + b / kPB) * nzc + z / zc] = 1;
+    }
+}
+
+// labels: [z][y][x]; a labelled voxel switches on every tile within (rx, ry, rz) of it
+__global__ void k_bp3d_flags(const uint8_t *__restrict__ lab, uint8_t *__restrict__ flags, int n, int nz, int rx,
+                             int ry, int rz, int zc, int gx, int gy, int gz) {
+    const long long total = (long long)nz * n * n;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+        if (!lab[i]) continue;
+        const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
+        const int tx0 = max(x - rx, 0) / kBpTX, tx1 = min(x + rx, n - 1) / kBpTX;
+        const int ty0 = max(y - ry, 0) / kBpTY, ty1 = min(y + ry, n - 1) / kBpTY;
+        const int tz0 = max(z - rz, 0) / zc, tz1 = min(z + rz, nz - 1) / zc;
+        for (int tz = tz0; tz <= tz1 && tz < gz; ++tz)
+            for (int ty = ty0; ty <= ty1 && ty < gy; ++ty)
+                for (int tx = tx0; tx <= tx1 && tx < gx; ++tx) flags[((size_t)tz * gy + ty) * gx + tx] = 1;
+    }
+}
+
+int launch_p3d_flags(sipo_plan p, const uint8_t *act_t, uint8_t *flags, hipStream_t s) {
+    const size_t cnt = p3d_flag_count(p);
+    if (!cnt) return SIPO_OK;
+    hipLaunchKernelGGL(k_flags_clear, dim3((unsigned)std::min<size_t>((cnt + 255) / 256, 4096)), dim3(256), 0, s, flags,
+                       (long long)cnt);
+    const long long total = (long long)p->n_angles * p->n_bins * p->nz;
+    hipLaunchKernelGGL(k_p3d_flags, dim3((unsigned)std::min<long long>((total + 255) / 256, 16384)), dim3(256), 0, s,
+                       act_t, flags, p->d_view_batch, p->n_angles, p->n_bins, p->nz, (p->n_bins + kPB - 1) / kPB,
+                       p->p3d_zc, p3d_zchunks(p));
+    SIPO_LAUNCHED("k_p3d_flags");
+    return SIPO_OK;
+}
+
+int launch_bp3d_flags(sipo_plan p, const uint8_t *labels, uint8_t *flags, hipStream_t s) {
+    const size_t cnt = bp3d_flag_count(p);
+    if (!cnt) return SIPO_OK;
+    hipLaunchKernelGGL(k_flags_clear, dim3((unsigned)std::min<size_t>((cnt + 255) / 256, 4096)), dim3(256), 0, s, flags,
+                       (long long)cnt);
+    const int rx = p->has_psf ? p->taps_d.rx : 0, ry = p->has_psf ? p->taps_d.ry : 0, rz = p->has_psf ? p->taps_d.rz : 0;
+    const int gx = (p->n + kBpTX - 1) / kBpTX, gy = (p->n + kBpTY - 1) / kBpTY, gz = (p->nz + p->bp3d_zc - 1) / p->bp3d_zc;
+    const long long total = (long long)p->nz * p->n * p->n;
+    hipLaunchKernelGGL(k_bp3d_flags, dim3((unsigned)std::min<long long>((total + 255) / 256, 16384)), dim3(256), 0, s,
+                       labels, flags, p->n, p->nz, rx, ry, rz, p->bp3d_zc, gx, gy, gz);
+    SIPO_LAUNCHED("k_bp3d_flags");
+    return SIPO_OK;
 }
 
 static int ensure_scratch(sipo_plan p) {

@@ -70,6 +70,7 @@ struct sipo_plan_s {
     int *d_angle_order;     // views the 3D projector walks: x-major first, then y-major
                             // (only the first view of each opposite pair when p3d_pair)
     int *d_partner;         // [n_angles]: index of the opposite view (theta + pi), or -1
+    int *d_view_batch;      // [n_angles]: 2 * projector batch (+1 for the opposite view of a walked one), or -1
     // view batches of the 3D projector: (first index into d_angle_order, count, x-major flag, unused)
     int n_batches;
     int4 *d_batches;
@@ -111,8 +112,25 @@ int launch_blur(sipo_plan p, const void *in, void *out, hipStream_t s);
 // Internal 3D layouts (fast3d plans): sinograms [view][bin][z] ("sino_t") and, as
 // the projector's input, volumes [y][x][z] ("vol_t"); both keep z contiguous.
 // Volumes produced by the backprojector stay in the ABI layout [z][y][x].
-int launch_backproject_t(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s);
-int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s);
+// tile_on / wg_on: optional per-workgroup flags of an LP solve (nullptr = the full operator);
+// workgroups that are off write zeros.  SplitSpec: the 3D kernels' serial walk (march steps of
+// the asynchronous projector, views of the backprojector) split over `parts` workgroups whose
+// partial sums go to `partial` (parts x the output's elements) and are then added in a fixed
+// order; parts <= 1 = no split.
+struct SplitSpec {
+    int parts = 1;
+    void *partial = nullptr;
+};
+int launch_backproject_t(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s,
+                         const uint8_t *tile_on = nullptr, const SplitSpec &sp = SplitSpec());
+int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *wg_on = nullptr,
+                     const SplitSpec &sp = SplitSpec());
+// projector workgroups / backprojector tiles of a fast3d plan (else 0) at zc slices per thread
+// (zc <= 0: the plan's current tuning)
+size_t p3d_flag_count(sipo_plan p, int zc = 0);
+size_t bp3d_flag_count(sipo_plan p, int zc = 0);
+int launch_p3d_flags(sipo_plan p, const uint8_t *act_t, uint8_t *flags, hipStream_t s);
+int launch_bp3d_flags(sipo_plan p, const uint8_t *labels, uint8_t *flags, hipStream_t s);
 int launch_vol_to_t(sipo_plan p, const void *vol, void *vol_t, hipStream_t s);
 int launch_sino_to_t(sipo_plan p, const void *sino, void *sino_t, hipStream_t s);
 int launch_sino_from_t(sipo_plan p, const void *sino_t, void *sino, int accumulate, hipStream_t s);

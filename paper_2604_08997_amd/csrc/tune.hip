@@ -121,11 +121,10 @@ extern "C" int sipo_plan_set_tuning(sipo_plan p, const sipo_tuning *t) {
     SIPO_REQUIRE(t->blur_zc == 0 || ((t->blur_zc == 8 || t->blur_zc == 16 || t->blur_zc == 32) && t->blur_zc <= p->nz),
                  "blur_zc %d: expected 0, or 8, 16 or 32 not above nz = %d", t->blur_zc, p->nz);
     SIPO_REQUIRE(!t->p3d_skip || t->p3d_dma, "p3d_skip applies to the asynchronous projector only");
-    SIPO_REQUIRE(t->bp3d_zc == 8 || t->bp3d_zc == 16 || (f32 && t->bp3d_zc == 32),
-                 "bp3d_zc %d: expected 8 or 16%s", t->bp3d_zc, f32 ? " or 32" : "");
-    if (t->p3d_dma && !(p->p3d_dma_ok && t->p3d_zc >= 16))
-        return fail(SIPO_E_UNSUPPORTED, "the asynchronous 3D projector does not apply to this plan%s",
-                    p->p3d_dma_ok ? " with fewer than 16 slices per thread" : "");
+    SIPO_REQUIRE(t->bp3d_zc == 4 || t->bp3d_zc == 8 || t->bp3d_zc == 16 || (f32 && t->bp3d_zc == 32),
+                 "bp3d_zc %d: expected 4, 8 or 16%s", t->bp3d_zc, f32 ? " or 32" : "");
+    if (t->p3d_dma && !p->p3d_dma_ok)
+        return fail(SIPO_E_UNSUPPORTED, "the asynchronous 3D projector does not apply to this plan");
     p->p3d_zc = t->p3d_zc;
     p->p3d_dma = t->p3d_dma != 0;
     p->p3d_skip = t->p3d_skip != 0;
