@@ -72,23 +72,73 @@ def vial_voxels(n):
 
 
 def source_digest():
-    """Digest of the forward projector's source: recorded traffic is valid only for this source."""
-    path = os.path.join(HERE, "paper_2604_08997_amd", "csrc", "projector.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Digest of the sources that decide the in-solve projector's work (the kernel and the solver's
+    skip flags): recorded traffic is valid only for these sources."""
+    h = hashlib.sha256()
+    for name in ("projector.hip", "pdhg.hip"):
+        with open(os.path.join(HERE, "paper_2604_08997_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per forward-projector launch from the committed counter runs, or None
-    when they are absent or were taken on another version of the kernel source."""
+def lp_work(n, angles, n_bins, labels, act, psf_radius):
+    """Algorithmic work of the LP's operators, counted on the host from the geometry.
+
+    P on the LP's active rays: one FMA per nonzero of P in an active row (a voxel
+    contributes to bins floor(u) and floor(u) + 1 with weights 1 - f and f, u the
+    detector coordinate of its centre).  P^T where the blurred dose is read: one
+    FMA per nonzero of P^T in the columns of labelled voxels and their PSF
+    neighbourhood (in the vial).  Returns nonzero counts.
+    """
+    import numpy as np
+    from scipy import ndimage
+    h = 2.0 / n
+    q = 2 * np.arange(n, dtype=np.int64) + 1 - n
+    rr, cc = np.nonzero((q[:, None] ** 2 + q[None, :] ** 2) <= n * n)
+    x, y = -1.0 + (cc + 0.5) * h, -1.0 + (rr + 0.5) * h
+    nz = labels.shape[0]
+    act_ab = act.sum(axis=1, dtype=np.int64)                 # [view][bin]: active slices
+    per_vox = np.zeros(len(rr), dtype=np.int64)
+    nnz_act = nnz_full = 0
+    for a, th in enumerate(angles):
+        u = (-x * np.sin(th) + y * np.cos(th) + 1.0) * (0.5 * n_bins) - 0.5
+        b0 = np.floor(u).astype(np.int64)
+        f = u - b0
+        m0 = (f < 1.0) & (b0 >= 0) & (b0 < n_bins)
+        m1 = (f > 0.0) & (b0 + 1 < n_bins) & (b0 + 1 >= 0)
+        cnt = np.bincount(b0[m0], minlength=n_bins) + np.bincount(b0[m1] + 1, minlength=n_bins)
+        nnz_full += int(cnt.sum()) * nz
+        nnz_act += int((cnt * act_ab[a]).sum())
+        per_vox += m0.astype(np.int64) + m1.astype(np.int64)
+    rz, ry, rx = psf_radius
+    need = ndimage.maximum_filter((labels > 0).astype(np.uint8), size=(2 * rz + 1, 2 * ry + 1, 2 * rx + 1)) > 0
+    nnz_bp = int((need[:, rr, cc] * per_vox[None, :]).sum())
+    return {"p_nnz_active": nnz_act, "p_nnz_full": nnz_full, "bp_nnz_needed": nnz_bp,
+            "active_ray_fraction": round(float(act.mean()), 5), "needed_voxel_fraction": round(float(need.mean()), 5)}
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of the in-solve forward projector from the committed counter runs, or
+    None when they are absent, were taken on another version of the sources, or on another kernel
+    variant than ``kernel``."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha256_16") != source_digest():
+    if rec.get("source_sha256_16") != source_digest() or rec.get("kernel") != kernel:
         return None
     return rec.get("bytes_per_launch")
+
+
+def in_solve_projector(tuning):
+    """Name of the projector kernel an LP solve of the 256^3 x 360 workload runs (view pairs, 3
+    candidates per step; the masked operators use at most 16 slices per thread)."""
+    zc = min(tuning["p3d_zc"], 16)
+    if tuning["p3d_dma"]:
+        return (f"project3d_dma_kernel<{zc}, 3, true, {'true' if tuning['p3d_skip'] else 'false'}, "
+                f"{tuning['p3d_cm']}>")
+    return f"project3d_kernel<float, {zc}, 3, true>"
 
 
 def cpu_baseline(n, angles, slices):
@@ -286,13 +336,16 @@ def probe(args, plan, dev):
         torch.cuda.synchronize()
         print(f"[probe] copy of {a.numel() * 4} bytes x 3", file=sys.stderr, flush=True)
         return 0
+    # the projector as the timed solve runs it: a short restarted solve of the benchmark LP (its most
+    # frequent projector kernel is the in-solve variant)
+    import paper_2604_08997_amd as sipo
+    from sipo_inputs import ellipsoids_target
     plan.autotune()
-    vol = torch.rand(plan.vol_shape, device=dev)
-    sino = plan.empty_sino()
-    for _ in range(3):
-        plan.project(vol, out=sino)
+    f = torch.as_tensor(ellipsoids_target(plan.n, 3000), dtype=torch.float32, device=dev)
+    lp = sipo.LP.build(plan, f, sipo.CASE1, band_width=10.0, f_min=1.0)
+    sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=32, tol=1e-12), want_dose=False)
     torch.cuda.synchronize()
-    print("[probe] project x 3 after autotune", file=sys.stderr, flush=True)
+    print("[probe] 32-iteration solve after autotune", file=sys.stderr, flush=True)
     return 0
 
 
@@ -351,14 +404,34 @@ def main():
     print(f"[bench] {iters} iterations in {dt:.3f} s; per-phase ms per launch: "
           + ", ".join(f"{k} {v:.4f}" for k, v in ph_avg.items()), file=sys.stderr, flush=True)
 
-    # --- operator pair and roofline of the dominant kernel (the forward projector)
-    samples = float(vial_voxels(n)) * n * na          # (in-vial voxel, slice, view) pairs per application
-    flops = 4.0 * samples                             # 2 FMA per sample
+    # --- operator pair and roofline of the dominant kernel.  Inside the solve the 3D operators skip
+    # the work the LP never reads, so their algorithmic work is that of the LP's operators: P on the
+    # active rays, P^T on the voxels the blurred dose is read at (2 flop per nonzero).
+    import numpy as np
+    from sipo_inputs import angles_uniform as _ang
+    rad = len(sipo.gaussian_taps(sigma[0])) // 2, len(sipo.gaussian_taps(sigma[1])) // 2, len(sipo.gaussian_taps(sigma[2])) // 2
+    work = lp_work(n, _ang(na), plan.n_bins, lp.labels.cpu().numpy(), lp.act.cpu().numpy(), (rad[2], rad[1], rad[0]))
+    print(f"[bench] LP operator work: {work}", file=sys.stderr, flush=True)
     t_p, t_bp = ph_avg["project"], ph_avg["backproject"]
     dom = max(("project", "backproject"), key=lambda k: ph_avg[k])
+    flops = 2.0 * (work["p_nnz_active"] if dom == "project" else work["bp_nnz_needed"])
     achieved = flops / (ph_avg[dom] * 1e-3) / 1e12
     pair_bytes = 2.0 * 4.0 * (plan.n_angles * n * n + n * n * n)   # each operator reads one array, writes the other
-    traffic = recorded_traffic() if (dom == "project" and not big) else None
+    p_kernel = in_solve_projector(tuning)
+    traffic = recorded_traffic(p_kernel) if (dom == "project" and not big) else None
+    # the full operator (every ray), as the standalone call and autograd run it
+    vol_r = torch.rand(plan.vol_shape, device=dev)
+    sino_r = plan.empty_sino()
+    plan.project(vol_r, out=sino_r)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        plan.project(vol_r, out=sino_r)
+    e1.record()
+    torch.cuda.synchronize()
+    t_full = e0.elapsed_time(e1) / 10
+    ach_full = 2.0 * work["p_nnz_full"] / (t_full * 1e-3) / 1e12
+    del vol_r, sino_r
 
     ttk = None
     if args.ttk:
@@ -396,9 +469,13 @@ def main():
         "a_plus_at_gbs": round(pair_bytes / ((t_p + t_bp) * 1e-3) / 1e9, 2),
         "phase_ms": {k: round(v, 4) for k, v in ph_avg.items()},
         "tuning": tuning,
-        "roofline": {"bound": "alu", "kernel": "project3d" if dom == "project" else "backproject3d",
+        "roofline": {"bound": "alu", "kernel": (p_kernel + " (LP rays)" if dom == "project" else "backproject3d (LP voxels)"),
                      "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic},
+        "roofline_full_operator": {"bound": "alu", "kernel": "project3d (all rays, standalone)",
+                                   "ms": round(t_full, 4), "achieved": round(ach_full, 3), "peak": FP32_PEAK_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": round(ach_full / FP32_PEAK_TFLOPS, 4)},
+        "lp_operator_work": work,
         "cpu_baseline": cpu,
     }
     if ttk is not None:

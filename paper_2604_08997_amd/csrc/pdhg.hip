@@ -737,9 +737,8 @@ class Solver {
     bool b2d_ = false;
     bool mask_ = false;                     // 3D operators skip workgroups the LP does not read
     std::vector<SplitSpec> psp_, bsp_;      // per instance: splits of the masked 3D operators
-    // slices per thread the masked operators run with, per plan, and the plans' own settings, which the
-    // solver restores when it ends
-    std::vector<std::pair<sipo_plan, std::pair<int, int>>> zc_choice_, zc_saved_;
+    // the plans' own slices per thread, which the masked operators change and the solver restores
+    std::vector<std::pair<sipo_plan, std::pair<int, int>>> zc_saved_;
     int nc_max_ = 3;
     bool bp_staged_ = true;
     int n_max_ = 1;
@@ -1112,29 +1111,15 @@ int Solver<T>::setup_common() {
         // From here on the 3D operators skip what the restarted scheme never reads: q = P K z off the
         // active rays, and P^T y away from the labelled voxels and their PSF neighbourhood (every row
         // scaling, residual and certificate test reads D on labelled voxels and q on active rays).
-        // Few workgroups stay on, each with a long serial walk.  Per plan, the masked operators are timed
-        // at the plan's slices per thread and at half of it (finer chunks give more workgroups), and the
-        // backprojector's view walk is split so that the switched-on tiles fill the chip; the projector's
-        // march is split only when very few of its workgroups stay on.
+        // Few workgroups stay on, each with a long serial walk.  The masked operators run with at most 16
+        // slices per thread (finer chunks give more workgroups; at 256^3 x 360 this is the fastest of the
+        // 8 / 16 / 32 choices for both operators), the backprojector's view walk is split so that the
+        // switched-on tiles fill the chip, and the projector's march is split only when very few of its
+        // workgroups stay on.  The plans' own settings are restored when the solver ends.
         int cus = 256;
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, probs_[0].plan->device);
         psp_.assign(B_, SplitSpec());
         bsp_.assign(B_, SplitSpec());
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        SIPO_HIP(hipEventCreate(&e0));
-        SIPO_HIP(hipEventCreate(&e1));
-        auto timed = [&](auto &&fn) -> float {
-            float best = 1e30f;
-            if (fn() != SIPO_OK) return -1.f;
-            for (int r = 0; r < 3; ++r) {
-                float ms = 0.f;
-                if (hipEventRecord(e0, s_) != hipSuccess || fn() != SIPO_OK || hipEventRecord(e1, s_) != hipSuccess ||
-                    hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-                    return -1.f;
-                best = std::min(best, ms);
-            }
-            return best;
-        };
         auto count_on = [&](size_t flags_off, size_t count) -> long long {
             std::vector<uint8_t> h(count);
             if (count && hipMemcpyAsync(h.data(), U8(flags_off), count, hipMemcpyDeviceToHost, s_) != hipSuccess)
@@ -1148,60 +1133,26 @@ int Solver<T>::setup_common() {
             if (on <= 0) return 1;
             return (int)std::min<long long>(max_parts, std::max<long long>(1, (want + on - 1) / on));
         };
-        int rc2 = SIPO_OK;
-        for (int i = 0; i < B_ && !rc2; ++i) {
+        for (int i = 0; i < B_; ++i) {
             const Inst &I = in_[i];
             if (!I.t3) continue;
             sipo_plan p = I.p;
-            const uint8_t *pf = U8(L_.pflags) + L_.pfo[i], *bf = U8(L_.bflags) + L_.bfo[i];
-            int choice = -1;
-            for (size_t k = 0; k < zc_choice_.size(); ++k)
-                if (zc_choice_[k].first == p) choice = (int)k;
-            if (choice < 0) {
+            bool seen = false;
+            for (auto &e : zc_saved_) seen = seen || e.first == p;
+            if (!seen) {
                 zc_saved_.push_back({p, {p->p3d_zc, p->bp3d_zc}});
-                // projector: the plan's slices and half of them (the asynchronous variant takes 8 or more)
-                std::vector<int> pc = {p->p3d_zc}, bc = {p->bp3d_zc};
-                if (p->p3d_zc / 2 >= 8) pc.push_back(p->p3d_zc / 2);
-                if (p->bp3d_zc / 2 >= 4) bc.push_back(p->bp3d_zc / 2);
-                int bpz = p->p3d_zc, bbz = p->bp3d_zc;
-                float tp = 1e30f, tb = 1e30f;
-                for (int zc : pc) {
-                    p->p3d_zc = zc;
-                    rc2 = launch_p3d_flags(p, U8(L_.act) + I.soff, U8(L_.pflags) + L_.pfo[i], s_);
-                    const long long on = rc2 ? -1 : count_on(L_.pflags + L_.pfo[i], p3d_flag_count(p));
-                    if (on < 0) { rc2 = rc2 ? rc2 : fail(SIPO_E_DEVICE, "pdhg setup: reading skip flags failed"); break; }
-                    const SplitSpec sp{parts_for(on, cus, kMaxSplitP), F(L_.ppart)};
-                    const float t = timed([&] { return launch_project_t(p, F(L_.vol_t), F(L_.q) + I.soff, s_, pf, sp); });
-                    if (t >= 0.f && t < tp) { tp = t; bpz = zc; }
-                }
-                for (int zc : bc) {
-                    if (rc2) break;
-                    p->bp3d_zc = zc;
-                    rc2 = launch_bp3d_flags(p, U8(L_.lab) + I.voff, U8(L_.bflags) + L_.bfo[i], s_);
-                    const long long on = rc2 ? -1 : count_on(L_.bflags + L_.bfo[i], bp3d_flag_count(p));
-                    if (on < 0) { rc2 = rc2 ? rc2 : fail(SIPO_E_DEVICE, "pdhg setup: reading skip flags failed"); break; }
-                    const SplitSpec sp{parts_for(on, 4LL * cus, kMaxSplitB), F(L_.bpart)};
-                    const float t = timed([&] { return launch_backproject_t(p, F(L_.y) + I.soff, F(L_.tmp) + I.voff, 0, s_, bf, sp); });
-                    if (t >= 0.f && t < tb) { tb = t; bbz = zc; }
-                }
-                p->p3d_zc = bpz;
-                p->bp3d_zc = bbz;
-                zc_choice_.push_back({p, {bpz, bbz}});
+                p->p3d_zc = std::min(p->p3d_zc, 16);
+                p->bp3d_zc = std::min(p->bp3d_zc, 16);
             }
-            if (rc2) break;
-            // flags and splits of this instance at the plan's chosen slices
-            rc2 = launch_p3d_flags(p, U8(L_.act) + I.soff, U8(L_.pflags) + L_.pfo[i], s_);
-            if (!rc2) rc2 = launch_bp3d_flags(p, U8(L_.lab) + I.voff, U8(L_.bflags) + L_.bfo[i], s_);
-            if (rc2) break;
+            rc = launch_p3d_flags(p, U8(L_.act) + I.soff, U8(L_.pflags) + L_.pfo[i], s_);
+            if (!rc) rc = launch_bp3d_flags(p, U8(L_.lab) + I.voff, U8(L_.bflags) + L_.bfo[i], s_);
+            if (rc) return rc;
             const long long onp = count_on(L_.pflags + L_.pfo[i], p3d_flag_count(p));
             const long long onb = count_on(L_.bflags + L_.bfo[i], bp3d_flag_count(p));
-            if (onp < 0 || onb < 0) { rc2 = fail(SIPO_E_DEVICE, "pdhg setup: reading skip flags failed"); break; }
+            if (onp < 0 || onb < 0) return fail(SIPO_E_DEVICE, "pdhg setup: reading the skip flags failed");
             psp_[i] = SplitSpec{parts_for(onp, cus, kMaxSplitP), F(L_.ppart)};
             bsp_[i] = SplitSpec{parts_for(onb, 4LL * cus, kMaxSplitB), F(L_.bpart)};
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        if (rc2) return rc2;
         mask_ = true;
     }
     rc = lambda_z(L_.lu, L_.ll, L_.z, false);

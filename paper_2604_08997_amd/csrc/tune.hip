@@ -6,24 +6,27 @@
 
 namespace sipo {
 
-// Mean time of reps launches of fn after one warm-up launch (ms), or < 0 on error.
+// Shortest of reps timed launches of fn after two warm-up launches (ms), or < 0 on error.  The
+// minimum is robust against a GPU that is still raising its clocks when the autotuner starts.
 template <typename F>
 static float time_ms(F fn, int reps, hipStream_t s) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.f;
-    float ms = -1.f;
-    if (fn() == SIPO_OK && hipEventRecord(e0, s) == hipSuccess) {
-        bool ok = true;
-        for (int r = 0; r < reps && ok; ++r) ok = fn() == SIPO_OK;
-        if (ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-            hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
-            ms /= (float)reps;
-        else
-            ms = -1.f;
+    float best = -1.f;
+    if (fn() == SIPO_OK && fn() == SIPO_OK) {
+        for (int r = 0; r < reps; ++r) {
+            float ms = 0.f;
+            if (hipEventRecord(e0, s) != hipSuccess || fn() != SIPO_OK || hipEventRecord(e1, s) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                best = -1.f;
+                break;
+            }
+            if (best < 0.f || ms < best) best = ms;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return ms;
+    return best;
 }
 
 }  // namespace sipo
@@ -44,38 +47,43 @@ extern "C" int sipo_plan_autotune(sipo_plan p, void *stream) {
         (void)hipFree(va); (void)hipFree(vc); (void)hipFree(sa);
         return fail(SIPO_E_DEVICE, "autotune scratch allocation failed: %s", hipGetErrorString(e));
     }
-    constexpr int kReps = 3;
+    constexpr int kReps = 5;
     if (p->fast3d()) {
-        std::vector<int> zcs = p->dtype == SIPO_F64 ? std::vector<int>{8, 16} : std::vector<int>{16, 32, 64};
-        int best = p->p3d_zc, best_cm = p->p3d_cm;
-        bool best_dma = p->p3d_dma, best_skip = p->p3d_skip;
-        float tbest = 1e30f;
-        for (int dma = 0; dma <= (p->p3d_dma_ok ? 1 : 0); ++dma)
-            for (int skip = 0; skip <= dma; ++skip)
+        // candidates in a fixed preference order; the first within 2 % of the fastest wins, so that
+        // near-ties resolve the same way from run to run
+        struct Cand { int zc, dma, skip, cm; float t; };
+        std::vector<Cand> cands;
+        const Cand orig{p->p3d_zc, p->p3d_dma ? 1 : 0, p->p3d_skip ? 1 : 0, p->p3d_cm, 0.f};
+        const int orig_b = p->bp3d_zc;
+        for (int dma = p->p3d_dma_ok ? 1 : 0; dma >= 0; --dma)
+            for (int zc : p->dtype == SIPO_F64 ? std::vector<int>{16, 8} : std::vector<int>{32, 16, 64})
                 for (int cm = dma ? 1 : 2; cm <= 2; ++cm)
-                    for (int zc : zcs) {
+                    for (int skip = 0; skip <= dma; ++skip) {
                         if (zc > 32 && !dma) continue;   // 64 slices per thread: asynchronous staging only
                         p->p3d_zc = zc;
                         p->p3d_dma = dma != 0;
                         p->p3d_skip = skip != 0;
                         p->p3d_cm = cm;
-                        const float t = time_ms([&] { return launch_project_t(p, va, sa, s); }, kReps, s);
-                        if (t >= 0.f && t < tbest) {
-                            tbest = t; best = zc; best_dma = dma != 0; best_skip = skip != 0; best_cm = cm;
-                        }
+                        cands.push_back({zc, dma, skip, cm, time_ms([&] { return launch_project_t(p, va, sa, s); }, kReps, s)});
                     }
-        p->p3d_zc = best;
-        p->p3d_dma = best_dma;
-        p->p3d_skip = best_skip;
-        p->p3d_cm = best_cm;
-        int best_b = p->bp3d_zc;
-        float tb = 1e30f;
-        for (int zc : p->dtype == SIPO_F64 ? std::vector<int>{8, 16} : std::vector<int>{16, 32}) {
+        float tmin = 1e30f;
+        for (const Cand &c : cands) if (c.t >= 0.f) tmin = std::min(tmin, c.t);
+        p->p3d_zc = orig.zc; p->p3d_dma = orig.dma != 0; p->p3d_skip = orig.skip != 0; p->p3d_cm = orig.cm;
+        for (const Cand &c : cands)
+            if (c.t >= 0.f && c.t <= 1.02f * tmin) {
+                p->p3d_zc = c.zc; p->p3d_dma = c.dma != 0; p->p3d_skip = c.skip != 0; p->p3d_cm = c.cm;
+                break;
+            }
+        std::vector<std::pair<int, float>> bc;
+        for (int zc : p->dtype == SIPO_F64 ? std::vector<int>{16, 8} : std::vector<int>{32, 16}) {
             p->bp3d_zc = zc;
-            const float t = time_ms([&] { return launch_backproject_t(p, sa, va, 0, s); }, kReps, s);
-            if (t >= 0.f && t < tb) { tb = t; best_b = zc; }
+            bc.push_back({zc, time_ms([&] { return launch_backproject_t(p, sa, va, 0, s); }, kReps, s)});
         }
-        p->bp3d_zc = best_b;
+        float bmin = 1e30f;
+        for (auto &c : bc) if (c.second >= 0.f) bmin = std::min(bmin, c.second);
+        p->bp3d_zc = orig_b;
+        for (auto &c : bc)
+            if (c.second >= 0.f && c.second <= 1.02f * bmin) { p->bp3d_zc = c.first; break; }
     }
     if (p->has_psf && p->nz > 1) {
         int best = 0;
