@@ -246,16 +246,25 @@ __global__ void k_primal(T *__restrict__ y, T *__restrict__ yt, const T *__restr
     const DevScal &sc = scal[segs[blockIdx.x].inst];
     const T tf = (T)sc.tau_fac;
     const T w = (T)sc.w, rho = (T)sc.rho;
-    SEG_LOOP(i) {
-        T t = (T)0;
-        const T yo = y[i];
-        if (act[i]) {
+    // A masked ray keeps y = t.y = anchor = 0 (all three start at zero there), so it is not touched.
+    // Each thread takes four consecutive rays and skips them with one 4-byte test of the mask (runs of
+    // masked rays are long: z is the fastest index of the 3D layout).  Segments start on multiples of
+    // four elements; mask bytes past a segment's end lie in the packing gap and are ignored.
+    const Seg sg = segs[blockIdx.x];
+    for (long long i0 = sg.b + 4 * (long long)threadIdx.x; i0 < sg.e; i0 += 4 * (long long)kThreads) {
+        const uint32_t a4 = *(const uint32_t *)(act + i0);
+        if (!a4) continue;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const long long i = i0 + k;
+            if (i >= sg.e || !((a4 >> (8 * k)) & 0xFFu)) continue;
+            const T yo = y[i];
             const T st = Tj ? tf * Tj[i] : tf;
-            t = yo - st * q[i];
+            T t = yo - st * q[i];
             t = t > (T)0 ? t : (T)0;
+            yt[i] = t;
+            y[i] = y0 ? w * (((T)1 + rho) * t - rho * yo) + ((T)1 - w) * y0[i] : t;
         }
-        yt[i] = t;
-        y[i] = y0 ? w * (((T)1 + rho) * t - rho * yo) + ((T)1 - w) * y0[i] : t;
     }
 }
 
@@ -268,7 +277,8 @@ __global__ void k_dual(const T *__restrict__ Dt, T *__restrict__ D, const T *__r
                        const uint8_t *__restrict__ lab, const T *__restrict__ lo, const T *__restrict__ hi,
                        const T *__restrict__ s_up, const T *__restrict__ s_lo, T *__restrict__ lut,
                        T *__restrict__ llt, T *__restrict__ luo, T *__restrict__ llo, const DevScal *__restrict__ scal,
-                       const InstC *__restrict__ insts, const Seg *__restrict__ segs, double *partials) {
+                       const InstC *__restrict__ insts, const Seg *__restrict__ segs, double *partials,
+                       int labelled_only) {
     const int inst = segs[blockIdx.x].inst;
     const DevScal &sc = scal[inst];
     const LPConst c = insts[inst].c;
@@ -277,34 +287,46 @@ __global__ void k_dual(const T *__restrict__ Dt, T *__restrict__ D, const T *__r
     const T vb = (T)(c.v_free ? sc.vbar : 1.0);
     const T w = (T)sc.w, rho = (T)sc.rho, w1 = (T)1 - w, rp = (T)1 + rho;
     double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
-    SEG_LOOP(i) {
-        const T dt = Dt[i], dz = D[i];
-        D[i] = D0 ? w * (rp * dt - rho * dz) + w1 * D0[i] : dt;
-        const uint8_t L = lab[i];
-        if (L == 0) continue;
-        const T Db = (T)2 * dt - dz;
-        const T su = s_up ? (T)sf * s_up[i] : (T)sf;
-        const T a_old = lu[i];
-        T a = a_old + su * (Db - (L == 1 ? ub : vb * ld_or(hi, i, c.hi_s)));
-        a = a > (T)0 ? a : (T)0;
-        const T a_new = lu0 ? w * (rp * a - rho * a_old) + w1 * lu0[i] : a;
-        lu[i] = a_new;
-        if (lut) { lut[i] = a; luo[i] = a_old; }
-        T zz = a_new;
-        if (L == 1) {
-            acc[0] += (double)a_new;
-        } else {
-            const T sl = s_lo ? (T)sf * s_lo[i] : (T)sf;
-            const T b_old = ll[i];
-            T b = b_old + sl * (ld_or(lo, i, c.lo_s) - Db);
-            b = b > (T)0 ? b : (T)0;
-            const T b_new = ll0 ? w * (rp * b - rho * b_old) + w1 * ll0[i] : b;
-            ll[i] = b_new;
-            if (llt) { llt[i] = b; llo[i] = b_old; }
-            zz = a_new - b_new;
-            acc[1] += (double)ld_or(hi, i, c.hi_s) * (double)a_new;
+    // four consecutive voxels per thread; labelled_only: the dose of unlabelled voxels is not kept
+    // (nothing reads it during the solve), so groups of four unlabelled voxels are skipped on one
+    // 4-byte test (label bytes past a segment's end lie in the packing gap and are ignored)
+    const Seg sg = segs[blockIdx.x];
+    for (long long i0 = sg.b + 4 * (long long)threadIdx.x; i0 < sg.e; i0 += 4 * (long long)kThreads) {
+        const uint32_t l4 = *(const uint32_t *)(lab + i0);
+        if (labelled_only && !l4) continue;
+    #pragma unroll
+        for (int k4 = 0; k4 < 4; ++k4) {
+            const long long i = i0 + k4;
+            if (i >= sg.e) continue;
+            const uint8_t L = (uint8_t)((l4 >> (8 * k4)) & 0xFFu);
+            if (labelled_only && L == 0) continue;
+            const T dt = Dt[i], dz = D[i];
+            D[i] = D0 ? w * (rp * dt - rho * dz) + w1 * D0[i] : dt;
+            if (L == 0) continue;
+            const T Db = (T)2 * dt - dz;
+            const T su = s_up ? (T)sf * s_up[i] : (T)sf;
+            const T a_old = lu[i];
+            T a = a_old + su * (Db - (L == 1 ? ub : vb * ld_or(hi, i, c.hi_s)));
+            a = a > (T)0 ? a : (T)0;
+            const T a_new = lu0 ? w * (rp * a - rho * a_old) + w1 * lu0[i] : a;
+            lu[i] = a_new;
+            if (lut) { lut[i] = a; luo[i] = a_old; }
+            T zz = a_new;
+            if (L == 1) {
+                acc[0] += (double)a_new;
+            } else {
+                const T sl = s_lo ? (T)sf * s_lo[i] : (T)sf;
+                const T b_old = ll[i];
+                T b = b_old + sl * (ld_or(lo, i, c.lo_s) - Db);
+                b = b > (T)0 ? b : (T)0;
+                const T b_new = ll0 ? w * (rp * b - rho * b_old) + w1 * ll0[i] : b;
+                ll[i] = b_new;
+                if (llt) { llt[i] = b; llo[i] = b_old; }
+                zz = a_new - b_new;
+                acc[1] += (double)ld_or(hi, i, c.hi_s) * (double)a_new;
+            }
+            z[i] = zz;
         }
-        z[i] = zz;
     }
     block_sums(acc, partials);
 }
@@ -1107,6 +1129,7 @@ int Solver<T>::setup_common() {
     if (!rc) rc = put_insts();
     if (rc) return rc;
     hipLaunchKernelGGL((k_project_y<T>), gS(), dim3(kThreads), 0, s_, F(L_.y), (const uint8_t *)U8(L_.act), segS());
+    copyS(L_.yt, L_.y, false);   // t.y starts as y: zero on masked rays, which the primal step never touches
     if (o_.mode == SIPO_PDHG_RESTARTED) {
         // From here on the 3D operators skip what the restarted scheme never reads: q = P K z off the
         // active rays, and P^T y away from the labelled voxels and their PSF neighbourhood (every row
@@ -1332,7 +1355,7 @@ int Solver<T>::iteration(bool check) {
                        hal ? (const T *)F(L_.s_up) : (const T *)nullptr, hal ? (const T *)F(L_.s_lo) : (const T *)nullptr,
                        check ? F(L_.lut) : (T *)nullptr, check ? F(L_.llt) : (T *)nullptr,
                        check ? F(L_.luo) : (T *)nullptr, check ? F(L_.llo) : (T *)nullptr, (const DevScal *)scal(),
-                       insts(), segV(), partials());
+                       insts(), segV(), partials(), mask_ ? 1 : 0);
     rc = mark(SIPO_PHASE_DUAL);
     if (rc) return rc;
     hipLaunchKernelGGL(k_scalars, dim3(active_.size()), dim3(kThreads), 0, s_, (const double *)partials(),
@@ -1658,9 +1681,10 @@ int Solver<T>::run(sipo_pdhg_result *res) {
         if (rc) return rc;
     }
     if (mask_) {
-        // a requested dose is returned on the whole volume
+        // a requested dose is returned on the whole volume (the masked operators and the dual step kept
+        // it on the LP's rows only)
         bool full = false;
-        for (int i = 0; i < B_; ++i) full = full || (probs_[i].dose_out && in_[i].t3);
+        for (int i = 0; i < B_; ++i) full = full || probs_[i].dose_out;
         mask_ = false;
         if (full) {
             rc = dose(L_.y, L_.D);
