@@ -107,12 +107,14 @@ int sipo_plan_autotune(sipo_plan plan, void *stream);
 typedef struct {
     int32_t p3d_zc;     /* slices per 3D projector thread: 8 or 16 (FP64); 8, 16, 32 or 64
                            (FP32; 64 with the asynchronous projector only)                       */
-    int32_t p3d_dma;    /* 1 = 3D projector with asynchronous LDS staging (FP32, slices per
-                           thread >= 16, and only where the plan's staged ranges allow it)      */
+    int32_t p3d_dma;    /* 1 = 3D projector with asynchronous LDS staging (FP32 only, and only
+                           where the plan's staged ranges allow it)                             */
     int32_t p3d_skip;   /* asynchronous projector: lanes skip candidates outside their ray (0/1) */
-    int32_t p3d_cm;     /* asynchronous projector: march steps per staged chunk, 1 or 2          */
+    int32_t p3d_cm;     /* asynchronous projector: march steps per staged chunk, 1 or 2 (1 with
+                           64 slices per thread)                                                */
     int32_t blur_zc;    /* slices per blur workgroup: 0 (whole columns), 8, 16 or 32 (<= nz)     */
-    int32_t bp3d_zc;    /* slices per 3D backprojector thread: 8 or 16 (FP64); 8, 16 or 32 (FP32) */
+    int32_t bp3d_zc;    /* slices per 3D backprojector thread: 4, 8 or 16 (FP64); 4, 8, 16 or
+                           32 (FP32)                                                            */
 } sipo_tuning;
 
 /* Current settings of the plan (defaults, autotuned or set).  Errors: NULL

@@ -138,6 +138,21 @@ __global__ void __launch_bounds__(256) project_kernel(const T *__restrict__ vol,
 // by the 16 lanes of one LDS pass land in different banks.  A voxel then reads
 // four slices of each tap bin per 128-bit load.  Bins outside the detector are
 // staged as zeros, so the inner loop has no bounds tests.
+// Tile coordinates (x, y, z) of this workgroup, spread over the XCDs.  Workgroups reach the eight
+// XCDs in turn by linear id, so with x taken straight from blockIdx a grid whose x extent is a
+// multiple of eight would pin each x column of tiles to one XCD; a masked launch, whose live tiles
+// cluster in a few columns, would then run on a few XCDs.  x is rotated by the index of the run of
+// RY consecutive y tiles (RY = 0: the whole y extent, i.e. by z alone), so every XCD gets every
+// column while a run of RY y-neighbours stays on one XCD and shares its L2.  A bijection of the grid.
+template <int RY>
+__device__ __forceinline__ int3 xcd_tile() {
+    const unsigned ry = RY > 0 ? RY : gridDim.y;
+    const unsigned q = blockIdx.y / ry + ((gridDim.y + ry - 1) / ry) * blockIdx.z;
+    return make_int3((int)((blockIdx.x + q) % gridDim.x), (int)blockIdx.y, (int)blockIdx.z);
+}
+// runs of y tiles kept together: view batches for the projector, rows for the backprojector
+constexpr int kXcdRunP = 1, kXcdRunBp = 0;
+
 constexpr int kBpTX = 32, kBpTY = 16, kBpTB = 6, kBpW = 40;
 
 static bool bp3d_fits(int n, int nb) {
@@ -158,11 +173,12 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
     __shared__ int bmin_s[kBpTB];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     // grid.z = z chunks x view splits; split s sums its share of the views into partial sum s
-    const int nzc = gridDim.z / nsplit, zb = blockIdx.z % nzc, split = blockIdx.z / nzc;
-    const int x0 = blockIdx.x * kBpTX, y0 = blockIdx.y * kBpTY, z0 = zb * ZC;
+    const int3 tile = xcd_tile<kXcdRunBp>();
+    const int nzc = gridDim.z / nsplit, zb = tile.z % nzc, split = tile.z / nzc;
+    const int x0 = tile.x * kBpTX, y0 = tile.y * kBpTY, z0 = zb * ZC;
     const int c = x0 + tx;
     const int r[2] = {y0 + ty, y0 + ty + 8};
-    if (tile_on && !tile_on[((size_t)zb * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x]) {
+    if (tile_on && !tile_on[((size_t)zb * gridDim.y + tile.y) * gridDim.x + tile.x]) {
         // no voxel of the tile is needed: write zeros (or leave an accumulated output as it is);
         // with splits the reduction writes those zeros
         if (!accumulate && nsplit == 1)
@@ -303,14 +319,15 @@ __global__ void __launch_bounds__(256) project3d_kernel(const T *__restrict__ vo
     constexpr int NR = PAIR ? 2 : 1;
     __shared__ V4 lds[kPCM][Z4][kPCR + 1];   // +1: the z/4 planes start on different banks
     __shared__ int jmin_s, jmax_s;
-    const int4 bt = batches[blockIdx.y];
+    const int3 tile = xcd_tile<kXcdRunP>();
+    const int4 bt = batches[tile.y];
     const int tb = threadIdx.x % kPB, tk = threadIdx.x / kPB;
-    const int b = blockIdx.x * kPB + tb;
-    const int z0 = blockIdx.z * ZC;
+    const int b = tile.x * kPB + tb;
+    const int z0 = tile.z * ZC;
     const bool xmajor = bt.z != 0;
     const bool active = tk < bt.y && b < nb;
     const int a = order[bt.x + min(tk, bt.y - 1)];
-    if (wg_on && !wg_on[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * gridDim.z + blockIdx.z]) {
+    if (wg_on && !wg_on[((size_t)tile.y * gridDim.x + tile.x) * gridDim.z + tile.z]) {
         // none of this workgroup's rays is active: their outputs are zero
         if (active)
             for (int r = 0; r < NR; ++r) {
@@ -456,13 +473,25 @@ __global__ void __launch_bounds__(256) project3d_kernel(const T *__restrict__ vo
 // the plan (conservative by one voxel on each side); a chunk stages the union
 // of its steps' ranges.
 constexpr int kDmaMaxCM = 2;
+// s_waitcnt immediate (GFX9 encoding) that waits for at most n outstanding vector-memory
+// operations and leaves the export and LDS/scalar counters unconstrained.
+__host__ __device__ constexpr int vm_wait_imm(int n) {
+    return (n & 0xF) | (((n >> 4) & 0x3) << 14) | (0x7 << 4) | (0xF << 8);
+}
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+// Workgroup barrier of the staging ring.  Each wave has already waited (vector-memory counter) for
+// its own copies of the chunk it reads next, and its reads of earlier chunks have returned (LDS
+// counter 0); copies of later chunks stay in flight.  A release fence would wait for those too,
+// since staging copies write LDS; the empty asm statements keep the compiler from moving LDS
+// accesses across the barrier instead.
+constexpr int kLgkmWaitOnly = 0xF | (0x3 << 14) | (0x7 << 4);   // lgkmcnt(0), others unconstrained
+__device__ __forceinline__ void ring_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(kLgkmWaitOnly);
     __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    asm volatile("" ::: "memory");
 }
 
 template <int ZC, int NC, bool PAIR, bool SKIP, int CM>
@@ -475,23 +504,27 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     static_assert(CM >= 1 && CM <= kDmaMaxCM, "chunk length");
     constexpr int Z4 = ZC / 4, RS = kPCR + 1, SLOTS = CM * Z4 * RS, PER = (SLOTS + 255) / 256;
     constexpr int NR = PAIR ? 2 : 1;
+    // three separate arrays, not one indexed ring: the compiler tells LDS variables apart when it
+    // decides which staging copies a read has to wait for, but not slices of one array
     __shared__ float4 bufA[SLOTS];
     __shared__ float4 bufB[SLOTS];
+    __shared__ float4 bufC[SLOTS];
     const int tid = threadIdx.x;
-    const int4 bt = batches[blockIdx.y];
+    const int3 tile = xcd_tile<kXcdRunP>();
+    const int4 bt = batches[tile.y];
     // lane -> (bin, view): each wave holds two neighbouring views; a 16-lane quarter holds the same
     // 8 bins of both, whose candidate voxels nearly coincide, so one quarter's LDS reads stay
     // within about one pass of the 64 banks
     const int lane = tid & 63, wv = tid >> 6;
     const int tb = (lane & 7) | ((lane >> 4) << 3), tk = 2 * wv + ((lane >> 3) & 1);
-    const int b = blockIdx.x * kPB + tb;
+    const int b = tile.x * kPB + tb;
     // grid.z = z chunks x march splits; split s walks its share of the chunks into partial sum s
-    const int nzc = gridDim.z / nsplit, zb = blockIdx.z % nzc, split = blockIdx.z / nzc;
+    const int nzc = gridDim.z / nsplit, zb = tile.z % nzc, split = tile.z / nzc;
     const int z0 = zb * ZC;
     const bool xmajor = bt.z != 0;
     const bool active = tk < bt.y && b < nb;
     const int a = order[bt.x + min(tk, bt.y - 1)];
-    if (wg_on && !wg_on[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * nzc + zb]) {
+    if (wg_on && !wg_on[((size_t)tile.y * gridDim.x + tile.x) * nzc + zb]) {
         // none of this workgroup's rays is active: their outputs are zero (before any barrier);
         // with splits the reduction writes those zeros
         if (active && nsplit == 1)
@@ -512,13 +545,13 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     const double inv_du = 1.0 / du;
     const float du_t = (float)du, dsj_t = (float)dsj, dtj_t = (float)dtj;
     const int nch = (n + CM - 1) / CM;
-    const int2 *rg = ranges + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * n;
+    const int2 *rg = ranges + ((size_t)tile.y * gridDim.x + tile.x) * n;
     const size_t zrow = (size_t)(nz >> 2), zoff = (size_t)(z0 >> 2);
     const float4 *vol4 = (const float4 *)vol_t;
 
     // staged cross range of chunk k: the union of its steps' ranges (first index, count)
     auto chunk_range = [&](int k) {
-        const int m0 = k * CM;
+        const int m0 = __builtin_amdgcn_readfirstlane(k * CM);   // uniform: scalar loads
         int lo = rg[m0].x, hi = rg[m0].x + rg[m0].y;
 #pragma unroll
         for (int q = 1; q < CM; ++q)
@@ -542,7 +575,7 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     }
     auto issue = [&](float4 *buf, int k) {
         const int2 r = chunk_range(k);
-        const int m0 = k * CM;
+        const int m0 = __builtin_amdgcn_readfirstlane(k * CM);
         int2 vr[CM];   // vial interval of each step's row (uniform loads)
 #pragma unroll
         for (int q = 0; q < CM; ++q) vr[q] = vial_rows[min(m0 + q, n - 1)];
@@ -618,18 +651,34 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
         }
     };
 
+    // Ring of three buffers: chunk k + 2 is copied while chunk k is consumed, so each copy has two
+    // chunks of compute to land.  Before consuming chunk k a wave waits until its own copies of
+    // chunk k have landed (vector-memory counter: the copies of chunk k + 1 may stay in flight;
+    // loads retire in order), then the barrier makes that hold for all waves and frees the buffer
+    // the next copy goes to.  A wave issues PER copies per chunk, or PER - 1 when its lanes have no
+    // slot in the last copy round (that copy is branched around).
+    const bool full_wave = (PER - 1) * 256 + 64 * __builtin_amdgcn_readfirstlane(tid >> 6) < SLOTS;
+    constexpr int kWaitFull = vm_wait_imm(PER), kWaitPart = vm_wait_imm(PER - 1);
     const int per = (nch + nsplit - 1) / nsplit, kb = split * per, ke = min(nch, kb + per);
+    auto step = [&](const float4 *cur, float4 *next2, int k) {
+        if (k + 1 < ke) {
+            if (full_wave) __builtin_amdgcn_s_waitcnt(kWaitFull);
+            else __builtin_amdgcn_s_waitcnt(kWaitPart);
+        } else {
+            __builtin_amdgcn_s_waitcnt(0);
+        }
+        ring_barrier();
+        if (k + 2 < ke) issue(next2, k + 2);
+        if (active) compute(cur, k);
+    };
     if (kb < ke) issue(bufA, kb);
-    for (int k = kb; k < ke; k += 2) {
-        __builtin_amdgcn_s_waitcnt(0);   // this thread's copies into bufA have landed
-        lds_barrier();                   // everyone's have; bufB is no longer being read
-        if (k + 1 < ke) issue(bufB, k + 1);
-        if (active) compute(bufA, k);
+    if (kb + 1 < ke) issue(bufB, kb + 1);
+    for (int k = kb; k < ke; k += 3) {
+        step(bufA, bufC, k);
         if (k + 1 >= ke) break;
-        __builtin_amdgcn_s_waitcnt(0);
-        lds_barrier();
-        if (k + 2 < ke) issue(bufA, k + 2);
-        if (active) compute(bufB, k + 1);
+        step(bufB, bufA, k + 1);
+        if (k + 2 >= ke) break;
+        step(bufC, bufB, k + 2);
     }
     if (!active) return;
     float *out = sino_t + (size_t)split * split_stride;
@@ -996,8 +1045,9 @@ static void fp3d_dma_launch(sipo_plan p, const void *vol_t, void *sino_t, hipStr
 template <int ZC, int NC, bool PAIR, bool SKIP>
 static void fp3d_dma_go(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
                         const SplitSpec &sp) {
-    if (p->p3d_cm == 1) fp3d_dma_launch<ZC, NC, PAIR, SKIP, 1>(p, vol_t, sino_t, s, on, sp);
-    else fp3d_dma_launch<ZC, NC, PAIR, SKIP, kDmaMaxCM>(p, vol_t, sino_t, s, on, sp);
+    // 64 slices stage one step per chunk only: three two-step buffers would not fit in LDS
+    if (ZC > 32 || p->p3d_cm == 1) fp3d_dma_launch<ZC, NC, PAIR, SKIP, 1>(p, vol_t, sino_t, s, on, sp);
+    else fp3d_dma_launch<ZC, NC, PAIR, SKIP, (ZC > 32 ? 1 : kDmaMaxCM)>(p, vol_t, sino_t, s, on, sp);
 }
 
 template <int ZC, int NC>

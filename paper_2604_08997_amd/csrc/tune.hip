@@ -59,7 +59,7 @@ extern "C" int sipo_plan_autotune(sipo_plan p, void *stream) {
             for (int zc : p->dtype == SIPO_F64 ? std::vector<int>{16, 8} : std::vector<int>{32, 16, 64})
                 for (int cm = dma ? 1 : 2; cm <= 2; ++cm)
                     for (int skip = 0; skip <= dma; ++skip) {
-                        if (zc > 32 && !dma) continue;   // 64 slices per thread: asynchronous staging only
+                        if (zc > 32 && (!dma || cm > 1)) continue;   // 64 slices: asynchronous, one-step chunks
                         p->p3d_zc = zc;
                         p->p3d_dma = dma != 0;
                         p->p3d_skip = skip != 0;
@@ -126,6 +126,7 @@ extern "C" int sipo_plan_set_tuning(sipo_plan p, const sipo_tuning *t) {
     SIPO_REQUIRE(t->p3d_dma == 0 || t->p3d_dma == 1, "p3d_dma must be 0 or 1");
     SIPO_REQUIRE(t->p3d_skip == 0 || t->p3d_skip == 1, "p3d_skip must be 0 or 1");
     SIPO_REQUIRE(t->p3d_cm == 1 || t->p3d_cm == 2, "p3d_cm must be 1 or 2");
+    SIPO_REQUIRE(t->p3d_zc <= 32 || t->p3d_cm == 1, "64 slices per thread stage one march step per chunk");
     SIPO_REQUIRE(t->blur_zc == 0 || ((t->blur_zc == 8 || t->blur_zc == 16 || t->blur_zc == 32) && t->blur_zc <= p->nz),
                  "blur_zc %d: expected 0, or 8, 16 or 32 not above nz = %d", t->blur_zc, p->nz);
     SIPO_REQUIRE(!t->p3d_skip || t->p3d_dma, "p3d_skip applies to the asynchronous projector only");

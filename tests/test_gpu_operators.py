@@ -216,13 +216,13 @@ def test_every_projector_and_blur_variant_matches_oracle(case):
             try:
                 plan.set_tuning(p3d_zc=zc, p3d_dma=dma, p3d_skip=skip, p3d_cm=cm)
             except SipoError as e:
-                assert (dma == 1 and not default["p3d_dma"]) or (zc == 64 and dma == 0), (zc, dma, e)
+                assert (dma == 1 and not default["p3d_dma"]) or (zc == 64 and (dma == 0 or cm == 2)), (zc, dma, e)
                 continue
             assert plan.tuning()["p3d_zc"] == zc and plan.tuning()["p3d_cm"] == cm
             fp = plan.project(vol_d).double().cpu().numpy()
             assert rel_norm(fp, fp_ref) < F32_NORM_TOL, (zc, dma, skip, cm)
             ran_async += dma
-    assert ran_async == 16 or not default["p3d_dma"]
+    assert ran_async == 14 or not default["p3d_dma"]
     sino = uniform_field(g.sino_shape, 12)
     bp_ref = P.backproject(sino)
     for bzc in (4, 8, 16, 32):
@@ -250,3 +250,9 @@ def test_set_tuning_rejects_invalid_settings():
         assert p64.tuning() == before
     with pytest.raises(ValueError):
         p64.set_tuning(zc=16)
+    p32 = plan_for(24, 20, nz=64, dtype=torch.float32)
+    before = p32.tuning()
+    for bad in [dict(p3d_zc=64, p3d_dma=0, p3d_skip=0), dict(p3d_zc=64, p3d_dma=1, p3d_cm=2)]:
+        with pytest.raises(SipoError):
+            p32.set_tuning(**bad)
+        assert p32.tuning() == before
