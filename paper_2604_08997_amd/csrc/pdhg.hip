@@ -238,94 +238,218 @@ __global__ void k_row_scaling(const T *R, T *s_up, T *s_lo, const uint8_t *lab, 
 }
 
 // --------------------------------------------------------- iteration kernels
-// t.y = act ? max(0, y - tau q) : 0 with tau = tau_fac T_j (or tau_fac); y <- w ((1+rho) t.y - rho y) + (1-w) y0.
+// The iteration kernels give each thread kPer consecutive elements of its segment, one 16-byte
+// test of the mask bytes for all of them, and four-element vector accesses.  Segments start on
+// multiples of 64 elements and every packed array has the same padding after each instance, so the
+// kPer elements starting at an index below the segment's end are always inside the allocation:
+// elements past the end (the packing gap) are loaded but never stored.
+constexpr int kPer = (int)(kChunk / kThreads);
+static_assert(kPer == 16, "one 16-byte mask word per thread");
+
+template <typename T> struct Q4 { T v[4]; };
+
 template <typename T>
-__global__ void k_primal(T *__restrict__ y, T *__restrict__ yt, const T *__restrict__ q, const T *__restrict__ Tj,
-                         const uint8_t *__restrict__ act, const T *__restrict__ y0, const DevScal *__restrict__ scal,
-                         const Seg *__restrict__ segs) {
-    const DevScal &sc = scal[segs[blockIdx.x].inst];
+__device__ __forceinline__ Q4<T> ld4(const T *p) {
+    Q4<T> r;
+    if constexpr (sizeof(T) == 4) {
+        const float4 a = *(const float4 *)p;
+        r.v[0] = a.x; r.v[1] = a.y; r.v[2] = a.z; r.v[3] = a.w;
+    } else {
+        const double2 a = ((const double2 *)p)[0], b = ((const double2 *)p)[1];
+        r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
+    }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void st4(T *p, const Q4<T> &r) {
+    if constexpr (sizeof(T) == 4) {
+        *(float4 *)p = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+    } else {
+        ((double2 *)p)[0] = make_double2(r.v[0], r.v[1]);
+        ((double2 *)p)[1] = make_double2(r.v[2], r.v[3]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ Q4<T> ld4_or(const T *p, long long i, double s) {
+    if (p) return ld4(p + i);
+    Q4<T> r;
+    r.v[0] = r.v[1] = r.v[2] = r.v[3] = (T)s;
+    return r;
+}
+
+// all four bytes of a mask word nonzero
+__device__ __forceinline__ bool all_bytes(uint32_t w) { return ((w - 0x01010101u) & ~w & 0x80808080u) == 0; }
+__device__ __forceinline__ uint32_t byte_of(uint32_t w, int k) { return (w >> (8 * k)) & 0xFFu; }
+
+// live[s] = 1 when some mask byte of segment s is nonzero (one workgroup per segment)
+__global__ void __launch_bounds__(kThreads) k_seg_live(const uint8_t *__restrict__ m, const Seg *__restrict__ segs,
+                                                       uint8_t *__restrict__ live) {
+    const Seg sg = segs[blockIdx.x];
+    const long long i0 = sg.b + (long long)kPer * threadIdx.x;
+    bool any = false;
+    if (i0 < sg.e) {
+        const uint4 v = *(const uint4 *)(m + i0);
+        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+        const long long n = sg.e - i0;   // bytes of the segment (the rest is packing gap)
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) any = any || (4 * g + k < n && byte_of(w4[g], k) != 0);
+    }
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) live[blockIdx.x] = any ? 1 : 0;
+}
+
+// t.y = act ? max(0, y - tau q) : 0 with tau = tau_fac T_j (or tau_fac); y <- w ((1+rho) t.y - rho y) + (1-w) y0.
+// A masked ray keeps y = t.y = anchor = 0 (all three start at zero there), so it is not stored.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_primal(T *__restrict__ y, T *__restrict__ yt, const T *__restrict__ q,
+                                                     const T *__restrict__ Tj, const uint8_t *__restrict__ act,
+                                                     const T *__restrict__ y0, const DevScal *__restrict__ scal,
+                                                     const Seg *__restrict__ segs) {
+    const Seg sg = segs[blockIdx.x];
+    const long long i0 = sg.b + (long long)kPer * threadIdx.x;
+    if (i0 >= sg.e) return;
+    const uint4 m = *(const uint4 *)(act + i0);
+    if (!(m.x | m.y | m.z | m.w)) return;
+    const DevScal &sc = scal[sg.inst];
     const T tf = (T)sc.tau_fac;
     const T w = (T)sc.w, rho = (T)sc.rho;
-    // A masked ray keeps y = t.y = anchor = 0 (all three start at zero there), so it is not touched.
-    // Each thread takes four consecutive rays and skips them with one 4-byte test of the mask (runs of
-    // masked rays are long: z is the fastest index of the 3D layout).  Segments start on multiples of
-    // four elements; mask bytes past a segment's end lie in the packing gap and are ignored.
-    const Seg sg = segs[blockIdx.x];
-    for (long long i0 = sg.b + 4 * (long long)threadIdx.x; i0 < sg.e; i0 += 4 * (long long)kThreads) {
-        const uint32_t a4 = *(const uint32_t *)(act + i0);
-        if (!a4) continue;
+    const uint32_t mw[4] = {m.x, m.y, m.z, m.w};
+    Q4<T> yo[4], qq[4], tj[4], a0[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        yo[g] = ld4(y + i0 + 4 * g);
+        qq[g] = ld4(q + i0 + 4 * g);
+        tj[g] = ld4_or(Tj, i0 + 4 * g, 1.0);
+        a0[g] = ld4_or(y0, i0 + 4 * g, 0.0);
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        Q4<T> t, yn;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const long long i = i0 + k;
-            if (i >= sg.e || !((a4 >> (8 * k)) & 0xFFu)) continue;
-            const T yo = y[i];
-            const T st = Tj ? tf * Tj[i] : tf;
-            T t = yo - st * q[i];
-            t = t > (T)0 ? t : (T)0;
-            yt[i] = t;
-            y[i] = y0 ? w * (((T)1 + rho) * t - rho * yo) + ((T)1 - w) * y0[i] : t;
+            T v = yo[g].v[k] - tf * tj[g].v[k] * qq[g].v[k];
+            v = v > (T)0 ? v : (T)0;
+            t.v[k] = v;
+            yn.v[k] = y0 ? w * (((T)1 + rho) * v - rho * yo[g].v[k]) + ((T)1 - w) * a0[g].v[k] : v;
+        }
+        const long long ib = i0 + 4 * g;
+        if (all_bytes(mw[g]) && ib + 4 <= sg.e) {
+            st4(yt + ib, t);
+            st4(y + ib, yn);
+        } else if (mw[g]) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (ib + k < sg.e && byte_of(mw[g], k)) { yt[ib + k] = t.v[k]; y[ib + k] = yn.v[k]; }
         }
     }
 }
 
 // Dual step on voxels from D_t (= K P^T t.y) and D (= K P^T z.y); Halpern update of lambda and D;
 // z_lambda for the next step; on check iterations t.lambda and the pre-step lambda are kept.
-// [0] sum_band lambda1, [1] sum_gel U lambda2 of the new lambda.
+// [0] sum_band lambda1, [1] sum_gel U lambda2 of the new lambda.  labelled_only: the dose of
+// unlabelled voxels is not kept (nothing reads it during the solve), so a thread whose voxels are
+// all unlabelled does nothing.  The voxels of a thread are handled in two halves of eight, each
+// with all of its loads issued before its arithmetic.
 template <typename T>
-__global__ void k_dual(const T *__restrict__ Dt, T *__restrict__ D, const T *__restrict__ D0, T *__restrict__ lu,
-                       T *__restrict__ ll, const T *__restrict__ lu0, const T *__restrict__ ll0, T *__restrict__ z,
-                       const uint8_t *__restrict__ lab, const T *__restrict__ lo, const T *__restrict__ hi,
-                       const T *__restrict__ s_up, const T *__restrict__ s_lo, T *__restrict__ lut,
-                       T *__restrict__ llt, T *__restrict__ luo, T *__restrict__ llo, const DevScal *__restrict__ scal,
-                       const InstC *__restrict__ insts, const Seg *__restrict__ segs, double *partials,
-                       int labelled_only) {
-    const int inst = segs[blockIdx.x].inst;
-    const DevScal &sc = scal[inst];
-    const LPConst c = insts[inst].c;
-    const double sf = sc.sig_fac;
+__global__ void __launch_bounds__(kThreads) k_dual(
+    const T *__restrict__ Dt, T *__restrict__ D, const T *__restrict__ D0, T *__restrict__ lu, T *__restrict__ ll,
+    const T *__restrict__ lu0, const T *__restrict__ ll0, T *__restrict__ z, const uint8_t *__restrict__ lab,
+    const T *__restrict__ lo, const T *__restrict__ hi, const T *__restrict__ s_up, const T *__restrict__ s_lo,
+    T *__restrict__ lut, T *__restrict__ llt, T *__restrict__ luo, T *__restrict__ llo,
+    const DevScal *__restrict__ scal, const InstC *__restrict__ insts, const Seg *__restrict__ segs, double *partials,
+    int labelled_only) {
+    const Seg sg = segs[blockIdx.x];
+    const DevScal &sc = scal[sg.inst];
+    const LPConst c = insts[sg.inst].c;
+    const T sf = (T)sc.sig_fac;
     const T ub = (T)(c.u_free ? sc.ubar : c.h);
     const T vb = (T)(c.v_free ? sc.vbar : 1.0);
     const T w = (T)sc.w, rho = (T)sc.rho, w1 = (T)1 - w, rp = (T)1 + rho;
     double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
-    // four consecutive voxels per thread; labelled_only: the dose of unlabelled voxels is not kept
-    // (nothing reads it during the solve), so groups of four unlabelled voxels are skipped on one
-    // 4-byte test (label bytes past a segment's end lie in the packing gap and are ignored)
-    const Seg sg = segs[blockIdx.x];
-    for (long long i0 = sg.b + 4 * (long long)threadIdx.x; i0 < sg.e; i0 += 4 * (long long)kThreads) {
-        const uint32_t l4 = *(const uint32_t *)(lab + i0);
-        if (labelled_only && !l4) continue;
-    #pragma unroll
-        for (int k4 = 0; k4 < 4; ++k4) {
-            const long long i = i0 + k4;
-            if (i >= sg.e) continue;
-            const uint8_t L = (uint8_t)((l4 >> (8 * k4)) & 0xFFu);
-            if (labelled_only && L == 0) continue;
-            const T dt = Dt[i], dz = D[i];
-            D[i] = D0 ? w * (rp * dt - rho * dz) + w1 * D0[i] : dt;
-            if (L == 0) continue;
-            const T Db = (T)2 * dt - dz;
-            const T su = s_up ? (T)sf * s_up[i] : (T)sf;
-            const T a_old = lu[i];
-            T a = a_old + su * (Db - (L == 1 ? ub : vb * ld_or(hi, i, c.hi_s)));
-            a = a > (T)0 ? a : (T)0;
-            const T a_new = lu0 ? w * (rp * a - rho * a_old) + w1 * lu0[i] : a;
-            lu[i] = a_new;
-            if (lut) { lut[i] = a; luo[i] = a_old; }
-            T zz = a_new;
-            if (L == 1) {
-                acc[0] += (double)a_new;
-            } else {
-                const T sl = s_lo ? (T)sf * s_lo[i] : (T)sf;
-                const T b_old = ll[i];
-                T b = b_old + sl * (ld_or(lo, i, c.lo_s) - Db);
-                b = b > (T)0 ? b : (T)0;
-                const T b_new = ll0 ? w * (rp * b - rho * b_old) + w1 * ll0[i] : b;
-                ll[i] = b_new;
-                if (llt) { llt[i] = b; llo[i] = b_old; }
-                zz = a_new - b_new;
-                acc[1] += (double)ld_or(hi, i, c.hi_s) * (double)a_new;
+    const long long i0 = sg.b + (long long)kPer * threadIdx.x;
+    uint4 l16 = make_uint4(0u, 0u, 0u, 0u);
+    if (i0 < sg.e) l16 = *(const uint4 *)(lab + i0);
+    const uint32_t lw[4] = {l16.x, l16.y, l16.z, l16.w};
+    if (i0 < sg.e && (!labelled_only || (l16.x | l16.y | l16.z | l16.w))) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            Q4<T> dt[2], dz[2], d0[2], a_old[2], a_0[2], su[2], U[2], b_old[2], b_0[2], sl[2], Lo[2];
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                const long long ib = i0 + 4 * (2 * h + g);
+                dt[g] = ld4(Dt + ib);
+                dz[g] = ld4(D + ib);
+                d0[g] = ld4_or(D0, ib, 0.0);
+                a_old[g] = ld4(lu + ib);
+                a_0[g] = ld4_or(lu0, ib, 0.0);
+                su[g] = ld4_or(s_up, ib, 1.0);
+                U[g] = ld4_or(hi, ib, c.hi_s);
+                b_old[g] = ld4(ll + ib);
+                b_0[g] = ld4_or(ll0, ib, 0.0);
+                sl[g] = ld4_or(s_lo, ib, 1.0);
+                Lo[g] = ld4_or(lo, ib, c.lo_s);
             }
-            z[i] = zz;
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                const uint32_t L4 = lw[2 * h + g];
+                const long long ib = i0 + 4 * (2 * h + g);
+                Q4<T> dn, an, at, bn, bt, zz;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t L = byte_of(L4, k);
+                    const T t = dt[g].v[k], d = dz[g].v[k];
+                    dn.v[k] = D0 ? w * (rp * t - rho * d) + w1 * d0[g].v[k] : t;
+                    const T Db = (T)2 * t - d;
+                    T a = a_old[g].v[k] + sf * su[g].v[k] * (Db - (L == 1 ? ub : vb * U[g].v[k]));
+                    a = a > (T)0 ? a : (T)0;
+                    at.v[k] = a;
+                    an.v[k] = lu0 ? w * (rp * a - rho * a_old[g].v[k]) + w1 * a_0[g].v[k] : a;
+                    T b = b_old[g].v[k] + sf * sl[g].v[k] * (Lo[g].v[k] - Db);
+                    b = b > (T)0 ? b : (T)0;
+                    bt.v[k] = b;
+                    bn.v[k] = ll0 ? w * (rp * b - rho * b_old[g].v[k]) + w1 * b_0[g].v[k] : b;
+                    zz.v[k] = L == 2 ? an.v[k] - bn.v[k] : an.v[k];
+                    if (ib + k < sg.e) {
+                        if (L == 1) acc[0] += (double)an.v[k];
+                        if (L == 2) acc[1] += (double)U[g].v[k] * (double)an.v[k];
+                    }
+                }
+                if (ib + 4 <= sg.e) {
+                    st4(D + ib, dn);   // unlabelled voxels too: their dose is either kept or not read
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (ib + k < sg.e) D[ib + k] = dn.v[k];
+                }
+                if (ib + 4 <= sg.e && all_bytes(L4)) {
+                    st4(lu + ib, an);
+                    st4(z + ib, zz);
+                    if (lut) { st4(lut + ib, at); st4(luo + ib, a_old[g]); }
+                } else if (L4) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (ib + k < sg.e && byte_of(L4, k)) {
+                            lu[ib + k] = an.v[k];
+                            z[ib + k] = zz.v[k];
+                            if (lut) { lut[ib + k] = at.v[k]; luo[ib + k] = a_old[g].v[k]; }
+                        }
+                }
+                if (ib + 4 <= sg.e && L4 == 0x02020202u) {
+                    st4(ll + ib, bn);
+                    if (llt) { st4(llt + ib, bt); st4(llo + ib, b_old[g]); }
+                } else if (L4) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (ib + k < sg.e && byte_of(L4, k) == 2) {
+                            ll[ib + k] = bn.v[k];
+                            if (llt) { llt[ib + k] = bt.v[k]; llo[ib + k] = b_old[g].v[k]; }
+                        }
+                }
+            }
         }
     }
     block_sums(acc, partials);
@@ -599,6 +723,7 @@ struct Layout {
     size_t lu, ll, D, Dt, D0, z, tmp, tmp2, s_up, s_lo, lut, llt, luo, llo, snap_u, snap_l, lu0, ll0, lul, lll, lab,
         lo, hi, vol_t;
     // tables
+    size_t segSL = 0, segVL = 0, firstVL = 0, cntVL = 0, live = 0;   // tables of the segments with work
     size_t partials, insts, scal, segS, segV, firstS, cntS, firstV, cntV, list_act, list_tmp, sums, geo, items_bp,
         items_fp, items_tr;
     size_t total = 0;
@@ -680,6 +805,10 @@ static Layout make_layout(const sipo_problem *probs, int B) {
     L.segV = take(sizeof(Seg) * std::max(L.max_seg_v, 1));
     L.firstS = take(sizeof(int) * B); L.cntS = take(sizeof(int) * B);
     L.firstV = take(sizeof(int) * B); L.cntV = take(sizeof(int) * B);
+    L.segSL = take(sizeof(Seg) * std::max(L.max_seg_s, 1));
+    L.segVL = take(sizeof(Seg) * std::max(L.max_seg_v, 1));
+    L.firstVL = take(sizeof(int) * B); L.cntVL = take(sizeof(int) * B);
+    L.live = take((size_t)L.max_seg_s + L.max_seg_v + 2);
     L.list_act = take(sizeof(int) * B); L.list_tmp = take(sizeof(int) * B);
     L.sums = take(sizeof(double) * kNS * B);
     L.geo = take(sizeof(Geo2D) * B);
@@ -769,6 +898,12 @@ class Solver {
     std::vector<DevScal> hsc_;
     std::vector<int> active_;               // instances the iteration kernels run on
     int n_seg_s_ = 0, n_seg_v_ = 0, n_items_bp_ = 0, n_items_fp_ = 0, n_items_tr_ = 0;
+    // Segments where the primal step (some active ray) and the dual step (some labelled voxel, when
+    // the dual step skips unlabelled ones) have work: per instance and segment, empty = all.  The
+    // masks are fixed for the solve, so these are found once; the two steps launch over them only.
+    std::vector<std::vector<uint8_t>> live_s_, live_v_;
+    std::vector<int> fs_, cs_, fv_, cv_;   // ranges of each instance in the current full tables
+    int n_seg_sl_ = 0, n_seg_vl_ = 0;
     std::vector<double> hsums_;             // [B][kNS]
     hipGraphExec_t graph_exec_ = nullptr;
     int graph_len_ = 0;
@@ -782,6 +917,8 @@ class Solver {
     const T *hi_() const { return L_.lohi ? F(L_.hi) : nullptr; }
     const Seg *segS() const { return P<Seg>(L_.segS); }
     const Seg *segV() const { return P<Seg>(L_.segV); }
+    const Seg *segSL() const { return P<Seg>(L_.segSL); }
+    const Seg *segVL() const { return P<Seg>(L_.segVL); }
     double *partials() const { return P<double>(L_.partials); }
     const InstC *insts() const { return P<InstC>(L_.insts); }
     DevScal *scal() const { return P<DevScal>(L_.scal); }
@@ -802,6 +939,28 @@ class Solver {
     void set_flags(const std::vector<int> &on) {
         for (int i = 0; i < B_; ++i) hin_[i].flag = 0;
         for (int i : on) hin_[i].flag = 1;
+    }
+
+    // Finds the segments with work for the primal and dual steps (see live_s_) and rebuilds the tables.
+    int live_tables() {
+        const size_t nv_off = (size_t)L_.max_seg_s;
+        if (n_seg_s_)
+            hipLaunchKernelGGL(k_seg_live, dim3(n_seg_s_), dim3(kThreads), 0, s_, (const uint8_t *)U8(L_.act), segS(),
+                               U8(L_.live));
+        if (mask_ && n_seg_v_)
+            hipLaunchKernelGGL(k_seg_live, dim3(n_seg_v_), dim3(kThreads), 0, s_, (const uint8_t *)U8(L_.lab), segV(),
+                               U8(L_.live) + nv_off);
+        std::vector<uint8_t> h(nv_off + (size_t)L_.max_seg_v);
+        SIPO_HIP(hipMemcpyAsync(h.data(), U8(L_.live), h.size(), hipMemcpyDeviceToHost, s_));
+        SIPO_HIP(hipStreamSynchronize(s_));
+        live_s_.assign(B_, {});
+        live_v_.assign(B_, {});
+        for (int i : active_) {
+            live_s_[i].assign(h.begin() + fs_[i], h.begin() + fs_[i] + cs_[i]);
+            if (mask_) live_v_[i].assign(h.begin() + nv_off + fv_[i], h.begin() + nv_off + fv_[i] + cv_[i]);
+        }
+        const std::vector<int> list = active_;
+        return set_active(list);
     }
 
     // Segment tables, per-instance workgroup ranges and work items for the instances in `list`.
@@ -838,6 +997,20 @@ class Solver {
         }
         n_seg_s_ = (int)ss.size();
         n_seg_v_ = (int)sv.size();
+        std::vector<Seg> ssl, svl;
+        std::vector<int> fvl(B_, 0), cvl(B_, 0);
+        for (int i : list) {
+            const bool all_s = live_s_.empty() || live_s_[i].empty(), all_v = live_v_.empty() || live_v_[i].empty();
+            for (int k = 0; k < cs[i]; ++k)
+                if (all_s || live_s_[i][k]) ssl.push_back(ss[fs[i] + k]);
+            fvl[i] = (int)svl.size();
+            for (int k = 0; k < cv[i]; ++k)
+                if (all_v || live_v_[i][k]) svl.push_back(sv[fv[i] + k]);
+            cvl[i] = (int)svl.size() - fvl[i];
+        }
+        n_seg_sl_ = (int)ssl.size();
+        n_seg_vl_ = (int)svl.size();
+        fs_ = fs; cs_ = cs; fv_ = fv; cv_ = cv;
         n_items_bp_ = (int)ib.size();
         n_items_fp_ = (int)ifp.size();
         n_items_tr_ = (int)itr.size();
@@ -847,6 +1020,10 @@ class Solver {
         if (!rc) rc = upload(L_.cntS, cs.data(), sizeof(int) * B_);
         if (!rc) rc = upload(L_.firstV, fv.data(), sizeof(int) * B_);
         if (!rc) rc = upload(L_.cntV, cv.data(), sizeof(int) * B_);
+        if (!rc) rc = upload(L_.segSL, ssl.data(), sizeof(Seg) * ssl.size());
+        if (!rc) rc = upload(L_.segVL, svl.data(), sizeof(Seg) * svl.size());
+        if (!rc) rc = upload(L_.firstVL, fvl.data(), sizeof(int) * B_);
+        if (!rc) rc = upload(L_.cntVL, cvl.data(), sizeof(int) * B_);
         if (!rc) rc = upload(L_.list_act, list.data(), sizeof(int) * list.size());
         if (!rc && b2d_) {
             rc = upload(L_.geo, geo.data(), sizeof(Geo2D) * B_);
@@ -1134,11 +1311,12 @@ int Solver<T>::setup_common() {
         // From here on the 3D operators skip what the restarted scheme never reads: q = P K z off the
         // active rays, and P^T y away from the labelled voxels and their PSF neighbourhood (every row
         // scaling, residual and certificate test reads D on labelled voxels and q on active rays).
-        // Few workgroups stay on, each with a long serial walk.  The masked operators run with at most 16
-        // slices per thread (finer chunks give more workgroups; at 256^3 x 360 this is the fastest of the
-        // 8 / 16 / 32 choices for both operators), the backprojector's view walk is split so that the
-        // switched-on tiles fill the chip, and the projector's march is split only when very few of its
-        // workgroups stay on.  The plans' own settings are restored when the solver ends.
+        // Few workgroups stay on, each with a long serial walk.  The masked projector runs with at most 16
+        // slices per thread and the masked backprojector with at most 8 (finer chunks give more
+        // workgroups; at 256^3 x 360 these are the fastest of the 4 / 8 / 16 / 32 choices), the
+        // backprojector's view walk is split so that the switched-on tiles give about eight workgroups
+        // per CU, and the projector's march is split only when very few of its workgroups stay on.  The
+        // plans' own settings are restored when the solver ends.
         int cus = 256;
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, probs_[0].plan->device);
         psp_.assign(B_, SplitSpec());
@@ -1165,7 +1343,7 @@ int Solver<T>::setup_common() {
             if (!seen) {
                 zc_saved_.push_back({p, {p->p3d_zc, p->bp3d_zc}});
                 p->p3d_zc = std::min(p->p3d_zc, 16);
-                p->bp3d_zc = std::min(p->bp3d_zc, 16);
+                p->bp3d_zc = std::min(p->bp3d_zc, 8);
             }
             rc = launch_p3d_flags(p, U8(L_.act) + I.soff, U8(L_.pflags) + L_.pfo[i], s_);
             if (!rc) rc = launch_bp3d_flags(p, U8(L_.lab) + I.voff, U8(L_.bflags) + L_.bfo[i], s_);
@@ -1174,10 +1352,12 @@ int Solver<T>::setup_common() {
             const long long onb = count_on(L_.bflags + L_.bfo[i], bp3d_flag_count(p));
             if (onp < 0 || onb < 0) return fail(SIPO_E_DEVICE, "pdhg setup: reading the skip flags failed");
             psp_[i] = SplitSpec{parts_for(onp, cus, kMaxSplitP), F(L_.ppart)};
-            bsp_[i] = SplitSpec{parts_for(onb, 4LL * cus, kMaxSplitB), F(L_.bpart)};
+            bsp_[i] = SplitSpec{parts_for(onb, 8LL * cus, kMaxSplitB), F(L_.bpart)};
         }
         mask_ = true;
     }
+    rc = live_tables();
+    if (rc) return rc;
     rc = lambda_z(L_.lu, L_.ll, L_.z, false);
     if (!rc) rc = finish(true, all, 2);
     if (rc) return rc;
@@ -1342,24 +1522,26 @@ int Solver<T>::iteration(bool check) {
     int rc = mark(-1);   // start of this iteration's timeline segment
     if (!rc) rc = adjoint(L_.z, L_.q);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_primal<T>), gS(), dim3(kThreads), 0, s_, F(L_.y), F(L_.yt), (const T *)F(L_.q),
-                       hal ? (const T *)F(L_.Tj) : (const T *)nullptr, (const uint8_t *)U8(L_.act),
-                       hal ? (const T *)F(L_.y0) : (const T *)nullptr, (const DevScal *)scal(), segS());
+    if (n_seg_sl_)
+        hipLaunchKernelGGL((k_primal<T>), dim3(n_seg_sl_), dim3(kThreads), 0, s_, F(L_.y), F(L_.yt), (const T *)F(L_.q),
+                           hal ? (const T *)F(L_.Tj) : (const T *)nullptr, (const uint8_t *)U8(L_.act),
+                           hal ? (const T *)F(L_.y0) : (const T *)nullptr, (const DevScal *)scal(), segSL());
     rc = mark(SIPO_PHASE_PRIMAL);
     if (!rc) rc = dose(L_.yt, L_.Dt);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_dual<T>), gV(), dim3(kThreads), 0, s_, (const T *)F(L_.Dt), F(L_.D),
+    if (n_seg_vl_)
+        hipLaunchKernelGGL((k_dual<T>), dim3(n_seg_vl_), dim3(kThreads), 0, s_, (const T *)F(L_.Dt), F(L_.D),
                        hal ? (const T *)F(L_.D0) : (const T *)nullptr, F(L_.lu), F(L_.ll),
                        hal ? (const T *)F(L_.lu0) : (const T *)nullptr, hal ? (const T *)F(L_.ll0) : (const T *)nullptr,
                        F(L_.z), (const uint8_t *)U8(L_.lab), lo_(), hi_(),
                        hal ? (const T *)F(L_.s_up) : (const T *)nullptr, hal ? (const T *)F(L_.s_lo) : (const T *)nullptr,
                        check ? F(L_.lut) : (T *)nullptr, check ? F(L_.llt) : (T *)nullptr,
                        check ? F(L_.luo) : (T *)nullptr, check ? F(L_.llo) : (T *)nullptr, (const DevScal *)scal(),
-                       insts(), segV(), partials(), mask_ ? 1 : 0);
+                       insts(), segVL(), partials(), mask_ ? 1 : 0);
     rc = mark(SIPO_PHASE_DUAL);
     if (rc) return rc;
     hipLaunchKernelGGL(k_scalars, dim3(active_.size()), dim3(kThreads), 0, s_, (const double *)partials(),
-                       (const int *)P<int>(L_.firstV), (const int *)P<int>(L_.cntV), (const int *)P<int>(L_.list_act),
+                       (const int *)P<int>(L_.firstVL), (const int *)P<int>(L_.cntVL), (const int *)P<int>(L_.list_act),
                        scal(), insts());
     rc = mark(SIPO_PHASE_SCALARS);
     prof_on_ = false;
