@@ -20,16 +20,30 @@ constexpr int kBTX = 64, kBTY = 16, kBRows = kBTY / 4;   // tile; 256 threads = 
 
 template <typename T, int RXY, int RZ>
 __global__ void __launch_bounds__(256) blur_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int nz,
-                                                   Taps<T> tp, int zchunk) {
+                                                   Taps<T> tp, int zchunk, const uint8_t *__restrict__ tile_on,
+                                                   int zero_off) {
     constexpr int RW = kBTX + 2 * RXY, RH = kBTY + 2 * RXY;
     constexpr int LR = (RH + 3) / 4;   // staged rows per thread
     __shared__ T raw[RH][RW + 1];
     __shared__ T xb[RH][kBTX + 1];
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int x0 = blockIdx.x * kBTX, y0 = blockIdx.y * kBTY;
-    const int z0 = blockIdx.z * zchunk;
+    const int3 tile = xcd_tile<0>();   // x rotated per z chunk: row neighbours share halos in L2
+    const int x0 = tile.x * kBTX, y0 = tile.y * kBTY;
+    const int z0 = tile.z * zchunk;
     const int zend = min(nz, z0 + zchunk);
     const size_t plane = (size_t)n * n;
+    if (tile_on && !tile_on[((size_t)tile.z * gridDim.y + tile.y) * gridDim.x + tile.x]) {
+        if (zero_off) {
+            const int gx = x0 + tx;
+            for (int zo = z0; zo < zend; ++zo)
+#pragma unroll
+                for (int j = 0; j < kBRows; ++j) {
+                    const int gy = y0 + ty + 4 * j;
+                    if (gx < n && gy < n) out[(size_t)zo * plane + (size_t)gy * n + gx] = (T)0;
+                }
+        }
+        return;
+    }
     const int gxm = x0 - RXY + tx, gxh = x0 - RXY + kBTX + tx;
     const bool okm = gxm >= 0 && gxm < n, okh = tx < 2 * RXY && gxh >= 0 && gxh < n;
 
@@ -124,49 +138,100 @@ static int pick_zchunk(int n, int nz, int rz) {
     return (int)std::min<long>(zc, nz);
 }
 
+static int blur_zchunk(sipo_plan p) {
+    const int rz = p->dtype == SIPO_F64 ? p->taps_d.rz : p->taps_f.rz;
+    return p->blur_zc > 0 ? std::min(p->blur_zc, p->nz) : pick_zchunk(p->n, p->nz, rz);
+}
+
+size_t blur_tile_count(sipo_plan p, int zc) {
+    if (!p->has_psf) return 0;
+    zc = zc > 0 ? std::min(zc, p->nz) : blur_zchunk(p);
+    return (size_t)((p->n + kBTX - 1) / kBTX) * ((p->n + kBTY - 1) / kBTY) * ((p->nz + zc - 1) / zc);
+}
+
+// own[tile of a labelled voxel] = 1; reach[every tile within (rx, ry, rz) of it] = 1
+__global__ void k_blur_flags(const uint8_t *__restrict__ lab, uint8_t *__restrict__ own, uint8_t *__restrict__ reach,
+                             int n, int nz, int rx, int ry, int rz, int zc, int gx, int gy, int gz) {
+    const long long total = (long long)nz * n * n;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+        if (!lab[i]) continue;
+        const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
+        own[((size_t)(z / zc) * gy + y / kBTY) * gx + x / kBTX] = 1;
+        const int tx0 = max(x - rx, 0) / kBTX, tx1 = min(x + rx, n - 1) / kBTX;
+        const int ty0 = max(y - ry, 0) / kBTY, ty1 = min(y + ry, n - 1) / kBTY;
+        const int tz0 = max(z - rz, 0) / zc, tz1 = min(z + rz, nz - 1) / zc;
+        for (int tz = tz0; tz <= tz1 && tz < gz; ++tz)
+            for (int ty = ty0; ty <= ty1 && ty < gy; ++ty)
+                for (int tx = tx0; tx <= tx1 && tx < gx; ++tx) reach[((size_t)tz * gy + ty) * gx + tx] = 1;
+    }
+}
+
+__global__ void k_blur_flags_clear(uint8_t *a, uint8_t *b, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        a[i] = b[i] = 0;
+}
+
+int launch_blur_flags(sipo_plan p, const uint8_t *labels, uint8_t *own, uint8_t *reach, hipStream_t s) {
+    const size_t cnt = blur_tile_count(p);
+    if (!cnt) return SIPO_OK;
+    const int zc = blur_zchunk(p);
+    const int gx = (p->n + kBTX - 1) / kBTX, gy = (p->n + kBTY - 1) / kBTY, gz = (p->nz + zc - 1) / zc;
+    hipLaunchKernelGGL(k_blur_flags_clear, dim3((unsigned)std::min<size_t>((cnt + 255) / 256, 4096)), dim3(256), 0, s,
+                       own, reach, (long long)cnt);
+    const int rx = p->taps_d.rx, ry = p->taps_d.ry, rz = p->taps_d.rz;
+    const long long total = (long long)p->nz * p->n * p->n;
+    hipLaunchKernelGGL(k_blur_flags, dim3((unsigned)std::min<long long>((total + 255) / 256, 16384)), dim3(256), 0, s,
+                       labels, own, reach, p->n, p->nz, rx, ry, rz, zc, gx, gy, gz);
+    SIPO_LAUNCHED("k_blur_flags");
+    return SIPO_OK;
+}
+
 template <typename T, int RXY, int RZ>
-static void launch_r(const Taps<T> &tp, const void *in, void *out, int n, int nz, int zc, hipStream_t s) {
-    const int zchunk = zc > 0 ? std::min(zc, nz) : pick_zchunk(n, nz, RZ);
+static void launch_r(const Taps<T> &tp, const void *in, void *out, int n, int nz, int zchunk, hipStream_t s,
+                     const uint8_t *on, int zero_off) {
     const dim3 grid((n + kBTX - 1) / kBTX, (n + kBTY - 1) / kBTY, (nz + zchunk - 1) / zchunk);
     hipLaunchKernelGGL((blur_kernel<T, RXY, RZ>), grid, dim3(kBTX, 4), 0, s, (const T *)in, (T *)out, n, nz, tp,
-                       zchunk);
+                       zchunk, on, zero_off);
 }
 
 template <typename T, int RXY>
-static int launch_rz(const Taps<T> &tp, const void *in, void *out, int n, int nz, int zc, hipStream_t s) {
+static int launch_rz(const Taps<T> &tp, const void *in, void *out, int n, int nz, int zc, hipStream_t s,
+                     const uint8_t *on, int zero_off) {
     switch (tp.rz) {
-        case 0: launch_r<T, RXY, 0>(tp, in, out, n, nz, zc, s); break;
-        case 1: launch_r<T, RXY, 1>(tp, in, out, n, nz, zc, s); break;
-        case 2: launch_r<T, RXY, 2>(tp, in, out, n, nz, zc, s); break;
-        case 3: launch_r<T, RXY, 3>(tp, in, out, n, nz, zc, s); break;
-        case 4: launch_r<T, RXY, 4>(tp, in, out, n, nz, zc, s); break;
-        case 5: launch_r<T, RXY, 5>(tp, in, out, n, nz, zc, s); break;
-        case 6: launch_r<T, RXY, 6>(tp, in, out, n, nz, zc, s); break;
-        case 7: launch_r<T, RXY, 7>(tp, in, out, n, nz, zc, s); break;
-        case 8: launch_r<T, RXY, 8>(tp, in, out, n, nz, zc, s); break;
+        case 0: launch_r<T, RXY, 0>(tp, in, out, n, nz, zc, s, on, zero_off); break;
+        case 1: launch_r<T, RXY, 1>(tp, in, out, n, nz, zc, s, on, zero_off); break;
+        case 2: launch_r<T, RXY, 2>(tp, in, out, n, nz, zc, s, on, zero_off); break;
+        case 3: launch_r<T, RXY, 3>(tp, in, out, n, nz, zc, s, on, zero_off); break;
+        case 4: launch_r<T, RXY, 4>(tp, in, out, n, nz, zc, s, on, zero_off); break;
+        case 5: launch_r<T, RXY, 5>(tp, in, out, n, nz, zc, s, on, zero_off); break;
+        case 6: launch_r<T, RXY, 6>(tp, in, out, n, nz, zc, s, on, zero_off); break;
+        case 7: launch_r<T, RXY, 7>(tp, in, out, n, nz, zc, s, on, zero_off); break;
+        case 8: launch_r<T, RXY, 8>(tp, in, out, n, nz, zc, s, on, zero_off); break;
         default: return fail(SIPO_E_UNSUPPORTED, "PSF z radius %d > %d", tp.rz, kMaxR);
     }
     return SIPO_OK;
 }
 
 template <typename T>
-static int blur_dispatch(sipo_plan p, const Taps<T> &taps, const void *in, void *out, hipStream_t s) {
+static int blur_dispatch(sipo_plan p, const Taps<T> &taps, const void *in, void *out, hipStream_t s,
+                         const uint8_t *on, int zero_off) {
     Taps<T> tp = taps;
     const int R = std::max(tp.rx, tp.ry);
     pad_taps(tp.kx, tp.rx, R);
     pad_taps(tp.ky, tp.ry, R);
     tp.rx = tp.ry = R;
+    const int zc = blur_zchunk(p);
     int rc;
     switch (R) {
-        case 0: rc = launch_rz<T, 0>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
-        case 1: rc = launch_rz<T, 1>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
-        case 2: rc = launch_rz<T, 2>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
-        case 3: rc = launch_rz<T, 3>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
-        case 4: rc = launch_rz<T, 4>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
-        case 5: rc = launch_rz<T, 5>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
-        case 6: rc = launch_rz<T, 6>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
-        case 7: rc = launch_rz<T, 7>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
-        case 8: rc = launch_rz<T, 8>(tp, in, out, p->n, p->nz, p->blur_zc, s); break;
+        case 0: rc = launch_rz<T, 0>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
+        case 1: rc = launch_rz<T, 1>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
+        case 2: rc = launch_rz<T, 2>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
+        case 3: rc = launch_rz<T, 3>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
+        case 4: rc = launch_rz<T, 4>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
+        case 5: rc = launch_rz<T, 5>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
+        case 6: rc = launch_rz<T, 6>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
+        case 7: rc = launch_rz<T, 7>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
+        case 8: rc = launch_rz<T, 8>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
         default: return fail(SIPO_E_UNSUPPORTED, "PSF xy radius %d > %d", R, kMaxR);
     }
     if (rc) return rc;
@@ -174,13 +239,13 @@ static int blur_dispatch(sipo_plan p, const Taps<T> &taps, const void *in, void 
     return SIPO_OK;
 }
 
-int launch_blur(sipo_plan p, const void *in, void *out, hipStream_t s) {
+int launch_blur(sipo_plan p, const void *in, void *out, hipStream_t s, const uint8_t *tile_on, int zero_off) {
     if (!p->has_psf) {
         SIPO_HIP(hipMemcpyAsync(out, in, p->vol_elems() * p->elem_bytes(), hipMemcpyDeviceToDevice, s));
         return SIPO_OK;
     }
-    return p->dtype == SIPO_F64 ? blur_dispatch<double>(p, p->taps_d, in, out, s)
-                                : blur_dispatch<float>(p, p->taps_f, in, out, s);
+    return p->dtype == SIPO_F64 ? blur_dispatch<double>(p, p->taps_d, in, out, s, tile_on, zero_off)
+                                : blur_dispatch<float>(p, p->taps_f, in, out, s, tile_on, zero_off);
 }
 
 }  // namespace sipo

@@ -713,6 +713,8 @@ struct Layout {
     bool lohi = false;                          // per-voxel bounds packed (some instance has arrays)
     size_t vol_t_elems = 0;                     // internal-layout volume scratch (largest 3D instance)
     std::vector<size_t> pfo, bfo;               // byte offsets of each 3D instance's skip flags
+    std::vector<size_t> kfo;                    // and of its two blur tile flag arrays (own, reach)
+    size_t kf_bytes = 0, kflags = 0;
     size_t pf_bytes = 0, bf_bytes = 0;          // projector / backprojector flag totals
     size_t pflags = 0, bflags = 0;              // their fields
     size_t part_s = 0, part_v = 0;              // elements of the largest 3D instance's sinogram / volume
@@ -731,6 +733,9 @@ struct Layout {
 
 // Largest splits of the 3D projector's march and of the backprojector's views in LP solves.
 constexpr int kMaxSplitP = 4, kMaxSplitB = 8;
+// slices per blur tile in masked solves: a blur workgroup streams its slices and the PSF halo one by
+// one, so the few tiles left on run shortest with short chunks
+constexpr int kMaskBlurZc = 4;
 
 static bool use_batch2d(const sipo_problem *probs, int B) {
     for (int i = 0; i < B; ++i) {
@@ -748,6 +753,7 @@ static Layout make_layout(const sipo_problem *probs, int B) {
     L.voff.resize(B);
     L.pfo.assign(B, 0);
     L.bfo.assign(B, 0);
+    L.kfo.assign(B, 0);
     const bool b2d = use_batch2d(probs, B);
     for (int i = 0; i < B; ++i) {
         const sipo_plan p = probs[i].plan;
@@ -766,6 +772,8 @@ static Layout make_layout(const sipo_problem *probs, int B) {
             // room for the finest slice counts the solve may switch to (8 and 4 slices per thread)
             L.pf_bytes += align_up(p3d_flag_count(p, 8));
             L.bf_bytes += align_up(bp3d_flag_count(p, 4));
+            L.kfo[i] = L.kf_bytes;
+            L.kf_bytes += 2 * align_up(blur_tile_count(p, kMaskBlurZc));
             L.part_s = std::max(L.part_s, (size_t)ns);
             L.part_v = std::max(L.part_v, (size_t)nv);
         }
@@ -795,6 +803,7 @@ static Layout make_layout(const sipo_problem *probs, int B) {
     L.vol_t = take(L.vol_t_elems * L.eb);
     L.pflags = take(L.pf_bytes);
     L.bflags = take(L.bf_bytes);
+    L.kflags = take(L.kf_bytes);
     L.ppart = take(L.part_s * L.eb * kMaxSplitP);
     L.bpart = take(L.part_v * L.eb * kMaxSplitB);
     const int max_seg = std::max(std::max(L.max_seg_s, L.max_seg_v), 1);
@@ -858,8 +867,9 @@ class Solver {
     }
     ~Solver() {
         for (auto &e : zc_saved_) {
-            e.first->p3d_zc = e.second.first;
-            e.first->bp3d_zc = e.second.second;
+            e.p->p3d_zc = e.p3d;
+            e.p->bp3d_zc = e.bp3d;
+            e.p->blur_zc = e.blur;
         }
         if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
         for (hipEvent_t e : ev_) (void)hipEventDestroy(e);
@@ -889,7 +899,11 @@ class Solver {
     bool mask_ = false;                     // 3D operators skip workgroups the LP does not read
     std::vector<SplitSpec> psp_, bsp_;      // per instance: splits of the masked 3D operators
     // the plans' own slices per thread, which the masked operators change and the solver restores
-    std::vector<std::pair<sipo_plan, std::pair<int, int>>> zc_saved_;
+    struct ZcSaved {
+        sipo_plan p;
+        int p3d, bp3d, blur;
+    };
+    std::vector<ZcSaved> zc_saved_;
     int nc_max_ = 3;
     bool bp_staged_ = true;
     int n_max_ = 1;
@@ -918,6 +932,10 @@ class Solver {
     const Seg *segS() const { return P<Seg>(L_.segS); }
     const Seg *segV() const { return P<Seg>(L_.segV); }
     const Seg *segSL() const { return P<Seg>(L_.segSL); }
+    // blur tile flags of a 3D instance (restarted solves): tiles holding a labelled voxel, and tiles
+    // within the PSF radius of one
+    uint8_t *blur_own(int i) const { return U8(L_.kflags) + L_.kfo[i]; }
+    uint8_t *blur_reach(int i) const { return U8(L_.kflags) + L_.kfo[i] + align_up(blur_tile_count(in_[i].p, kMaskBlurZc)); }
     const Seg *segVL() const { return P<Seg>(L_.segVL); }
     double *partials() const { return P<double>(L_.partials); }
     const InstC *insts() const { return P<InstC>(L_.insts); }
@@ -1101,7 +1119,8 @@ class Solver {
             T *tmp = F(L_.tmp) + I.voff;
             int rc = launch_backproject_t(I.p, y, tmp, 0, s_, on, sp);
             if (!rc) rc = mark(SIPO_PHASE_BACKPROJECT);
-            if (!rc) rc = launch_blur(I.p, tmp, out, s_);
+            // masked: the dose is read on labelled voxels only, so tiles without one are skipped
+            if (!rc) rc = launch_blur(I.p, tmp, out, s_, m ? blur_own(i) : nullptr, 0);
             if (!rc) rc = mark(SIPO_PHASE_BLUR);
             if (rc) return rc;
         }
@@ -1123,7 +1142,10 @@ class Solver {
             int rc = SIPO_OK;
             if (I.p->has_psf) {
                 T *tmp = F(L_.tmp) + I.voff;
-                rc = launch_blur(I.p, src, tmp, s_);
+                // masked: z vanishes off the labelled voxels, so K z is zero on tiles out of the PSF's
+                // reach of them; those tiles are written as zeros without reading z
+                const bool m = mask_ && I.t3;
+                rc = launch_blur(I.p, src, tmp, s_, m ? blur_reach(i) : nullptr, 1);
                 if (!rc) rc = mark(SIPO_PHASE_BLUR);
                 src = tmp;
             }
@@ -1339,14 +1361,16 @@ int Solver<T>::setup_common() {
             if (!I.t3) continue;
             sipo_plan p = I.p;
             bool seen = false;
-            for (auto &e : zc_saved_) seen = seen || e.first == p;
+            for (auto &e : zc_saved_) seen = seen || e.p == p;
             if (!seen) {
-                zc_saved_.push_back({p, {p->p3d_zc, p->bp3d_zc}});
+                zc_saved_.push_back({p, p->p3d_zc, p->bp3d_zc, p->blur_zc});
+                p->blur_zc = std::min(kMaskBlurZc, p->nz);
                 p->p3d_zc = std::min(p->p3d_zc, 16);
                 p->bp3d_zc = std::min(p->bp3d_zc, 8);
             }
             rc = launch_p3d_flags(p, U8(L_.act) + I.soff, U8(L_.pflags) + L_.pfo[i], s_);
             if (!rc) rc = launch_bp3d_flags(p, U8(L_.lab) + I.voff, U8(L_.bflags) + L_.bfo[i], s_);
+            if (!rc) rc = launch_blur_flags(p, U8(L_.lab) + I.voff, blur_own(i), blur_reach(i), s_);
             if (rc) return rc;
             const long long onp = count_on(L_.pflags + L_.pfo[i], p3d_flag_count(p));
             const long long onb = count_on(L_.bflags + L_.bfo[i], bp3d_flag_count(p));

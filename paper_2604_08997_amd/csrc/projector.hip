@@ -138,18 +138,6 @@ __global__ void __launch_bounds__(256) project_kernel(const T *__restrict__ vol,
 // by the 16 lanes of one LDS pass land in different banks.  A voxel then reads
 // four slices of each tap bin per 128-bit load.  Bins outside the detector are
 // staged as zeros, so the inner loop has no bounds tests.
-// Tile coordinates (x, y, z) of this workgroup, spread over the XCDs.  Workgroups reach the eight
-// XCDs in turn by linear id, so with x taken straight from blockIdx a grid whose x extent is a
-// multiple of eight would pin each x column of tiles to one XCD; a masked launch, whose live tiles
-// cluster in a few columns, would then run on a few XCDs.  x is rotated by the index of the run of
-// RY consecutive y tiles (RY = 0: the whole y extent, i.e. by z alone), so every XCD gets every
-// column while a run of RY y-neighbours stays on one XCD and shares its L2.  A bijection of the grid.
-template <int RY>
-__device__ __forceinline__ int3 xcd_tile() {
-    const unsigned ry = RY > 0 ? RY : gridDim.y;
-    const unsigned q = blockIdx.y / ry + ((gridDim.y + ry - 1) / ry) * blockIdx.z;
-    return make_int3((int)((blockIdx.x + q) % gridDim.x), (int)blockIdx.y, (int)blockIdx.z);
-}
 // runs of y tiles kept together: view batches for the projector, rows for the backprojector
 constexpr int kXcdRunP = 1, kXcdRunBp = 0;
 

@@ -105,10 +105,31 @@ namespace sipo {
 
 int check_plan(sipo_plan p);
 
+// Tile coordinates (x, y, z) of this workgroup, spread over the XCDs.  Workgroups reach the eight
+// XCDs in turn by linear id, so with x taken straight from blockIdx a grid whose x extent is a
+// multiple of eight would pin each x column of tiles to one XCD; a masked launch, whose live tiles
+// cluster in a few columns, would then run on a few XCDs.  x is rotated by the index of the run of
+// RY consecutive y tiles (RY = 0: the whole y extent, i.e. by z alone), so every XCD gets every
+// column while a run of RY y-neighbours stays on one XCD and shares its L2.  A bijection of the grid.
+template <int RY>
+__device__ __forceinline__ int3 xcd_tile() {
+    const unsigned ry = RY > 0 ? RY : gridDim.y;
+    const unsigned q = blockIdx.y / ry + ((gridDim.y + ry - 1) / ry) * blockIdx.z;
+    return make_int3((int)((blockIdx.x + q) % gridDim.x), (int)blockIdx.y, (int)blockIdx.z);
+}
+
 // Launchers (return sipo_status).
 int launch_backproject(sipo_plan p, const void *sino, void *vol, int accumulate, hipStream_t s);
 int launch_project(sipo_plan p, const void *vol, void *sino, int accumulate, hipStream_t s);
-int launch_blur(sipo_plan p, const void *in, void *out, hipStream_t s);
+// tile_on: optional flags per blur tile (see blur_tile_count); a tile that is off is skipped, or,
+// with zero_off, has its output set to zero without reading the input.
+int launch_blur(sipo_plan p, const void *in, void *out, hipStream_t s, const uint8_t *tile_on = nullptr,
+                int zero_off = 0);
+// Blur tiles of the plan's current tuning (0 without a PSF), and their flags from a label volume
+// [z][y][x]: own = the tile holds a labelled voxel, reach = a labelled voxel lies within the PSF
+// radius of the tile (elsewhere the blur of a field supported on labelled voxels is zero).
+size_t blur_tile_count(sipo_plan p, int zc = 0);   // zc > 0: at zc slices per tile
+int launch_blur_flags(sipo_plan p, const uint8_t *labels, uint8_t *own, uint8_t *reach, hipStream_t s);
 // Internal 3D layouts (fast3d plans): sinograms [view][bin][z] ("sino_t") and, as
 // the projector's input, volumes [y][x][z] ("vol_t"); both keep z contiguous.
 // Volumes produced by the backprojector stay in the ABI layout [z][y][x].
