@@ -264,15 +264,27 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
 
 // Sum of the view splits' partial volumes on switched-on tiles, zero elsewhere (fixed order).
 template <typename T>
-__global__ void k_bp3d_reduce(const T *__restrict__ part, T *__restrict__ vol, const uint8_t *__restrict__ tile_on,
-                              int n, int nz, int zc, int gx, int gy, int nsplit, long long total) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
-        const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
-        T v = (T)0;
-        if (!tile_on || tile_on[((size_t)(z / zc) * gy + y / kBpTY) * gx + x / kBpTX])
-            for (int k = 0; k < nsplit; ++k) v += part[(size_t)k * total + i];
-        vol[i] = v;
-    }
+__global__ void __launch_bounds__(256) k_bp3d_reduce(const T *__restrict__ part, T *__restrict__ vol,
+                                                     const uint8_t *__restrict__ tile_on, int n, int nz, int zc,
+                                                     int nsplit, long long total) {
+    // one workgroup per backprojector tile (grid = the backprojector's tiles): a thread owns voxel x of
+    // rows y and y + 8 in every slice of the tile; partial sums are read on switched-on tiles only
+    const int3 tile = xcd_tile<0>();
+    const bool on = !tile_on || tile_on[((size_t)tile.z * gridDim.y + tile.y) * gridDim.x + tile.x];
+    const int x = tile.x * kBpTX + (threadIdx.x & 31), y = tile.y * kBpTY + (threadIdx.x >> 5);
+    const int z0 = tile.z * zc, z1 = min(nz, z0 + zc);
+    if (x >= n) return;
+    for (int z = z0; z < z1; ++z)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int yy = y + 8 * h;
+            if (yy >= n) continue;
+            const size_t i = ((size_t)z * n + yy) * n + x;
+            T v = (T)0;
+            if (on)
+                for (int k = 0; k < nsplit; ++k) v += part[(size_t)k * total + i];
+            vol[i] = v;
+        }
 }
 
 // ------------------------------------------------------------------- 3D P
@@ -953,8 +965,8 @@ static void bp3d_zc(sipo_plan p, const void *sino_t, void *vol, int accumulate, 
                        (T)p->atten, accumulate, on, ns, (long long)p->vol_elems());
     if (ns > 1) {
         const long long total = (long long)p->vol_elems();
-        hipLaunchKernelGGL((k_bp3d_reduce<T>), dim3((unsigned)std::min<long long>((total + 255) / 256, 16384)), dim3(256),
-                           0, s, (const T *)sp.partial, (T *)vol, on, p->n, p->nz, ZC, gx, gy, ns, total);
+        hipLaunchKernelGGL((k_bp3d_reduce<T>), dim3(gx, gy, gz), dim3(256), 0, s, (const T *)sp.partial, (T *)vol, on,
+                           p->n, p->nz, ZC, ns, total);
     }
 }
 
