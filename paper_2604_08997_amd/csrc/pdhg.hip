@@ -43,6 +43,7 @@
 // iterations can be captured once in a HIP graph and replayed.
 #include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cstring>
 #include <vector>
 
@@ -69,6 +70,7 @@ struct DevScal {
     double sum_l1, sum_Ul2;   // sums of the current lambda
     double init_l1, init_Ul2; // lambda sums handed to k_scalars_init
 };
+static_assert(offsetof(DevScal, rho) == offsetof(DevScal, w) + sizeof(double), "the fused primal step reads (w, rho)");
 
 struct LPConst {
     int u_free, v_free;
@@ -898,6 +900,7 @@ class Solver {
     bool b2d_ = false;
     bool mask_ = false;                     // 3D operators skip workgroups the LP does not read
     std::vector<SplitSpec> psp_, bsp_;      // per instance: splits of the masked 3D operators
+    std::vector<char> fused_;               // per instance: primal step fused into the masked projector
     // the plans' own slices per thread, which the masked operators change and the solver restores
     struct ZcSaved {
         sipo_plan p;
@@ -1019,7 +1022,8 @@ class Solver {
         std::vector<int> fvl(B_, 0), cvl(B_, 0);
         for (int i : list) {
             const bool all_s = live_s_.empty() || live_s_[i].empty(), all_v = live_v_.empty() || live_v_[i].empty();
-            for (int k = 0; k < cs[i]; ++k)
+            const bool fused = !fused_.empty() && fused_[i];   // its primal step runs in the projector
+            for (int k = 0; k < cs[i] && !fused; ++k)
                 if (all_s || live_s_[i][k]) ssl.push_back(ss[fs[i] + k]);
             fvl[i] = (int)svl.size();
             for (int k = 0; k < cv[i]; ++k)
@@ -1126,7 +1130,9 @@ class Solver {
         }
         return SIPO_OK;
     }
-    int adjoint(size_t zf, size_t outf) {   // out = P K z on the active instances
+    // out = P K z on the active instances; with fuse_primal, instances whose primal step is fused
+    // into the projector take that step instead (y, t.y updated; out not written for them)
+    int adjoint(size_t zf, size_t outf, bool fuse_primal = false) {
         if (b2d_) {
             // rays marching along x read an [x][y] copy (tmp is free: no blur in this path)
             int rc = launch_tr2d(I_dtype(), P<Geo2D>(L_.geo), P<int4>(L_.items_tr), n_items_tr_, F(zf), F(L_.tmp), s_);
@@ -1156,8 +1162,21 @@ class Solver {
             }
             if (!rc) {
                 const bool m = mask_ && I.t3;
+                PrimalFuse fz;
+                const bool fuse = fuse_primal && m && !fused_.empty() && fused_[i];
+                if constexpr (sizeof(T) == 4) {
+                    if (fuse) {
+                        fz.y = F(L_.y) + I.soff;
+                        fz.yt = F(L_.yt) + I.soff;
+                        fz.Tj = F(L_.Tj) + I.soff;
+                        fz.y0 = F(L_.y0) + I.soff;
+                        fz.act = U8(L_.act) + I.soff;
+                        fz.tau_fac = &scal()[i].tau_fac;
+                        fz.w_rho = &scal()[i].w;
+                    }
+                }
                 rc = launch_project_t(I.p, src, out, s_, m ? U8(L_.pflags) + L_.pfo[i] : nullptr,
-                                      m ? psp_[i] : SplitSpec());
+                                      m ? psp_[i] : SplitSpec(), fuse ? &fz : nullptr);
             }
             if (!rc) rc = mark(SIPO_PHASE_PROJECT);
             if (rc) return rc;
@@ -1343,6 +1362,7 @@ int Solver<T>::setup_common() {
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, probs_[0].plan->device);
         psp_.assign(B_, SplitSpec());
         bsp_.assign(B_, SplitSpec());
+        fused_.assign(B_, 0);
         auto count_on = [&](size_t flags_off, size_t count) -> long long {
             std::vector<uint8_t> h(count);
             if (count && hipMemcpyAsync(h.data(), U8(flags_off), count, hipMemcpyDeviceToHost, s_) != hipSuccess)
@@ -1377,6 +1397,8 @@ int Solver<T>::setup_common() {
             if (onp < 0 || onb < 0) return fail(SIPO_E_DEVICE, "pdhg setup: reading the skip flags failed");
             psp_[i] = SplitSpec{parts_for(onp, cus, kMaxSplitP), F(L_.ppart)};
             bsp_[i] = SplitSpec{parts_for(onb, 8LL * cus, kMaxSplitB), F(L_.bpart)};
+            // the primal step rides in the projector's output when its march is not split (FP32)
+            fused_[i] = sizeof(T) == 4 && p->p3d_dma && psp_[i].parts == 1;
         }
         mask_ = true;
     }
@@ -1544,7 +1566,7 @@ int Solver<T>::iteration(bool check) {
     const bool hal = o_.mode == SIPO_PDHG_RESTARTED;
     prof_on_ = o_.profile != 0;
     int rc = mark(-1);   // start of this iteration's timeline segment
-    if (!rc) rc = adjoint(L_.z, L_.q);
+    if (!rc) rc = adjoint(L_.z, L_.q, hal);
     if (rc) return rc;
     if (n_seg_sl_)
         hipLaunchKernelGGL((k_primal<T>), dim3(n_seg_sl_), dim3(kThreads), 0, s_, F(L_.y), F(L_.yt), (const T *)F(L_.q),

@@ -500,7 +500,7 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     const double2 *__restrict__ trig, const int *__restrict__ order, const int *__restrict__ partner,
     const int4 *__restrict__ batches, const int2 *__restrict__ ranges, const int2 *__restrict__ vial_rows,
     const float4 *__restrict__ zero16, double h, double inv_ds, float atten, const uint8_t *__restrict__ wg_on,
-    int nsplit, long long split_stride) {
+    int nsplit, long long split_stride, PrimalFuse fz) {
     static_assert(CM >= 1 && CM <= kDmaMaxCM, "chunk length");
     constexpr int Z4 = ZC / 4, RS = kPCR + 1, SLOTS = CM * Z4 * RS, PER = (SLOTS + 255) / 256;
     constexpr int NR = PAIR ? 2 : 1;
@@ -526,8 +526,8 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     const int a = order[bt.x + min(tk, bt.y - 1)];
     if (wg_on && !wg_on[((size_t)tile.y * gridDim.x + tile.x) * nzc + zb]) {
         // none of this workgroup's rays is active: their outputs are zero (before any barrier);
-        // with splits the reduction writes those zeros
-        if (active && nsplit == 1)
+        // with splits the reduction writes those zeros; with the fused primal step nothing changes
+        if (active && nsplit == 1 && !fz.y)
             for (int r = 0; r < NR; ++r) {
                 float4 *dst = (float4 *)(r == 0 ? sino_t + ((size_t)a * nb + b) * nz + z0
                                                 : sino_t + ((size_t)partner[a] * nb + (nb - 1 - b)) * nz + z0);
@@ -681,6 +681,43 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
         step(bufC, bufB, k + 2);
     }
     if (!active) return;
+    if (fz.y) {
+        // fused primal step on this lane's rays (same arithmetic as the solver's primal kernel)
+        const float tf = (float)*fz.tau_fac, w = (float)fz.w_rho[0], rho = (float)fz.w_rho[1];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const size_t base = r == 0 ? ((size_t)a * nb + b) * nz + z0
+                                       : ((size_t)partner[a] * nb + (nb - 1 - b)) * nz + z0;
+#pragma unroll
+            for (int z4 = 0; z4 < Z4; ++z4) {
+                const size_t i = base + 4 * z4;
+                if (z0 + 4 * z4 >= nz) continue;
+                const uint32_t m = *(const uint32_t *)(fz.act + i);
+                if (!m) continue;
+                const float4 yo = *(const float4 *)(fz.y + i), tj = *(const float4 *)(fz.Tj + i),
+                             a0 = *(const float4 *)(fz.y0 + i);
+                const float yv[4] = {yo.x, yo.y, yo.z, yo.w}, tv[4] = {tj.x, tj.y, tj.z, tj.w},
+                            av[4] = {a0.x, a0.y, a0.z, a0.w};
+                float t4[4], y4[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    float v = yv[k] - tf * tv[k] * acc[r][4 * z4 + k];
+                    v = v > 0.f ? v : 0.f;
+                    t4[k] = v;
+                    y4[k] = w * ((1.f + rho) * v - rho * yv[k]) + (1.f - w) * av[k];
+                }
+                if (((m - 0x01010101u) & ~m & 0x80808080u) == 0) {   // all four active
+                    *(float4 *)(fz.yt + i) = make_float4(t4[0], t4[1], t4[2], t4[3]);
+                    *(float4 *)(fz.y + i) = make_float4(y4[0], y4[1], y4[2], y4[3]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if ((m >> (8 * k)) & 0xFFu) { fz.yt[i + k] = t4[k]; fz.y[i + k] = y4[k]; }
+                }
+            }
+        }
+        return;
+    }
     float *out = sino_t + (size_t)split * split_stride;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -1026,14 +1063,14 @@ __global__ void k_p3d_reduce(const float4 *__restrict__ part, float4 *__restrict
 
 template <int ZC, int NC, bool PAIR, bool SKIP, int CM>
 static void fp3d_dma_launch(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
-                            const SplitSpec &sp) {
+                            const SplitSpec &sp, const PrimalFuse &fz) {
     const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
     const int ns = sp.parts > 1 ? sp.parts : 1;
     const dim3 grid((p->n_bins + kPB - 1) / kPB, p->n_batches, ((p->nz + ZC - 1) / ZC) * ns);
     hipLaunchKernelGGL((project3d_dma_kernel<ZC, NC, PAIR, SKIP, CM>), grid, dim3(256), 0, s, (const float *)vol_t,
                        (float *)(ns > 1 ? sp.partial : sino_t), p->n, p->nz, p->n_bins, p->d_trig, p->d_angle_order,
                        p->d_partner, p->d_batches, p->d_ranges, p->d_vial_rows, (const float4 *)p->d_zero, h, inv_ds,
-                       (float)p->atten, on, ns, (long long)p->sino_elems());
+                       (float)p->atten, on, ns, (long long)p->sino_elems(), fz);
     if (ns > 1) {
         const long long total4 = (long long)p->sino_elems() / 4;
         hipLaunchKernelGGL(k_p3d_reduce, dim3((unsigned)std::min<long long>((total4 + 255) / 256, 16384)), dim3(256), 0,
@@ -1044,38 +1081,42 @@ static void fp3d_dma_launch(sipo_plan p, const void *vol_t, void *sino_t, hipStr
 
 template <int ZC, int NC, bool PAIR, bool SKIP>
 static void fp3d_dma_go(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
-                        const SplitSpec &sp) {
+                        const SplitSpec &sp, const PrimalFuse &fz) {
     // 64 slices stage one step per chunk only: three two-step buffers would not fit in LDS
-    if (ZC > 32 || p->p3d_cm == 1) fp3d_dma_launch<ZC, NC, PAIR, SKIP, 1>(p, vol_t, sino_t, s, on, sp);
-    else fp3d_dma_launch<ZC, NC, PAIR, SKIP, (ZC > 32 ? 1 : kDmaMaxCM)>(p, vol_t, sino_t, s, on, sp);
+    if (ZC > 32 || p->p3d_cm == 1) fp3d_dma_launch<ZC, NC, PAIR, SKIP, 1>(p, vol_t, sino_t, s, on, sp, fz);
+    else fp3d_dma_launch<ZC, NC, PAIR, SKIP, (ZC > 32 ? 1 : kDmaMaxCM)>(p, vol_t, sino_t, s, on, sp, fz);
 }
 
 template <int ZC, int NC>
 static void fp3d_dma_nc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
-                        const SplitSpec &sp) {
+                        const SplitSpec &sp, const PrimalFuse &fz) {
     if (p->p3d_pair) {
-        if (p->p3d_skip) fp3d_dma_go<ZC, NC, true, true>(p, vol_t, sino_t, s, on, sp);
-        else fp3d_dma_go<ZC, NC, true, false>(p, vol_t, sino_t, s, on, sp);
+        if (p->p3d_skip) fp3d_dma_go<ZC, NC, true, true>(p, vol_t, sino_t, s, on, sp, fz);
+        else fp3d_dma_go<ZC, NC, true, false>(p, vol_t, sino_t, s, on, sp, fz);
     } else {
-        if (p->p3d_skip) fp3d_dma_go<ZC, NC, false, true>(p, vol_t, sino_t, s, on, sp);
-        else fp3d_dma_go<ZC, NC, false, false>(p, vol_t, sino_t, s, on, sp);
+        if (p->p3d_skip) fp3d_dma_go<ZC, NC, false, true>(p, vol_t, sino_t, s, on, sp, fz);
+        else fp3d_dma_go<ZC, NC, false, false>(p, vol_t, sino_t, s, on, sp, fz);
     }
 }
 
 template <typename T, int ZC>
 static int fp3d_zc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
-                   const SplitSpec &sp) {
+                   const SplitSpec &sp, const PrimalFuse *fuse) {
     if constexpr (sizeof(T) == 4 && ZC >= 8) {
         if (p->p3d_dma) {
+            if (fuse && sp.parts > 1)
+                return fail(SIPO_E_UNSUPPORTED, "3D projector: the fused primal step needs an unsplit march");
+            const PrimalFuse fz = fuse ? *fuse : PrimalFuse();
             switch (p->p3d_nc) {
-                case 3: fp3d_dma_nc<ZC, 3>(p, vol_t, sino_t, s, on, sp); break;
-                case 4: fp3d_dma_nc<ZC, 4>(p, vol_t, sino_t, s, on, sp); break;
-                case 6: fp3d_dma_nc<ZC, 6>(p, vol_t, sino_t, s, on, sp); break;
+                case 3: fp3d_dma_nc<ZC, 3>(p, vol_t, sino_t, s, on, sp, fz); break;
+                case 4: fp3d_dma_nc<ZC, 4>(p, vol_t, sino_t, s, on, sp, fz); break;
+                case 6: fp3d_dma_nc<ZC, 6>(p, vol_t, sino_t, s, on, sp, fz); break;
                 default: return fail(SIPO_E_UNSUPPORTED, "3D projector: unsupported candidate count");
             }
             return SIPO_OK;
         }
     }
+    if (fuse) return fail(SIPO_E_UNSUPPORTED, "3D projector: the fused primal step needs the asynchronous variant");
     if constexpr (ZC > 32) {
         return fail(SIPO_E_UNSUPPORTED, "3D projector: %d slices per thread need the asynchronous variant", ZC);
     } else {
@@ -1091,17 +1132,17 @@ static int fp3d_zc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, 
 
 template <typename T>
 static int fp3d(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
-                const SplitSpec &sp) {
+                const SplitSpec &sp, const PrimalFuse *fuse) {
     int rc;
     switch (p->p3d_zc) {
-        case 8: rc = fp3d_zc<T, 8>(p, vol_t, sino_t, s, on, sp); break;
-        case 16: rc = fp3d_zc<T, 16>(p, vol_t, sino_t, s, on, sp); break;
+        case 8: rc = fp3d_zc<T, 8>(p, vol_t, sino_t, s, on, sp, fuse); break;
+        case 16: rc = fp3d_zc<T, 16>(p, vol_t, sino_t, s, on, sp, fuse); break;
         case 32:
-            if constexpr (sizeof(T) == 4) rc = fp3d_zc<T, 32>(p, vol_t, sino_t, s, on, sp);
+            if constexpr (sizeof(T) == 4) rc = fp3d_zc<T, 32>(p, vol_t, sino_t, s, on, sp, fuse);
             else rc = fail(SIPO_E_UNSUPPORTED, "3D projector: 32 slices per thread in FP64");
             break;
         case 64:
-            if constexpr (sizeof(T) == 4) rc = fp3d_zc<T, 64>(p, vol_t, sino_t, s, on, sp);
+            if constexpr (sizeof(T) == 4) rc = fp3d_zc<T, 64>(p, vol_t, sino_t, s, on, sp, fuse);
             else rc = fail(SIPO_E_UNSUPPORTED, "3D projector: 64 slices per thread in FP64");
             break;
         default: return fail(SIPO_E_UNSUPPORTED, "3D projector: %d slices per thread", p->p3d_zc);
@@ -1151,12 +1192,15 @@ int launch_backproject_t(sipo_plan p, const void *sino_t, void *vol, int accumul
 }
 
 int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *wg_on,
-                     const SplitSpec &sp) {
+                     const SplitSpec &sp, const PrimalFuse *fuse) {
+    if (fuse && (!p->fast3d() || p->dtype != SIPO_F32 || p->p2d_ok))
+        return fail(SIPO_E_UNSUPPORTED, "the fused primal step needs an FP32 3D plan");
     if (p->p2d_ok) return fp2d_plan(p, vol_t, sino_t, 0, s);
     if (!p->fast3d())
         return p->dtype == SIPO_F64 ? fp_slices<double>(p, vol_t, sino_t, 0, s)
                                     : fp_slices<float>(p, vol_t, sino_t, 0, s);
-    return p->dtype == SIPO_F64 ? fp3d<double>(p, vol_t, sino_t, s, wg_on, sp) : fp3d<float>(p, vol_t, sino_t, s, wg_on, sp);
+    return p->dtype == SIPO_F64 ? fp3d<double>(p, vol_t, sino_t, s, wg_on, sp, fuse)
+                                : fp3d<float>(p, vol_t, sino_t, s, wg_on, sp, fuse);
 }
 
 // ------------------------------------------------------- skip flags (LP solves)

@@ -144,8 +144,19 @@ struct SplitSpec {
 };
 int launch_backproject_t(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s,
                          const uint8_t *tile_on = nullptr, const SplitSpec &sp = SplitSpec());
+// Primal step of an LP solve fused into the asynchronous projector's output (FP32, no splits):
+// instead of storing q = P x, a ray's lane applies t.y = max(0, y - tau_fac T_j q) and
+// y <- w ((1 + rho) t.y - rho y) + (1 - w) y0 on its active elements and stores y and t.y; q is
+// not stored, and workgroups that are off store nothing.  Arrays are the instance's fields in the
+// projector's output layout; the scalars are read from device memory when the kernel runs.
+struct PrimalFuse {
+    float *y = nullptr, *yt = nullptr;
+    const float *Tj = nullptr, *y0 = nullptr;
+    const uint8_t *act = nullptr;
+    const double *tau_fac = nullptr, *w_rho = nullptr;   // w_rho[0] = w, w_rho[1] = rho
+};
 int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *wg_on = nullptr,
-                     const SplitSpec &sp = SplitSpec());
+                     const SplitSpec &sp = SplitSpec(), const PrimalFuse *fuse = nullptr);
 // projector workgroups / backprojector tiles of a fast3d plan (else 0) at zc slices per thread
 // (zc <= 0: the plan's current tuning)
 size_t p3d_flag_count(sipo_plan p, int zc = 0);
