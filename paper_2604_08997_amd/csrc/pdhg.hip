@@ -1355,7 +1355,7 @@ int Solver<T>::setup_common() {
         // Few workgroups stay on, each with a long serial walk.  The masked projector runs with at most 16
         // slices per thread and the masked backprojector with at most 8 (finer chunks give more
         // workgroups; at 256^3 x 360 these are the fastest of the 4 / 8 / 16 / 32 choices), the
-        // backprojector's view walk is split so that the switched-on tiles give about eight workgroups
+        // backprojector's view walk is split so that the switched-on tiles give about four workgroups
         // per CU, and the projector's march is split only when very few of its workgroups stay on.  The
         // plans' own settings are restored when the solver ends.
         int cus = 256;
@@ -1396,7 +1396,7 @@ int Solver<T>::setup_common() {
             const long long onb = count_on(L_.bflags + L_.bfo[i], bp3d_flag_count(p));
             if (onp < 0 || onb < 0) return fail(SIPO_E_DEVICE, "pdhg setup: reading the skip flags failed");
             psp_[i] = SplitSpec{parts_for(onp, cus, kMaxSplitP), F(L_.ppart)};
-            bsp_[i] = SplitSpec{parts_for(onb, 8LL * cus, kMaxSplitB), F(L_.bpart)};
+            bsp_[i] = SplitSpec{parts_for(onb, 4LL * cus, kMaxSplitB), F(L_.bpart)};
             // the primal step rides in the projector's output when its march is not split (FP32)
             fused_[i] = sizeof(T) == 4 && p->p3d_dma && psp_[i].parts == 1;
         }
