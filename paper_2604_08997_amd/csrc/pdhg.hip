@@ -713,7 +713,7 @@ struct Layout {
     int max_seg_s = 0, max_seg_v = 0, max_items_bp = 0, max_items_fp = 0, max_items_tr = 0;
     size_t eb = 4;
     bool lohi = false;                          // per-voxel bounds packed (some instance has arrays)
-    size_t vol_t_elems = 0;                     // internal-layout volume scratch (largest 3D instance)
+    size_t vol_t_elems = 0;                     // largest 3D instance (the projector's input is per instance)
     std::vector<size_t> pfo, bfo;               // byte offsets of each 3D instance's skip flags
     std::vector<size_t> kfo;                    // and of its two blur tile flag arrays (own, reach)
     size_t kf_bytes = 0, kflags = 0;
@@ -775,7 +775,7 @@ static Layout make_layout(const sipo_problem *probs, int B) {
             L.pf_bytes += align_up(p3d_flag_count(p, 8));
             L.bf_bytes += align_up(bp3d_flag_count(p, 4));
             L.kfo[i] = L.kf_bytes;
-            L.kf_bytes += 2 * align_up(blur_tile_count(p, kMaskBlurZc));
+            L.kf_bytes += 2 * align_up(blur_tile_count(p, kMaskBlurZc)) + align_up(vol_t_tile_count(p));
             L.part_s = std::max(L.part_s, (size_t)ns);
             L.part_v = std::max(L.part_v, (size_t)nv);
         }
@@ -802,7 +802,9 @@ static Layout make_layout(const sipo_problem *probs, int B) {
     L.lab = take((size_t)L.NV);
     L.lo = L.lohi ? take(vb) : 0;
     L.hi = L.lohi ? take(vb) : 0;
-    L.vol_t = take(L.vol_t_elems * L.eb);
+    // the projector's z-contiguous input, one per instance: in masked solves the parts of it that
+    // stay zero are written once (setup) and then skipped
+    L.vol_t = take(vb);
     L.pflags = take(L.pf_bytes);
     L.bflags = take(L.bf_bytes);
     L.kflags = take(L.kf_bytes);
@@ -939,6 +941,8 @@ class Solver {
     // within the PSF radius of one
     uint8_t *blur_own(int i) const { return U8(L_.kflags) + L_.kfo[i]; }
     uint8_t *blur_reach(int i) const { return U8(L_.kflags) + L_.kfo[i] + align_up(blur_tile_count(in_[i].p, kMaskBlurZc)); }
+    // transpose tiles of the projector's input that hold a voxel of a reach tile
+    uint8_t *vol_t_on(int i) const { return blur_reach(i) + align_up(blur_tile_count(in_[i].p, kMaskBlurZc)); }
     const Seg *segVL() const { return P<Seg>(L_.segVL); }
     double *partials() const { return P<double>(L_.partials); }
     const InstC *insts() const { return P<InstC>(L_.insts); }
@@ -1156,9 +1160,13 @@ class Solver {
                 src = tmp;
             }
             if (!rc && I.t3) {
-                rc = launch_vol_to_t(I.p, src, F(L_.vol_t), s_);
+                // masked: only tiles that can hold a nonzero of K z (with a PSF; without one, z's own
+                // support is not tracked per tile and the whole volume moves)
+                const bool mt = mask_ && I.p->has_psf;
+                T *vt = F(L_.vol_t) + I.voff;
+                rc = launch_vol_to_t(I.p, src, vt, s_, mt ? vol_t_on(i) : nullptr);
                 if (!rc) rc = mark(SIPO_PHASE_TRANSPOSE);
-                src = F(L_.vol_t);
+                src = vt;
             }
             if (!rc) {
                 const bool m = mask_ && I.t3;
@@ -1391,6 +1399,7 @@ int Solver<T>::setup_common() {
             rc = launch_p3d_flags(p, U8(L_.act) + I.soff, U8(L_.pflags) + L_.pfo[i], s_);
             if (!rc) rc = launch_bp3d_flags(p, U8(L_.lab) + I.voff, U8(L_.bflags) + L_.bfo[i], s_);
             if (!rc) rc = launch_blur_flags(p, U8(L_.lab) + I.voff, blur_own(i), blur_reach(i), s_);
+            if (!rc) rc = launch_vol_t_flags(p, blur_reach(i), vol_t_on(i), s_);
             if (rc) return rc;
             const long long onp = count_on(L_.pflags + L_.pfo[i], p3d_flag_count(p));
             const long long onb = count_on(L_.bflags + L_.bfo[i], bp3d_flag_count(p));
@@ -1401,6 +1410,7 @@ int Solver<T>::setup_common() {
             fused_[i] = sizeof(T) == 4 && p->p3d_dma && psp_[i].parts == 1;
         }
         mask_ = true;
+        fill_vol(L_.vol_t);   // zero where the masked transposes never write
     }
     rc = live_tables();
     if (rc) return rc;

@@ -737,8 +737,11 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
 // Batched transpose: [B][R][C] -> [B][C][R] (out = in^T, or out += in^T).
 template <typename T>
 __global__ void __launch_bounds__(256) transpose_kernel(const T *__restrict__ in, T *__restrict__ out, int rows,
-                                                        int cols, int accumulate) {
+                                                        int cols, int accumulate,
+                                                        const uint8_t *__restrict__ tile_on) {
     __shared__ T tile[64][65];
+    // tile_on (one byte per 64 x 64 tile of one plane): tiles that are off are left as they are
+    if (tile_on && !tile_on[(size_t)blockIdx.y * gridDim.x + blockIdx.x]) return;
     const size_t plane = (size_t)rows * cols;
     const T *src = in + (size_t)blockIdx.z * plane;
     T *dst = out + (size_t)blockIdx.z * plane;
@@ -759,15 +762,17 @@ __global__ void __launch_bounds__(256) transpose_kernel(const T *__restrict__ in
 }
 
 template <typename T>
-static void transpose(const void *in, void *out, int batch, int rows, int cols, int accumulate, hipStream_t s) {
+static void transpose(const void *in, void *out, int batch, int rows, int cols, int accumulate, hipStream_t s,
+                      const uint8_t *tile_on = nullptr) {
     const dim3 grid((cols + 63) / 64, (rows + 63) / 64, batch);
-    hipLaunchKernelGGL((transpose_kernel<T>), grid, dim3(256), 0, s, (const T *)in, (T *)out, rows, cols, accumulate);
+    hipLaunchKernelGGL((transpose_kernel<T>), grid, dim3(256), 0, s, (const T *)in, (T *)out, rows, cols, accumulate,
+                       tile_on);
 }
 
 static int transpose_any(sipo_plan p, const void *in, void *out, int batch, int rows, int cols, int accumulate,
-                         hipStream_t s) {
-    if (p->dtype == SIPO_F64) transpose<double>(in, out, batch, rows, cols, accumulate, s);
-    else transpose<float>(in, out, batch, rows, cols, accumulate, s);
+                         hipStream_t s, const uint8_t *tile_on = nullptr) {
+    if (p->dtype == SIPO_F64) transpose<double>(in, out, batch, rows, cols, accumulate, s, tile_on);
+    else transpose<float>(in, out, batch, rows, cols, accumulate, s, tile_on);
     SIPO_LAUNCHED("transpose_kernel");
     return SIPO_OK;
 }
@@ -1152,8 +1157,8 @@ static int fp3d(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, con
     return SIPO_OK;
 }
 
-int launch_vol_to_t(sipo_plan p, const void *vol, void *vol_t, hipStream_t s) {
-    return transpose_any(p, vol, vol_t, 1, p->nz, p->n * p->n, 0, s);
+int launch_vol_to_t(sipo_plan p, const void *vol, void *vol_t, hipStream_t s, const uint8_t *tile_on) {
+    return transpose_any(p, vol, vol_t, 1, p->nz, p->n * p->n, 0, s, tile_on);
 }
 
 int launch_sino_to_t(sipo_plan p, const void *sino, void *sino_t, hipStream_t s) {
