@@ -187,18 +187,18 @@ int launch_blur_flags(sipo_plan p, const uint8_t *labels, uint8_t *own, uint8_t 
 }
 
 size_t vol_t_tile_count(sipo_plan p) {
-    return (size_t)(((long long)p->n * p->n + 63) / 64) * ((p->nz + 63) / 64);
+    return (size_t)(((long long)p->n * p->n + kTrCols - 1) / kTrCols) * ((p->nz + kTrRows - 1) / kTrRows);
 }
 
-// tflags[t] = 1 when transpose tile t (64 slices x 64 consecutive (y n + x) columns) holds a voxel
-// of a blur tile that is on in `reach`
+// tflags[t] = 1 when transpose tile t (kTrRows slices x kTrCols consecutive (y n + x)
+// columns) holds a voxel of a blur tile that is on in `reach`
 __global__ void k_vol_t_flags(const uint8_t *__restrict__ reach, uint8_t *__restrict__ tflags, int n, int nz, int zc,
                               int gx, int gy, int tcols, int trows) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= tcols * trows) return;
     const int cb = t % tcols, rb = t / tcols;
-    const long long c0 = 64LL * cb, c1 = min(c0 + 63, (long long)n * n - 1);
-    const int z0 = 64 * rb, z1 = min(z0 + 63, nz - 1);
+    const long long c0 = (long long)kTrCols * cb, c1 = min(c0 + kTrCols - 1, (long long)n * n - 1);
+    const int z0 = kTrRows * rb, z1 = min(z0 + kTrRows - 1, nz - 1);
     uint8_t on = 0;
     for (int y = (int)(c0 / n); y <= (int)(c1 / n) && !on; ++y) {
         const int xa = (int)max(c0 - (long long)y * n, 0LL), xb = (int)min(c1 - (long long)y * n, (long long)n - 1);
@@ -212,7 +212,8 @@ int launch_vol_t_flags(sipo_plan p, const uint8_t *reach, uint8_t *tflags, hipSt
     if (!blur_tile_count(p)) return SIPO_OK;
     const int zc = blur_zchunk(p);
     const int gx = (p->n + kBTX - 1) / kBTX, gy = (p->n + kBTY - 1) / kBTY;
-    const int tcols = (int)(((long long)p->n * p->n + 63) / 64), trows = (p->nz + 63) / 64;
+    const int tcols = (int)(((long long)p->n * p->n + kTrCols - 1) / kTrCols);
+    const int trows = (p->nz + kTrRows - 1) / kTrRows;
     hipLaunchKernelGGL(k_vol_t_flags, dim3((tcols * trows + 255) / 256), dim3(256), 0, s, reach, tflags, p->n, p->nz, zc,
                        gx, gy, tcols, trows);
     SIPO_LAUNCHED("k_vol_t_flags");

@@ -737,11 +737,8 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
 // Batched transpose: [B][R][C] -> [B][C][R] (out = in^T, or out += in^T).
 template <typename T>
 __global__ void __launch_bounds__(256) transpose_kernel(const T *__restrict__ in, T *__restrict__ out, int rows,
-                                                        int cols, int accumulate,
-                                                        const uint8_t *__restrict__ tile_on) {
+                                                        int cols, int accumulate) {
     __shared__ T tile[64][65];
-    // tile_on (one byte per 64 x 64 tile of one plane): tiles that are off are left as they are
-    if (tile_on && !tile_on[(size_t)blockIdx.y * gridDim.x + blockIdx.x]) return;
     const size_t plane = (size_t)rows * cols;
     const T *src = in + (size_t)blockIdx.z * plane;
     T *dst = out + (size_t)blockIdx.z * plane;
@@ -761,12 +758,43 @@ __global__ void __launch_bounds__(256) transpose_kernel(const T *__restrict__ in
     }
 }
 
+// Flagged variant for masked solves, in tiles of kTrRows rows x kTrCols columns (one plane): tiles
+// that are off are not written.  Reads are 1 KB rows; a column's kTrRows values are written as one
+// 64-byte run.
+static_assert(kTrCols == 256 && 256 % kTrRows == 0, "one column per thread when reading a tile row");
+
+template <typename T>
+__global__ void __launch_bounds__(256) transpose_flagged_kernel(const T *__restrict__ in, T *__restrict__ out,
+                                                                int rows, int cols,
+                                                                const uint8_t *__restrict__ tile_on) {
+    __shared__ T tile[kTrRows][kTrCols + 1];
+    if (!tile_on[(size_t)blockIdx.y * gridDim.x + blockIdx.x]) return;
+    const int c0 = blockIdx.x * kTrCols, r0 = blockIdx.y * kTrRows, t = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < kTrRows; ++i) {
+        const int r = r0 + i, c = c0 + t;
+        tile[i][t] = (r < rows && c < cols) ? in[(size_t)r * cols + c] : (T)0;
+    }
+    __syncthreads();
+    const int rr = t % kTrRows, r = r0 + rr;
+#pragma unroll
+    for (int k = 0; k < kTrCols / (256 / kTrRows); ++k) {
+        const int cc = t / kTrRows + (256 / kTrRows) * k, c = c0 + cc;
+        if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[rr][cc];
+    }
+}
+
 template <typename T>
 static void transpose(const void *in, void *out, int batch, int rows, int cols, int accumulate, hipStream_t s,
                       const uint8_t *tile_on = nullptr) {
+    if (tile_on) {   // one plane, overwrite
+        const dim3 grid((cols + kTrCols - 1) / kTrCols, (rows + kTrRows - 1) / kTrRows, 1);
+        hipLaunchKernelGGL((transpose_flagged_kernel<T>), grid, dim3(256), 0, s, (const T *)in, (T *)out, rows, cols,
+                           tile_on);
+        return;
+    }
     const dim3 grid((cols + 63) / 64, (rows + 63) / 64, batch);
-    hipLaunchKernelGGL((transpose_kernel<T>), grid, dim3(256), 0, s, (const T *)in, (T *)out, rows, cols, accumulate,
-                       tile_on);
+    hipLaunchKernelGGL((transpose_kernel<T>), grid, dim3(256), 0, s, (const T *)in, (T *)out, rows, cols, accumulate);
 }
 
 static int transpose_any(sipo_plan p, const void *in, void *out, int batch, int rows, int cols, int accumulate,

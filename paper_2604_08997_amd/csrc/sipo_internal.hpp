@@ -163,10 +163,11 @@ size_t p3d_flag_count(sipo_plan p, int zc = 0);
 size_t bp3d_flag_count(sipo_plan p, int zc = 0);
 int launch_p3d_flags(sipo_plan p, const uint8_t *act_t, uint8_t *flags, hipStream_t s);
 int launch_bp3d_flags(sipo_plan p, const uint8_t *labels, uint8_t *flags, hipStream_t s);
-// tile_on: optional flags per 64 (z) x 64 (y n + x) tile of the volume (see vol_t_tile_count);
+// tile_on: optional flags per 16 (z) x 256 (y n + x) tile of the volume (see vol_t_tile_count);
 // tiles that are off are not written
 int launch_vol_to_t(sipo_plan p, const void *vol, void *vol_t, hipStream_t s, const uint8_t *tile_on = nullptr);
 size_t vol_t_tile_count(sipo_plan p);
+constexpr int kTrRows = 16, kTrCols = 256;   // tile of the flagged transpose: slices x (y n + x) columns
 // Transpose tiles holding a voxel of a blur tile flagged in `reach` (flags of blur_tile_count
 // at the plan's current blur tuning): elsewhere the blurred field is zero.
 int launch_vol_t_flags(sipo_plan p, const uint8_t *reach, uint8_t *tflags, hipStream_t s);
