@@ -357,7 +357,7 @@ def main():
         return 2
     import torch
     import paper_2604_08997_amd as sipo
-    from sipo_inputs import ellipsoids_target, angles_uniform
+    from sipo_inputs import ellipsoids_target, angles_uniform, lattice_target
 
     big = args.workload == "vol512"
     n, na = (512, 720) if big else (256, 360)

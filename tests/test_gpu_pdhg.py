@@ -172,3 +172,31 @@ def test_restarted_3d_blur_matches_highs(case, dtype):
     assert abs(res["primal_obj"] - ref.objective) <= 1e-4 * (1 + abs(ref.objective))
     y, lu, ll = gpu_state(gl)
     assert okkt.residuals(op, y, res["u"], res["v"], lu, ll).rel <= 5 * tol
+
+
+def test_restarted_3d_ragged_tiles_fp32_paths_match_fp64_and_highs():
+    # 40^2 x 20 slices, 18 views: no tile of the masked operators, blurs or transposes divides the
+    # volume evenly (n^2 = 1600 columns, 20 slices), so every masked path meets a ragged edge.  The
+    # FP32 solve runs the asynchronous projector with the primal step in its output and the masked
+    # transpose; the FP64 solve runs none of them.  This LP converges slowly (about 1.2e-4 relative
+    # KKT after 20000 iterations), so both are stopped there and compared with each other, with
+    # HiGHS and with the oracle's residuals.
+    import paper_2604_08997_amd as sipo
+    from sipo_inputs import ellipsoids_target
+    n, na, nz, sigma = 40, 18, 20, (1.0, 1.0, 1.5)
+    f = ellipsoids_target(n, 31, count=2, nz=nz)
+    op = oracle_lp3d(n, na, f, olp.CASE1, sigma)
+    ref = olp.solve_highs(op)
+    assert ref.status == "optimal"
+    out = {}
+    for dtype in (torch.float64, torch.float32):
+        gl = gpu_lp3d(n, na, f, sipo.CASE1, dtype, sigma)
+        res = sipo.solve(gl, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=20000, tol=1e-4))
+        assert res["status_name"] in ("optimal", "iter_limit"), res["status_name"]
+        y, lu, ll = gpu_state(gl)
+        k = okkt.residuals(op, y, res["u"], res["v"], lu, ll)
+        assert k.rel <= 3e-4, (dtype, k)
+        assert abs(res["primal_obj"] - ref.objective) <= 3e-4 * (1 + abs(ref.objective)), (dtype, res["primal_obj"])
+        out[dtype] = res["primal_obj"]
+    # the optimal y need not be unique; the objective is
+    assert abs(out[torch.float32] - out[torch.float64]) <= 1e-5 * (1 + abs(out[torch.float64]))
