@@ -1125,7 +1125,11 @@ class Solver {
                 continue;
             }
             T *tmp = F(L_.tmp) + I.voff;
-            int rc = launch_backproject_t(I.p, y, tmp, 0, s_, on, sp);
+            // masked: switched-off tiles of tmp keep older (finite) values; the blur reads them only
+            // in halos of outputs the solve does not read (tmp is zeroed at setup)
+            SplitSpec spk = sp;
+            spk.keep_off = m;
+            int rc = launch_backproject_t(I.p, y, tmp, 0, s_, on, spk);
             if (!rc) rc = mark(SIPO_PHASE_BACKPROJECT);
             // masked: the dose is read on labelled voxels only, so tiles without one are skipped
             if (!rc) rc = launch_blur(I.p, tmp, out, s_, m ? blur_own(i) : nullptr, 0);
@@ -1411,6 +1415,7 @@ int Solver<T>::setup_common() {
         }
         mask_ = true;
         fill_vol(L_.vol_t);   // zero where the masked transposes never write
+        fill_vol(L_.tmp);     // finite where the masked backprojector leaves tiles as they are
     }
     rc = live_tables();
     if (rc) return rc;

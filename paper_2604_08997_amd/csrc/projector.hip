@@ -262,15 +262,17 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
     }
 }
 
-// Sum of the view splits' partial volumes on switched-on tiles, zero elsewhere (fixed order).
+// Sum of the view splits' partial volumes on switched-on tiles (fixed order); switched-off tiles get
+// zeros, or with keep_off are left as they are.
 template <typename T>
 __global__ void __launch_bounds__(256) k_bp3d_reduce(const T *__restrict__ part, T *__restrict__ vol,
                                                      const uint8_t *__restrict__ tile_on, int n, int nz, int zc,
-                                                     int nsplit, long long total) {
+                                                     int nsplit, long long total, int keep_off) {
     // one workgroup per backprojector tile (grid = the backprojector's tiles): a thread owns voxel x of
-    // rows y and y + 8 in every slice of the tile; partial sums are read on switched-on tiles only
+    // rows y and y + 8 in every slice of the tile
     const int3 tile = xcd_tile<0>();
     const bool on = !tile_on || tile_on[((size_t)tile.z * gridDim.y + tile.y) * gridDim.x + tile.x];
+    if (!on && keep_off) return;
     const int x = tile.x * kBpTX + (threadIdx.x & 31), y = tile.y * kBpTY + (threadIdx.x >> 5);
     const int z0 = tile.z * zc, z1 = min(nz, z0 + zc);
     if (x >= n) return;
@@ -1036,7 +1038,7 @@ static void bp3d_zc(sipo_plan p, const void *sino_t, void *vol, int accumulate, 
     if (ns > 1) {
         const long long total = (long long)p->vol_elems();
         hipLaunchKernelGGL((k_bp3d_reduce<T>), dim3(gx, gy, gz), dim3(256), 0, s, (const T *)sp.partial, (T *)vol, on,
-                           p->n, p->nz, ZC, ns, total);
+                           p->n, p->nz, ZC, ns, total, sp.keep_off ? 1 : 0);
     }
 }
 

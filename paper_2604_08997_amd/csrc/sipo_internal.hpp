@@ -137,10 +137,12 @@ int launch_blur_flags(sipo_plan p, const uint8_t *labels, uint8_t *own, uint8_t 
 // workgroups that are off write zeros.  SplitSpec: the 3D kernels' serial walk (march steps of
 // the asynchronous projector, views of the backprojector) split over `parts` workgroups whose
 // partial sums go to `partial` (parts x the output's elements) and are then added in a fixed
-// order; parts <= 1 = no split.
+// order; parts <= 1 = no split.  keep_off: the fixed-order sum leaves the output of switched-off
+// tiles as it is instead of writing zeros (for outputs that are only read near switched-on tiles).
 struct SplitSpec {
     int parts = 1;
     void *partial = nullptr;
+    bool keep_off = false;
 };
 int launch_backproject_t(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s,
                          const uint8_t *tile_on = nullptr, const SplitSpec &sp = SplitSpec());
