@@ -145,3 +145,33 @@ def test_mixed_3d_and_2d_batch_equals_individual_solves():
         assert (ra["status"], ra["iters"], ra["restarts"]) == (rb["status"], rb["iters"], rb["restarts"])
         for a, b in zip(sa, state(lp)):
             np.testing.assert_array_equal(a, b)
+
+
+def test_fp32_3d_instances_after_a_2d_one_equal_individual_solves():
+    # two blurred FP32 3D instances of different ragged sizes behind a 2D one, so every per-instance
+    # field of the masked 3D path (projector input, blur and transpose flags, live segments, the
+    # primal step fused into the projector) sits at a nonzero offset of the batch workspace
+    import paper_2604_08997_amd as sipo
+    opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=640, tol=1e-12, check_every=64)
+
+    def make():
+        out = [build(SMALL[0], torch.float32)[0]]
+        for n, na, nz, seed in ((24, 16, 12, 9), (40, 18, 20, 31)):
+            f3 = ellipsoids_target(n, seed, count=2, nz=nz)
+            p3 = sipo.Plan(n, list(angles_uniform(na)), nz=nz, sigma=(1.0, 1.0, 1.5), dtype=torch.float32,
+                           device=dev())
+            out.append(sipo.LP.build(p3, torch.as_tensor(f3, dtype=torch.float32, device=dev()), sipo.CASE1,
+                                     band_width=2.0, f_min=1.0))
+        return out
+
+    alone = []
+    for lp in make():
+        r = sipo.solve(lp, opts)
+        alone.append((r, state(lp)))
+    lps = make()
+    res = sipo.solve(lps, opts)
+    for (ra, sa), rb, lp in zip(alone, res, lps):
+        assert (ra["status"], ra["iters"], ra["restarts"]) == (rb["status"], rb["iters"], rb["restarts"])
+        assert ra["primal_obj"] == rb["primal_obj"]
+        for a, b in zip(sa, state(lp)):
+            np.testing.assert_array_equal(a, b)
