@@ -257,6 +257,9 @@ typedef struct {
                                   sum of their rows (0 = plain Pock-Chambolle, weight 1):
                                   tau_u = w_u / |band|, band rows sigma = 1/(R + w_u); the
                                   step bound holds for any positive weight               */
+    int32_t progress_every;    /* restarted mode: > 0 writes one line to stderr every this
+                                  many KKT checks, per unfinished instance (iterations,
+                                  relative residuals, restarts); 0 = silent (>= 0)        */
 } sipo_pdhg_options;
 
 /* Phases of one PDHG iteration, for sipo_pdhg_result.phase_ms. */

@@ -50,7 +50,7 @@ class PdhgOptions(C.Structure):
     _fields_ = [("mode", C.c_int32), ("max_iters", C.c_int32), ("check_every", C.c_int32), ("tol", C.c_double),
                 ("tau", C.c_double), ("sigma", C.c_double), ("power_iters", C.c_int32), ("eta", C.c_double),
                 ("infeas_tol", C.c_double), ("use_graph", C.c_int32), ("profile", C.c_int32),
-                ("scalar_weight", C.c_double)]
+                ("scalar_weight", C.c_double), ("progress_every", C.c_int32)]
 
 NUM_PHASES = 7
 PHASES = ("project", "backproject", "blur", "transpose", "primal", "dual", "scalars")
@@ -373,10 +373,10 @@ class LP:
 
 
 def pdhg_options(mode=RESTARTED, max_iters=20000, check_every=64, tol=1e-4, tau=0.0, sigma=0.0, power_iters=100,
-                 eta=0.95, infeas_tol=1e-6, use_graph=0, profile=0, scalar_weight=0.0):
+                 eta=0.95, infeas_tol=1e-6, use_graph=0, profile=0, scalar_weight=0.0, progress_every=0):
     return PdhgOptions(int(mode), int(max_iters), int(check_every), float(tol), float(tau), float(sigma),
                        int(power_iters), float(eta), float(infeas_tol), int(use_graph), int(profile),
-                       float(scalar_weight))
+                       float(scalar_weight), int(progress_every))
 
 
 def solve(lps, opts=None, want_dose=True, workspace=None):

@@ -44,6 +44,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstddef>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -1746,7 +1747,7 @@ int Solver<T>::run(sipo_pdhg_result *res) {
         rc = put_insts();
         if (rc) return rc;
     }
-    int it = 0;
+    int it = 0, checks = 0;
     bool have_t = false;
     while (it < o_.max_iters && !active_.empty()) {
         const int nblk = std::min(check, o_.max_iters - it);
@@ -1773,6 +1774,13 @@ int Solver<T>::run(sipo_pdhg_result *res) {
         rc = lambda_z(L_.lut, L_.llt, L_.tmp2, false);
         if (!rc) rc = kkt(L_.yt, L_.Dt, true, L_.lut, L_.llt, L_.tmp2, live);
         if (rc) return rc;
+        ++checks;
+        if (o_.progress_every > 0 && checks % o_.progress_every == 0)
+            for (int i : live) {
+                const Kkt &k = in_[i].kc;
+                fprintf(stderr, "[sipo] instance %d: iteration %d, relative KKT %.3e (primal %.3e dual %.3e gap %.3e), "
+                        "restarts %d\n", i, it, k.rel(), k.eps_p, k.eps_d, k.eps_gap, in_[i].restarts);
+            }
         std::vector<int> open;
         for (int i : live) {
             const Kkt &k = in_[i].kc;
@@ -1981,6 +1989,7 @@ static int validate(const sipo_problem &pb, const sipo_pdhg_options &o, int idx,
     SIPO_REQUIRE(o.mode == SIPO_PDHG_PLAIN || o.check_every >= 1, "check_every must be >= 1");
     SIPO_REQUIRE(!(o.eta >= 1.0), "eta must be < 1");
     SIPO_REQUIRE(std::isfinite(o.scalar_weight) && o.scalar_weight >= 0, "scalar_weight must be finite and >= 0");
+    SIPO_REQUIRE(o.progress_every >= 0, "progress_every must be >= 0");
     return SIPO_OK;
 }
 

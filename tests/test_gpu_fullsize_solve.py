@@ -99,7 +99,7 @@ def test_solve_rejects_invalid_arguments_before_launching():
     b = sipo.LP.build(p32, torch.as_tensor(f, dtype=torch.float32, device=dev()), sipo.CASE1, band_width=2.0, f_min=1.0)
     y0 = a.y.clone()
     bad_opts = [dict(max_iters=0), dict(eta=1.0), dict(mode=7), dict(check_every=0), dict(scalar_weight=-1.0),
-                dict(profile=1, use_graph=1)]
+                dict(profile=1, use_graph=1), dict(progress_every=-1)]
     for kw in bad_opts:
         with pytest.raises(SipoError):
             sipo.solve(a, sipo.pdhg_options(**kw))
@@ -109,3 +109,20 @@ def test_solve_rejects_invalid_arguments_before_launching():
     with pytest.raises(SipoError):          # negative objective weight
         sipo.solve(a)
     assert torch.equal(a.y, y0)             # nothing ran
+
+
+def test_progress_lines_report_the_checks(capfd):
+    # progress_every = 2: one line per unfinished instance at every second KKT check (64 iterations apart)
+    import paper_2604_08997_amd as sipo
+    n, na = 16, 12
+    f = ellipses_target(n, 53)
+    plan = sipo.Plan(n, list(angles_uniform(na)), dtype=torch.float64, device=dev())
+    lps = [sipo.LP.build(plan, torch.as_tensor(f, device=dev()), sipo.CASE1, band_width=2.0, f_min=1.0)
+           for _ in range(2)]
+    r = sipo.solve(lps, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=512, tol=1e-14, check_every=64,
+                                          progress_every=2))
+    assert [x["iters"] for x in r] == [512, 512]
+    lines = [ln for ln in capfd.readouterr().err.splitlines() if ln.startswith("[sipo] instance")]
+    assert len(lines) == 2 * 4
+    for k, ln in enumerate(lines):
+        assert ln.startswith(f"[sipo] instance {k % 2}: iteration {128 * (k // 2 + 1)}, relative KKT ")
