@@ -200,3 +200,28 @@ def test_restarted_3d_ragged_tiles_fp32_paths_match_fp64_and_highs():
         out[dtype] = res["primal_obj"]
     # the optimal y need not be unique; the objective is
     assert abs(out[torch.float32] - out[torch.float64]) <= 1e-5 * (1 + abs(out[torch.float64]))
+
+
+def test_restarted_3d_without_psf_fp32_and_fp64_match_highs():
+    # no blur: the masked solve backprojects straight into the dose and moves the whole projector
+    # input; in FP32 the primal step still runs inside the projector
+    import paper_2604_08997_amd as sipo
+    from sipo_inputs import ellipsoids_target
+    n, na, nz = 32, 16, 8
+    f = ellipsoids_target(n, 28, count=3, nz=nz)
+    g = make_geometry(n, angles_uniform(na), nz=nz, atten=1.0)
+    op = olp.build(Projector(g), f, olp.CASE1, band_width=2.0)
+    ref = olp.solve_highs(op)
+    assert ref.status == "optimal"
+    objs = {}
+    for dtype in (torch.float64, torch.float32):
+        plan = sipo.Plan(n, list(angles_uniform(na)), nz=nz, dtype=dtype, device=dev())
+        gl = sipo.LP.build(plan, torch.as_tensor(f, dtype=dtype, device=dev()), sipo.CASE1, band_width=2.0, f_min=1.0)
+        res = sipo.solve(gl, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=20000, tol=1e-4))
+        assert res["status_name"] in ("optimal", "iter_limit"), res["status_name"]
+        y, lu, ll = gpu_state(gl)
+        k = okkt.residuals(op, y, res["u"], res["v"], lu, ll)
+        assert k.rel <= 3e-4, (dtype, k)
+        assert abs(res["primal_obj"] - ref.objective) <= 3e-4 * (1 + abs(ref.objective)), (dtype, res["primal_obj"])
+        objs[dtype] = res["primal_obj"]
+    assert abs(objs[torch.float32] - objs[torch.float64]) <= 1e-4 * (1 + abs(objs[torch.float64]))
