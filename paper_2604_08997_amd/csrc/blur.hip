@@ -17,8 +17,15 @@
 namespace sipo {
 
 constexpr int kBTX = 64, kBTY = 16, kBRows = kBTY / 4;   // tile; 256 threads = 64 x 4, 4 rows per thread
+constexpr int kBlurMaskedPF = 2;   // slices fetched ahead by tile-masked launches
 
-template <typename T, int RXY, int RZ>
+// PF is the number of slices fetched ahead.  PF = 1 (full volumes, many workgroups per CU): guarded
+// loads, one slice ahead.  PF > 1 (tile-masked launches, few workgroups whose serial slice walk is the
+// whole cost): every load is unconditional, from an address clamped into the volume, with the values
+// outside it selected to zero, so the compiler can count them in its memory waits; slices are fetched PF
+// ahead into statically indexed register slots, and the walk is padded to a multiple of PF (a padded slice
+// re-reads the last walked one and stores nothing).
+template <typename T, int RXY, int RZ, int PF>
 __global__ void __launch_bounds__(256) blur_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int nz,
                                                    Taps<T> tp, int zchunk, const uint8_t *__restrict__ tile_on,
                                                    int zero_off) {
@@ -46,17 +53,44 @@ __global__ void __launch_bounds__(256) blur_kernel(const T *__restrict__ in, T *
     }
     const int gxm = x0 - RXY + tx, gxh = x0 - RXY + kBTX + tx;
     const bool okm = gxm >= 0 && gxm < n, okh = tx < 2 * RXY && gxh >= 0 && gxh < n;
+    const int zfirst = z0 - RZ, zlast = zend + RZ;   // walked input slices [zfirst, zlast)
 
-    T pm[LR], ph[LR];
-    auto fetch = [&](int zi) {
-        const bool zok = zi >= 0 && zi < nz;
-        const T *src = in + (size_t)(zok ? zi : 0) * plane;
+    T pm[PF][LR], ph[PF][LR];
+    // PF = 1: values outside the volume are zeroed as they are loaded.  PF > 1: the slots hold the raw loads
+    // and stage() zeroes them, so no wait is needed until a slot is staged.
+    auto fetch = [&](T (&m)[LR], T (&hh)[LR], int zi) {
+        if constexpr (PF == 1) {
+            const bool zok = zi >= 0 && zi < nz;
+            const T *src = in + (size_t)(zok ? zi : 0) * plane;
+#pragma unroll
+            for (int k = 0; k < LR; ++k) {
+                const int ly = ty + 4 * k, gy = y0 - RXY + ly;
+                const bool yok = zok && ly < RH && gy >= 0 && gy < n;
+                m[k] = (yok && okm) ? src[(size_t)gy * n + gxm] : (T)0;
+                hh[k] = (yok && okh) ? src[(size_t)gy * n + gxh] : (T)0;
+            }
+        } else {
+            const int za = min(max(min(zi, zlast - 1), 0), nz - 1);
+            const T *src = in + (size_t)za * plane;
+            const int xm = min(max(gxm, 0), n - 1), xh = min(max(gxh, 0), n - 1);
+#pragma unroll
+            for (int k = 0; k < LR; ++k) {
+                const size_t row = (size_t)min(max(y0 - RXY + ty + 4 * k, 0), n - 1) * n;
+                m[k] = src[row + xm];
+                hh[k] = src[row + xh];
+            }
+        }
+    };
+    auto stage = [&](const T (&m)[LR], const T (&hh)[LR], int zi) {
+        const bool zok = PF == 1 || (zi >= 0 && zi < nz && zi < zlast);
 #pragma unroll
         for (int k = 0; k < LR; ++k) {
             const int ly = ty + 4 * k, gy = y0 - RXY + ly;
-            const bool yok = zok && ly < RH && gy >= 0 && gy < n;
-            pm[k] = (yok && okm) ? src[(size_t)gy * n + gxm] : (T)0;
-            ph[k] = (yok && okh) ? src[(size_t)gy * n + gxh] : (T)0;
+            const bool yok = PF == 1 || (zok && gy >= 0 && gy < n);
+            if (ly < RH) {
+                raw[ly][tx] = (PF == 1 || (yok && okm)) ? m[k] : (T)0;
+                if (tx < 2 * RXY) raw[ly][kBTX + tx] = (PF == 1 || (yok && okh)) ? hh[k] : (T)0;
+            }
         }
     };
 
@@ -66,18 +100,8 @@ __global__ void __launch_bounds__(256) blur_kernel(const T *__restrict__ in, T *
 #pragma unroll
         for (int m = 0; m < 2 * RZ + 1; ++m) ring[j][m] = (T)0;
 
-    fetch(z0 - RZ);
-    for (int zi = z0 - RZ; zi < zend + RZ; ++zi) {
-#pragma unroll
-        for (int k = 0; k < LR; ++k) {
-            const int ly = ty + 4 * k;
-            if (ly < RH) {
-                raw[ly][tx] = pm[k];
-                if (tx < 2 * RXY) raw[ly][kBTX + tx] = ph[k];
-            }
-        }
-        __syncthreads();
-        if (zi + 1 < zend + RZ) fetch(zi + 1);
+    // x and y passes of the staged slice zi, the z ring, and output slice zi - RZ
+    auto blur_slice = [&](int zi) {
 #pragma unroll
         for (int k = 0; k < LR; ++k) {
             const int ly = ty + 4 * k;
@@ -113,6 +137,32 @@ __global__ void __launch_bounds__(256) blur_kernel(const T *__restrict__ in, T *
 #pragma unroll
                 for (int m = 0; m < 2 * RZ + 1; ++m) s = fma(tp.kz[m], ring[j][m], s);
                 if (gx < n && gy < n) out[(size_t)zo * plane + (size_t)gy * n + gx] = s;
+            }
+        }
+    };
+
+    if constexpr (PF == 1) {
+        fetch(pm[0], ph[0], zfirst);
+        for (int zi = zfirst; zi < zlast; ++zi) {
+            stage(pm[0], ph[0], zi);
+            __syncthreads();
+            if (zi + 1 < zlast) fetch(pm[0], ph[0], zi + 1);
+            blur_slice(zi);
+        }
+    } else {
+        const int zpad = zfirst + (zlast - zfirst + PF - 1) / PF * PF;
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            fetch(pm[q], ph[q], zfirst + q);
+            asm volatile("" ::: "memory");   // slot q's loads issue before slot q + 1's (the waits count in order)
+        }
+        for (int zb = zfirst; zb < zpad; zb += PF) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                stage(pm[q], ph[q], zb + q);
+                __syncthreads();
+                fetch(pm[q], ph[q], zb + q + PF);
+                blur_slice(zb + q);
             }
         }
     }
@@ -224,8 +274,12 @@ template <typename T, int RXY, int RZ>
 static void launch_r(const Taps<T> &tp, const void *in, void *out, int n, int nz, int zchunk, hipStream_t s,
                      const uint8_t *on, int zero_off) {
     const dim3 grid((n + kBTX - 1) / kBTX, (n + kBTY - 1) / kBTY, (nz + zchunk - 1) / zchunk);
-    hipLaunchKernelGGL((blur_kernel<T, RXY, RZ>), grid, dim3(kBTX, 4), 0, s, (const T *)in, (T *)out, n, nz, tp,
-                       zchunk, on, zero_off);
+    if (on)
+        hipLaunchKernelGGL((blur_kernel<T, RXY, RZ, kBlurMaskedPF>), grid, dim3(kBTX, 4), 0, s, (const T *)in,
+                           (T *)out, n, nz, tp, zchunk, on, zero_off);
+    else
+        hipLaunchKernelGGL((blur_kernel<T, RXY, RZ, 1>), grid, dim3(kBTX, 4), 0, s, (const T *)in, (T *)out, n, nz,
+                           tp, zchunk, on, zero_off);
 }
 
 template <typename T, int RXY>
