@@ -274,14 +274,6 @@ __device__ __forceinline__ void st4(T *p, const Q4<T> &r) {
     }
 }
 
-template <typename T>
-__device__ __forceinline__ Q4<T> ld4_or(const T *p, long long i, double s) {
-    if (p) return ld4(p + i);
-    Q4<T> r;
-    r.v[0] = r.v[1] = r.v[2] = r.v[3] = (T)s;
-    return r;
-}
-
 // all four bytes of a mask word nonzero
 __device__ __forceinline__ bool all_bytes(uint32_t w) { return ((w - 0x01010101u) & ~w & 0x80808080u) == 0; }
 __device__ __forceinline__ uint32_t byte_of(uint32_t w, int k) { return (w >> (8 * k)) & 0xFFu; }
@@ -305,9 +297,25 @@ __global__ void __launch_bounds__(kThreads) k_seg_live(const uint8_t *__restrict
     if (threadIdx.x == 0) live[blockIdx.x] = any ? 1 : 0;
 }
 
+// Optional fields known at compile time.  A kernel variant either loads a field or uses its
+// constant, so every load of the variant is unconditional and the compiler issues them back to back
+// and waits once; a pointer test per field had put a branch around each load and a full memory wait
+// after some of them.  HAL = Halpern anchors and row scalings present (restarted mode); BND =
+// per-voxel bounds present.
+template <bool HAS, typename T>
+__device__ __forceinline__ Q4<T> ld4_if(const T *p, long long i, double s) {
+    if constexpr (HAS) {
+        return ld4(p + i);
+    } else {
+        Q4<T> r;
+        r.v[0] = r.v[1] = r.v[2] = r.v[3] = (T)s;
+        return r;
+    }
+}
+
 // t.y = act ? max(0, y - tau q) : 0 with tau = tau_fac T_j (or tau_fac); y <- w ((1+rho) t.y - rho y) + (1-w) y0.
 // A masked ray keeps y = t.y = anchor = 0 (all three start at zero there), so it is not stored.
-template <typename T>
+template <typename T, bool HAL>
 __global__ void __launch_bounds__(kThreads) k_primal(T *__restrict__ y, T *__restrict__ yt, const T *__restrict__ q,
                                                      const T *__restrict__ Tj, const uint8_t *__restrict__ act,
                                                      const T *__restrict__ y0, const DevScal *__restrict__ scal,
@@ -326,8 +334,8 @@ __global__ void __launch_bounds__(kThreads) k_primal(T *__restrict__ y, T *__res
     for (int g = 0; g < 4; ++g) {
         yo[g] = ld4(y + i0 + 4 * g);
         qq[g] = ld4(q + i0 + 4 * g);
-        tj[g] = ld4_or(Tj, i0 + 4 * g, 1.0);
-        a0[g] = ld4_or(y0, i0 + 4 * g, 0.0);
+        tj[g] = ld4_if<HAL>(Tj, i0 + 4 * g, 1.0);
+        a0[g] = ld4_if<HAL>(y0, i0 + 4 * g, 0.0);
     }
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
@@ -337,7 +345,7 @@ __global__ void __launch_bounds__(kThreads) k_primal(T *__restrict__ y, T *__res
             T v = yo[g].v[k] - tf * tj[g].v[k] * qq[g].v[k];
             v = v > (T)0 ? v : (T)0;
             t.v[k] = v;
-            yn.v[k] = y0 ? w * (((T)1 + rho) * v - rho * yo[g].v[k]) + ((T)1 - w) * a0[g].v[k] : v;
+            yn.v[k] = HAL ? w * (((T)1 + rho) * v - rho * yo[g].v[k]) + ((T)1 - w) * a0[g].v[k] : v;
         }
         const long long ib = i0 + 4 * g;
         if (all_bytes(mw[g]) && ib + 4 <= sg.e) {
@@ -357,7 +365,8 @@ __global__ void __launch_bounds__(kThreads) k_primal(T *__restrict__ y, T *__res
 // unlabelled voxels is not kept (nothing reads it during the solve), so a thread whose voxels are
 // all unlabelled does nothing.  The voxels of a thread are handled in two halves of eight, each
 // with all of its loads issued before its arithmetic.
-template <typename T>
+// HAL and BND: see ld4_if.
+template <typename T, bool HAL, bool BND>
 __global__ void __launch_bounds__(kThreads) k_dual(
     const T *__restrict__ Dt, T *__restrict__ D, const T *__restrict__ D0, T *__restrict__ lu, T *__restrict__ ll,
     const T *__restrict__ lu0, const T *__restrict__ ll0, T *__restrict__ z, const uint8_t *__restrict__ lab,
@@ -386,15 +395,15 @@ __global__ void __launch_bounds__(kThreads) k_dual(
                 const long long ib = i0 + 4 * (2 * h + g);
                 dt[g] = ld4(Dt + ib);
                 dz[g] = ld4(D + ib);
-                d0[g] = ld4_or(D0, ib, 0.0);
+                d0[g] = ld4_if<HAL>(D0, ib, 0.0);
                 a_old[g] = ld4(lu + ib);
-                a_0[g] = ld4_or(lu0, ib, 0.0);
-                su[g] = ld4_or(s_up, ib, 1.0);
-                U[g] = ld4_or(hi, ib, c.hi_s);
+                a_0[g] = ld4_if<HAL>(lu0, ib, 0.0);
+                su[g] = ld4_if<HAL>(s_up, ib, 1.0);
+                U[g] = ld4_if<BND>(hi, ib, c.hi_s);
                 b_old[g] = ld4(ll + ib);
-                b_0[g] = ld4_or(ll0, ib, 0.0);
-                sl[g] = ld4_or(s_lo, ib, 1.0);
-                Lo[g] = ld4_or(lo, ib, c.lo_s);
+                b_0[g] = ld4_if<HAL>(ll0, ib, 0.0);
+                sl[g] = ld4_if<HAL>(s_lo, ib, 1.0);
+                Lo[g] = ld4_if<BND>(lo, ib, c.lo_s);
             }
 #pragma unroll
             for (int g = 0; g < 2; ++g) {
@@ -405,16 +414,16 @@ __global__ void __launch_bounds__(kThreads) k_dual(
                 for (int k = 0; k < 4; ++k) {
                     const uint32_t L = byte_of(L4, k);
                     const T t = dt[g].v[k], d = dz[g].v[k];
-                    dn.v[k] = D0 ? w * (rp * t - rho * d) + w1 * d0[g].v[k] : t;
+                    dn.v[k] = HAL ? w * (rp * t - rho * d) + w1 * d0[g].v[k] : t;
                     const T Db = (T)2 * t - d;
                     T a = a_old[g].v[k] + sf * su[g].v[k] * (Db - (L == 1 ? ub : vb * U[g].v[k]));
                     a = a > (T)0 ? a : (T)0;
                     at.v[k] = a;
-                    an.v[k] = lu0 ? w * (rp * a - rho * a_old[g].v[k]) + w1 * a_0[g].v[k] : a;
+                    an.v[k] = HAL ? w * (rp * a - rho * a_old[g].v[k]) + w1 * a_0[g].v[k] : a;
                     T b = b_old[g].v[k] + sf * sl[g].v[k] * (Lo[g].v[k] - Db);
                     b = b > (T)0 ? b : (T)0;
                     bt.v[k] = b;
-                    bn.v[k] = ll0 ? w * (rp * b - rho * b_old[g].v[k]) + w1 * b_0[g].v[k] : b;
+                    bn.v[k] = HAL ? w * (rp * b - rho * b_old[g].v[k]) + w1 * b_0[g].v[k] : b;
                     zz.v[k] = L == 2 ? an.v[k] - bn.v[k] : an.v[k];
                     if (ib + k < sg.e) {
                         if (L == 1) acc[0] += (double)an.v[k];
@@ -456,6 +465,12 @@ __global__ void __launch_bounds__(kThreads) k_dual(
         }
     }
     block_sums(acc, partials);
+}
+
+template <typename T>
+static auto dual_kernel(bool hal, bool bnd) -> decltype(&k_dual<T, true, true>) {
+    if (hal) return bnd ? &k_dual<T, true, true> : &k_dual<T, true, false>;
+    return bnd ? &k_dual<T, false, true> : &k_dual<T, false, false>;
 }
 
 // Next scalar primal step from the current z and the lambda sums.
@@ -1585,21 +1600,23 @@ int Solver<T>::iteration(bool check) {
     if (!rc) rc = adjoint(L_.z, L_.q, hal);
     if (rc) return rc;
     if (n_seg_sl_)
-        hipLaunchKernelGGL((k_primal<T>), dim3(n_seg_sl_), dim3(kThreads), 0, s_, F(L_.y), F(L_.yt), (const T *)F(L_.q),
-                           hal ? (const T *)F(L_.Tj) : (const T *)nullptr, (const uint8_t *)U8(L_.act),
-                           hal ? (const T *)F(L_.y0) : (const T *)nullptr, (const DevScal *)scal(), segSL());
+        hipLaunchKernelGGL((hal ? &k_primal<T, true> : &k_primal<T, false>), dim3(n_seg_sl_), dim3(kThreads), 0, s_,
+                           F(L_.y), F(L_.yt), (const T *)F(L_.q), hal ? (const T *)F(L_.Tj) : (const T *)nullptr,
+                           (const uint8_t *)U8(L_.act), hal ? (const T *)F(L_.y0) : (const T *)nullptr,
+                           (const DevScal *)scal(), segSL());
     rc = mark(SIPO_PHASE_PRIMAL);
     if (!rc) rc = dose(L_.yt, L_.Dt);
     if (rc) return rc;
     if (n_seg_vl_)
-        hipLaunchKernelGGL((k_dual<T>), dim3(n_seg_vl_), dim3(kThreads), 0, s_, (const T *)F(L_.Dt), F(L_.D),
-                       hal ? (const T *)F(L_.D0) : (const T *)nullptr, F(L_.lu), F(L_.ll),
-                       hal ? (const T *)F(L_.lu0) : (const T *)nullptr, hal ? (const T *)F(L_.ll0) : (const T *)nullptr,
-                       F(L_.z), (const uint8_t *)U8(L_.lab), lo_(), hi_(),
-                       hal ? (const T *)F(L_.s_up) : (const T *)nullptr, hal ? (const T *)F(L_.s_lo) : (const T *)nullptr,
-                       check ? F(L_.lut) : (T *)nullptr, check ? F(L_.llt) : (T *)nullptr,
-                       check ? F(L_.luo) : (T *)nullptr, check ? F(L_.llo) : (T *)nullptr, (const DevScal *)scal(),
-                       insts(), segVL(), partials(), mask_ ? 1 : 0);
+        hipLaunchKernelGGL(dual_kernel<T>(hal, L_.lohi), dim3(n_seg_vl_), dim3(kThreads), 0, s_,
+                           (const T *)F(L_.Dt), F(L_.D), hal ? (const T *)F(L_.D0) : (const T *)nullptr, F(L_.lu),
+                           F(L_.ll), hal ? (const T *)F(L_.lu0) : (const T *)nullptr,
+                           hal ? (const T *)F(L_.ll0) : (const T *)nullptr, F(L_.z), (const uint8_t *)U8(L_.lab), lo_(),
+                           hi_(), hal ? (const T *)F(L_.s_up) : (const T *)nullptr,
+                           hal ? (const T *)F(L_.s_lo) : (const T *)nullptr, check ? F(L_.lut) : (T *)nullptr,
+                           check ? F(L_.llt) : (T *)nullptr, check ? F(L_.luo) : (T *)nullptr,
+                           check ? F(L_.llo) : (T *)nullptr, (const DevScal *)scal(), insts(), segVL(), partials(),
+                           mask_ ? 1 : 0);
     rc = mark(SIPO_PHASE_DUAL);
     if (rc) return rc;
     hipLaunchKernelGGL(k_scalars, dim3(active_.size()), dim3(kThreads), 0, s_, (const double *)partials(),
