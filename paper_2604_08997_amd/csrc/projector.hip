@@ -264,29 +264,52 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
 
 // Sum of the view splits' partial volumes on switched-on tiles (fixed order); switched-off tiles get
 // zeros, or with keep_off are left as they are.
-template <typename T>
+template <typename T, int ZC>
 __global__ void __launch_bounds__(256) k_bp3d_reduce(const T *__restrict__ part, T *__restrict__ vol,
-                                                     const uint8_t *__restrict__ tile_on, int n, int nz, int zc,
-                                                     int nsplit, long long total, int keep_off) {
+                                                     const uint8_t *__restrict__ tile_on, int n, int nz, int nsplit,
+                                                     long long total, int keep_off) {
     // one workgroup per backprojector tile (grid = the backprojector's tiles): a thread owns voxel x of
-    // rows y and y + 8 in every slice of the tile
+    // rows y and y + 8 in every slice of the tile.  Per group of up to 8 slices, a split's 2 x 8 values
+    // are loaded together, from addresses clamped into the volume (rows or slices past its edge are
+    // loaded but never stored), so the loads carry no branches and the thread waits once per split;
+    // every sum adds the splits in order 0, 1, ...
+    constexpr int G = ZC < 8 ? ZC : 8;
     const int3 tile = xcd_tile<0>();
     const bool on = !tile_on || tile_on[((size_t)tile.z * gridDim.y + tile.y) * gridDim.x + tile.x];
     if (!on && keep_off) return;
     const int x = tile.x * kBpTX + (threadIdx.x & 31), y = tile.y * kBpTY + (threadIdx.x >> 5);
-    const int z0 = tile.z * zc, z1 = min(nz, z0 + zc);
     if (x >= n) return;
-    for (int z = z0; z < z1; ++z)
+    const int ya = min(y, n - 1), yb = min(y + 8, n - 1);
+    for (int z0 = tile.z * ZC; z0 < min(nz, (tile.z + 1) * ZC); z0 += G) {
+        size_t at[G][2];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int yy = y + 8 * h;
-            if (yy >= n) continue;
-            const size_t i = ((size_t)z * n + yy) * n + x;
-            T v = (T)0;
-            if (on)
-                for (int k = 0; k < nsplit; ++k) v += part[(size_t)k * total + i];
-            vol[i] = v;
+        for (int k = 0; k < G; ++k) {
+            const size_t zz = (size_t)min(z0 + k, nz - 1) * n;
+            at[k][0] = (zz + ya) * n + x;
+            at[k][1] = (zz + yb) * n + x;
         }
+        T v[G][2];
+#pragma unroll
+        for (int k = 0; k < G; ++k) v[k][0] = v[k][1] = (T)0;
+        if (on)
+            for (int s = 0; s < nsplit; ++s) {
+                const T *ps = part + (size_t)s * total;
+                T t[G][2];
+#pragma unroll
+                for (int k = 0; k < G; ++k)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) t[k][h] = ps[at[k][h]];
+#pragma unroll
+                for (int k = 0; k < G; ++k)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) v[k][h] += t[k][h];
+            }
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                if (z0 + k < nz && y + 8 * h < n) vol[at[k][h]] = v[k][h];
+    }
 }
 
 // ------------------------------------------------------------------- 3D P
@@ -1037,8 +1060,8 @@ static void bp3d_zc(sipo_plan p, const void *sino_t, void *vol, int accumulate, 
                        (T)p->atten, accumulate, on, ns, (long long)p->vol_elems());
     if (ns > 1) {
         const long long total = (long long)p->vol_elems();
-        hipLaunchKernelGGL((k_bp3d_reduce<T>), dim3(gx, gy, gz), dim3(256), 0, s, (const T *)sp.partial, (T *)vol, on,
-                           p->n, p->nz, ZC, ns, total, sp.keep_off ? 1 : 0);
+        hipLaunchKernelGGL((k_bp3d_reduce<T, ZC>), dim3(gx, gy, gz), dim3(256), 0, s, (const T *)sp.partial,
+                           (T *)vol, on, p->n, p->nz, ns, total, sp.keep_off ? 1 : 0);
     }
 }
 
