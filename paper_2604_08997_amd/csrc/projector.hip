@@ -148,7 +148,13 @@ static bool bp3d_fits(int n, int nb) {
     return span + 5.0 <= (double)kBpW;
 }
 
-template <typename T, int ZC>
+// VEC (nz a multiple of 4, at most 16 slices per thread): the staging of a view batch issues every
+// b128 load of the window at once, from addresses clamped into the sinogram, and zeroes the values
+// outside it as they are written to LDS, so the loads carry no branches and a thread waits once per
+// batch.  Otherwise the window is staged word by word with guarded loads (at 32 slices per thread
+// the registers of a whole window would cost a wave per SIMD).  Either way the next batch's
+// (sin, cos) is fetched during the current batch.
+template <typename T, int ZC, bool VEC>
 __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict__ sino_t, T *__restrict__ vol, int n,
                                                             int nz, int n_angles, int nb,
                                                             const double2 *__restrict__ trig, double h,
@@ -185,14 +191,14 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
     for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int k = 0; k < ZC; ++k) acc[j][k] = (T)0;
-    const bool vec_ok = (nz & 3) == 0;
     const int cx1 = min(x0 + kBpTX, n) - 1, cy1 = min(y0 + kBpTY, n) - 1;
     const int nvb = (n_angles + kBpTB - 1) / kBpTB, per = (nvb + nsplit - 1) / nsplit;
     const int a_beg = split * per * kBpTB, a_end = min(n_angles, (split + 1) * per * kBpTB);
+    double2 tr_next = trig[min(a_beg + (int)threadIdx.x, n_angles - 1)];
     for (int a0 = a_beg; a0 < a_end; a0 += kBpTB) {
         const int na = min(kBpTB, a_end - a0);
         if ((int)threadIdx.x < na) {
-            const double2 tr = trig[a0 + threadIdx.x];
+            const double2 tr = tr_next;
             double umin = 1e300;
             const int cs_[2] = {x0, cx1}, rs_[2] = {y0, cy1};
             for (int i = 0; i < 2; ++i)
@@ -203,27 +209,56 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
             bmin_s[threadIdx.x] = (int)floor(umin) - 1;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < na * kBpW * Z4; e += 256) {
-            const int z4 = e % Z4;
-            const int rest = e / Z4;
-            const int b = rest % kBpW;
-            const int k = rest / kBpW;
-            const int gb = bmin_s[k] + b, gz = z0 + 4 * z4;
-            V4 v;
-            T *vv = (T *)&v;
-            if (gb >= 0 && gb < nb) {
-                const T *src = sino_t + ((size_t)(a0 + k) * nb + gb) * nz + gz;
-                if (vec_ok && gz + 3 < nz) {
-                    v = *(const V4 *)src;   // 16-byte aligned: nz % 4 == 0
+        const int tot = na * kBpW * Z4;
+        if constexpr (VEC) {
+            constexpr int NE = (kBpTB * kBpW * Z4 + 255) / 256;   // b128 words per thread and batch
+            V4 wv[NE];
+#pragma unroll
+            for (int i = 0; i < NE; ++i) {
+                const int e = min((int)threadIdx.x + 256 * i, tot - 1);
+                const int z4 = e % Z4, rest = e / Z4, b = rest % kBpW, k = rest / kBpW;
+                const int gb = min(max(bmin_s[k] + b, 0), nb - 1), gz = min(z0 + 4 * z4, nz - 4);
+                wv[i] = *(const V4 *)(sino_t + ((size_t)(a0 + k) * nb + gb) * nz + gz);   // 16-byte aligned
+            }
+            tr_next = trig[min(a0 + kBpTB + (int)threadIdx.x, n_angles - 1)];
+#pragma unroll
+            for (int i = 0; i < NE; ++i) {
+                const int e = (int)threadIdx.x + 256 * i;
+                if (e < tot) {
+                    const int z4 = e % Z4, rest = e / Z4, b = rest % kBpW, k = rest / kBpW;
+                    const int gb = bmin_s[k] + b, gz = z0 + 4 * z4;
+                    const bool ok = gb >= 0 && gb < nb && gz < nz;
+                    V4 v = wv[i];
+                    T *vv = (T *)&v;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) vv[q] = ok ? vv[q] : (T)0;
+                    *(V4 *)&lds[k][b][4 * z4] = v;
+                }
+            }
+        } else {
+            for (int e = threadIdx.x; e < tot; e += 256) {
+                const int z4 = e % Z4;
+                const int rest = e / Z4;
+                const int b = rest % kBpW;
+                const int k = rest / kBpW;
+                const int gb = bmin_s[k] + b, gz = z0 + 4 * z4;
+                V4 v;
+                T *vv = (T *)&v;
+                if (gb >= 0 && gb < nb) {
+                    const T *src = sino_t + ((size_t)(a0 + k) * nb + gb) * nz + gz;
+                    if ((nz & 3) == 0 && gz + 3 < nz) {
+                        v = *(const V4 *)src;   // 16-byte aligned: nz % 4 == 0
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) vv[q] = (gz + q < nz) ? src[q] : (T)0;
+                    }
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) vv[q] = (gz + q < nz) ? src[q] : (T)0;
+                    for (int q = 0; q < 4; ++q) vv[q] = (T)0;
                 }
-            } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) vv[q] = (T)0;
+                *(V4 *)&lds[k][b][4 * z4] = v;
             }
-            *(V4 *)&lds[k][b][4 * z4] = v;
+            tr_next = trig[min(a0 + kBpTB + (int)threadIdx.x, n_angles - 1)];
         }
         __syncthreads();
         for (int k = 0; k < na; ++k) {
@@ -1055,9 +1090,14 @@ static void bp3d_zc(sipo_plan p, const void *sino_t, void *vol, int accumulate, 
     const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
     const int ns = (sp.parts > 1 && !accumulate) ? sp.parts : 1;
     const int gx = (p->n + kBpTX - 1) / kBpTX, gy = (p->n + kBpTY - 1) / kBpTY, gz = (p->nz + ZC - 1) / ZC;
-    hipLaunchKernelGGL((backproject3d_kernel<T, ZC>), dim3(gx, gy, gz * ns), dim3(256), 0, s, (const T *)sino_t,
-                       (T *)(ns > 1 ? sp.partial : vol), p->n, p->nz, p->n_angles, p->n_bins, p->d_trig, h, inv_ds,
-                       (T)p->atten, accumulate, on, ns, (long long)p->vol_elems());
+    if (p->nz % 4 == 0 && ZC <= 16)
+        hipLaunchKernelGGL((backproject3d_kernel<T, ZC, ZC <= 16>), dim3(gx, gy, gz * ns), dim3(256), 0, s,
+                           (const T *)sino_t, (T *)(ns > 1 ? sp.partial : vol), p->n, p->nz, p->n_angles, p->n_bins,
+                           p->d_trig, h, inv_ds, (T)p->atten, accumulate, on, ns, (long long)p->vol_elems());
+    else
+        hipLaunchKernelGGL((backproject3d_kernel<T, ZC, false>), dim3(gx, gy, gz * ns), dim3(256), 0, s,
+                           (const T *)sino_t, (T *)(ns > 1 ? sp.partial : vol), p->n, p->nz, p->n_angles, p->n_bins,
+                           p->d_trig, h, inv_ds, (T)p->atten, accumulate, on, ns, (long long)p->vol_elems());
     if (ns > 1) {
         const long long total = (long long)p->vol_elems();
         hipLaunchKernelGGL((k_bp3d_reduce<T, ZC>), dim3(gx, gy, gz), dim3(256), 0, s, (const T *)sp.partial,
