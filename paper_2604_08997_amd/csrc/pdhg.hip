@@ -139,6 +139,37 @@ __device__ double block_total(const double *__restrict__ partials, int first, in
     return r;
 }
 
+// Columns 0 and 1 of partials[first .. first + count) at once, by one block: each thread adds its rows
+// b = t, t + kThreads, ... in that order (one 16-byte load per row, four rows in flight), then one fixed
+// tree; per column the additions are the ones block_total<false> makes, in the same order.
+__device__ double2 block_total01(const double *__restrict__ partials, int first, int count, double2 *sh) {
+    double a0 = 0.0, a1 = 0.0;
+    for (int b0 = threadIdx.x; b0 < count; b0 += 4 * kThreads) {
+        double2 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            v[q] = *(const double2 *)(partials + (size_t)(first + min(b0 + q * kThreads, count - 1)) * kNS);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (b0 + q * kThreads < count) {
+                a0 += v[q].x;
+                a1 += v[q].y;
+            }
+    }
+    sh[threadIdx.x] = make_double2(a0, a1);
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const double2 x = sh[threadIdx.x], y = sh[threadIdx.x + o];
+            sh[threadIdx.x] = make_double2(x.x + y.x, x.y + y.y);
+        }
+        __syncthreads();
+    }
+    const double2 r = sh[0];
+    __syncthreads();
+    return r;
+}
+
 // out[i][k] for the instances i = list[blockIdx.x]: totals of their workgroups' partials.
 template <bool MAX>
 __global__ void __launch_bounds__(kThreads) k_finish(const double *__restrict__ partials, const int *__restrict__ first,
@@ -486,10 +517,10 @@ __global__ void __launch_bounds__(kThreads) k_scalars(const double *__restrict__
                                                        const int *__restrict__ first, const int *__restrict__ count,
                                                        const int *__restrict__ list, DevScal *scal,
                                                        const InstC *__restrict__ insts) {
-    __shared__ double sh[kThreads];
+    __shared__ double2 sh[kThreads];
     const int i = list[blockIdx.x];
-    const double s0 = block_total<false>(partials, first[i], count[i], 0, sh);
-    const double s1 = block_total<false>(partials, first[i], count[i], 1, sh);
+    const double2 s01 = block_total01(partials, first[i], count[i], sh);
+    const double s0 = s01.x, s1 = s01.y;
     if (threadIdx.x != 0) return;
     DevScal *sc = scal + i;
     const LPConst c = insts[i].c;

@@ -830,11 +830,14 @@ __global__ void __launch_bounds__(256) transpose_flagged_kernel(const T *__restr
     __shared__ T tile[kTrRows][kTrCols + 1];
     if (!tile_on[(size_t)blockIdx.y * gridDim.x + blockIdx.x]) return;
     const int c0 = blockIdx.x * kTrCols, r0 = blockIdx.y * kTrRows, t = threadIdx.x;
+    // all kTrRows loads of a thread in flight at once: unconditional, from a clamped address, with the
+    // values outside the matrix zeroed as they are written to LDS
+    const int cl = min(c0 + t, cols - 1);
+    T v[kTrRows];
 #pragma unroll
-    for (int i = 0; i < kTrRows; ++i) {
-        const int r = r0 + i, c = c0 + t;
-        tile[i][t] = (r < rows && c < cols) ? in[(size_t)r * cols + c] : (T)0;
-    }
+    for (int i = 0; i < kTrRows; ++i) v[i] = in[(size_t)min(r0 + i, rows - 1) * cols + cl];
+#pragma unroll
+    for (int i = 0; i < kTrRows; ++i) tile[i][t] = (r0 + i < rows && c0 + t < cols) ? v[i] : (T)0;
     __syncthreads();
     const int rr = t % kTrRows, r = r0 + rr;
 #pragma unroll
