@@ -392,19 +392,18 @@ __global__ void __launch_bounds__(kThreads) k_primal(T *__restrict__ y, T *__res
 
 // Dual step on voxels from D_t (= K P^T t.y) and D (= K P^T z.y); Halpern update of lambda and D;
 // z_lambda for the next step; on check iterations t.lambda and the pre-step lambda are kept.
-// [0] sum_band lambda1, [1] sum_gel U lambda2 of the new lambda.  labelled_only: the dose of
+// [0] sum_band lambda1, [1] sum_gel U lambda2 of the new lambda.  LAB (labelled only): the dose of
 // unlabelled voxels is not kept (nothing reads it during the solve), so a thread whose voxels are
 // all unlabelled does nothing.  The voxels of a thread are handled in two halves of eight, each
 // with all of its loads issued before its arithmetic.
 // HAL and BND: see ld4_if.
-template <typename T, bool HAL, bool BND>
+template <typename T, bool HAL, bool BND, bool LAB>
 __global__ void __launch_bounds__(kThreads) k_dual(
     const T *__restrict__ Dt, T *__restrict__ D, const T *__restrict__ D0, T *__restrict__ lu, T *__restrict__ ll,
     const T *__restrict__ lu0, const T *__restrict__ ll0, T *__restrict__ z, const uint8_t *__restrict__ lab,
     const T *__restrict__ lo, const T *__restrict__ hi, const T *__restrict__ s_up, const T *__restrict__ s_lo,
     T *__restrict__ lut, T *__restrict__ llt, T *__restrict__ luo, T *__restrict__ llo,
-    const DevScal *__restrict__ scal, const InstC *__restrict__ insts, const Seg *__restrict__ segs, double *partials,
-    int labelled_only) {
+    const DevScal *__restrict__ scal, const InstC *__restrict__ insts, const Seg *__restrict__ segs, double *partials) {
     const Seg sg = segs[blockIdx.x];
     const DevScal &sc = scal[sg.inst];
     const LPConst c = insts[sg.inst].c;
@@ -417,7 +416,8 @@ __global__ void __launch_bounds__(kThreads) k_dual(
     uint4 l16 = make_uint4(0u, 0u, 0u, 0u);
     if (i0 < sg.e) l16 = *(const uint4 *)(lab + i0);
     const uint32_t lw[4] = {l16.x, l16.y, l16.z, l16.w};
-    if (i0 < sg.e && (!labelled_only || (l16.x | l16.y | l16.z | l16.w))) {
+    const bool any_label = (l16.x | l16.y | l16.z | l16.w) != 0;
+    if (i0 < sg.e && (!LAB || any_label)) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             Q4<T> dt[2], dz[2], d0[2], a_old[2], a_0[2], su[2], U[2], b_old[2], b_0[2], sl[2], Lo[2];
@@ -461,35 +461,39 @@ __global__ void __launch_bounds__(kThreads) k_dual(
                         if (L == 2) acc[1] += (double)U[g].v[k] * (double)an.v[k];
                     }
                 }
-                if (ib + 4 <= sg.e) {
-                    st4(D + ib, dn);   // unlabelled voxels too: their dose is either kept or not read
-                } else {
+                // D, lambda and z are stored as whole 16-byte words with no branch, so the compiler can
+                // count the stores in its waits: an element that is not updated (not labelled, or past
+                // the segment end, in the packing gap that nothing reads) gets back the value loaded
+                // for it, or 0 for z (z, lambda_up and lambda_lo are zero off their labels).  The dose
+                // of an unlabelled voxel is stored too: it is either kept or not read.
+                Q4<T> dS, luS, zS, llS;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (ib + k < sg.e) D[ib + k] = dn.v[k];
+                for (int k = 0; k < 4; ++k) {
+                    const bool in = ib + k < sg.e;
+                    const uint32_t L = byte_of(L4, k);
+                    dS.v[k] = in ? dn.v[k] : dz[g].v[k];
+                    luS.v[k] = (in && L) ? an.v[k] : a_old[g].v[k];
+                    zS.v[k] = (in && L) ? zz.v[k] : (T)0;
+                    llS.v[k] = (in && L == 2) ? bn.v[k] : b_old[g].v[k];
                 }
-                if (ib + 4 <= sg.e && all_bytes(L4)) {
-                    st4(lu + ib, an);
-                    st4(z + ib, zz);
-                    if (lut) { st4(lut + ib, at); st4(luo + ib, a_old[g]); }
-                } else if (L4) {
+                st4(D + ib, dS);
+                if (LAB || any_label) {   // LAB: the thread holds a label, no test needed
+                    st4(lu + ib, luS);
+                    st4(z + ib, zS);
+                    st4(ll + ib, llS);
+                }
+                // check iterations only: the restart copies take these fields over whole segments, so
+                // they are written on labelled voxels alone
+                if (lut) {
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
                         if (ib + k < sg.e && byte_of(L4, k)) {
-                            lu[ib + k] = an.v[k];
-                            z[ib + k] = zz.v[k];
-                            if (lut) { lut[ib + k] = at.v[k]; luo[ib + k] = a_old[g].v[k]; }
-                        }
-                }
-                if (ib + 4 <= sg.e && L4 == 0x02020202u) {
-                    st4(ll + ib, bn);
-                    if (llt) { st4(llt + ib, bt); st4(llo + ib, b_old[g]); }
-                } else if (L4) {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (ib + k < sg.e && byte_of(L4, k) == 2) {
-                            ll[ib + k] = bn.v[k];
-                            if (llt) { llt[ib + k] = bt.v[k]; llo[ib + k] = b_old[g].v[k]; }
+                            lut[ib + k] = at.v[k];
+                            luo[ib + k] = a_old[g].v[k];
+                            if (byte_of(L4, k) == 2) {
+                                llt[ib + k] = bt.v[k];
+                                llo[ib + k] = b_old[g].v[k];
+                            }
                         }
                 }
             }
@@ -498,10 +502,15 @@ __global__ void __launch_bounds__(kThreads) k_dual(
     block_sums(acc, partials);
 }
 
+template <typename T, bool LAB>
+static auto dual_kernel_l(bool hal, bool bnd) -> decltype(&k_dual<T, true, true, LAB>) {
+    if (hal) return bnd ? &k_dual<T, true, true, LAB> : &k_dual<T, true, false, LAB>;
+    return bnd ? &k_dual<T, false, true, LAB> : &k_dual<T, false, false, LAB>;
+}
+
 template <typename T>
-static auto dual_kernel(bool hal, bool bnd) -> decltype(&k_dual<T, true, true>) {
-    if (hal) return bnd ? &k_dual<T, true, true> : &k_dual<T, true, false>;
-    return bnd ? &k_dual<T, false, true> : &k_dual<T, false, false>;
+static auto dual_kernel(bool hal, bool bnd, bool lab) -> decltype(&k_dual<T, true, true, true>) {
+    return lab ? dual_kernel_l<T, true>(hal, bnd) : dual_kernel_l<T, false>(hal, bnd);
 }
 
 // Next scalar primal step from the current z and the lambda sums.
@@ -1639,15 +1648,14 @@ int Solver<T>::iteration(bool check) {
     if (!rc) rc = dose(L_.yt, L_.Dt);
     if (rc) return rc;
     if (n_seg_vl_)
-        hipLaunchKernelGGL(dual_kernel<T>(hal, L_.lohi), dim3(n_seg_vl_), dim3(kThreads), 0, s_,
+        hipLaunchKernelGGL(dual_kernel<T>(hal, L_.lohi, mask_), dim3(n_seg_vl_), dim3(kThreads), 0, s_,
                            (const T *)F(L_.Dt), F(L_.D), hal ? (const T *)F(L_.D0) : (const T *)nullptr, F(L_.lu),
                            F(L_.ll), hal ? (const T *)F(L_.lu0) : (const T *)nullptr,
                            hal ? (const T *)F(L_.ll0) : (const T *)nullptr, F(L_.z), (const uint8_t *)U8(L_.lab), lo_(),
                            hi_(), hal ? (const T *)F(L_.s_up) : (const T *)nullptr,
                            hal ? (const T *)F(L_.s_lo) : (const T *)nullptr, check ? F(L_.lut) : (T *)nullptr,
                            check ? F(L_.llt) : (T *)nullptr, check ? F(L_.luo) : (T *)nullptr,
-                           check ? F(L_.llo) : (T *)nullptr, (const DevScal *)scal(), insts(), segVL(), partials(),
-                           mask_ ? 1 : 0);
+                           check ? F(L_.llo) : (T *)nullptr, (const DevScal *)scal(), insts(), segVL(), partials());
     rc = mark(SIPO_PHASE_DUAL);
     if (rc) return rc;
     hipLaunchKernelGGL(k_scalars, dim3(active_.size()), dim3(kThreads), 0, s_, (const double *)partials(),
