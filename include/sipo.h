@@ -83,14 +83,44 @@ typedef struct {
 #define SIPO_MAX_PSF_RADIUS 8
 
 /* A plan binds a geometry, an optional PSF and an element type, and holds the
- * device-side tables the kernels need (view sines and cosines).  Creating a
- * plan allocates a few KB of device memory on the current device; the plan
- * must be used on that device only.  psf == NULL means K = I. */
+ * device-side tables the kernels need: view sines and cosines, the view walk
+ * order and opposite-view pairs, the staged cross ranges of the 3D projector
+ * and, for single-slice plans, the work-item lists of the 2D kernels.  These
+ * tables are the only device memory the library keeps (sipo_plan_autotune
+ * allocates temporary arrays and frees them before it returns); they are
+ * created with the plan on the current device, freed by sipo_plan_destroy,
+ * and sipo_plan_device_bytes reports their size.  The plan must be used on
+ * that device only.
+ * psf == NULL means K = I.  Errors: NULL pointers, sizes < 1 or above 16384
+ * (65535 views), non-finite angles or taps, PSF radius above
+ * SIPO_MAX_PSF_RADIUS (SIPO_E_INVALID); allocation failure (SIPO_E_DEVICE). */
 typedef struct sipo_plan_s *sipo_plan;
 
 int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype dtype,
                      sipo_plan *plan_out);
 int sipo_plan_destroy(sipo_plan plan);
+
+/* Device bytes of the plan's own tables (0 for a NULL plan). */
+size_t sipo_plan_device_bytes(sipo_plan plan);
+
+/* Operator workspace (matrix-free operators on caller-owned arrays, Sec. 2.8).
+ * sipo_project, sipo_backproject, sipo_active_rays and sipo_evaluate need
+ * scratch device memory beyond their inputs and outputs: a 128 KiB reduction
+ * area, and for single-slice and 3D plans a z-contiguous copy of the volume
+ * (and, in 3D, of the sinogram) that the projector kernels read and write.
+ * The caller provides it once per plan: sipo_plan_workspace_size gives the
+ * bytes (128 KiB + one volume + one sinogram in 3D; 128 KiB + one slice for
+ * single-slice plans), and sipo_plan_set_workspace attaches a device buffer of
+ * at least that size, 256-byte aligned, owned by the caller and kept until it
+ * is replaced, detached (workspace == NULL) or the plan is destroyed.  Calls
+ * that need it return SIPO_E_WORKSPACE while none is attached.  Every call on
+ * the plan uses the same workspace, so calls on one plan must be ordered (one
+ * stream, or streams the caller synchronises): calls that overlap race.
+ * sipo_pdhg_solve and sipo_blur do not use it.  Errors of set_workspace:
+ * misaligned pointer (SIPO_E_INVALID), too small (SIPO_E_WORKSPACE); nothing
+ * is changed on error. */
+size_t sipo_plan_workspace_size(sipo_plan plan);
+int sipo_plan_set_workspace(sipo_plan plan, void *workspace, size_t bytes);
 
 /* Times the plan's kernel variants that compute the same result with
  * different work splits (slices per projector thread, slices per blur
@@ -132,12 +162,13 @@ int sipo_plan_set_tuning(sipo_plan plan, const sipo_tuning *t);
 /* vol (+)= P^T sino: backprojection, the geometric part of the dose model
  * f = A^T g = K P^T g (Eq. 2-3).  sino: device [n_angles][nz][n_bins];
  * vol: device [nz][n][n].  accumulate != 0 adds to vol, else overwrites.
- * sino and vol must not overlap. */
+ * sino and vol must not overlap.  3D plans use the plan workspace. */
 int sipo_backproject(sipo_plan plan, const void *sino, void *vol, int accumulate, void *stream);
 
 /* sino (+)= P vol: forward projection, the exact transpose of
  * sipo_backproject (Sec. 2.3).  vol: device [nz][n][n];
- * sino: device [n_angles][nz][n_bins].  Must not overlap. */
+ * sino: device [n_angles][nz][n_bins].  Must not overlap.  Single-slice and
+ * 3D plans use the plan workspace. */
 int sipo_project(sipo_plan plan, const void *vol, void *sino, int accumulate, void *stream);
 
 /* out = K in: the plan's separable PSF with zero boundary ("same" size).
@@ -159,7 +190,8 @@ int sipo_regions(sipo_plan plan, const void *f_target, double band_width, uint8_
 
 /* Active rays (Sec. 2.2, Fig. 2b): act[j] = 1 where (P f_target)_j exceeds
  * 1e-6 times its maximum, else 0.  scratch_sino: device sinogram of the plan
- * dtype used for P f_target (left holding it); act: device uint8 sinogram. */
+ * dtype used for P f_target (left holding it); act: device uint8 sinogram.
+ * Uses the plan workspace. */
 int sipo_active_rays(sipo_plan plan, const void *f_target, void *scratch_sino, uint8_t *act,
                      void *stream);
 
@@ -197,7 +229,7 @@ typedef struct {
  * device volume of f~_T or NULL (then f_t_scalar everywhere on the gel); f_crit:
  * physical critical dose (f_T = f_crit f~_T); weights: device volume or NULL (1);
  * resin, m_target (device volume or NULL -> m_t_scalar): response-domain terms,
- * skipped when resin is NULL.  Uses the plan's scratch; synchronous on stream. */
+ * skipped when resin is NULL.  Uses the plan workspace; synchronous on stream. */
 int sipo_evaluate(sipo_plan plan, const void *dose, const uint8_t *labels, const void *f_target_norm,
                   double f_t_scalar, double f_crit, const void *weights, const sipo_resin *resin,
                   const void *m_target, double m_t_scalar, sipo_metrics *out, void *stream);

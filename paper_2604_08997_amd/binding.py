@@ -95,6 +95,9 @@ class Metrics(C.Structure):
 SIGNATURES = {
     "sipo_plan_create": (C.c_int, [C.POINTER(Geometry), C.POINTER(Psf), C.c_int, C.POINTER(C.c_void_p)]),
     "sipo_plan_destroy": (C.c_int, [C.c_void_p]),
+    "sipo_plan_device_bytes": (C.c_size_t, [C.c_void_p]),
+    "sipo_plan_workspace_size": (C.c_size_t, [C.c_void_p]),
+    "sipo_plan_set_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "sipo_plan_autotune": (C.c_int, [C.c_void_p, C.c_void_p]),
     "sipo_plan_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning)]),
     "sipo_plan_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning)]),
@@ -202,6 +205,16 @@ class Plan:
             _check(lib().sipo_plan_create(C.byref(geom), psf_p, SIPO_F64 if dtype == torch.float64 else SIPO_F32,
                                           C.byref(h)))
         self.handle = h
+        # the operator workspace is caller memory: one torch buffer per plan, attached once
+        need = int(lib().sipo_plan_workspace_size(h))
+        self.workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().sipo_plan_set_workspace(h, _ptr(self.workspace), C.c_size_t(need)))
+
+    @property
+    def device_bytes(self):
+        """Device bytes of the plan's own tables (the workspace is the separate ``workspace`` tensor)."""
+        return int(lib().sipo_plan_device_bytes(self.handle))
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -35,6 +35,23 @@ int check_plan(sipo_plan p) {
     return SIPO_OK;
 }
 
+int check_plan_ws(sipo_plan p) {
+    if (!p->ws)
+        return fail(SIPO_E_WORKSPACE, "this call needs the plan's workspace: attach %zu bytes of device memory with "
+                    "sipo_plan_set_workspace", p->ws_need());
+    if (p->ws_bytes < p->ws_need())
+        return fail(SIPO_E_WORKSPACE, "plan workspace of %zu bytes is smaller than the %zu bytes needed", p->ws_bytes,
+                    p->ws_need());
+    return SIPO_OK;
+}
+
+int plan_alloc(sipo_plan p, void **ptr, size_t bytes) {
+    *ptr = nullptr;
+    SIPO_HIP(hipMalloc(ptr, bytes));
+    p->table_bytes += bytes;
+    return SIPO_OK;
+}
+
 template <typename T>
 static int fill_taps(Taps<T> &t, const sipo_psf *psf) {
     std::memset(&t, 0, sizeof(t));
@@ -100,15 +117,16 @@ int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype 
     for (int a = 0; a < geom->n_angles; ++a)
         if (!(std::fabs(trig[a].y) >= std::fabs(trig[a].x))) order.push_back(a);
 
-    hipError_t e = hipMalloc(&p->d_trig, sizeof(double2) * geom->n_angles);
-    if (e == hipSuccess) e = hipMalloc(&p->d_angle_order, sizeof(int) * geom->n_angles);
-    if (e == hipSuccess) e = hipMalloc(&p->d_scratch, kPlanScratchBytes);
-    if (e == hipSuccess) e = hipMemcpy(p->d_trig, trig.data(), sizeof(double2) * geom->n_angles, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(p->d_angle_order, order.data(), sizeof(int) * geom->n_angles, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        (void)hipFree(p->d_trig); (void)hipFree(p->d_angle_order); (void)hipFree(p->d_scratch);
+    rc = plan_alloc(p, (void **)&p->d_trig, sizeof(double2) * geom->n_angles);
+    if (rc == SIPO_OK) rc = plan_alloc(p, (void **)&p->d_angle_order, sizeof(int) * geom->n_angles);
+    hipError_t e = hipSuccess;
+    if (rc == SIPO_OK) e = hipMemcpy(p->d_trig, trig.data(), sizeof(double2) * geom->n_angles, hipMemcpyHostToDevice);
+    if (rc == SIPO_OK && e == hipSuccess)
+        e = hipMemcpy(p->d_angle_order, order.data(), sizeof(int) * geom->n_angles, hipMemcpyHostToDevice);
+    if (rc != SIPO_OK || e != hipSuccess) {
+        (void)hipFree(p->d_trig); (void)hipFree(p->d_angle_order);
         delete p;
-        return fail(SIPO_E_DEVICE, "plan device allocation failed: %s", hipGetErrorString(e));
+        return rc != SIPO_OK ? rc : fail(SIPO_E_DEVICE, "plan table upload failed: %s", hipGetErrorString(e));
     }
     p->d_batches = nullptr;
     p->d_partner = nullptr;
@@ -120,12 +138,12 @@ int sipo_plan_create(const sipo_geometry *geom, const sipo_psf *psf, sipo_dtype 
     p->d_items_bp2d = p->d_items_fp2d = p->d_items_tr2d = nullptr;
     p->n_items_bp2d = p->n_items_fp2d = p->n_items_tr2d = 0;
     p->p2d_ok = false;
-    p->d_vol_t = nullptr;
-    p->d_sino_t = nullptr;
+    p->ws = nullptr;
+    p->ws_bytes = 0;
     rc = plan_build_batches(p, trig.data());
     if (rc == SIPO_OK) rc = plan_build_2d(p);
     if (rc != SIPO_OK) {
-        (void)hipFree(p->d_trig); (void)hipFree(p->d_angle_order); (void)hipFree(p->d_scratch);
+        (void)hipFree(p->d_trig); (void)hipFree(p->d_angle_order);
         (void)hipFree(p->d_batches);
         (void)hipFree(p->d_partner);
         (void)hipFree(p->d_view_batch);
@@ -150,7 +168,6 @@ int sipo_plan_destroy(sipo_plan p) {
     if (cur != p->device) (void)hipSetDevice(p->device);
     (void)hipFree(p->d_trig);
     (void)hipFree(p->d_angle_order);
-    (void)hipFree(p->d_scratch);
     (void)hipFree(p->d_batches);
     (void)hipFree(p->d_partner);
     (void)hipFree(p->d_view_batch);
@@ -161,10 +178,29 @@ int sipo_plan_destroy(sipo_plan p) {
     (void)hipFree(p->d_items_bp2d);
     (void)hipFree(p->d_items_fp2d);
     (void)hipFree(p->d_items_tr2d);
-    if (p->d_vol_t) (void)hipFree(p->d_vol_t);
-    if (p->d_sino_t) (void)hipFree(p->d_sino_t);
     if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);
     delete p;
+    return SIPO_OK;
+}
+
+size_t sipo_plan_workspace_size(sipo_plan plan) { return plan ? plan->ws_need() : 0; }
+
+size_t sipo_plan_device_bytes(sipo_plan plan) { return plan ? plan->table_bytes : 0; }
+
+int sipo_plan_set_workspace(sipo_plan plan, void *workspace, size_t bytes) {
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!workspace) {
+        plan->ws = nullptr;
+        plan->ws_bytes = 0;
+        return SIPO_OK;
+    }
+    SIPO_REQUIRE(((uintptr_t)workspace & 255) == 0, "plan workspace must be 256-byte aligned");
+    if (bytes < plan->ws_need())
+        return fail(SIPO_E_WORKSPACE, "plan workspace of %zu bytes is smaller than the %zu bytes needed", bytes,
+                    plan->ws_need());
+    plan->ws = workspace;
+    plan->ws_bytes = bytes;
     return SIPO_OK;
 }
 

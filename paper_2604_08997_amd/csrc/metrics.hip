@@ -2,7 +2,7 @@
 // and post-scaling (Eq. 25-28) of a normalised dose on the device.
 //
 // Each metric pass is one grid-stride kernel that leaves, per workgroup, eight
-// FP64 fields (maxima, or sums) in the plan's scratch, finished by one block in
+// FP64 fields (maxima, or sums) in the plan's workspace, finished by one block in
 // a fixed order.  The response-domain calibration (Eq. 28) is a 1-D search on
 // the host over alpha, each step one device reduction of
 // sum_gel w (M(alpha D) - m_T)^2: a log-spaced scan around the dose-domain
@@ -16,6 +16,9 @@
 namespace sipo {
 
 constexpr int kMT = 256, kMF = 8, kMBlocks = 1024;
+// device scratch of one evaluation: kMBlocks rows of kMF partials, then the kMF results
+constexpr size_t kEvalScratchBytes = sizeof(double) * (size_t)(kMBlocks + 1) * kMF;
+static_assert(kEvalScratchBytes <= kPlanRedBytes, "plan reduction area too small for the metric partials");
 
 __device__ __forceinline__ double resp(const sipo_resin &r, double f) {
     return r.alpha + (r.k - r.alpha) / pow(1.0 + exp(-r.beta * (f - r.f0)), 1.0 / r.gamma);
@@ -130,10 +133,11 @@ static int check_resin(const sipo_resin *r) {
 template <typename T>
 class Evaluator {
   public:
-    Evaluator(sipo_plan p, const T *D, const uint8_t *lab, const T *w, hipStream_t s)
+    // scratch: kEvalScratchBytes of device memory for the per-workgroup partials and the result
+    Evaluator(sipo_plan p, const T *D, const uint8_t *lab, const T *w, double *scratch, hipStream_t s)
         : p_(p), D_(D), lab_(lab), w_(w), s_(s), n_(p->vol_elems()) {
         nb_ = (int)std::max<size_t>(1, std::min<size_t>((n_ + 4 * kMT - 1) / (4 * kMT), kMBlocks));
-        partials_ = (double *)p->d_scratch;
+        partials_ = scratch;
         out_ = partials_ + (size_t)kMBlocks * kMF;
     }
     int pass1(const T *ftn, double fts, double fcrit, double *h) {
@@ -167,8 +171,8 @@ class Evaluator {
 template <typename T>
 static int evaluate(sipo_plan p, const void *dose, const uint8_t *labels, const void *ftn, double fts, double fcrit,
                     const void *weights, const sipo_resin *resin, const void *mt, double mts, sipo_metrics *o,
-                    hipStream_t s) {
-    Evaluator<T> ev(p, (const T *)dose, labels, (const T *)weights, s);
+                    double *scratch, hipStream_t s) {
+    Evaluator<T> ev(p, (const T *)dose, labels, (const T *)weights, scratch, s);
     double h[kMF];
     int rc = ev.pass1((const T *)ftn, fts, fcrit, h);
     if (rc) return rc;
@@ -256,13 +260,15 @@ int sipo_evaluate(sipo_plan plan, const void *dose, const uint8_t *labels, const
         if (rc) return rc;
         SIPO_REQUIRE(m_target || std::isfinite(m_t_scalar), "m_T scalar must be finite");
     }
-    static_assert(sizeof(double) * (kMBlocks + 1) * kMF <= kPlanScratchBytes, "plan scratch too small");
+    rc = check_plan_ws(plan);
+    if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
+    double *scratch = (double *)plan->ws_red();
     return plan->dtype == SIPO_F64
                ? evaluate<double>(plan, dose, labels, f_target_norm, f_t_scalar, f_crit, weights, resin, m_target,
-                                  m_t_scalar, out, s)
+                                  m_t_scalar, out, scratch, s)
                : evaluate<float>(plan, dose, labels, f_target_norm, f_t_scalar, f_crit, weights, resin, m_target,
-                                 m_t_scalar, out, s);
+                                 m_t_scalar, out, scratch, s);
 }
 
 }  // extern "C"

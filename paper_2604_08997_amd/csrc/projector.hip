@@ -1024,12 +1024,12 @@ int plan_build_batches(sipo_plan p, const double2 *trig) {
     }
     p->p3d_dma_ok = p->p3d_dma = dma;
     if (dma) {
-        SIPO_HIP(hipMalloc(&p->d_ranges, sizeof(int2) * ranges.size()));
+        SIPO_TRY(plan_alloc(p, (void **)&p->d_ranges, sizeof(int2) * ranges.size()));
         SIPO_HIP(hipMemcpy(p->d_ranges, ranges.data(), sizeof(int2) * ranges.size(), hipMemcpyHostToDevice));
     }
-    SIPO_HIP(hipMalloc(&p->d_vial_rows, sizeof(int2) * vial.size()));
+    SIPO_TRY(plan_alloc(p, (void **)&p->d_vial_rows, sizeof(int2) * vial.size()));
     SIPO_HIP(hipMemcpy(p->d_vial_rows, vial.data(), sizeof(int2) * vial.size(), hipMemcpyHostToDevice));
-    SIPO_HIP(hipMalloc(&p->d_zero, 256));
+    SIPO_TRY(plan_alloc(p, (void **)&p->d_zero, 256));
     SIPO_HIP(hipMemset(p->d_zero, 0, 256));
     // batch of every view (2 * batch, plus 1 for the opposite view of a walked one), -1 if unwalked
     std::vector<int> vbatch(p->n_angles, -1);
@@ -1039,10 +1039,10 @@ int plan_build_batches(sipo_plan p, const double2 *trig) {
             vbatch[v] = 2 * (int)bi;
             if (pair && opp[v] >= 0) vbatch[opp[v]] = 2 * (int)bi + 1;
         }
-    SIPO_HIP(hipMalloc(&p->d_view_batch, sizeof(int) * p->n_angles));
+    SIPO_TRY(plan_alloc(p, (void **)&p->d_view_batch, sizeof(int) * p->n_angles));
     SIPO_HIP(hipMemcpy(p->d_view_batch, vbatch.data(), sizeof(int) * p->n_angles, hipMemcpyHostToDevice));
-    SIPO_HIP(hipMalloc(&p->d_batches, sizeof(int4) * std::max<size_t>(batches.size(), 1)));
-    SIPO_HIP(hipMalloc(&p->d_partner, sizeof(int) * p->n_angles));
+    SIPO_TRY(plan_alloc(p, (void **)&p->d_batches, sizeof(int4) * std::max<size_t>(batches.size(), 1)));
+    SIPO_TRY(plan_alloc(p, (void **)&p->d_partner, sizeof(int) * p->n_angles));
     if (!batches.empty())
         SIPO_HIP(hipMemcpy(p->d_batches, batches.data(), sizeof(int4) * batches.size(), hipMemcpyHostToDevice));
     SIPO_HIP(hipMemcpy(p->d_angle_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
@@ -1271,11 +1271,12 @@ int launch_mask_to_t(sipo_plan p, const uint8_t *mask, uint8_t *mask_t, hipStrea
     return SIPO_OK;
 }
 
-// Single-slice P through the plan's [x][y] scratch copy (allocated with the plan).
+// Single-slice P through an [x][y] copy of the volume in the caller's plan workspace.
 static int fp2d_plan(sipo_plan p, const void *vol, void *sino, int accumulate, hipStream_t s) {
-    int rc = launch_tr2d(p->dtype, p->d_geo2d, p->d_items_tr2d, p->n_items_tr2d, vol, p->d_vol_t, s);
+    int rc = check_plan_ws(p);
+    if (!rc) rc = launch_tr2d(p->dtype, p->d_geo2d, p->d_items_tr2d, p->n_items_tr2d, vol, p->ws_vol_t(), s);
     return rc ? rc : launch_fp2d(p->dtype, p->p3d_nc, p->n, p->d_geo2d, p->d_items_fp2d, p->n_items_fp2d, vol,
-                                 p->d_vol_t, sino, accumulate, s);
+                                 p->ws_vol_t(), sino, accumulate, s);
 }
 
 // Internal-layout entry points (see sipo_internal.hpp).  Slice and fallback
@@ -1388,18 +1389,13 @@ int launch_bp3d_flags(sipo_plan p, const uint8_t *labels, uint8_t *flags, hipStr
     return SIPO_OK;
 }
 
-static int ensure_scratch(sipo_plan p) {
-    if (!p->d_vol_t) SIPO_HIP(hipMalloc(&p->d_vol_t, p->vol_elems() * p->elem_bytes()));
-    if (!p->d_sino_t) SIPO_HIP(hipMalloc(&p->d_sino_t, p->sino_elems() * p->elem_bytes()));
-    return SIPO_OK;
-}
-
-// ABI-layout entry points: the volume kernels run on z-contiguous copies made in the plan's scratch.
+// ABI-layout entry points: the volume kernels run on z-contiguous copies made in the caller's
+// plan workspace.
 int launch_backproject(sipo_plan p, const void *sino, void *vol, int accumulate, hipStream_t s) {
     if (!p->fast3d()) return launch_backproject_t(p, sino, vol, accumulate, s);
-    int rc = ensure_scratch(p);
-    if (!rc) rc = launch_sino_to_t(p, sino, p->d_sino_t, s);
-    return rc ? rc : launch_backproject_t(p, p->d_sino_t, vol, accumulate, s);
+    int rc = check_plan_ws(p);
+    if (!rc) rc = launch_sino_to_t(p, sino, p->ws_sino_t(), s);
+    return rc ? rc : launch_backproject_t(p, p->ws_sino_t(), vol, accumulate, s);
 }
 
 int launch_project(sipo_plan p, const void *vol, void *sino, int accumulate, hipStream_t s) {
@@ -1407,10 +1403,10 @@ int launch_project(sipo_plan p, const void *vol, void *sino, int accumulate, hip
     if (!p->fast3d())
         return p->dtype == SIPO_F64 ? fp_slices<double>(p, vol, sino, accumulate, s)
                                     : fp_slices<float>(p, vol, sino, accumulate, s);
-    int rc = ensure_scratch(p);
-    if (!rc) rc = launch_vol_to_t(p, vol, p->d_vol_t, s);
-    if (!rc) rc = launch_project_t(p, p->d_vol_t, p->d_sino_t, s);
-    return rc ? rc : launch_sino_from_t(p, p->d_sino_t, sino, accumulate, s);
+    int rc = check_plan_ws(p);
+    if (!rc) rc = launch_vol_to_t(p, vol, p->ws_vol_t(), s);
+    if (!rc) rc = launch_project_t(p, p->ws_vol_t(), p->ws_sino_t(), s);
+    return rc ? rc : launch_sino_from_t(p, p->ws_sino_t(), sino, accumulate, s);
 }
 
 }  // namespace sipo

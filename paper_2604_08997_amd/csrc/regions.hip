@@ -161,10 +161,11 @@ __global__ void threshold_act(const T *__restrict__ v, size_t count, const typen
 
 template <typename T>
 static int act_impl(sipo_plan p, const void *f, void *pf, uint8_t *act, hipStream_t s) {
-    int rc = launch_project(p, f, pf, 0, s);
+    int rc = check_plan_ws(p);
+    if (!rc) rc = launch_project(p, f, pf, 0, s);
     if (rc) return rc;
     using U = typename MaxBits<T>::U;
-    U *m = (U *)p->d_scratch;
+    U *m = (U *)p->ws_red();
     const size_t count = p->sino_elems();
     const int blocks = (int)std::min<size_t>((count + 255) / 256, 4096);
     hipLaunchKernelGGL((zero_bits<T>), dim3(1), dim3(1), 0, s, m);

@@ -33,6 +33,12 @@ int fail(int code, const char *fmt, ...);
                                 hipGetErrorString(e_));                                 \
     } while (0)
 
+#define SIPO_TRY(call)                                                                  \
+    do {                                                                                \
+        int rc_ = (call);                                                               \
+        if (rc_ != SIPO_OK) return rc_;                                                 \
+    } while (0)
+
 #define SIPO_REQUIRE(cond, ...)                                                         \
     do {                                                                                \
         if (!(cond)) return ::sipo::fail(SIPO_E_INVALID, __VA_ARGS__);                  \
@@ -48,8 +54,13 @@ struct Taps {
 };
 
 // -------------------------------------------------------------------- plan
-// Small device scratch owned by a plan: reduction partials and scalars.
-constexpr size_t kPlanScratchBytes = 1 << 20;
+// The plan's operator workspace is caller memory (sipo_plan_set_workspace).  It holds, in order:
+// a reduction area (per-workgroup partials of the metric passes, the maximum of the active-ray
+// test), the z-contiguous copy of a volume (fast 3D plans: [y][x][z] input of the projector;
+// single-slice plans: the [x][y] copy read by rays that march along x) and the z-contiguous
+// sinogram ([view][bin][z], fast 3D plans).  Each part starts on a 256-byte boundary.
+constexpr size_t kPlanRedBytes = 1 << 17;
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct Geo2D;
 
@@ -64,7 +75,9 @@ struct sipo_plan_s {
     sipo::Taps<float> taps_f;
     sipo::Taps<double> taps_d;
     double2 *d_trig;        // [n_angles] (sin, cos)
-    void *d_scratch;        // kPlanScratchBytes
+    size_t table_bytes;     // device bytes of the plan's own tables (everything allocated below)
+    void *ws;               // caller workspace for the standalone operator calls (not owned), or NULL
+    size_t ws_bytes;
     // per-angle march axis split, on the host, for launch decisions
     int n_xmajor;
     int *d_angle_order;     // views the 3D projector walks: x-major first, then y-major
@@ -93,17 +106,26 @@ struct sipo_plan_s {
     int blur_zc;            // slices per blur workgroup (0 = built-in choice)
     int bp3d_zc;            // slices per 3D backprojector thread (8 or 16 in FP64; 8, 16 or 32 in FP32)
     bool bp3d_ok;           // the 3D backprojector's bin window fits its LDS tile
-    void *d_vol_t;          // lazily allocated [y][x][z] scratch volume (standalone 3D calls)
-    void *d_sino_t;         // lazily allocated [view][bin][z] scratch sinogram (standalone 3D calls)
     bool fast3d() const { return nz > 1 && p3d_ok && bp3d_ok; }
     size_t vol_elems() const { return (size_t)nz * n * n; }
     size_t sino_elems() const { return (size_t)n_angles * nz * n_bins; }
     size_t elem_bytes() const { return dtype == SIPO_F64 ? 8 : 4; }
+    // workspace layout (see kPlanRedBytes)
+    size_t ws_vol_t_bytes() const { return (p2d_ok || fast3d()) ? sipo::align256(vol_elems() * elem_bytes()) : 0; }
+    size_t ws_sino_t_bytes() const { return fast3d() ? sipo::align256(sino_elems() * elem_bytes()) : 0; }
+    size_t ws_need() const { return sipo::kPlanRedBytes + ws_vol_t_bytes() + ws_sino_t_bytes(); }
+    void *ws_red() const { return ws; }
+    void *ws_vol_t() const { return (char *)ws + sipo::kPlanRedBytes; }
+    void *ws_sino_t() const { return (char *)ws + sipo::kPlanRedBytes + ws_vol_t_bytes(); }
 };
 
 namespace sipo {
 
 int check_plan(sipo_plan p);
+// SIPO_E_WORKSPACE unless the caller has attached a large enough workspace to the plan
+int check_plan_ws(sipo_plan p);
+// hipMalloc of a plan table, counted in p->table_bytes
+int plan_alloc(sipo_plan p, void **ptr, size_t bytes);
 
 // Tile coordinates (x, y, z) of this workgroup, spread over the XCDs.  Workgroups reach the eight
 // XCDs in turn by linear id, so with x taken straight from blockIdx a grid whose x extent is a

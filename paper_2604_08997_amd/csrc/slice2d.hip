@@ -332,14 +332,13 @@ int plan_build_2d(sipo_plan p) {
     append_items_bp2d(g, 0, ib);
     append_items_fp2d(g, 0, ifp);
     append_items_tr2d(g, 0, itr);
-    SIPO_HIP(hipMalloc(&p->d_geo2d, sizeof(Geo2D)));
-    SIPO_HIP(hipMalloc(&p->d_items_bp2d, sizeof(int4) * ib.size()));
-    SIPO_HIP(hipMalloc(&p->d_items_fp2d, sizeof(int4) * ifp.size()));
+    SIPO_TRY(plan_alloc(p, (void **)&p->d_geo2d, sizeof(Geo2D)));
+    SIPO_TRY(plan_alloc(p, (void **)&p->d_items_bp2d, sizeof(int4) * ib.size()));
+    SIPO_TRY(plan_alloc(p, (void **)&p->d_items_fp2d, sizeof(int4) * ifp.size()));
     SIPO_HIP(hipMemcpy(p->d_geo2d, &g, sizeof(Geo2D), hipMemcpyHostToDevice));
     SIPO_HIP(hipMemcpy(p->d_items_bp2d, ib.data(), sizeof(int4) * ib.size(), hipMemcpyHostToDevice));
     SIPO_HIP(hipMemcpy(p->d_items_fp2d, ifp.data(), sizeof(int4) * ifp.size(), hipMemcpyHostToDevice));
-    SIPO_HIP(hipMalloc(&p->d_vol_t, p->vol_elems() * p->elem_bytes()));   // [x][y] copy for P
-    SIPO_HIP(hipMalloc(&p->d_items_tr2d, sizeof(int4) * itr.size()));
+    SIPO_TRY(plan_alloc(p, (void **)&p->d_items_tr2d, sizeof(int4) * itr.size()));
     SIPO_HIP(hipMemcpy(p->d_items_tr2d, itr.data(), sizeof(int4) * itr.size(), hipMemcpyHostToDevice));
     p->n_items_bp2d = (int)ib.size();
     p->n_items_fp2d = (int)ifp.size();
