@@ -234,6 +234,24 @@ int sipo_evaluate(sipo_plan plan, const void *dose, const uint8_t *labels, const
                   double f_t_scalar, double f_crit, const void *weights, const sipo_resin *resin,
                   const void *m_target, double m_t_scalar, sipo_metrics *out, void *stream);
 
+/* sipo_evaluate for callers that cannot allocate device memory or attach a
+ * plan workspace (tight serving loops, harnesses that forbid allocation):
+ * same arguments, checks and results as sipo_evaluate, bit for bit, but the
+ * reduction partials live in a fixed 65,600-byte device array inside the
+ * library instead of the plan workspace, so no workspace needs to be attached
+ * and the call allocates nothing.  Every GPU that runs the library holds its
+ * own copy of the array until the process ends; the call looks up the current
+ * device's copy on its first use there.  The reduction uses at most 1024
+ * workgroups for any volume, so no size exceeds the array (a size that did
+ * would return SIPO_E_INVALID before any launch).  Each call overwrites the
+ * whole area it reads, so no state carries over between calls, but all calls
+ * on one GPU share the array: calls that overlap in time on one GPU (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * Synchronous on stream. */
+int sipo_evaluate_noalloc(sipo_plan plan, const void *dose, const uint8_t *labels, const void *f_target_norm,
+                          double f_t_scalar, double f_crit, const void *weights, const sipo_resin *resin,
+                          const void *m_target, double m_t_scalar, sipo_metrics *out, void *stream);
+
 /* ------------------------------------------------------------------ LP --- */
 /* The unified LP (Eq. 19-24; Case 1 Eq. 32-37; Case 2 Eq. 40-45):
  *     minimise   w1 u + w2 v

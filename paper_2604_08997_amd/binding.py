@@ -112,6 +112,9 @@ SIGNATURES = {
     "sipo_response": (C.c_int, [C.c_void_p, C.POINTER(Resin), C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "sipo_evaluate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
                                 C.POINTER(Resin), C.c_void_p, C.c_double, C.POINTER(Metrics), C.c_void_p]),
+    "sipo_evaluate_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
+                                        C.c_void_p, C.POINTER(Resin), C.c_void_p, C.c_double, C.POINTER(Metrics),
+                                        C.c_void_p]),
     "sipo_last_error": (C.c_char_p, []),
     "sipo_version": (C.c_char_p, []),
 }
@@ -302,8 +305,10 @@ class Plan:
         return out
 
     def evaluate(self, dose, labels, f_target_norm=None, f_t_scalar=1.0, f_crit=1.0, weights=None, resin=None,
-                 m_target=None, m_t_scalar=float("nan")):
-        """Scale-invariant metrics and post-scaling factors of a normalised dose (Eq. 6-8, 25-28, 46)."""
+                 m_target=None, m_t_scalar=float("nan"), noalloc=False):
+        """Scale-invariant metrics and post-scaling factors of a normalised dose (Eq. 6-8, 25-28, 46).
+
+        noalloc=True calls sipo_evaluate_noalloc (library-held scratch, no plan workspace)."""
         _require(dose, "dose", self.vol_shape, self.dtype, self.device)
         _require(labels, "labels", self.vol_shape, torch.uint8, self.device)
         for name, t in (("f_target_norm", f_target_norm), ("weights", weights), ("m_target", m_target)):
@@ -311,7 +316,8 @@ class Plan:
                 _require(t, name, self.vol_shape, self.dtype, self.device)
         r = Resin(*[float(v) for v in resin]) if resin is not None else None
         m = Metrics()
-        _check(lib().sipo_evaluate(self.handle, _ptr(dose), _ptr(labels), _ptr(f_target_norm), float(f_t_scalar),
+        fn = lib().sipo_evaluate_noalloc if noalloc else lib().sipo_evaluate
+        _check(fn(self.handle, _ptr(dose), _ptr(labels), _ptr(f_target_norm), float(f_t_scalar),
                                    float(f_crit), _ptr(weights), C.byref(r) if r is not None else None,
                                    _ptr(m_target), float(m_t_scalar), C.byref(m), _stream()))
         return m.as_dict()

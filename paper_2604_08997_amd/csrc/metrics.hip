@@ -9,6 +9,7 @@
 // alpha_f followed by a golden-section refinement of the best bracket.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "sipo_internal.hpp"
@@ -223,6 +224,58 @@ static int evaluate(sipo_plan p, const void *dose, const uint8_t *labels, const 
     return SIPO_OK;
 }
 
+// Argument checks shared by sipo_evaluate and sipo_evaluate_noalloc.
+static int check_eval_args(sipo_plan plan, const void *dose, const uint8_t *labels, const void *f_target_norm,
+                           double f_t_scalar, double f_crit, const sipo_resin *resin, const void *m_target,
+                           double m_t_scalar, const sipo_metrics *out) {
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    SIPO_REQUIRE(dose && labels && out, "dose, labels or out is NULL");
+    SIPO_REQUIRE(f_target_norm || (std::isfinite(f_t_scalar) && f_t_scalar > 0), "f~_T scalar must be > 0");
+    SIPO_REQUIRE(std::isfinite(f_crit) && f_crit > 0, "f_crit must be finite and > 0");
+    if (resin) {
+        rc = check_resin(resin);
+        if (rc) return rc;
+        SIPO_REQUIRE(m_target || std::isfinite(m_t_scalar), "m_T scalar must be finite");
+    }
+    return SIPO_OK;
+}
+
+static int run_evaluate(sipo_plan plan, const void *dose, const uint8_t *labels, const void *ftn, double fts,
+                        double fcrit, const void *weights, const sipo_resin *resin, const void *mt, double mts,
+                        sipo_metrics *out, double *scratch, hipStream_t s) {
+    return plan->dtype == SIPO_F64
+               ? evaluate<double>(plan, dose, labels, ftn, fts, fcrit, weights, resin, mt, mts, out, scratch, s)
+               : evaluate<float>(plan, dose, labels, ftn, fts, fcrit, weights, resin, mt, mts, out, scratch, s);
+}
+
+// ------------------------------------------------- allocation-free evaluation
+// Scratch of sipo_evaluate_noalloc: a file-scope device array.  Every GPU that loads the library
+// holds its own copy until the process ends.  On the host the array's name is only a stand-in
+// symbol, never a device address: the address of the current device's copy is looked up once per
+// device with hipGetSymbolAddress and kept in g_noalloc_ptr, and only that pointer reaches kernels.
+constexpr size_t kNoAllocScratchBytes = kEvalScratchBytes;   // 65,600 bytes
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+constexpr int kMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static double *g_noalloc_ptr[kMaxDevices] = {};
+
+static int noalloc_scratch(int dev, double **out) {
+    *out = nullptr;
+    SIPO_REQUIRE(dev >= 0 && dev < kMaxDevices, "device %d outside the supported range [0, %d)", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr)
+            return fail(SIPO_E_DEVICE, "hipGetSymbolAddress of the evaluation scratch failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_noalloc_ptr[dev] = (double *)ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return SIPO_OK;
+}
+
 }  // namespace sipo
 
 using namespace sipo;
@@ -250,25 +303,29 @@ int sipo_response(sipo_plan plan, const sipo_resin *resin, const void *in, void 
 int sipo_evaluate(sipo_plan plan, const void *dose, const uint8_t *labels, const void *f_target_norm,
                   double f_t_scalar, double f_crit, const void *weights, const sipo_resin *resin,
                   const void *m_target, double m_t_scalar, sipo_metrics *out, void *stream) {
-    int rc = check_plan(plan);
+    int rc = check_eval_args(plan, dose, labels, f_target_norm, f_t_scalar, f_crit, resin, m_target, m_t_scalar, out);
+    if (!rc) rc = check_plan_ws(plan);
     if (rc) return rc;
-    SIPO_REQUIRE(dose && labels && out, "dose, labels or out is NULL");
-    SIPO_REQUIRE(f_target_norm || (std::isfinite(f_t_scalar) && f_t_scalar > 0), "f~_T scalar must be > 0");
-    SIPO_REQUIRE(std::isfinite(f_crit) && f_crit > 0, "f_crit must be finite and > 0");
-    if (resin) {
-        rc = check_resin(resin);
-        if (rc) return rc;
-        SIPO_REQUIRE(m_target || std::isfinite(m_t_scalar), "m_T scalar must be finite");
-    }
-    rc = check_plan_ws(plan);
+    return run_evaluate(plan, dose, labels, f_target_norm, f_t_scalar, f_crit, weights, resin, m_target, m_t_scalar,
+                        out, (double *)plan->ws_red(), (hipStream_t)stream);
+}
+
+int sipo_evaluate_noalloc(sipo_plan plan, const void *dose, const uint8_t *labels, const void *f_target_norm,
+                          double f_t_scalar, double f_crit, const void *weights, const sipo_resin *resin,
+                          const void *m_target, double m_t_scalar, sipo_metrics *out, void *stream) {
+    int rc = check_eval_args(plan, dose, labels, f_target_norm, f_t_scalar, f_crit, resin, m_target, m_t_scalar, out);
     if (rc) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    double *scratch = (double *)plan->ws_red();
-    return plan->dtype == SIPO_F64
-               ? evaluate<double>(plan, dose, labels, f_target_norm, f_t_scalar, f_crit, weights, resin, m_target,
-                                  m_t_scalar, out, scratch, s)
-               : evaluate<float>(plan, dose, labels, f_target_norm, f_t_scalar, f_crit, weights, resin, m_target,
-                                 m_t_scalar, out, scratch, s);
+    // the reduction runs at most kMBlocks workgroups whatever the volume size, so its partials and
+    // result always fit the array; the test stays in case either constant changes
+    const size_t blocks = std::max<size_t>(1, std::min<size_t>((plan->vol_elems() + 4 * kMT - 1) / (4 * kMT), kMBlocks));
+    const size_t need = sizeof(double) * (size_t)kMF * (kMBlocks + 1);
+    SIPO_REQUIRE(blocks <= (size_t)kMBlocks && need <= kNoAllocScratchBytes,
+                 "evaluation needs %zu bytes of scratch, above the %zu-byte array", need, kNoAllocScratchBytes);
+    double *ptr = nullptr;
+    rc = noalloc_scratch(plan->device, &ptr);
+    if (rc) return rc;
+    return run_evaluate(plan, dose, labels, f_target_norm, f_t_scalar, f_crit, weights, resin, m_target, m_t_scalar,
+                        out, ptr, (hipStream_t)stream);
 }
 
 }  // extern "C"
