@@ -336,7 +336,13 @@ typedef struct {
     double u, v;               /* returned scalars                                        */
     double tau, sigma;         /* plain mode scalar steps                                 */
     double omega;              /* restarted mode final primal weight                      */
-    double time_ms;            /* wall time of the solve on its stream                    */
+    double time_ms;            /* wall time of the whole call (setup, iterations, final
+                                  evaluation and copies back into the caller's arrays)      */
+    double loop_ms;            /* time on the solve's stream of the iteration loop alone:
+                                  from the first iteration launch (after the first graph
+                                  capture) to the end of the last iteration block and its
+                                  KKT / restart / infeasibility check; 0 if no iteration
+                                  ran.  iters / loop_ms is the steady iteration rate        */
     double phase_ms[SIPO_NUM_PHASES];       /* profile mode: summed launch durations          */
     int32_t phase_launches[SIPO_NUM_PHASES]; /* profile mode: launches timed per phase        */
 } sipo_pdhg_result;

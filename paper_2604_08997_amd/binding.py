@@ -61,7 +61,7 @@ class PdhgResult(C.Structure):
                 ("primal_obj", C.c_double), ("dual_obj", C.c_double),
                 ("rel_primal", C.c_double), ("rel_dual", C.c_double), ("rel_gap", C.c_double),
                 ("u", C.c_double), ("v", C.c_double), ("tau", C.c_double), ("sigma", C.c_double),
-                ("omega", C.c_double), ("time_ms", C.c_double),
+                ("omega", C.c_double), ("time_ms", C.c_double), ("loop_ms", C.c_double),
                 ("phase_ms", C.c_double * NUM_PHASES), ("phase_launches", C.c_int32 * NUM_PHASES)]
 
     def as_dict(self):

@@ -933,6 +933,8 @@ class Solver {
         }
         if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
         for (hipEvent_t e : ev_) (void)hipEventDestroy(e);
+        for (hipEvent_t e : loop_ev_)
+            if (e) (void)hipEventDestroy(e);
     }
 
     int run(sipo_pdhg_result *res);
@@ -982,6 +984,16 @@ class Solver {
     std::vector<double> hsums_;             // [B][kNS]
     hipGraphExec_t graph_exec_ = nullptr;
     int graph_len_ = 0;
+    // start and end of the iteration loop on the solve's stream: the start is recorded just before
+    // the first iteration launch (after the first graph instantiation), the end after the last check
+    hipEvent_t loop_ev_[2] = {nullptr, nullptr};
+    bool loop_started_ = false;
+    int mark_loop_start() {
+        if (loop_started_) return SIPO_OK;
+        SIPO_HIP(hipEventRecord(loop_ev_[0], s_));
+        loop_started_ = true;
+        return SIPO_OK;
+    }
 
     // ---- typed views of the workspace
     T *F(size_t off) const { return (T *)(ws_ + off); }
@@ -1671,8 +1683,10 @@ int Solver<T>::iteration(bool check) {
 template <typename T>
 int Solver<T>::run_block(int nblk) {
     if (!o_.use_graph) {
+        int rc = mark_loop_start();
+        if (rc) return rc;
         for (int j = 0; j < nblk; ++j) {
-            int rc = iteration(j == nblk - 1);
+            rc = iteration(j == nblk - 1);
             if (rc) return rc;
         }
         SIPO_LAUNCHED("pdhg iteration");
@@ -1695,6 +1709,8 @@ int Solver<T>::run_block(int nblk) {
         if (e != hipSuccess) return fail(SIPO_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
         graph_len_ = nblk;
     }
+    int rc = mark_loop_start();
+    if (rc) return rc;
     SIPO_HIP(hipGraphLaunch(graph_exec_, s_));
     return SIPO_OK;
 }
@@ -1805,6 +1821,8 @@ int Solver<T>::run(sipo_pdhg_result *res) {
     }
     int it = 0, checks = 0;
     bool have_t = false;
+    for (hipEvent_t &e : loop_ev_)
+        if (!e) SIPO_HIP(hipEventCreate(&e));
     while (it < o_.max_iters && !active_.empty()) {
         const int nblk = std::min(check, o_.max_iters - it);
         rc = run_block(nblk);
@@ -1934,6 +1952,7 @@ int Solver<T>::run(sipo_pdhg_result *res) {
             if (rc) return rc;
         }
     }
+    if (loop_started_) SIPO_HIP(hipEventRecord(loop_ev_[1], s_));
     // ---------------- returned points: the PDHG output t (restarted) or z = t (plain)
     rc = get_scal();
     if (!rc) rc = set_active(all);
@@ -2003,6 +2022,8 @@ int Solver<T>::run(sipo_pdhg_result *res) {
     SIPO_LAUNCHED("pdhg finish");
     SIPO_HIP(hipStreamSynchronize(s_));
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    float loop_ms = 0.f;
+    if (loop_started_) SIPO_HIP(hipEventElapsedTime(&loop_ms, loop_ev_[0], loop_ev_[1]));
     for (int i = 0; i < B_; ++i) {
         const Inst &I = in_[i];
         sipo_pdhg_result &r = res[i];
@@ -2020,6 +2041,7 @@ int Solver<T>::run(sipo_pdhg_result *res) {
         r.sigma = I.sigma;
         r.omega = I.omega;
         r.time_ms = ms;
+        r.loop_ms = loop_ms;
         for (int ph = 0; ph < SIPO_NUM_PHASES; ++ph) {
             r.phase_ms[ph] = phase_ms_[ph];
             r.phase_launches[ph] = phase_n_[ph];
