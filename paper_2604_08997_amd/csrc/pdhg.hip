@@ -771,6 +771,9 @@ struct Layout {
     bool lohi = false;                          // per-voxel bounds packed (some instance has arrays)
     size_t vol_t_elems = 0;                     // largest 3D instance (the projector's input is per instance)
     std::vector<size_t> pfo, bfo;               // byte offsets of each 3D instance's skip flags
+    std::vector<size_t> pso, pco;               // and of its projector step lists and step counts
+    size_t ps_bytes = 0, pc_bytes = 0, reach_bytes = 0;
+    size_t psteps = 0, pcount = 0, preach = 0;  // their fields; the reach masks of the list builder
     std::vector<size_t> kfo;                    // and of its two blur tile flag arrays (own, reach)
     size_t kf_bytes = 0, kflags = 0;
     size_t pf_bytes = 0, bf_bytes = 0;          // projector / backprojector flag totals
@@ -811,6 +814,8 @@ static Layout make_layout(const sipo_problem *probs, int B) {
     L.voff.resize(B);
     L.pfo.assign(B, 0);
     L.bfo.assign(B, 0);
+    L.pso.assign(B, 0);
+    L.pco.assign(B, 0);
     L.kfo.assign(B, 0);
     const bool b2d = use_batch2d(probs, B);
     for (int i = 0; i < B; ++i) {
@@ -830,6 +835,11 @@ static Layout make_layout(const sipo_problem *probs, int B) {
             // room for the finest slice counts the solve may switch to (8 and 4 slices per thread)
             L.pf_bytes += align_up(p3d_flag_count(p, 8));
             L.bf_bytes += align_up(bp3d_flag_count(p, 4));
+            L.pso[i] = L.ps_bytes;
+            L.pco[i] = L.pc_bytes;
+            L.ps_bytes += align_up(sizeof(int) * p3d_flag_count(p, 8) * (size_t)p->n);
+            L.pc_bytes += align_up(sizeof(int) * p3d_flag_count(p, 8));
+            L.reach_bytes = std::max(L.reach_bytes, p3d_reach_bytes(p, 8));
             L.kfo[i] = L.kf_bytes;
             L.kf_bytes += 2 * align_up(blur_tile_count(p, kMaskBlurZc)) + align_up(vol_t_tile_count(p));
             L.part_s = std::max(L.part_s, (size_t)ns);
@@ -863,6 +873,9 @@ static Layout make_layout(const sipo_problem *probs, int B) {
     L.vol_t = take(vb);
     L.pflags = take(L.pf_bytes);
     L.bflags = take(L.bf_bytes);
+    L.psteps = take(L.ps_bytes);
+    L.pcount = take(L.pc_bytes);
+    L.preach = take(L.reach_bytes);
     L.kflags = take(L.kf_bytes);
     L.ppart = take(L.part_s * L.eb * kMaxSplitP);
     L.bpart = take(L.part_v * L.eb * kMaxSplitB);
@@ -961,6 +974,7 @@ class Solver {
     bool mask_ = false;                     // 3D operators skip workgroups the LP does not read
     std::vector<SplitSpec> psp_, bsp_;      // per instance: splits of the masked 3D operators
     std::vector<char> fused_;               // per instance: primal step fused into the masked projector
+    std::vector<char> steps_;               // per instance: the masked projector walks its step lists
     // the plans' own slices per thread, which the masked operators change and the solver restores
     struct ZcSaved {
         sipo_plan p;
@@ -1255,8 +1269,13 @@ class Solver {
                         fz.w_rho = &scal()[i].w;
                     }
                 }
+                StepList sl;
+                if (m && !steps_.empty() && steps_[i]) {
+                    sl.steps = P<int>(L_.psteps + L_.pso[i]);
+                    sl.count = P<int>(L_.pcount + L_.pco[i]);
+                }
                 rc = launch_project_t(I.p, src, out, s_, m ? U8(L_.pflags) + L_.pfo[i] : nullptr,
-                                      m ? psp_[i] : SplitSpec(), fuse ? &fz : nullptr);
+                                      m ? psp_[i] : SplitSpec(), fuse ? &fz : nullptr, sl);
             }
             if (!rc) rc = mark(SIPO_PHASE_PROJECT);
             if (rc) return rc;
@@ -1443,6 +1462,7 @@ int Solver<T>::setup_common() {
         psp_.assign(B_, SplitSpec());
         bsp_.assign(B_, SplitSpec());
         fused_.assign(B_, 0);
+        steps_.assign(B_, 0);
         auto count_on = [&](size_t flags_off, size_t count) -> long long {
             std::vector<uint8_t> h(count);
             if (count && hipMemcpyAsync(h.data(), U8(flags_off), count, hipMemcpyDeviceToHost, s_) != hipSuccess)
@@ -1472,6 +1492,13 @@ int Solver<T>::setup_common() {
             if (!rc) rc = launch_bp3d_flags(p, U8(L_.lab) + I.voff, U8(L_.bflags) + L_.bfo[i], s_);
             if (!rc) rc = launch_blur_flags(p, U8(L_.lab) + I.voff, blur_own(i), blur_reach(i), s_);
             if (!rc) rc = launch_vol_t_flags(p, blur_reach(i), vol_t_on(i), s_);
+            if (rc) return rc;
+            // the asynchronous projector walks only the march steps that can meet K z (FP32)
+            if (!rc && sizeof(T) == 4 && p3d_steps_ok(p)) {
+                rc = launch_p3d_steps(p, U8(L_.lab) + I.voff, U8(L_.pflags) + L_.pfo[i], U8(L_.preach),
+                                      P<int>(L_.psteps + L_.pso[i]), P<int>(L_.pcount + L_.pco[i]), s_);
+                steps_[i] = 1;
+            }
             if (rc) return rc;
             const long long onp = count_on(L_.pflags + L_.pfo[i], p3d_flag_count(p));
             const long long onb = count_on(L_.bflags + L_.bfo[i], bp3d_flag_count(p));

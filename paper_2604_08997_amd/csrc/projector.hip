@@ -554,14 +554,17 @@ __device__ __forceinline__ void ring_barrier() {
     asm volatile("" ::: "memory");
 }
 
-template <int ZC, int NC, bool PAIR, bool SKIP, int CM>
+constexpr int kMaxListSteps = 1024;   // longest march that step lists serve
+template <int ZC, int NC, bool PAIR, bool SKIP, int CM, bool LIST>
 __global__ void __launch_bounds__(256) project3d_dma_kernel(
     const float *__restrict__ vol_t, float *__restrict__ sino_t, int n, int nz, int nb,
     const double2 *__restrict__ trig, const int *__restrict__ order, const int *__restrict__ partner,
     const int4 *__restrict__ batches, const int2 *__restrict__ ranges, const int2 *__restrict__ vial_rows,
     const float4 *__restrict__ zero16, double h, double inv_ds, float atten, const uint8_t *__restrict__ wg_on,
-    int nsplit, long long split_stride, PrimalFuse fz) {
+    int nsplit, long long split_stride, PrimalFuse fz, const int *__restrict__ step_list,
+    const int *__restrict__ step_cnt) {
     static_assert(CM >= 1 && CM <= kDmaMaxCM, "chunk length");
+    static_assert(!LIST || CM == 1, "step lists walk one step per chunk");
     constexpr int Z4 = ZC / 4, RS = kPCR + 1, SLOTS = CM * Z4 * RS, PER = (SLOTS + 255) / 256;
     constexpr int NR = PAIR ? 2 : 1;
     // three separate arrays, not one indexed ring: the compiler tells LDS variables apart when it
@@ -604,14 +607,29 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     const double du = dsj * inv_ds, dU = dsm * inv_ds, U00 = fma(s00 + 1.0, inv_ds, -0.5);
     const double inv_du = 1.0 / du;
     const float du_t = (float)du, dsj_t = (float)dsj, dtj_t = (float)dtj;
-    const int nch = (n + CM - 1) / CM;
+    // the march: every step in chunks of CM, or (step lists, CM = 1) only the listed steps, in
+    // increasing order; the steps left out stage nothing but zeros
+    // LIST: the workgroup's listed steps are copied to LDS first, so that reading a chunk's step adds
+    // no vector-memory load to the staging waits below (their counts cover the staging copies only)
+    __shared__ int slist[LIST ? kMaxListSteps : 1];
+    int nch = (n + CM - 1) / CM;
+    if constexpr (LIST) {
+        const size_t wgi = ((size_t)tile.y * gridDim.x + tile.x) * nzc + zb;
+        nch = __builtin_amdgcn_readfirstlane(step_cnt[wgi]);
+        for (int i = tid; i < nch; i += 256) slist[i] = step_list[wgi * n + i];
+        __syncthreads();
+    }
+    auto first_step = [&](int k) {
+        if constexpr (LIST) return __builtin_amdgcn_readfirstlane(slist[k]);
+        else return __builtin_amdgcn_readfirstlane(k * CM);
+    };
     const int2 *rg = ranges + ((size_t)tile.y * gridDim.x + tile.x) * n;
     const size_t zrow = (size_t)(nz >> 2), zoff = (size_t)(z0 >> 2);
     const float4 *vol4 = (const float4 *)vol_t;
 
     // staged cross range of chunk k: the union of its steps' ranges (first index, count)
     auto chunk_range = [&](int k) {
-        const int m0 = __builtin_amdgcn_readfirstlane(k * CM);   // uniform: scalar loads
+        const int m0 = first_step(k);   // uniform: scalar loads
         int lo = rg[m0].x, hi = rg[m0].x + rg[m0].y;
 #pragma unroll
         for (int q = 1; q < CM; ++q)
@@ -635,7 +653,7 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     }
     auto issue = [&](float4 *buf, int k) {
         const int2 r = chunk_range(k);
-        const int m0 = __builtin_amdgcn_readfirstlane(k * CM);
+        const int m0 = first_step(k);
         int2 vr[CM];   // vial interval of each step's row (uniform loads)
 #pragma unroll
         for (int q = 0; q < CM; ++q) vr[q] = vial_rows[min(m0 + q, n - 1)];
@@ -664,7 +682,7 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     auto compute = [&](const float4 *buf, int k) {
         const int2 r = chunk_range(k);
         const int j0 = r.x, cr = r.y;
-        const int m0 = k * CM;
+        const int m0 = first_step(k);
         const int mc = min(CM, n - m0);
         for (int mm = 0; mm < mc; ++mm) {
             const int m = m0 + mm;
@@ -1030,6 +1048,7 @@ int plan_build_batches(sipo_plan p, const double2 *trig) {
     SIPO_TRY(plan_alloc(p, (void **)&p->d_vial_rows, sizeof(int2) * vial.size()));
     SIPO_HIP(hipMemcpy(p->d_vial_rows, vial.data(), sizeof(int2) * vial.size(), hipMemcpyHostToDevice));
     SIPO_TRY(plan_alloc(p, (void **)&p->d_zero, 256));
+
     SIPO_HIP(hipMemset(p->d_zero, 0, 256));
     // batch of every view (2 * batch, plus 1 for the opposite view of a walked one), -1 if unwalked
     std::vector<int> vbatch(p->n_angles, -1);
@@ -1162,16 +1181,16 @@ __global__ void k_p3d_reduce(const float4 *__restrict__ part, float4 *__restrict
     }
 }
 
-template <int ZC, int NC, bool PAIR, bool SKIP, int CM>
+template <int ZC, int NC, bool PAIR, bool SKIP, int CM, bool LIST>
 static void fp3d_dma_launch(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
-                            const SplitSpec &sp, const PrimalFuse &fz) {
+                            const SplitSpec &sp, const PrimalFuse &fz, const StepList &sl) {
     const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
     const int ns = sp.parts > 1 ? sp.parts : 1;
     const dim3 grid((p->n_bins + kPB - 1) / kPB, p->n_batches, ((p->nz + ZC - 1) / ZC) * ns);
-    hipLaunchKernelGGL((project3d_dma_kernel<ZC, NC, PAIR, SKIP, CM>), grid, dim3(256), 0, s, (const float *)vol_t,
+    hipLaunchKernelGGL((project3d_dma_kernel<ZC, NC, PAIR, SKIP, CM, LIST>), grid, dim3(256), 0, s, (const float *)vol_t,
                        (float *)(ns > 1 ? sp.partial : sino_t), p->n, p->nz, p->n_bins, p->d_trig, p->d_angle_order,
                        p->d_partner, p->d_batches, p->d_ranges, p->d_vial_rows, (const float4 *)p->d_zero, h, inv_ds,
-                       (float)p->atten, on, ns, (long long)p->sino_elems(), fz);
+                       (float)p->atten, on, ns, (long long)p->sino_elems(), fz, sl.steps, sl.count);
     if (ns > 1) {
         const long long total4 = (long long)p->sino_elems() / 4;
         hipLaunchKernelGGL(k_p3d_reduce, dim3((unsigned)std::min<long long>((total4 + 255) / 256, 16384)), dim3(256), 0,
@@ -1182,41 +1201,49 @@ static void fp3d_dma_launch(sipo_plan p, const void *vol_t, void *sino_t, hipStr
 
 template <int ZC, int NC, bool PAIR, bool SKIP>
 static void fp3d_dma_go(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
-                        const SplitSpec &sp, const PrimalFuse &fz) {
-    // 64 slices stage one step per chunk only: three two-step buffers would not fit in LDS
-    if (ZC > 32 || p->p3d_cm == 1) fp3d_dma_launch<ZC, NC, PAIR, SKIP, 1>(p, vol_t, sino_t, s, on, sp, fz);
-    else fp3d_dma_launch<ZC, NC, PAIR, SKIP, (ZC > 32 ? 1 : kDmaMaxCM)>(p, vol_t, sino_t, s, on, sp, fz);
+                        const SplitSpec &sp, const PrimalFuse &fz, const StepList &sl) {
+    // 64 slices stage one step per chunk only: three two-step buffers would not fit in LDS; step
+    // lists (masked solves: 8 or 16 slices) walk one listed step per chunk
+    if constexpr (ZC <= 16) {
+        if (sl.steps) {
+            fp3d_dma_launch<ZC, NC, PAIR, SKIP, 1, true>(p, vol_t, sino_t, s, on, sp, fz, sl);
+            return;
+        }
+    }
+    if (ZC > 32 || p->p3d_cm == 1) fp3d_dma_launch<ZC, NC, PAIR, SKIP, 1, false>(p, vol_t, sino_t, s, on, sp, fz, sl);
+    else fp3d_dma_launch<ZC, NC, PAIR, SKIP, (ZC > 32 ? 1 : kDmaMaxCM), false>(p, vol_t, sino_t, s, on, sp, fz, sl);
 }
 
 template <int ZC, int NC>
 static void fp3d_dma_nc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
-                        const SplitSpec &sp, const PrimalFuse &fz) {
+                        const SplitSpec &sp, const PrimalFuse &fz, const StepList &sl) {
     if (p->p3d_pair) {
-        if (p->p3d_skip) fp3d_dma_go<ZC, NC, true, true>(p, vol_t, sino_t, s, on, sp, fz);
-        else fp3d_dma_go<ZC, NC, true, false>(p, vol_t, sino_t, s, on, sp, fz);
+        if (p->p3d_skip) fp3d_dma_go<ZC, NC, true, true>(p, vol_t, sino_t, s, on, sp, fz, sl);
+        else fp3d_dma_go<ZC, NC, true, false>(p, vol_t, sino_t, s, on, sp, fz, sl);
     } else {
-        if (p->p3d_skip) fp3d_dma_go<ZC, NC, false, true>(p, vol_t, sino_t, s, on, sp, fz);
-        else fp3d_dma_go<ZC, NC, false, false>(p, vol_t, sino_t, s, on, sp, fz);
+        if (p->p3d_skip) fp3d_dma_go<ZC, NC, false, true>(p, vol_t, sino_t, s, on, sp, fz, sl);
+        else fp3d_dma_go<ZC, NC, false, false>(p, vol_t, sino_t, s, on, sp, fz, sl);
     }
 }
 
 template <typename T, int ZC>
 static int fp3d_zc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
-                   const SplitSpec &sp, const PrimalFuse *fuse) {
+                   const SplitSpec &sp, const PrimalFuse *fuse, const StepList &sl) {
     if constexpr (sizeof(T) == 4 && ZC >= 8) {
         if (p->p3d_dma) {
             if (fuse && sp.parts > 1)
                 return fail(SIPO_E_UNSUPPORTED, "3D projector: the fused primal step needs an unsplit march");
             const PrimalFuse fz = fuse ? *fuse : PrimalFuse();
             switch (p->p3d_nc) {
-                case 3: fp3d_dma_nc<ZC, 3>(p, vol_t, sino_t, s, on, sp, fz); break;
-                case 4: fp3d_dma_nc<ZC, 4>(p, vol_t, sino_t, s, on, sp, fz); break;
-                case 6: fp3d_dma_nc<ZC, 6>(p, vol_t, sino_t, s, on, sp, fz); break;
+                case 3: fp3d_dma_nc<ZC, 3>(p, vol_t, sino_t, s, on, sp, fz, sl); break;
+                case 4: fp3d_dma_nc<ZC, 4>(p, vol_t, sino_t, s, on, sp, fz, sl); break;
+                case 6: fp3d_dma_nc<ZC, 6>(p, vol_t, sino_t, s, on, sp, fz, sl); break;
                 default: return fail(SIPO_E_UNSUPPORTED, "3D projector: unsupported candidate count");
             }
             return SIPO_OK;
         }
     }
+    if (sl.steps) return fail(SIPO_E_UNSUPPORTED, "3D projector: step lists need the asynchronous variant");
     if (fuse) return fail(SIPO_E_UNSUPPORTED, "3D projector: the fused primal step needs the asynchronous variant");
     if constexpr (ZC > 32) {
         return fail(SIPO_E_UNSUPPORTED, "3D projector: %d slices per thread need the asynchronous variant", ZC);
@@ -1233,17 +1260,17 @@ static int fp3d_zc(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, 
 
 template <typename T>
 static int fp3d(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
-                const SplitSpec &sp, const PrimalFuse *fuse) {
+                const SplitSpec &sp, const PrimalFuse *fuse, const StepList &sl) {
     int rc;
     switch (p->p3d_zc) {
-        case 8: rc = fp3d_zc<T, 8>(p, vol_t, sino_t, s, on, sp, fuse); break;
-        case 16: rc = fp3d_zc<T, 16>(p, vol_t, sino_t, s, on, sp, fuse); break;
+        case 8: rc = fp3d_zc<T, 8>(p, vol_t, sino_t, s, on, sp, fuse, sl); break;
+        case 16: rc = fp3d_zc<T, 16>(p, vol_t, sino_t, s, on, sp, fuse, sl); break;
         case 32:
-            if constexpr (sizeof(T) == 4) rc = fp3d_zc<T, 32>(p, vol_t, sino_t, s, on, sp, fuse);
+            if constexpr (sizeof(T) == 4) rc = fp3d_zc<T, 32>(p, vol_t, sino_t, s, on, sp, fuse, sl);
             else rc = fail(SIPO_E_UNSUPPORTED, "3D projector: 32 slices per thread in FP64");
             break;
         case 64:
-            if constexpr (sizeof(T) == 4) rc = fp3d_zc<T, 64>(p, vol_t, sino_t, s, on, sp, fuse);
+            if constexpr (sizeof(T) == 4) rc = fp3d_zc<T, 64>(p, vol_t, sino_t, s, on, sp, fuse, sl);
             else rc = fail(SIPO_E_UNSUPPORTED, "3D projector: 64 slices per thread in FP64");
             break;
         default: return fail(SIPO_E_UNSUPPORTED, "3D projector: %d slices per thread", p->p3d_zc);
@@ -1294,15 +1321,18 @@ int launch_backproject_t(sipo_plan p, const void *sino_t, void *vol, int accumul
 }
 
 int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *wg_on,
-                     const SplitSpec &sp, const PrimalFuse *fuse) {
+                     const SplitSpec &sp, const PrimalFuse *fuse, const StepList &sl) {
     if (fuse && (!p->fast3d() || p->dtype != SIPO_F32 || p->p2d_ok))
         return fail(SIPO_E_UNSUPPORTED, "the fused primal step needs an FP32 3D plan");
+    if (sl.steps && (!p->fast3d() || p->p2d_ok || !wg_on || !p->p3d_dma || p->p3d_zc > 16 || p->n > kMaxListSteps))
+        return fail(SIPO_E_UNSUPPORTED, "projector step lists need a 3D plan with the asynchronous projector at "
+                    "8 or 16 slices per thread, workgroup flags and n <= %d", kMaxListSteps);
     if (p->p2d_ok) return fp2d_plan(p, vol_t, sino_t, 0, s);
     if (!p->fast3d())
         return p->dtype == SIPO_F64 ? fp_slices<double>(p, vol_t, sino_t, 0, s)
                                     : fp_slices<float>(p, vol_t, sino_t, 0, s);
-    return p->dtype == SIPO_F64 ? fp3d<double>(p, vol_t, sino_t, s, wg_on, sp, fuse)
-                                : fp3d<float>(p, vol_t, sino_t, s, wg_on, sp, fuse);
+    return p->dtype == SIPO_F64 ? fp3d<double>(p, vol_t, sino_t, s, wg_on, sp, fuse, sl)
+                                : fp3d<float>(p, vol_t, sino_t, s, wg_on, sp, fuse, sl);
 }
 
 // ------------------------------------------------------- skip flags (LP solves)
@@ -1360,6 +1390,107 @@ __global__ void k_bp3d_flags(const uint8_t *__restrict__ lab, uint8_t *__restric
             for (int ty = ty0; ty <= ty1 && ty < gy; ++ty)
                 for (int tx = tx0; tx <= tx1 && tx < gx; ++tx) flags[((size_t)tz * gy + ty) * gx + tx] = 1;
     }
+}
+
+// ------------------------------------------------------ step lists (LP solves)
+// In an LP solve the projector reads K z, and z vanishes off the labelled voxels, so K z vanishes
+// outside the PSF box around them.  A march step whose staged strip holds no voxel of that box in
+// the workgroup's slices contributes exactly zero to every ray of the workgroup; the step lists leave
+// such steps out.  Built once per solve from the labels: C[zb] marks the columns (x, y) with a
+// labelled voxel in a slice within rz of z chunk zb, R[zb] dilates C by (rx, ry) in the plane.
+
+// C[zb][y][x]: a labelled voxel at (x, y) in slices [zb zc - rz, zb zc + zc - 1 + rz]
+__global__ void k_reach_z(const uint8_t *__restrict__ lab, uint8_t *__restrict__ C, int n, int nz, int zc, int nzc,
+                          int rz) {
+    const long long nn = (long long)n * n, total = nn * nzc;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+        const int zb = (int)(i / nn);
+        const long long xy = i - zb * nn;
+        const int za = max(zb * zc - rz, 0), ze = min(zb * zc + zc - 1 + rz, nz - 1);
+        uint8_t on = 0;
+        for (int z = za; z <= ze && !on; ++z) on = lab[(size_t)z * nn + xy];
+        C[i] = on ? 1 : 0;
+    }
+}
+
+// R[zb][y][x]: C set within (rx, ry) of (x, y)
+__global__ void k_reach_xy(const uint8_t *__restrict__ C, uint8_t *__restrict__ R, int n, int nzc, int rx, int ry) {
+    const long long nn = (long long)n * n, total = nn * nzc;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+        const int zb = (int)(i / nn);
+        const int y = (int)((i - zb * nn) / n), x = (int)(i % n);
+        const uint8_t *c = C + (size_t)zb * nn;
+        uint8_t on = 0;
+        for (int yy = max(y - ry, 0); yy <= min(y + ry, n - 1) && !on; ++yy)
+            for (int xx = max(x - rx, 0); xx <= min(x + rx, n - 1) && !on; ++xx) on = c[(size_t)yy * n + xx];
+        R[i] = on ? 1 : 0;
+    }
+}
+
+// One workgroup per projector workgroup (flag index wg = (batch ngroups + group) nzc + zb): the steps
+// m whose staged cross range [j0, j0 + count) holds a voxel of R[zb], compacted in increasing order.
+__global__ void __launch_bounds__(256) k_p3d_steps(const int4 *__restrict__ batches, const int2 *__restrict__ ranges,
+                                                   const uint8_t *__restrict__ R, const uint8_t *__restrict__ wg_on,
+                                                   int *__restrict__ steps, int *__restrict__ count, int n, int ngroups,
+                                                   int nzc) {
+    __shared__ int wave_cnt[4];
+    const int wg = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int zb = wg % nzc, bg = wg / nzc, group = bg % ngroups, batch = bg / ngroups;
+    if (!wg_on[wg]) {
+        if (tid == 0) count[wg] = 0;
+        return;
+    }
+    const bool xmajor = batches[batch].z != 0;
+    const int2 *rg = ranges + ((size_t)batch * ngroups + group) * n;
+    const uint8_t *Rz = R + (size_t)zb * n * n;
+    int base = 0;
+    for (int m0 = 0; m0 < n; m0 += 256) {
+        const int m = m0 + tid;
+        bool on = false;
+        if (m < n) {
+            const int2 r = rg[m];
+            const int ja = max(r.x, 0), jb = min(r.x + r.y, n);
+            for (int j = ja; j < jb && !on; ++j) on = Rz[xmajor ? (size_t)j * n + m : (size_t)m * n + j] != 0;
+        }
+        const unsigned long long bal = __ballot(on);
+        if (lane == 0) wave_cnt[w] = __popcll(bal);
+        __syncthreads();
+        int off = base;
+        for (int q = 0; q < w; ++q) off += wave_cnt[q];
+        const int tot = wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
+        if (on) steps[(size_t)wg * n + off + __popcll(bal & ((1ull << lane) - 1ull))] = m;
+        base += tot;
+        __syncthreads();
+    }
+    if (tid == 0) count[wg] = base;
+}
+
+bool p3d_steps_ok(sipo_plan p) {
+    return p->fast3d() && p->p3d_dma && p->d_ranges && p->p3d_zc <= 16 && p->n <= kMaxListSteps;
+}
+
+size_t p3d_reach_bytes(sipo_plan p, int zc) {
+    if (zc <= 0) zc = p->p3d_zc;
+    return p->fast3d() ? 2 * (size_t)((p->nz + zc - 1) / zc) * p->n * p->n : 0;
+}
+
+int launch_p3d_steps(sipo_plan p, const uint8_t *labels, const uint8_t *wg_on, uint8_t *reach, int *steps, int *count,
+                     hipStream_t s) {
+    const size_t cnt = p3d_flag_count(p);
+    if (!cnt) return SIPO_OK;
+    if (!p3d_steps_ok(p)) return fail(SIPO_E_UNSUPPORTED, "projector step lists do not apply to this plan");
+    const int zc = p->p3d_zc, nzc = p3d_zchunks(p), ngroups = (p->n_bins + kPB - 1) / kPB;
+    if (cnt != (size_t)p->n_batches * ngroups * nzc) return fail(SIPO_E_INVALID, "projector flag count mismatch");
+    const int rx = p->has_psf ? p->taps_d.rx : 0, ry = p->has_psf ? p->taps_d.ry : 0, rz = p->has_psf ? p->taps_d.rz : 0;
+    uint8_t *C = reach, *R = reach + (size_t)nzc * p->n * p->n;
+    const long long total = (long long)nzc * p->n * p->n;
+    const unsigned g = (unsigned)std::min<long long>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_reach_z, dim3(g), dim3(256), 0, s, labels, C, p->n, p->nz, zc, nzc, rz);
+    hipLaunchKernelGGL(k_reach_xy, dim3(g), dim3(256), 0, s, (const uint8_t *)C, R, p->n, nzc, rx, ry);
+    hipLaunchKernelGGL(k_p3d_steps, dim3((unsigned)cnt), dim3(256), 0, s, (const int4 *)p->d_batches,
+                       (const int2 *)p->d_ranges, (const uint8_t *)R, wg_on, steps, count, p->n, ngroups, nzc);
+    SIPO_LAUNCHED("k_p3d_steps");
+    return SIPO_OK;
 }
 
 int launch_p3d_flags(sipo_plan p, const uint8_t *act_t, uint8_t *flags, hipStream_t s) {

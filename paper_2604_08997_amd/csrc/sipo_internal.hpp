@@ -179,8 +179,25 @@ struct PrimalFuse {
     const uint8_t *act = nullptr;
     const double *tau_fac = nullptr, *w_rho = nullptr;   // w_rho[0] = w, w_rho[1] = rho
 };
+// March-step lists of the asynchronous projector in an LP solve: per projector workgroup (the
+// index of its skip flag), `count` steps listed in `steps` (n entries reserved per workgroup), in
+// increasing order; the workgroup walks those steps only.  nullptr = every step.
+struct StepList {
+    const int *steps = nullptr;
+    const int *count = nullptr;
+};
 int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *wg_on = nullptr,
-                     const SplitSpec &sp = SplitSpec(), const PrimalFuse *fuse = nullptr);
+                     const SplitSpec &sp = SplitSpec(), const PrimalFuse *fuse = nullptr,
+                     const StepList &sl = StepList());
+// Step lists of an LP solve: a workgroup of the projector (at the plan's current slices per thread)
+// lists the march steps whose staged strip holds a voxel within the PSF box of a labelled voxel in
+// one of its slices (K z vanishes elsewhere, since z does off the labelled voxels); workgroups whose
+// flag is off list none.  labels: [z][y][x]; reach: scratch of p3d_reach_bytes; steps: int
+// [p3d_flag_count][n]; count: int [p3d_flag_count].  Needs the asynchronous projector's ranges.
+bool p3d_steps_ok(sipo_plan p);   // the plan's projector (current tuning) can walk step lists
+size_t p3d_reach_bytes(sipo_plan p, int zc = 0);
+int launch_p3d_steps(sipo_plan p, const uint8_t *labels, const uint8_t *wg_on, uint8_t *reach, int *steps, int *count,
+                     hipStream_t s);
 // projector workgroups / backprojector tiles of a fast3d plan (else 0) at zc slices per thread
 // (zc <= 0: the plan's current tuning)
 size_t p3d_flag_count(sipo_plan p, int zc = 0);
