@@ -143,11 +143,11 @@ def recorded_traffic(kernel):
 
 def in_solve_projector(tuning):
     """Name of the projector kernel an LP solve of the 256^3 x 360 workload runs (view pairs, 3
-    candidates per step; the masked operators use at most 16 slices per thread)."""
+    candidates per step; the masked operators use at most 16 slices per thread and, with the
+    asynchronous projector, walk their step lists one step per chunk)."""
     zc = min(tuning["p3d_zc"], 16)
     if tuning["p3d_dma"]:
-        return (f"project3d_dma_kernel<{zc}, 3, true, {'true' if tuning['p3d_skip'] else 'false'}, "
-                f"{tuning['p3d_cm']}>")
+        return f"project3d_dma_kernel<{zc}, 3, true, {'true' if tuning['p3d_skip'] else 'false'}, 1, true>"
     return f"project3d_kernel<float, {zc}, 3, true>"
 
 
