@@ -338,6 +338,22 @@ def version():
 GENERAL, CASE1, CASE2 = 0, 1, 2
 
 
+def target_levels(plan, f_target, labels):
+    """Problem set-up (Sec. 2.5, 3.3) on the host: the smallest gel value of f_T, and a function
+    c -> device array c f_T (the per-voxel bounds of a graded target) or None when f_T takes a
+    single value on the gel (then scalar bounds are exact)."""
+    import numpy as np
+    f = f_target.detach().cpu().numpy()
+    gel = labels.cpu().numpy() == 2
+    if not gel.any():
+        return 1.0, lambda c: None
+    vals = f[gel].astype(np.float64)
+    fmin = float(vals.min())
+    if float(vals.max()) == fmin:
+        return fmin, lambda c: None
+    return fmin, lambda c: torch.as_tensor(c * f.astype(np.float64), dtype=plan.dtype, device=plan.device)
+
+
 class LP:
     """One LP instance (Eq. 19-24 / 32-37 / 40-45) with its device state.
 
@@ -364,19 +380,25 @@ class LP:
               f_min=None):
         labels = plan.regions(f_target, band_width)
         act = plan.active_rays(f_target)
-        if f_min is None:
-            gel = labels == 2
-            f_min = float(f_target[gel].min().item()) if bool(gel.any()) else 1.0
+        fmin, level = target_levels(plan, f_target, labels)
+        if f_min is not None:
+            fmin = float(f_min)
+        # graded targets carry per-voxel bounds (f_T / f_crit on the gel); single-level ones scalars
         if case == GENERAL:
-            fc = f_min
-            return cls(plan, labels, act, case, 1, 1, w1, w2, 1.0, 1.0, 1.0, f_crit=fc)
-        if case == CASE1:
-            fc = tol_lo * f_min
-            return cls(plan, labels, act, case, 1, 0, 1.0, 0.0, 1.0, tol_lo * f_min / fc, tol_hi * f_min / fc,
+            fc = fmin
+            lo = hi = level(1.0 / fc)
+            return cls(plan, labels, act, case, 1, 1, w1, w2, 1.0, fmin / fc, fmin / fc, lo_arr=lo, hi_arr=hi,
                        f_crit=fc)
+        if case == CASE1:
+            fc = tol_lo * fmin
+            lo, hi = level(tol_lo / fc), level(tol_hi / fc)
+            return cls(plan, labels, act, case, 1, 0, 1.0, 0.0, 1.0, tol_lo * fmin / fc, tol_hi * fmin / fc,
+                       lo_arr=lo, hi_arr=hi, f_crit=fc)
         if case == CASE2:
-            fc = cap * f_min
-            return cls(plan, labels, act, case, 0, 1, 0.0, 1.0, 1.0, f_min / fc, f_min / fc, f_crit=fc)
+            fc = cap * fmin
+            lo = hi = level(1.0 / fc)
+            return cls(plan, labels, act, case, 0, 1, 0.0, 1.0, 1.0, fmin / fc, fmin / fc, lo_arr=lo, hi_arr=hi,
+                       f_crit=fc)
         raise ValueError(f"unknown case {case}")
 
     def c_struct(self, want_dose=False):

@@ -25,19 +25,23 @@ import time
 from . import binding as _b
 
 
-def _f_min(plan, f_target, labels):
-    gel = labels == 2
-    return float(f_target[gel].min().item()) if bool(gel.any()) else 1.0
+def _levels(plan, f_target, labels):
+    """min_gel f_T and the general-units normalised target f~_T = f_T / min_gel f_T as a per-voxel
+    array (graded targets) or None (single-level targets, where f~_T = 1 on the gel)."""
+    fmin, level = _b.target_levels(plan, f_target, labels)
+    return fmin, level(1.0 / fmin)
 
 
-def h_min_lp(plan, labels, act, f_min):
-    """General LP with w = (1, 0): min u s.t. D <= u on band, D >= 1 on gel (v free, unpriced)."""
-    return _b.LP(plan, labels, act, _b.GENERAL, 1, 1, 1.0, 0.0, 1.0, 1.0, 1.0, f_crit=f_min)
+def h_min_lp(plan, labels, act, f_min, ftn=None):
+    """General LP with w = (1, 0): min u s.t. D <= u on band, D >= f~_T on gel (v free, unpriced)."""
+    return _b.LP(plan, labels, act, _b.GENERAL, 1, 1, 1.0, 0.0, 1.0, 1.0, 1.0, lo_arr=ftn, hi_arr=ftn, f_crit=f_min)
 
 
-def case2_lp(plan, labels, act, f_min, cap):
-    """Case 2 (Eq. 40-45) at band threshold ``cap`` in general units: band cap h = cap, f~_T = 1, w = (0, 1)."""
-    return _b.LP(plan, labels, act, _b.CASE2, 0, 1, 0.0, 1.0, float(cap), 1.0, 1.0, f_crit=f_min)
+def case2_lp(plan, labels, act, f_min, cap, ftn=None):
+    """Case 2 (Eq. 40-45) at band threshold ``cap`` in general units: band cap h = cap, D = f~_T on the
+    gel's lower rows and D <= v f~_T on its upper rows, w = (0, 1)."""
+    return _b.LP(plan, labels, act, _b.CASE2, 0, 1, 0.0, 1.0, float(cap), 1.0, 1.0, lo_arr=ftn, hi_arr=ftn,
+                 f_crit=f_min)
 
 
 def transfer_cap(u1, margin):
@@ -45,10 +49,10 @@ def transfer_cap(u1, margin):
     return float(u1) * (1.0 + float(margin))
 
 
-def _metrics(lp, f_min):
+def _metrics(lp, f_min, ftn=None):
     if lp.dose is None:
         return None
-    return lp.plan.evaluate(lp.dose, lp.labels, f_t_scalar=1.0, f_crit=f_min)
+    return lp.plan.evaluate(lp.dose, lp.labels, f_target_norm=ftn, f_t_scalar=1.0, f_crit=f_min)
 
 
 def two_stage(items, band_width=10.0, tol_lo=0.9, tol_hi=1.0, margin=0.02, opts=None, warm=True,
@@ -68,14 +72,16 @@ def two_stage(items, band_width=10.0, tol_lo=0.9, tol_hi=1.0, margin=0.02, opts=
     dict, receives the wall-clock seconds of each stage's batched solve.
     """
     opts = _b.pdhg_options() if opts is None else opts
-    lp1s, hms, fmins = [], [], []
+    lp1s, hms, fmins, ftns = [], [], [], []
     for plan, f in items:
         lp1 = _b.LP.build(plan, f, _b.CASE1, band_width=band_width, tol_lo=tol_lo, tol_hi=tol_hi)
         fmin = lp1.f_crit / tol_lo
+        ftn = lp1.lo_arr          # f~_T per voxel for graded targets (Case 1's L is f_T / min f_T)
         lp1s.append(lp1)
         fmins.append(fmin)
+        ftns.append(ftn)
         if with_h_min:
-            hms.append(h_min_lp(plan, lp1.labels, lp1.act, fmin))
+            hms.append(h_min_lp(plan, lp1.labels, lp1.act, fmin, ftn))
     t0 = time.perf_counter()
     res_a = _b.solve(lp1s + hms, opts, workspace=workspace)
     if times is not None:
@@ -86,11 +92,12 @@ def two_stage(items, band_width=10.0, tol_lo=0.9, tol_hi=1.0, margin=0.02, opts=
     for k, (lp1, r1, fmin) in enumerate(zip(lp1s, res1, fmins)):
         d = {"stage1": r1, "lp1": lp1, "f_min": fmin, "u1": math.nan, "cap": math.nan, "stage2": None,
              "lp2": None, "h_min": resh[k]["u"] if with_h_min and resh[k]["status_name"] == "optimal" else math.nan,
-             "h_min_result": resh[k] if with_h_min else None, "metrics1": _metrics(lp1, fmin), "metrics2": None}
+             "h_min_result": resh[k] if with_h_min else None, "metrics1": _metrics(lp1, fmin, ftns[k]),
+             "metrics2": None, "ftn": ftns[k]}
         if r1["status_name"] == "optimal":
             d["u1"] = r1["u"]
             d["cap"] = transfer_cap(r1["u"], margin)
-            lp2 = case2_lp(lp1.plan, lp1.labels, lp1.act, fmin, d["cap"])
+            lp2 = case2_lp(lp1.plan, lp1.labels, lp1.act, fmin, d["cap"], ftns[k])
             if warm:
                 lp2.y.copy_(lp1.y)
                 lp2.v0 = tol_hi / tol_lo
@@ -104,7 +111,7 @@ def two_stage(items, band_width=10.0, tol_lo=0.9, tol_hi=1.0, margin=0.02, opts=
             times["stage2"] = time.perf_counter() - t0
         for (k, lp2), r2 in zip(lp2s, res_b):
             out[k]["stage2"] = r2
-            out[k]["metrics2"] = _metrics(lp2, out[k]["f_min"])
+            out[k]["metrics2"] = _metrics(lp2, out[k]["f_min"], out[k]["ftn"])
     return out
 
 
@@ -122,14 +129,16 @@ def sweep(plan, f_target, weights, band_widths, opts=None, f_min=None, workspace
     lps, keys = [], []
     for bw in band_widths:
         labels = plan.regions(f_target, bw)
-        fmin = _f_min(plan, f_target, labels) if f_min is None else float(f_min)
+        fmin, ftn = _levels(plan, f_target, labels)
+        if f_min is not None:
+            fmin = float(f_min)
         for w1, w2 in weights:
-            lps.append(_b.LP(plan, labels, act, _b.GENERAL, 1, 1, float(w1), float(w2), 1.0, 1.0, 1.0,
-                             f_crit=fmin))
-            keys.append((math.inf if bw is None else bw, float(w1), float(w2), fmin))
+            lps.append(_b.LP(plan, labels, act, _b.GENERAL, 1, 1, float(w1), float(w2), 1.0, 1.0, 1.0, lo_arr=ftn,
+                             hi_arr=ftn, f_crit=fmin))
+            keys.append((math.inf if bw is None else bw, float(w1), float(w2), fmin, ftn))
     res = _b.solve(lps, opts, workspace=workspace)
-    return [{"band_width": bw, "w1": w1, "w2": w2, "result": r, "lp": lp, "metrics": _metrics(lp, fmin)}
-            for (bw, w1, w2, fmin), r, lp in zip(keys, res, lps)]
+    return [{"band_width": bw, "w1": w1, "w2": w2, "result": r, "lp": lp, "metrics": _metrics(lp, fmin, ftn)}
+            for (bw, w1, w2, fmin, ftn), r, lp in zip(keys, res, lps)]
 
 
 def case2_screened(items, caps, band_width=10.0, opts=None, h_min_opts=None, workspace=None, times=None):
@@ -148,20 +157,21 @@ def case2_screened(items, caps, band_width=10.0, opts=None, h_min_opts=None, wor
     """
     opts = _b.pdhg_options() if opts is None else opts
     h_min_opts = opts if h_min_opts is None else h_min_opts
-    hms, fmins = [], []
+    hms, fmins, ftns = [], [], []
     for plan, f in items:
         labels = plan.regions(f, band_width)
         act = plan.active_rays(f)
-        fmin = _f_min(plan, f, labels)
-        hms.append(h_min_lp(plan, labels, act, fmin))
+        fmin, ftn = _levels(plan, f, labels)
+        hms.append(h_min_lp(plan, labels, act, fmin, ftn))
         fmins.append(fmin)
+        ftns.append(ftn)
     t0 = time.perf_counter()
     rh = _b.solve(hms, h_min_opts, want_dose=False, workspace=workspace)
     if times is not None:
         times["h_min"] = time.perf_counter() - t0
     lps, screened = [], []
-    for hm, r, fmin, cap in zip(hms, rh, fmins, caps):
-        lp = case2_lp(hm.plan, hm.labels, hm.act, fmin, cap)
+    for hm, r, fmin, cap, ftn in zip(hms, rh, fmins, caps, ftns):
+        lp = case2_lp(hm.plan, hm.labels, hm.act, fmin, cap, ftn)
         below = r["status_name"] in ("optimal", "iter_limit") and float(cap) < r["u"]
         if below:
             lp.lam_up.copy_(hm.lam_up)

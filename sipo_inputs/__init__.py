@@ -26,7 +26,7 @@ import numpy as np
 
 __all__ = [
     "rng", "angles_uniform", "ellipses_target", "annulus_disks_target",
-    "ellipsoids_target", "lattice_target", "uniform_field", "signed_field",
+    "ellipsoids_target", "lattice_target", "uniform_field", "signed_field", "graded_levels",
     "BatchInstance", "batch_instances", "CONFIGS", "Config",
 ]
 
@@ -203,6 +203,29 @@ def lattice_target(n: int, seed: int, nz: int | None = None) -> np.ndarray:
                     _paint(inside, n, nz, np.minimum(p0, p1) - rad, np.maximum(p0, p1) + rad, cyl)
     inside &= _vial(n, nz)
     return inside.astype(np.float64)
+
+
+def graded_levels(shape, seed: int, lo: float = 0.5, hi: float = 1.0, waves: int = 4) -> np.ndarray:
+    """Smooth seeded field with values in [lo, hi] over a volume [nz][n][n] on [-1, 1]^3.
+
+    A grayscale target is a binary target times this field (Sec. 3.3 designs for
+    graded in-part doses): the mean of ``waves`` plane cosines with directions
+    uniform on the sphere, wave numbers U[2, 6] and phases U[0, 2 pi), mapped
+    affinely from [-1, 1] onto [lo, hi].
+    """
+    g = rng(seed)
+    nz, ny, nx = shape
+    z = _centres(nz) if nz > 1 else np.zeros(1)
+    Z, Y, X = np.meshgrid(z, _centres(ny), _centres(nx), indexing="ij")
+    acc = np.zeros(shape)
+    for _ in range(waves):
+        d = g.normal(size=3)
+        d /= np.linalg.norm(d)
+        k = g.uniform(2.0, 6.0)
+        ph = g.uniform(0.0, 2.0 * math.pi)
+        acc += np.cos(k * (d[0] * X + d[1] * Y + d[2] * Z) + ph)
+    acc /= waves
+    return lo + (hi - lo) * 0.5 * (acc + 1.0)
 
 
 def uniform_field(shape, seed: int) -> np.ndarray:
