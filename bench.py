@@ -58,8 +58,8 @@ def parse():
                     help="skip the cold solve to relative KKT 1e-4 (time_to_1e-4, about 95 s at 256^3)")
     ap.add_argument("--ttk-iters", type=int, default=200000, help="iteration budget of the time-to-1e-4 solve")
     ap.add_argument("--batch", type=int, default=8,
-                    help="instances of the uneven 2D batch (seeds 2000..) for the batched-vs-plain time to 1e-4 "
-                         "(0 = skip)")
+                    help="instances of the uneven 2D batch (seeds 2000..) for the batched-vs-plain time to 1e-4, "
+                         "cold and h_min-screened (0 = skip)")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched-vs-plain comparison")
     ap.add_argument("--two-stage", type=int, default=0,
                     help="run only the two-stage Case 1 -> Case 2 workflow on this many instances of the uneven "
@@ -198,60 +198,129 @@ def cpu_baseline(n, angles, slices):
                       f"value = measured slice-iterations per second / {n} slices"}
 
 
-def batch_vs_plain(count, dev, max_iters=20000):
-    """Time to relative KKT 1e-4 (or a checked infeasibility certificate) of the first
-    ``count`` instances of the uneven 2D batch: one batched, graph-captured solve against
-    the same solver run instance by instance (also graph-captured), on the same GPU."""
+def batch_vs_plain(count, dev, max_iters=40000, infeas_tol=1e-4, h_min_tol=1e-5):
+    """Time to relative KKT 1e-4 (or a checked infeasibility certificate) of the first ``count``
+    instances of the uneven 2D batch, one batched graph-captured solve against the same solver run
+    instance by instance (also graph-captured), on the same GPU, by two routes:
+
+    * cold: every instance as posed (Case 1 [0.9, 1.0] or Case 2 cap 0.7) from zero;
+    * screened: the Case-2 instances first solve their h_min LP (the smallest feasible band cap,
+      general LP with w = (1, 0)); a Case 2 whose cap lies below it starts from the h_min
+      multipliers, which the solver's iteration-0 Farkas test accepts as its certificate.  In the
+      batched route the h_min LPs form one batch and all instances the second; one by one, each
+      Case 2 runs its h_min LP and then itself.
+
+    The Farkas tolerance equals the KKT tolerance (1e-4, relative to the ray's dual objective)."""
     import torch
     import paper_2604_08997_amd as sipo
+    from paper_2604_08997_amd import workflow
     from sipo_inputs import batch_instances, angles_uniform
+    from collections import Counter
     insts = batch_instances(count, 2000)
-    lps = []
+    items, cold = [], []
     for b in insts:
         plan = sipo.Plan(b.n, list(angles_uniform(b.n_angles)), dtype=torch.float32, device=dev)
-        lps.append(sipo.LP.build(plan, torch.as_tensor(b.target, dtype=torch.float32, device=dev), b.case,
-                                 band_width=10.0, f_min=1.0))
-    opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=max_iters, tol=1e-4, infeas_tol=1e-5, use_graph=1)
+        f = torch.as_tensor(b.target, dtype=torch.float32, device=dev)
+        items.append((plan, f, b.case))
+        cold.append(sipo.LP.build(plan, f, b.case, band_width=10.0, f_min=1.0))
+    opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=max_iters, tol=1e-4, infeas_tol=infeas_tol, use_graph=1)
+    h_opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=max_iters, tol=h_min_tol, use_graph=1)
     stream = torch.cuda.Stream()
+    keys = ("status", "iters", "restarts", "primal_obj", "dual_obj", "rel_primal", "rel_dual", "rel_gap", "u", "v")
 
-    def reset():
+    def reset(lps):
         for lp in lps:
             lp.y.zero_(); lp.lam_up.zero_(); lp.lam_lo.zero_()
         torch.cuda.synchronize()
 
-    reset()
-    with torch.cuda.stream(stream):
-        t0 = time.perf_counter()
-        rb = sipo.solve(lps, opts, want_dose=False)
-        stream.synchronize()
-        t_batch = time.perf_counter() - t0
-    from collections import Counter
-    print(f"[bench] batch of {count}: batched {t_batch:.2f} s, "
-          f"{dict(Counter(r['status_name'] for r in rb))}", file=sys.stderr, flush=True)
-    reset()
-    rp = []
-    with torch.cuda.stream(stream):
-        t0 = time.perf_counter()
-        for k, lp in enumerate(lps):
-            rp.append(sipo.solve(lp, opts, want_dose=False))
-            print(f"[bench] one by one: instance {k} {rp[-1]['status_name']} after {rp[-1]['iters']} iterations",
+    def timed(fn):
+        with torch.cuda.stream(stream):
+            t0 = time.perf_counter()
+            out = fn()
+            stream.synchronize()
+        return out, time.perf_counter() - t0
+
+    # ---- cold route
+    reset(cold)
+    rb, t_batch = timed(lambda: sipo.solve(cold, opts, want_dose=False))
+    print(f"[bench] batch of {count}, cold: batched {t_batch:.2f} s, {dict(Counter(r['status_name'] for r in rb))}",
+          file=sys.stderr, flush=True)
+    reset(cold)
+
+    def one_by_one():
+        out = []
+        for k, lp in enumerate(cold):
+            out.append(sipo.solve(lp, opts, want_dose=False))
+            print(f"[bench] cold one by one: instance {k} {out[-1]['status_name']} after {out[-1]['iters']} iterations",
                   file=sys.stderr, flush=True)
-        stream.synchronize()
-        t_plain = time.perf_counter() - t0
-    print(f"[bench] batch of {count}: one by one {t_plain:.2f} s", file=sys.stderr, flush=True)
-    keys = ("status", "iters", "restarts", "primal_obj", "dual_obj", "rel_primal", "rel_dual", "rel_gap", "u", "v")
+        return out
+    rp, t_plain = timed(one_by_one)
+    print(f"[bench] batch of {count}, cold: one by one {t_plain:.2f} s", file=sys.stderr, flush=True)
     same = all(all(a[k] == b[k] for k in keys) for a, b in zip(rb, rp))
-    samples = sum(float(b.n) * b.n * b.n_angles for b in insts)
     capped = [k for k, r in enumerate(rb) if r["status_name"] not in ("optimal", "infeasible")]
+
+    # ---- screened route (Case 2 in general units: band cap 0.7, f~_T = 1)
+    def screened_lps():
+        hms, finals = {}, []
+        for k, (plan, f, case) in enumerate(items):
+            lab, act = cold[k].labels, cold[k].act
+            if case == sipo.CASE2:
+                hms[k] = workflow.h_min_lp(plan, lab, act, 1.0)
+                finals.append(workflow.case2_lp(plan, lab, act, 1.0, 0.7))
+            else:
+                finals.append(sipo.LP.build(plan, f, case, band_width=10.0, f_min=1.0))
+        return hms, finals
+
+    def warm(lp, hm, r):
+        if r["status_name"] in ("optimal", "iter_limit") and 0.7 < r["u"]:
+            lp.lam_up.copy_(hm.lam_up)
+            lp.lam_lo.copy_(hm.lam_lo)
+
+    hms, finals = screened_lps()
+
+    def screened_batched():
+        ks = sorted(hms)
+        rh = sipo.solve([hms[k] for k in ks], h_opts, want_dose=False) if ks else []
+        for k, r in zip(ks, rh):
+            warm(finals[k], hms[k], r)
+        return sipo.solve(finals, opts, want_dose=False), dict(zip(ks, rh))
+    (sb, sbh), ts_batch = timed(screened_batched)
+    print(f"[bench] batch of {count}, screened: batched {ts_batch:.2f} s, "
+          f"{dict(Counter(r['status_name'] for r in sb))}", file=sys.stderr, flush=True)
+    hms, finals = screened_lps()
+
+    def screened_one_by_one():
+        out, outh = [], {}
+        for k, lp in enumerate(finals):
+            if k in hms:
+                outh[k] = sipo.solve(hms[k], h_opts, want_dose=False)
+                warm(lp, hms[k], outh[k])
+            out.append(sipo.solve(lp, opts, want_dose=False))
+            print(f"[bench] screened one by one: instance {k} {out[-1]['status_name']} after {out[-1]['iters']} "
+                  f"iterations", file=sys.stderr, flush=True)
+        return out, outh
+    (sp, sph), ts_plain = timed(screened_one_by_one)
+    print(f"[bench] batch of {count}, screened: one by one {ts_plain:.2f} s", file=sys.stderr, flush=True)
+    s_same = all(all(a[k] == b[k] for k in keys) for a, b in zip(sb, sp)) and \
+        all(all(sbh[k][q] == sph[k][q] for q in keys) for k in sbh)
+    s_capped = [k for k, r in enumerate(sb) if r["status_name"] not in ("optimal", "infeasible")]
+    samples = sum(float(b.n) * b.n * b.n_angles for b in insts)
     return {"instances": count, "seeds": f"2000-{2000 + count - 1}", "samples_per_application": samples,
-            "batched_s": round(t_batch, 3), "plain_s": round(t_plain, 3),
-            # a time to 1e-4 only when every instance ended optimal or with a certificate
-            "speedup": round(t_plain / t_batch, 3) if not capped else None,
-            "speedup_with_capped_instances": round(t_plain / t_batch, 3),
-            "status": dict(Counter(r["status_name"] for r in rb)), "max_iters": max_iters,
-            "capped_instances": capped,
-            "max_iters_used": max(r["iters"] for r in rb),
-            "per_instance_results_identical": same, "compared_fields": list(keys)}
+            "max_iters": max_iters, "infeas_tol": infeas_tol, "compared_fields": list(keys),
+            "cold": {"batched_s": round(t_batch, 3), "plain_s": round(t_plain, 3),
+                     # a time to 1e-4 only when every instance ended optimal or with a certificate
+                     "speedup": round(t_plain / t_batch, 3) if not capped else None,
+                     "speedup_with_capped_instances": round(t_plain / t_batch, 3),
+                     "status": dict(Counter(r["status_name"] for r in rb)), "capped_instances": capped,
+                     "iters": [r["iters"] for r in rb], "per_instance_results_identical": same},
+            "screened": {"batched_s": round(ts_batch, 3), "plain_s": round(ts_plain, 3),
+                         "speedup": round(ts_plain / ts_batch, 3) if not s_capped else None,
+                         "status": dict(Counter(r["status_name"] for r in sb)), "capped_instances": s_capped,
+                         "h_min_tol": h_min_tol,
+                         "h_min": {str(k): round(r["u"], 6) for k, r in sbh.items()},
+                         "certified_at_iteration_0": sum(1 for r in sb if r["status_name"] == "infeasible"
+                                                         and r["iters"] == 0),
+                         "iters": [r["iters"] for r in sb], "per_instance_results_identical": s_same}}
 
 
 def two_stage_batch(count, dev, margin, max_iters=20000):

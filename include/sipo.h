@@ -362,7 +362,14 @@ size_t sipo_pdhg_workspace_size(const sipo_problem *probs, int32_t n_probs,
  * min u s.t. D <= u on band and D >= L on gel, handed to a Case-2 LP whose
  * band cap is below that minimum), the instance returns at once with status
  * SIPO_PRIMAL_INFEASIBLE, iters = 0, that ray as its certificate and y and the
- * scalars as passed in.  Zero multipliers (a cold start) never pass.
+ * scalars as passed in.  Zero multipliers (a cold start) never pass.  At every
+ * check the same test runs, in this order, on max(d, 0) for d = lambda(t) -
+ * lambda(z) (one step), lambda(t) - lambda(t at the previous check), lambda(t)
+ * itself, and lambda(t) - lambda at the last restart; the first that passes is
+ * returned as the certificate.  The test normalises the ray to unit dual
+ * objective and accepts it when its reduced-cost violations (the most
+ * negative P K z on active rays; the band, resp. weighted gel, sum of a free
+ * u, resp. v) are at most infeas_tol.
  * Returns after the stream has finished. */
 int sipo_pdhg_solve(const sipo_problem *probs, int32_t n_probs, const sipo_pdhg_options *opts,
                     void *workspace, size_t ws_bytes, sipo_pdhg_result *results, void *stream);

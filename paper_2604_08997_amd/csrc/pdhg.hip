@@ -607,8 +607,8 @@ __global__ void k_kkt_ray(const T *q, const T *y, const uint8_t *act, const Seg 
     block_sums(acc, partials);
 }
 
-// Farkas candidate d = max(a - b, 0) on the regions of the flagged instances -> z_d;
-// [0] sum L d3, [1] sum_band d1, [2] sum_gel U d2, [3] ||d||_1.
+// Farkas candidate d = max(a - b, 0) on the regions of the flagged instances -> z_d (b = NULL: the
+// candidate is max(a, 0) itself); [0] sum L d3, [1] sum_band d1, [2] sum_gel U d2, [3] ||d||_1.
 template <typename T>
 __global__ void k_ray_candidate(const T *alu, const T *all, const T *blu, const T *bll, T *zd, const uint8_t *lab,
                                 const T *lo, const T *hi, const InstC *insts, const Seg *segs, double *partials) {
@@ -620,14 +620,14 @@ __global__ void k_ray_candidate(const T *alu, const T *all, const T *blu, const 
             const uint8_t L = lab[i];
             T zz = 0;
             if (L) {
-                T a = alu[i] - blu[i];
+                T a = alu[i] - (blu ? blu[i] : (T)0);
                 a = a > (T)0 ? a : (T)0;
                 zz = a;
                 acc[3] += (double)a;
                 if (L == 1) {
                     acc[1] += (double)a;
                 } else {
-                    T b = all[i] - bll[i];
+                    T b = all[i] - (bll ? bll[i] : (T)0);
                     b = b > (T)0 ? b : (T)0;
                     zz = a - b;
                     acc[0] += (double)ld_or(lo, i, c.lo_s) * (double)b;
@@ -641,19 +641,16 @@ __global__ void k_ray_candidate(const T *alu, const T *all, const T *blu, const 
     block_sums(acc, partials);
 }
 
-// Certificate output of the flagged instances: max(a - b, 0) on the regions with b the
-// pre-step (sel 0) or snapshot (sel 1) lambda.
+// Certificate output of the flagged instances: max(a - b, 0) on the regions (b = NULL: max(a, 0)).
 template <typename T>
-__global__ void k_certificate(T *olu, T *oll, const T *alu, const T *all, const T *blu0, const T *bll0,
-                              const T *blu1, const T *bll1, const uint8_t *lab, const InstC *insts, const Seg *segs) {
+__global__ void k_certificate(T *olu, T *oll, const T *alu, const T *all, const T *blu, const T *bll,
+                              const uint8_t *lab, const InstC *insts, const Seg *segs) {
     const InstC &ic = insts[segs[blockIdx.x].inst];
     if (!ic.flag) return;
-    const T *blu = ic.sel ? blu1 : blu0;
-    const T *bll = ic.sel ? bll1 : bll0;
     SEG_LOOP(i) {
         const uint8_t L = lab[i];
-        T a = L ? alu[i] - blu[i] : (T)0;
-        T b = (L == 2) ? all[i] - bll[i] : (T)0;
+        T a = L ? alu[i] - (blu ? blu[i] : (T)0) : (T)0;
+        T b = (L == 2) ? all[i] - (bll ? bll[i] : (T)0) : (T)0;
         olu[i] = a > (T)0 ? a : (T)0;
         oll[i] = b > (T)0 ? b : (T)0;
     }
@@ -791,6 +788,8 @@ struct Layout {
         items_fp, items_tr;
     size_t total = 0;
 };
+
+constexpr size_t kNoField = ~(size_t)0;   // "no field": the Farkas candidate is lambda itself
 
 // Largest splits of the 3D projector's march and of the backprojector's views in LP solves.
 constexpr int kMaxSplitP = 4, kMaxSplitB = 8;
@@ -961,7 +960,9 @@ class Solver {
         double omega = 1.0, m_anchor = 0, m_prev = 1e300, last_u = 0, last_v = 0, tau = 0, sigma = 0;
         int k_restart = 0, restarts = 0, iters = 0, status = SIPO_ITER_LIMIT;
         bool done = false;
-        int cert = -1;      // certificate when infeasible: 0 / 1 iterate pairs, 2 the warm-start multipliers
+        double fk = INFINITY;   // smallest Farkas violation of this check's candidates (progress lines)
+        int cert = -1;      // certificate when infeasible: 0 / 1 iterate pairs, 2 the warm-start multipliers,
+                            // 3 lambda(t), 4 lambda(t) - lambda at the last restart
         Kkt kc;
     };
     const sipo_problem *probs_;
@@ -1011,6 +1012,8 @@ class Solver {
 
     // ---- typed views of the workspace
     T *F(size_t off) const { return (T *)(ws_ + off); }
+    // a field or, for kNoField, NULL (the candidate and certificate kernels read it as zeros)
+    const T *Fz(size_t off) const { return off == kNoField ? nullptr : (const T *)(ws_ + off); }
     uint8_t *U8(size_t off) const { return (uint8_t *)(ws_ + off); }
     template <typename X>
     X *P(size_t off) const { return (X *)(ws_ + off); }
@@ -1640,12 +1643,12 @@ int Solver<T>::farkas(size_t alu, size_t all, size_t blu, size_t bll, double tol
     int rc = put_insts();
     if (rc) return rc;
     hipLaunchKernelGGL((k_ray_candidate<T>), gV(), dim3(kThreads), 0, s_, (const T *)F(alu), (const T *)F(all),
-                       (const T *)F(blu), (const T *)F(bll), F(L_.tmp2), (const uint8_t *)U8(L_.lab), lo_(), hi_(),
-                       insts(), segV(), partials());
+                       Fz(blu), Fz(bll), F(L_.tmp2), (const uint8_t *)U8(L_.lab), lo_(), hi_(), insts(), segV(),
+                       partials());
     rc = finish(true, list, 4);
     if (rc) return rc;
     std::vector<int> need;
-    std::vector<double> obj(B_, 0.0);
+    std::vector<double> obj(B_, 0.0), sw(B_, 0.0);
     for (int i : list) {
         const LPConst &c = hin_[i].c;
         double ray_obj = sum(i, 0);
@@ -1654,8 +1657,13 @@ int Solver<T>::farkas(size_t alu, size_t all, size_t blu, size_t bll, double tol
         if (!(ray_obj > 0) || !(sum(i, 3) > 0)) continue;
         const double worst_u = c.u_free ? sum(i, 1) / ray_obj : 0.0;
         const double worst_v = c.v_free ? sum(i, 2) / ray_obj : 0.0;
-        if (std::max(worst_u, worst_v) > tol) continue;
+        const double ws = std::max(worst_u, worst_v);
+        if (ws > tol) {
+            in_[i].fk = std::min(in_[i].fk, ws);
+            continue;
+        }
         obj[i] = ray_obj;
+        sw[i] = ws;
         need.push_back(i);
     }
     if (need.empty()) return SIPO_OK;
@@ -1665,7 +1673,10 @@ int Solver<T>::farkas(size_t alu, size_t all, size_t blu, size_t bll, double tol
                        segS(), partials());
     rc = finish(false, need, 2, true);
     if (rc) return rc;
-    for (int i : need) ok[i] = sum(i, 0) / obj[i] <= tol;
+    for (int i : need) {
+        ok[i] = sum(i, 0) / obj[i] <= tol;
+        in_[i].fk = std::min(in_[i].fk, std::max(sw[i], sum(i, 0) / obj[i]));
+    }
     return SIPO_OK;
 }
 
@@ -1819,10 +1830,8 @@ int Solver<T>::run(sipo_pdhg_result *res) {
         // the first iteration: the candidate is max(lambda, 0) on the regions, put to the same
         // test as the iterates' rays.  Cold starts (all-zero multipliers) drop out of that test
         // after one reduction.  lut / llt hold zeros here and are rewritten by every iteration.
-        rc = fill_vol(L_.lut);
-        if (!rc) rc = fill_vol(L_.llt);
         std::vector<char> ok0;
-        if (!rc) rc = farkas(L_.lu, L_.ll, L_.lut, L_.llt, itol, all, ok0);
+        rc = farkas(L_.lu, L_.ll, kNoField, kNoField, itol, all, ok0);
         if (rc) return rc;
         std::vector<int> warm, rest;
         for (int i : all) (ok0[i] ? warm : rest).push_back(i);
@@ -1837,8 +1846,8 @@ int Solver<T>::run(sipo_pdhg_result *res) {
             rc = put_insts();
             if (rc) return rc;
             hipLaunchKernelGGL((k_certificate<T>), gV(), dim3(kThreads), 0, s_, F(L_.lu), F(L_.ll), (const T *)F(L_.lu),
-                               (const T *)F(L_.ll), (const T *)F(L_.lut), (const T *)F(L_.llt), (const T *)F(L_.lut),
-                               (const T *)F(L_.llt), (const uint8_t *)U8(L_.lab), insts(), segV());
+                               (const T *)F(L_.ll), (const T *)nullptr, (const T *)nullptr,
+                               (const uint8_t *)U8(L_.lab), insts(), segV());
             rc = set_active(rest);
             if (rc) return rc;
         }
@@ -1876,12 +1885,6 @@ int Solver<T>::run(sipo_pdhg_result *res) {
         if (!rc) rc = kkt(L_.yt, L_.Dt, true, L_.lut, L_.llt, L_.tmp2, live);
         if (rc) return rc;
         ++checks;
-        if (o_.progress_every > 0 && checks % o_.progress_every == 0)
-            for (int i : live) {
-                const Kkt &k = in_[i].kc;
-                fprintf(stderr, "[sipo] instance %d: iteration %d, relative KKT %.3e (primal %.3e dual %.3e gap %.3e), "
-                        "restarts %d\n", i, it, k.rel(), k.eps_p, k.eps_d, k.eps_gap, in_[i].restarts);
-            }
         std::vector<int> open;
         for (int i : live) {
             const Kkt &k = in_[i].kc;
@@ -1890,6 +1893,7 @@ int Solver<T>::run(sipo_pdhg_result *res) {
             else open.push_back(i);
         }
         // infeasibility: lambda(t) - lambda(z), then lambda(t) - lambda(t at the previous check)
+        for (int i : open) in_[i].fk = INFINITY;
         std::vector<char> ok1, ok2;
         rc = farkas(L_.lut, L_.llt, L_.luo, L_.llo, itol, open, ok1);
         if (rc) return rc;
@@ -1900,11 +1904,34 @@ int Solver<T>::run(sipo_pdhg_result *res) {
         }
         rc = farkas(L_.lut, L_.llt, L_.snap_u, L_.snap_l, itol, second, ok2);
         if (rc) return rc;
-        std::vector<int> cont;
+        // then lambda(t) itself, and lambda(t) - lambda at the last restart: for an infeasible LP the
+        // restarted iterates' multipliers grow along the ray, so their direction approaches it; the
+        // multipliers of a feasible LP carry the objective's price and fail the scalar conditions
+        std::vector<int> third, fourth, cont;
         for (int i : second) {
             if (ok2[i]) { in_[i].status = SIPO_PRIMAL_INFEASIBLE; in_[i].cert = 1; in_[i].done = true; }
+            else third.push_back(i);
+        }
+        std::vector<char> ok3, ok4;
+        rc = farkas(L_.lut, L_.llt, kNoField, kNoField, itol, third, ok3);
+        if (rc) return rc;
+        for (int i : third) {
+            if (ok3[i]) { in_[i].status = SIPO_PRIMAL_INFEASIBLE; in_[i].cert = 3; in_[i].done = true; }
+            else fourth.push_back(i);
+        }
+        rc = farkas(L_.lut, L_.llt, L_.lu0, L_.ll0, itol, fourth, ok4);
+        if (rc) return rc;
+        for (int i : fourth) {
+            if (ok4[i]) { in_[i].status = SIPO_PRIMAL_INFEASIBLE; in_[i].cert = 4; in_[i].done = true; }
             else cont.push_back(i);
         }
+        if (o_.progress_every > 0 && checks % o_.progress_every == 0)
+            for (int i : live) {
+                const Kkt &k = in_[i].kc;
+                fprintf(stderr, "[sipo] instance %d: iteration %d, relative KKT %.3e (primal %.3e dual %.3e gap %.3e), "
+                        "restarts %d, least Farkas violation %.2e\n", i, it, k.rel(), k.eps_p, k.eps_d, k.eps_gap,
+                        in_[i].restarts, in_[i].fk);
+            }
         set_flags(cont);
         rc = put_insts();
         if (rc) return rc;
@@ -2000,7 +2027,6 @@ int Solver<T>::run(sipo_pdhg_result *res) {
     }
     if (!from_t.empty()) {
         set_flags(from_t);
-        for (int i : certs) hin_[i].sel = in_[i].cert;
         rc = put_insts();
         if (rc) return rc;
         copyS(L_.y, L_.yt, true);
@@ -2013,13 +2039,20 @@ int Solver<T>::run(sipo_pdhg_result *res) {
         if (rc) return rc;
         copyV(L_.lu, L_.lut, true);
         copyV(L_.ll, L_.llt, true);
-        if (!certs.empty()) {
-            set_flags(certs);
+        // certificates: max(lambda(t) - b, 0) with b the pre-step (0), snapshot (1), zero (3) or
+        // restart point (4) multipliers of the test that accepted it
+        const struct { int cert; size_t bu, bl; } kinds[] = {
+            {0, L_.luo, L_.llo}, {1, L_.snap_u, L_.snap_l}, {3, kNoField, kNoField}, {4, L_.lu0, L_.ll0}};
+        for (const auto &kd : kinds) {
+            std::vector<int> sel;
+            for (int i : certs)
+                if (in_[i].cert == kd.cert) sel.push_back(i);
+            if (sel.empty()) continue;
+            set_flags(sel);
             rc = put_insts();
             if (rc) return rc;
             hipLaunchKernelGGL((k_certificate<T>), gV(), dim3(kThreads), 0, s_, F(L_.lu), F(L_.ll), (const T *)F(L_.lut),
-                               (const T *)F(L_.llt), (const T *)F(L_.luo), (const T *)F(L_.llo),
-                               (const T *)F(L_.snap_u), (const T *)F(L_.snap_l), (const uint8_t *)U8(L_.lab), insts(),
+                               (const T *)F(L_.llt), Fz(kd.bu), Fz(kd.bl), (const uint8_t *)U8(L_.lab), insts(),
                                segV());
         }
     }

@@ -60,7 +60,7 @@ def test_plain_fp64_batch_equals_individual_solves():
 def test_restarted_batch_reaches_each_lp_value(dtype):
     import paper_2604_08997_amd as sipo
     built = [build(spec, dtype) for spec in SMALL]
-    tol = 1e-6 if dtype == torch.float64 else 2e-5
+    tol = 1e-6 if dtype == torch.float64 else 1e-5
     res = sipo.solve([b[0] for b in built], sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=100000, tol=tol))
     for (lp, op), r, spec in zip(built, res, SMALL):
         ref = olp.solve_highs(op)
@@ -73,9 +73,8 @@ def test_restarted_batch_reaches_each_lp_value(dtype):
         assert abs(r["primal_obj"] - ref.objective) <= 1e-4 * (1 + abs(ref.objective)), (spec, r, ref.objective)
         y, lu, ll = state(lp)
         assert okkt.residuals(op, y, r["u"], r["v"], lu, ll).rel <= 5 * tol, spec
-        # the relative KKT bound allows an absolute violation of about tol (1 + ||h||) on one row;
-        # the check holds it to 1e-4 of the bound scale
-        assert op.violation(y, r["u"], r["v"]) <= 1e-4 * (1.0 + float(np.abs(op.hi).max())), spec
+        # max constraint violation in normalised dose units
+        assert op.violation(y, r["u"], r["v"]) <= 1e-4, spec
 
 
 def test_batch_with_an_infeasible_instance_certifies_it_and_solves_the_rest():

@@ -99,26 +99,83 @@ def test_infeasible_case1_returns_checked_certificate(dtype):
     assert chk["valid"], chk
 
 
-@pytest.mark.parametrize("case", [1, 2])
-def test_slice256_fp32_solution_passes_oracle_kkt(case):
-    # 256 x 256 slice, 360 views, annulus + 4 disks (seed 1000), FP32 restarted PDHG to 1e-4
+def test_slice256_case1_fp32_matches_oracle_checked_reference():
+    # 256 x 256 slice, 360 views, annulus + 4 disks (seed 1000), Case 1.  Reference optimum: an FP64
+    # solve to relative KKT 1e-6 whose optimality the oracle's FP64 residuals confirm (no exact LP
+    # solver finishes at this size in test time).  The FP32 solve (the production precision) must reach
+    # that objective within 1e-4, with oracle residuals and violation within tolerance.
     import paper_2604_08997_amd as sipo
     n, na = 256, 360
     f = annulus_disks_target(n, 1000)
-    gl = gpu_lp(n, na, f, case, torch.float32)
-    res = sipo.solve(gl, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=30000, tol=1e-4, infeas_tol=1e-5))
-    print(CASE_NAMES[case], {k: res[k] for k in ("status_name", "iters", "restarts", "primal_obj", "rel_primal",
-                                                "rel_dual", "rel_gap", "time_ms")})
-    op = oracle_lp(n, na, f, case)
-    np.testing.assert_array_equal(gl.labels.cpu().numpy(), op.labels)
-    y, lu, ll = gpu_state(gl)
-    if res["status_name"] == "infeasible":
-        assert okkt.farkas_check(op, lu, ll, tol=1e-3)["valid"]
-        return
-    assert res["status_name"] == "optimal"
+    op = oracle_lp(n, na, f, olp.CASE1)
+    g64 = gpu_lp(n, na, f, olp.CASE1, torch.float64)
+    r64 = sipo.solve(g64, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=400000, tol=1e-6))
+    assert r64["status_name"] == "optimal", r64
+    y, lu, ll = gpu_state(g64)
+    k64 = okkt.residuals(op, y, r64["u"], r64["v"], lu, ll)
+    assert k64.rel <= 2e-6, k64
+    ref = k64.primal_obj
+    g32 = gpu_lp(n, na, f, olp.CASE1, torch.float32)
+    np.testing.assert_array_equal(g32.labels.cpu().numpy(), op.labels)
+    # relative KKT 4e-6: the l2 residual bound then also holds the largest single violation under 1e-4
+    res = sipo.solve(g32, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=300000, tol=4e-6))
+    print({k: res[k] for k in ("status_name", "iters", "restarts", "primal_obj", "rel_primal", "rel_dual", "rel_gap")},
+          "reference", ref, r64["iters"])
+    assert res["status_name"] == "optimal", res
+    y, lu, ll = gpu_state(g32)
     k = okkt.residuals(op, y, res["u"], res["v"], lu, ll)
-    assert k.rel <= 3e-4, k
-    assert abs(k.primal_obj - res["primal_obj"]) <= 1e-4 * (1 + abs(k.primal_obj))
+    assert k.rel <= 8e-6, k
+    assert abs(k.primal_obj - ref) <= 1e-4 * (1 + abs(ref)), (k.primal_obj, ref)
+    assert op.violation(y, res["u"], res["v"]) <= 1e-4
+
+
+def test_slice256_case2_classified_by_h_min_and_certified():
+    # the same slice, Case 2 at cap 0.7: the h_min LP (FP64 GPU solve, confirmed by the oracle's
+    # residuals) classifies it; an infeasible Case 2 must end infeasible in FP32 with a certificate the
+    # oracle's Farkas test accepts at the solver's tolerance
+    check_case2_classified(256, 360, annulus_disks_target(256, 1000), 0.7)
+
+
+def check_case2_classified(n, na, f, cap):
+    import paper_2604_08997_amd as sipo
+    from paper_2604_08997_amd import workflow
+    from oracle import workflow as owf
+    plan64 = sipo.Plan(n, list(angles_uniform(na)), dtype=torch.float64, device=dev())
+    f64 = torch.as_tensor(f, device=dev())
+    lab, act = plan64.regions(f64, 10.0), plan64.active_rays(f64)
+    hm = workflow.h_min_lp(plan64, lab, act, 1.0)
+    rh = sipo.solve(hm, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=400000, tol=1e-6))
+    assert rh["status_name"] == "optimal", rh
+    P = Projector(make_geometry(n, angles_uniform(na), atten=1.0))
+    oh = olp.build(P, f, olp.GENERAL, band_width=10.0, w1=1.0, w2=0.0)
+    y, lu, ll = gpu_state(hm)
+    kh = okkt.residuals(oh, y, rh["u"], rh["v"], lu, ll)
+    assert kh.rel <= 2e-6, kh
+    h_min = kh.primal_obj
+    op = olp.build(P, f, olp.CASE2, band_width=10.0, cap=cap)
+    g32 = gpu_lp(n, na, f, olp.CASE2, torch.float32, cap=cap)
+    res = sipo.solve(g32, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=100000, tol=1e-4, infeas_tol=1e-4))
+    print("h_min", h_min, rh["iters"], {k: res[k] for k in ("status_name", "iters", "restarts", "primal_obj")})
+    y, lu, ll = gpu_state(g32)
+    assert abs(h_min - cap) > 1e-3 * cap, "too close to the feasibility threshold to classify"
+    if h_min > cap:
+        assert res["status_name"] == "infeasible", (res, h_min)
+        assert okkt.farkas_check(op, lu, ll, tol=1e-4)["valid"]
+        # FP64: the h_min multipliers (relative residuals 1e-6), put to the solver's iteration-0 test,
+        # are a Farkas ray of this Case 2 (dual objective h_min - cap per unit band sum); the oracle
+        # accepts it at 1e-5 per unit dual objective
+        c2 = workflow.case2_lp(plan64, lab, act, 1.0, cap)
+        c2.lam_up.copy_(hm.lam_up)
+        c2.lam_lo.copy_(hm.lam_lo)
+        r2 = sipo.solve(c2, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=1000, tol=1e-6, infeas_tol=1e-5))
+        assert r2["status_name"] == "infeasible" and r2["iters"] == 0, r2
+        _, lu, ll = gpu_state(c2)
+        op_gen = owf.case2_in_general_units(P, f, cap, band_width=10.0)
+        assert okkt.farkas_check(op_gen, lu, ll, tol=1e-5)["valid"]
+    else:
+        assert res["status_name"] == "optimal", (res, h_min)
+        k = okkt.residuals(op, y, res["u"], res["v"], lu, ll)
+        assert k.rel <= 2e-4, k
 
 
 def gpu_lp3d(n, n_angles, f, case, dtype, sigma, band=2.0, **kw):
@@ -177,10 +234,10 @@ def test_restarted_3d_blur_matches_highs(case, dtype):
 def test_restarted_3d_ragged_tiles_fp32_paths_match_fp64_and_highs():
     # 40^2 x 20 slices, 18 views: no tile of the masked operators, blurs or transposes divides the
     # volume evenly (n^2 = 1600 columns, 20 slices), so every masked path meets a ragged edge.  The
-    # FP32 solve runs the asynchronous projector with the primal step in its output and the masked
-    # transpose; the FP64 solve runs none of them.  This LP converges slowly (about 1.2e-4 relative
-    # KKT after 20000 iterations), so both are stopped there and compared with each other, with
-    # HiGHS and with the oracle's residuals.
+    # FP32 solve runs the asynchronous projector (step lists) with the primal step in its output and
+    # the masked transpose; the FP64 solve runs none of them.  Both solve to relative KKT 1e-5 (so that
+    # the objective holds to 1e-4 with margin) and are compared with each other, with HiGHS and with
+    # the oracle's residuals.
     import paper_2604_08997_amd as sipo
     from sipo_inputs import ellipsoids_target
     n, na, nz, sigma = 40, 18, 20, (1.0, 1.0, 1.5)
@@ -191,15 +248,15 @@ def test_restarted_3d_ragged_tiles_fp32_paths_match_fp64_and_highs():
     out = {}
     for dtype in (torch.float64, torch.float32):
         gl = gpu_lp3d(n, na, f, sipo.CASE1, dtype, sigma)
-        res = sipo.solve(gl, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=20000, tol=1e-4))
-        assert res["status_name"] in ("optimal", "iter_limit"), res["status_name"]
+        res = sipo.solve(gl, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=400000, tol=1e-5))
+        assert res["status_name"] == "optimal", (dtype, res)
         y, lu, ll = gpu_state(gl)
         k = okkt.residuals(op, y, res["u"], res["v"], lu, ll)
-        assert k.rel <= 3e-4, (dtype, k)
-        assert abs(res["primal_obj"] - ref.objective) <= 3e-4 * (1 + abs(ref.objective)), (dtype, res["primal_obj"])
+        assert k.rel <= 2e-5, (dtype, k)
+        assert abs(res["primal_obj"] - ref.objective) <= 1e-4 * (1 + abs(ref.objective)), (dtype, res["primal_obj"])
         out[dtype] = res["primal_obj"]
     # the optimal y need not be unique; the objective is
-    assert abs(out[torch.float32] - out[torch.float64]) <= 1e-5 * (1 + abs(out[torch.float64]))
+    assert abs(out[torch.float32] - out[torch.float64]) <= 1e-4 * (1 + abs(out[torch.float64]))
 
 
 def test_restarted_3d_without_psf_fp32_and_fp64_match_highs():
@@ -217,11 +274,11 @@ def test_restarted_3d_without_psf_fp32_and_fp64_match_highs():
     for dtype in (torch.float64, torch.float32):
         plan = sipo.Plan(n, list(angles_uniform(na)), nz=nz, dtype=dtype, device=dev())
         gl = sipo.LP.build(plan, torch.as_tensor(f, dtype=dtype, device=dev()), sipo.CASE1, band_width=2.0, f_min=1.0)
-        res = sipo.solve(gl, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=20000, tol=1e-4))
-        assert res["status_name"] in ("optimal", "iter_limit"), res["status_name"]
+        res = sipo.solve(gl, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=400000, tol=1e-5))
+        assert res["status_name"] == "optimal", (dtype, res)
         y, lu, ll = gpu_state(gl)
         k = okkt.residuals(op, y, res["u"], res["v"], lu, ll)
-        assert k.rel <= 3e-4, (dtype, k)
-        assert abs(res["primal_obj"] - ref.objective) <= 3e-4 * (1 + abs(ref.objective)), (dtype, res["primal_obj"])
+        assert k.rel <= 2e-5, (dtype, k)
+        assert abs(res["primal_obj"] - ref.objective) <= 1e-4 * (1 + abs(ref.objective)), (dtype, res["primal_obj"])
         objs[dtype] = res["primal_obj"]
     assert abs(objs[torch.float32] - objs[torch.float64]) <= 1e-4 * (1 + abs(objs[torch.float64]))
