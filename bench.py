@@ -61,6 +61,9 @@ def parse():
                     help="instances of the uneven 2D batch (seeds 2000..) for the batched-vs-plain time to 1e-4, "
                          "cold and h_min-screened (0 = skip)")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched-vs-plain comparison")
+    ap.add_argument("--screened", action="store_true",
+                    help="batched-vs-plain comparison also by the h_min-screened route (Case 2 instances first solve "
+                         "their h_min LP)")
     ap.add_argument("--two-stage", type=int, default=0,
                     help="run only the two-stage Case 1 -> Case 2 workflow on this many instances of the uneven "
                          "2D batch, against Case 2 at the fixed cap 0.7 on the same targets")
@@ -198,13 +201,13 @@ def cpu_baseline(n, angles, slices):
                       f"value = measured slice-iterations per second / {n} slices"}
 
 
-def batch_vs_plain(count, dev, max_iters=40000, infeas_tol=1e-4, h_min_tol=1e-5):
+def batch_vs_plain(count, dev, max_iters=40000, infeas_tol=1e-4, h_min_tol=1e-5, screened=False):
     """Time to relative KKT 1e-4 (or a checked infeasibility certificate) of the first ``count``
     instances of the uneven 2D batch, one batched graph-captured solve against the same solver run
     instance by instance (also graph-captured), on the same GPU, by two routes:
 
     * cold: every instance as posed (Case 1 [0.9, 1.0] or Case 2 cap 0.7) from zero;
-    * screened: the Case-2 instances first solve their h_min LP (the smallest feasible band cap,
+    * screened (``screened``, --screened): the Case-2 instances first solve their h_min LP (the smallest feasible band cap,
       general LP with w = (1, 0)); a Case 2 whose cap lies below it starts from the h_min
       multipliers, which the solver's iteration-0 Farkas test accepts as its certificate.  In the
       batched route the h_min LPs form one batch and all instances the second; one by one, each
@@ -259,6 +262,18 @@ def batch_vs_plain(count, dev, max_iters=40000, infeas_tol=1e-4, h_min_tol=1e-5)
     same = all(all(a[k] == b[k] for k in keys) for a, b in zip(rb, rp))
     capped = [k for k, r in enumerate(rb) if r["status_name"] not in ("optimal", "infeasible")]
 
+    samples = sum(float(b.n) * b.n * b.n_angles for b in insts)
+    out = {"instances": count, "seeds": f"2000-{2000 + count - 1}", "samples_per_application": samples,
+           "max_iters": max_iters, "infeas_tol": infeas_tol, "compared_fields": list(keys),
+           "cold": {"batched_s": round(t_batch, 3), "plain_s": round(t_plain, 3),
+                    # a time to 1e-4 only when every instance ended optimal or with a certificate
+                    "speedup": round(t_plain / t_batch, 3) if not capped else None,
+                    "speedup_with_capped_instances": round(t_plain / t_batch, 3),
+                    "status": dict(Counter(r["status_name"] for r in rb)), "capped_instances": capped,
+                    "iters": [r["iters"] for r in rb], "per_instance_results_identical": same}}
+    if not screened:
+        return out
+
     # ---- screened route (Case 2 in general units: band cap 0.7, f~_T = 1)
     def screened_lps():
         hms, finals = {}, []
@@ -304,23 +319,15 @@ def batch_vs_plain(count, dev, max_iters=40000, infeas_tol=1e-4, h_min_tol=1e-5)
     s_same = all(all(a[k] == b[k] for k in keys) for a, b in zip(sb, sp)) and \
         all(all(sbh[k][q] == sph[k][q] for q in keys) for k in sbh)
     s_capped = [k for k, r in enumerate(sb) if r["status_name"] not in ("optimal", "infeasible")]
-    samples = sum(float(b.n) * b.n * b.n_angles for b in insts)
-    return {"instances": count, "seeds": f"2000-{2000 + count - 1}", "samples_per_application": samples,
-            "max_iters": max_iters, "infeas_tol": infeas_tol, "compared_fields": list(keys),
-            "cold": {"batched_s": round(t_batch, 3), "plain_s": round(t_plain, 3),
-                     # a time to 1e-4 only when every instance ended optimal or with a certificate
-                     "speedup": round(t_plain / t_batch, 3) if not capped else None,
-                     "speedup_with_capped_instances": round(t_plain / t_batch, 3),
-                     "status": dict(Counter(r["status_name"] for r in rb)), "capped_instances": capped,
-                     "iters": [r["iters"] for r in rb], "per_instance_results_identical": same},
-            "screened": {"batched_s": round(ts_batch, 3), "plain_s": round(ts_plain, 3),
-                         "speedup": round(ts_plain / ts_batch, 3) if not s_capped else None,
-                         "status": dict(Counter(r["status_name"] for r in sb)), "capped_instances": s_capped,
-                         "h_min_tol": h_min_tol,
-                         "h_min": {str(k): round(r["u"], 6) for k, r in sbh.items()},
-                         "certified_at_iteration_0": sum(1 for r in sb if r["status_name"] == "infeasible"
-                                                         and r["iters"] == 0),
-                         "iters": [r["iters"] for r in sb], "per_instance_results_identical": s_same}}
+    out["screened"] = {"batched_s": round(ts_batch, 3), "plain_s": round(ts_plain, 3),
+                       "speedup": round(ts_plain / ts_batch, 3) if not s_capped else None,
+                       "speedup_with_capped_instances": round(ts_plain / ts_batch, 3),
+                       "status": dict(Counter(r["status_name"] for r in sb)), "capped_instances": s_capped,
+                       "h_min_tol": h_min_tol, "h_min": {str(k): round(r["u"], 6) for k, r in sbh.items()},
+                       "certified_at_iteration_0": sum(1 for r in sb if r["status_name"] == "infeasible"
+                                                       and r["iters"] == 0),
+                       "iters": [r["iters"] for r in sb], "per_instance_results_identical": s_same}
+    return out
 
 
 def two_stage_batch(count, dev, margin, max_iters=20000):
@@ -513,7 +520,8 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     if args.batch_only:
-        print(json.dumps({"batched_vs_plain_time_to_1e-4": batch_vs_plain(args.batch, dev)}), flush=True)
+        print(json.dumps({"batched_vs_plain_time_to_1e-4": batch_vs_plain(args.batch, dev, screened=args.screened)}),
+              flush=True)
         return 0
     if args.two_stage > 0:
         print(json.dumps({"two_stage": two_stage_batch(args.two_stage, dev, args.margin)}), flush=True)
@@ -600,7 +608,7 @@ def main():
                "rel_dual": r["rel_dual"], "rel_gap": r["rel_gap"]}
         print(f"[bench] time to 1e-4: {ttk}", file=sys.stderr, flush=True)
 
-    bvp = batch_vs_plain(args.batch, dev) if args.batch > 0 else None
+    bvp = batch_vs_plain(args.batch, dev, screened=args.screened) if args.batch > 0 else None
     cpu = None if (args.no_cpu_baseline or big) else cpu_baseline(n, na, args.cpu_slices)
     line = {
         "metric": "PDHG iters/s",
