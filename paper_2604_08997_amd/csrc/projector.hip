@@ -165,6 +165,9 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
     constexpr int Z4 = ZC / 4, ZP = ZC + 4;
     __shared__ __align__(16) T lds[kBpTB][kBpW][ZP];
     __shared__ int bmin_s[kBpTB];
+    // FP32: per view of the batch, the detector coordinate at the tile's origin relative to its first
+    // staged bin and its increments per column and row (hi / lo splits, see taps_rel32), and (sin, cos)
+    __shared__ float geo_s[sizeof(T) == 4 ? kBpTB : 1][8];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     // grid.z = z chunks x view splits; split s sums its share of the views into partial sum s
     const int3 tile = xcd_tile<kXcdRunBp>();
@@ -183,6 +186,8 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
     }
     const double xv = centre(c, h);
     const double yv[2] = {centre(r[0], h), centre(r[1], h)};
+    const float xf = (float)xv, yf[2] = {(float)yv[0], (float)yv[1]};
+    const float dcf = (float)tx, drf[2] = {(float)ty, (float)(ty + 8)};
     bool inside[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) inside[j] = c < n && r[j] < n && vial_ij(c, r[j], n);
@@ -206,7 +211,19 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
                     const double s = fma(-centre(cs_[i], h), tr.x, centre(rs_[k], h) * tr.y);
                     umin = fmin(umin, fma(s + 1.0, inv_ds, -0.5));
                 }
-            bmin_s[threadIdx.x] = (int)floor(umin) - 1;
+            const int bm = (int)floor(umin) - 1;
+            bmin_s[threadIdx.x] = bm;
+            if constexpr (sizeof(T) == 4) {
+                // once per (tile, view) in FP64: u at the tile's first voxel relative to bm, and its
+                // steps per column and per row
+                const double s0 = fma(-centre(x0, h), tr.x, centre(y0, h) * tr.y);
+                const Split32 u0 = split32(fma(s0 + 1.0, inv_ds, -0.5) - (double)bm, kTapScale, kTapInvScale);
+                const Split32 ux = split32(-tr.x * h * inv_ds, kTapScale, kTapInvScale);
+                const Split32 uy = split32(tr.y * h * inv_ds, kTapScale, kTapInvScale);
+                float *g = geo_s[threadIdx.x];
+                g[0] = u0.hi; g[1] = u0.lo; g[2] = ux.hi; g[3] = ux.lo; g[4] = uy.hi; g[5] = uy.lo;
+                g[6] = (float)tr.x; g[7] = (float)tr.y;
+            }
         }
         __syncthreads();
         const int tot = na * kBpW * Z4;
@@ -262,13 +279,22 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
         }
         __syncthreads();
         for (int k = 0; k < na; ++k) {
-            const double2 tr = trig[a0 + k];
-            const int bm = bmin_s[k];
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 if (!inside[j]) continue;
                 T w0, w1;
-                const int br = taps<T>(xv, yv[j], tr.x, tr.y, inv_ds, atten, w0, w1) - bm;
+                int br;
+                if constexpr (sizeof(T) == 4) {
+                    // FP32 throughout: the voxel's offsets in the tile against the view's split origin
+                    const float *g = geo_s[k];
+                    const float sn = g[6], cs = g[7];
+                    const float sv = fmaf(-xf, sn, yf[j] * cs), tv = fmaf(xf, cs, yf[j] * sn);
+                    br = taps_rel32(dcf, drf[j], Split32{g[0], g[1]}, Split32{g[2], g[3]}, Split32{g[4], g[5]}, sv, tv,
+                                    (float)atten, w0, w1);
+                } else {
+                    const double2 tr = trig[a0 + k];
+                    br = taps<T>(xv, yv[j], tr.x, tr.y, inv_ds, atten, w0, w1) - bmin_s[k];
+                }
                 const T *row0 = &lds[k][br][0];
                 const T *row1 = &lds[k][br + 1][0];
 #pragma unroll
@@ -407,6 +433,7 @@ __global__ void __launch_bounds__(256) project3d_kernel(const T *__restrict__ vo
     const double du = dsj * inv_ds, dU = dsm * inv_ds, U00 = fma(s00 + 1.0, inv_ds, -0.5);
     const double inv_du = 1.0 / du;
     const T du_t = (T)du, dsj_t = (T)dsj, dtj_t = (T)dtj;
+    const MarchF32 mc32 = march_f32(U00 - (double)b, dU, du, inv_du, s00, dsm, t00, dtm, nb);
     T acc[NR][ZC];
 #pragma unroll
     for (int r = 0; r < NR; ++r)
@@ -459,13 +486,19 @@ __global__ void __launch_bounds__(256) project3d_kernel(const T *__restrict__ vo
         if (active) {
             for (int mm = 0; mm < mc; ++mm) {
                 const int m = m0 + mm;
-                const double U = fma((double)m, dU, U00);
-                const double jA = ((double)b - 1.0 - U) * inv_du, jB = ((double)b + 1.0 - U) * inv_du;
-                const int jlo = (int)ceil(fmin(jA, jB) - 1e-9);
-                const double jl = (double)jlo;
-                const T d0 = (T)(fma(jl, du, U) - (double)b);
-                const T s0 = (T)fma(jl, dsj, fma((double)m, dsm, s00));
-                const T t0 = (T)fma(jl, dtj, fma((double)m, dtm, t00));
+                int jlo;
+                T d0, s0, t0;
+                if constexpr (sizeof(T) == 4) {
+                    jlo = march_step_f32(mc32, m, dsj_t, dtj_t, d0, s0, t0);
+                } else {
+                    const double U = fma((double)m, dU, U00);
+                    const double jA = ((double)b - 1.0 - U) * inv_du, jB = ((double)b + 1.0 - U) * inv_du;
+                    jlo = (int)ceil(fmin(jA, jB) - 1e-9);
+                    const double jl = (double)jlo;
+                    d0 = (T)(fma(jl, du, U) - (double)b);
+                    s0 = (T)fma(jl, dsj, fma((double)m, dsm, s00));
+                    t0 = (T)fma(jl, dtj, fma((double)m, dtm, t00));
+                }
                 const int jj0 = jlo - j0;
 #pragma unroll
                 for (int q = 0; q < NC; ++q) {
@@ -607,6 +640,7 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     const double du = dsj * inv_ds, dU = dsm * inv_ds, U00 = fma(s00 + 1.0, inv_ds, -0.5);
     const double inv_du = 1.0 / du;
     const float du_t = (float)du, dsj_t = (float)dsj, dtj_t = (float)dtj;
+    const MarchF32 mc32 = march_f32(U00 - (double)b, dU, du, inv_du, s00, dsm, t00, dtm, nb);
     // the march: every step in chunks of CM, or (step lists, CM = 1) only the listed steps, in
     // increasing order; the steps left out stage nothing but zeros
     // LIST: the workgroup's listed steps are copied to LDS first, so that reading a chunk's step adds
@@ -686,13 +720,8 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
         const int mc = min(CM, n - m0);
         for (int mm = 0; mm < mc; ++mm) {
             const int m = m0 + mm;
-            const double U = fma((double)m, dU, U00);
-            const double jA = ((double)b - 1.0 - U) * inv_du, jB = ((double)b + 1.0 - U) * inv_du;
-            const int jlo = (int)ceil(fmin(jA, jB) - 1e-9);
-            const double jl = (double)jlo;
-            const float d0 = (float)(fma(jl, du, U) - (double)b);
-            const float s0 = (float)fma(jl, dsj, fma((double)m, dsm, s00));
-            const float t0 = (float)fma(jl, dtj, fma((double)m, dtm, t00));
+            float d0, s0, t0;
+            const int jlo = march_step_f32(mc32, m, dsj_t, dtj_t, d0, s0, t0);
             const int jj0 = jlo - j0;
             const float4 *row = buf + mm * (Z4 * RS);
 #pragma unroll

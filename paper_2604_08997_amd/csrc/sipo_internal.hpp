@@ -295,4 +295,89 @@ __device__ __forceinline__ int taps(double x, double y, double sn, double cs, do
     return (int)bf;
 }
 
+// ------------------------------------------------ FP32 detector coordinates
+// The FP32 kernels evaluate the detector coordinate u (and the position of a voxel in a ray's hat
+// function) without FP64 in their inner loops.  A per-(tile, view) or per-ray origin and the
+// coordinate's increments are formed in FP64 once, then each is split into hi = the value rounded to
+// a multiple of 2^-q and lo = the rest, both FP32.  Sums of hi parts with small integer multipliers
+// are exact in FP32 while they stay below 2^(24 - q) (every such sum is a multiple of 2^-q), and the lo
+// parts are small enough that their FP32 rounding is far below 1e-7, so the fractional part that
+// weights the interpolation taps comes out with an absolute error near 1e-7 whatever the grid size.
+struct Split32 {
+    float hi, lo;
+};
+__device__ __forceinline__ Split32 split32(double v, double scale, double inv_scale) {
+    const double h = rint(v * scale) * inv_scale;
+    return {(float)h, (float)(v - h)};
+}
+
+// floor and fraction of hi + lo, where hi is an exact multiple of 2^-q and |lo| < 1:
+// returns b with hi + lo = b + f, 0 <= f < 1 (f to about 1e-7)
+__device__ __forceinline__ int floor_frac(float hi, float lo, float &f) {
+    const float bh = floorf(hi);
+    float fr = (hi - bh) + lo;          // hi - bh is exact
+    int b = (int)bh;
+    if (fr < 0.f) { fr += 1.f; --b; }
+    if (fr >= 1.f) { fr -= 1.f; ++b; }
+    f = fr;
+    return b;
+}
+
+// Taps of a voxel at integer offsets (dc, dr) from its tile's origin, relative to the tile's first
+// staged bin: u - bm = u0 + dc du_dc + dr du_dr with the three terms split as above (q = 16: the
+// relative coordinate stays below 128).  Returns the bin index relative to bm; w0 = a (1 - f) belongs
+// to it, w1 = a f to the next bin; s and t are the voxel's detector and depth coordinates.
+__device__ __forceinline__ int taps_rel32(float dc, float dr, const Split32 &u0, const Split32 &ux, const Split32 &uy,
+                                          float s, float t, float atten, float &w0, float &w1) {
+    const float hi = fmaf(dr, uy.hi, fmaf(dc, ux.hi, u0.hi));   // exact
+    const float lo = fmaf(dr, uy.lo, fmaf(dc, ux.lo, u0.lo));
+    float f;
+    const int b = floor_frac(hi, lo, f);
+    float r = fmaf(-s, s, 1.f);
+    r = r > 0.f ? sqrt_t<float>(r) : 0.f;
+    const float a = exp_neg<float>(atten, t + r);
+    w1 = a * f;
+    w0 = a - w1;
+    return b;
+}
+constexpr double kTapScale = 65536.0, kTapInvScale = 1.0 / 65536.0;   // q = 16
+
+// A ray's march in FP32.  Along grid line m the ray's hat position of the voxel at cross index j is
+// d = w(m) + j du with w(m) = U00 - b + m dU (b the ray's bin); its detector and depth coordinates
+// are s00 + m dsm + j dsj and t00 + m dtm + j dtj.  w's origin and both steps are split at 2^-q with
+// q = 20 - floor(log2(n_bins)) (in [4, 16]): the hi parts of w and d then stay below 2^(24 - q), so
+// they are exact, and d, which lies in [-1, 1], keeps an absolute error near 1e-7.  The first
+// candidate jlo comes from w rounded to FP32; near a hat edge it may be off by one, which drops or
+// adds only a voxel whose weight is below that rounding (about 1e-4 at 512 bins), and the candidate
+// count (at least 2 / |du|) still covers the rest.
+struct MarchF32 {
+    Split32 w0, dU, du;
+    float inv_du, s00, dsm, t00, dtm;
+};
+__device__ __forceinline__ MarchF32 march_f32(double w0, double dU, double du, double inv_du, double s00, double dsm,
+                                              double t00, double dtm, int nb) {
+    const int q = min(16, max(4, 20 - (31 - __clz(max(nb, 1)))));
+    const double qs = ldexp(1.0, q), qi = ldexp(1.0, -q);
+    MarchF32 r;
+    r.w0 = split32(w0, qs, qi);
+    r.dU = split32(dU, qs, qi);
+    r.du = split32(du, qs, qi);
+    r.inv_du = (float)inv_du;
+    r.s00 = (float)s00; r.dsm = (float)dsm; r.t00 = (float)t00; r.dtm = (float)dtm;
+    return r;
+}
+// First candidate of grid line m, its hat position d0 and coordinates s0, t0 (FP32 only).
+template <typename T>
+__device__ __forceinline__ int march_step_f32(const MarchF32 &c, int m, T dsj, T dtj, T &d0, T &s0, T &t0) {
+    const float mf = (float)m;
+    const float whi = fmaf(mf, c.dU.hi, c.w0.hi), wlo = fmaf(mf, c.dU.lo, c.w0.lo);   // whi exact
+    const float wf = whi + wlo;
+    const int jlo = (int)ceilf(fminf((-1.f - wf) * c.inv_du, (1.f - wf) * c.inv_du));
+    const float jl = (float)jlo;
+    d0 = fmaf(jl, c.du.hi, whi) + fmaf(jl, c.du.lo, wlo);   // the first product-sum is exact
+    s0 = fmaf(jl, (float)dsj, fmaf(mf, c.dsm, c.s00));
+    t0 = fmaf(jl, (float)dtj, fmaf(mf, c.dtm, c.t00));
+    return jlo;
+}
+
 }  // namespace sipo
