@@ -39,6 +39,11 @@ __global__ void __launch_bounds__(256) bp2d_kernel(const Geo2D *__restrict__ geo
     __shared__ T rows[STAGED ? 2 * kB2VB : 1][STAGED ? kB2W : 1];
     __shared__ int rbase[2 * kB2VB];
     __shared__ double2 vtrig[kB2VB];   // (sin, cos) of the batch's walked views
+    // FP32 staged path: per walked view, u at the tile's first voxel relative to each row's first
+    // staged bin (the view's, and the mirrored partner's) and u's steps per column and row, split as
+    // in taps_rel32, and (sin, cos)
+    constexpr bool G32 = STAGED && sizeof(T) == 4;
+    __shared__ float vgeo[G32 ? kB2VB : 1][10];
     const int4 it = items[blockIdx.x];
     const Geo2D &g = geo[it.x];
     const int n = g.n, nb = g.n_bins;
@@ -46,6 +51,8 @@ __global__ void __launch_bounds__(256) bp2d_kernel(const Geo2D *__restrict__ geo
     const bool in_grid = c < n && r < n;
     const bool inside = in_grid && in_vial(c, r, n);
     const double x = centre(c, g.h), y = centre(r, g.h);
+    const float xf = (float)x, yf = (float)y;
+    const float dcf = (float)(threadIdx.x % kB2X), drf = (float)(threadIdx.x / kB2X);
     const T atten = (T)g.atten;
     const T *s0 = sino + g.soff;
     T acc = (T)0;
@@ -66,8 +73,25 @@ __global__ void __launch_bounds__(256) bp2d_kernel(const Geo2D *__restrict__ geo
                         umax = fmax(umax, u);
                     }
                 const double lo = mir ? (double)(nb - 1) - umax : umin;
-                rbase[threadIdx.x] = (int)floor(lo) - 1;
+                const int rb = (int)floor(lo) - 1;
+                rbase[threadIdx.x] = rb;
                 if (!mir) vtrig[threadIdx.x / 2] = tr;
+                if constexpr (G32) {
+                    // once per (tile, view) in FP64; the mirrored row runs along u' = nb - 1 - u
+                    const double u00 = fma(fma(-centre(it.y, g.h), tr.x, centre(it.z, g.h) * tr.y) + 1.0, g.inv_ds,
+                                           -0.5);
+                    float *vg = vgeo[threadIdx.x / 2];
+                    const Split32 o = split32(mir ? (double)(nb - 1) - u00 - (double)rb : u00 - (double)rb, kTapScale,
+                                              kTapInvScale);
+                    vg[mir ? 2 : 0] = o.hi;
+                    vg[mir ? 3 : 1] = o.lo;
+                    if (!mir) {
+                        const Split32 ux = split32(-tr.x * g.h * g.inv_ds, kTapScale, kTapInvScale);
+                        const Split32 uy = split32(tr.y * g.h * g.inv_ds, kTapScale, kTapInvScale);
+                        vg[4] = ux.hi; vg[5] = ux.lo; vg[6] = uy.hi; vg[7] = uy.lo;
+                        vg[8] = (float)tr.x; vg[9] = (float)tr.y;
+                    }
+                }
             }
             __syncthreads();
             for (int e = threadIdx.x; e < 2 * nk * kB2W; e += 256) {
@@ -79,7 +103,28 @@ __global__ void __launch_bounds__(256) bp2d_kernel(const Geo2D *__restrict__ geo
             }
             __syncthreads();
         }
-        if (inside) {
+        if (G32 && inside) {
+            // FP32 throughout: the voxel's offsets in the tile against each row's split origin
+            for (int kq = 0; kq < nk; ++kq) {
+                const float *vg = vgeo[kq];
+                const float sn = vg[8], cs = vg[9];
+                const float sv = fmaf(-xf, sn, yf * cs), tv = fmaf(xf, cs, yf * sn);
+                const Split32 ux{vg[4], vg[5]}, uy{vg[6], vg[7]};
+                float w0, w1;
+                int bl = taps_rel32(dcf, drf, Split32{vg[0], vg[1]}, ux, uy, sv, tv, (float)atten, w0, w1);
+                bl = min(max(bl, 0), kB2W - 2);
+                acc = fma((T)w0, rows[2 * kq][bl], acc);
+                acc = fma((T)w1, rows[2 * kq][bl + 1], acc);
+                if (g.pair) {
+                    // opposite view: u' = nb - 1 - u (steps negated), t' = -t, same sqrt(1 - s^2)
+                    const Split32 nx{-ux.hi, -ux.lo}, ny{-uy.hi, -uy.lo};
+                    bl = taps_rel32(dcf, drf, Split32{vg[2], vg[3]}, nx, ny, sv, -tv, (float)atten, w0, w1);
+                    bl = min(max(bl, 0), kB2W - 2);
+                    acc = fma((T)w0, rows[2 * kq + 1][bl], acc);
+                    acc = fma((T)w1, rows[2 * kq + 1][bl + 1], acc);
+                }
+            }
+        } else if (inside) {
             for (int kq = 0; kq < nk; ++kq) {
                 const int a = STAGED ? 0 : g.walk[k0 + kq];
                 const double2 tr = STAGED ? vtrig[kq] : g.trig[a];
@@ -162,6 +207,7 @@ __global__ void __launch_bounds__(256) fp2d_kernel(const Geo2D *__restrict__ geo
     const double du = dsj * inv_ds, dU = dsm * inv_ds, U00 = fma(s00 + 1.0, inv_ds, -0.5);
     const double inv_du = 1.0 / du;
     const T du_t = (T)du, dsj_t = (T)dsj, dtj_t = (T)dtj, atten = (T)g.atten;
+    const MarchF32 mc32 = march_f32(U00 - (double)b, dU, du, inv_du, s00, dsm, t00, dtm, nb);
     const bool pair = g.pair != 0;
     // along the cross index j the voxels of step m are contiguous in vol ([y][x], y-major rays)
     // or in vol_xt ([x][y], x-major rays); without vol_xt x-major rays read vol with stride n
@@ -170,13 +216,19 @@ __global__ void __launch_bounds__(256) fp2d_kernel(const Geo2D *__restrict__ geo
     T acc1 = (T)0, acc2 = (T)0;
     for (int m = 0; m < n; ++m) {
         const int2 vr = vials[m];
-        const double U = fma((double)m, dU, U00);
-        const double jA = ((double)b - 1.0 - U) * inv_du, jB = ((double)b + 1.0 - U) * inv_du;
-        const int jlo = (int)ceil(fmin(jA, jB) - 1e-9);
-        const double jl = (double)jlo;
-        const T d0 = (T)(fma(jl, du, U) - (double)b);
-        const T s0 = (T)fma(jl, dsj, fma((double)m, dsm, s00));
-        const T t0 = (T)fma(jl, dtj, fma((double)m, dtm, t00));
+        int jlo;
+        T d0, s0, t0;
+        if constexpr (sizeof(T) == 4) {
+            jlo = march_step_f32(mc32, m, dsj_t, dtj_t, d0, s0, t0);   // FP32 (see MarchF32)
+        } else {
+            const double U = fma((double)m, dU, U00);
+            const double jA = ((double)b - 1.0 - U) * inv_du, jB = ((double)b + 1.0 - U) * inv_du;
+            jlo = (int)ceil(fmin(jA, jB) - 1e-9);
+            const double jl = (double)jlo;
+            d0 = (T)(fma(jl, du, U) - (double)b);
+            s0 = (T)fma(jl, dsj, fma((double)m, dsm, s00));
+            t0 = (T)fma(jl, dtj, fma((double)m, dtm, t00));
+        }
         const T *row = base + m * sm;
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
