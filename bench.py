@@ -144,11 +144,10 @@ def recorded_traffic(kernel):
     return rec.get("bytes_per_launch")
 
 
-def in_solve_projector(tuning):
+def in_solve_projector(tuning, zc):
     """Name of the projector kernel an LP solve of the 256^3 x 360 workload runs (view pairs, 3
-    candidates per step; the masked operators use at most 16 slices per thread and, with the
-    asynchronous projector, walk their step lists one step per chunk)."""
-    zc = min(tuning["p3d_zc"], 16)
+    candidates per step, ``zc`` slices per thread as the solve reports it; with the asynchronous
+    projector the masked operator walks its step lists one step per chunk)."""
     if tuning["p3d_dma"]:
         return f"project3d_dma_kernel<{zc}, 3, true, {'true' if tuning['p3d_skip'] else 'false'}, 1, true>"
     return f"project3d_kernel<float, {zc}, 3, true>"
@@ -499,9 +498,10 @@ def probe(args, plan, dev):
     plan.autotune()
     f = torch.as_tensor(ellipsoids_target(plan.n, 3000), dtype=torch.float32, device=dev)
     lp = sipo.LP.build(plan, f, sipo.CASE1, band_width=10.0, f_min=1.0)
-    sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=32, tol=1e-12), want_dose=False)
+    r = sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=32, tol=1e-12, tune_operators=1),
+                   want_dose=False)
     torch.cuda.synchronize()
-    print("[probe] 32-iteration solve after autotune", file=sys.stderr, flush=True)
+    print(f"[probe] 32-iteration solve after autotune; masked operators {r['op_config']}", file=sys.stderr, flush=True)
     return 0
 
 
@@ -548,12 +548,13 @@ def main():
     # profiled solve of the same length (HIP events on the solve's stream) for the per-phase times
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=max(args.warmup, 1), tol=1e-12,
+        sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=max(args.warmup, 1), tol=1e-12, tune_operators=1,
                                          use_graph=1), want_dose=False)
         torch.cuda.synchronize()
         print(f"[bench] warmup {args.warmup} iterations done", file=sys.stderr, flush=True)
         lp.y.zero_(); lp.lam_up.zero_(); lp.lam_lo.zero_()
-        opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=args.steps, tol=1e-12, check_every=64, use_graph=1)
+        opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=args.steps, tol=1e-12, check_every=64, use_graph=1,
+                                 tune_operators=1, progress_every=1 << 30)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = sipo.solve(lp, opts, want_dose=False)
@@ -565,7 +566,8 @@ def main():
         print(f"[bench] {iters} iterations in {loop_s:.4f} s of solver loop ({dt:.4f} s for the whole call, "
               f"graph-captured blocks)", file=sys.stderr, flush=True)
         lp.y.zero_(); lp.lam_up.zero_(); lp.lam_lo.zero_()
-        popts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=args.steps, tol=1e-12, check_every=64, profile=1)
+        popts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=args.steps, tol=1e-12, check_every=64, profile=1,
+                                  tune_operators=1)
         torch.cuda.synchronize()
         tp0 = time.perf_counter()
         pres = sipo.solve(lp, popts, want_dose=False)
@@ -588,7 +590,7 @@ def main():
     dom = max(("project", "backproject"), key=lambda k: ph_avg[k])
     flops = 2.0 * (work["p_nnz_active"] if dom == "project" else work["bp_nnz_needed"])
     achieved = flops / (ph_avg[dom] * 1e-3) / 1e12
-    p_kernel = in_solve_projector(tuning)
+    p_kernel = in_solve_projector(tuning, pres["op_config"]["p_zc"])
     traffic = recorded_traffic(p_kernel) if (dom == "project" and not big) else None
     ops = full_operators(plan, dev, work)
     print(f"[bench] standalone operators (median of 20): {ops}", file=sys.stderr, flush=True)
@@ -601,7 +603,7 @@ def main():
         # graph-captured like the timed solve; the solver reports its residuals every 64 checks
         with torch.cuda.stream(stream):
             r = sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=args.ttk_iters, tol=1e-4, use_graph=1,
-                                                 progress_every=64), want_dose=False)
+                                                 progress_every=64, tune_operators=1), want_dose=False)
             torch.cuda.synchronize()
         ttk = {"seconds": round(time.perf_counter() - t1, 3), "iters": r["iters"], "status": r["status_name"],
                "restarts": r["restarts"], "objective": r["primal_obj"], "rel_primal": r["rel_primal"],
@@ -640,6 +642,9 @@ def main():
         "phase_ms": {k: round(v, 4) for k, v in ph_avg.items()},
         "profiled_solve_iters_per_s": round(pres["iters"] / (pres["loop_ms"] * 1e-3), 3),
         "tuning": tuning,
+        # the masked operators' work splits the solver's own tuning picked (timed and profiled solves)
+        "in_solve_ops": res["op_config"],
+        "in_solve_ops_profiled": pres["op_config"],
         "roofline": {"bound": "alu", "kernel": (p_kernel + " (LP rays)" if dom == "project" else "backproject3d (LP voxels)"),
                      "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic},

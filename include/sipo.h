@@ -310,6 +310,23 @@ typedef struct {
     int32_t progress_every;    /* restarted mode: > 0 writes one line to stderr every this
                                   many KKT checks, per unfinished instance (iterations,
                                   relative residuals, restarts); 0 = silent (>= 0)        */
+    int32_t tune_operators;    /* restarted mode, 3D instances: 1 = at setup, time the
+                                  masked operators' work splits on each instance's own
+                                  masks and run the fastest (projector 8 / 16 / 32 slices
+                                  per thread, backprojector 4 / 8 / 16 slices and 1 / 2 /
+                                  4 / 8 view splits, blur 4 / 8 slices per chunk; a few
+                                  tens of ms at 256^3).  The view split sets the
+                                  backprojector's summation order, so a tuned solve is
+                                  reproducible bit for bit only when it picks the same
+                                  splits (op_config in the result).  0 = fixed rules      */
+    int32_t op_config[4];      /* restarted mode, 3D instances: a nonzero entry fixes that
+                                  work split of the masked operators, as reported in the
+                                  result's op_config (projector slices per thread 8 / 16 /
+                                  32, the last FP32 only; backprojector slices per thread
+                                  4 / 8 / 16; backprojector view splits 1..8; blur slices
+                                  per chunk 4 / 8 / 16); passing a tuned result's
+                                  op_config back repeats that solve bit for bit.  Zero
+                                  entries are tuned or follow the fixed rules             */
 } sipo_pdhg_options;
 
 /* Phases of one PDHG iteration, for sipo_pdhg_result.phase_ms. */
@@ -345,6 +362,10 @@ typedef struct {
                                   ran.  iters / loop_ms is the steady iteration rate        */
     double phase_ms[SIPO_NUM_PHASES];       /* profile mode: summed launch durations          */
     int32_t phase_launches[SIPO_NUM_PHASES]; /* profile mode: launches timed per phase        */
+    int32_t op_config[4];      /* restarted mode, 3D instance: the masked operators' work
+                                  splits as run (projector slices per thread,
+                                  backprojector slices per thread, backprojector view
+                                  splits, blur slices per chunk); zeros otherwise          */
 } sipo_pdhg_result;
 
 /* Bytes of device workspace sipo_pdhg_solve needs for these problems. */

@@ -50,7 +50,8 @@ class PdhgOptions(C.Structure):
     _fields_ = [("mode", C.c_int32), ("max_iters", C.c_int32), ("check_every", C.c_int32), ("tol", C.c_double),
                 ("tau", C.c_double), ("sigma", C.c_double), ("power_iters", C.c_int32), ("eta", C.c_double),
                 ("infeas_tol", C.c_double), ("use_graph", C.c_int32), ("profile", C.c_int32),
-                ("scalar_weight", C.c_double), ("progress_every", C.c_int32)]
+                ("scalar_weight", C.c_double), ("progress_every", C.c_int32), ("tune_operators", C.c_int32),
+                ("op_config", C.c_int32 * 4)]
 
 NUM_PHASES = 7
 PHASES = ("project", "backproject", "blur", "transpose", "primal", "dual", "scalars")
@@ -62,12 +63,14 @@ class PdhgResult(C.Structure):
                 ("rel_primal", C.c_double), ("rel_dual", C.c_double), ("rel_gap", C.c_double),
                 ("u", C.c_double), ("v", C.c_double), ("tau", C.c_double), ("sigma", C.c_double),
                 ("omega", C.c_double), ("time_ms", C.c_double), ("loop_ms", C.c_double),
-                ("phase_ms", C.c_double * NUM_PHASES), ("phase_launches", C.c_int32 * NUM_PHASES)]
+                ("phase_ms", C.c_double * NUM_PHASES), ("phase_launches", C.c_int32 * NUM_PHASES),
+                ("op_config", C.c_int32 * 4)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("phase_")}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("phase_") and k != "op_config"}
         d["phase_ms"] = dict(zip(PHASES, list(self.phase_ms)))
         d["phase_launches"] = dict(zip(PHASES, list(self.phase_launches)))
+        d["op_config"] = dict(zip(("p_zc", "bp_zc", "bp_splits", "blur_zc"), list(self.op_config)))
         return d
 
 
@@ -414,10 +417,22 @@ class LP:
 
 
 def pdhg_options(mode=RESTARTED, max_iters=20000, check_every=64, tol=1e-4, tau=0.0, sigma=0.0, power_iters=100,
-                 eta=0.95, infeas_tol=1e-6, use_graph=0, profile=0, scalar_weight=0.0, progress_every=0):
+                 eta=0.95, infeas_tol=1e-6, use_graph=0, profile=0, scalar_weight=0.0, progress_every=0,
+                 tune_operators=0, op_config=None):
+    """Solver options.  op_config fixes the masked 3D operators' work splits: a dict with any of the
+    keys p_zc, bp_zc, bp_splits, blur_zc (as in a result's op_config) or a 4-sequence; 0 = free."""
+    keys = ("p_zc", "bp_zc", "bp_splits", "blur_zc")
+    if op_config is None:
+        oc = (0, 0, 0, 0)
+    elif isinstance(op_config, dict):
+        oc = tuple(int(op_config.get(k, 0)) for k in keys)
+    else:
+        oc = tuple(int(v) for v in op_config)
+        if len(oc) != 4:
+            raise ValueError("op_config needs 4 entries")
     return PdhgOptions(int(mode), int(max_iters), int(check_every), float(tol), float(tau), float(sigma),
                        int(power_iters), float(eta), float(infeas_tol), int(use_graph), int(profile),
-                       float(scalar_weight), int(progress_every))
+                       float(scalar_weight), int(progress_every), int(tune_operators), (C.c_int32 * 4)(*oc))
 
 
 def solve(lps, opts=None, want_dose=True, workspace=None):

@@ -973,6 +973,7 @@ class Solver {
     hipStream_t s_;
     bool b2d_ = false;
     bool mask_ = false;                     // 3D operators skip workgroups the LP does not read
+    bool masked_run_ = false;               // the iterations ran masked (mask_ ends before the last dose)
     std::vector<SplitSpec> psp_, bsp_;      // per instance: splits of the masked 3D operators
     std::vector<char> fused_;               // per instance: primal step fused into the masked projector
     std::vector<char> steps_;               // per instance: the masked projector walks its step lists
@@ -1287,6 +1288,164 @@ class Solver {
     }
     sipo_dtype I_dtype() const { return sizeof(T) == 8 ? SIPO_F64 : SIPO_F32; }
 
+    // ---- masked 3D operators: per-instance skip flags, step lists and splits for the plan's
+    // current slice counts.  bparts > 0 fixes the backprojector's view splits; 0 takes the rule:
+    // enough parts that the switched-on tiles give about four workgroups per CU.  The projector's
+    // march is split only when fewer of its workgroups stay on than there are CUs.
+    int cus_ = 256;
+    int mask_setup(int i, int bparts) {
+        const Inst &I = in_[i];
+        sipo_plan p = I.p;
+        auto count_on = [&](size_t flags_off, size_t count) -> long long {
+            std::vector<uint8_t> h(count);
+            if (count && hipMemcpyAsync(h.data(), U8(flags_off), count, hipMemcpyDeviceToHost, s_) != hipSuccess)
+                return -1;
+            if (hipStreamSynchronize(s_) != hipSuccess) return -1;
+            long long on = 0;
+            for (uint8_t f : h) on += f ? 1 : 0;
+            return on;
+        };
+        auto parts_for = [&](long long on, long long want, int max_parts) {
+            if (on <= 0) return 1;
+            return (int)std::min<long long>(max_parts, std::max<long long>(1, (want + on - 1) / on));
+        };
+        int rc = launch_p3d_flags(p, U8(L_.act) + I.soff, U8(L_.pflags) + L_.pfo[i], s_);
+        if (!rc) rc = launch_bp3d_flags(p, U8(L_.lab) + I.voff, U8(L_.bflags) + L_.bfo[i], s_);
+        if (!rc) rc = launch_blur_flags(p, U8(L_.lab) + I.voff, blur_own(i), blur_reach(i), s_);
+        if (!rc) rc = launch_vol_t_flags(p, blur_reach(i), vol_t_on(i), s_);
+        if (rc) return rc;
+        // the asynchronous projector walks only the march steps that can meet K z (FP32)
+        steps_[i] = 0;
+        if (sizeof(T) == 4 && p3d_steps_ok(p)) {
+            rc = launch_p3d_steps(p, U8(L_.lab) + I.voff, U8(L_.pflags) + L_.pfo[i], U8(L_.preach),
+                                  P<int>(L_.psteps + L_.pso[i]), P<int>(L_.pcount + L_.pco[i]), s_);
+            if (rc) return rc;
+            steps_[i] = 1;
+        }
+        const long long onp = count_on(L_.pflags + L_.pfo[i], p3d_flag_count(p));
+        const long long onb = count_on(L_.bflags + L_.bfo[i], bp3d_flag_count(p));
+        if (onp < 0 || onb < 0) return fail(SIPO_E_DEVICE, "pdhg setup: reading the skip flags failed");
+        psp_[i] = SplitSpec{parts_for(onp, cus_, kMaxSplitP), F(L_.ppart)};
+        bsp_[i] = SplitSpec{bparts > 0 ? std::min(bparts, kMaxSplitB) : parts_for(onb, 4LL * cus_, kMaxSplitB),
+                            F(L_.bpart)};
+        // the primal step rides in the projector's output when its march is not split (FP32)
+        fused_[i] = sizeof(T) == 4 && p->p3d_dma && psp_[i].parts == 1;
+        return SIPO_OK;
+    }
+
+    // Mean stream time (ms) of reps calls of fn after one untimed call.
+    template <typename Fn>
+    int time_launches(Fn fn, int reps, double &ms) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        SIPO_HIP(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return fail(SIPO_E_DEVICE, "hipEventCreate failed");
+        }
+        int rc = fn();
+        if (!rc) rc = hipEventRecord(e0, s_) == hipSuccess ? SIPO_OK : fail(SIPO_E_DEVICE, "hipEventRecord failed");
+        for (int r = 0; r < reps && !rc; ++r) rc = fn();
+        if (!rc) rc = hipEventRecord(e1, s_) == hipSuccess ? SIPO_OK : fail(SIPO_E_DEVICE, "hipEventRecord failed");
+        float t = 0.f;
+        if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+            rc = fail(SIPO_E_DEVICE, "operator timing failed");
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ms = t / reps;
+        return rc;
+    }
+
+    // Work splits of the masked operators timed on this instance's own masks: the projector's slices
+    // per thread, the backprojector's slices per thread and view splits, and the blur's slices per
+    // chunk; each is set to the fastest candidate (ties keep the earlier one).  Inputs are the zeroed
+    // working fields: the operators' work does not depend on the values.
+    int tune_masked(int i, int &bparts) {
+        const Inst &I = in_[i];
+        sipo_plan p = I.p;
+        constexpr int kReps = 3;
+        double ms = 0;
+        int rc = SIPO_OK;
+        auto proj = [&]() {
+            StepList sl;
+            if (steps_[i]) {
+                sl.steps = P<int>(L_.psteps + L_.pso[i]);
+                sl.count = P<int>(L_.pcount + L_.pco[i]);
+            }
+            return launch_project_t(p, F(L_.vol_t) + I.voff, F(L_.q) + I.soff, s_, U8(L_.pflags) + L_.pfo[i], psp_[i],
+                                    nullptr, sl);
+        };
+        auto back = [&]() {
+            SplitSpec sp = bsp_[i];
+            sp.keep_off = p->has_psf;
+            return launch_backproject_t(p, F(L_.yt) + I.soff, F(L_.tmp) + I.voff, 0, s_, U8(L_.bflags) + L_.bfo[i], sp);
+        };
+        auto blurs = [&]() {
+            int r = launch_blur(p, F(L_.tmp) + I.voff, F(L_.Dt) + I.voff, s_, blur_own(i), 0);
+            if (!r) r = launch_blur(p, F(L_.Dt) + I.voff, F(L_.tmp2) + I.voff, s_, blur_reach(i), 1);
+            return r;
+        };
+        // projector: 8, 16 or 32 slices per thread (the asynchronous variant only)
+        const int *fx = o_.op_config;   // nonzero entries are fixed by the caller
+        if (sizeof(T) == 4 && p->p3d_dma && p->nz % 4 == 0 && !fx[0]) {
+            int best = p->p3d_zc;
+            double best_ms = INFINITY;
+            for (int zc : {8, 16, 32}) {
+                if (zc > 8 && zc / 2 >= p->nz) break;
+                p->p3d_zc = zc;
+                rc = mask_setup(i, fx[2] ? fx[2] : bsp_[i].parts);
+                if (!rc) rc = time_launches(proj, kReps, ms);
+                if (rc) return rc;
+                if (ms < best_ms) { best_ms = ms; best = zc; }
+            }
+            p->p3d_zc = best;
+            tuned_.p_ms = best_ms;
+        }
+        // backprojector: 4, 8 or 16 slices per thread, each with 1, 2, 4 or 8 view splits
+        {
+            int best = p->bp3d_zc, best_parts = fx[2];
+            double best_ms = INFINITY;
+            for (int zc : {4, 8, 16}) {
+                if (fx[1] ? zc != fx[1] : (zc > 4 && zc / 2 >= p->nz)) continue;
+                p->bp3d_zc = zc;
+                for (int parts : {1, 2, 4, 8}) {
+                    if (fx[2] && parts != fx[2]) continue;
+                    rc = mask_setup(i, parts);
+                    if (!rc) rc = time_launches(back, kReps, ms);
+                    if (rc) return rc;
+                    if (ms < best_ms) { best_ms = ms; best = zc; best_parts = parts; }
+                }
+            }
+            p->bp3d_zc = best;
+            tuned_.bp_parts = best_parts;
+            tuned_.bp_ms = best_ms;
+        }
+        // blur (both masked applications of an iteration): 4 or 8 slices per chunk
+        if (p->has_psf && !fx[3]) {
+            int best = p->blur_zc;
+            double best_ms = INFINITY;
+            for (int zc : {4, 8}) {
+                if (zc > 4 && zc / 2 >= p->nz) break;
+                p->blur_zc = zc;
+                rc = mask_setup(i, tuned_.bp_parts);
+                if (!rc) rc = time_launches(blurs, kReps, ms);
+                if (rc) return rc;
+                if (ms < best_ms) { best_ms = ms; best = zc; }
+            }
+            p->blur_zc = best;
+            tuned_.k_ms = best_ms;
+        }
+        bparts = tuned_.bp_parts;
+        if (o_.progress_every > 0)
+            fprintf(stderr, "[sipo] instance %d: masked operators tuned: P %d slices/thread %.4f ms, P^T %d slices/thread "
+                    "x %d view splits %.4f ms, blur %d slices/chunk %.4f ms (both applications)\n", i, p->p3d_zc,
+                    tuned_.p_ms, p->bp3d_zc, bparts, tuned_.bp_ms, p->has_psf ? p->blur_zc : 0, tuned_.k_ms);
+        return SIPO_OK;
+    }
+    struct Tuned {
+        int bp_parts = 0;
+        double p_ms = 0, bp_ms = 0, k_ms = 0;
+    } tuned_;
+
     // ---- profile mode: a timeline of events between consecutive iteration launches
     bool prof_on_ = false;
     std::vector<hipEvent_t> ev_;
@@ -1460,25 +1619,12 @@ int Solver<T>::setup_common() {
         // backprojector's view walk is split so that the switched-on tiles give about four workgroups
         // per CU, and the projector's march is split only when very few of its workgroups stay on.  The
         // plans' own settings are restored when the solver ends.
-        int cus = 256;
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, probs_[0].plan->device);
+        cus_ = 256;
+        (void)hipDeviceGetAttribute(&cus_, hipDeviceAttributeMultiprocessorCount, probs_[0].plan->device);
         psp_.assign(B_, SplitSpec());
         bsp_.assign(B_, SplitSpec());
         fused_.assign(B_, 0);
         steps_.assign(B_, 0);
-        auto count_on = [&](size_t flags_off, size_t count) -> long long {
-            std::vector<uint8_t> h(count);
-            if (count && hipMemcpyAsync(h.data(), U8(flags_off), count, hipMemcpyDeviceToHost, s_) != hipSuccess)
-                return -1;
-            if (hipStreamSynchronize(s_) != hipSuccess) return -1;
-            long long on = 0;
-            for (uint8_t f : h) on += f ? 1 : 0;
-            return on;
-        };
-        auto parts_for = [&](long long on, long long want, int max_parts) {
-            if (on <= 0) return 1;
-            return (int)std::min<long long>(max_parts, std::max<long long>(1, (want + on - 1) / on));
-        };
         for (int i = 0; i < B_; ++i) {
             const Inst &I = in_[i];
             if (!I.t3) continue;
@@ -1487,33 +1633,41 @@ int Solver<T>::setup_common() {
             for (auto &e : zc_saved_) seen = seen || e.p == p;
             if (!seen) {
                 zc_saved_.push_back({p, p->p3d_zc, p->bp3d_zc, p->blur_zc});
-                p->blur_zc = std::min(kMaskBlurZc, p->nz);
-                p->p3d_zc = std::min(p->p3d_zc, 16);
-                p->bp3d_zc = std::min(p->bp3d_zc, 8);
+                p->blur_zc = o_.op_config[3] ? o_.op_config[3] : std::min(kMaskBlurZc, p->nz);
+                p->p3d_zc = o_.op_config[0] ? o_.op_config[0] : std::min(p->p3d_zc, 16);
+                p->bp3d_zc = o_.op_config[1] ? o_.op_config[1] : std::min(p->bp3d_zc, 8);
             }
-            rc = launch_p3d_flags(p, U8(L_.act) + I.soff, U8(L_.pflags) + L_.pfo[i], s_);
-            if (!rc) rc = launch_bp3d_flags(p, U8(L_.lab) + I.voff, U8(L_.bflags) + L_.bfo[i], s_);
-            if (!rc) rc = launch_blur_flags(p, U8(L_.lab) + I.voff, blur_own(i), blur_reach(i), s_);
-            if (!rc) rc = launch_vol_t_flags(p, blur_reach(i), vol_t_on(i), s_);
+            rc = mask_setup(i, o_.op_config[2]);
             if (rc) return rc;
-            // the asynchronous projector walks only the march steps that can meet K z (FP32)
-            if (!rc && sizeof(T) == 4 && p3d_steps_ok(p)) {
-                rc = launch_p3d_steps(p, U8(L_.lab) + I.voff, U8(L_.pflags) + L_.pfo[i], U8(L_.preach),
-                                      P<int>(L_.psteps + L_.pso[i]), P<int>(L_.pcount + L_.pco[i]), s_);
-                steps_[i] = 1;
-            }
-            if (rc) return rc;
-            const long long onp = count_on(L_.pflags + L_.pfo[i], p3d_flag_count(p));
-            const long long onb = count_on(L_.bflags + L_.bfo[i], bp3d_flag_count(p));
-            if (onp < 0 || onb < 0) return fail(SIPO_E_DEVICE, "pdhg setup: reading the skip flags failed");
-            psp_[i] = SplitSpec{parts_for(onp, cus, kMaxSplitP), F(L_.ppart)};
-            bsp_[i] = SplitSpec{parts_for(onb, 4LL * cus, kMaxSplitB), F(L_.bpart)};
-            // the primal step rides in the projector's output when its march is not split (FP32)
-            fused_[i] = sizeof(T) == 4 && p->p3d_dma && psp_[i].parts == 1;
         }
-        mask_ = true;
+        mask_ = masked_run_ = true;
         fill_vol(L_.vol_t);   // zero where the masked transposes never write
         fill_vol(L_.tmp);     // finite where the masked backprojector leaves tiles as they are
+        if (o_.tune_operators) {
+            // tune on the first instance of each plan, then rebuild every instance's flags for the
+            // plan's chosen slice counts (instances of one plan share them)
+            std::vector<std::pair<sipo_plan, int>> chosen;   // plan, backprojector view splits
+            for (int i = 0; i < B_; ++i) {
+                if (!in_[i].t3) continue;
+                bool seen = false;
+                for (auto &c : chosen) seen = seen || c.first == in_[i].p;
+                if (seen) continue;
+                int parts = 0;
+                rc = tune_masked(i, parts);
+                if (rc) return rc;
+                chosen.push_back({in_[i].p, parts});
+            }
+            for (int i = 0; i < B_; ++i) {
+                if (!in_[i].t3) continue;
+                int parts = 0;
+                for (auto &c : chosen)
+                    if (c.first == in_[i].p) parts = c.second;
+                rc = mask_setup(i, parts);
+                if (rc) return rc;
+            }
+            fill_vol(L_.vol_t);
+            fill_vol(L_.tmp);
+        }
     }
     rc = live_tables();
     if (rc) return rc;
@@ -2106,6 +2260,13 @@ int Solver<T>::run(sipo_pdhg_result *res) {
             r.phase_ms[ph] = phase_ms_[ph];
             r.phase_launches[ph] = phase_n_[ph];
         }
+        for (int k = 0; k < 4; ++k) r.op_config[k] = 0;
+        if (masked_run_ && I.t3) {
+            r.op_config[0] = I.p->p3d_zc;
+            r.op_config[1] = I.p->bp3d_zc;
+            r.op_config[2] = bsp_[i].parts;
+            r.op_config[3] = I.p->has_psf ? I.p->blur_zc : 0;
+        }
     }
     return SIPO_OK;
 }
@@ -2128,6 +2289,18 @@ static int validate(const sipo_problem &pb, const sipo_pdhg_options &o, int idx,
     SIPO_REQUIRE(!(o.eta >= 1.0), "eta must be < 1");
     SIPO_REQUIRE(std::isfinite(o.scalar_weight) && o.scalar_weight >= 0, "scalar_weight must be finite and >= 0");
     SIPO_REQUIRE(o.progress_every >= 0, "progress_every must be >= 0");
+    SIPO_REQUIRE(o.tune_operators == 0 || o.tune_operators == 1, "tune_operators must be 0 or 1");
+    {
+        const int *c = o.op_config;
+        SIPO_REQUIRE(c[0] == 0 || c[0] == 8 || c[0] == 16 || c[0] == 32, "op_config[0] (projector slices per thread) "
+                     "must be 0, 8, 16 or 32, not %d", c[0]);
+        SIPO_REQUIRE(c[1] == 0 || c[1] == 4 || c[1] == 8 || c[1] == 16, "op_config[1] (backprojector slices per thread) "
+                     "must be 0, 4, 8 or 16, not %d", c[1]);
+        SIPO_REQUIRE(c[2] >= 0 && c[2] <= kMaxSplitB, "op_config[2] (backprojector view splits) must be in [0, %d], not %d",
+                     kMaxSplitB, c[2]);
+        SIPO_REQUIRE(c[3] == 0 || c[3] == 4 || c[3] == 8 || c[3] == 16, "op_config[3] (blur slices per chunk) must be "
+                     "0, 4, 8 or 16, not %d", c[3]);
+    }
     return SIPO_OK;
 }
 

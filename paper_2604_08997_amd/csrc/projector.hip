@@ -1232,8 +1232,8 @@ template <int ZC, int NC, bool PAIR, bool SKIP>
 static void fp3d_dma_go(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
                         const SplitSpec &sp, const PrimalFuse &fz, const StepList &sl) {
     // 64 slices stage one step per chunk only: three two-step buffers would not fit in LDS; step
-    // lists (masked solves: 8 or 16 slices) walk one listed step per chunk
-    if constexpr (ZC <= 16) {
+    // lists (masked solves: 8, 16 or 32 slices) walk one listed step per chunk
+    if constexpr (ZC <= 32) {
         if (sl.steps) {
             fp3d_dma_launch<ZC, NC, PAIR, SKIP, 1, true>(p, vol_t, sino_t, s, on, sp, fz, sl);
             return;
@@ -1353,9 +1353,9 @@ int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s
                      const SplitSpec &sp, const PrimalFuse *fuse, const StepList &sl) {
     if (fuse && (!p->fast3d() || p->dtype != SIPO_F32 || p->p2d_ok))
         return fail(SIPO_E_UNSUPPORTED, "the fused primal step needs an FP32 3D plan");
-    if (sl.steps && (!p->fast3d() || p->p2d_ok || !wg_on || !p->p3d_dma || p->p3d_zc > 16 || p->n > kMaxListSteps))
+    if (sl.steps && (!p->fast3d() || p->p2d_ok || !wg_on || !p->p3d_dma || p->p3d_zc > 32 || p->n > kMaxListSteps))
         return fail(SIPO_E_UNSUPPORTED, "projector step lists need a 3D plan with the asynchronous projector at "
-                    "8 or 16 slices per thread, workgroup flags and n <= %d", kMaxListSteps);
+                    "8, 16 or 32 slices per thread, workgroup flags and n <= %d", kMaxListSteps);
     if (p->p2d_ok) return fp2d_plan(p, vol_t, sino_t, 0, s);
     if (!p->fast3d())
         return p->dtype == SIPO_F64 ? fp_slices<double>(p, vol_t, sino_t, 0, s)
@@ -1495,7 +1495,7 @@ __global__ void __launch_bounds__(256) k_p3d_steps(const int4 *__restrict__ batc
 }
 
 bool p3d_steps_ok(sipo_plan p) {
-    return p->fast3d() && p->p3d_dma && p->d_ranges && p->p3d_zc <= 16 && p->n <= kMaxListSteps;
+    return p->fast3d() && p->p3d_dma && p->d_ranges && p->p3d_zc <= 32 && p->n <= kMaxListSteps;
 }
 
 size_t p3d_reach_bytes(sipo_plan p, int zc) {

@@ -1,0 +1,109 @@
+"""Work splits of the masked 3D operators inside a restarted solve (Sec. 2.8 solver, Eq. 50-51 operators).
+
+The solver runs the LP's operators masked to what the LP reads, and the split of that work (slices per
+thread of the projector and backprojector, view splits of the backprojector, slices per blur chunk) can
+be tuned at setup on the instance's own masks or fixed by the caller.  Every choice must compute the
+same operators: the returned states are checked against the oracle's FP64 KKT residuals (Supp. 6.1,
+Eq. 47-51), and a choice passed back repeats its solve bit for bit.  (Different choices regroup the
+projector's partial sums when its march is split and the backprojector's when its views are, so
+their iterates agree only to rounding.)
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lp as olp, kkt as okkt, blur as oblur
+from oracle.geometry import make_geometry
+from oracle.projector import Projector
+from sipo_inputs import ellipsoids_target, angles_uniform
+
+pytestmark = pytest.mark.gpu
+
+N, NZ, NA, SIGMA, SEED = 48, 48, 36, (1.5, 1.5, 1.5), 3210
+ITERS = 640
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def target():
+    return ellipsoids_target(N, SEED, count=3, nz=NZ)
+
+
+def gpu_lp():
+    import paper_2604_08997_amd as sipo
+    plan = sipo.Plan(N, list(angles_uniform(NA)), nz=NZ, sigma=SIGMA, dtype=torch.float32, device=dev())
+    lp = sipo.LP.build(plan, torch.as_tensor(target(), dtype=torch.float32, device=dev()), sipo.CASE1,
+                       band_width=4.0, f_min=1.0)
+    return plan, lp
+
+
+def run(**kw):
+    import paper_2604_08997_amd as sipo
+    plan, lp = gpu_lp()
+    r = sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=ITERS, tol=1e-12, check_every=64, **kw))
+    st = [t.double().cpu().numpy().copy() for t in (lp.y, lp.lam_up, lp.lam_lo)]
+    return r, st
+
+
+@pytest.fixture(scope="module")
+def oracle_lp():
+    taps = oblur.psf_taps(SIGMA)
+    return olp.build(Projector(make_geometry(N, angles_uniform(NA), nz=NZ, atten=1.0)), target(), olp.CASE1,
+                     taps=taps, band_width=4.0)
+
+
+def check_against_oracle(op, r, st):
+    y, lu, ll = st
+    k = okkt.residuals(op, y, r["u"], r["v"], lu, ll)
+    assert k.primal_obj == pytest.approx(r["primal_obj"], rel=1e-5)
+    for got, want in ((r["rel_primal"], k.eps_p), (r["rel_dual"], k.eps_d), (r["rel_gap"], k.eps_gap)):
+        assert got == pytest.approx(want, rel=2e-2, abs=1e-7), (got, want)
+
+
+def test_fixed_slice_counts_match_oracle_kkt(oracle_lp):
+    # the fixed-rule solve, then projector / backprojector / blur slice counts fixed by the caller
+    # (32 slices per projector thread is a ragged chunk at 48 slices)
+    base_r, base_st = run()
+    cfg = base_r["op_config"]
+    assert cfg["p_zc"] in (8, 16) and cfg["bp_zc"] in (4, 8) and 1 <= cfg["bp_splits"] <= 8 and cfg["blur_zc"] == 4
+    check_against_oracle(oracle_lp, base_r, base_st)
+    for p_zc, bp_zc, blur_zc in ((32, 4, 8), (8, 16, 16)):
+        want = {"p_zc": p_zc, "bp_zc": bp_zc, "bp_splits": cfg["bp_splits"], "blur_zc": blur_zc}
+        r, st = run(op_config=want)
+        assert r["op_config"] == want
+        check_against_oracle(oracle_lp, r, st)
+        assert r["primal_obj"] == pytest.approx(base_r["primal_obj"], rel=1e-3)
+
+
+def test_other_view_splits_match_oracle_kkt(oracle_lp):
+    for splits in (1, 3, 8):
+        r, st = run(op_config={"p_zc": 32, "bp_zc": 16, "bp_splits": splits})
+        assert r["op_config"]["bp_splits"] == splits
+        check_against_oracle(oracle_lp, r, st)
+
+
+def test_tuned_solve_picks_candidates_and_repeats_bit_for_bit(oracle_lp, capfd):
+    r, st = run(tune_operators=1, progress_every=1 << 20)
+    err = capfd.readouterr().err
+    assert "masked operators tuned" in err
+    cfg = r["op_config"]
+    assert cfg["p_zc"] in (8, 16, 32) and cfg["bp_zc"] in (4, 8, 16)
+    assert cfg["bp_splits"] in (1, 2, 4, 8) and cfg["blur_zc"] in (4, 8)
+    check_against_oracle(oracle_lp, r, st)
+    # the reported splits, passed back, repeat the tuned solve exactly
+    r2, st2 = run(op_config=cfg)
+    assert r2["op_config"] == cfg and r2["primal_obj"] == r["primal_obj"]
+    for a, b in zip(st, st2):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_invalid_work_splits_are_rejected():
+    import paper_2604_08997_amd as sipo
+    plan, lp = gpu_lp()
+    for bad in ({"p_zc": 12}, {"bp_zc": 32}, {"bp_splits": 9}, {"blur_zc": 2}):
+        with pytest.raises(RuntimeError, match="op_config"):
+            sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=64, op_config=bad))
+    with pytest.raises(RuntimeError, match="tune_operators"):
+        sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=64, tune_operators=2))
