@@ -144,12 +144,14 @@ def recorded_traffic(kernel):
     return rec.get("bytes_per_launch")
 
 
-def in_solve_projector(tuning, zc):
+def in_solve_projector(tuning, ops):
     """Name of the projector kernel an LP solve of the 256^3 x 360 workload runs (view pairs, 3
-    candidates per step, ``zc`` slices per thread as the solve reports it; with the asynchronous
-    projector the masked operator walks its step lists one step per chunk)."""
+    candidates per step, slices per thread and work queue as the solve reports them in ``ops``;
+    with the asynchronous projector the masked operator walks its step lists one step per chunk)."""
+    zc = ops["p_zc"]
     if tuning["p3d_dma"]:
-        return f"project3d_dma_kernel<{zc}, 3, true, {'true' if tuning['p3d_skip'] else 'false'}, 1, true>"
+        queue = "true" if ops.get("p_queue", -1) > 0 else "false"
+        return f"project3d_dma_kernel<{zc}, 3, true, {'true' if tuning['p3d_skip'] else 'false'}, 1, true, {queue}>"
     return f"project3d_kernel<float, {zc}, 3, true>"
 
 
@@ -590,7 +592,7 @@ def main():
     dom = max(("project", "backproject"), key=lambda k: ph_avg[k])
     flops = 2.0 * (work["p_nnz_active"] if dom == "project" else work["bp_nnz_needed"])
     achieved = flops / (ph_avg[dom] * 1e-3) / 1e12
-    p_kernel = in_solve_projector(tuning, pres["op_config"]["p_zc"])
+    p_kernel = in_solve_projector(tuning, pres["op_config"])
     traffic = recorded_traffic(p_kernel) if (dom == "project" and not big) else None
     ops = full_operators(plan, dev, work)
     print(f"[bench] standalone operators (median of 20): {ops}", file=sys.stderr, flush=True)

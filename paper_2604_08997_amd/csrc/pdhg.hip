@@ -771,6 +771,7 @@ struct Layout {
     std::vector<size_t> pso, pco;               // and of its projector step lists and step counts
     size_t ps_bytes = 0, pc_bytes = 0, reach_bytes = 0;
     size_t psteps = 0, pcount = 0, preach = 0;  // their fields; the reach masks of the list builder
+    size_t pitems = 0, pqueue = 0;              // the projector's work queue: tiles (offsets pco) and counters
     std::vector<size_t> kfo;                    // and of its two blur tile flag arrays (own, reach)
     size_t kf_bytes = 0, kflags = 0;
     size_t pf_bytes = 0, bf_bytes = 0;          // projector / backprojector flag totals
@@ -796,6 +797,7 @@ constexpr int kMaxSplitP = 4, kMaxSplitB = 8;
 // slices per blur tile in masked solves: a blur workgroup streams its slices and the PSF halo one by
 // one, so the few tiles left on run shortest with short chunks
 constexpr int kMaskBlurZc = 4;
+constexpr size_t kQueueStride = 256;   // bytes per instance of the projector's work-queue counters
 
 static bool use_batch2d(const sipo_problem *probs, int B) {
     for (int i = 0; i < B; ++i) {
@@ -874,6 +876,8 @@ static Layout make_layout(const sipo_problem *probs, int B) {
     L.bflags = take(L.bf_bytes);
     L.psteps = take(L.ps_bytes);
     L.pcount = take(L.pc_bytes);
+    L.pitems = take(L.pc_bytes);
+    L.pqueue = take((size_t)kQueueStride * B);
     L.preach = take(L.reach_bytes);
     L.kflags = take(L.kf_bytes);
     L.ppart = take(L.part_s * L.eb * kMaxSplitP);
@@ -1273,11 +1277,7 @@ class Solver {
                         fz.w_rho = &scal()[i].w;
                     }
                 }
-                StepList sl;
-                if (m && !steps_.empty() && steps_[i]) {
-                    sl.steps = P<int>(L_.psteps + L_.pso[i]);
-                    sl.count = P<int>(L_.pcount + L_.pco[i]);
-                }
+                const StepList sl = m ? step_list(i, false) : StepList();
                 rc = launch_project_t(I.p, src, out, s_, m ? U8(L_.pflags) + L_.pfo[i] : nullptr,
                                       m ? psp_[i] : SplitSpec(), fuse ? &fz : nullptr, sl);
             }
@@ -1328,9 +1328,51 @@ class Solver {
         psp_[i] = SplitSpec{parts_for(onp, cus_, kMaxSplitP), F(L_.ppart)};
         bsp_[i] = SplitSpec{bparts > 0 ? std::min(bparts, kMaxSplitB) : parts_for(onb, 4LL * cus_, kMaxSplitB),
                             F(L_.bpart)};
-        // the primal step rides in the projector's output when its march is not split (FP32)
-        fused_[i] = sizeof(T) == 4 && p->p3d_dma && psp_[i].parts == 1;
+        // the primal step rides in the projector's output when its march is not split (FP32), unless
+        // it is set to run as its own kernel
+        fused_[i] = sizeof(T) == 4 && p->p3d_dma && psp_[i].parts == 1 && pfuse_[i] >= 0;
+        // the unsplit listed march takes its switched-on workgroups from a queue, longest list first
+        n_pitems_[i] = 0;
+        if (steps_[i] && psp_[i].parts == 1) {
+            const size_t cnt = p3d_flag_count(p);
+            std::vector<int> hc(cnt);
+            std::vector<uint8_t> hf(cnt);
+            if (cnt && (hipMemcpyAsync(hc.data(), P<int>(L_.pcount + L_.pco[i]), sizeof(int) * cnt,
+                                       hipMemcpyDeviceToHost, s_) != hipSuccess ||
+                        hipMemcpyAsync(hf.data(), U8(L_.pflags) + L_.pfo[i], cnt, hipMemcpyDeviceToHost, s_) !=
+                            hipSuccess ||
+                        hipStreamSynchronize(s_) != hipSuccess))
+                return fail(SIPO_E_DEVICE, "pdhg setup: reading the projector's step counts failed");
+            std::vector<int> items;
+            for (size_t w = 0; w < cnt; ++w)
+                if (hf[w]) items.push_back((int)w);
+            std::stable_sort(items.begin(), items.end(), [&](int a, int b) { return hc[a] > hc[b]; });
+            if (!items.empty()) {
+                SIPO_HIP(hipMemcpyAsync(P<int>(L_.pitems + L_.pco[i]), items.data(), sizeof(int) * items.size(),
+                                        hipMemcpyHostToDevice, s_));
+                SIPO_HIP(hipMemsetAsync(U8(L_.pqueue) + kQueueStride * i, 0, 2 * sizeof(int), s_));
+                SIPO_HIP(hipStreamSynchronize(s_));
+            }
+            n_pitems_[i] = (int)items.size();
+        }
         return SIPO_OK;
+    }
+    std::vector<int> n_pitems_;   // per instance: tiles in the projector's work queue
+    std::vector<int> pqueue_;     // per instance: queue workgroups per CU (-1 = one workgroup per tile)
+    std::vector<int> pfuse_;      // per instance: -1 = the primal step runs as its own kernel
+    StepList step_list(int i, bool off_unread) {
+        StepList sl;
+        if (steps_.empty() || !steps_[i]) return sl;
+        sl.steps = P<int>(L_.psteps + L_.pso[i]);
+        sl.count = P<int>(L_.pcount + L_.pco[i]);
+        if (n_pitems_[i] > 0 && pqueue_[i] > 0) {
+            sl.items = P<int>(L_.pitems + L_.pco[i]);
+            sl.n_items = n_pitems_[i];
+            sl.queue = P<int>(L_.pqueue + kQueueStride * i);
+            sl.queue_per_cu = pqueue_[i];
+            sl.off_unread = off_unread;
+        }
+        return sl;
     }
 
     // Mean stream time (ms) of reps calls of fn after one untimed call.
@@ -1366,13 +1408,28 @@ class Solver {
         double ms = 0;
         int rc = SIPO_OK;
         auto proj = [&]() {
-            StepList sl;
-            if (steps_[i]) {
-                sl.steps = P<int>(L_.psteps + L_.pso[i]);
-                sl.count = P<int>(L_.pcount + L_.pco[i]);
+            // as the iteration runs it: the primal step fused where it is fused there, else the primal
+            // kernel after the projector, but writing fields that setup fills afterwards (q, T_j) instead
+            // of y and t.y; timing only, so the queue's unwritten outputs of switched-off tiles are
+            // never read
+            PrimalFuse fz;
+            const bool fuse = sizeof(T) == 4 && fused_[i];
+            if constexpr (sizeof(T) == 4) {
+                fz.y = F(L_.q) + I.soff;
+                fz.yt = F(L_.Tj) + I.soff;
+                fz.Tj = F(L_.Tj) + I.soff;
+                fz.y0 = F(L_.y0) + I.soff;
+                fz.act = U8(L_.act) + I.soff;
+                fz.tau_fac = &scal()[i].tau_fac;
+                fz.w_rho = &scal()[i].w;
             }
-            return launch_project_t(p, F(L_.vol_t) + I.voff, F(L_.q) + I.soff, s_, U8(L_.pflags) + L_.pfo[i], psp_[i],
-                                    nullptr, sl);
+            int r = launch_project_t(p, F(L_.vol_t) + I.voff, F(L_.q) + I.soff, s_, U8(L_.pflags) + L_.pfo[i],
+                                     psp_[i], fuse ? &fz : nullptr, step_list(i, true));
+            if (!r && !fuse && n_seg_s_)
+                hipLaunchKernelGGL((k_primal<T, true>), gS(), dim3(kThreads), 0, s_, F(L_.Tj), F(L_.Tj),
+                                   (const T *)F(L_.q), (const T *)F(L_.Tj), (const uint8_t *)U8(L_.act),
+                                   (const T *)F(L_.y0), (const DevScal *)scal(), segS());
+            return r;
         };
         auto back = [&]() {
             SplitSpec sp = bsp_[i];
@@ -1387,17 +1444,28 @@ class Solver {
         // projector: 8, 16 or 32 slices per thread (the asynchronous variant only)
         const int *fx = o_.op_config;   // nonzero entries are fixed by the caller
         if (sizeof(T) == 4 && p->p3d_dma && p->nz % 4 == 0 && !fx[0]) {
-            int best = p->p3d_zc;
+            int best = p->p3d_zc, best_q = pqueue_[i], best_f = pfuse_[i];
             double best_ms = INFINITY;
             for (int zc : {8, 16, 32}) {
                 if (zc > 8 && zc / 2 >= p->nz) break;
                 p->p3d_zc = zc;
-                rc = mask_setup(i, fx[2] ? fx[2] : bsp_[i].parts);
-                if (!rc) rc = time_launches(proj, kReps, ms);
-                if (rc) return rc;
-                if (ms < best_ms) { best_ms = ms; best = zc; }
+                for (int pf : {1, -1}) {
+                    if (fx[5] && pf != fx[5]) continue;
+                    pfuse_[i] = pf;
+                    rc = mask_setup(i, fx[2] ? fx[2] : bsp_[i].parts);
+                    if (rc) return rc;
+                    for (int qw : {-1, 2, 3, 4, 6, 16}) {   // 16: as many as fit
+                        if (fx[4] && qw != fx[4]) continue;
+                        pqueue_[i] = qw;
+                        rc = time_launches(proj, kReps, ms);
+                        if (rc) return rc;
+                        if (ms < best_ms) { best_ms = ms; best = zc; best_q = qw; best_f = pf; }
+                    }
+                }
             }
             p->p3d_zc = best;
+            pqueue_[i] = best_q;
+            pfuse_[i] = best_f;
             tuned_.p_ms = best_ms;
         }
         // backprojector: 4, 8 or 16 slices per thread, each with 1, 2, 4 or 8 view splits
@@ -1436,9 +1504,10 @@ class Solver {
         }
         bparts = tuned_.bp_parts;
         if (o_.progress_every > 0)
-            fprintf(stderr, "[sipo] instance %d: masked operators tuned: P %d slices/thread %.4f ms, P^T %d slices/thread "
-                    "x %d view splits %.4f ms, blur %d slices/chunk %.4f ms (both applications)\n", i, p->p3d_zc,
-                    tuned_.p_ms, p->bp3d_zc, bparts, tuned_.bp_ms, p->has_psf ? p->blur_zc : 0, tuned_.k_ms);
+            fprintf(stderr, "[sipo] instance %d: masked operators tuned: P %d slices/thread, queue %d/CU, primal step "
+                    "%s %.4f ms, P^T %d slices/thread x %d view splits %.4f ms, blur %d slices/chunk %.4f ms (both "
+                    "applications)\n", i, p->p3d_zc, pqueue_[i], pfuse_[i] > 0 ? "fused" : "separate", tuned_.p_ms,
+                    p->bp3d_zc, bparts, tuned_.bp_ms, p->has_psf ? p->blur_zc : 0, tuned_.k_ms);
         return SIPO_OK;
     }
     struct Tuned {
@@ -1625,6 +1694,9 @@ int Solver<T>::setup_common() {
         bsp_.assign(B_, SplitSpec());
         fused_.assign(B_, 0);
         steps_.assign(B_, 0);
+        n_pitems_.assign(B_, 0);
+        pqueue_.assign(B_, o_.op_config[4] ? o_.op_config[4] : -1);
+        pfuse_.assign(B_, o_.op_config[5] ? o_.op_config[5] : 1);
         for (int i = 0; i < B_; ++i) {
             const Inst &I = in_[i];
             if (!I.t3) continue;
@@ -2260,12 +2332,15 @@ int Solver<T>::run(sipo_pdhg_result *res) {
             r.phase_ms[ph] = phase_ms_[ph];
             r.phase_launches[ph] = phase_n_[ph];
         }
-        for (int k = 0; k < 4; ++k) r.op_config[k] = 0;
+        for (int k = 0; k < 6; ++k) r.op_config[k] = 0;
         if (masked_run_ && I.t3) {
             r.op_config[0] = I.p->p3d_zc;
             r.op_config[1] = I.p->bp3d_zc;
             r.op_config[2] = bsp_[i].parts;
             r.op_config[3] = I.p->has_psf ? I.p->blur_zc : 0;
+            const bool queued = !pqueue_.empty() && pqueue_[i] > 0 && steps_[i] && psp_[i].parts == 1;
+            r.op_config[4] = queued ? pqueue_[i] : -1;
+            r.op_config[5] = fused_[i] ? 1 : -1;
         }
     }
     return SIPO_OK;
@@ -2300,6 +2375,8 @@ static int validate(const sipo_problem &pb, const sipo_pdhg_options &o, int idx,
                      kMaxSplitB, c[2]);
         SIPO_REQUIRE(c[3] == 0 || c[3] == 4 || c[3] == 8 || c[3] == 16, "op_config[3] (blur slices per chunk) must be "
                      "0, 4, 8 or 16, not %d", c[3]);
+        SIPO_REQUIRE(c[4] >= -1 && c[4] <= 16, "op_config[4] (projector work queue) must be in [-1, 16], not %d", c[4]);
+        SIPO_REQUIRE(c[5] >= -1 && c[5] <= 1, "op_config[5] (primal step) must be -1, 0 or 1, not %d", c[5]);
     }
     return SIPO_OK;
 }

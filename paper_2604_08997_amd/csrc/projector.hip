@@ -588,25 +588,32 @@ __device__ __forceinline__ void ring_barrier() {
 }
 
 constexpr int kMaxListSteps = 1024;   // longest march that step lists serve
-template <int ZC, int NC, bool PAIR, bool SKIP, int CM, bool LIST>
-__global__ void __launch_bounds__(256) project3d_dma_kernel(
+// A listed step's record, packed in 8 bytes: x = m | cross count << 10 | (first cross index + bias)
+// << 17 (m < 1024, count <= kPCR < 128, 12 bits for the biased first index); y = vial interval of
+// the step's grid line, lo | hi << 16.
+constexpr int kListJ0Bias = 1024;
+template <int ZC, int CM>
+struct DmaRing {
+    static constexpr int Z4 = ZC / 4, RS = kPCR + 1, SLOTS = CM * Z4 * RS, PER = (SLOTS + 255) / 256;
+};
+
+// One workgroup tile (bin group tile.x, view batch tile.y, z chunk x march split tile.z) of a
+// grid of gx bin groups and gz z entries.  bufA..C and smeta are the kernel's LDS arrays.
+template <int ZC, int NC, bool PAIR, bool SKIP, int CM, bool LIST, bool QUEUE>
+__device__ __forceinline__ void p3d_dma_tile(
     const float *__restrict__ vol_t, float *__restrict__ sino_t, int n, int nz, int nb,
     const double2 *__restrict__ trig, const int *__restrict__ order, const int *__restrict__ partner,
     const int4 *__restrict__ batches, const int2 *__restrict__ ranges, const int2 *__restrict__ vial_rows,
     const float4 *__restrict__ zero16, double h, double inv_ds, float atten, const uint8_t *__restrict__ wg_on,
-    int nsplit, long long split_stride, PrimalFuse fz, const int *__restrict__ step_list,
-    const int *__restrict__ step_cnt) {
+    int nsplit, long long split_stride, const PrimalFuse &fz, const int *__restrict__ step_list,
+    const int *__restrict__ step_cnt, int3 tile, int gx, int gz, float4 *bufA, float4 *bufB, float4 *bufC,
+    int2 *smeta) {
     static_assert(CM >= 1 && CM <= kDmaMaxCM, "chunk length");
     static_assert(!LIST || CM == 1, "step lists walk one step per chunk");
-    constexpr int Z4 = ZC / 4, RS = kPCR + 1, SLOTS = CM * Z4 * RS, PER = (SLOTS + 255) / 256;
+    constexpr int Z4 = DmaRing<ZC, CM>::Z4, RS = DmaRing<ZC, CM>::RS, SLOTS = DmaRing<ZC, CM>::SLOTS;
+    constexpr int PER = DmaRing<ZC, CM>::PER;
     constexpr int NR = PAIR ? 2 : 1;
-    // three separate arrays, not one indexed ring: the compiler tells LDS variables apart when it
-    // decides which staging copies a read has to wait for, but not slices of one array
-    __shared__ float4 bufA[SLOTS];
-    __shared__ float4 bufB[SLOTS];
-    __shared__ float4 bufC[SLOTS];
     const int tid = threadIdx.x;
-    const int3 tile = xcd_tile<kXcdRunP>();
     const int4 bt = batches[tile.y];
     // lane -> (bin, view): each wave holds two neighbouring views; a 16-lane quarter holds the same
     // 8 bins of both, whose candidate voxels nearly coincide, so one quarter's LDS reads stay
@@ -615,12 +622,12 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     const int tb = (lane & 7) | ((lane >> 4) << 3), tk = 2 * wv + ((lane >> 3) & 1);
     const int b = tile.x * kPB + tb;
     // grid.z = z chunks x march splits; split s walks its share of the chunks into partial sum s
-    const int nzc = gridDim.z / nsplit, zb = tile.z % nzc, split = tile.z / nzc;
+    const int nzc = gz / nsplit, zb = tile.z % nzc, split = tile.z / nzc;
     const int z0 = zb * ZC;
     const bool xmajor = bt.z != 0;
     const bool active = tk < bt.y && b < nb;
     const int a = order[bt.x + min(tk, bt.y - 1)];
-    if (wg_on && !wg_on[((size_t)tile.y * gridDim.x + tile.x) * nzc + zb]) {
+    if (wg_on && !wg_on[((size_t)tile.y * gx + tile.x) * nzc + zb]) {
         // none of this workgroup's rays is active: their outputs are zero (before any barrier);
         // with splits the reduction writes those zeros; with the fused primal step nothing changes
         if (active && nsplit == 1 && !fz.y)
@@ -643,26 +650,37 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     const MarchF32 mc32 = march_f32(U00 - (double)b, dU, du, inv_du, s00, dsm, t00, dtm, nb);
     // the march: every step in chunks of CM, or (step lists, CM = 1) only the listed steps, in
     // increasing order; the steps left out stage nothing but zeros
-    // LIST: the workgroup's listed steps are copied to LDS first, so that reading a chunk's step adds
-    // no vector-memory load to the staging waits below (their counts cover the staging copies only)
-    __shared__ int slist[LIST ? kMaxListSteps : 1];
+    // LIST: each listed step's record (step, staged cross range, vial interval of its grid line) is
+    // gathered into LDS first, so that a chunk's metadata costs one LDS read instead of a chain of
+    // dependent scalar loads from global memory, and adds no vector-memory load to the staging waits
+    // below (their counts cover the staging copies only)
+    // (a static array of the kernel: the compiler then knows that the staging copies into the ring
+    // never write it)
+    const int2 *rg = ranges + ((size_t)tile.y * gx + tile.x) * n;
     int nch = (n + CM - 1) / CM;
     if constexpr (LIST) {
-        const size_t wgi = ((size_t)tile.y * gridDim.x + tile.x) * nzc + zb;
+        const size_t wgi = ((size_t)tile.y * gx + tile.x) * nzc + zb;
         nch = __builtin_amdgcn_readfirstlane(step_cnt[wgi]);
-        for (int i = tid; i < nch; i += 256) slist[i] = step_list[wgi * n + i];
+        for (int i = tid; i < nch; i += 256) {
+            const int m = step_list[wgi * n + i];
+            const int2 r = rg[m], v = vial_rows[m];
+            smeta[i] = make_int2(m | (r.y << 10) | ((r.x + kListJ0Bias) << 17), (v.x & 0xFFFF) | (v.y << 16));
+        }
         __syncthreads();
     }
     auto first_step = [&](int k) {
-        if constexpr (LIST) return __builtin_amdgcn_readfirstlane(slist[k]);
+        if constexpr (LIST) return __builtin_amdgcn_readfirstlane(smeta[k].x) & 1023;
         else return __builtin_amdgcn_readfirstlane(k * CM);
     };
-    const int2 *rg = ranges + ((size_t)tile.y * gridDim.x + tile.x) * n;
     const size_t zrow = (size_t)(nz >> 2), zoff = (size_t)(z0 >> 2);
     const float4 *vol4 = (const float4 *)vol_t;
 
     // staged cross range of chunk k: the union of its steps' ranges (first index, count)
     auto chunk_range = [&](int k) {
+        if constexpr (LIST) {
+            const int e = __builtin_amdgcn_readfirstlane(smeta[k].x);
+            return make_int2((e >> 17) - kListJ0Bias, (e >> 10) & 127);
+        }
         const int m0 = first_step(k);   // uniform: scalar loads
         int lo = rg[m0].x, hi = rg[m0].x + rg[m0].y;
 #pragma unroll
@@ -686,11 +704,21 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
         s_jj[i] = rem - s_z4[i] * RS;
     }
     auto issue = [&](float4 *buf, int k) {
-        const int2 r = chunk_range(k);
-        const int m0 = first_step(k);
-        int2 vr[CM];   // vial interval of each step's row (uniform loads)
+        int2 r;
+        int m0;
+        int2 vr[CM];   // vial interval of each step's row (uniform)
+        if constexpr (LIST) {
+            const int2 e = smeta[k];
+            const int ex = __builtin_amdgcn_readfirstlane(e.x), ey = __builtin_amdgcn_readfirstlane(e.y);
+            m0 = ex & 1023;
+            r = make_int2((ex >> 17) - kListJ0Bias, (ex >> 10) & 127);
+            vr[0] = make_int2(ey & 0xFFFF, ey >> 16);
+        } else {
+            r = chunk_range(k);
+            m0 = first_step(k);
 #pragma unroll
-        for (int q = 0; q < CM; ++q) vr[q] = vial_rows[min(m0 + q, n - 1)];
+            for (int q = 0; q < CM; ++q) vr[q] = vial_rows[min(m0 + q, n - 1)];
+        }
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             if (i * 256 + tid < SLOTS) {
@@ -791,35 +819,93 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
     if (fz.y) {
         // fused primal step on this lane's rays (same arithmetic as the solver's primal kernel)
         const float tf = (float)*fz.tau_fac, w = (float)fz.w_rho[0], rho = (float)fz.w_rho[1];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const size_t base = r == 0 ? ((size_t)a * nb + b) * nz + z0
-                                       : ((size_t)partner[a] * nb + (nb - 1 - b)) * nz + z0;
-#pragma unroll
-            for (int z4 = 0; z4 < Z4; ++z4) {
-                const size_t i = base + 4 * z4;
-                if (z0 + 4 * z4 >= nz) continue;
-                const uint32_t m = *(const uint32_t *)(fz.act + i);
-                if (!m) continue;
-                const float4 yo = *(const float4 *)(fz.y + i), tj = *(const float4 *)(fz.Tj + i),
-                             a0 = *(const float4 *)(fz.y0 + i);
-                const float yv[4] = {yo.x, yo.y, yo.z, yo.w}, tv[4] = {tj.x, tj.y, tj.z, tj.w},
-                            av[4] = {a0.x, a0.y, a0.z, a0.w};
-                float t4[4], y4[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    float v = yv[k] - tf * tv[k] * acc[r][4 * z4 + k];
-                    v = v > 0.f ? v : 0.f;
-                    t4[k] = v;
-                    y4[k] = w * ((1.f + rho) * v - rho * yv[k]) + (1.f - w) * av[k];
+        if constexpr (QUEUE) {
+            // in the work queue the epilogue's memory waits lie on the workgroup's path to its next
+            // tile, so its loads go out in batches: every ray's activity words first, then y, T_j
+            // and y0 of four four-slice groups at once (groups without an active ray read a zero
+            // block), a few waits per tile instead of one or two per group
+            size_t base[NR];
+            uint32_t am[NR][Z4];
+    #pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                base[r] = r == 0 ? ((size_t)a * nb + b) * nz + z0 : ((size_t)partner[a] * nb + (nb - 1 - b)) * nz + z0;
+    #pragma unroll
+                for (int z4 = 0; z4 < Z4; ++z4)
+                    am[r][z4] = z0 + 4 * z4 < nz ? *(const uint32_t *)(fz.act + base[r] + 4 * z4) : 0u;
+            }
+    #pragma unroll
+            for (int r = 0; r < NR; ++r) {
+    #pragma unroll
+                for (int h = 0; h < Z4; h += 4) {
+                    constexpr int G = Z4 < 4 ? Z4 : 4;
+                    float4 yo[G], tj[G], a0[G];
+    #pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        const size_t i = base[r] + 4 * (h + g);
+                        const bool on = am[r][h + g] != 0u;
+                        yo[g] = on ? *(const float4 *)(fz.y + i) : *zero16;
+                        tj[g] = on ? *(const float4 *)(fz.Tj + i) : *zero16;
+                        a0[g] = on ? *(const float4 *)(fz.y0 + i) : *zero16;
+                    }
+    #pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        const uint32_t m = am[r][h + g];
+                        if (!m) continue;
+                        const size_t i = base[r] + 4 * (h + g);
+                        const float yv[4] = {yo[g].x, yo[g].y, yo[g].z, yo[g].w}, tv[4] = {tj[g].x, tj[g].y, tj[g].z, tj[g].w},
+                                    av[4] = {a0[g].x, a0[g].y, a0[g].z, a0[g].w};
+                        float t4[4], y4[4];
+    #pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            float v = yv[k] - tf * tv[k] * acc[r][4 * (h + g) + k];
+                            v = v > 0.f ? v : 0.f;
+                            t4[k] = v;
+                            y4[k] = w * ((1.f + rho) * v - rho * yv[k]) + (1.f - w) * av[k];
+                        }
+                        if (((m - 0x01010101u) & ~m & 0x80808080u) == 0) {   // all four active
+                            *(float4 *)(fz.yt + i) = make_float4(t4[0], t4[1], t4[2], t4[3]);
+                            *(float4 *)(fz.y + i) = make_float4(y4[0], y4[1], y4[2], y4[3]);
+                        } else {
+    #pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                if ((m >> (8 * k)) & 0xFFu) { fz.yt[i + k] = t4[k]; fz.y[i + k] = y4[k]; }
+                        }
+                    }
+                    // one batch of loads live at a time: the next batch is not hoisted above this one
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                if (((m - 0x01010101u) & ~m & 0x80808080u) == 0) {   // all four active
-                    *(float4 *)(fz.yt + i) = make_float4(t4[0], t4[1], t4[2], t4[3]);
-                    *(float4 *)(fz.y + i) = make_float4(y4[0], y4[1], y4[2], y4[3]);
-                } else {
+            }
+        } else {
 #pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if ((m >> (8 * k)) & 0xFFu) { fz.yt[i + k] = t4[k]; fz.y[i + k] = y4[k]; }
+            for (int r = 0; r < NR; ++r) {
+                const size_t base = r == 0 ? ((size_t)a * nb + b) * nz + z0
+                                           : ((size_t)partner[a] * nb + (nb - 1 - b)) * nz + z0;
+#pragma unroll
+                for (int z4 = 0; z4 < Z4; ++z4) {
+                    const size_t i = base + 4 * z4;
+                    if (z0 + 4 * z4 >= nz) continue;
+                    const uint32_t m = *(const uint32_t *)(fz.act + i);
+                    if (!m) continue;
+                    const float4 yo = *(const float4 *)(fz.y + i), tj = *(const float4 *)(fz.Tj + i),
+                                 a0 = *(const float4 *)(fz.y0 + i);
+                    const float yv[4] = {yo.x, yo.y, yo.z, yo.w}, tv[4] = {tj.x, tj.y, tj.z, tj.w},
+                                av[4] = {a0.x, a0.y, a0.z, a0.w};
+                    float t4[4], y4[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        float v = yv[k] - tf * tv[k] * acc[r][4 * z4 + k];
+                        v = v > 0.f ? v : 0.f;
+                        t4[k] = v;
+                        y4[k] = w * ((1.f + rho) * v - rho * yv[k]) + (1.f - w) * av[k];
+                    }
+                    if (((m - 0x01010101u) & ~m & 0x80808080u) == 0) {   // all four active
+                        *(float4 *)(fz.yt + i) = make_float4(t4[0], t4[1], t4[2], t4[3]);
+                        *(float4 *)(fz.y + i) = make_float4(y4[0], y4[1], y4[2], y4[3]);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            if ((m >> (8 * k)) & 0xFFu) { fz.yt[i + k] = t4[k]; fz.y[i + k] = y4[k]; }
+                    }
                 }
             }
         }
@@ -837,6 +923,62 @@ __global__ void __launch_bounds__(256) project3d_dma_kernel(
                 v.x = acc[r][4 * z4 + 0]; v.y = acc[r][4 * z4 + 1]; v.z = acc[r][4 * z4 + 2]; v.w = acc[r][4 * z4 + 3];
                 *(float4 *)(dst + 4 * z4) = v;
             }
+        }
+    }
+}
+
+// Grid mode (!QUEUE): one workgroup per tile of the launch grid.  Work-queue mode (QUEUE, step
+// lists of an LP solve): a persistent grid takes tiles from items[0, n_items) in that order -- the
+// switched-on tiles, longest step list first -- through an atomic counter, so the chip stays evenly
+// loaded while the tiles' walks differ several-fold in length; tile indices are flag indices of a
+// virtual grid of gx bin groups x batches x gz z chunks (no march splits).  queue[0] counts taken
+// tiles, queue[1] finished workgroups; the last workgroup to finish sets both back to zero, so
+// consecutive launches on one stream reuse the counters (they start zeroed).
+template <int ZC, int NC, bool PAIR, bool SKIP, int CM, bool LIST, bool QUEUE>
+__global__ void __launch_bounds__(256) project3d_dma_kernel(
+    const float *__restrict__ vol_t, float *__restrict__ sino_t, int n, int nz, int nb,
+    const double2 *__restrict__ trig, const int *__restrict__ order, const int *__restrict__ partner,
+    const int4 *__restrict__ batches, const int2 *__restrict__ ranges, const int2 *__restrict__ vial_rows,
+    const float4 *__restrict__ zero16, double h, double inv_ds, float atten, const uint8_t *__restrict__ wg_on,
+    int nsplit, long long split_stride, PrimalFuse fz, const int *__restrict__ step_list,
+    const int *__restrict__ step_cnt, const int *__restrict__ items, int n_items, int *__restrict__ queue, int vgx,
+    int vgz) {
+    constexpr int SLOTS = DmaRing<ZC, CM>::SLOTS;
+    // three separate arrays, not one indexed ring: the compiler tells LDS variables apart when it
+    // decides which staging copies a read has to wait for, but not slices of one array
+    __shared__ float4 bufA[SLOTS];
+    __shared__ float4 bufB[SLOTS];
+    __shared__ float4 bufC[SLOTS];
+    __shared__ int2 smeta[LIST ? kMaxListSteps : 1];
+    if constexpr (!QUEUE) {
+        p3d_dma_tile<ZC, NC, PAIR, SKIP, CM, LIST, false>(vol_t, sino_t, n, nz, nb, trig, order, partner, batches,
+                                                         ranges, vial_rows, zero16, h, inv_ds, atten, wg_on, nsplit,
+                                                         split_stride, fz, step_list, step_cnt, xcd_tile<kXcdRunP>(),
+                                                         gridDim.x, gridDim.z, bufA, bufB, bufC, smeta);
+        return;
+    }
+    static_assert(!QUEUE || LIST, "the work queue serves listed marches");
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();   // every wave has its tile before thread 0 takes the next one
+        if (it >= n_items) break;
+        const int wgi = items[it];
+        const int zb = wgi % vgz, t = wgi / vgz;
+        p3d_dma_tile<ZC, NC, PAIR, SKIP, CM, LIST, QUEUE>(vol_t, sino_t, n, nz, nb, trig, order, partner, batches,
+                                                         ranges, vial_rows, zero16, h, inv_ds, atten, wg_on, 1,
+                                                         split_stride, fz, step_list, step_cnt,
+                                                         make_int3(t % vgx, t / vgx, zb), vgx, vgz, bufA, bufB, bufC,
+                                                         smeta);
+        __syncthreads();   // the tile's LDS reads are done before the next tile stages into the ring
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(queue + 1, 1) == (int)gridDim.x - 1) {   // every workgroup has taken its last tile
+            atomicExch(queue, 0);
+            atomicExch(queue + 1, 0);
         }
     }
 }
@@ -1033,6 +1175,7 @@ int plan_build_batches(sipo_plan p, const double2 *trig) {
     const int ngroups = (p->n_bins + kPB - 1) / kPB;
     std::vector<int2> ranges;
     bool dma = p->dtype == SIPO_F32 && (p->nz & 3) == 0 && p->p3d_ok;
+    int j0_min = 0, j0_max = 0;
     if (dma) {
         ranges.resize((size_t)batches.size() * ngroups * p->n);
         for (size_t bi = 0; bi < batches.size() && dma; ++bi) {
@@ -1043,6 +1186,8 @@ int plan_build_batches(sipo_plan p, const double2 *trig) {
                     int j0, cr;
                     staged_range(bt.z != 0, trig, order.data() + bt.x, bt.y, g * kPB, m, m, h, inv_ds, &j0, &cr);
                     row[m] = make_int2(j0, cr);
+                    j0_min = std::min(j0_min, j0);
+                    j0_max = std::max(j0_max, j0);
                 }
                 for (int m0 = 0; m0 < p->n && dma; m0 += kDmaMaxCM) {
                     int lo = row[m0].x, hi = row[m0].x + row[m0].y;
@@ -1070,6 +1215,7 @@ int plan_build_batches(sipo_plan p, const double2 *trig) {
         vial[m] = lo <= hi ? make_int2((int)lo, (int)hi) : make_int2(1, 0);
     }
     p->p3d_dma_ok = p->p3d_dma = dma;
+    p->p3d_list_ok = dma && p->n <= kMaxListSteps && j0_min >= -kListJ0Bias && j0_max < (1 << 12) - kListJ0Bias;
     if (dma) {
         SIPO_TRY(plan_alloc(p, (void **)&p->d_ranges, sizeof(int2) * ranges.size()));
         SIPO_HIP(hipMemcpy(p->d_ranges, ranges.data(), sizeof(int2) * ranges.size(), hipMemcpyHostToDevice));
@@ -1210,22 +1356,56 @@ __global__ void k_p3d_reduce(const float4 *__restrict__ part, float4 *__restrict
     }
 }
 
-template <int ZC, int NC, bool PAIR, bool SKIP, int CM, bool LIST>
-static void fp3d_dma_launch(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
-                            const SplitSpec &sp, const PrimalFuse &fz, const StepList &sl) {
+template <int ZC, int NC, bool PAIR, bool SKIP, int CM, bool LIST, bool QUEUE>
+static void fp3d_dma_launch_k(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
+                              const SplitSpec &sp, const PrimalFuse &fz, const StepList &sl) {
     const double h = 2.0 / p->n, inv_ds = 0.5 * p->n_bins;
     const int ns = sp.parts > 1 ? sp.parts : 1;
     const dim3 grid((p->n_bins + kPB - 1) / kPB, p->n_batches, ((p->nz + ZC - 1) / ZC) * ns);
-    hipLaunchKernelGGL((project3d_dma_kernel<ZC, NC, PAIR, SKIP, CM, LIST>), grid, dim3(256), 0, s, (const float *)vol_t,
-                       (float *)(ns > 1 ? sp.partial : sino_t), p->n, p->nz, p->n_bins, p->d_trig, p->d_angle_order,
-                       p->d_partner, p->d_batches, p->d_ranges, p->d_vial_rows, (const float4 *)p->d_zero, h, inv_ds,
-                       (float)p->atten, on, ns, (long long)p->sino_elems(), fz, sl.steps, sl.count);
+    dim3 g = grid;
+    if constexpr (QUEUE) {
+        // persistent grid: queue_per_cu workgroups per CU (at most as many as fit), at most one per tile
+        static int occ[64] = {}, cus[64] = {};
+        const int d = p->device >= 0 && p->device < 64 ? p->device : 0;
+        if (!occ[d]) {
+            int o = 0, c = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, project3d_dma_kernel<ZC, NC, PAIR, SKIP, CM, LIST, true>,
+                                                             256, 0) != hipSuccess || o < 1)
+                o = 1;
+            if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || c < 1)
+                c = 1;
+            cus[d] = c;
+            occ[d] = o;
+        }
+        const int per_cu = sl.queue_per_cu > 0 ? std::min(sl.queue_per_cu, occ[d]) : occ[d];
+        g = dim3((unsigned)std::max(1, std::min(sl.n_items, per_cu * cus[d])));
+    }
+    hipLaunchKernelGGL((project3d_dma_kernel<ZC, NC, PAIR, SKIP, CM, LIST, QUEUE>), g, dim3(256), 0, s,
+                       (const float *)vol_t, (float *)(ns > 1 ? sp.partial : sino_t), p->n, p->nz, p->n_bins, p->d_trig,
+                       p->d_angle_order, p->d_partner, p->d_batches, p->d_ranges, p->d_vial_rows,
+                       (const float4 *)p->d_zero, h, inv_ds, (float)p->atten, on, ns, (long long)p->sino_elems(), fz,
+                       sl.steps, sl.count, QUEUE ? sl.items : nullptr, sl.n_items, QUEUE ? sl.queue : nullptr,
+                       (int)grid.x, (int)(grid.z / ns));
     if (ns > 1) {
         const long long total4 = (long long)p->sino_elems() / 4;
         hipLaunchKernelGGL(k_p3d_reduce, dim3((unsigned)std::min<long long>((total4 + 255) / 256, 16384)), dim3(256), 0,
                            s, (const float4 *)sp.partial, (float4 *)sino_t, on, p->d_view_batch, p->n_angles, p->n_bins,
                            p->nz, (p->n_bins + kPB - 1) / kPB, ZC, (p->nz + ZC - 1) / ZC, ns, total4);
     }
+}
+
+// The listed march of an unsplit solve takes the work queue when the caller set one up (and the
+// outputs the queue leaves unwritten are not read); everything else runs one workgroup per tile.
+template <int ZC, int NC, bool PAIR, bool SKIP, int CM, bool LIST>
+static void fp3d_dma_launch(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
+                            const SplitSpec &sp, const PrimalFuse &fz, const StepList &sl) {
+    if constexpr (LIST) {
+        if (sl.items && sl.queue && sp.parts <= 1 && (fz.y || sl.off_unread)) {
+            fp3d_dma_launch_k<ZC, NC, PAIR, SKIP, CM, true, true>(p, vol_t, sino_t, s, on, sp, fz, sl);
+            return;
+        }
+    }
+    fp3d_dma_launch_k<ZC, NC, PAIR, SKIP, CM, LIST, false>(p, vol_t, sino_t, s, on, sp, fz, sl);
 }
 
 template <int ZC, int NC, bool PAIR, bool SKIP>
@@ -1353,7 +1533,7 @@ int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s
                      const SplitSpec &sp, const PrimalFuse *fuse, const StepList &sl) {
     if (fuse && (!p->fast3d() || p->dtype != SIPO_F32 || p->p2d_ok))
         return fail(SIPO_E_UNSUPPORTED, "the fused primal step needs an FP32 3D plan");
-    if (sl.steps && (!p->fast3d() || p->p2d_ok || !wg_on || !p->p3d_dma || p->p3d_zc > 32 || p->n > kMaxListSteps))
+    if (sl.steps && (!p->fast3d() || p->p2d_ok || !wg_on || !p->p3d_dma || !p->p3d_list_ok || p->p3d_zc > 32))
         return fail(SIPO_E_UNSUPPORTED, "projector step lists need a 3D plan with the asynchronous projector at "
                     "8, 16 or 32 slices per thread, workgroup flags and n <= %d", kMaxListSteps);
     if (p->p2d_ok) return fp2d_plan(p, vol_t, sino_t, 0, s);
@@ -1495,7 +1675,7 @@ __global__ void __launch_bounds__(256) k_p3d_steps(const int4 *__restrict__ batc
 }
 
 bool p3d_steps_ok(sipo_plan p) {
-    return p->fast3d() && p->p3d_dma && p->d_ranges && p->p3d_zc <= 32 && p->n <= kMaxListSteps;
+    return p->fast3d() && p->p3d_dma && p->p3d_list_ok && p->d_ranges && p->p3d_zc <= 32;
 }
 
 size_t p3d_reach_bytes(sipo_plan p, int zc) {

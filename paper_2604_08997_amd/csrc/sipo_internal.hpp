@@ -92,6 +92,7 @@ struct sipo_plan_s {
     int p3d_nc;             // candidate voxels per ray step of the 3D projector (0 = unsupported)
     int p3d_zc;             // slices per projector thread (set by defaults or sipo_plan_autotune)
     bool p3d_dma_ok;        // the asynchronous-staging projector applies (FP32, nz % 4 == 0, ranges fit)
+    bool p3d_list_ok;       // its step-list variant applies (n and every staged range fit the packed records)
     bool p3d_dma;           // use it (default when it applies; sipo_plan_autotune may switch)
     bool p3d_skip;          // asynchronous projector: lanes skip candidates outside their ray's reach
     int p3d_cm;             // asynchronous projector: march steps per staged chunk (1 or 2)
@@ -185,6 +186,15 @@ struct PrimalFuse {
 struct StepList {
     const int *steps = nullptr;
     const int *count = nullptr;
+    // optional work queue (unsplit march only): the switched-on workgroups' flag indices, longest
+    // list first, and two zeroed int counters that the projector leaves zeroed
+    const int *items = nullptr;
+    int n_items = 0;
+    int *queue = nullptr;
+    int queue_per_cu = 0;   // persistent workgroups per CU (0 or more than fit: as many as fit)
+    // the queue leaves the outputs of switched-off workgroups unwritten; without the fused primal step
+    // it is used only when the caller never reads them (off_unread)
+    bool off_unread = false;
 };
 int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *wg_on = nullptr,
                      const SplitSpec &sp = SplitSpec(), const PrimalFuse *fuse = nullptr,

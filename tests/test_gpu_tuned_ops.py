@@ -68,9 +68,11 @@ def test_fixed_slice_counts_match_oracle_kkt(oracle_lp):
     base_r, base_st = run()
     cfg = base_r["op_config"]
     assert cfg["p_zc"] in (8, 16) and cfg["bp_zc"] in (4, 8) and 1 <= cfg["bp_splits"] <= 8 and cfg["blur_zc"] == 4
+    assert cfg["p_queue"] == -1 and cfg["p_fuse"] in (1, -1)
     check_against_oracle(oracle_lp, base_r, base_st)
     for p_zc, bp_zc, blur_zc in ((32, 4, 8), (8, 16, 16)):
-        want = {"p_zc": p_zc, "bp_zc": bp_zc, "bp_splits": cfg["bp_splits"], "blur_zc": blur_zc}
+        want = {"p_zc": p_zc, "bp_zc": bp_zc, "bp_splits": cfg["bp_splits"], "blur_zc": blur_zc, "p_queue": -1,
+                "p_fuse": cfg["p_fuse"]}
         r, st = run(op_config=want)
         assert r["op_config"] == want
         check_against_oracle(oracle_lp, r, st)
@@ -90,7 +92,8 @@ def test_tuned_solve_picks_candidates_and_repeats_bit_for_bit(oracle_lp, capfd):
     assert "masked operators tuned" in err
     cfg = r["op_config"]
     assert cfg["p_zc"] in (8, 16, 32) and cfg["bp_zc"] in (4, 8, 16)
-    assert cfg["bp_splits"] in (1, 2, 4, 8) and cfg["blur_zc"] in (4, 8)
+    assert cfg["bp_splits"] in (1, 2, 4, 8) and cfg["blur_zc"] in (4, 8) and cfg["p_queue"] in (-1, 2, 3, 4, 6, 16)
+    assert cfg["p_fuse"] in (1, -1)
     check_against_oracle(oracle_lp, r, st)
     # the reported splits, passed back, repeat the tuned solve exactly
     r2, st2 = run(op_config=cfg)
@@ -102,8 +105,48 @@ def test_tuned_solve_picks_candidates_and_repeats_bit_for_bit(oracle_lp, capfd):
 def test_invalid_work_splits_are_rejected():
     import paper_2604_08997_amd as sipo
     plan, lp = gpu_lp()
-    for bad in ({"p_zc": 12}, {"bp_zc": 32}, {"bp_splits": 9}, {"blur_zc": 2}):
+    for bad in ({"p_zc": 12}, {"bp_zc": 32}, {"bp_splits": 9}, {"blur_zc": 2}, {"p_queue": 17}, {"p_queue": -2}, {"p_fuse": 2}):
         with pytest.raises(RuntimeError, match="op_config"):
             sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=64, op_config=bad))
     with pytest.raises(RuntimeError, match="tune_operators"):
         sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=64, tune_operators=2))
+
+
+def test_projector_work_queue_at_full_size_leaves_iterates_unchanged():
+    # the queue only changes which workgroup walks a tile: every ray's sums and its fused primal step
+    # are the same, so the states agree bit for bit with one workgroup per tile, whatever the queue
+    # width.  It serves an unsplit march (small LPs split theirs), so the benchmark LP is used:
+    # 256^3 x 360, about 1300 switched-on tiles, so at 1 workgroup per CU every workgroup walks
+    # several tiles from the queue, and the counters are reused launch after launch
+    import paper_2604_08997_amd as sipo
+    n, na = 256, 360
+    plan = sipo.Plan(n, list(angles_uniform(na)), nz=n, sigma=SIGMA, dtype=torch.float32, device=dev())
+    f = torch.as_tensor(ellipsoids_target(n, 3000), dtype=torch.float32, device=dev())
+    lp = sipo.LP.build(plan, f, sipo.CASE1, band_width=10.0, f_min=1.0)
+    fixed = {"p_zc": 8, "bp_zc": 8, "bp_splits": 8, "blur_zc": 4}
+    stream = torch.cuda.Stream()   # graph-captured iteration blocks, as the benchmark runs them
+
+    def solve(qw, pf):
+        lp.y.zero_(); lp.lam_up.zero_(); lp.lam_lo.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            r = sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=192, tol=1e-12, check_every=64,
+                                                 use_graph=1, op_config=dict(fixed, p_queue=qw, p_fuse=pf)),
+                           want_dose=False)
+            torch.cuda.synchronize()
+        assert (r["op_config"]["p_queue"], r["op_config"]["p_fuse"]) == (qw, pf)
+        return r, [t.cpu().numpy().copy() for t in (lp.y, lp.lam_up, lp.lam_lo)]
+
+    # with the primal step fused into the projector, and as its own kernel after it
+    for pf in (1, -1):
+        r0, st0 = solve(-1, pf)
+        for qw in (1, 16):
+            r, st = solve(qw, pf)
+            assert (r["iters"], r["primal_obj"], r["rel_primal"]) == (r0["iters"], r0["primal_obj"], r0["rel_primal"])
+            for a, b in zip(st0, st):
+                np.testing.assert_array_equal(a, b)
+        if pf == 1:
+            fused = r0
+        else:
+            # both forms of the primal step evaluate the same expressions
+            assert r0["primal_obj"] == pytest.approx(fused["primal_obj"], rel=1e-5)
