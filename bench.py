@@ -144,6 +144,15 @@ def recorded_traffic(kernel):
     return rec.get("bytes_per_launch")
 
 
+# Work splits of the masked operators in the benchmark's solves (a result's op_config): the
+# solver's tuner, run in the warm-up solve, picks among candidates that differ by a few percent at
+# this workload, so the timed, profiled and counter-collection solves fix one choice -- the fastest
+# in repeated tuner runs on MI355X: 16 slices per projector thread, 3 queue workgroups per CU, the
+# primal step fused, candidate skipping on; 8 slices and 8 view splits for the backprojector, 4
+# slices per blur chunk -- and the line reports the tuner's own pick beside it.
+BENCH_OPS = {"p_zc": 16, "bp_zc": 8, "bp_splits": 8, "blur_zc": 4, "p_queue": 3, "p_fuse": 1, "p_skip": 1}
+
+
 def in_solve_projector(tuning, ops):
     """Name of the projector kernel an LP solve of the 256^3 x 360 workload runs (view pairs, 3
     candidates per step, slices per thread and work queue as the solve reports them in ``ops``;
@@ -151,7 +160,8 @@ def in_solve_projector(tuning, ops):
     zc = ops["p_zc"]
     if tuning["p3d_dma"]:
         queue = "true" if ops.get("p_queue", -1) > 0 else "false"
-        return f"project3d_dma_kernel<{zc}, 3, true, {'true' if tuning['p3d_skip'] else 'false'}, 1, true, {queue}>"
+        skip = "true" if ops.get("p_skip", 1 if tuning["p3d_skip"] else -1) > 0 else "false"
+        return f"project3d_dma_kernel<{zc}, 3, true, {skip}, 1, true, {queue}>"
     return f"project3d_kernel<float, {zc}, 3, true>"
 
 
@@ -500,7 +510,7 @@ def probe(args, plan, dev):
     plan.autotune()
     f = torch.as_tensor(ellipsoids_target(plan.n, 3000), dtype=torch.float32, device=dev)
     lp = sipo.LP.build(plan, f, sipo.CASE1, band_width=10.0, f_min=1.0)
-    r = sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=32, tol=1e-12, tune_operators=1),
+    r = sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=32, tol=1e-12, op_config=BENCH_OPS),
                    want_dose=False)
     torch.cuda.synchronize()
     print(f"[probe] 32-iteration solve after autotune; masked operators {r['op_config']}", file=sys.stderr, flush=True)
@@ -550,13 +560,13 @@ def main():
     # profiled solve of the same length (HIP events on the solve's stream) for the per-phase times
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=max(args.warmup, 1), tol=1e-12, tune_operators=1,
-                                         use_graph=1), want_dose=False)
+        wres = sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=max(args.warmup, 1), tol=1e-12,
+                                                tune_operators=1, progress_every=1 << 30, use_graph=1), want_dose=False)
         torch.cuda.synchronize()
         print(f"[bench] warmup {args.warmup} iterations done", file=sys.stderr, flush=True)
         lp.y.zero_(); lp.lam_up.zero_(); lp.lam_lo.zero_()
         opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=args.steps, tol=1e-12, check_every=64, use_graph=1,
-                                 tune_operators=1, progress_every=1 << 30)
+                                 op_config=BENCH_OPS)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = sipo.solve(lp, opts, want_dose=False)
@@ -569,7 +579,7 @@ def main():
               f"graph-captured blocks)", file=sys.stderr, flush=True)
         lp.y.zero_(); lp.lam_up.zero_(); lp.lam_lo.zero_()
         popts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=args.steps, tol=1e-12, check_every=64, profile=1,
-                                  tune_operators=1)
+                                  op_config=BENCH_OPS)
         torch.cuda.synchronize()
         tp0 = time.perf_counter()
         pres = sipo.solve(lp, popts, want_dose=False)
@@ -605,7 +615,7 @@ def main():
         # graph-captured like the timed solve; the solver reports its residuals every 64 checks
         with torch.cuda.stream(stream):
             r = sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=args.ttk_iters, tol=1e-4, use_graph=1,
-                                                 progress_every=64, tune_operators=1), want_dose=False)
+                                                 progress_every=64, op_config=BENCH_OPS), want_dose=False)
             torch.cuda.synchronize()
         ttk = {"seconds": round(time.perf_counter() - t1, 3), "iters": r["iters"], "status": r["status_name"],
                "restarts": r["restarts"], "objective": r["primal_obj"], "rel_primal": r["rel_primal"],
@@ -644,9 +654,10 @@ def main():
         "phase_ms": {k: round(v, 4) for k, v in ph_avg.items()},
         "profiled_solve_iters_per_s": round(pres["iters"] / (pres["loop_ms"] * 1e-3), 3),
         "tuning": tuning,
-        # the masked operators' work splits the solver's own tuning picked (timed and profiled solves)
+        # the masked operators' work splits of the timed and profiled solves, and the solver's own
+        # tuner's pick in the warm-up solve
         "in_solve_ops": res["op_config"],
-        "in_solve_ops_profiled": pres["op_config"],
+        "in_solve_ops_tuned": wres["op_config"],
         "roofline": {"bound": "alu", "kernel": (p_kernel + " (LP rays)" if dom == "project" else "backproject3d (LP voxels)"),
                      "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic},

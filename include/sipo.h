@@ -319,7 +319,7 @@ typedef struct {
                                   backprojector's summation order, so a tuned solve is
                                   reproducible bit for bit only when it picks the same
                                   splits (op_config in the result).  0 = fixed rules      */
-    int32_t op_config[6];      /* restarted mode, 3D instances: a nonzero entry fixes that
+    int32_t op_config[7];      /* restarted mode, 3D instances: a nonzero entry fixes that
                                   work split of the masked operators, as reported in the
                                   result's op_config (projector slices per thread 8 / 16 /
                                   32, the last FP32 only; backprojector slices per thread
@@ -329,7 +329,10 @@ typedef struct {
                                   persistent grid of k workgroups per CU, at most as many
                                   as fit, taking the tiles longest step list first; the
                                   primal step: 1 = fused into the projector's output where
-                                  its march is unsplit, -1 = its own kernel); passing a
+                                  its march is unsplit, -1 = its own kernel; the
+                                  projector's lanes: 1 = skip the LDS reads of candidates
+                                  out of their ray's reach, -1 = read them, which changes
+                                  no result); passing a
                                   tuned result's op_config back repeats that solve bit for
                                   bit.  Zero entries are tuned or follow the fixed rules (no
                                   queue, fused)                                            */
@@ -368,11 +371,12 @@ typedef struct {
                                   ran.  iters / loop_ms is the steady iteration rate        */
     double phase_ms[SIPO_NUM_PHASES];       /* profile mode: summed launch durations          */
     int32_t phase_launches[SIPO_NUM_PHASES]; /* profile mode: launches timed per phase        */
-    int32_t op_config[6];      /* restarted mode, 3D instance: the masked operators' work
+    int32_t op_config[7];      /* restarted mode, 3D instance: the masked operators' work
                                   splits as run (projector slices per thread,
                                   backprojector slices per thread, backprojector view
-                                  splits, blur slices per chunk, projector work queue and
-                                  primal step as in the options); zeros otherwise          */
+                                  splits, blur slices per chunk, projector work queue,
+                                  primal step and candidate skipping as in the options);
+                                  zeros otherwise                                          */
 } sipo_pdhg_result;
 
 /* Bytes of device workspace sipo_pdhg_solve needs for these problems. */

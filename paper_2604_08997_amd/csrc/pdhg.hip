@@ -798,6 +798,7 @@ constexpr int kMaxSplitP = 4, kMaxSplitB = 8;
 // one, so the few tiles left on run shortest with short chunks
 constexpr int kMaskBlurZc = 4;
 constexpr size_t kQueueStride = 256;   // bytes per instance of the projector's work-queue counters
+constexpr double kTuneMargin = 0.98;   // a tuning candidate must beat the best so far by 2 %
 
 static bool use_batch2d(const sipo_problem *probs, int B) {
     for (int i = 0; i < B; ++i) {
@@ -946,6 +947,7 @@ class Solver {
             e.p->p3d_zc = e.p3d;
             e.p->bp3d_zc = e.bp3d;
             e.p->blur_zc = e.blur;
+            e.p->p3d_skip = e.skip;
         }
         if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
         for (hipEvent_t e : ev_) (void)hipEventDestroy(e);
@@ -985,6 +987,7 @@ class Solver {
     struct ZcSaved {
         sipo_plan p;
         int p3d, bp3d, blur;
+        bool skip;
     };
     std::vector<ZcSaved> zc_saved_;
     int nc_max_ = 3;
@@ -1398,9 +1401,11 @@ class Solver {
     }
 
     // Work splits of the masked operators timed on this instance's own masks: the projector's slices
-    // per thread, the backprojector's slices per thread and view splits, and the blur's slices per
-    // chunk; each is set to the fastest candidate (ties keep the earlier one).  Inputs are the zeroed
-    // working fields: the operators' work does not depend on the values.
+    // per thread, work queue and primal step, the backprojector's slices per thread and view splits,
+    // and the blur's slices per chunk.  Candidates run in a fixed preference order and a later one
+    // replaces the best only when it is more than 2 % faster, so near-ties resolve the same way from
+    // run to run.  Inputs are the zeroed working fields: the operators' work does not depend on the
+    // values.
     int tune_masked(int i, int &bparts) {
         const Inst &I = in_[i];
         sipo_plan p = I.p;
@@ -1445,25 +1450,35 @@ class Solver {
         const int *fx = o_.op_config;   // nonzero entries are fixed by the caller
         if (sizeof(T) == 4 && p->p3d_dma && p->nz % 4 == 0 && !fx[0]) {
             int best = p->p3d_zc, best_q = pqueue_[i], best_f = pfuse_[i];
+            bool best_skip = p->p3d_skip;
             double best_ms = INFINITY;
-            for (int zc : {8, 16, 32}) {
-                if (zc > 8 && zc / 2 >= p->nz) break;
+            for (int zc : {16, 8, 32}) {
+                if (zc > 8 && zc / 2 >= p->nz) continue;
                 p->p3d_zc = zc;
                 for (int pf : {1, -1}) {
                     if (fx[5] && pf != fx[5]) continue;
                     pfuse_[i] = pf;
                     rc = mask_setup(i, fx[2] ? fx[2] : bsp_[i].parts);
                     if (rc) return rc;
-                    for (int qw : {-1, 2, 3, 4, 6, 16}) {   // 16: as many as fit
-                        if (fx[4] && qw != fx[4]) continue;
-                        pqueue_[i] = qw;
-                        rc = time_launches(proj, kReps, ms);
-                        if (rc) return rc;
-                        if (ms < best_ms) { best_ms = ms; best = zc; best_q = qw; best_f = pf; }
+                    // skipping the LDS reads of out-of-reach candidates changes no result (their
+                    // weights are zero), only the time
+                    for (bool skip : {true, false}) {
+                        if (fx[6] && skip != (fx[6] > 0)) continue;
+                        p->p3d_skip = skip;
+                        for (int qw : {-1, 3, 6, 16}) {   // 16: as many as fit
+                            if (fx[4] && qw != fx[4]) continue;
+                            pqueue_[i] = qw;
+                            rc = time_launches(proj, kReps, ms);
+                            if (rc) return rc;
+                            if (ms < kTuneMargin * best_ms) {
+                                best_ms = ms; best = zc; best_q = qw; best_f = pf; best_skip = skip;
+                            }
+                        }
                     }
                 }
             }
             p->p3d_zc = best;
+            p->p3d_skip = best_skip;
             pqueue_[i] = best_q;
             pfuse_[i] = best_f;
             tuned_.p_ms = best_ms;
@@ -1472,15 +1487,15 @@ class Solver {
         {
             int best = p->bp3d_zc, best_parts = fx[2];
             double best_ms = INFINITY;
-            for (int zc : {4, 8, 16}) {
+            for (int zc : {8, 4, 16}) {
                 if (fx[1] ? zc != fx[1] : (zc > 4 && zc / 2 >= p->nz)) continue;
                 p->bp3d_zc = zc;
-                for (int parts : {1, 2, 4, 8}) {
+                for (int parts : {8, 4, 2, 1}) {
                     if (fx[2] && parts != fx[2]) continue;
                     rc = mask_setup(i, parts);
                     if (!rc) rc = time_launches(back, kReps, ms);
                     if (rc) return rc;
-                    if (ms < best_ms) { best_ms = ms; best = zc; best_parts = parts; }
+                    if (ms < kTuneMargin * best_ms) { best_ms = ms; best = zc; best_parts = parts; }
                 }
             }
             p->bp3d_zc = best;
@@ -1497,17 +1512,18 @@ class Solver {
                 rc = mask_setup(i, tuned_.bp_parts);
                 if (!rc) rc = time_launches(blurs, kReps, ms);
                 if (rc) return rc;
-                if (ms < best_ms) { best_ms = ms; best = zc; }
+                if (ms < kTuneMargin * best_ms) { best_ms = ms; best = zc; }
             }
             p->blur_zc = best;
             tuned_.k_ms = best_ms;
         }
         bparts = tuned_.bp_parts;
         if (o_.progress_every > 0)
-            fprintf(stderr, "[sipo] instance %d: masked operators tuned: P %d slices/thread, queue %d/CU, primal step "
-                    "%s %.4f ms, P^T %d slices/thread x %d view splits %.4f ms, blur %d slices/chunk %.4f ms (both "
-                    "applications)\n", i, p->p3d_zc, pqueue_[i], pfuse_[i] > 0 ? "fused" : "separate", tuned_.p_ms,
-                    p->bp3d_zc, bparts, tuned_.bp_ms, p->has_psf ? p->blur_zc : 0, tuned_.k_ms);
+            fprintf(stderr, "[sipo] instance %d: masked operators tuned: P %d slices/thread, %s, queue %d/CU, primal "
+                    "step %s %.4f ms, P^T %d slices/thread x %d view splits %.4f ms, blur %d slices/chunk %.4f ms (both "
+                    "applications)\n", i, p->p3d_zc, p->p3d_skip ? "skip" : "no skip", pqueue_[i],
+                    pfuse_[i] > 0 ? "fused" : "separate", tuned_.p_ms, p->bp3d_zc, bparts, tuned_.bp_ms,
+                    p->has_psf ? p->blur_zc : 0, tuned_.k_ms);
         return SIPO_OK;
     }
     struct Tuned {
@@ -1704,10 +1720,11 @@ int Solver<T>::setup_common() {
             bool seen = false;
             for (auto &e : zc_saved_) seen = seen || e.p == p;
             if (!seen) {
-                zc_saved_.push_back({p, p->p3d_zc, p->bp3d_zc, p->blur_zc});
+                zc_saved_.push_back({p, p->p3d_zc, p->bp3d_zc, p->blur_zc, p->p3d_skip});
                 p->blur_zc = o_.op_config[3] ? o_.op_config[3] : std::min(kMaskBlurZc, p->nz);
                 p->p3d_zc = o_.op_config[0] ? o_.op_config[0] : std::min(p->p3d_zc, 16);
                 p->bp3d_zc = o_.op_config[1] ? o_.op_config[1] : std::min(p->bp3d_zc, 8);
+                if (o_.op_config[6]) p->p3d_skip = o_.op_config[6] > 0;
             }
             rc = mask_setup(i, o_.op_config[2]);
             if (rc) return rc;
@@ -2332,7 +2349,7 @@ int Solver<T>::run(sipo_pdhg_result *res) {
             r.phase_ms[ph] = phase_ms_[ph];
             r.phase_launches[ph] = phase_n_[ph];
         }
-        for (int k = 0; k < 6; ++k) r.op_config[k] = 0;
+        for (int k = 0; k < 7; ++k) r.op_config[k] = 0;
         if (masked_run_ && I.t3) {
             r.op_config[0] = I.p->p3d_zc;
             r.op_config[1] = I.p->bp3d_zc;
@@ -2341,6 +2358,7 @@ int Solver<T>::run(sipo_pdhg_result *res) {
             const bool queued = !pqueue_.empty() && pqueue_[i] > 0 && steps_[i] && psp_[i].parts == 1;
             r.op_config[4] = queued ? pqueue_[i] : -1;
             r.op_config[5] = fused_[i] ? 1 : -1;
+            r.op_config[6] = I.p->p3d_skip ? 1 : -1;
         }
     }
     return SIPO_OK;
@@ -2377,6 +2395,7 @@ static int validate(const sipo_problem &pb, const sipo_pdhg_options &o, int idx,
                      "0, 4, 8 or 16, not %d", c[3]);
         SIPO_REQUIRE(c[4] >= -1 && c[4] <= 16, "op_config[4] (projector work queue) must be in [-1, 16], not %d", c[4]);
         SIPO_REQUIRE(c[5] >= -1 && c[5] <= 1, "op_config[5] (primal step) must be -1, 0 or 1, not %d", c[5]);
+        SIPO_REQUIRE(c[6] >= -1 && c[6] <= 1, "op_config[6] (candidate skipping) must be -1, 0 or 1, not %d", c[6]);
     }
     return SIPO_OK;
 }

@@ -72,7 +72,7 @@ def test_fixed_slice_counts_match_oracle_kkt(oracle_lp):
     check_against_oracle(oracle_lp, base_r, base_st)
     for p_zc, bp_zc, blur_zc in ((32, 4, 8), (8, 16, 16)):
         want = {"p_zc": p_zc, "bp_zc": bp_zc, "bp_splits": cfg["bp_splits"], "blur_zc": blur_zc, "p_queue": -1,
-                "p_fuse": cfg["p_fuse"]}
+                "p_fuse": cfg["p_fuse"], "p_skip": -cfg["p_skip"]}
         r, st = run(op_config=want)
         assert r["op_config"] == want
         check_against_oracle(oracle_lp, r, st)
@@ -93,7 +93,7 @@ def test_tuned_solve_picks_candidates_and_repeats_bit_for_bit(oracle_lp, capfd):
     cfg = r["op_config"]
     assert cfg["p_zc"] in (8, 16, 32) and cfg["bp_zc"] in (4, 8, 16)
     assert cfg["bp_splits"] in (1, 2, 4, 8) and cfg["blur_zc"] in (4, 8) and cfg["p_queue"] in (-1, 2, 3, 4, 6, 16)
-    assert cfg["p_fuse"] in (1, -1)
+    assert cfg["p_fuse"] in (1, -1) and cfg["p_skip"] in (1, -1)
     check_against_oracle(oracle_lp, r, st)
     # the reported splits, passed back, repeat the tuned solve exactly
     r2, st2 = run(op_config=cfg)
@@ -105,7 +105,7 @@ def test_tuned_solve_picks_candidates_and_repeats_bit_for_bit(oracle_lp, capfd):
 def test_invalid_work_splits_are_rejected():
     import paper_2604_08997_amd as sipo
     plan, lp = gpu_lp()
-    for bad in ({"p_zc": 12}, {"bp_zc": 32}, {"bp_splits": 9}, {"blur_zc": 2}, {"p_queue": 17}, {"p_queue": -2}, {"p_fuse": 2}):
+    for bad in ({"p_zc": 12}, {"bp_zc": 32}, {"bp_splits": 9}, {"blur_zc": 2}, {"p_queue": 17}, {"p_queue": -2}, {"p_fuse": 2}, {"p_skip": 3}):
         with pytest.raises(RuntimeError, match="op_config"):
             sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=64, op_config=bad))
     with pytest.raises(RuntimeError, match="tune_operators"):
