@@ -254,12 +254,19 @@ def batch_vs_plain(count, dev, max_iters=40000, infeas_tol=1e-4, h_min_tol=1e-5,
             stream.synchronize()
         return out, time.perf_counter() - t0
 
-    # ---- cold route
+    # ---- cold route: the batched solve tunes the 2D pair's work shapes on the batch (its time counts);
+    # the instances one by one run those shapes, so both legs do the same arithmetic
     reset(cold)
-    rb, t_batch = timed(lambda: sipo.solve(cold, opts, want_dose=False))
-    print(f"[bench] batch of {count}, cold: batched {t_batch:.2f} s, {dict(Counter(r['status_name'] for r in rb))}",
-          file=sys.stderr, flush=True)
+    t_opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=max_iters, tol=1e-4, infeas_tol=infeas_tol, use_graph=1,
+                               tune_operators=1, progress_every=1 << 30)
+    rb, t_batch = timed(lambda: sipo.solve(cold, t_opts, want_dose=False))
+    tiles = rb[0]["tiles_2d"]
+    print(f"[bench] batch of {count}, cold: batched {t_batch:.2f} s, {dict(Counter(r['status_name'] for r in rb))}, "
+          f"2D work shapes {tiles}", file=sys.stderr, flush=True)
     reset(cold)
+    opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=max_iters, tol=1e-4, infeas_tol=infeas_tol, use_graph=1,
+                             tiles_2d=tiles)
+    h_opts = sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=max_iters, tol=h_min_tol, use_graph=1, tiles_2d=tiles)
 
     def one_by_one():
         out = []
@@ -275,7 +282,7 @@ def batch_vs_plain(count, dev, max_iters=40000, infeas_tol=1e-4, h_min_tol=1e-5,
 
     samples = sum(float(b.n) * b.n * b.n_angles for b in insts)
     out = {"instances": count, "seeds": f"2000-{2000 + count - 1}", "samples_per_application": samples,
-           "max_iters": max_iters, "infeas_tol": infeas_tol, "compared_fields": list(keys),
+           "max_iters": max_iters, "infeas_tol": infeas_tol, "compared_fields": list(keys), "tiles_2d": tiles,
            "cold": {"batched_s": round(t_batch, 3), "plain_s": round(t_plain, 3),
                     # a time to 1e-4 only when every instance ended optimal or with a certificate
                     "speedup": round(t_plain / t_batch, 3) if not capped else None,

@@ -310,15 +310,19 @@ typedef struct {
     int32_t progress_every;    /* restarted mode: > 0 writes one line to stderr every this
                                   many KKT checks, per unfinished instance (iterations,
                                   relative residuals, restarts); 0 = silent (>= 0)        */
-    int32_t tune_operators;    /* restarted mode, 3D instances: 1 = at setup, time the
-                                  masked operators' work splits on each instance's own
-                                  masks and run the fastest (projector 8 / 16 / 32 slices
-                                  per thread, backprojector 4 / 8 / 16 slices and 1 / 2 /
-                                  4 / 8 view splits, blur 4 / 8 slices per chunk; a few
-                                  tens of ms at 256^3).  The view split sets the
-                                  backprojector's summation order, so a tuned solve is
-                                  reproducible bit for bit only when it picks the same
-                                  splits (op_config in the result).  0 = fixed rules      */
+    int32_t tune_operators;    /* 1 = at setup, time the work splits on this solve's own
+                                  data and run the fastest: for batched single-slice FP32
+                                  instances the 2D pair's work shapes (tiles_2d); in
+                                  restarted mode for 3D instances the masked operators'
+                                  splits on each instance's own masks (projector 8 / 16 /
+                                  32 slices per thread, work queue, fused or separate
+                                  primal step, candidate skipping; backprojector 4 / 8 /
+                                  16 slices and 1 / 2 / 4 / 8 view splits; blur 4 / 8
+                                  slices per chunk; tens of ms at 256^3).  Backprojector
+                                  tiles and view splits set summation orders, so a tuned
+                                  solve is reproducible bit for bit only with the same
+                                  picks (op_config and tiles_2d in the result; pass them
+                                  back to repeat it).  0 = fixed rules                     */
     int32_t op_config[7];      /* restarted mode, 3D instances: a nonzero entry fixes that
                                   work split of the masked operators, as reported in the
                                   result's op_config (projector slices per thread 8 / 16 /
@@ -336,6 +340,13 @@ typedef struct {
                                   tuned result's op_config back repeats that solve bit for
                                   bit.  Zero entries are tuned or follow the fixed rules (no
                                   queue, fused)                                            */
+    int32_t tiles_2d[3];       /* batched single-slice instances: a nonzero entry fixes that
+                                  work shape of the 2D pair (the backprojector's tile width
+                                  16 / 32 / 64 voxels, with 256 / width rows; views per
+                                  staged batch 8 / 16 / 32; the projector's bundle of 32 /
+                                  64 / 128 bins by 256 / bins views); shapes other than
+                                  32, 16, 64 need FP32.  With tune_operators the others
+                                  are timed on the batch at setup (FP32)                   */
 } sipo_pdhg_options;
 
 /* Phases of one PDHG iteration, for sipo_pdhg_result.phase_ms. */
@@ -377,6 +388,8 @@ typedef struct {
                                   splits, blur slices per chunk, projector work queue,
                                   primal step and candidate skipping as in the options);
                                   zeros otherwise                                          */
+    int32_t tiles_2d[3];       /* batched single-slice instances: the 2D pair's work shapes
+                                  as run (as in the options); zeros otherwise              */
 } sipo_pdhg_result;
 
 /* Bytes of device workspace sipo_pdhg_solve needs for these problems. */

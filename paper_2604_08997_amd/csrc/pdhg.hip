@@ -800,6 +800,25 @@ constexpr int kMaskBlurZc = 4;
 constexpr size_t kQueueStride = 256;   // bytes per instance of the projector's work-queue counters
 constexpr double kTuneMargin = 0.98;   // a tuning candidate must beat the best so far by 2 %
 
+// The 2D pair's work shapes the batched solver's tuner tries, in preference order (the default first).
+static std::vector<Tiles2D> tiles2d_candidates() {
+    std::vector<Tiles2D> out;
+    for (int shape = 0; shape < 3; ++shape)
+        for (int vb : {16, 8, 32}) {
+            Tiles2D t;
+            t.bx = shape == 0 ? 32 : shape == 1 ? 16 : 64;
+            t.by = 256 / t.bx;
+            t.vb = vb;
+            out.push_back(t);
+        }
+    for (int fb : {32, 128}) {
+        Tiles2D t;
+        t.fb = fb;
+        out.push_back(t);
+    }
+    return out;
+}
+
 static bool use_batch2d(const sipo_problem *probs, int B) {
     for (int i = 0; i < B; ++i) {
         const sipo_plan p = probs[i].plan;
@@ -848,13 +867,20 @@ static Layout make_layout(const sipo_problem *probs, int B) {
             L.part_v = std::max(L.part_v, (size_t)nv);
         }
         if (b2d) {
+            // room for the largest item lists of every 2D work shape the tuner may pick
             const Geo2D g = plan_geo2d(p, 0, 0);
-            std::vector<int4> a, b, c;
-            append_items_bp2d(g, 0, a);
-            append_items_fp2d(g, 0, b);
+            std::vector<int4> c;
+            size_t na = 0, nb = 0;
+            for (const Tiles2D &t : tiles2d_candidates()) {
+                std::vector<int4> a, b;
+                append_items_bp2d(g, 0, a, t);
+                append_items_fp2d(g, 0, b, t);
+                na = std::max(na, a.size());
+                nb = std::max(nb, b.size());
+            }
             append_items_tr2d(g, 0, c);
-            L.max_items_bp += (int)a.size();
-            L.max_items_fp += (int)b.size();
+            L.max_items_bp += (int)na;
+            L.max_items_fp += (int)nb;
             L.max_items_tr += (int)c.size();
         }
     }
@@ -992,6 +1018,7 @@ class Solver {
     std::vector<ZcSaved> zc_saved_;
     int nc_max_ = 3;
     bool bp_staged_ = true;
+    Tiles2D t2d_;                           // work shapes of the batched 2D pair
     int n_max_ = 1;
     std::vector<Inst> in_;
     std::vector<InstC> hin_;
@@ -1105,11 +1132,11 @@ class Solver {
             cv[i] = (int)sv.size() - fv[i];
             if (b2d_) {
                 geo[i] = plan_geo2d(I.p, I.soff, I.voff);
-                append_items_bp2d(geo[i], i, ib);
-                append_items_fp2d(geo[i], i, ifp);
+                append_items_bp2d(geo[i], i, ib, t2d_);
+                append_items_fp2d(geo[i], i, ifp, t2d_);
                 append_items_tr2d(geo[i], i, itr);
                 nc_max_ = std::max(nc_max_, I.p->p3d_nc);
-                bp_staged_ = bp_staged_ && bp2d_stage_fits(I.p->n, I.p->n_bins);
+                bp_staged_ = bp_staged_ && bp2d_stage_fits(I.p->n, I.p->n_bins, t2d_);
                 n_max_ = std::max(n_max_, I.p->n);
             }
         }
@@ -1201,7 +1228,7 @@ class Solver {
     int dose(size_t yf, size_t outf) {   // out = K P^T y on the active instances
         if (b2d_) {
             int rc = launch_bp2d(I_dtype(), bp_staged_, P<Geo2D>(L_.geo), P<int4>(L_.items_bp), n_items_bp_, F(yf),
-                                 F(outf), 0, s_);
+                                 F(outf), 0, s_, t2d_);
             return rc ? rc : mark(SIPO_PHASE_BACKPROJECT);
         }
         for (int i : active_) {
@@ -1239,7 +1266,7 @@ class Solver {
             int rc = launch_tr2d(I_dtype(), P<Geo2D>(L_.geo), P<int4>(L_.items_tr), n_items_tr_, F(zf), F(L_.tmp), s_);
             if (!rc) rc = mark(SIPO_PHASE_TRANSPOSE);
             if (!rc) rc = launch_fp2d(I_dtype(), nc_max_, n_max_, P<Geo2D>(L_.geo), P<int4>(L_.items_fp), n_items_fp_, F(zf),
-                                      F(L_.tmp), F(outf), 0, s_);
+                                      F(L_.tmp), F(outf), 0, s_, t2d_);
             return rc ? rc : mark(SIPO_PHASE_PROJECT);
         }
         for (int i : active_) {
@@ -1526,6 +1553,59 @@ class Solver {
                     p->has_psf ? p->blur_zc : 0, tuned_.k_ms);
         return SIPO_OK;
     }
+    // Work shapes of the batched 2D pair timed on this batch (FP32): the backprojector's tile (32 x 8,
+    // 16 x 16, 64 x 4 voxels) and views per staged batch (16, 8, 32), then the projector's bundle (64,
+    // 32, 128 bins); preference order and 2 % margin as for the 3D splits.  Caller-fixed shapes
+    // (options tiles_2d) are kept.  Only shapes whose staged windows fit every instance are tried.
+    int tune_2d() {
+        constexpr int kReps = 3;
+        const int *fx = o_.tiles_2d;
+        std::vector<int> all(B_);
+        for (int i = 0; i < B_; ++i) all[i] = i;
+        auto fits = [&](const Tiles2D &t) {
+            for (int i = 0; i < B_; ++i)
+                if (!bp2d_stage_fits(in_[i].p->n, in_[i].p->n_bins, t)) return false;
+            return true;
+        };
+        double ms = 0, best_ms = INFINITY;
+        Tiles2D best = t2d_;
+        int rc = SIPO_OK;
+        if (!fx[0] && !fx[1]) {
+            for (const Tiles2D &c : tiles2d_candidates()) {
+                if (c.fb != t2d_.fb || !fits(c)) continue;
+                Tiles2D t = t2d_;
+                t.bx = c.bx; t.by = c.by; t.vb = c.vb;
+                t2d_ = t;
+                rc = set_active(all);
+                if (!rc) rc = time_launches([&]() { return dose(L_.yt, L_.tmp2); }, kReps, ms);
+                if (rc) return rc;
+                if (ms < kTuneMargin * best_ms) { best_ms = ms; best = t; }
+            }
+            t2d_ = best;
+            tuned_.bp_ms = best_ms;
+        }
+        if (!fx[2]) {
+            best_ms = INFINITY;
+            best = t2d_;
+            for (int fb : {64, 32, 128}) {
+                Tiles2D t = t2d_;
+                t.fb = fb;
+                t2d_ = t;
+                rc = set_active(all);
+                if (!rc) rc = time_launches([&]() { return adjoint(L_.lu, L_.q); }, kReps, ms);
+                if (rc) return rc;
+                if (ms < kTuneMargin * best_ms) { best_ms = ms; best = t; }
+            }
+            t2d_ = best;
+            tuned_.p_ms = best_ms;
+        }
+        rc = set_active(all);
+        if (!rc && o_.progress_every > 0)
+            fprintf(stderr, "[sipo] 2D batch of %d: work shapes tuned: P^T %d x %d voxels, %d views per batch %.4f ms, "
+                    "P %d bins x %d views %.4f ms\n", B_, t2d_.bx, t2d_.by, t2d_.vb, tuned_.bp_ms, t2d_.fb, t2d_.fv(),
+                    tuned_.p_ms);
+        return rc;
+    }
     struct Tuned {
         int bp_parts = 0;
         double p_ms = 0, bp_ms = 0, k_ms = 0;
@@ -1694,6 +1774,21 @@ int Solver<T>::setup_common() {
     if (rc) return rc;
     hipLaunchKernelGGL((k_project_y<T>), gS(), dim3(kThreads), 0, s_, F(L_.y), (const uint8_t *)U8(L_.act), segS());
     copyS(L_.yt, L_.y, false);   // t.y starts as y: zero on masked rays, which the primal step never touches
+    if (b2d_) {
+        // the batched 2D pair's work shapes: fixed by the caller, tuned, or the defaults
+        const int *fx = o_.tiles_2d;
+        if (fx[0] || fx[1] || fx[2]) {
+            if (fx[0]) { t2d_.bx = fx[0]; t2d_.by = 256 / fx[0]; }
+            if (fx[1]) t2d_.vb = fx[1];
+            if (fx[2]) t2d_.fb = fx[2];
+            rc = set_active(all);
+            if (rc) return rc;
+        }
+        if (o_.tune_operators && sizeof(T) == 4 && bp_staged_) {
+            rc = tune_2d();
+            if (rc) return rc;
+        }
+    }
     if (o_.mode == SIPO_PDHG_RESTARTED) {
         // From here on the 3D operators skip what the restarted scheme never reads: q = P K z off the
         // active rays, and P^T y away from the labelled voxels and their PSF neighbourhood (every row
@@ -2350,6 +2445,9 @@ int Solver<T>::run(sipo_pdhg_result *res) {
             r.phase_launches[ph] = phase_n_[ph];
         }
         for (int k = 0; k < 7; ++k) r.op_config[k] = 0;
+        r.tiles_2d[0] = b2d_ ? t2d_.bx : 0;
+        r.tiles_2d[1] = b2d_ ? t2d_.vb : 0;
+        r.tiles_2d[2] = b2d_ ? t2d_.fb : 0;
         if (masked_run_ && I.t3) {
             r.op_config[0] = I.p->p3d_zc;
             r.op_config[1] = I.p->bp3d_zc;
@@ -2396,6 +2494,13 @@ static int validate(const sipo_problem &pb, const sipo_pdhg_options &o, int idx,
         SIPO_REQUIRE(c[4] >= -1 && c[4] <= 16, "op_config[4] (projector work queue) must be in [-1, 16], not %d", c[4]);
         SIPO_REQUIRE(c[5] >= -1 && c[5] <= 1, "op_config[5] (primal step) must be -1, 0 or 1, not %d", c[5]);
         SIPO_REQUIRE(c[6] >= -1 && c[6] <= 1, "op_config[6] (candidate skipping) must be -1, 0 or 1, not %d", c[6]);
+        const int *t = o.tiles_2d;
+        SIPO_REQUIRE(t[0] == 0 || t[0] == 16 || t[0] == 32 || t[0] == 64, "tiles_2d[0] (backprojector tile width) must "
+                     "be 0, 16, 32 or 64, not %d", t[0]);
+        SIPO_REQUIRE(t[1] == 0 || t[1] == 8 || t[1] == 16 || t[1] == 32, "tiles_2d[1] (views per staged batch) must be "
+                     "0, 8, 16 or 32, not %d", t[1]);
+        SIPO_REQUIRE(t[2] == 0 || t[2] == 32 || t[2] == 64 || t[2] == 128, "tiles_2d[2] (projector bins per bundle) "
+                     "must be 0, 32, 64 or 128, not %d", t[2]);
     }
     return SIPO_OK;
 }

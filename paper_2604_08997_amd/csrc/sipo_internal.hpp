@@ -241,19 +241,27 @@ struct Geo2D {
     double h, inv_ds, atten;
     const int2 *vial;        // [n]: first and last index along a grid line inside the vial
 };
-constexpr int kB2X = 32, kB2Y = 8;   // P^T tile: 32 x 8 voxels per workgroup
-constexpr int kF2B = 64, kF2V = 4;   // P bundle: 64 bins x 4 walked views per workgroup
+// Work shapes of the 2D pair (256 threads per workgroup): P^T tiles of bx x by voxels with vb walked
+// views staged per batch, P bundles of fb bins x 256 / fb walked views.  The defaults serve every
+// plan; the other shapes exist for FP32 staged launches (the batched solver's tuner picks them).
+struct Tiles2D {
+    int bx = 32, by = 8, vb = 16, fb = 64;
+    int fv() const { return 256 / fb; }
+    bool is_default() const { return bx == 32 && by == 8 && vb == 16 && fb == 64; }
+    bool operator==(const Tiles2D &o) const { return bx == o.bx && by == o.by && vb == o.vb && fb == o.fb; }
+};
+bool tiles2d_valid(const Tiles2D &t);
 Geo2D plan_geo2d(sipo_plan p, long long soff, long long voff);
 // Items of one instance appended to a list: P^T (geo, x0, y0, 0) and P (geo, first walked view, b0, 0).
-void append_items_bp2d(const Geo2D &g, int geo_index, std::vector<int4> &items);
-void append_items_fp2d(const Geo2D &g, int geo_index, std::vector<int4> &items);
-bool bp2d_stage_fits(int n, int n_bins);
+void append_items_bp2d(const Geo2D &g, int geo_index, std::vector<int4> &items, const Tiles2D &t = Tiles2D());
+void append_items_fp2d(const Geo2D &g, int geo_index, std::vector<int4> &items, const Tiles2D &t = Tiles2D());
+bool bp2d_stage_fits(int n, int n_bins, const Tiles2D &t = Tiles2D());
 int launch_bp2d(sipo_dtype dt, bool staged, const Geo2D *geo, const int4 *items, int n_items, const void *sino,
-                void *vol, int accumulate, hipStream_t s);
+                void *vol, int accumulate, hipStream_t s, const Tiles2D &t = Tiles2D());
 // vol_xt: optional [x][y] copy of the volume (from launch_tr2d), read by rays that march along x
 constexpr int kF2MaxN = 16384;   // largest single-slice grid of the 2D projector (its LDS holds n vial extents)
 int launch_fp2d(sipo_dtype dt, int nc, int n_max, const Geo2D *geo, const int4 *items, int n_items, const void *vol,
-                const void *vol_xt, void *sino, int accumulate, hipStream_t s);
+                const void *vol_xt, void *sino, int accumulate, hipStream_t s, const Tiles2D &t = Tiles2D());
 // Per-instance transpose of single-slice volumes: out[x][y] = in[y][x]; items (geo, x0, y0, 0) of 64 x 64 tiles.
 void append_items_tr2d(const Geo2D &g, int geo_index, std::vector<int4> &items);
 int launch_tr2d(sipo_dtype dt, const Geo2D *geo, const int4 *items, int n_items, const void *in, void *out,

@@ -28,42 +28,44 @@ __device__ __forceinline__ bool in_vial(int c, int r, int n) {
     return a * a + b * b <= (long long)n * n;
 }
 
-// P^T.  STAGED: per batch of kB2VB walked views the sinogram window each view
-// (and its partner) can send into the tile is copied to LDS first, so the
-// per-voxel gathers hit LDS; used when the tile's bin window fits kB2W.
-constexpr int kB2VB = 16, kB2W = 48;
+// P^T over TX x TY voxel tiles.  STAGED: per batch of VB walked views the sinogram window each
+// view (and its partner) can send into the tile is copied to LDS first, so the per-voxel gathers
+// hit LDS; used when the tile's bin window fits the staged row width.
+__host__ __device__ constexpr int bp2d_row_width(int tx, int ty) { return tx + ty <= 40 ? 48 : 80; }
 
-template <typename T, bool STAGED>
+template <typename T, bool STAGED, int TX, int TY, int VB>
 __global__ void __launch_bounds__(256) bp2d_kernel(const Geo2D *__restrict__ geo, const int4 *__restrict__ items,
                                                    const T *__restrict__ sino, T *__restrict__ vol, int accumulate) {
-    __shared__ T rows[STAGED ? 2 * kB2VB : 1][STAGED ? kB2W : 1];
-    __shared__ int rbase[2 * kB2VB];
-    __shared__ double2 vtrig[kB2VB];   // (sin, cos) of the batch's walked views
+    static_assert(TX * TY == 256, "one voxel per thread");
+    constexpr int W = bp2d_row_width(TX, TY);
+    __shared__ T rows[STAGED ? 2 * VB : 1][STAGED ? W : 1];
+    __shared__ int rbase[2 * VB];
+    __shared__ double2 vtrig[VB];   // (sin, cos) of the batch's walked views
     // FP32 staged path: per walked view, u at the tile's first voxel relative to each row's first
     // staged bin (the view's, and the mirrored partner's) and u's steps per column and row, split as
     // in taps_rel32, and (sin, cos)
     constexpr bool G32 = STAGED && sizeof(T) == 4;
-    __shared__ float vgeo[G32 ? kB2VB : 1][10];
+    __shared__ float vgeo[G32 ? VB : 1][10];
     const int4 it = items[blockIdx.x];
     const Geo2D &g = geo[it.x];
     const int n = g.n, nb = g.n_bins;
-    const int c = it.y + (int)(threadIdx.x % kB2X), r = it.z + (int)(threadIdx.x / kB2X);
+    const int c = it.y + (int)(threadIdx.x % TX), r = it.z + (int)(threadIdx.x / TX);
     const bool in_grid = c < n && r < n;
     const bool inside = in_grid && in_vial(c, r, n);
     const double x = centre(c, g.h), y = centre(r, g.h);
     const float xf = (float)x, yf = (float)y;
-    const float dcf = (float)(threadIdx.x % kB2X), drf = (float)(threadIdx.x / kB2X);
+    const float dcf = (float)(threadIdx.x % TX), drf = (float)(threadIdx.x / TX);
     const T atten = (T)g.atten;
     const T *s0 = sino + g.soff;
     T acc = (T)0;
-    for (int k0 = 0; k0 < g.n_walk; k0 += (STAGED ? kB2VB : g.n_walk)) {
-        const int nk = STAGED ? min(kB2VB, g.n_walk - k0) : g.n_walk;
+    for (int k0 = 0; k0 < g.n_walk; k0 += (STAGED ? VB : g.n_walk)) {
+        const int nk = STAGED ? min(VB, g.n_walk - k0) : g.n_walk;
         if (STAGED) {
             if ((int)threadIdx.x < 2 * nk) {
                 // first staged bin of row (view, mirror): floor of the smallest u over the tile corners, minus 1
                 const int kk = k0 + (int)threadIdx.x / 2, mir = threadIdx.x & 1;
                 const double2 tr = g.trig[g.walk[kk]];
-                const int cx[2] = {it.y, min(it.y + kB2X, n) - 1}, ry[2] = {it.z, min(it.z + kB2Y, n) - 1};
+                const int cx[2] = {it.y, min(it.y + TX, n) - 1}, ry[2] = {it.z, min(it.z + TY, n) - 1};
                 double umin = 1e300, umax = -1e300;
                 for (int i = 0; i < 2; ++i)
                     for (int j = 0; j < 2; ++j) {
@@ -94,8 +96,8 @@ __global__ void __launch_bounds__(256) bp2d_kernel(const Geo2D *__restrict__ geo
                 }
             }
             __syncthreads();
-            for (int e = threadIdx.x; e < 2 * nk * kB2W; e += 256) {
-                const int row = e / kB2W, col = e - row * kB2W;
+            for (int e = threadIdx.x; e < 2 * nk * W; e += 256) {
+                const int row = e / W, col = e - row * W;
                 const int a = g.walk[k0 + row / 2];
                 const int av = (row & 1) ? (g.pair ? g.partner[a] : -1) : a;
                 const int b = rbase[row] + col;
@@ -112,14 +114,14 @@ __global__ void __launch_bounds__(256) bp2d_kernel(const Geo2D *__restrict__ geo
                 const Split32 ux{vg[4], vg[5]}, uy{vg[6], vg[7]};
                 float w0, w1;
                 int bl = taps_rel32(dcf, drf, Split32{vg[0], vg[1]}, ux, uy, sv, tv, (float)atten, w0, w1);
-                bl = min(max(bl, 0), kB2W - 2);
+                bl = min(max(bl, 0), W - 2);
                 acc = fma((T)w0, rows[2 * kq][bl], acc);
                 acc = fma((T)w1, rows[2 * kq][bl + 1], acc);
                 if (g.pair) {
                     // opposite view: u' = nb - 1 - u (steps negated), t' = -t, same sqrt(1 - s^2)
                     const Split32 nx{-ux.hi, -ux.lo}, ny{-uy.hi, -uy.lo};
                     bl = taps_rel32(dcf, drf, Split32{vg[2], vg[3]}, nx, ny, sv, -tv, (float)atten, w0, w1);
-                    bl = min(max(bl, 0), kB2W - 2);
+                    bl = min(max(bl, 0), W - 2);
                     acc = fma((T)w0, rows[2 * kq + 1][bl], acc);
                     acc = fma((T)w1, rows[2 * kq + 1][bl + 1], acc);
                 }
@@ -140,7 +142,7 @@ __global__ void __launch_bounds__(256) bp2d_kernel(const Geo2D *__restrict__ geo
                     const T w = exp_neg<T>(atten, (T)t + rr);
                     T v0, v1;
                     if (STAGED) {
-                        const int bl = min(max(b - rbase[2 * kq], 0), kB2W - 2);
+                        const int bl = min(max(b - rbase[2 * kq], 0), W - 2);
                         v0 = rows[2 * kq][bl];
                         v1 = rows[2 * kq][bl + 1];
                     } else {
@@ -161,7 +163,7 @@ __global__ void __launch_bounds__(256) bp2d_kernel(const Geo2D *__restrict__ geo
                     const T w = exp_neg<T>(atten, rr - (T)t);
                     T v0, v1;
                     if (STAGED) {
-                        const int bl = min(max(b - rbase[2 * kq + 1], 0), kB2W - 2);
+                        const int bl = min(max(b - rbase[2 * kq + 1], 0), W - 2);
                         v0 = rows[2 * kq + 1][bl];
                         v1 = rows[2 * kq + 1][bl + 1];
                     } else {
@@ -182,7 +184,7 @@ __global__ void __launch_bounds__(256) bp2d_kernel(const Geo2D *__restrict__ geo
     *dst = accumulate ? *dst + acc : acc;
 }
 
-template <typename T, int NC>
+template <typename T, int NC, int FB>
 __global__ void __launch_bounds__(256) fp2d_kernel(const Geo2D *__restrict__ geo, const int4 *__restrict__ items,
                                                    const T *__restrict__ vol, const T *__restrict__ vol_xt,
                                                    T *__restrict__ sino, int accumulate) {
@@ -192,7 +194,7 @@ __global__ void __launch_bounds__(256) fp2d_kernel(const Geo2D *__restrict__ geo
     const int n = g.n, nb = g.n_bins;
     for (int m = threadIdx.x; m < n; m += 256) vials[m] = g.vial[m];
     __syncthreads();
-    const int b = it.z + (int)(threadIdx.x % kF2B), k = it.y + (int)(threadIdx.x / kF2B);
+    const int b = it.z + (int)(threadIdx.x % FB), k = it.y + (int)(threadIdx.x / FB);
     if (b >= nb || k >= g.n_walk) return;
     const int a = g.walk[k];
     const double2 tr = g.trig[a];
@@ -295,9 +297,14 @@ Geo2D plan_geo2d(sipo_plan p, long long soff, long long voff) {
     return g;
 }
 
-void append_items_bp2d(const Geo2D &g, int gi, std::vector<int4> &items) {
-    for (int y0 = 0; y0 < g.n; y0 += kB2Y)
-        for (int x0 = 0; x0 < g.n; x0 += kB2X) items.push_back(make_int4(gi, x0, y0, 0));
+bool tiles2d_valid(const Tiles2D &t) {
+    const bool tile = (t.bx == 32 && t.by == 8) || (t.bx == 16 && t.by == 16) || (t.bx == 64 && t.by == 4);
+    return tile && (t.vb == 8 || t.vb == 16 || t.vb == 32) && (t.fb == 32 || t.fb == 64 || t.fb == 128);
+}
+
+void append_items_bp2d(const Geo2D &g, int gi, std::vector<int4> &items, const Tiles2D &t) {
+    for (int y0 = 0; y0 < g.n; y0 += t.by)
+        for (int x0 = 0; x0 < g.n; x0 += t.bx) items.push_back(make_int4(gi, x0, y0, 0));
 }
 
 void append_items_tr2d(const Geo2D &g, int gi, std::vector<int4> &items) {
@@ -318,49 +325,70 @@ int launch_tr2d(sipo_dtype dt, const Geo2D *geo, const int4 *items, int n_items,
     return SIPO_OK;
 }
 
-void append_items_fp2d(const Geo2D &g, int gi, std::vector<int4> &items) {
-    for (int k0 = 0; k0 < g.n_walk; k0 += kF2V)
-        for (int b0 = 0; b0 < g.n_bins; b0 += kF2B) items.push_back(make_int4(gi, k0, b0, 0));
+void append_items_fp2d(const Geo2D &g, int gi, std::vector<int4> &items, const Tiles2D &t) {
+    for (int k0 = 0; k0 < g.n_walk; k0 += t.fv())
+        for (int b0 = 0; b0 < g.n_bins; b0 += t.fb) items.push_back(make_int4(gi, k0, b0, 0));
 }
 
 // The tile's bin window (with guards) fits the staged row width for this detector/grid ratio.
-bool bp2d_stage_fits(int n, int n_bins) {
-    const double span = std::sqrt((double)(kB2X - 1) * (kB2X - 1) + (double)(kB2Y - 1) * (kB2Y - 1)) * n_bins / n;
-    return span + 5.0 <= (double)kB2W;
+bool bp2d_stage_fits(int n, int n_bins, const Tiles2D &t) {
+    const double span = std::sqrt((double)(t.bx - 1) * (t.bx - 1) + (double)(t.by - 1) * (t.by - 1)) * n_bins / n;
+    return span + 5.0 <= (double)bp2d_row_width(t.bx, t.by);
+}
+
+template <typename T, bool STAGED, int TX, int TY>
+static void bp2d_vb(const Tiles2D &t, dim3 grid, const Geo2D *geo, const int4 *items, const void *sino, void *vol,
+                    int accumulate, hipStream_t s) {
+    switch (t.vb) {
+        case 8: hipLaunchKernelGGL((bp2d_kernel<T, STAGED, TX, TY, 8>), grid, dim3(256), 0, s, geo, items,
+                                   (const T *)sino, (T *)vol, accumulate); break;
+        case 32: hipLaunchKernelGGL((bp2d_kernel<T, STAGED, TX, TY, 32>), grid, dim3(256), 0, s, geo, items,
+                                    (const T *)sino, (T *)vol, accumulate); break;
+        default: hipLaunchKernelGGL((bp2d_kernel<T, STAGED, TX, TY, 16>), grid, dim3(256), 0, s, geo, items,
+                                    (const T *)sino, (T *)vol, accumulate); break;
+    }
 }
 
 int launch_bp2d(sipo_dtype dt, bool staged, const Geo2D *geo, const int4 *items, int n_items, const void *sino,
-                void *vol, int accumulate, hipStream_t s) {
+                void *vol, int accumulate, hipStream_t s, const Tiles2D &t) {
     if (n_items <= 0) return SIPO_OK;
-    const dim3 grid(n_items), block(256);
-    if (dt == SIPO_F64) {
-        if (staged) hipLaunchKernelGGL((bp2d_kernel<double, true>), grid, block, 0, s, geo, items, (const double *)sino,
-                                       (double *)vol, accumulate);
-        else hipLaunchKernelGGL((bp2d_kernel<double, false>), grid, block, 0, s, geo, items, (const double *)sino,
-                                (double *)vol, accumulate);
+    if (!tiles2d_valid(t)) return fail(SIPO_E_INVALID, "2D backprojector: unsupported tile %d x %d, %d views", t.bx,
+                                       t.by, t.vb);
+    const dim3 grid(n_items);
+    if (dt == SIPO_F64 || !staged) {
+        // the other shapes serve FP32 staged launches only
+        if (!t.is_default())
+            return fail(SIPO_E_UNSUPPORTED, "2D backprojector: %d x %d tiles need an FP32 staged launch", t.bx, t.by);
+        if (dt == SIPO_F64) {
+            if (staged) bp2d_vb<double, true, 32, 8>(t, grid, geo, items, sino, vol, accumulate, s);
+            else bp2d_vb<double, false, 32, 8>(t, grid, geo, items, sino, vol, accumulate, s);
+        } else {
+            bp2d_vb<float, false, 32, 8>(t, grid, geo, items, sino, vol, accumulate, s);
+        }
+    } else if (t.bx == 16) {
+        bp2d_vb<float, true, 16, 16>(t, grid, geo, items, sino, vol, accumulate, s);
+    } else if (t.bx == 64) {
+        bp2d_vb<float, true, 64, 4>(t, grid, geo, items, sino, vol, accumulate, s);
     } else {
-        if (staged) hipLaunchKernelGGL((bp2d_kernel<float, true>), grid, block, 0, s, geo, items, (const float *)sino,
-                                       (float *)vol, accumulate);
-        else hipLaunchKernelGGL((bp2d_kernel<float, false>), grid, block, 0, s, geo, items, (const float *)sino,
-                                (float *)vol, accumulate);
+        bp2d_vb<float, true, 32, 8>(t, grid, geo, items, sino, vol, accumulate, s);
     }
     SIPO_LAUNCHED("bp2d_kernel");
     return SIPO_OK;
 }
 
-template <typename T>
+template <typename T, int FB>
 static int fp2d_t(int nc, int n_max, const Geo2D *geo, const int4 *items, int n_items, const void *vol,
                   const void *vol_xt, void *sino, int accumulate, hipStream_t s) {
     const dim3 grid(n_items), block(256);
     const size_t shm = sizeof(int2) * (size_t)n_max;
     const T *v = (const T *)vol, *vx = (const T *)vol_xt;
     switch (nc) {
-        case 3: hipLaunchKernelGGL((fp2d_kernel<T, 3>), grid, block, shm, s, geo, items, v, vx, (T *)sino, accumulate);
-                break;
-        case 4: hipLaunchKernelGGL((fp2d_kernel<T, 4>), grid, block, shm, s, geo, items, v, vx, (T *)sino, accumulate);
-                break;
-        case 6: hipLaunchKernelGGL((fp2d_kernel<T, 6>), grid, block, shm, s, geo, items, v, vx, (T *)sino, accumulate);
-                break;
+        case 3: hipLaunchKernelGGL((fp2d_kernel<T, 3, FB>), grid, block, shm, s, geo, items, v, vx, (T *)sino,
+                                   accumulate); break;
+        case 4: hipLaunchKernelGGL((fp2d_kernel<T, 4, FB>), grid, block, shm, s, geo, items, v, vx, (T *)sino,
+                                   accumulate); break;
+        case 6: hipLaunchKernelGGL((fp2d_kernel<T, 6, FB>), grid, block, shm, s, geo, items, v, vx, (T *)sino,
+                                   accumulate); break;
         default: return fail(SIPO_E_UNSUPPORTED, "2D projector: unsupported candidate count %d", nc);
     }
     SIPO_LAUNCHED("fp2d_kernel");
@@ -368,11 +396,19 @@ static int fp2d_t(int nc, int n_max, const Geo2D *geo, const int4 *items, int n_
 }
 
 int launch_fp2d(sipo_dtype dt, int nc, int n_max, const Geo2D *geo, const int4 *items, int n_items, const void *vol,
-                const void *vol_xt, void *sino, int accumulate, hipStream_t s) {
+                const void *vol_xt, void *sino, int accumulate, hipStream_t s, const Tiles2D &t) {
     if (n_items <= 0) return SIPO_OK;
     if (n_max < 1 || n_max > kF2MaxN) return fail(SIPO_E_UNSUPPORTED, "2D projector: grid %d > %d", n_max, kF2MaxN);
-    return dt == SIPO_F64 ? fp2d_t<double>(nc, n_max, geo, items, n_items, vol, vol_xt, sino, accumulate, s)
-                          : fp2d_t<float>(nc, n_max, geo, items, n_items, vol, vol_xt, sino, accumulate, s);
+    if (!tiles2d_valid(t)) return fail(SIPO_E_INVALID, "2D projector: unsupported bundle of %d bins", t.fb);
+    if (dt == SIPO_F64) {
+        if (t.fb != 64) return fail(SIPO_E_UNSUPPORTED, "2D projector: %d-bin bundles need FP32", t.fb);
+        return fp2d_t<double, 64>(nc, n_max, geo, items, n_items, vol, vol_xt, sino, accumulate, s);
+    }
+    switch (t.fb) {
+        case 32: return fp2d_t<float, 32>(nc, n_max, geo, items, n_items, vol, vol_xt, sino, accumulate, s);
+        case 128: return fp2d_t<float, 128>(nc, n_max, geo, items, n_items, vol, vol_xt, sino, accumulate, s);
+        default: return fp2d_t<float, 64>(nc, n_max, geo, items, n_items, vol, vol_xt, sino, accumulate, s);
+    }
 }
 
 // The plan as a one-instance batch (single-slice plans only).

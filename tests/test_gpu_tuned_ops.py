@@ -150,3 +150,75 @@ def test_projector_work_queue_at_full_size_leaves_iterates_unchanged():
         else:
             # both forms of the primal step evaluate the same expressions
             assert r0["primal_obj"] == pytest.approx(fused["primal_obj"], rel=1e-5)
+
+
+# ---- the batched 2D pair's work shapes (P^T tiles and staged view batches, P bundles)
+SMALL2D = [(20, 12, 1, 31), (28, 24, 2, 32), (36, 18, 0, 33), (24, 15, 1, 34), (48, 30, 2, 35)]
+
+
+def batch2d(dtype=torch.float32, band=3.0):
+    import paper_2604_08997_amd as sipo
+    from oracle.projector import Projector as OP
+    from sipo_inputs import ellipses_target
+    lps, ops = [], []
+    for n, na, case, seed in SMALL2D:
+        f = ellipses_target(n, seed)
+        kw = {"cap": 0.9} if case == 2 else {}
+        plan = sipo.Plan(n, list(angles_uniform(na)), dtype=dtype, device=dev())
+        lps.append(sipo.LP.build(plan, torch.as_tensor(f, dtype=dtype, device=dev()), case, band_width=band,
+                                 f_min=1.0, **kw))
+        ops.append(olp.build(OP(make_geometry(n, angles_uniform(na), atten=1.0)), f, case, band_width=band, **kw))
+    return lps, ops
+
+
+def solve2d(tiles=None, tune=0, iters=640):
+    import paper_2604_08997_amd as sipo
+    lps, ops = batch2d()
+    res = sipo.solve(lps, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=iters, tol=1e-12, check_every=64,
+                                            tiles_2d=tiles, tune_operators=tune, progress_every=1 << 20 if tune else 0))
+    return res, [[t.double().cpu().numpy().copy() for t in (lp.y, lp.lam_up, lp.lam_lo)] for lp in lps], ops
+
+
+def test_2d_projector_bundles_leave_iterates_unchanged():
+    # a bundle's shape only regroups rays: each ray's march and sums are the same
+    r0, st0, _ = solve2d()
+    assert all(r["tiles_2d"] == {"bp_tile_x": 32, "bp_views": 16, "fp_bins": 64} for r in r0)
+    for fb in (32, 128):
+        r1, st1, _ = solve2d({"fp_bins": fb})
+        assert all(r["tiles_2d"]["fp_bins"] == fb for r in r1)
+        for a, b in zip(st0, st1):
+            for x, y in zip(a, b):
+                np.testing.assert_array_equal(x, y)
+
+
+def test_2d_backprojector_tiles_match_oracle_kkt():
+    # other tiles and view batches regroup the FP32 tap geometry (split origins per tile and view),
+    # so iterates agree to rounding: each returned state is checked by the oracle's residuals
+    for tiles in ({"bp_tile_x": 16, "bp_views": 8}, {"bp_tile_x": 64, "bp_views": 32}, {"bp_tile_x": 32, "bp_views": 32}):
+        res, states, ops = solve2d(tiles)
+        for r, (y, lu, ll), op in zip(res, states, ops):
+            assert r["tiles_2d"]["bp_tile_x"] == tiles["bp_tile_x"] and r["tiles_2d"]["bp_views"] == tiles["bp_views"]
+            k = okkt.residuals(op, y, r["u"], r["v"], lu, ll)
+            assert k.primal_obj == pytest.approx(r["primal_obj"], rel=1e-5, abs=1e-7)
+            for got, want in ((r["rel_primal"], k.eps_p), (r["rel_dual"], k.eps_d)):
+                assert got == pytest.approx(want, rel=2e-2, abs=1e-6), (tiles, got, want)
+
+
+def test_2d_tuned_shapes_repeat_bit_for_bit(capfd):
+    res, states, _ = solve2d(tune=1)
+    assert "work shapes tuned" in capfd.readouterr().err
+    t = res[0]["tiles_2d"]
+    assert t["bp_tile_x"] in (16, 32, 64) and t["bp_views"] in (8, 16, 32) and t["fp_bins"] in (32, 64, 128)
+    res2, states2, _ = solve2d(t)
+    assert [r["tiles_2d"] for r in res2] == [t] * len(res2)
+    for a, b in zip(states, states2):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_invalid_2d_shapes_are_rejected():
+    import paper_2604_08997_amd as sipo
+    lps, _ = batch2d()
+    for bad in ({"bp_tile_x": 8}, {"bp_views": 12}, {"fp_bins": 16}):
+        with pytest.raises(RuntimeError, match="tiles_2d"):
+            sipo.solve(lps, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=64, tiles_2d=bad))
