@@ -57,3 +57,40 @@ def test_512cube_720_projector_pair_and_blur_sampled():
     want_b = np.array([rows[k] @ sino[:, vz[k], :].astype(np.float64).reshape(-1) for k in range(2000)]).ravel()
     got_b = bp[torch.as_tensor(vz), torch.as_tensor(vr), torch.as_tensor(vc)].double().cpu().numpy()
     assert rel_norm(got_b, want_b) < 1e-5
+
+
+def test_512cube_720_checkpointed_backward_sampled():
+    # configs[4]'s backward: a nonlinear objective of dose = K P^T p through torch.utils.checkpoint, so
+    # the forward is recomputed in the backward pass and nothing of it is kept; the backward itself
+    # keeps nothing either (the projector recomputes the attenuation factors).  Sampled entries of
+    # grad p = P K (dL/dD) against the oracle, dL/dD = 2 max(D - thr, 0) formed from the GPU's dose.
+    import paper_2604_08997_amd as sipo
+    from torch.utils.checkpoint import checkpoint
+    dev = torch.device("cuda", 0)
+    ang = angles_uniform(NA)
+    plan = sipo.Plan(N, list(ang), nz=N, sigma=SIGMA, dtype=torch.float32, device=dev)
+    p = torch.as_tensor(uniform_field((NA, N, N), 4004).astype(np.float32), device=dev)
+    with torch.no_grad():
+        D = sipo.dose(p, plan).double().cpu().numpy()
+    thr = float(np.median(D[D > 0]))   # the hinge is active on about half of the vial
+    p.requires_grad_(True)
+
+    def objective(q):
+        return (torch.relu(sipo.dose(q, plan) - thr) ** 2).sum()
+
+    loss = checkpoint(objective, p, use_reentrant=False)
+    loss.backward()
+    grad = p.grad
+    dD = 2.0 * np.maximum(D - thr, 0.0)
+    assert 0.2 < float((dD > 0).mean()) < 0.8
+    del D
+    kdd = oblur.apply(dD, oblur.psf_taps(SIGMA))
+    del dD
+    rng = np.random.default_rng(4005)
+    views = rng.choice(NA, 8, replace=False)
+    PT_v = slice_matrix(make_geometry(N, ang[views], atten=1.0))
+    iv, iz, ib = rng.integers(0, 8, 2000), rng.integers(0, N, 2000), rng.integers(0, N, 2000)
+    cols = PT_v[:, iv * N + ib].tocsc()
+    want = np.array([cols[:, k].T @ kdd[iz[k]].reshape(-1) for k in range(2000)]).ravel()
+    got = grad[torch.as_tensor(views[iv]), torch.as_tensor(iz), torch.as_tensor(ib)].double().cpu().numpy()
+    assert rel_norm(got, want) < 1e-5
