@@ -1830,22 +1830,28 @@ int Solver<T>::setup_common() {
         if (o_.tune_operators) {
             // tune on the first instance of each plan, then rebuild every instance's flags for the
             // plan's chosen slice counts (instances of one plan share them)
-            std::vector<std::pair<sipo_plan, int>> chosen;   // plan, backprojector view splits
+            struct Chosen { sipo_plan p; int parts, tuned_on; };   // plan, view splits, instance tuned on
+            std::vector<Chosen> chosen;
             for (int i = 0; i < B_; ++i) {
                 if (!in_[i].t3) continue;
                 bool seen = false;
-                for (auto &c : chosen) seen = seen || c.first == in_[i].p;
+                for (auto &c : chosen) seen = seen || c.p == in_[i].p;
                 if (seen) continue;
                 int parts = 0;
                 rc = tune_masked(i, parts);
                 if (rc) return rc;
-                chosen.push_back({in_[i].p, parts});
+                chosen.push_back({in_[i].p, parts, i});
             }
             for (int i = 0; i < B_; ++i) {
                 if (!in_[i].t3) continue;
                 int parts = 0;
                 for (auto &c : chosen)
-                    if (c.first == in_[i].p) parts = c.second;
+                    if (c.p == in_[i].p) {
+                        // the queue width and the primal step's form are per instance: take the tuned ones
+                        parts = c.parts;
+                        pqueue_[i] = pqueue_[c.tuned_on];
+                        pfuse_[i] = pfuse_[c.tuned_on];
+                    }
                 rc = mask_setup(i, parts);
                 if (rc) return rc;
             }

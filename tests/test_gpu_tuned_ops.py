@@ -152,6 +152,20 @@ def test_projector_work_queue_at_full_size_leaves_iterates_unchanged():
             assert r0["primal_obj"] == pytest.approx(fused["primal_obj"], rel=1e-5)
 
 
+def test_tuned_batch_of_one_plan_shares_its_picks():
+    # two 256^3 x 360 instances of one plan: the splits are tuned on the first and every instance of
+    # the plan runs them, the queue width and the primal step's form included
+    import paper_2604_08997_amd as sipo
+    n, na = 256, 360
+    plan = sipo.Plan(n, list(angles_uniform(na)), nz=n, sigma=SIGMA, dtype=torch.float32, device=dev())
+    lps = [sipo.LP.build(plan, torch.as_tensor(ellipsoids_target(n, seed), dtype=torch.float32, device=dev()),
+                         sipo.CASE1, band_width=10.0, f_min=1.0) for seed in (3000, 3001)]
+    res = sipo.solve(lps, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=64, tol=1e-12, tune_operators=1),
+                     want_dose=False)
+    assert res[0]["op_config"] == res[1]["op_config"]
+    assert res[0]["op_config"]["p_zc"] in (8, 16, 32)
+
+
 # ---- the batched 2D pair's work shapes (P^T tiles and staged view batches, P bundles)
 SMALL2D = [(20, 12, 1, 31), (28, 24, 2, 32), (36, 18, 0, 33), (24, 15, 1, 34), (48, 30, 2, 35)]
 
