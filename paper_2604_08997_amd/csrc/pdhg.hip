@@ -772,6 +772,8 @@ struct Layout {
     size_t ps_bytes = 0, pc_bytes = 0, reach_bytes = 0;
     size_t psteps = 0, pcount = 0, preach = 0;  // their fields; the reach masks of the list builder
     size_t pitems = 0, pqueue = 0;              // the projector's work queue: tiles (offsets pco) and counters
+    std::vector<size_t> bno;                    // and of its backprojector's per-column need mask
+    size_t bn_bytes = 0, bneed = 0;
     std::vector<size_t> kfo;                    // and of its two blur tile flag arrays (own, reach)
     size_t kf_bytes = 0, kflags = 0;
     size_t pf_bytes = 0, bf_bytes = 0;          // projector / backprojector flag totals
@@ -838,6 +840,7 @@ static Layout make_layout(const sipo_problem *probs, int B) {
     L.pso.assign(B, 0);
     L.pco.assign(B, 0);
     L.kfo.assign(B, 0);
+    L.bno.assign(B, 0);
     const bool b2d = use_batch2d(probs, B);
     for (int i = 0; i < B; ++i) {
         const sipo_plan p = probs[i].plan;
@@ -860,7 +863,9 @@ static Layout make_layout(const sipo_problem *probs, int B) {
             L.pco[i] = L.pc_bytes;
             L.ps_bytes += align_up(sizeof(int) * p3d_flag_count(p, 8) * (size_t)p->n);
             L.pc_bytes += align_up(sizeof(int) * p3d_flag_count(p, 8));
-            L.reach_bytes = std::max(L.reach_bytes, p3d_reach_bytes(p, 8));
+            L.reach_bytes = std::max(L.reach_bytes, std::max(p3d_reach_bytes(p, 8), bp3d_need_bytes(p, 4)));
+            L.bno[i] = L.bn_bytes;
+            L.bn_bytes += align_up(bp3d_need_bytes(p, 4));
             L.kfo[i] = L.kf_bytes;
             L.kf_bytes += 2 * align_up(blur_tile_count(p, kMaskBlurZc)) + align_up(vol_t_tile_count(p));
             L.part_s = std::max(L.part_s, (size_t)ns);
@@ -906,6 +911,7 @@ static Layout make_layout(const sipo_problem *probs, int B) {
     L.pitems = take(L.pc_bytes);
     L.pqueue = take((size_t)kQueueStride * B);
     L.preach = take(L.reach_bytes);
+    L.bneed = take(L.bn_bytes);
     L.kflags = take(L.kf_bytes);
     L.ppart = take(L.part_s * L.eb * kMaxSplitP);
     L.bpart = take(L.part_v * L.eb * kMaxSplitB);
@@ -1341,6 +1347,7 @@ class Solver {
         };
         int rc = launch_p3d_flags(p, U8(L_.act) + I.soff, U8(L_.pflags) + L_.pfo[i], s_);
         if (!rc) rc = launch_bp3d_flags(p, U8(L_.lab) + I.voff, U8(L_.bflags) + L_.bfo[i], s_);
+        if (!rc) rc = launch_bp3d_need(p, U8(L_.lab) + I.voff, U8(L_.preach), U8(L_.bneed) + L_.bno[i], s_);
         if (!rc) rc = launch_blur_flags(p, U8(L_.lab) + I.voff, blur_own(i), blur_reach(i), s_);
         if (!rc) rc = launch_vol_t_flags(p, blur_reach(i), vol_t_on(i), s_);
         if (rc) return rc;
@@ -1358,6 +1365,7 @@ class Solver {
         psp_[i] = SplitSpec{parts_for(onp, cus_, kMaxSplitP), F(L_.ppart)};
         bsp_[i] = SplitSpec{bparts > 0 ? std::min(bparts, kMaxSplitB) : parts_for(onb, 4LL * cus_, kMaxSplitB),
                             F(L_.bpart)};
+        bsp_[i].need = U8(L_.bneed) + L_.bno[i];
         // the primal step rides in the projector's output when its march is not split (FP32), unless
         // it is set to run as its own kernel
         fused_[i] = sizeof(T) == 4 && p->p3d_dma && psp_[i].parts == 1 && pfuse_[i] >= 0;

@@ -160,7 +160,8 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
                                                             const double2 *__restrict__ trig, double h,
                                                             double inv_ds, T atten, int accumulate,
                                                             const uint8_t *__restrict__ tile_on, int nsplit,
-                                                            long long split_stride) {
+                                                            long long split_stride,
+                                                            const uint8_t *__restrict__ need) {
     using V4 = typename Vec4<T>::type;
     constexpr int Z4 = ZC / 4, ZP = ZC + 4;
     __shared__ __align__(16) T lds[kBpTB][kBpW][ZP];
@@ -188,9 +189,13 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
     const double yv[2] = {centre(r[0], h), centre(r[1], h)};
     const float xf = (float)xv, yf[2] = {(float)yv[0], (float)yv[1]};
     const float dcf = (float)tx, drf[2] = {(float)ty, (float)(ty + 8)};
+    // need (masked solves): per z chunk and column, whether any of the column's voxels in the chunk
+    // is read; the lanes of the others skip the sum and store zero, and a wave whose lanes all skip
+    // issues no LDS reads or FMAs
     bool inside[2];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) inside[j] = c < n && r[j] < n && vial_ij(c, r[j], n);
+    for (int j = 0; j < 2; ++j)
+        inside[j] = c < n && r[j] < n && vial_ij(c, r[j], n) && (!need || need[((size_t)zb * n + r[j]) * n + c]);
     T acc[2][ZC];
 #pragma unroll
     for (int j = 0; j < 2; ++j)
@@ -1290,11 +1295,13 @@ static void bp3d_zc(sipo_plan p, const void *sino_t, void *vol, int accumulate, 
     if (p->nz % 4 == 0 && ZC <= 16)
         hipLaunchKernelGGL((backproject3d_kernel<T, ZC, ZC <= 16>), dim3(gx, gy, gz * ns), dim3(256), 0, s,
                            (const T *)sino_t, (T *)(ns > 1 ? sp.partial : vol), p->n, p->nz, p->n_angles, p->n_bins,
-                           p->d_trig, h, inv_ds, (T)p->atten, accumulate, on, ns, (long long)p->vol_elems());
+                           p->d_trig, h, inv_ds, (T)p->atten, accumulate, on, ns, (long long)p->vol_elems(),
+                           on ? sp.need : nullptr);
     else
         hipLaunchKernelGGL((backproject3d_kernel<T, ZC, false>), dim3(gx, gy, gz * ns), dim3(256), 0, s,
                            (const T *)sino_t, (T *)(ns > 1 ? sp.partial : vol), p->n, p->nz, p->n_angles, p->n_bins,
-                           p->d_trig, h, inv_ds, (T)p->atten, accumulate, on, ns, (long long)p->vol_elems());
+                           p->d_trig, h, inv_ds, (T)p->atten, accumulate, on, ns, (long long)p->vol_elems(),
+                           on ? sp.need : nullptr);
     if (ns > 1) {
         const long long total = (long long)p->vol_elems();
         hipLaunchKernelGGL((k_bp3d_reduce<T, ZC>), dim3(gx, gy, gz), dim3(256), 0, s, (const T *)sp.partial,
@@ -1726,6 +1733,23 @@ int launch_bp3d_flags(sipo_plan p, const uint8_t *labels, uint8_t *flags, hipStr
     hipLaunchKernelGGL(k_bp3d_flags, dim3((unsigned)std::min<long long>((total + 255) / 256, 16384)), dim3(256), 0, s,
                        labels, flags, p->n, p->nz, rx, ry, rz, p->bp3d_zc, gx, gy, gz);
     SIPO_LAUNCHED("k_bp3d_flags");
+    return SIPO_OK;
+}
+
+size_t bp3d_need_bytes(sipo_plan p, int zc) {
+    if (zc <= 0) zc = p->bp3d_zc;
+    return p->fast3d() ? (size_t)((p->nz + zc - 1) / zc) * p->n * p->n : 0;
+}
+
+int launch_bp3d_need(sipo_plan p, const uint8_t *labels, uint8_t *scratch, uint8_t *need, hipStream_t s) {
+    if (!p->fast3d()) return SIPO_OK;
+    const int zc = p->bp3d_zc, nzc = (p->nz + zc - 1) / zc;
+    const int rx = p->has_psf ? p->taps_d.rx : 0, ry = p->has_psf ? p->taps_d.ry : 0, rz = p->has_psf ? p->taps_d.rz : 0;
+    const long long total = (long long)nzc * p->n * p->n;
+    const unsigned g = (unsigned)std::min<long long>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_reach_z, dim3(g), dim3(256), 0, s, labels, scratch, p->n, p->nz, zc, nzc, rz);
+    hipLaunchKernelGGL(k_reach_xy, dim3(g), dim3(256), 0, s, (const uint8_t *)scratch, need, p->n, nzc, rx, ry);
+    SIPO_LAUNCHED("k_reach_xy");
     return SIPO_OK;
 }
 

@@ -166,6 +166,10 @@ struct SplitSpec {
     int parts = 1;
     void *partial = nullptr;
     bool keep_off = false;
+    // masked backprojector: per z chunk of its slices, row and column, whether any voxel of the
+    // column in the chunk lies within the PSF box of a labelled voxel (launch_bp3d_need); voxels
+    // of the other columns are stored as zero
+    const uint8_t *need = nullptr;
 };
 int launch_backproject_t(sipo_plan p, const void *sino_t, void *vol, int accumulate, hipStream_t s,
                          const uint8_t *tile_on = nullptr, const SplitSpec &sp = SplitSpec());
@@ -212,6 +216,10 @@ int launch_p3d_steps(sipo_plan p, const uint8_t *labels, const uint8_t *wg_on, u
 // (zc <= 0: the plan's current tuning)
 size_t p3d_flag_count(sipo_plan p, int zc = 0);
 size_t bp3d_flag_count(sipo_plan p, int zc = 0);
+// Bytes of the backprojector's per-column need mask at zc slices per thread (0 = the plan's), and
+// its builder (scratch: as many bytes, overwritten).
+size_t bp3d_need_bytes(sipo_plan p, int zc = 0);
+int launch_bp3d_need(sipo_plan p, const uint8_t *labels, uint8_t *scratch, uint8_t *need, hipStream_t s);
 int launch_p3d_flags(sipo_plan p, const uint8_t *act_t, uint8_t *flags, hipStream_t s);
 int launch_bp3d_flags(sipo_plan p, const uint8_t *labels, uint8_t *flags, hipStream_t s);
 // tile_on: optional flags per 16 (z) x 256 (y n + x) tile of the volume (see vol_t_tile_count);
