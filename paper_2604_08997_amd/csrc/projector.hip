@@ -169,7 +169,9 @@ __global__ void __launch_bounds__(256) backproject3d_kernel(const T *__restrict_
     // FP32: per view of the batch, the detector coordinate at the tile's origin relative to its first
     // staged bin and its increments per column and row (hi / lo splits, see taps_rel32), and (sin, cos)
     __shared__ float geo_s[sizeof(T) == 4 ? kBpTB : 1][8];
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    // a wave owns two 8 x 8 blocks of the tile's 32 x 16 columns (rows ty and ty + 8 of its 8 columns):
+    // compact blocks let whole waves skip where the needed voxels end (need)
+    const int tx = ((threadIdx.x >> 6) << 3) | (threadIdx.x & 7), ty = (threadIdx.x >> 3) & 7;
     // grid.z = z chunks x view splits; split s sums its share of the views into partial sum s
     const int3 tile = xcd_tile<kXcdRunBp>();
     const int nzc = gridDim.z / nsplit, zb = tile.z % nzc, split = tile.z / nzc;
