@@ -25,10 +25,15 @@ constexpr int kBlurMaskedPF = 2;   // slices fetched ahead by tile-masked launch
 // outside it selected to zero, so the compiler can count them in its memory waits; slices are fetched PF
 // ahead into statically indexed register slots, and the walk is padded to a multiple of PF (a padded slice
 // re-reads the last walked one and stores nothing).
-template <typename T, int RXY, int RZ, int PF>
+// TOUT (FP32, tile-masked, z chunks and nz multiples of 4): the output goes to the projector's
+// z-contiguous layout [y][x][z] instead of [z][y][x]: a thread keeps its rows' last four output slices
+// and stores them as one 16-byte word, so no separate transpose follows; switched-off tiles write
+// nothing (that layout holds zeros there).
+template <typename T, int RXY, int RZ, int PF, bool TOUT = false>
 __global__ void __launch_bounds__(256) blur_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int nz,
                                                    Taps<T> tp, int zchunk, const uint8_t *__restrict__ tile_on,
                                                    int zero_off) {
+    static_assert(!TOUT || (sizeof(T) == 4 && PF > 1), "z-contiguous output: FP32 tile-masked launches");
     constexpr int RW = kBTX + 2 * RXY, RH = kBTY + 2 * RXY;
     constexpr int LR = (RH + 3) / 4;   // staged rows per thread
     __shared__ T raw[RH][RW + 1];
@@ -99,6 +104,7 @@ __global__ void __launch_bounds__(256) blur_kernel(const T *__restrict__ in, T *
     for (int j = 0; j < kBRows; ++j)
 #pragma unroll
         for (int m = 0; m < 2 * RZ + 1; ++m) ring[j][m] = (T)0;
+    T zq[TOUT ? kBRows : 1][4];   // TOUT: the last four output slices of each row
 
     // x and y passes of the staged slice zi, the z ring, and output slice zi - RZ
     auto blur_slice = [&](int zi) {
@@ -136,7 +142,17 @@ __global__ void __launch_bounds__(256) blur_kernel(const T *__restrict__ in, T *
                 T s = (T)0;
 #pragma unroll
                 for (int m = 0; m < 2 * RZ + 1; ++m) s = fma(tp.kz[m], ring[j][m], s);
-                if (gx < n && gy < n) out[(size_t)zo * plane + (size_t)gy * n + gx] = s;
+                if constexpr (TOUT) {
+                    zq[j][0] = zq[j][1];
+                    zq[j][1] = zq[j][2];
+                    zq[j][2] = zq[j][3];
+                    zq[j][3] = s;
+                    if (((zo - z0) & 3) == 3 && gx < n && gy < n)
+                        *(float4 *)(out + ((size_t)gy * n + gx) * nz + (zo - 3)) =
+                            make_float4(zq[j][0], zq[j][1], zq[j][2], zq[j][3]);
+                } else {
+                    if (gx < n && gy < n) out[(size_t)zo * plane + (size_t)gy * n + gx] = s;
+                }
             }
         }
     };
@@ -272,8 +288,15 @@ int launch_vol_t_flags(sipo_plan p, const uint8_t *reach, uint8_t *tflags, hipSt
 
 template <typename T, int RXY, int RZ>
 static void launch_r(const Taps<T> &tp, const void *in, void *out, int n, int nz, int zchunk, hipStream_t s,
-                     const uint8_t *on, int zero_off) {
+                     const uint8_t *on, int zero_off, bool tout) {
     const dim3 grid((n + kBTX - 1) / kBTX, (n + kBTY - 1) / kBTY, (nz + zchunk - 1) / zchunk);
+    if constexpr (sizeof(T) == 4) {
+        if (tout) {
+            hipLaunchKernelGGL((blur_kernel<T, RXY, RZ, kBlurMaskedPF, true>), grid, dim3(kBTX, 4), 0, s, (const T *)in,
+                               (T *)out, n, nz, tp, zchunk, on, 0);
+            return;
+        }
+    }
     if (on)
         hipLaunchKernelGGL((blur_kernel<T, RXY, RZ, kBlurMaskedPF>), grid, dim3(kBTX, 4), 0, s, (const T *)in,
                            (T *)out, n, nz, tp, zchunk, on, zero_off);
@@ -284,17 +307,17 @@ static void launch_r(const Taps<T> &tp, const void *in, void *out, int n, int nz
 
 template <typename T, int RXY>
 static int launch_rz(const Taps<T> &tp, const void *in, void *out, int n, int nz, int zc, hipStream_t s,
-                     const uint8_t *on, int zero_off) {
+                     const uint8_t *on, int zero_off, bool tout) {
     switch (tp.rz) {
-        case 0: launch_r<T, RXY, 0>(tp, in, out, n, nz, zc, s, on, zero_off); break;
-        case 1: launch_r<T, RXY, 1>(tp, in, out, n, nz, zc, s, on, zero_off); break;
-        case 2: launch_r<T, RXY, 2>(tp, in, out, n, nz, zc, s, on, zero_off); break;
-        case 3: launch_r<T, RXY, 3>(tp, in, out, n, nz, zc, s, on, zero_off); break;
-        case 4: launch_r<T, RXY, 4>(tp, in, out, n, nz, zc, s, on, zero_off); break;
-        case 5: launch_r<T, RXY, 5>(tp, in, out, n, nz, zc, s, on, zero_off); break;
-        case 6: launch_r<T, RXY, 6>(tp, in, out, n, nz, zc, s, on, zero_off); break;
-        case 7: launch_r<T, RXY, 7>(tp, in, out, n, nz, zc, s, on, zero_off); break;
-        case 8: launch_r<T, RXY, 8>(tp, in, out, n, nz, zc, s, on, zero_off); break;
+        case 0: launch_r<T, RXY, 0>(tp, in, out, n, nz, zc, s, on, zero_off, tout); break;
+        case 1: launch_r<T, RXY, 1>(tp, in, out, n, nz, zc, s, on, zero_off, tout); break;
+        case 2: launch_r<T, RXY, 2>(tp, in, out, n, nz, zc, s, on, zero_off, tout); break;
+        case 3: launch_r<T, RXY, 3>(tp, in, out, n, nz, zc, s, on, zero_off, tout); break;
+        case 4: launch_r<T, RXY, 4>(tp, in, out, n, nz, zc, s, on, zero_off, tout); break;
+        case 5: launch_r<T, RXY, 5>(tp, in, out, n, nz, zc, s, on, zero_off, tout); break;
+        case 6: launch_r<T, RXY, 6>(tp, in, out, n, nz, zc, s, on, zero_off, tout); break;
+        case 7: launch_r<T, RXY, 7>(tp, in, out, n, nz, zc, s, on, zero_off, tout); break;
+        case 8: launch_r<T, RXY, 8>(tp, in, out, n, nz, zc, s, on, zero_off, tout); break;
         default: return fail(SIPO_E_UNSUPPORTED, "PSF z radius %d > %d", tp.rz, kMaxR);
     }
     return SIPO_OK;
@@ -302,7 +325,7 @@ static int launch_rz(const Taps<T> &tp, const void *in, void *out, int n, int nz
 
 template <typename T>
 static int blur_dispatch(sipo_plan p, const Taps<T> &taps, const void *in, void *out, hipStream_t s,
-                         const uint8_t *on, int zero_off) {
+                         const uint8_t *on, int zero_off, bool tout = false) {
     Taps<T> tp = taps;
     const int R = std::max(tp.rx, tp.ry);
     pad_taps(tp.kx, tp.rx, R);
@@ -311,15 +334,15 @@ static int blur_dispatch(sipo_plan p, const Taps<T> &taps, const void *in, void 
     const int zc = blur_zchunk(p);
     int rc;
     switch (R) {
-        case 0: rc = launch_rz<T, 0>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
-        case 1: rc = launch_rz<T, 1>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
-        case 2: rc = launch_rz<T, 2>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
-        case 3: rc = launch_rz<T, 3>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
-        case 4: rc = launch_rz<T, 4>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
-        case 5: rc = launch_rz<T, 5>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
-        case 6: rc = launch_rz<T, 6>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
-        case 7: rc = launch_rz<T, 7>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
-        case 8: rc = launch_rz<T, 8>(tp, in, out, p->n, p->nz, zc, s, on, zero_off); break;
+        case 0: rc = launch_rz<T, 0>(tp, in, out, p->n, p->nz, zc, s, on, zero_off, tout); break;
+        case 1: rc = launch_rz<T, 1>(tp, in, out, p->n, p->nz, zc, s, on, zero_off, tout); break;
+        case 2: rc = launch_rz<T, 2>(tp, in, out, p->n, p->nz, zc, s, on, zero_off, tout); break;
+        case 3: rc = launch_rz<T, 3>(tp, in, out, p->n, p->nz, zc, s, on, zero_off, tout); break;
+        case 4: rc = launch_rz<T, 4>(tp, in, out, p->n, p->nz, zc, s, on, zero_off, tout); break;
+        case 5: rc = launch_rz<T, 5>(tp, in, out, p->n, p->nz, zc, s, on, zero_off, tout); break;
+        case 6: rc = launch_rz<T, 6>(tp, in, out, p->n, p->nz, zc, s, on, zero_off, tout); break;
+        case 7: rc = launch_rz<T, 7>(tp, in, out, p->n, p->nz, zc, s, on, zero_off, tout); break;
+        case 8: rc = launch_rz<T, 8>(tp, in, out, p->n, p->nz, zc, s, on, zero_off, tout); break;
         default: return fail(SIPO_E_UNSUPPORTED, "PSF xy radius %d > %d", R, kMaxR);
     }
     if (rc) return rc;
@@ -334,6 +357,17 @@ int launch_blur(sipo_plan p, const void *in, void *out, hipStream_t s, const uin
     }
     return p->dtype == SIPO_F64 ? blur_dispatch<double>(p, p->taps_d, in, out, s, tile_on, zero_off)
                                 : blur_dispatch<float>(p, p->taps_f, in, out, s, tile_on, zero_off);
+}
+
+bool blur_to_t_ok(sipo_plan p) {
+    return p->has_psf && p->dtype == SIPO_F32 && p->fast3d() && p->nz % 4 == 0 && blur_zchunk(p) % 4 == 0;
+}
+
+int launch_blur_to_t(sipo_plan p, const void *in, void *vol_t, hipStream_t s, const uint8_t *tile_on) {
+    if (!blur_to_t_ok(p) || !tile_on)
+        return fail(SIPO_E_UNSUPPORTED, "blur into the projector's layout: FP32 tile-masked 3D launches with z chunks "
+                                        "and slice counts multiple of 4");
+    return blur_dispatch<float>(p, p->taps_f, in, vol_t, s, tile_on, 0, true);
 }
 
 }  // namespace sipo

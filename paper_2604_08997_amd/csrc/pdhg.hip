@@ -1280,16 +1280,25 @@ class Solver {
             const T *src = F(zf) + I.voff;
             T *out = F(outf) + I.soff;
             int rc = SIPO_OK;
+            bool in_t = false;   // src is already in the projector's layout
             if (I.p->has_psf) {
-                T *tmp = F(L_.tmp) + I.voff;
                 // masked: z vanishes off the labelled voxels, so K z is zero on tiles out of the PSF's
-                // reach of them; those tiles are written as zeros without reading z
+                // reach of them; those tiles are written as zeros without reading z, or (FP32) the
+                // blur writes the projector's layout itself, where they stay zero from setup on
                 const bool m = mask_ && I.t3;
-                rc = launch_blur(I.p, src, tmp, s_, m ? blur_reach(i) : nullptr, 1);
+                if (m && blur_to_t_ok(I.p)) {
+                    T *vt = F(L_.vol_t) + I.voff;
+                    rc = launch_blur_to_t(I.p, src, vt, s_, blur_reach(i));
+                    src = vt;
+                    in_t = true;
+                } else {
+                    T *tmp = F(L_.tmp) + I.voff;
+                    rc = launch_blur(I.p, src, tmp, s_, m ? blur_reach(i) : nullptr, 1);
+                    src = tmp;
+                }
                 if (!rc) rc = mark(SIPO_PHASE_BLUR);
-                src = tmp;
             }
-            if (!rc && I.t3) {
+            if (!rc && I.t3 && !in_t) {
                 // masked: only tiles that can hold a nonzero of K z (with a PSF; without one, z's own
                 // support is not tracked per tile and the whole volume moves)
                 const bool mt = mask_ && I.p->has_psf;
@@ -1476,9 +1485,11 @@ class Solver {
             sp.keep_off = p->has_psf;
             return launch_backproject_t(p, F(L_.yt) + I.soff, F(L_.tmp) + I.voff, 0, s_, U8(L_.bflags) + L_.bfo[i], sp);
         };
-        auto blurs = [&]() {
+        auto blurs = [&]() {   // as the iteration runs them (the second into the projector's layout where it can)
             int r = launch_blur(p, F(L_.tmp) + I.voff, F(L_.Dt) + I.voff, s_, blur_own(i), 0);
-            if (!r) r = launch_blur(p, F(L_.Dt) + I.voff, F(L_.tmp2) + I.voff, s_, blur_reach(i), 1);
+            if (!r)
+                r = blur_to_t_ok(p) ? launch_blur_to_t(p, F(L_.Dt) + I.voff, F(L_.vol_t) + I.voff, s_, blur_reach(i))
+                                    : launch_blur(p, F(L_.Dt) + I.voff, F(L_.tmp2) + I.voff, s_, blur_reach(i), 1);
             return r;
         };
         // projector: 8, 16 or 32 slices per thread (the asynchronous variant only)

@@ -148,6 +148,11 @@ int launch_project(sipo_plan p, const void *vol, void *sino, int accumulate, hip
 // with zero_off, has its output set to zero without reading the input.
 int launch_blur(sipo_plan p, const void *in, void *out, hipStream_t s, const uint8_t *tile_on = nullptr,
                 int zero_off = 0);
+// K of a z that vanishes off the switched-on tiles' reach, written straight into the projector's
+// z-contiguous layout (the input of launch_project_t) for the tiles on in tile_on; the layout must
+// hold zeros elsewhere.  FP32 3D plans whose blur z chunk and slice count are multiples of 4.
+bool blur_to_t_ok(sipo_plan p);
+int launch_blur_to_t(sipo_plan p, const void *in, void *vol_t, hipStream_t s, const uint8_t *tile_on);
 // Blur tiles of the plan's current tuning (0 without a PSF), and their flags from a label volume
 // [z][y][x]: own = the tile holds a labelled voxel, reach = a labelled voxel lies within the PSF
 // radius of the tile (elsewhere the blur of a field supported on labelled voxels is zero).
