@@ -527,7 +527,7 @@ def probe(args, plan, dev):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py runs on one GPU only; --gpus must be 1", file=sys.stderr)
         return 2
     import torch
     import paper_2604_08997_amd as sipo

@@ -57,7 +57,7 @@ typedef enum {
     SIPO_E_INVALID = -1,      /* bad argument; nothing was launched          */
     SIPO_E_DEVICE = -2,       /* a HIP call failed                           */
     SIPO_E_WORKSPACE = -3,    /* caller workspace smaller than required      */
-    SIPO_E_UNSUPPORTED = -4   /* valid request this build does not support   */
+    SIPO_E_UNSUPPORTED = -4   /* valid request the library does not support  */
 } sipo_status;
 
 typedef enum { SIPO_F32 = 0, SIPO_F64 = 1 } sipo_dtype;
