@@ -62,7 +62,7 @@ def test_512cube_720_projector_pair_and_blur_sampled():
 
 
 def test_512cube_720_checkpointed_backward_sampled():
-    # configs[4]'s backward: a nonlinear objective of dose = K P^T p through torch.utils.checkpoint, so
+    # the 512^3 x 720 workload's backward: a nonlinear objective of dose = K P^T p through torch.utils.checkpoint, so
     # the forward is recomputed in the backward pass and nothing of it is kept; the backward itself
     # keeps nothing either (the projector recomputes the attenuation factors).  Sampled entries of
     # grad p = P K (dL/dD) against the oracle, dL/dD = 2 max(D - thr, 0) formed from the GPU's dose.
@@ -101,7 +101,7 @@ def test_512cube_720_checkpointed_backward_sampled():
 @pytest.mark.skipif(os.environ.get("SIPO_LARGE_SOLVE") != "1",
                     reason="minutes of oracle CPU time at 512^3; run with SIPO_LARGE_SOLVE=1")
 def test_512cube_720_case2_solve_state_matches_oracle_kkt():
-    # configs[4]: the 512^3 x 720 lattice LP (Case 2 at threshold 0.65, blur (1, 1, 2)), FP32, solved
+    # the 512^3 x 720 lattice LP (Case 2 at threshold 0.65, blur (1, 1, 2)), FP32, solved
     # toward relative KKT 1e-4 within a bounded budget; the state it returns is checked by the oracle:
     # regions and active rays bit-exact, and the solver's relative residuals and objective equal the
     # oracle's FP64 ones of that state (or, if it ends infeasible, the oracle's Farkas test accepts it)
