@@ -148,20 +148,23 @@ def recorded_traffic(kernel):
 # solver's tuner, run in the warm-up solve, picks among candidates that differ by a few percent at
 # this workload, so the timed, profiled and counter-collection solves fix one choice -- the fastest
 # in repeated tuner runs on MI355X: 16 slices per projector thread, 3 queue workgroups per CU, the
-# primal step fused, candidate skipping on; 8 slices and 8 view splits for the backprojector, 4
-# slices per blur chunk -- and the line reports the tuner's own pick beside it.
-BENCH_OPS = {"p_zc": 16, "bp_zc": 8, "bp_splits": 8, "blur_zc": 4, "p_queue": 3, "p_fuse": 1, "p_skip": 1}
+# primal step fused, candidate skipping on, two listed march steps per staged chunk; 8 slices and 8
+# view splits for the backprojector, 4 slices per blur chunk -- and the line reports the tuner's own
+# pick beside it.
+BENCH_OPS = {"p_zc": 16, "bp_zc": 8, "bp_splits": 8, "blur_zc": 4, "p_queue": 3, "p_fuse": 1, "p_skip": 1,
+             "p_chunk": 2}
 
 
 def in_solve_projector(tuning, ops):
     """Name of the projector kernel an LP solve of the 256^3 x 360 workload runs (view pairs, 3
-    candidates per step, slices per thread and work queue as the solve reports them in ``ops``;
-    with the asynchronous projector the masked operator walks its step lists one step per chunk)."""
+    candidates per step, slices per thread, work queue and listed march steps per staged chunk as
+    the solve reports them in ``ops``)."""
     zc = ops["p_zc"]
     if tuning["p3d_dma"]:
         queue = "true" if ops.get("p_queue", -1) > 0 else "false"
         skip = "true" if ops.get("p_skip", 1 if tuning["p3d_skip"] else -1) > 0 else "false"
-        return f"project3d_dma_kernel<{zc}, 3, true, {skip}, 1, true, {queue}>"
+        cm = ops.get("p_chunk", 1) or 1
+        return f"project3d_dma_kernel<{zc}, 3, true, {skip}, {cm}, true, {queue}>"
     return f"project3d_kernel<float, {zc}, 3, true>"
 
 

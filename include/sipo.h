@@ -323,7 +323,7 @@ typedef struct {
                                   solve is reproducible bit for bit only with the same
                                   picks (op_config and tiles_2d in the result; pass them
                                   back to repeat it).  0 = fixed rules                     */
-    int32_t op_config[7];      /* restarted mode, 3D instances: a nonzero entry fixes that
+    int32_t op_config[8];      /* restarted mode, 3D instances: a nonzero entry fixes that
                                   work split of the masked operators, as reported in the
                                   result's op_config (projector slices per thread 8 / 16 /
                                   32, the last FP32 only; backprojector slices per thread
@@ -336,7 +336,11 @@ typedef struct {
                                   its march is unsplit, -1 = its own kernel; the
                                   projector's lanes: 1 = skip the LDS reads of candidates
                                   out of their ray's reach, -1 = read them, which changes
-                                  no result); passing a
+                                  no result; the projector's listed march steps per staged
+                                  chunk, 1 or 2 (2 halves its barriers; 32 slices always
+                                  take 1; 0: 2 when every switched-on workgroup fits on the
+                                  device at once with the larger ring), which changes no
+                                  result where the march is unsplit); passing a
                                   tuned result's op_config back repeats that solve bit for
                                   bit.  Zero entries are tuned or follow the fixed rules (no
                                   queue, fused)                                            */
@@ -382,11 +386,12 @@ typedef struct {
                                   ran.  iters / loop_ms is the steady iteration rate        */
     double phase_ms[SIPO_NUM_PHASES];       /* profile mode: summed launch durations          */
     int32_t phase_launches[SIPO_NUM_PHASES]; /* profile mode: launches timed per phase        */
-    int32_t op_config[7];      /* restarted mode, 3D instance: the masked operators' work
+    int32_t op_config[8];      /* restarted mode, 3D instance: the masked operators' work
                                   splits as run (projector slices per thread,
                                   backprojector slices per thread, backprojector view
                                   splits, blur slices per chunk, projector work queue,
-                                  primal step and candidate skipping as in the options);
+                                  primal step, candidate skipping and listed steps per
+                                  chunk as in the options; the last 0 without step lists);
                                   zeros otherwise                                          */
     int32_t tiles_2d[3];       /* batched single-slice instances: the 2D pair's work shapes
                                   as run (as in the options); zeros otherwise              */

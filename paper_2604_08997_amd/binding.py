@@ -51,10 +51,10 @@ class PdhgOptions(C.Structure):
                 ("tau", C.c_double), ("sigma", C.c_double), ("power_iters", C.c_int32), ("eta", C.c_double),
                 ("infeas_tol", C.c_double), ("use_graph", C.c_int32), ("profile", C.c_int32),
                 ("scalar_weight", C.c_double), ("progress_every", C.c_int32), ("tune_operators", C.c_int32),
-                ("op_config", C.c_int32 * 7), ("tiles_2d", C.c_int32 * 3)]
+                ("op_config", C.c_int32 * 8), ("tiles_2d", C.c_int32 * 3)]
 
 NUM_PHASES = 7
-OP_KEYS = ("p_zc", "bp_zc", "bp_splits", "blur_zc", "p_queue", "p_fuse", "p_skip")
+OP_KEYS = ("p_zc", "bp_zc", "bp_splits", "blur_zc", "p_queue", "p_fuse", "p_skip", "p_chunk")
 TILE2D_KEYS = ("bp_tile_x", "bp_views", "fp_bins")
 PHASES = ("project", "backproject", "blur", "transpose", "primal", "dual", "scalars")
 
@@ -66,7 +66,7 @@ class PdhgResult(C.Structure):
                 ("u", C.c_double), ("v", C.c_double), ("tau", C.c_double), ("sigma", C.c_double),
                 ("omega", C.c_double), ("time_ms", C.c_double), ("loop_ms", C.c_double),
                 ("phase_ms", C.c_double * NUM_PHASES), ("phase_launches", C.c_int32 * NUM_PHASES),
-                ("op_config", C.c_int32 * 7), ("tiles_2d", C.c_int32 * 3)]
+                ("op_config", C.c_int32 * 8), ("tiles_2d", C.c_int32 * 3)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_
@@ -424,8 +424,8 @@ def pdhg_options(mode=RESTARTED, max_iters=20000, check_every=64, tol=1e-4, tau=
                  eta=0.95, infeas_tol=1e-6, use_graph=0, profile=0, scalar_weight=0.0, progress_every=0,
                  tune_operators=0, op_config=None, tiles_2d=None):
     """Solver options.  op_config fixes the masked 3D operators' work splits: a dict with any of the
-    keys p_zc, bp_zc, bp_splits, blur_zc, p_queue, p_fuse, p_skip (as in a result's op_config) or
-    a 7-sequence; 0 = free."""
+    keys p_zc, bp_zc, bp_splits, blur_zc, p_queue, p_fuse, p_skip, p_chunk (as in a result's
+    op_config) or an 8-sequence; 0 = free."""
     if op_config is None:
         oc = (0,) * len(OP_KEYS)
     elif isinstance(op_config, dict):
@@ -450,7 +450,7 @@ def pdhg_options(mode=RESTARTED, max_iters=20000, check_every=64, tol=1e-4, tau=
             raise ValueError(f"tiles_2d needs {len(TILE2D_KEYS)} entries")
     return PdhgOptions(int(mode), int(max_iters), int(check_every), float(tol), float(tau), float(sigma),
                        int(power_iters), float(eta), float(infeas_tol), int(use_graph), int(profile),
-                       float(scalar_weight), int(progress_every), int(tune_operators), (C.c_int32 * 7)(*oc),
+                       float(scalar_weight), int(progress_every), int(tune_operators), (C.c_int32 * 8)(*oc),
                        (C.c_int32 * 3)(*t2))
 
 

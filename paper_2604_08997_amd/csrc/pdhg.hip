@@ -1372,6 +1372,7 @@ class Solver {
         const long long onb = count_on(L_.bflags + L_.bfo[i], bp3d_flag_count(p));
         if (onp < 0 || onb < 0) return fail(SIPO_E_DEVICE, "pdhg setup: reading the skip flags failed");
         psp_[i] = SplitSpec{parts_for(onp, cus_, kMaxSplitP), F(L_.ppart)};
+        pon_[i] = onp;
         bsp_[i] = SplitSpec{bparts > 0 ? std::min(bparts, kMaxSplitB) : parts_for(onb, 4LL * cus_, kMaxSplitB),
                             F(L_.bpart)};
         bsp_[i].need = U8(L_.bneed) + L_.bno[i];
@@ -1405,6 +1406,7 @@ class Solver {
         return SIPO_OK;
     }
     std::vector<int> n_pitems_;   // per instance: tiles in the projector's work queue
+    std::vector<long long> pon_;  // per instance: switched-on projector workgroups
     std::vector<int> pqueue_;     // per instance: queue workgroups per CU (-1 = one workgroup per tile)
     std::vector<int> pfuse_;      // per instance: -1 = the primal step runs as its own kernel
     StepList step_list(int i, bool off_unread) {
@@ -1412,6 +1414,8 @@ class Solver {
         if (steps_.empty() || !steps_[i]) return sl;
         sl.steps = P<int>(L_.psteps + L_.pso[i]);
         sl.count = P<int>(L_.pcount + L_.pco[i]);
+        sl.n_on = pon_[i];
+        sl.chunk = o_.op_config[7];
         if (n_pitems_[i] > 0 && pqueue_[i] > 0) {
             sl.items = P<int>(L_.pitems + L_.pco[i]);
             sl.n_items = n_pitems_[i];
@@ -1825,6 +1829,7 @@ int Solver<T>::setup_common() {
         fused_.assign(B_, 0);
         steps_.assign(B_, 0);
         n_pitems_.assign(B_, 0);
+        pon_.assign(B_, 0);
         pqueue_.assign(B_, o_.op_config[4] ? o_.op_config[4] : -1);
         pfuse_.assign(B_, o_.op_config[5] ? o_.op_config[5] : 1);
         for (int i = 0; i < B_; ++i) {
@@ -2469,7 +2474,7 @@ int Solver<T>::run(sipo_pdhg_result *res) {
             r.phase_ms[ph] = phase_ms_[ph];
             r.phase_launches[ph] = phase_n_[ph];
         }
-        for (int k = 0; k < 7; ++k) r.op_config[k] = 0;
+        for (int k = 0; k < 8; ++k) r.op_config[k] = 0;
         r.tiles_2d[0] = b2d_ ? t2d_.bx : 0;
         r.tiles_2d[1] = b2d_ ? t2d_.vb : 0;
         r.tiles_2d[2] = b2d_ ? t2d_.fb : 0;
@@ -2482,6 +2487,7 @@ int Solver<T>::run(sipo_pdhg_result *res) {
             r.op_config[4] = queued ? pqueue_[i] : -1;
             r.op_config[5] = fused_[i] ? 1 : -1;
             r.op_config[6] = I.p->p3d_skip ? 1 : -1;
+            r.op_config[7] = steps_[i] ? p3d_list_chunk(I.p, step_list(i, false)) : 0;
         }
     }
     return SIPO_OK;
@@ -2519,6 +2525,8 @@ static int validate(const sipo_problem &pb, const sipo_pdhg_options &o, int idx,
         SIPO_REQUIRE(c[4] >= -1 && c[4] <= 16, "op_config[4] (projector work queue) must be in [-1, 16], not %d", c[4]);
         SIPO_REQUIRE(c[5] >= -1 && c[5] <= 1, "op_config[5] (primal step) must be -1, 0 or 1, not %d", c[5]);
         SIPO_REQUIRE(c[6] >= -1 && c[6] <= 1, "op_config[6] (candidate skipping) must be -1, 0 or 1, not %d", c[6]);
+        SIPO_REQUIRE(c[7] >= 0 && c[7] <= 2, "op_config[7] (listed steps per staged chunk) must be 0, 1 or 2, not %d",
+                     c[7]);
         const int *t = o.tiles_2d;
         SIPO_REQUIRE(t[0] == 0 || t[0] == 16 || t[0] == 32 || t[0] == 64, "tiles_2d[0] (backprojector tile width) must "
                      "be 0, 16, 32 or 64, not %d", t[0]);

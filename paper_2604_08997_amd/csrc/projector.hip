@@ -616,7 +616,7 @@ __device__ __forceinline__ void p3d_dma_tile(
     const int *__restrict__ step_cnt, int3 tile, int gx, int gz, float4 *bufA, float4 *bufB, float4 *bufC,
     int2 *smeta) {
     static_assert(CM >= 1 && CM <= kDmaMaxCM, "chunk length");
-    static_assert(!LIST || CM == 1, "step lists walk one step per chunk");
+    static_assert(!LIST || CM <= 2, "step lists walk one or two listed steps per chunk");
     constexpr int Z4 = DmaRing<ZC, CM>::Z4, RS = DmaRing<ZC, CM>::RS, SLOTS = DmaRing<ZC, CM>::SLOTS;
     constexpr int PER = DmaRing<ZC, CM>::PER;
     constexpr int NR = PAIR ? 2 : 1;
@@ -655,8 +655,9 @@ __device__ __forceinline__ void p3d_dma_tile(
     const double inv_du = 1.0 / du;
     const float du_t = (float)du, dsj_t = (float)dsj, dtj_t = (float)dtj;
     const MarchF32 mc32 = march_f32(U00 - (double)b, dU, du, inv_du, s00, dsm, t00, dtm, nb);
-    // the march: every step in chunks of CM, or (step lists, CM = 1) only the listed steps, in
-    // increasing order; the steps left out stage nothing but zeros
+    // the march: every step in chunks of CM, or (step lists) only the listed steps, in increasing
+    // order and CM listed steps per chunk, each staged with its own cross range; the steps left out
+    // stage nothing but zeros
     // LIST: each listed step's record (step, staged cross range, vial interval of its grid line) is
     // gathered into LDS first, so that a chunk's metadata costs one LDS read instead of a chain of
     // dependent scalar loads from global memory, and adds no vector-memory load to the staging waits
@@ -664,30 +665,39 @@ __device__ __forceinline__ void p3d_dma_tile(
     // (a static array of the kernel: the compiler then knows that the staging copies into the ring
     // never write it)
     const int2 *rg = ranges + ((size_t)tile.y * gx + tile.x) * n;
-    int nch = (n + CM - 1) / CM;
+    int nch = (n + CM - 1) / CM, nlist = 0;
     if constexpr (LIST) {
         const size_t wgi = ((size_t)tile.y * gx + tile.x) * nzc + zb;
-        nch = __builtin_amdgcn_readfirstlane(step_cnt[wgi]);
-        for (int i = tid; i < nch; i += 256) {
+        nlist = __builtin_amdgcn_readfirstlane(step_cnt[wgi]);
+        nch = (nlist + CM - 1) / CM;   // a chunk: CM consecutive entries of the list
+        for (int i = tid; i < nlist; i += 256) {
             const int m = step_list[wgi * n + i];
             const int2 r = rg[m], v = vial_rows[m];
             smeta[i] = make_int2(m | (r.y << 10) | ((r.x + kListJ0Bias) << 17), (v.x & 0xFFFF) | (v.y << 16));
         }
         __syncthreads();
     }
-    auto first_step = [&](int k) {
-        if constexpr (LIST) return __builtin_amdgcn_readfirstlane(smeta[k].x) & 1023;
-        else return __builtin_amdgcn_readfirstlane(k * CM);
+    auto first_step = [&](int k) { return __builtin_amdgcn_readfirstlane(k * CM); };
+    // LIST: entry e of the list (uniform): step m, staged cross range r (first index, count) and the
+    // vial interval v of its grid line; entries past the list stage and compute nothing
+    auto list_rec = [&](int e, int &m, int2 &r, int2 &v) {
+        if (e < nlist) {
+            const int2 sm = smeta[e];
+            const int ex = __builtin_amdgcn_readfirstlane(sm.x), ey = __builtin_amdgcn_readfirstlane(sm.y);
+            m = ex & 1023;
+            r = make_int2((ex >> 17) - kListJ0Bias, (ex >> 10) & 127);
+            v = make_int2(ey & 0xFFFF, ey >> 16);
+        } else {
+            m = 0;
+            r = make_int2(0, 0);
+            v = make_int2(1, 0);
+        }
     };
     const size_t zrow = (size_t)(nz >> 2), zoff = (size_t)(z0 >> 2);
     const float4 *vol4 = (const float4 *)vol_t;
 
     // staged cross range of chunk k: the union of its steps' ranges (first index, count)
     auto chunk_range = [&](int k) {
-        if constexpr (LIST) {
-            const int e = __builtin_amdgcn_readfirstlane(smeta[k].x);
-            return make_int2((e >> 17) - kListJ0Bias, (e >> 10) & 127);
-        }
         const int m0 = first_step(k);   // uniform: scalar loads
         int lo = rg[m0].x, hi = rg[m0].x + rg[m0].y;
 #pragma unroll
@@ -711,27 +721,33 @@ __device__ __forceinline__ void p3d_dma_tile(
         s_jj[i] = rem - s_z4[i] * RS;
     }
     auto issue = [&](float4 *buf, int k) {
-        int2 r;
-        int m0;
-        int2 vr[CM];   // vial interval of each step's row (uniform)
+        // per row of the chunk (uniform): step, staged cross range and vial interval; without step
+        // lists the rows are consecutive steps sharing the union of their ranges
+        int mq[CM];
+        int2 rq[CM], vq[CM];
         if constexpr (LIST) {
-            const int2 e = smeta[k];
-            const int ex = __builtin_amdgcn_readfirstlane(e.x), ey = __builtin_amdgcn_readfirstlane(e.y);
-            m0 = ex & 1023;
-            r = make_int2((ex >> 17) - kListJ0Bias, (ex >> 10) & 127);
-            vr[0] = make_int2(ey & 0xFFFF, ey >> 16);
-        } else {
-            r = chunk_range(k);
-            m0 = first_step(k);
 #pragma unroll
-            for (int q = 0; q < CM; ++q) vr[q] = vial_rows[min(m0 + q, n - 1)];
+            for (int q = 0; q < CM; ++q) list_rec(k * CM + q, mq[q], rq[q], vq[q]);
+        } else {
+            const int2 r = chunk_range(k);
+            const int m0 = first_step(k);
+#pragma unroll
+            for (int q = 0; q < CM; ++q) {
+                mq[q] = m0 + q;
+                rq[q] = r;
+                vq[q] = vial_rows[min(m0 + q, n - 1)];
+            }
         }
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             if (i * 256 + tid < SLOTS) {
                 const int mm = CM == 1 ? 0 : s_mm[i];
-                const int m = m0 + mm, j = r.x + s_jj[i];
-                const int2 v = CM == 1 ? vr[0] : (mm ? vr[CM - 1] : vr[0]);
+                int m = mq[0];
+                int2 r = rq[0], v = vq[0];
+#pragma unroll
+                for (int q = 1; q < CM; ++q)
+                    if (mm == q) { m = mq[q]; r = rq[q]; v = vq[q]; }
+                const int j = r.x + s_jj[i];
                 const float4 *src = zero16;
                 if (m < n && s_jj[i] < r.y && z0 + 4 * s_z4[i] < nz && j >= v.x && j <= v.y)
                     src = vol4 + (xmajor ? ((size_t)j * n + m) : ((size_t)m * n + j)) * zrow + zoff + s_z4[i];
@@ -749,12 +765,21 @@ __device__ __forceinline__ void p3d_dma_tile(
         for (int k = 0; k < ZC; ++k) acc[r][k] = 0.f;
 
     auto compute = [&](const float4 *buf, int k) {
-        const int2 r = chunk_range(k);
-        const int j0 = r.x, cr = r.y;
-        const int m0 = first_step(k);
-        const int mc = min(CM, n - m0);
+        int2 r = make_int2(0, 0);
+        int m0 = 0, mc = CM;
+        if constexpr (!LIST) {
+            r = chunk_range(k);
+            m0 = first_step(k);
+            mc = min(CM, n - m0);
+        }
         for (int mm = 0; mm < mc; ++mm) {
-            const int m = m0 + mm;
+            int m = m0 + mm;
+            if constexpr (LIST) {
+                if (k * CM + mm >= nlist) break;   // the list's last chunk may be short
+                int2 v;
+                list_rec(k * CM + mm, m, r, v);
+            }
+            const int j0 = r.x, cr = r.y;
             float d0, s0, t0;
             const int jlo = march_step_f32(mc32, m, dsj_t, dtj_t, d0, s0, t0);
             const int jj0 = jlo - j0;
@@ -1405,11 +1430,15 @@ static void fp3d_dma_launch_k(sipo_plan p, const void *vol_t, void *sino_t, hipS
 
 // The listed march of an unsplit solve takes the work queue when the caller set one up (and the
 // outputs the queue leaves unwritten are not read); everything else runs one workgroup per tile.
+static bool list_queued(const SplitSpec &sp, const PrimalFuse &fz, const StepList &sl) {
+    return sl.items && sl.queue && sp.parts <= 1 && (fz.y || sl.off_unread);
+}
+
 template <int ZC, int NC, bool PAIR, bool SKIP, int CM, bool LIST>
 static void fp3d_dma_launch(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
                             const SplitSpec &sp, const PrimalFuse &fz, const StepList &sl) {
     if constexpr (LIST) {
-        if (sl.items && sl.queue && sp.parts <= 1 && (fz.y || sl.off_unread)) {
+        if (list_queued(sp, fz, sl)) {
             fp3d_dma_launch_k<ZC, NC, PAIR, SKIP, CM, true, true>(p, vol_t, sino_t, s, on, sp, fz, sl);
             return;
         }
@@ -1420,10 +1449,16 @@ static void fp3d_dma_launch(sipo_plan p, const void *vol_t, void *sino_t, hipStr
 template <int ZC, int NC, bool PAIR, bool SKIP>
 static void fp3d_dma_go(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s, const uint8_t *on,
                         const SplitSpec &sp, const PrimalFuse &fz, const StepList &sl) {
-    // 64 slices stage one step per chunk only: three two-step buffers would not fit in LDS; step
-    // lists (masked solves: 8, 16 or 32 slices) walk one listed step per chunk
+    // 64 slices stage one step per chunk only: three two-step buffers would not fit in LDS.  Step
+    // lists (masked solves) stage one or two listed steps per chunk (p3d_list_chunk)
     if constexpr (ZC <= 32) {
         if (sl.steps) {
+            if constexpr (ZC <= 16) {
+                if (p3d_list_chunk(p, sl) == 2) {
+                    fp3d_dma_launch<ZC, NC, PAIR, SKIP, 2, true>(p, vol_t, sino_t, s, on, sp, fz, sl);
+                    return;
+                }
+            }
             fp3d_dma_launch<ZC, NC, PAIR, SKIP, 1, true>(p, vol_t, sino_t, s, on, sp, fz, sl);
             return;
         }
@@ -1681,6 +1716,23 @@ __global__ void __launch_bounds__(256) k_p3d_steps(const int4 *__restrict__ batc
         __syncthreads();
     }
     if (tid == 0) count[wg] = base;
+}
+
+int p3d_list_chunk(sipo_plan p, const StepList &sl) {
+    if (p->p3d_zc > 16) return 1;   // a two-step ring at 32 slices would not fit beside a second workgroup
+    if (sl.chunk == 1 || sl.chunk == 2) return sl.chunk;
+    // rule: two steps when every switched-on tile can be resident at once with the two-step ring
+    // (its LDS bounds the workgroups per CU; the registers allow at least as many at 16 slices)
+    static int cus[64] = {};
+    const int d = p->device >= 0 && p->device < 64 ? p->device : 0;
+    if (!cus[d]) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || c < 1) c = 1;
+        cus[d] = c;
+    }
+    const long long ring = 3LL * 2 * (p->p3d_zc / 4) * (kPCR + 1) * 16, lds = ring + 8LL * kMaxListSteps + 256;
+    const long long per_cu = (160LL * 1024) / lds;
+    return sl.n_on > 0 && sl.n_on <= per_cu * cus[d] ? 2 : 1;
 }
 
 bool p3d_steps_ok(sipo_plan p) {

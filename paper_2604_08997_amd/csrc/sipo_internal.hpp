@@ -201,6 +201,8 @@ struct StepList {
     int n_items = 0;
     int *queue = nullptr;
     int queue_per_cu = 0;   // persistent workgroups per CU (0 or more than fit: as many as fit)
+    long long n_on = 0;     // switched-on workgroups of the march (0: not known)
+    int chunk = 0;          // listed steps per staged chunk: 1, 2, or 0 = p3d_list_chunk's rule
     // the queue leaves the outputs of switched-off workgroups unwritten; without the fused primal step
     // it is used only when the caller never reads them (off_unread)
     bool off_unread = false;
@@ -214,6 +216,10 @@ int launch_project_t(sipo_plan p, const void *vol_t, void *sino_t, hipStream_t s
 // flag is off list none.  labels: [z][y][x]; reach: scratch of p3d_reach_bytes; steps: int
 // [p3d_flag_count][n]; count: int [p3d_flag_count].  Needs the asynchronous projector's ranges.
 bool p3d_steps_ok(sipo_plan p);   // the plan's projector (current tuning) can walk step lists
+// Listed march steps per staged chunk of the projector on these lists: 1 at 32 slices per thread;
+// else sl.chunk if set; else 2 when all sl.n_on switched-on workgroups fit on the device at once
+// with the two-step ring, 1 otherwise.  The sums are the same either way (steps in list order).
+int p3d_list_chunk(sipo_plan p, const StepList &sl);
 size_t p3d_reach_bytes(sipo_plan p, int zc = 0);
 int launch_p3d_steps(sipo_plan p, const uint8_t *labels, const uint8_t *wg_on, uint8_t *reach, int *steps, int *count,
                      hipStream_t s);

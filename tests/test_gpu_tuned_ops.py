@@ -70,9 +70,9 @@ def test_fixed_slice_counts_match_oracle_kkt(oracle_lp):
     assert cfg["p_zc"] in (8, 16) and cfg["bp_zc"] in (4, 8) and 1 <= cfg["bp_splits"] <= 8 and cfg["blur_zc"] == 4
     assert cfg["p_queue"] == -1 and cfg["p_fuse"] in (1, -1)
     check_against_oracle(oracle_lp, base_r, base_st)
-    for p_zc, bp_zc, blur_zc in ((32, 4, 8), (8, 16, 16)):
+    for p_zc, bp_zc, blur_zc, chunk in ((32, 4, 8, 1), (8, 16, 16, 2), (16, 8, 4, 1)):
         want = {"p_zc": p_zc, "bp_zc": bp_zc, "bp_splits": cfg["bp_splits"], "blur_zc": blur_zc, "p_queue": -1,
-                "p_fuse": cfg["p_fuse"], "p_skip": -cfg["p_skip"]}
+                "p_fuse": cfg["p_fuse"], "p_skip": -cfg["p_skip"], "p_chunk": chunk}
         r, st = run(op_config=want)
         assert r["op_config"] == want
         check_against_oracle(oracle_lp, r, st)
@@ -93,7 +93,7 @@ def test_tuned_solve_picks_candidates_and_repeats_bit_for_bit(oracle_lp, capfd):
     cfg = r["op_config"]
     assert cfg["p_zc"] in (8, 16, 32) and cfg["bp_zc"] in (4, 8, 16)
     assert cfg["bp_splits"] in (1, 2, 4, 8) and cfg["blur_zc"] in (4, 8) and cfg["p_queue"] in (-1, 2, 3, 4, 6, 16)
-    assert cfg["p_fuse"] in (1, -1) and cfg["p_skip"] in (1, -1)
+    assert cfg["p_fuse"] in (1, -1) and cfg["p_skip"] in (1, -1) and cfg["p_chunk"] in (1, 2)
     check_against_oracle(oracle_lp, r, st)
     # the reported splits, passed back, repeat the tuned solve exactly
     r2, st2 = run(op_config=cfg)
@@ -105,7 +105,8 @@ def test_tuned_solve_picks_candidates_and_repeats_bit_for_bit(oracle_lp, capfd):
 def test_invalid_work_splits_are_rejected():
     import paper_2604_08997_amd as sipo
     plan, lp = gpu_lp()
-    for bad in ({"p_zc": 12}, {"bp_zc": 32}, {"bp_splits": 9}, {"blur_zc": 2}, {"p_queue": 17}, {"p_queue": -2}, {"p_fuse": 2}, {"p_skip": 3}):
+    for bad in ({"p_zc": 12}, {"bp_zc": 32}, {"bp_splits": 9}, {"blur_zc": 2}, {"p_queue": 17}, {"p_queue": -2}, {"p_fuse": 2}, {"p_skip": 3},
+                {"p_chunk": 3}, {"p_chunk": -1}):
         with pytest.raises(RuntimeError, match="op_config"):
             sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=64, op_config=bad))
     with pytest.raises(RuntimeError, match="tune_operators"):
@@ -126,22 +127,25 @@ def test_projector_work_queue_at_full_size_leaves_iterates_unchanged():
     fixed = {"p_zc": 8, "bp_zc": 8, "bp_splits": 8, "blur_zc": 4}
     stream = torch.cuda.Stream()   # graph-captured iteration blocks, as the benchmark runs them
 
-    def solve(qw, pf):
+    def solve(qw, pf, chunk=0):
         lp.y.zero_(); lp.lam_up.zero_(); lp.lam_lo.zero_()
         torch.cuda.synchronize()
         with torch.cuda.stream(stream):
             r = sipo.solve(lp, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=192, tol=1e-12, check_every=64,
-                                                 use_graph=1, op_config=dict(fixed, p_queue=qw, p_fuse=pf)),
+                                                 use_graph=1, op_config=dict(fixed, p_queue=qw, p_fuse=pf,
+                                                                             p_chunk=chunk)),
                            want_dose=False)
             torch.cuda.synchronize()
         assert (r["op_config"]["p_queue"], r["op_config"]["p_fuse"]) == (qw, pf)
+        assert r["op_config"]["p_chunk"] == (chunk or r["op_config"]["p_chunk"]) and r["op_config"]["p_chunk"] in (1, 2)
         return r, [t.cpu().numpy().copy() for t in (lp.y, lp.lam_up, lp.lam_lo)]
 
-    # with the primal step fused into the projector, and as its own kernel after it
+    # with the primal step fused into the projector, and as its own kernel after it; one or two
+    # listed march steps per staged chunk (the unsplit march adds each ray's steps in the same order)
     for pf in (1, -1):
         r0, st0 = solve(-1, pf)
-        for qw in (1, 16):
-            r, st = solve(qw, pf)
+        for qw, chunk in ((1, 0), (16, 0), (16, 1), (-1, 2), (3, 2)):
+            r, st = solve(qw, pf, chunk)
             assert (r["iters"], r["primal_obj"], r["rel_primal"]) == (r0["iters"], r0["primal_obj"], r0["rel_primal"])
             for a, b in zip(st0, st):
                 np.testing.assert_array_equal(a, b)
@@ -154,7 +158,8 @@ def test_projector_work_queue_at_full_size_leaves_iterates_unchanged():
 
 def test_tuned_batch_of_one_plan_shares_its_picks():
     # two 256^3 x 360 instances of one plan: the splits are tuned on the first and every instance of
-    # the plan runs them, the queue width and the primal step's form included
+    # the plan runs them, the queue width and the primal step's form included (the listed steps per
+    # staged chunk follow each instance's own count of switched-on workgroups)
     import paper_2604_08997_amd as sipo
     n, na = 256, 360
     plan = sipo.Plan(n, list(angles_uniform(na)), nz=n, sigma=SIGMA, dtype=torch.float32, device=dev())
@@ -162,8 +167,10 @@ def test_tuned_batch_of_one_plan_shares_its_picks():
                          sipo.CASE1, band_width=10.0, f_min=1.0) for seed in (3000, 3001)]
     res = sipo.solve(lps, sipo.pdhg_options(mode=sipo.RESTARTED, max_iters=64, tol=1e-12, tune_operators=1),
                      want_dose=False)
-    assert res[0]["op_config"] == res[1]["op_config"]
+    tuned = [{k: v for k, v in r["op_config"].items() if k != "p_chunk"} for r in res]
+    assert tuned[0] == tuned[1]
     assert res[0]["op_config"]["p_zc"] in (8, 16, 32)
+    assert all(r["op_config"]["p_chunk"] in (1, 2) for r in res)
 
 
 # ---- the batched 2D pair's work shapes (P^T tiles and staged view batches, P bundles)
