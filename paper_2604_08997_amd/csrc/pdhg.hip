@@ -118,6 +118,20 @@ __device__ __forceinline__ void block_sums(double (&v)[kNS], double *partials) {
     }
 }
 
+// block_sums for kernels whose consumers read columns 0 and 1 only (the others are left as they are)
+__device__ __forceinline__ void block_sums2(double a, double b, double *partials) {
+    __shared__ double red2[kThreads / 64][2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const double sa = wave_sum(a), sb = wave_sum(b);
+    if (lane == 0) { red2[w][0] = sa; red2[w][1] = sb; }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double s = 0.0;
+        for (int i = 0; i < kThreads / 64; ++i) s += red2[i][threadIdx.x];
+        partials[blockIdx.x * kNS + threadIdx.x] = s;
+    }
+}
+
 // Total of column k over partials[first .. first + count), by one block: strided
 // per-thread sums, then a fixed tree, so the result does not depend on timing.
 template <bool MAX>
@@ -411,7 +425,7 @@ __global__ void __launch_bounds__(kThreads) k_dual(
     const T ub = (T)(c.u_free ? sc.ubar : c.h);
     const T vb = (T)(c.v_free ? sc.vbar : 1.0);
     const T w = (T)sc.w, rho = (T)sc.rho, w1 = (T)1 - w, rp = (T)1 + rho;
-    double acc[kNS] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[2] = {0, 0};   // the consumers (k_scalars) read these two columns only
     const long long i0 = sg.b + (long long)kPer * threadIdx.x;
     uint4 l16 = make_uint4(0u, 0u, 0u, 0u);
     if (i0 < sg.e) l16 = *(const uint4 *)(lab + i0);
@@ -499,7 +513,7 @@ __global__ void __launch_bounds__(kThreads) k_dual(
             }
         }
     }
-    block_sums(acc, partials);
+    block_sums2(acc[0], acc[1], partials);
 }
 
 template <typename T, bool LAB>
