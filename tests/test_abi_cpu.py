@@ -41,3 +41,31 @@ def test_binding_has_no_cpu_fallback(monkeypatch):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(binding.SipoError):
         binding.lib()
+
+
+def test_binding_structures_match_the_header(tmp_path):
+    # the ctypes mirrors of the ABI structures have the C layout: size and every field's offset, as a
+    # C compiler lays the header out (a field added on one side only would shift all that follow)
+    import ctypes as C
+    from paper_2604_08997_amd import binding
+    pairs = {"sipo_geometry": binding.Geometry, "sipo_psf": binding.Psf, "sipo_problem": binding.Problem,
+             "sipo_pdhg_options": binding.PdhgOptions, "sipo_pdhg_result": binding.PdhgResult,
+             "sipo_tuning": binding.Tuning, "sipo_resin": binding.Resin, "sipo_metrics": binding.Metrics}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sipo.h"', 'int main(void) {']
+    for cname, py in pairs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'    printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ['    return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        name, field, val = ln.split()
+        got[(name, field)] = int(val)
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
